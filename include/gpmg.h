@@ -1,0 +1,164 @@
+/*
+ * gpmg -- MI355X (gfx950) monolithic multigrid for the ghost-point level-set Navier-Stokes method of
+ * A. Coco, "A multigrid ghost-point level-set method for incompressible Navier-Stokes equations on moving
+ * domains with curved boundaries" (arXiv:1911.00994).
+ *
+ * C ABI.  Every entry point takes plain pointers and sizes; no C++ or torch types cross this boundary.
+ *
+ * Problem solved (Sect. 2, eq. (spaceprobaug); Sect. 3, Alg. LS; Sect. 4, eq. (eq:LS)): on D = (-1,1)^2
+ * with a body R = {phi > 0} and fluid Omega = D \ R, find (u, v, p, xi) with
+ *     u - alpha lap u + grad p = f      (internal points of the two staggered velocity grids)
+ *     div u - xi = g                    (internal cell centres)
+ *     sum over internal p of p = 0      (mean-pressure row, eq. (eq:midpoint), scaled by 1/count)
+ * and one boundary row per ghost point (biquadratic Dirichlet rows eq. (BCu) for u and v, normal-derivative
+ * rows of the same interpolant for p), Dirichlet rows for the normal velocity on the box walls, and
+ * second-order ghost rows for the tangential velocity on the box walls.  A Crank-Nicolson step (Sect. 2,
+ * eqs. (NSCN1), (extrUdU), (NSitconv)) assembles f from the previous state and calls the solver; the
+ * pressure unknown is dt * p (the paper's rescaling after eq. (spaceprob)).
+ *
+ * Grid layout (all arrays of this ABI): N cells per side (a power of two, >= 16), h = 2/N, W = N + 2.
+ * Each grid array has W*W doubles, entry [(j+1)*W + (i+1)] for i, j in [-1, N]:
+ *     u(i,j) at (-1 + i h,       -1 + (j+1/2) h)     vertical faces   (i = 0 and N are the box walls)
+ *     v(i,j) at (-1 + (i+1/2) h, -1 + j h)           horizontal faces (j = 0 and N are the box walls)
+ *     p(i,j) at (-1 + (i+1/2) h, -1 + (j+1/2) h)     cell centres
+ * Entries that carry no equation are ignored on input and returned as stored.  The level set is sampled
+ * on the half-step lattice: phi[ky*(2N+1) + kx] at (-1 + kx h/2, -1 + ky h/2), kx, ky in [0, 2N], positive
+ * inside the body (Sect. 3.1).
+ *
+ * Ownership: the context owns every device buffer it uses.  Input pointers are borrowed for the duration of
+ * the call and copied (host pointers, or device pointers when on_device != 0, which must belong to the
+ * context's device).  Output pointers are caller-allocated host buffers unless stated otherwise.  All GPU
+ * work is ordered on the stream given to gp_setup_grid; calls that return data to the host synchronise it.
+ * A context is not thread-safe; use one context per stream.
+ *
+ * Errors: every call returns a gp_status; 0 is success.  On error the context stays usable unless stated.
+ */
+#ifndef GPMG_H
+#define GPMG_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct gp_ctx gp_ctx;
+typedef int gp_status;
+
+enum {
+  GP_OK = 0,
+  GP_EINVAL = -1,    /* bad argument (N not a power of two or < 16, NULL pointer, bad option) */
+  GP_ENOMEM = -2,    /* device or host allocation failed */
+  GP_EHIP = -3,      /* HIP runtime error (gp_last_hip_error gives the text) */
+  GP_EGEOM = -4,     /* geometry rejected: body touches the box walls, a finest-level ghost has no usable
+                        row, or an internal cell has no internal face */
+  GP_ENOCONV = -5,   /* max_cycles reached before the tolerance; the iterate is kept, stats are filled */
+  GP_EDIVERGED = -6  /* NaN/Inf or residual growth beyond 1e6 times the initial one */
+};
+
+enum { GP_FP64 = 0, GP_MIXED = 1 };
+
+/* point classes returned by gp_get_classes */
+enum { GP_INACTIVE = 0, GP_INTERNAL = 1, GP_GHOST = 2, GP_WALL_DIRICHLET = 3, GP_WALL_GHOST = 4, GP_EXTENSION = 5,
+       GP_GHOST_EXTRAP = 7 };
+
+/* Solver parameters.  Defaults (gp_default_params): V(2,2) cycles (nu1 = nu2 = 2, gamma = 1; the paper's
+ * W cycle is gamma = 2, Sect. 4.3), lambda_ghost = 2 ghost sweeps per box sweep (Alg. relax), coarsest grid
+ * 8 x 8 cells solved exactly (Sect. 4.3), Alg. 1 march limit 8 steps and bisection accuracy 0.01 h (Sect. 3.3),
+ * fictitious time steps 0.9 (Dirichlet) and 0.9 h (normal derivative) (Sect. 4.1.2), extension band of 4
+ * grid steps, minimum ghost-row diagonal 0.1 (below it the ghost takes an extrapolation row). */
+typedef struct {
+  int nu1, nu2, gamma, lambda_ghost, coarsest_n, march_max, ext_radius;
+  double dtau_dir, dtau_neu_over_h, bisect_eps_over_h, cg_min;
+  int mixed_inner_cycles; /* FP32 cycles per FP64 refinement step in GP_MIXED solves */
+} gp_params;
+
+/* rigid motion: the body frame point of x at time t is R(-omega t) (x - X0 - U t); the boundary velocity at a
+ * boundary point B is U + omega e_z x (B - X0 - U t) */
+typedef struct {
+  double X0x, X0y, Ux, Uy, omega;
+} gp_rigid;
+
+/* analytic body shapes (phi > 0 inside): kind 0: R - r; 1: R^2 - r^2; 2: 1 - (x'^2/A^2 + y'^2/B^2);
+ * 3: 1 - sqrt(x'^2/A^2 + y'^2/B^2) with (x', y') rotated by p[2]; 4: A + B cos(m (theta - theta0)) - r
+ * with p = {A, B, theta0, m}; 5: no body.  p = {R or A, B, angle, m}. */
+typedef struct {
+  int kind;
+  double p[4];
+} gp_shape;
+
+typedef struct {
+  int cycles;      /* multigrid cycles (inner FP32 cycles for GP_MIXED) */
+  int outer;       /* FP64 refinement steps (GP_MIXED), Picard iterations (gp_cn_step) */
+  double res0;     /* initial max-norm residual of the FP64 system */
+  double res;      /* final max-norm residual */
+  double rho;      /* last residual ratio */
+  double seconds;  /* wall time of the call (host clock, includes the final synchronisation) */
+} gp_stats;
+
+void gp_default_params(gp_params *prm);
+
+/* Create a context for an N x N cell grid and Reynolds number Re (used by gp_cn_step).  prm may be NULL
+ * (defaults).  hip_stream is a hipStream_t (NULL = the default stream).  *out is NULL on error. */
+gp_status gp_setup_grid(gp_ctx **out, int N, double Re, const gp_params *prm, void *hip_stream);
+void gp_destroy(gp_ctx *ctx);
+int gp_num_levels(const gp_ctx *ctx);
+const char *gp_strerror(gp_status st);
+const char *gp_last_hip_error(const gp_ctx *ctx);
+
+/* Geometry at time t (Sect. 3.1 - 3.4): classification of every grid point of every level, ghost closure,
+ * Alg. 1 boundary points and ghost rows, extension points, and the exact factorisation of the coarsest
+ * system.  Default boundary data are set: rigid-body velocity at B for velocity ghosts, zero normal pressure
+ * derivative, wall velocities from gp_set_walls.  gp_set_levelset takes sampled phi ((2N+1)^2 doubles);
+ * gp_set_levelset_analytic samples a built-in shape on the device.  motion may be NULL (body at rest). */
+gp_status gp_set_levelset(gp_ctx *ctx, const double *phi_half, int on_device, double t, const gp_rigid *motion);
+gp_status gp_set_levelset_analytic(gp_ctx *ctx, const gp_shape *shape, double t, const gp_rigid *motion);
+
+/* wall velocities: {bottom u, bottom v, right u, right v, top u, top v, left u, left v} (host array of 8) */
+gp_status gp_set_walls(gp_ctx *ctx, const double *walls8);
+
+/* boundary point B and unit normal n (pointing into the body) of every boundary row of the finest level:
+ * host arrays of 3*W*W*2 doubles each (grid-major, then point, then x/y); NaN where a point has no row. Wall
+ * Dirichlet points report the node itself. */
+gp_status gp_get_boundary_geometry(gp_ctx *ctx, double *B, double *nB);
+
+/* boundary data as full grid arrays (W*W each, any may be NULL): the entries at ghost, wall-ghost and
+ * wall-Dirichlet points are used (velocity value at B; for pressure ghosts the normal derivative of dt*p). */
+gp_status gp_set_boundary_values(gp_ctx *ctx, const double *bu, const double *bv, const double *bp, int on_device);
+
+/* linear-system interface (one solve of eq. (spaceprobaug) at the current geometry) */
+gp_status gp_set_alpha(gp_ctx *ctx, double alpha);
+gp_status gp_set_rhs(gp_ctx *ctx, const double *fu, const double *fv, const double *g, int on_device);
+gp_status gp_set_x(gp_ctx *ctx, const double *u, const double *v, const double *p, double xi, int on_device);
+gp_status gp_get_x(gp_ctx *ctx, double *u, double *v, double *p, double *xi, int on_device);
+/* one multigrid cycle on the finest level followed by the mean-pressure projection; *res_inf receives the
+ * max-norm residual afterwards (may be NULL) */
+gp_status gp_mg_vcycle(gp_ctx *ctx, int precision, double *res_inf);
+/* cycles until ||r||_inf <= tol * max(1, ||b||_inf) or max_cycles */
+gp_status gp_solve(gp_ctx *ctx, int precision, double tol, int max_cycles, gp_stats *st);
+/* residual of every row (host array of 3*W*W + 1 doubles, the last entry is the mean-pressure row; may be
+ * NULL) and its max norm */
+gp_status gp_residual(gp_ctx *ctx, double *r, double *res_inf);
+
+/* time stepping: gp_set_state sets (u, v, dt*p, xi) at t^0 in the current geometry; gp_cn_step advances one
+ * step of size dt into the geometry set last (set it for t^{n+1} before the call).  fu, fv: forcing at
+ * t^{n+1/2} (u- and v-grid arrays); g: continuity right-hand side at t^{n+1} (may be NULL for 0).  The first
+ * two steps use the fixed-point iteration of eq. (NSitconv) until the test eq. (iterativeNS) passes with
+ * picard_eps (or picard_max iterations), later steps the extrapolation eq. (extrUdU). */
+gp_status gp_set_state(gp_ctx *ctx, const double *u, const double *v, const double *p, double xi, int on_device);
+gp_status gp_cn_step(gp_ctx *ctx, double dt, const double *fu, const double *fv, const double *g, int on_device,
+                     int precision, double tol, int max_cycles, double picard_eps, int picard_max, gp_stats *st);
+
+/* inspection (tests): classes of one level (host array 3*W_l*W_l bytes); per-point ghost rows of one level
+ * (host arrays, 3*W_l*W_l points): B, nB, theta (2 each), weights (9), column indices (9, global index
+ * g*W_l*W_l + point), dtau, row kind (1 boundary condition, 2 extrapolation, 0 identity, -1 no row);
+ * extension rows (3 sources and 3 weights per point, -1 / NaN where none) */
+gp_status gp_get_classes(gp_ctx *ctx, int level, unsigned char *cls);
+gp_status gp_get_ghost_rows(gp_ctx *ctx, int level, double *B, double *nB, double *theta, double *w9, int *col9,
+                            double *dtau, int *kind);
+gp_status gp_get_ext_rows(gp_ctx *ctx, int level, int *src3, double *w3);
+/* relaxation steps (Alg. relax with nu = steps) on one level in FP64, on that level's current x and b */
+gp_status gp_relax(gp_ctx *ctx, int level, int steps);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GPMG_H */

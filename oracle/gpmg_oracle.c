@@ -732,17 +732,17 @@ static int build_level_geometry(OSolver *S, int l) {
         L->e_pt[e] = k;
         int found = extrap_sources(S, L, g, i, j, &L->e_src[3 * e], &L->e_w[3 * e]);
         if (!found) {
+          /* no sources: the point carries no value */
           for (int q = 0; q < 3; q++) {
             L->e_src[3 * e + q] = -1;
             L->e_w[3 * e + q] = 0;
           }
           L->n_ext_fail++;
+          L->cls[k] = C_INACTIVE;
         }
         e++;
       }
-  for (int k = 0; k < 3 * W * W; k++) L->valued[k] = (unsigned char)valued_class(L->cls[k]);
-  for (int q = 0; q < L->ne; q++)
-    if (L->e_src[3 * q] >= 0) L->valued[L->e_pt[q]] = 1;
+  for (int k = 0; k < 3 * W * W; k++) L->valued[k] = (unsigned char)(valued_class(L->cls[k]) || L->cls[k] == C_EXT);
   /* 7. internal pressure count for the mean row (eq. eq:midpoint) */
   L->Mp = 0;
   for (int k = 2 * W * W; k < 3 * W * W; k++)

@@ -1,0 +1,477 @@
+// C-ABI entry points of the gpmg library: context, geometry, linear-system and inspection calls.
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <limits>
+
+#include "internal.h"
+
+using namespace gpmg;
+
+
+namespace {
+
+template <typename T>
+gp_status dalloc(Ctx *ctx, T **p, size_t n) {
+  *p = nullptr;
+  if (n == 0) n = 1;
+  hipError_t e = hipMalloc((void **)p, n * sizeof(T));
+  if (e != hipSuccess) {
+    ctx->hip_err = std::string("hipMalloc: ") + hipGetErrorString(e);
+    *p = nullptr;
+    return GP_ENOMEM;
+  }
+  return GP_OK;
+}
+
+void dfree(void *p) {
+  if (p) (void)hipFree(p);
+}
+
+bool pow2(int n) { return n > 0 && (n & (n - 1)) == 0; }
+
+__global__ void k_scatter_pts(const uint8_t *cls, int n, int mode, const double *src, double *b, double *x) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  uint8_t c = cls[t];
+  if (mode == 0) {  // boundary data
+    if (c == K_GHOST || c == K_WALLG || c == K_WALLD) b[t] = src[t];
+    if (c == K_WALLD) x[t] = src[t];
+  } else {  // internal right-hand side
+    if (c == K_INT) b[t] = src[t];
+  }
+}
+__global__ void k_zero_int(const uint8_t *cls, int lo, int hi, double *b) {
+  int t = lo + blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < hi && cls[t] == K_INT) b[t] = 0;
+}
+
+gp_status stage_in(Ctx *ctx, const double *src, int on_device, double *dst, size_t n) {
+  GP_HIP(hipMemcpyAsync(dst, src, n * sizeof(double), on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                        ctx->stream));
+  return GP_OK;
+}
+
+gp_status ensure_coarse(Ctx *ctx) {
+  if (!ctx->have_geom) return GP_EINVAL;
+  if (ctx->c_ok) return GP_OK;
+  return coarse_factor(ctx);
+}
+
+gp_status after_geometry(Ctx *ctx) {
+  gp_status st = geometry_build(ctx);
+  ctx->c_ok = 0;
+  if (st) return st;
+  st = default_boundary_values(ctx);
+  if (st) return st;
+  return GP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void gp_default_params(gp_params *p) {
+  if (!p) return;
+  p->nu1 = 2;
+  p->nu2 = 2;
+  p->gamma = 1;
+  p->lambda_ghost = 2;
+  p->coarsest_n = 8;
+  p->march_max = 8;
+  p->ext_radius = 4;
+  p->dtau_dir = 0.9;
+  p->dtau_neu_over_h = 0.9;
+  p->bisect_eps_over_h = 0.01;
+  p->cg_min = 0.1;
+  p->mixed_inner_cycles = 2;
+}
+
+const char *gp_strerror(gp_status st) {
+  switch (st) {
+    case GP_OK: return "ok";
+    case GP_EINVAL: return "invalid argument";
+    case GP_ENOMEM: return "out of memory";
+    case GP_EHIP: return "HIP runtime error";
+    case GP_EGEOM: return "geometry rejected";
+    case GP_ENOCONV: return "no convergence within max_cycles";
+    case GP_EDIVERGED: return "iteration diverged";
+    default: return "unknown status";
+  }
+}
+
+const char *gp_last_hip_error(const gp_ctx *ctx) { return ctx ? ctx->hip_err.c_str() : ""; }
+
+int gp_num_levels(const gp_ctx *ctx) { return ctx ? ctx->L : 0; }
+
+void gp_destroy(gp_ctx *ctx) {
+  if (!ctx) return;
+  (void)hipStreamSynchronize(ctx->stream);
+  for (int l = 0; l < ctx->L; l++) {
+    Geo &G = ctx->geo[l];
+    dfree(G.cls);
+    dfree(G.g_pt);
+    dfree(G.g_col);
+    dfree(G.g_w);
+    dfree(G.g_dtau);
+    dfree(G.g_B);
+    dfree(G.g_nB);
+    dfree(G.g_th);
+    dfree(G.g_kind);
+    dfree(G.e_pt);
+    dfree(G.e_src);
+    dfree(G.e_w);
+    dfree(G.d_mp);
+    dfree(ctx->v64[l].x);
+    dfree(ctx->v64[l].b);
+    dfree(ctx->v64[l].r);
+    dfree(ctx->v32[l].x);
+    dfree(ctx->v32[l].b);
+    dfree(ctx->v32[l].r);
+  }
+  dfree(ctx->phi);
+  dfree(ctx->gtmp);
+  dfree(ctx->d_red);
+  dfree(ctx->d_ticket);
+  dfree(ctx->d_scal);
+  dfree(ctx->d_flags);
+  dfree(ctx->c_map);
+  dfree(ctx->c_A);
+  dfree(ctx->c_work);
+  for (int k = 0; k < 3; k++) {
+    dfree(ctx->cu[k]);
+    dfree(ctx->cv[k]);
+  }
+  dfree(ctx->lapu);
+  dfree(ctx->lapv);
+  dfree(ctx->fbase);
+  dfree(ctx->cku);
+  dfree(ctx->ckv);
+  dfree(ctx->fwork);
+  delete ctx;
+}
+
+gp_status gp_setup_grid(gp_ctx **out, int N, double Re, const gp_params *prm, void *hip_stream) {
+  if (!out) return GP_EINVAL;
+  *out = nullptr;
+  gp_params P;
+  if (prm)
+    P = *prm;
+  else
+    gp_default_params(&P);
+  if (!pow2(N) || N < 16 || !pow2(P.coarsest_n) || P.coarsest_n < 4 || P.coarsest_n > N / 2 || P.nu1 < 0 || P.nu2 < 0 ||
+      P.gamma < 1 || P.lambda_ghost < 0 || P.march_max < 1 || P.ext_radius < 1 || !(Re > 0) || P.mixed_inner_cycles < 1)
+    return GP_EINVAL;
+  gp_ctx *ctx = new gp_ctx();
+  ctx->N = N;
+  ctx->Re = Re;
+  ctx->prm = P;
+  ctx->stream = (hipStream_t)hip_stream;
+  int L = 0;
+  for (int n = N; n >= P.coarsest_n; n /= 2) {
+    Geo &G = ctx->geo[L];
+    G.N = n;
+    G.W = n + 2;
+    G.WW = G.W * G.W;
+    G.n = 3 * G.WW + 1;
+    G.h = 2.0 / n;
+    G.lstride = N / n;
+    G.gcap = 48 * n + 4096;
+    G.ecap = 96 * n + 4096;
+    L++;
+  }
+  ctx->L = L;
+  gp_status st = GP_OK;
+#define ALLOC(p, n)                      \
+  if ((st = dalloc(ctx, &(p), (n)))) { \
+    gp_destroy(ctx);                     \
+    return st;                           \
+  }
+  size_t gmax = 0;
+  for (int l = 0; l < L; l++) {
+    Geo &G = ctx->geo[l];
+    ALLOC(G.cls, (size_t)3 * G.WW);
+    ALLOC(G.g_pt, (size_t)G.gcap);
+    ALLOC(G.g_col, (size_t)9 * G.gcap);
+    ALLOC(G.g_w, (size_t)9 * G.gcap);
+    ALLOC(G.g_dtau, (size_t)G.gcap);
+    ALLOC(G.g_B, (size_t)2 * G.gcap);
+    ALLOC(G.g_nB, (size_t)2 * G.gcap);
+    ALLOC(G.g_th, (size_t)2 * G.gcap);
+    ALLOC(G.g_kind, (size_t)G.gcap);
+    ALLOC(G.e_pt, (size_t)G.ecap);
+    ALLOC(G.e_src, (size_t)3 * G.ecap);
+    ALLOC(G.e_w, (size_t)3 * G.ecap);
+    ALLOC(G.d_mp, 1);
+    ALLOC(ctx->v64[l].x, (size_t)G.n);
+    ALLOC(ctx->v64[l].b, (size_t)G.n);
+    ALLOC(ctx->v64[l].r, (size_t)G.n);
+    gmax = std::max(gmax, (size_t)G.gcap);
+    GP_HIP(hipMemsetAsync(ctx->v64[l].x, 0, G.n * sizeof(double), ctx->stream));
+    GP_HIP(hipMemsetAsync(ctx->v64[l].b, 0, G.n * sizeof(double), ctx->stream));
+    GP_HIP(hipMemsetAsync(ctx->v64[l].r, 0, G.n * sizeof(double), ctx->stream));
+  }
+  ALLOC(ctx->phi, (size_t)(2 * N + 1) * (2 * N + 1));
+  ALLOC(ctx->gtmp, gmax);
+  ALLOC(ctx->d_red, 1024);
+  ALLOC(ctx->d_ticket, 4);
+  ALLOC(ctx->d_scal, 16);
+  ALLOC(ctx->d_flags, 16);
+  GP_HIP(hipMemsetAsync(ctx->d_ticket, 0, 4 * sizeof(unsigned), ctx->stream));
+  Geo &C = ctx->geo[L - 1];
+  ALLOC(ctx->c_map, (size_t)3 * C.WW + 2);
+  ALLOC(ctx->c_A, (size_t)1024 * 1024);
+  ALLOC(ctx->c_work, (size_t)4 * (3 * C.WW + 1) + 2048);
+  int WW = ctx->geo[0].WW;
+  for (int k = 0; k < 3; k++) {
+    ALLOC(ctx->cu[k], (size_t)WW);
+    ALLOC(ctx->cv[k], (size_t)WW);
+  }
+  ALLOC(ctx->lapu, (size_t)WW);
+  ALLOC(ctx->lapv, (size_t)WW);
+  ALLOC(ctx->fbase, (size_t)2 * WW);
+  ALLOC(ctx->cku, (size_t)WW);
+  ALLOC(ctx->ckv, (size_t)WW);
+  ALLOC(ctx->fwork, (size_t)3 * WW + 1);
+#undef ALLOC
+  GP_HIP(hipStreamSynchronize(ctx->stream));
+  *out = ctx;
+  return GP_OK;
+}
+
+gp_status gp_set_levelset(gp_ctx *ctx, const double *phi, int on_device, double t, const gp_rigid *motion) {
+  if (!ctx || !phi) return GP_EINVAL;
+  size_t n = (size_t)(2 * ctx->N + 1) * (2 * ctx->N + 1);
+  gp_status st = stage_in(ctx, phi, on_device, ctx->phi, n);
+  if (st) return st;
+  ctx->t_geom = t;
+  ctx->motion = motion ? *motion : gp_rigid{0, 0, 0, 0, 0};
+  return after_geometry(ctx);
+}
+
+gp_status gp_set_levelset_analytic(gp_ctx *ctx, const gp_shape *shape, double t, const gp_rigid *motion) {
+  if (!ctx || !shape || shape->kind < 0 || shape->kind > 5) return GP_EINVAL;
+  gp_status st = levelset_analytic(ctx, shape, t, motion);
+  if (st) return st;
+  ctx->t_geom = t;
+  ctx->motion = motion ? *motion : gp_rigid{0, 0, 0, 0, 0};
+  return after_geometry(ctx);
+}
+
+gp_status gp_set_walls(gp_ctx *ctx, const double *w) {
+  if (!ctx || !w) return GP_EINVAL;
+  std::memcpy(ctx->walls, w, 8 * sizeof(double));
+  if (ctx->have_geom) return default_boundary_values(ctx);
+  return GP_OK;
+}
+
+gp_status gp_get_boundary_geometry(gp_ctx *ctx, double *B, double *nB) {
+  if (!ctx || !ctx->have_geom || !B || !nB) return GP_EINVAL;
+  Geo &G = ctx->geo[0];
+  int P = 3 * G.WW;
+  std::vector<int> pt(G.ng);
+  std::vector<double> hB(2 * G.ng), hn(2 * G.ng);
+  std::vector<uint8_t> cls(P);
+  GP_HIP(hipMemcpyAsync(pt.data(), G.g_pt, G.ng * sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+  GP_HIP(hipMemcpyAsync(hB.data(), G.g_B, 2 * G.ng * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+  GP_HIP(hipMemcpyAsync(hn.data(), G.g_nB, 2 * G.ng * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+  GP_HIP(hipMemcpyAsync(cls.data(), G.cls, P, hipMemcpyDeviceToHost, ctx->stream));
+  GP_HIP(hipStreamSynchronize(ctx->stream));
+  const double nan = std::numeric_limits<double>::quiet_NaN();
+  for (int k = 0; k < 2 * P; k++) B[k] = nB[k] = nan;
+  for (int r = 0; r < G.ng; r++) {
+    int k = pt[r];
+    if (cls[k] == K_GHOSTX) continue;
+    B[2 * k] = hB[2 * r];
+    B[2 * k + 1] = hB[2 * r + 1];
+    nB[2 * k] = hn[2 * r];
+    nB[2 * k + 1] = hn[2 * r + 1];
+  }
+  for (int k = 0; k < P; k++) {
+    if (cls[k] != K_WALLD) continue;
+    int g = k / G.WW, q = k % G.WW, j = q / G.W - 1, i = q % G.W - 1;
+    B[2 * k] = (g == 0) ? -1.0 + i * G.h : -1.0 + (i + 0.5) * G.h;
+    B[2 * k + 1] = (g == 1) ? -1.0 + j * G.h : -1.0 + (j + 0.5) * G.h;
+  }
+  return GP_OK;
+}
+
+gp_status gp_set_boundary_values(gp_ctx *ctx, const double *bu, const double *bv, const double *bp, int on_device) {
+  if (!ctx || !ctx->have_geom) return GP_EINVAL;
+  Geo &G = ctx->geo[0];
+  const double *src[3] = {bu, bv, bp};
+  for (int g = 0; g < 3; g++) {
+    if (!src[g]) continue;
+    gp_status st = stage_in(ctx, src[g], on_device, ctx->fwork + (size_t)g * G.WW, G.WW);
+    if (st) return st;
+    k_scatter_pts<<<nblk(G.WW), TPB, 0, ctx->stream>>>(G.cls + g * G.WW, G.WW, 0, ctx->fwork + (size_t)g * G.WW,
+                                                       ctx->v64[0].b + (size_t)g * G.WW, ctx->v64[0].x + (size_t)g * G.WW);
+  }
+  GP_HIP(hipGetLastError());
+  GP_HIP(hipStreamSynchronize(ctx->stream));
+  return GP_OK;
+}
+
+gp_status gp_set_alpha(gp_ctx *ctx, double alpha) {
+  if (!ctx || !(alpha >= 0)) return GP_EINVAL;
+  if (alpha != ctx->alpha) ctx->c_ok = 0;
+  ctx->alpha = alpha;
+  return GP_OK;
+}
+
+gp_status gp_set_rhs(gp_ctx *ctx, const double *fu, const double *fv, const double *g, int on_device) {
+  if (!ctx || !ctx->have_geom) return GP_EINVAL;
+  Geo &G = ctx->geo[0];
+  const double *src[3] = {fu, fv, g};
+  for (int q = 0; q < 3; q++) {
+    if (src[q]) {
+      gp_status st = stage_in(ctx, src[q], on_device, ctx->fwork + (size_t)q * G.WW, G.WW);
+      if (st) return st;
+      k_scatter_pts<<<nblk(G.WW), TPB, 0, ctx->stream>>>(G.cls + q * G.WW, G.WW, 1, ctx->fwork + (size_t)q * G.WW,
+                                                         ctx->v64[0].b + (size_t)q * G.WW, nullptr);
+    } else {
+      k_zero_int<<<nblk(G.WW), TPB, 0, ctx->stream>>>(G.cls, q * G.WW, (q + 1) * G.WW, ctx->v64[0].b);
+    }
+  }
+  GP_HIP(hipMemsetAsync(ctx->v64[0].b + 3 * (size_t)G.WW, 0, sizeof(double), ctx->stream));
+  GP_HIP(hipGetLastError());
+  GP_HIP(hipStreamSynchronize(ctx->stream));
+  return GP_OK;
+}
+
+gp_status gp_set_x(gp_ctx *ctx, const double *u, const double *v, const double *p, double xi, int on_device) {
+  if (!ctx || !u || !v || !p) return GP_EINVAL;
+  Geo &G = ctx->geo[0];
+  double *x = ctx->v64[0].x;
+  gp_status st;
+  if ((st = stage_in(ctx, u, on_device, x, G.WW))) return st;
+  if ((st = stage_in(ctx, v, on_device, x + G.WW, G.WW))) return st;
+  if ((st = stage_in(ctx, p, on_device, x + 2 * (size_t)G.WW, G.WW))) return st;
+  GP_HIP(hipMemcpyAsync(x + 3 * (size_t)G.WW, &xi, sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+  GP_HIP(hipStreamSynchronize(ctx->stream));
+  return GP_OK;
+}
+
+gp_status gp_get_x(gp_ctx *ctx, double *u, double *v, double *p, double *xi, int on_device) {
+  if (!ctx) return GP_EINVAL;
+  Geo &G = ctx->geo[0];
+  double *x = ctx->v64[0].x;
+  hipMemcpyKind k = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+  if (u) GP_HIP(hipMemcpyAsync(u, x, G.WW * sizeof(double), k, ctx->stream));
+  if (v) GP_HIP(hipMemcpyAsync(v, x + G.WW, G.WW * sizeof(double), k, ctx->stream));
+  if (p) GP_HIP(hipMemcpyAsync(p, x + 2 * (size_t)G.WW, G.WW * sizeof(double), k, ctx->stream));
+  if (xi) GP_HIP(hipMemcpyAsync(xi, x + 3 * (size_t)G.WW, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+  GP_HIP(hipStreamSynchronize(ctx->stream));
+  return GP_OK;
+}
+
+gp_status gp_mg_vcycle(gp_ctx *ctx, int precision, double *res_inf) {
+  if (!ctx || precision != GP_FP64) return GP_EINVAL;
+  gp_status st = ensure_coarse(ctx);
+  if (st) return st;
+  return mg_cycle64(ctx, res_inf);
+}
+
+gp_status gp_solve(gp_ctx *ctx, int precision, double tol, int max_cycles, gp_stats *s) {
+  if (!ctx || !(tol > 0) || max_cycles < 0 || (precision != GP_FP64 && precision != GP_MIXED)) return GP_EINVAL;
+  gp_status st = ensure_coarse(ctx);
+  if (st) return st;
+  return mg_solve(ctx, precision, tol, max_cycles, s);
+}
+
+gp_status gp_residual(gp_ctx *ctx, double *r, double *res_inf) {
+  if (!ctx || !ctx->have_geom) return GP_EINVAL;
+  double ri;
+  gp_status st = residual64(ctx, 0, &ri);
+  if (st) return st;
+  if (res_inf) *res_inf = ri;
+  if (r) {
+    GP_HIP(hipMemcpyAsync(r, ctx->v64[0].r, ctx->geo[0].n * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    GP_HIP(hipStreamSynchronize(ctx->stream));
+  }
+  return GP_OK;
+}
+
+gp_status gp_get_classes(gp_ctx *ctx, int level, unsigned char *cls) {
+  if (!ctx || !cls || level < 0 || level >= ctx->L) return GP_EINVAL;
+  Geo &G = ctx->geo[level];
+  GP_HIP(hipMemcpyAsync(cls, G.cls, 3 * (size_t)G.WW, hipMemcpyDeviceToHost, ctx->stream));
+  GP_HIP(hipStreamSynchronize(ctx->stream));
+  return GP_OK;
+}
+
+gp_status gp_get_ghost_rows(gp_ctx *ctx, int level, double *B, double *nB, double *th, double *w9, int *col9, double *dtau,
+                            int *kind) {
+  if (!ctx || level < 0 || level >= ctx->L || !B || !nB || !th || !w9 || !col9 || !dtau || !kind) return GP_EINVAL;
+  Geo &G = ctx->geo[level];
+  int P = 3 * G.WW, ng = G.ng;
+  std::vector<int> pt(ng), col(9 * ng);
+  std::vector<double> hB(2 * ng), hn(2 * ng), ht(2 * ng), hw(9 * ng), hd(ng);
+  std::vector<int8_t> hk(ng);
+  hipStream_t s = ctx->stream;
+  GP_HIP(hipMemcpyAsync(pt.data(), G.g_pt, ng * sizeof(int), hipMemcpyDeviceToHost, s));
+  GP_HIP(hipMemcpyAsync(col.data(), G.g_col, 9 * ng * sizeof(int), hipMemcpyDeviceToHost, s));
+  GP_HIP(hipMemcpyAsync(hB.data(), G.g_B, 2 * ng * sizeof(double), hipMemcpyDeviceToHost, s));
+  GP_HIP(hipMemcpyAsync(hn.data(), G.g_nB, 2 * ng * sizeof(double), hipMemcpyDeviceToHost, s));
+  GP_HIP(hipMemcpyAsync(ht.data(), G.g_th, 2 * ng * sizeof(double), hipMemcpyDeviceToHost, s));
+  GP_HIP(hipMemcpyAsync(hw.data(), G.g_w, 9 * ng * sizeof(double), hipMemcpyDeviceToHost, s));
+  GP_HIP(hipMemcpyAsync(hd.data(), G.g_dtau, ng * sizeof(double), hipMemcpyDeviceToHost, s));
+  GP_HIP(hipMemcpyAsync(hk.data(), G.g_kind, ng, hipMemcpyDeviceToHost, s));
+  GP_HIP(hipStreamSynchronize(s));
+  const double nan = std::numeric_limits<double>::quiet_NaN();
+  for (int k = 0; k < P; k++) {
+    for (int q = 0; q < 2; q++) B[2 * k + q] = nB[2 * k + q] = th[2 * k + q] = nan;
+    for (int q = 0; q < 9; q++) {
+      w9[9 * k + q] = nan;
+      col9[9 * k + q] = -1;
+    }
+    dtau[k] = nan;
+    kind[k] = -1;
+  }
+  for (int r = 0; r < ng; r++) {
+    int k = pt[r];
+    for (int q = 0; q < 2; q++) {
+      B[2 * k + q] = hB[2 * r + q];
+      nB[2 * k + q] = hn[2 * r + q];
+      th[2 * k + q] = ht[2 * r + q];
+    }
+    for (int q = 0; q < 9; q++) {
+      w9[9 * k + q] = hw[9 * r + q];
+      col9[9 * k + q] = col[9 * r + q];
+    }
+    dtau[k] = hd[r];
+    kind[k] = hk[r];
+  }
+  return GP_OK;
+}
+
+gp_status gp_get_ext_rows(gp_ctx *ctx, int level, int *src3, double *w3) {
+  if (!ctx || level < 0 || level >= ctx->L || !src3 || !w3) return GP_EINVAL;
+  Geo &G = ctx->geo[level];
+  int P = 3 * G.WW, ne = G.ne;
+  std::vector<int> pt(ne), src(3 * ne);
+  std::vector<double> w(3 * ne);
+  GP_HIP(hipMemcpyAsync(pt.data(), G.e_pt, ne * sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+  GP_HIP(hipMemcpyAsync(src.data(), G.e_src, 3 * ne * sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+  GP_HIP(hipMemcpyAsync(w.data(), G.e_w, 3 * ne * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+  GP_HIP(hipStreamSynchronize(ctx->stream));
+  for (int k = 0; k < 3 * P; k++) {
+    src3[k] = -1;
+    w3[k] = std::numeric_limits<double>::quiet_NaN();
+  }
+  for (int e = 0; e < ne; e++) {
+    if (src[3 * e] < 0) continue;
+    for (int q = 0; q < 3; q++) {
+      src3[3 * pt[e] + q] = src[3 * e + q];
+      w3[3 * pt[e] + q] = w[3 * e + q];
+    }
+  }
+  return GP_OK;
+}
+
+gp_status gp_relax(gp_ctx *ctx, int level, int steps) {
+  if (!ctx || !ctx->have_geom || level < 0 || level >= ctx->L || steps < 0) return GP_EINVAL;
+  return relax64(ctx, level, steps);
+}
+
+}  // extern "C"

@@ -1,0 +1,827 @@
+// Geometry on the device: level-set sampling, classification of the three staggered grids, ghost closure,
+// Alg. 1 boundary points, ghost rows (eq. (BCu) and its normal derivative), extension points, and the exact
+// factorisation of the coarsest system.  Arithmetic is kept in FP64 everywhere (small cut cells make the
+// ghost coefficients ill-conditioned); this file is built with FMA contraction off so that the branch
+// decisions of the bisection see the same roundings as a plain IEEE evaluation.
+#include <cmath>
+#include <cstdio>
+
+#include "internal.h"
+
+namespace gpmg {
+
+// ---------------------------------------------------------------------------------------------------------
+// lattice view of one level: phi of the level at lattice index (kx, ky), kx, ky in [0, 2N]
+// ---------------------------------------------------------------------------------------------------------
+struct Lat {
+  const double *phi;
+  int Lf;  // fine lattice points per axis
+  int s;   // stride
+  int N;   // level cells
+  double h;
+};
+
+__device__ __forceinline__ double lat_at(const Lat &L, int kx, int ky) {
+  return L.phi[(size_t)(ky * L.s) * L.Lf + (size_t)(kx * L.s)];
+}
+
+__device__ __forceinline__ double sgn1(double z) { return z >= 0.0 ? 1.0 : -1.0; }
+
+// bilinear interpolant of phi on the lattice cell containing (x, y) (half-open cells, clamped), value and gradient
+__device__ void bilin(const Lat &L, double x, double y, double *val, double *gx, double *gy) {
+  const double hl = 0.5 * L.h;
+  const int nl = 2 * L.N + 1;
+  double fx = (x + 1.0) / hl, fy = (y + 1.0) / hl;
+  int kx = (int)floor(fx), ky = (int)floor(fy);
+  kx = kx < 0 ? 0 : (kx > nl - 2 ? nl - 2 : kx);
+  ky = ky < 0 ? 0 : (ky > nl - 2 ? nl - 2 : ky);
+  double tx = fx - kx, ty = fy - ky;
+  double p00 = lat_at(L, kx, ky), p10 = lat_at(L, kx + 1, ky), p01 = lat_at(L, kx, ky + 1), p11 = lat_at(L, kx + 1, ky + 1);
+  if (val) *val = (1 - tx) * (1 - ty) * p00 + tx * (1 - ty) * p10 + (1 - tx) * ty * p01 + tx * ty * p11;
+  if (gx) *gx = ((1 - ty) * (p10 - p00) + ty * (p11 - p01)) / hl;
+  if (gy) *gy = ((1 - tx) * (p01 - p00) + tx * (p11 - p10)) / hl;
+}
+
+__device__ void normal_at(const Lat &L, double x, double y, double *nx, double *ny) {
+  double gx, gy;
+  bilin(L, x, y, nullptr, &gx, &gy);
+  double m = sqrt(gx * gx + gy * gy);
+  if (m > 0) {
+    *nx = gx / m;
+    *ny = gy / m;
+  } else {
+    *nx = 0;
+    *ny = 0;
+  }
+}
+
+// node (g, i, j): coordinates and lattice indices
+__device__ __forceinline__ void node_pos(int g, int i, int j, double h, double *x, double *y) {
+  *x = (g == 0) ? -1.0 + i * h : -1.0 + (i + 0.5) * h;
+  *y = (g == 1) ? -1.0 + j * h : -1.0 + (j + 0.5) * h;
+}
+__device__ __forceinline__ void node_lat(int g, int i, int j, int *kx, int *ky) {
+  *kx = (g == 0) ? 2 * i : 2 * i + 1;
+  *ky = (g == 1) ? 2 * j : 2 * j + 1;
+}
+__device__ __forceinline__ bool inside(int N, int i, int j) { return i >= -1 && i <= N && j >= -1 && j <= N; }
+__device__ __forceinline__ int gix(int W, int g, int i, int j) { return g * W * W + (j + 1) * W + (i + 1); }
+__device__ __forceinline__ uint8_t cls_of(const uint8_t *cls, int N, int W, int g, int i, int j) {
+  return inside(N, i, j) ? cls[gix(W, g, i, j)] : (uint8_t)K_INACTIVE;
+}
+__device__ __forceinline__ bool has_value(uint8_t c) {
+  return c == K_INT || c == K_GHOST || c == K_WALLD || c == K_WALLG || c == K_GHOSTX;
+}
+
+// ---------------------------------------------------------------------------------------------------------
+// level set (Sect. 3.1; shapes of eq. (eq:domains); rigid motion of Sect. 5)
+// ---------------------------------------------------------------------------------------------------------
+__device__ double shape_value(int kind, double a0, double a1, double a2, double a3, double xb, double yb) {
+  if (kind == 0) return a0 - sqrt(xb * xb + yb * yb);
+  if (kind == 1) return a0 * a0 - (xb * xb + yb * yb);
+  if (kind == 2 || kind == 3) {
+    double c = cos(a2), s = sin(a2);
+    double xr = c * xb - s * yb, yr = s * xb + c * yb;
+    double q = xr * xr / (a0 * a0) + yr * yr / (a1 * a1);
+    return kind == 2 ? 1.0 - q : 1.0 - sqrt(q);
+  }
+  if (kind == 4) {
+    double r = sqrt(xb * xb + yb * yb);
+    if (r == 0.0) return a0 + a1;
+    return a0 + a1 * cos(a3 * (atan2(yb, xb) - a2)) - r;
+  }
+  return -1.0;
+}
+
+__global__ void k_levelset(double *phi, int N, int kind, double a0, double a1, double a2, double a3, double X, double Y,
+                           double ang) {
+  int nl = 2 * N + 1;
+  long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (t >= (long)nl * nl) return;
+  int kx = (int)(t % nl), ky = (int)(t / nl);
+  double hl = 1.0 / N;
+  double x = -1.0 + kx * hl - X, y = -1.0 + ky * hl - Y;
+  double c = cos(ang), s = sin(ang);
+  phi[t] = shape_value(kind, a0, a1, a2, a3, c * x + s * y, -s * x + c * y);
+}
+
+// ---------------------------------------------------------------------------------------------------------
+// classification (Alg. LS: internal iff phi(P) < 0, each grid on its own)
+// ---------------------------------------------------------------------------------------------------------
+__global__ void k_classify(Lat L, uint8_t *cls, int W, int finest, int *flags) {
+  int N = L.N;
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= 3 * W * W) return;
+  int g = t / (W * W), loc = t % (W * W), j = loc / W - 1, i = loc % W - 1;
+  uint8_t c = K_INACTIVE;
+  int kx, ky;
+  node_lat(g, i, j, &kx, &ky);
+  if (g == 0) {
+    if ((i == 0 || i == N) && j >= 0 && j <= N - 1)
+      c = K_WALLD;
+    else if ((j == -1 || j == N) && i >= 1 && i <= N - 1)
+      c = K_WALLG;
+    else if (i >= 1 && i <= N - 1 && j >= 0 && j <= N - 1)
+      c = lat_at(L, kx, ky) < 0 ? K_INT : K_BODY;
+  } else if (g == 1) {
+    if ((j == 0 || j == N) && i >= 0 && i <= N - 1)
+      c = K_WALLD;
+    else if ((i == -1 || i == N) && j >= 1 && j <= N - 1)
+      c = K_WALLG;
+    else if (i >= 0 && i <= N - 1 && j >= 1 && j <= N - 1)
+      c = lat_at(L, kx, ky) < 0 ? K_INT : K_BODY;
+  } else {
+    if (i >= 0 && i <= N - 1 && j >= 0 && j <= N - 1) c = lat_at(L, kx, ky) < 0 ? K_INT : K_BODY;
+  }
+  if (finest && c == K_WALLD && lat_at(L, kx, ky) >= 0) atomicOr(&flags[1], 1);
+  cls[t] = c;
+}
+
+__device__ __forceinline__ void to_ghost(uint8_t *cls, int N, int W, int g, int i, int j, int *changed) {
+  if (!inside(N, i, j)) return;
+  int k = gix(W, g, i, j);
+  if (cls[k] == K_BODY) {
+    cls[k] = K_GHOST;
+    if (changed) *changed = 1;
+  }
+}
+
+// external points used by internal equations become ghosts (Sect. 3.3)
+__global__ void k_seed(uint8_t *cls, int N, int W) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= 3 * W * W) return;
+  if (cls[t] != K_INT) return;
+  int g = t / (W * W), loc = t % (W * W), j = loc / W - 1, i = loc % W - 1;
+  if (g == 0) {
+    to_ghost(cls, N, W, 0, i - 1, j, nullptr);
+    to_ghost(cls, N, W, 0, i + 1, j, nullptr);
+    to_ghost(cls, N, W, 0, i, j - 1, nullptr);
+    to_ghost(cls, N, W, 0, i, j + 1, nullptr);
+    to_ghost(cls, N, W, 2, i - 1, j, nullptr);
+    to_ghost(cls, N, W, 2, i, j, nullptr);
+  } else if (g == 1) {
+    to_ghost(cls, N, W, 1, i - 1, j, nullptr);
+    to_ghost(cls, N, W, 1, i + 1, j, nullptr);
+    to_ghost(cls, N, W, 1, i, j - 1, nullptr);
+    to_ghost(cls, N, W, 1, i, j + 1, nullptr);
+    to_ghost(cls, N, W, 2, i, j - 1, nullptr);
+    to_ghost(cls, N, W, 2, i, j, nullptr);
+  } else {
+    to_ghost(cls, N, W, 0, i, j, nullptr);
+    to_ghost(cls, N, W, 0, i + 1, j, nullptr);
+    to_ghost(cls, N, W, 1, i, j, nullptr);
+    to_ghost(cls, N, W, 1, i, j + 1, nullptr);
+  }
+}
+
+// external points of the upwind nine-point stencil of a ghost are ghosts too (closure, Sect. 3.3)
+__global__ void k_closure(Lat L, uint8_t *cls, int W, int *changed) {
+  int N = L.N;
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= 3 * W * W) return;
+  if (cls[t] != K_GHOST) return;
+  int g = t / (W * W), loc = t % (W * W), j = loc / W - 1, i = loc % W - 1;
+  double x, y, nx, ny;
+  node_pos(g, i, j, L.h, &x, &y);
+  normal_at(L, x, y, &nx, &ny);
+  int sx = (int)sgn1(nx), sy = (int)sgn1(ny);
+  for (int ky = 0; ky < 3; ky++)
+    for (int kx = 0; kx < 3; kx++) to_ghost(cls, N, W, g, i - sx * kx, j - sy * ky, changed);
+}
+
+// external points within R index steps of an internal point of the same grid carry extension values
+__global__ void k_ext_mark(uint8_t *cls, int N, int W, int R) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= 3 * W * W) return;
+  if (cls[t] != K_BODY) return;
+  int g = t / (W * W), loc = t % (W * W), j = loc / W - 1, i = loc % W - 1;
+  bool near = false;
+  for (int dj = -R; dj <= R && !near; dj++)
+    for (int di = -R; di <= R && !near; di++)
+      if (cls_of(cls, N, W, g, i + di, j + dj) == K_INT) near = true;
+  // a point never reads another point's BODY/EXT state here, so the in-place update is race free
+  cls[t] = near ? K_EXT : K_BODY;
+}
+__global__ void k_body_to_inactive(uint8_t *cls, int n) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n && cls[t] == K_BODY) cls[t] = K_INACTIVE;
+}
+
+// compaction (order does not matter: every consumer of these lists is order independent)
+__global__ void k_compact(const uint8_t *cls, int n, int mode, int *list, int cap, int *counter) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  uint8_t c = cls[t];
+  bool take = (mode == 0) ? (c == K_GHOST || c == K_WALLG) : (c == K_EXT);
+  if (!take) return;
+  int slot = atomicAdd(counter, 1);
+  if (slot < cap) list[slot] = t;
+}
+
+// ---------------------------------------------------------------------------------------------------------
+// ghost rows
+// ---------------------------------------------------------------------------------------------------------
+__device__ __forceinline__ void lagr3(double t, double T[3]) {
+  T[0] = (1 - t) * (2 - t) / 2;
+  T[1] = t * (2 - t);
+  T[2] = t * (t - 1) / 2;
+}
+__device__ __forceinline__ void dlagr3(double t, double D[3]) {
+  D[0] = t - 1.5;
+  D[1] = 2 - 2 * t;
+  D[2] = t - 0.5;
+}
+
+// Alg. 1 (march along the bilinear normal by h/2, then bisection on the last segment); returns success
+__device__ bool boundary_point(const Lat &L, double xg, double yg, double phig, int march_max, int nbis, double *Bx,
+                               double *By) {
+  double hx = xg, hy = yg, ph = phig, kx = xg, ky = yg;
+  int it = 0;
+  while (ph > 0) {
+    if (it == march_max) return false;
+    kx = hx;
+    ky = hy;
+    double nx, ny;
+    normal_at(L, hx, hy, &nx, &ny);
+    hx = hx - 0.5 * L.h * nx;
+    hy = hy - 0.5 * L.h * ny;
+    bilin(L, hx, hy, &ph, nullptr, nullptr);
+    it++;
+  }
+  if (it == 0 || ph == 0.0) {
+    *Bx = hx;
+    *By = hy;
+    return true;
+  }
+  double bx = hx, by = hy;
+  for (int q = 0; q < nbis; q++) {
+    bx = 0.5 * (hx + kx);
+    by = 0.5 * (hy + ky);
+    double pb;
+    bilin(L, bx, by, &pb, nullptr, nullptr);
+    if (pb * ph < 0) {
+      kx = bx;
+      ky = by;
+    } else {
+      hx = bx;
+      hy = by;
+      ph = pb;
+    }
+  }
+  *Bx = bx;
+  *By = by;
+  return true;
+}
+
+struct RowArgs {
+  int *g_pt, *g_col;
+  double *g_w, *g_dtau, *g_B, *g_nB, *g_th;
+  int8_t *g_kind;
+  int ng;
+};
+
+// pass A: wall-ghost rows and boundary-condition rows; unusable rows turn their point into GHOSTX
+__global__ void k_ghost_rows(Lat L, uint8_t *cls, int W, RowArgs R, int march_max, int nbis, double cg_min,
+                             double dtau_dir, double dtau_neu) {
+  int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= R.ng) return;
+  int N = L.N;
+  double h = L.h;
+  int k = R.g_pt[r];
+  int g = k / (W * W), loc = k % (W * W), j = loc / W - 1, i = loc % W - 1;
+  uint8_t c = cls[k];
+  int col[9];
+  double w[9];
+  for (int q = 0; q < 9; q++) {
+    col[q] = k;
+    w[q] = 0;
+  }
+  double xg, yg;
+  node_pos(g, i, j, h, &xg, &yg);
+  bool ok = true;
+  double Bx = xg, By = yg, nbx = 0, nby = 0, thx = 0, thy = 0, dtau = dtau_dir;
+  if (c == K_WALLG) {
+    // tangential velocity on the box wall: eq. (BCu) with exact wall geometry (theta_n = 1/2, theta_t = 0)
+    int di = 0, dj = 0;
+    if (g == 0) {
+      dj = (j == -1) ? 1 : -1;
+      By = (j == -1) ? -1.0 : 1.0;
+      nby = (j == -1) ? -1.0 : 1.0;
+      thy = 0.5;
+    } else {
+      di = (i == -1) ? 1 : -1;
+      Bx = (i == -1) ? -1.0 : 1.0;
+      nbx = (i == -1) ? -1.0 : 1.0;
+      thx = 0.5;
+    }
+    double T[3];
+    lagr3(0.5, T);
+    for (int q = 0; q < 3; q++) {
+      col[q] = gix(W, g, i + q * di, j + q * dj);
+      w[q] = T[q];
+      if (q > 0 && cls[col[q]] != K_INT) ok = false;
+    }
+  } else {
+    int kx, ky;
+    node_lat(g, i, j, &kx, &ky);
+    double phig = lat_at(L, kx, ky);
+    double ngx, ngy;
+    normal_at(L, xg, yg, &ngx, &ngy);
+    double sx = sgn1(ngx), sy = sgn1(ngy);
+    ok = boundary_point(L, xg, yg, phig, march_max, nbis, &Bx, &By);
+    thx = sx * (xg - Bx) / h;
+    thy = sy * (yg - By) / h;
+    normal_at(L, Bx, By, &nbx, &nby);
+    for (int ky2 = 0; ky2 < 3; ky2++)
+      for (int kx2 = 0; kx2 < 3; kx2++) {
+        int ii = i - (int)sx * kx2, jj = j - (int)sy * ky2;
+        if (!inside(N, ii, jj)) {
+          ok = false;
+          continue;
+        }
+        col[ky2 * 3 + kx2] = gix(W, g, ii, jj);
+        if (!has_value(cls[col[ky2 * 3 + kx2]])) ok = false;
+      }
+    double Tx[3], Ty[3];
+    lagr3(thx, Tx);
+    lagr3(thy, Ty);
+    if (g < 2) {
+      for (int ky2 = 0; ky2 < 3; ky2++)
+        for (int kx2 = 0; kx2 < 3; kx2++) w[ky2 * 3 + kx2] = Tx[kx2] * Ty[ky2];
+    } else {
+      double Dx[3], Dy[3];
+      dlagr3(thx, Dx);
+      dlagr3(thy, Dy);
+      for (int ky2 = 0; ky2 < 3; ky2++)
+        for (int kx2 = 0; kx2 < 3; kx2++)
+          w[ky2 * 3 + kx2] = -(nbx * sx * Dx[kx2] * Ty[ky2] + nby * sy * Tx[kx2] * Dy[ky2]) / h;
+      dtau = dtau_neu;
+    }
+    if (!(thx > -0.5 && thx < 1.0 && thy > -0.5 && thy < 1.0)) ok = false;
+    if (!((g < 2 ? w[0] : w[0] * h) > cg_min)) ok = false;
+  }
+  for (int q = 0; q < 9; q++) {
+    R.g_col[9 * r + q] = col[q];
+    R.g_w[9 * r + q] = w[q];
+  }
+  R.g_dtau[r] = dtau;
+  R.g_B[2 * r] = Bx;
+  R.g_B[2 * r + 1] = By;
+  R.g_nB[2 * r] = nbx;
+  R.g_nB[2 * r + 1] = nby;
+  R.g_th[2 * r] = thx;
+  R.g_th[2 * r + 1] = thy;
+  R.g_kind[r] = ok ? 1 : 0;
+  if (!ok) cls[k] = K_GHOSTX;
+}
+
+// quadratic extrapolation from the first three internal / boundary-condition points met towards the fluid,
+// along the grid axis closest to the normal (the other axis as a second choice)
+__device__ bool extrap_src(const Lat &L, const uint8_t *cls, int W, int g, int i, int j, int src[3], double w[3]) {
+  int N = L.N;
+  double x, y, nx, ny;
+  node_pos(g, i, j, L.h, &x, &y);
+  normal_at(L, x, y, &nx, &ny);
+  int first = fabs(nx) >= fabs(ny) ? 0 : 1;
+  for (int a = 0; a < 2; a++) {
+    int ax = (a == 0) ? first : 1 - first;
+    int s = (int)sgn1(ax == 0 ? nx : ny);
+    int di = ax == 0 ? -s : 0, dj = ax == 1 ? -s : 0;
+    int k0 = 0;
+    for (int q = 1; q <= 4; q++) {
+      uint8_t c = cls_of(cls, N, W, g, i + q * di, j + q * dj);
+      if (c == K_INT || c == K_GHOST) {
+        k0 = q;
+        break;
+      }
+    }
+    if (!k0) continue;
+    bool good = true;
+    for (int q = 0; q < 3; q++) {
+      uint8_t c = cls_of(cls, N, W, g, i + (k0 + q) * di, j + (k0 + q) * dj);
+      if (!(c == K_INT || c == K_GHOST)) good = false;
+    }
+    if (!good) continue;
+    double kk = k0;
+    w[0] = (kk + 1) * (kk + 2) / 2;
+    w[1] = -kk * (kk + 2);
+    w[2] = kk * (kk + 1) / 2;
+    for (int q = 0; q < 3; q++) src[q] = gix(W, g, i + (k0 + q) * di, j + (k0 + q) * dj);
+    return true;
+  }
+  return false;
+}
+
+// pass B: extrapolation rows x_G - sum w x_src = 0 for GHOSTX points (identity x_G = 0 when no source exists)
+__global__ void k_ghostx_rows(Lat L, const uint8_t *cls, int W, RowArgs R, int finest, int *flags) {
+  int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= R.ng) return;
+  int k = R.g_pt[r];
+  if (cls[k] != K_GHOSTX) return;
+  int g = k / (W * W), loc = k % (W * W), j = loc / W - 1, i = loc % W - 1;
+  for (int q = 0; q < 9; q++) {
+    R.g_col[9 * r + q] = k;
+    R.g_w[9 * r + q] = 0;
+  }
+  R.g_w[9 * r] = 1.0;
+  R.g_dtau[r] = 1.0;
+  int src[3];
+  double w[3];
+  if (extrap_src(L, cls, W, g, i, j, src, w)) {
+    for (int q = 0; q < 3; q++) {
+      R.g_col[9 * r + 1 + q] = src[q];
+      R.g_w[9 * r + 1 + q] = -w[q];
+    }
+    R.g_kind[r] = 2;
+  } else {
+    R.g_kind[r] = 0;
+    if (finest) atomicAdd(&flags[4], 1);
+  }
+}
+
+__global__ void k_ext_rows(Lat L, uint8_t *cls, int W, const int *e_pt, int ne, int *e_src, double *e_w) {
+  int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= ne) return;
+  int k = e_pt[e];
+  int g = k / (W * W), loc = k % (W * W), j = loc / W - 1, i = loc % W - 1;
+  int src[3];
+  double w[3];
+  if (extrap_src(L, cls, W, g, i, j, src, w)) {
+    for (int q = 0; q < 3; q++) {
+      e_src[3 * e + q] = src[q];
+      e_w[3 * e + q] = w[q];
+    }
+  } else {
+    for (int q = 0; q < 3; q++) {
+      e_src[3 * e + q] = -1;
+      e_w[3 * e + q] = 0;
+    }
+  }
+}
+// points whose extension has no source carry no value (separate pass: extrap_src above reads only INT/GHOST)
+__global__ void k_ext_fail(uint8_t *cls, const int *e_pt, int ne, const int *e_src) {
+  int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= ne) return;
+  if (e_src[3 * e] < 0) cls[e_pt[e]] = K_INACTIVE;
+}
+
+__global__ void k_count_mp(const uint8_t *cls, int W, int *mp) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= W * W) return;
+  if (cls[2 * W * W + t] == K_INT) atomicAdd(mp, 1);
+}
+
+// finest level: every internal cell needs an internal face (else its box has no velocity unknown)
+__global__ void k_empty_cells(const uint8_t *cls, int N, int W, int *flags) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= N * N) return;
+  int i = t % N, j = t / N;
+  if (cls[gix(W, 2, i, j)] != K_INT) return;
+  int nf = (cls[gix(W, 0, i, j)] == K_INT) + (cls[gix(W, 0, i + 1, j)] == K_INT) + (cls[gix(W, 1, i, j)] == K_INT) +
+           (cls[gix(W, 1, i, j + 1)] == K_INT);
+  if (nf == 0) atomicOr(&flags[1], 2);
+}
+
+// ---------------------------------------------------------------------------------------------------------
+// boundary data of the finest level
+// ---------------------------------------------------------------------------------------------------------
+__global__ void k_bvals_rows(const uint8_t *cls, int W, RowArgs R, double *b, double X0x, double X0y, double Ux, double Uy,
+                             double om, double t, double wbu, double wtu, double wlv, double wrv) {
+  int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= R.ng) return;
+  int k = R.g_pt[r];
+  int g = k / (W * W), loc = k % (W * W), j = loc / W - 1, i = loc % W - 1;
+  uint8_t c = cls[k];
+  double val = 0;
+  if (c == K_GHOST) {
+    double X = X0x + Ux * t, Y = X0y + Uy * t;
+    double Bx = R.g_B[2 * r], By = R.g_B[2 * r + 1];
+    if (g == 0) val = Ux - om * (By - Y);
+    if (g == 1) val = Uy + om * (Bx - X);
+  } else if (c == K_WALLG) {
+    if (g == 0) val = (j == -1) ? wbu : wtu;
+    if (g == 1) val = (i == -1) ? wlv : wrv;
+  }
+  b[k] = val;
+}
+__global__ void k_bvals_points(const uint8_t *cls, int N, int W, double *b, double *x, double wlu, double wru, double wbv,
+                               double wtv) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= 3 * W * W) return;
+  uint8_t c = cls[t];
+  if (c == K_INACTIVE || c == K_EXT) {
+    b[t] = 0;
+    return;
+  }
+  if (c != K_WALLD) return;
+  int g = t / (W * W), loc = t % (W * W), j = loc / W - 1, i = loc % W - 1;
+  double val = (g == 0) ? ((i == 0) ? wlu : wru) : ((j == 0) ? wbv : wtv);
+  b[t] = val;
+  x[t] = val;
+  (void)N;
+}
+
+// ---------------------------------------------------------------------------------------------------------
+// host drivers
+// ---------------------------------------------------------------------------------------------------------
+static Lat make_lat(Ctx *ctx, int l) {
+  Lat L;
+  L.phi = ctx->phi;
+  L.Lf = 2 * ctx->N + 1;
+  L.s = ctx->geo[l].lstride;
+  L.N = ctx->geo[l].N;
+  L.h = ctx->geo[l].h;
+  return L;
+}
+static RowArgs row_args(Geo &G) {
+  RowArgs R;
+  R.g_pt = G.g_pt;
+  R.g_col = G.g_col;
+  R.g_w = G.g_w;
+  R.g_dtau = G.g_dtau;
+  R.g_B = G.g_B;
+  R.g_nB = G.g_nB;
+  R.g_th = G.g_th;
+  R.g_kind = G.g_kind;
+  R.ng = G.ng;
+  return R;
+}
+
+gp_status levelset_analytic(Ctx *ctx, const gp_shape *sh, double t, const gp_rigid *mo) {
+  int N = ctx->N, nl = 2 * N + 1;
+  gp_rigid m{};
+  if (mo) m = *mo;
+  k_levelset<<<nblk((long)nl * nl), TPB, 0, ctx->stream>>>(ctx->phi, N, sh->kind, sh->p[0], sh->p[1], sh->p[2], sh->p[3],
+                                                           m.X0x + m.Ux * t, m.X0y + m.Uy * t, m.omega * t);
+  GP_HIP(hipGetLastError());
+  return GP_OK;
+}
+
+static gp_status read_flags(Ctx *ctx, int *h) {
+  GP_HIP(hipMemcpyAsync(h, ctx->d_flags, 8 * sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+  GP_HIP(hipStreamSynchronize(ctx->stream));
+  return GP_OK;
+}
+
+static gp_status build_level(Ctx *ctx, int l) {
+  Geo &G = ctx->geo[l];
+  Lat L = make_lat(ctx, l);
+  int W = G.W, P = 3 * W * W;
+  hipStream_t s = ctx->stream;
+  int hf[8];
+  GP_HIP(hipMemsetAsync(ctx->d_flags, 0, 8 * sizeof(int), s));
+  k_classify<<<nblk(P), TPB, 0, s>>>(L, G.cls, W, l == 0, ctx->d_flags);
+  k_seed<<<nblk(P), TPB, 0, s>>>(G.cls, G.N, W);
+  for (int it = 0;; it++) {
+    GP_HIP(hipMemsetAsync(ctx->d_flags, 0, sizeof(int), s));
+    k_closure<<<nblk(P), TPB, 0, s>>>(L, G.cls, W, ctx->d_flags);
+    gp_status st = read_flags(ctx, hf);
+    if (st) return st;
+    if (!hf[0]) break;
+    if (it > 64) return GP_EGEOM;
+  }
+  k_ext_mark<<<nblk(P), TPB, 0, s>>>(G.cls, G.N, W, ctx->prm.ext_radius);
+  k_body_to_inactive<<<nblk(P), TPB, 0, s>>>(G.cls, P);
+  // ghost rows
+  GP_HIP(hipMemsetAsync(ctx->d_flags + 2, 0, 2 * sizeof(int), s));
+  k_compact<<<nblk(P), TPB, 0, s>>>(G.cls, P, 0, G.g_pt, G.gcap, ctx->d_flags + 2);
+  k_compact<<<nblk(P), TPB, 0, s>>>(G.cls, P, 1, G.e_pt, G.ecap, ctx->d_flags + 3);
+  gp_status st = read_flags(ctx, hf);
+  if (st) return st;
+  if (hf[2] > G.gcap || hf[3] > G.ecap) return GP_ENOMEM;
+  G.ng = hf[2];
+  G.ne = hf[3];
+  RowArgs R = row_args(G);
+  double nbis_d = ceil(log2(0.5 / ctx->prm.bisect_eps_over_h) - 1e-12);
+  if (G.ng) {
+    k_ghost_rows<<<nblk(G.ng), TPB, 0, s>>>(L, G.cls, W, R, ctx->prm.march_max, (int)nbis_d, ctx->prm.cg_min,
+                                            ctx->prm.dtau_dir, ctx->prm.dtau_neu_over_h * G.h);
+    k_ghostx_rows<<<nblk(G.ng), TPB, 0, s>>>(L, G.cls, W, R, l == 0, ctx->d_flags);
+  }
+  if (G.ne) {
+    k_ext_rows<<<nblk(G.ne), TPB, 0, s>>>(L, G.cls, W, G.e_pt, G.ne, G.e_src, G.e_w);
+    k_ext_fail<<<nblk(G.ne), TPB, 0, s>>>(G.cls, G.e_pt, G.ne, G.e_src);
+  }
+  GP_HIP(hipMemsetAsync(G.d_mp, 0, sizeof(int), s));
+  k_count_mp<<<nblk(W * W), TPB, 0, s>>>(G.cls, W, G.d_mp);
+  if (l == 0) k_empty_cells<<<nblk(G.N * G.N), TPB, 0, s>>>(G.cls, G.N, W, ctx->d_flags);
+  GP_HIP(hipGetLastError());
+  GP_HIP(hipMemcpyAsync(&G.mp, G.d_mp, sizeof(int), hipMemcpyDeviceToHost, s));
+  st = read_flags(ctx, hf);
+  if (st) return st;
+  if (G.mp == 0) return GP_EGEOM;
+  if (l == 0 && (hf[1] || hf[4])) return GP_EGEOM;
+  return GP_OK;
+}
+
+gp_status geometry_build(Ctx *ctx) {
+  ctx->have_geom = 0;
+  for (int l = 0; l < ctx->L; l++) {
+    gp_status st = build_level(ctx, l);
+    if (st) return st;
+  }
+  ctx->have_geom = 1;
+  return GP_OK;
+}
+
+gp_status default_boundary_values(Ctx *ctx) {
+  Geo &G = ctx->geo[0];
+  int W = G.W;
+  RowArgs R = row_args(G);
+  const double *w = ctx->walls;
+  const gp_rigid &m = ctx->motion;
+  if (G.ng)
+    k_bvals_rows<<<nblk(G.ng), TPB, 0, ctx->stream>>>(G.cls, W, R, ctx->v64[0].b, m.X0x, m.X0y, m.Ux, m.Uy, m.omega,
+                                                      ctx->t_geom, w[0], w[4], w[7], w[3]);
+  k_bvals_points<<<nblk(3 * W * W), TPB, 0, ctx->stream>>>(G.cls, G.N, W, ctx->v64[0].b, ctx->v64[0].x, w[6], w[2], w[1],
+                                                           w[5]);
+  GP_HIP(hipGetLastError());
+  return GP_OK;
+}
+
+// ---------------------------------------------------------------------------------------------------------
+// coarsest level: dense matrix of the active unknowns and its inverse (Gauss-Jordan with partial pivoting)
+// ---------------------------------------------------------------------------------------------------------
+__global__ void k_coarse_map(const uint8_t *cls, int P, int *map, int *inv, int *count) {
+  // single thread: deterministic order of the active unknowns
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  int n = 0;
+  for (int k = 0; k < P; k++) {
+    uint8_t c = cls[k];
+    if (c == K_INT || c == K_GHOST || c == K_GHOSTX || c == K_WALLG) {
+      map[n] = k;
+      inv[k] = n;
+      n++;
+    } else
+      inv[k] = -1;
+  }
+  map[n] = P;  // xi
+  inv[P] = n;
+  *count = n + 1;
+}
+
+__global__ void k_coarse_fill(const uint8_t *cls, int N, int W, double h, double a, double d, const int *map,
+                              const int *inv, int nc, const int *row_of, const int *g_col, const double *g_w, int mp,
+                              double *A) {
+  int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= nc) return;
+  double *row = A + (size_t)q * nc;
+  for (int c = 0; c < nc; c++) row[c] = 0;
+  int P = 3 * W * W;
+  int k = map[q];
+  auto put = [&](int col, double v) {
+    int ci = inv[col];
+    if (ci >= 0) row[ci] += v;
+  };
+  if (k == P) {  // mean row
+    for (int t = 2 * W * W; t < P; t++)
+      if (cls[t] == K_INT) put(t, 1.0 / mp);
+    return;
+  }
+  int g = k / (W * W), loc = k % (W * W), j = loc / W - 1, i = loc % W - 1;
+  uint8_t c = cls[k];
+  if (c == K_INT) {
+    if (g == 0) {
+      put(k, d);
+      put(gix(W, 0, i - 1, j), -a);
+      put(gix(W, 0, i + 1, j), -a);
+      put(gix(W, 0, i, j - 1), -a);
+      put(gix(W, 0, i, j + 1), -a);
+      put(gix(W, 2, i, j), 1.0 / h);
+      put(gix(W, 2, i - 1, j), -1.0 / h);
+    } else if (g == 1) {
+      put(k, d);
+      put(gix(W, 1, i - 1, j), -a);
+      put(gix(W, 1, i + 1, j), -a);
+      put(gix(W, 1, i, j - 1), -a);
+      put(gix(W, 1, i, j + 1), -a);
+      put(gix(W, 2, i, j), 1.0 / h);
+      put(gix(W, 2, i, j - 1), -1.0 / h);
+    } else {
+      put(gix(W, 0, i + 1, j), 1.0 / h);
+      put(gix(W, 0, i, j), -1.0 / h);
+      put(gix(W, 1, i, j + 1), 1.0 / h);
+      put(gix(W, 1, i, j), -1.0 / h);
+      put(P, -1.0);
+    }
+  } else {
+    int r = row_of[k];
+    for (int z = 0; z < 9; z++)
+      if (g_w[9 * r + z] != 0.0) put(g_col[9 * r + z], g_w[9 * r + z]);
+  }
+  (void)N;
+}
+
+__global__ void k_row_of(const int *g_pt, int ng, int *row_of) {
+  int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r < ng) row_of[g_pt[r]] = r;
+}
+
+// in-place Gauss-Jordan inversion with partial pivoting, one workgroup; A (n x n) becomes A^{-1}
+constexpr int GJ_T = 1024;
+__global__ void __launch_bounds__(GJ_T) k_gauss_jordan(double *A, int n, int *piv, int *fail) {
+  __shared__ double sval[GJ_T];
+  __shared__ int sidx[GJ_T];
+  __shared__ double prow_s[1024];
+  __shared__ double pcol_s[1024];
+  int tid = threadIdx.x;
+  for (int k = 0; k < n; k++) {
+    // pivot search in column k, rows k..n-1 (ties: smallest row)
+    double best = -1;
+    int bi = k;
+    for (int i = k + tid; i < n; i += GJ_T) {
+      double v = fabs(A[(size_t)i * n + k]);
+      if (v > best) {
+        best = v;
+        bi = i;
+      }
+    }
+    sval[tid] = best;
+    sidx[tid] = bi;
+    __syncthreads();
+    for (int s = GJ_T / 2; s > 0; s >>= 1) {
+      if (tid < s) {
+        double o = sval[tid + s];
+        int oi = sidx[tid + s];
+        if (o > sval[tid] || (o == sval[tid] && oi < sidx[tid])) {
+          sval[tid] = o;
+          sidx[tid] = oi;
+        }
+      }
+      __syncthreads();
+    }
+    int p = sidx[0];
+    if (sval[0] == 0.0) {
+      if (tid == 0) *fail = 1;
+      return;
+    }
+    if (tid == 0) piv[k] = p;
+    // swap rows k and p
+    if (p != k)
+      for (int c = tid; c < n; c += GJ_T) {
+        double t = A[(size_t)k * n + c];
+        A[(size_t)k * n + c] = A[(size_t)p * n + c];
+        A[(size_t)p * n + c] = t;
+      }
+    __syncthreads();
+    double inv_p = 1.0 / A[(size_t)k * n + k];
+    // pivot row (scaled) and pivot column into shared memory
+    for (int c = tid; c < n; c += GJ_T) {
+      prow_s[c] = (c == k) ? inv_p : A[(size_t)k * n + c] * inv_p;
+      pcol_s[c] = A[(size_t)c * n + k];
+    }
+    __syncthreads();
+    for (int c = tid; c < n; c += GJ_T) A[(size_t)k * n + c] = prow_s[c];
+    // eliminate column k from every other row
+    for (long e = tid; e < (long)n * n; e += GJ_T) {
+      int i = (int)(e / n), c = (int)(e % n);
+      if (i == k) continue;
+      double f = pcol_s[i];
+      if (c == k)
+        A[e] = -f * inv_p;
+      else
+        A[e] -= f * prow_s[c];
+    }
+    __syncthreads();
+  }
+  // undo the row interchanges as column interchanges, in reverse order
+  for (int k = n - 1; k >= 0; k--) {
+    int p = piv[k];
+    if (p != k)
+      for (int i = tid; i < n; i += GJ_T) {
+        double t = A[(size_t)i * n + k];
+        A[(size_t)i * n + k] = A[(size_t)i * n + p];
+        A[(size_t)i * n + p] = t;
+      }
+    __syncthreads();
+  }
+}
+
+gp_status coarse_factor(Ctx *ctx) {
+  int l = ctx->L - 1;
+  Geo &G = ctx->geo[l];
+  int W = G.W, P = 3 * W * W;
+  hipStream_t s = ctx->stream;
+  int *inv = (int *)ctx->c_work;  // scratch (P+1 ints fit easily)
+  int *row_of = inv + (P + 1);
+  k_coarse_map<<<1, 1, 0, s>>>(G.cls, P, ctx->c_map, inv, ctx->d_flags + 5);
+  if (G.ng) k_row_of<<<nblk(G.ng), TPB, 0, s>>>(G.g_pt, G.ng, row_of);
+  int hf[8];
+  gp_status st = read_flags(ctx, hf);
+  if (st) return st;
+  ctx->nc = hf[5];
+  if (ctx->nc > 1024) return GP_EINVAL;
+  double a = ctx->alpha / (G.h * G.h), d = 1.0 + 4.0 * a;
+  k_coarse_fill<<<nblk(ctx->nc), TPB, 0, s>>>(G.cls, G.N, W, G.h, a, d, ctx->c_map, inv, ctx->nc, row_of, G.g_col, G.g_w,
+                                             G.mp, ctx->c_A);
+  GP_HIP(hipMemsetAsync(ctx->d_flags + 6, 0, sizeof(int), s));
+  k_gauss_jordan<<<1, GJ_T, 0, s>>>(ctx->c_A, ctx->nc, (int *)(ctx->c_work) + 2 * (P + 1), ctx->d_flags + 6);
+  GP_HIP(hipGetLastError());
+  st = read_flags(ctx, hf);
+  if (st) return st;
+  if (hf[6]) return GP_EGEOM;
+  ctx->c_ok = 1;
+  return GP_OK;
+}
+
+}  // namespace gpmg

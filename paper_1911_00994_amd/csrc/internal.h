@@ -1,0 +1,123 @@
+// Internal declarations of the gpmg HIP library (not part of the public ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/gpmg.h"
+
+namespace gpmg {
+
+// point classes (same numbering as the public GP_* class constants; BODY is transient)
+enum : uint8_t {
+  K_INACTIVE = 0,
+  K_INT = 1,
+  K_GHOST = 2,
+  K_WALLD = 3,
+  K_WALLG = 4,
+  K_EXT = 5,
+  K_BODY = 6,
+  K_GHOSTX = 7
+};
+
+constexpr int MAXLEV = 16;
+constexpr int TPB = 256;
+
+// geometry of one level (device pointers), shared by the FP64 and FP32 hierarchies
+struct Geo {
+  int N = 0, W = 0, WW = 0, n = 0;  // n = 3*WW + 1 unknowns (xi last)
+  double h = 0;
+  int lstride = 1;                  // level lattice step in fine lattice steps
+  uint8_t *cls = nullptr;           // 3*WW
+  // ghost rows (GHOST, GHOSTX, WALLG): compact, unordered
+  int ng = 0, gcap = 0;
+  int *g_pt = nullptr;              // global unknown index
+  int *g_col = nullptr;             // 9 per row
+  double *g_w = nullptr;            // 9 per row
+  double *g_dtau = nullptr;
+  double *g_B = nullptr, *g_nB = nullptr, *g_th = nullptr;  // 2 per row
+  int8_t *g_kind = nullptr;         // 1 BC row, 2 extrapolation, 0 identity
+  // extension points: compact
+  int ne = 0, ecap = 0;
+  int *e_pt = nullptr, *e_src = nullptr;  // 3 sources per point (-1 none)
+  double *e_w = nullptr;
+  int *d_mp = nullptr;              // device: number of internal pressure points
+  int mp = 0;                       // host copy
+};
+
+// one precision's vectors on one level
+template <typename T>
+struct Vec {
+  T *x = nullptr, *b = nullptr, *r = nullptr;
+};
+
+struct Ctx {
+  int N = 0, L = 0;
+  double Re = 100, alpha = 0;
+  gp_params prm{};
+  hipStream_t stream = nullptr;
+  std::string hip_err;
+  Geo geo[MAXLEV];
+  Vec<double> v64[MAXLEV];
+  Vec<float> v32[MAXLEV];
+  double *phi = nullptr;            // fine half lattice (2N+1)^2
+  double *gtmp = nullptr;           // ghost Jacobi scratch (max gcap)
+  // reductions / flags
+  double *d_red = nullptr;          // partial sums (blocks) scratch
+  unsigned int *d_ticket = nullptr; // last-block tickets
+  double *d_scal = nullptr;         // device scalars: [0] mean p, [1] res max (as bits), [2..] misc
+  int *d_flags = nullptr;           // device flags: [0] changed, [1] geometry error bits, [2] ghost count, [3] ext count, [4] bad rows
+  int have_geom = 0;
+  double t_geom = 0;
+  gp_rigid motion{};
+  double walls[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  // coarsest exact solve: compacted active unknowns and explicit inverse (FP64)
+  int nc = 0;                       // number of active unknowns on the coarsest level
+  int *c_map = nullptr;             // nc: global index of each active unknown
+  double *c_A = nullptr;            // nc*nc matrix, then overwritten by its inverse
+  double *c_work = nullptr;         // nc*nc scratch
+  int c_ok = 0;
+  // time-stepping state (finest level)
+  int nstep = 0;
+  double *cu[3] = {nullptr, nullptr, nullptr}, *cv[3] = {nullptr, nullptr, nullptr};
+  double *lapu = nullptr, *lapv = nullptr, *fbase = nullptr, *cku = nullptr, *ckv = nullptr;
+  double *fwork = nullptr;          // 3*WW staging for inputs
+  int last_cycles = 0;
+};
+
+// error handling
+#define GP_HIP(call)                                               \
+  do {                                                             \
+    hipError_t e_ = (call);                                        \
+    if (e_ != hipSuccess) {                                        \
+      ctx->hip_err = std::string(#call) + ": " + hipGetErrorString(e_); \
+      return GP_EHIP;                                              \
+    }                                                              \
+  } while (0)
+
+inline int nblk(long n) { return (int)((n + TPB - 1) / TPB); }
+
+// geometry (geom.hip)
+gp_status geometry_build(Ctx *ctx);
+gp_status levelset_analytic(Ctx *ctx, const gp_shape *shape, double t, const gp_rigid *mo);
+gp_status default_boundary_values(Ctx *ctx);
+gp_status coarse_factor(Ctx *ctx);
+
+// multigrid (mg.hip)
+gp_status mg_cycle64(Ctx *ctx, double *res_inf);
+gp_status mg_solve(Ctx *ctx, int precision, double tol, int max_cycles, gp_stats *st);
+gp_status relax64(Ctx *ctx, int level, int steps);
+gp_status residual64(Ctx *ctx, int level, double *res_inf);
+gp_status set_wall_dirichlet(Ctx *ctx);
+
+// time stepping (cn.hip)
+gp_status cn_set_state_finish(Ctx *ctx);
+gp_status cn_step(Ctx *ctx, double dt, const double *fu, const double *fv, const double *g, int precision, double tol,
+                  int max_cycles, double picard_eps, int picard_max, gp_stats *st);
+
+}  // namespace gpmg
+
+// the opaque public handle is the context itself
+struct gp_ctx : public gpmg::Ctx {};

@@ -1,0 +1,602 @@
+// Multigrid of Sect. 4 on the device: 5-colour box relaxation, fictitious-time ghost sweeps, the scalar
+// unknown xi, residual, boundary-aware restriction, extension fill, bilinear prolongation, exact coarsest solve
+// and the cycle driver.  Vectors are templated on the storage type T (double for the FP64 solver, float for the
+// inner cycles of the mixed-precision solver); all arithmetic inside a kernel is FP64 and ghost-row
+// coefficients are always FP64.
+#include <chrono>
+#include <cmath>
+#include <cstring>
+
+#include "internal.h"
+
+namespace gpmg {
+
+__device__ __forceinline__ int pidx(int W, int i, int j) { return (j + 1) * W + (i + 1); }
+
+// ---------------------------------------------------------------------------------------------------------
+// box relaxation of all cells of one colour (i + 2j) mod 5 (Sect. 4.1.1; the colour order replaces the
+// lexicographic order, same-colour boxes share no unknown and read nothing another one writes).
+// Box unknowns: p_ij and the four faces, those that are internal points; everything else is held fixed.
+// With the faces W/E coupled through -a and S/N likewise, each free face is affine in p:
+//   both free:  [d -a; -a d] [uW; uE] = [RW - p/h; RE + p/h]
+//   one free:   d uW = RW + a uE - p/h   (resp. d uE = RE + a uW + p/h)
+// and the continuity row fixes p.
+// ---------------------------------------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(TPB) k_box(int N, int W, double h, double a, double d, const uint8_t *__restrict__ cls,
+                                             T *__restrict__ x, const T *__restrict__ b, int colour) {
+  const int K = N / 5 + 1;
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  int j = t / K, kk = t - j * K;
+  if (j >= N) return;
+  int i = ((colour - 2 * j) % 5 + 5) % 5 + 5 * kk;
+  if (i >= N) return;
+  const int WW = W * W;
+  T *u = x, *v = x + WW, *p = x + 2 * WW;
+  const T *bu = b, *bv = b + WW, *bp = b + 2 * WW;
+  const int c = pidx(W, i, j);
+  const bool fW = cls[c] == K_INT, fE = cls[c + 1] == K_INT, fS = cls[WW + c] == K_INT, fN = cls[WW + c + W] == K_INT,
+             fP = cls[2 * WW + c] == K_INT;
+  if (!(fW || fE || fS || fN || fP)) return;
+  const double ih = 1.0 / h;
+  const double uW = u[c], uE = u[c + 1], vS = v[c], vN = v[c + W], pc = p[c];
+  double aW = uW, bW = 0, aE = uE, bE = 0, aS = vS, bS = 0, aN = vN, bN = 0;
+  const double det = d * d - a * a;
+  if (fW || fE) {
+    double RW = 0, RE = 0;
+    if (fW) RW = (double)bu[c] + a * ((double)u[c - 1] + (double)u[c - W] + (double)u[c + W]) + (double)p[c - 1] * ih;
+    if (fE) RE = (double)bu[c + 1] + a * ((double)u[c + 2] + (double)u[c + 1 - W] + (double)u[c + 1 + W]) - (double)p[c + 1] * ih;
+    if (fW && fE) {
+      aW = (d * RW + a * RE) / det;
+      bW = -ih / (d + a);
+      aE = (a * RW + d * RE) / det;
+      bE = ih / (d + a);
+    } else if (fW) {
+      aW = (RW + a * uE) / d;
+      bW = -ih / d;
+    } else {
+      aE = (RE + a * uW) / d;
+      bE = ih / d;
+    }
+  }
+  if (fS || fN) {
+    double RS = 0, RN = 0;
+    if (fS) RS = (double)bv[c] + a * ((double)v[c - W] + (double)v[c - 1] + (double)v[c + 1]) + (double)p[c - W] * ih;
+    if (fN) RN = (double)bv[c + W] + a * ((double)v[c + 2 * W] + (double)v[c + W - 1] + (double)v[c + W + 1]) - (double)p[c + W] * ih;
+    if (fS && fN) {
+      aS = (d * RS + a * RN) / det;
+      bS = -ih / (d + a);
+      aN = (a * RS + d * RN) / det;
+      bN = ih / (d + a);
+    } else if (fS) {
+      aS = (RS + a * vN) / d;
+      bS = -ih / d;
+    } else {
+      aN = (RN + a * vS) / d;
+      bN = ih / d;
+    }
+  }
+  double pn = pc;
+  if (fP) {
+    double den = bE - bW + bN - bS;
+    if (den == 0.0) return;  // no free face: the block is singular, the box is skipped
+    double xi = (double)x[3 * WW];
+    pn = (h * (xi + (double)bp[c]) - (aE - aW + aN - aS)) / den;
+    p[c] = (T)pn;
+  }
+  if (fW) u[c] = (T)(aW + bW * pn);
+  if (fE) u[c + 1] = (T)(aE + bE * pn);
+  if (fS) v[c] = (T)(aS + bS * pn);
+  if (fN) v[c + W] = (T)(aN + bN * pn);
+}
+
+// fictitious-time relaxation of every ghost row at once (eq. ghostrelax, Jacobi): w += dtau (g - B w)
+template <typename T>
+__global__ void k_ghost_a(const int *__restrict__ pt, const int *__restrict__ col, const double *__restrict__ w,
+                          const double *__restrict__ dtau, int ng, const T *__restrict__ x, const T *__restrict__ b,
+                          double *__restrict__ tmp) {
+  int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= ng) return;
+  int k = pt[r];
+  double s = 0;
+#pragma unroll
+  for (int q = 0; q < 9; q++) s += w[9 * r + q] * (double)x[col[9 * r + q]];
+  tmp[r] = (double)x[k] + dtau[r] * ((double)b[k] - s);
+}
+template <typename T>
+__global__ void k_ghost_b(const int *__restrict__ pt, int ng, const double *__restrict__ tmp, T *__restrict__ x) {
+  int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r < ng) x[pt[r]] = (T)tmp[r];
+}
+
+// ---------------------------------------------------------------------------------------------------------
+// deterministic grid reductions: fixed grid, fixed per-thread ranges, tree in LDS, the last block sums the
+// block partials in a fixed order
+// ---------------------------------------------------------------------------------------------------------
+constexpr int RED_BLOCKS = 512;
+
+__device__ double block_sum(double v) {
+  __shared__ double s[TPB];
+  s[threadIdx.x] = v;
+  __syncthreads();
+  for (int o = TPB / 2; o > 0; o >>= 1) {
+    if (threadIdx.x < o) s[threadIdx.x] += s[threadIdx.x + o];
+    __syncthreads();
+  }
+  double r = s[0];
+  __syncthreads();
+  return r;
+}
+
+// returns true in the last block (all partials visible); *total valid there
+__device__ bool last_block_total(double mine, double *part, unsigned *ticket, double *total) {
+  __shared__ bool last;
+  double bs = block_sum(mine);
+  if (threadIdx.x == 0) {
+    part[blockIdx.x] = bs;
+    __threadfence();
+    unsigned tk = atomicAdd(ticket, 1u);
+    last = (tk == gridDim.x - 1);
+  }
+  __syncthreads();
+  if (!last) return false;
+  __threadfence();
+  double v = 0;
+  for (int q = threadIdx.x; q < (int)gridDim.x; q += TPB) v += __hip_atomic_load(&part[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  *total = block_sum(v);
+  if (threadIdx.x == 0) *ticket = 0;
+  return true;
+}
+
+// xi = mean over internal cells of (div_h u - g): the value that makes the continuity residuals sum to zero
+template <typename T>
+__global__ void __launch_bounds__(TPB) k_xi(int N, int W, double h, const uint8_t *__restrict__ cls, T *__restrict__ x,
+                                            const T *__restrict__ b, double *part, unsigned *ticket, const int *mp) {
+  const int WW = W * W;
+  double s = 0;
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < N * N; t += gridDim.x * blockDim.x) {
+    int i = t % N, j = t / N, c = pidx(W, i, j);
+    if (cls[2 * WW + c] != K_INT) continue;
+    s += ((double)x[c + 1] - (double)x[c] + (double)x[WW + c + W] - (double)x[WW + c]) / h - (double)b[2 * WW + c];
+  }
+  double tot;
+  if (last_block_total(s, part, ticket, &tot) && threadIdx.x == 0) x[3 * WW] = (T)(tot / *mp);
+}
+
+// mean of the internal pressure (row eq:midpoint); result in *out
+template <typename T>
+__global__ void __launch_bounds__(TPB) k_pmean(int W, const uint8_t *__restrict__ cls, const T *__restrict__ x,
+                                               double *part, unsigned *ticket, const int *mp, double *out) {
+  const int WW = W * W;
+  double s = 0;
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < WW; t += gridDim.x * blockDim.x)
+    if (cls[2 * WW + t] == K_INT) s += (double)x[2 * WW + t];
+  double tot;
+  if (last_block_total(s, part, ticket, &tot) && threadIdx.x == 0) *out = tot / *mp;
+}
+template <typename T>
+__global__ void k_pshift(int W, const uint8_t *__restrict__ cls, T *__restrict__ x, const double *mean) {
+  const int WW = W * W;
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= WW) return;
+  uint8_t c = cls[2 * WW + t];
+  if (c == K_INT || c == K_GHOST || c == K_GHOSTX) x[2 * WW + t] = (T)((double)x[2 * WW + t] - *mean);
+}
+
+// ---------------------------------------------------------------------------------------------------------
+// residual r = b - M x
+// ---------------------------------------------------------------------------------------------------------
+__device__ __forceinline__ void max_abs(unsigned long long *m, double v) {
+  double a = fabs(v);
+  atomicMax(m, (unsigned long long)__double_as_longlong(a));
+}
+
+template <typename T>
+__global__ void __launch_bounds__(TPB) k_resid_pts(int N, int W, double h, double a, double d,
+                                                   const uint8_t *__restrict__ cls, const T *__restrict__ x,
+                                                   const T *__restrict__ b, T *__restrict__ r, unsigned long long *rmax) {
+  const int WW = W * W;
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= 3 * WW) return;
+  uint8_t c = cls[t];
+  double res = 0;
+  if (c == K_INT) {
+    int g = t / WW, q = t - g * WW;
+    const T *u = x, *v = x + WW, *p = x + 2 * WW;
+    double ih = 1.0 / h;
+    if (g == 0)
+      res = (double)b[t] - (d * (double)u[q] - a * ((double)u[q - 1] + (double)u[q + 1] + (double)u[q - W] + (double)u[q + W]) +
+                            ((double)p[q] - (double)p[q - 1]) * ih);
+    else if (g == 1)
+      res = (double)b[t] - (d * (double)v[q] - a * ((double)v[q - 1] + (double)v[q + 1] + (double)v[q - W] + (double)v[q + W]) +
+                            ((double)p[q] - (double)p[q - W]) * ih);
+    else
+      res = (double)b[t] - (((double)u[q + 1] - (double)u[q] + (double)v[q + W] - (double)v[q]) * ih - (double)x[3 * WW]);
+  } else if (c == K_WALLD) {
+    res = (double)b[t] - (double)x[t];
+  }
+  r[t] = (T)res;
+  if (rmax && res != 0.0) max_abs(rmax, res);
+  (void)N;
+}
+template <typename T>
+__global__ void k_resid_ghost(const int *__restrict__ pt, const int *__restrict__ col, const double *__restrict__ w, int ng,
+                              const T *__restrict__ x, const T *__restrict__ b, T *__restrict__ r, unsigned long long *rmax) {
+  int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= ng) return;
+  int k = pt[q];
+  double s = 0;
+#pragma unroll
+  for (int z = 0; z < 9; z++) s += w[9 * q + z] * (double)x[col[9 * q + z]];
+  double res = (double)b[k] - s;
+  r[k] = (T)res;
+  if (rmax) max_abs(rmax, res);
+}
+// mean row residual 0 - mean(p) into r[3WW] and the norm
+template <typename T>
+__global__ void k_resid_mean(int W, const double *mean, T *r, unsigned long long *rmax) {
+  double res = -*mean;
+  r[3 * W * W] = (T)res;
+  if (rmax) max_abs(rmax, res);
+}
+
+template <typename T>
+__global__ void k_set_walld(int n, const uint8_t *cls, T *x, const T *b) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n && cls[t] == K_WALLD) x[t] = b[t];
+}
+
+template <typename T>
+__global__ void k_fill(T *x, long n, T val) {
+  long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (t < n) x[t] = val;
+}
+
+// ---------------------------------------------------------------------------------------------------------
+// boundary-aware restriction (eqs. restop, restop5)
+// ---------------------------------------------------------------------------------------------------------
+template <typename TF, typename TC>
+__global__ void __launch_bounds__(TPB) k_restrict(int Nf, int Wf, const uint8_t *__restrict__ clsf, const TF *__restrict__ rf,
+                                                  int Nc, int Wc, const uint8_t *__restrict__ clsc, TC *__restrict__ bc) {
+  const int WWc = Wc * Wc, WWf = Wf * Wf;
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t == 3 * WWc) {
+    bc[t] = (TC)0;
+    return;
+  }
+  if (t > 3 * WWc) return;
+  int g = t / WWc, q = t - g * WWc, jc = q / Wc - 1, ic = q % Wc - 1;
+  uint8_t cc = clsc[t];
+  if (!(cc == K_INT || cc == K_GHOST || cc == K_WALLG)) {
+    bc[t] = (TC)0;
+    return;
+  }
+  int fi[6], fj[6];
+  double fw[6];
+  int m = 0;
+  if (g == 0) {
+    for (int dy = 0; dy < 2; dy++)
+      for (int dx = -1; dx <= 1; dx++) {
+        fi[m] = 2 * ic + dx;
+        fj[m] = 2 * jc + dy;
+        fw[m] = (dx == 0 ? 0.25 : 0.125);
+        m++;
+      }
+  } else if (g == 1) {
+    for (int dy = -1; dy <= 1; dy++)
+      for (int dx = 0; dx < 2; dx++) {
+        fi[m] = 2 * ic + dx;
+        fj[m] = 2 * jc + dy;
+        fw[m] = (dy == 0 ? 0.25 : 0.125);
+        m++;
+      }
+  } else {
+    for (int dy = 0; dy < 2; dy++)
+      for (int dx = 0; dx < 2; dx++) {
+        fi[m] = 2 * ic + dx;
+        fj[m] = 2 * jc + dy;
+        fw[m] = 0.25;
+        m++;
+      }
+  }
+  bool all = true;
+  int cnt = 0;
+  double sw = 0, sa = 0;
+  for (int z = 0; z < m; z++) {
+    if (fi[z] < -1 || fi[z] > Nf || fj[z] < -1 || fj[z] > Nf) {
+      all = false;
+      continue;
+    }
+    int kf = g * WWf + pidx(Wf, fi[z], fj[z]);
+    if (clsf[kf] == cc) {
+      double rv = (double)rf[kf];
+      cnt++;
+      sw += fw[z] * rv;
+      sa += rv;
+    } else
+      all = false;
+  }
+  bc[t] = (TC)(all ? sw : (cnt ? sa / cnt : 0.0));
+}
+
+// extension values: quadratic extrapolation from the sources
+template <typename T>
+__global__ void k_ext_fill(const int *__restrict__ e_pt, const int *__restrict__ e_src, const double *__restrict__ e_w, int ne,
+                           T *__restrict__ x) {
+  int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= ne) return;
+  if (e_src[3 * e] < 0) return;
+  double v = e_w[3 * e] * (double)x[e_src[3 * e]] + e_w[3 * e + 1] * (double)x[e_src[3 * e + 1]] +
+             e_w[3 * e + 2] * (double)x[e_src[3 * e + 2]];
+  x[e_pt[e]] = (T)v;
+}
+
+// bilinear prolongation of the coarse correction to fine internal and ghost points, x += e (Sect. 4.3)
+template <typename TC, typename TF>
+__global__ void __launch_bounds__(TPB) k_prolong(int Nf, int Wf, const uint8_t *__restrict__ clsf, TF *__restrict__ xf,
+                                                 int Nc, int Wc, const TC *__restrict__ xc) {
+  const int WWf = Wf * Wf, WWc = Wc * Wc;
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t == 3 * WWf) {
+    xf[t] = (TF)((double)xf[t] + (double)xc[3 * WWc]);
+    return;
+  }
+  if (t > 3 * WWf) return;
+  uint8_t c = clsf[t];
+  if (!(c == K_INT || c == K_GHOST || c == K_GHOSTX || c == K_WALLG)) return;
+  int g = t / WWf, q = t - g * WWf, j = q / Wf - 1, i = q % Wf - 1;
+  int xi_[2], yi_[2];
+  double xw[2], yw[2];
+  int nx, ny;
+  if (g == 0) {  // faces along x
+    if ((i & 1) == 0) {
+      xi_[0] = i / 2;
+      xw[0] = 1;
+      nx = 1;
+    } else {
+      xi_[0] = (i - 1) / 2;
+      xi_[1] = (i + 1) / 2;
+      xw[0] = xw[1] = 0.5;
+      nx = 2;
+    }
+  } else {
+    if ((i & 1) == 0) {
+      xi_[0] = i / 2;
+      xi_[1] = i / 2 - 1;
+    } else {
+      xi_[0] = (i - 1) / 2;
+      xi_[1] = (i - 1) / 2 + 1;
+    }
+    xw[0] = 0.75;
+    xw[1] = 0.25;
+    nx = 2;
+  }
+  if (g == 1) {  // faces along y
+    if ((j & 1) == 0) {
+      yi_[0] = j / 2;
+      yw[0] = 1;
+      ny = 1;
+    } else {
+      yi_[0] = (j - 1) / 2;
+      yi_[1] = (j + 1) / 2;
+      yw[0] = yw[1] = 0.5;
+      ny = 2;
+    }
+  } else {
+    if ((j & 1) == 0) {
+      yi_[0] = j / 2;
+      yi_[1] = j / 2 - 1;
+    } else {
+      yi_[0] = (j - 1) / 2;
+      yi_[1] = (j - 1) / 2 + 1;
+    }
+    yw[0] = 0.75;
+    yw[1] = 0.25;
+    ny = 2;
+  }
+  double e = 0;
+  for (int aa = 0; aa < ny; aa++)
+    for (int bb = 0; bb < nx; bb++) {
+      int ic = xi_[bb], jc = yi_[aa];
+      if (g == 2) {  // pressure outside the box mirrored
+        ic = ic < 0 ? 0 : (ic > Nc - 1 ? Nc - 1 : ic);
+        jc = jc < 0 ? 0 : (jc > Nc - 1 ? Nc - 1 : jc);
+      }
+      if (ic < -1 || ic > Nc || jc < -1 || jc > Nc) continue;
+      e += xw[bb] * yw[aa] * (double)xc[g * WWc + pidx(Wc, ic, jc)];
+    }
+  xf[t] = (TF)((double)xf[t] + e);
+}
+
+// exact coarsest solve with the stored inverse: x[map[q]] = sum_r Ainv[q][r] b[map[r]] (one wavefront per row)
+template <typename T>
+__global__ void __launch_bounds__(64) k_coarse_apply(const double *__restrict__ Ainv, const int *__restrict__ map, int nc,
+                                                     const T *__restrict__ b, T *__restrict__ x) {
+  int q = blockIdx.x;
+  double s = 0;
+  for (int r = threadIdx.x; r < nc; r += 64) s += Ainv[(size_t)q * nc + r] * (double)b[map[r]];
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
+  if (threadIdx.x == 0) x[map[q]] = (T)s;
+}
+
+// ---------------------------------------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------------------------------------
+template <typename T>
+static Vec<T> &vec(Ctx *ctx, int l);
+template <>
+Vec<double> &vec<double>(Ctx *ctx, int l) {
+  return ctx->v64[l];
+}
+template <>
+Vec<float> &vec<float>(Ctx *ctx, int l) {
+  return ctx->v32[l];
+}
+
+static inline double coef_a(Ctx *ctx, int l) { return ctx->alpha / (ctx->geo[l].h * ctx->geo[l].h); }
+
+template <typename T>
+static void relax(Ctx *ctx, int l) {
+  Geo &G = ctx->geo[l];
+  Vec<T> &V = vec<T>(ctx, l);
+  hipStream_t s = ctx->stream;
+  double a = coef_a(ctx, l), d = 1.0 + 4.0 * a;
+  int K = G.N / 5 + 1;
+  for (int col = 0; col < 5; col++) k_box<T><<<nblk((long)K * G.N), TPB, 0, s>>>(G.N, G.W, G.h, a, d, G.cls, V.x, V.b, col);
+  if (G.ng)
+    for (int it = 0; it < ctx->prm.lambda_ghost; it++) {
+      k_ghost_a<T><<<nblk(G.ng), TPB, 0, s>>>(G.g_pt, G.g_col, G.g_w, G.g_dtau, G.ng, V.x, V.b, ctx->gtmp);
+      k_ghost_b<T><<<nblk(G.ng), TPB, 0, s>>>(G.g_pt, G.ng, ctx->gtmp, V.x);
+    }
+  int nb = std::min(RED_BLOCKS, nblk((long)G.N * G.N));
+  k_xi<T><<<nb, TPB, 0, s>>>(G.N, G.W, G.h, G.cls, V.x, V.b, ctx->d_red, ctx->d_ticket, G.d_mp);
+}
+
+template <typename T>
+static void residual(Ctx *ctx, int l, unsigned long long *rmax) {
+  Geo &G = ctx->geo[l];
+  Vec<T> &V = vec<T>(ctx, l);
+  hipStream_t s = ctx->stream;
+  double a = coef_a(ctx, l), d = 1.0 + 4.0 * a;
+  k_resid_pts<T><<<nblk(3L * G.WW), TPB, 0, s>>>(G.N, G.W, G.h, a, d, G.cls, V.x, V.b, V.r, rmax);
+  if (G.ng) k_resid_ghost<T><<<nblk(G.ng), TPB, 0, s>>>(G.g_pt, G.g_col, G.g_w, G.ng, V.x, V.b, V.r, rmax);
+  if (rmax) {
+    int nb = std::min(RED_BLOCKS, nblk(G.WW));
+    k_pmean<T><<<nb, TPB, 0, s>>>(G.W, G.cls, V.x, ctx->d_red, ctx->d_ticket, G.d_mp, ctx->d_scal + 2);
+    k_resid_mean<T><<<1, 1, 0, s>>>(G.W, ctx->d_scal + 2, V.r, rmax);
+  }
+}
+
+template <typename T>
+static void coarse_solve(Ctx *ctx) {
+  int l = ctx->L - 1;
+  Vec<T> &V = vec<T>(ctx, l);
+  k_coarse_apply<T><<<ctx->nc, 64, 0, ctx->stream>>>(ctx->c_A, ctx->c_map, ctx->nc, V.b, V.x);
+}
+
+template <typename T>
+static void cycle(Ctx *ctx, int l) {
+  if (l == ctx->L - 1) {
+    coarse_solve<T>(ctx);
+    return;
+  }
+  Geo &F = ctx->geo[l], &C = ctx->geo[l + 1];
+  Vec<T> &VF = vec<T>(ctx, l), &VC = vec<T>(ctx, l + 1);
+  hipStream_t s = ctx->stream;
+  for (int q = 0; q < ctx->prm.nu1; q++) relax<T>(ctx, l);
+  residual<T>(ctx, l, nullptr);
+  k_restrict<T, T><<<nblk(3L * C.WW + 1), TPB, 0, s>>>(F.N, F.W, F.cls, VF.r, C.N, C.W, C.cls, VC.b);
+  k_fill<T><<<nblk(C.n), TPB, 0, s>>>(VC.x, C.n, (T)0);
+  int reps = (l + 1 == ctx->L - 1) ? 1 : ctx->prm.gamma;
+  for (int q = 0; q < reps; q++) cycle<T>(ctx, l + 1);
+  if (C.ne) k_ext_fill<T><<<nblk(C.ne), TPB, 0, s>>>(C.e_pt, C.e_src, C.e_w, C.ne, VC.x);
+  k_prolong<T, T><<<nblk(3L * F.WW + 1), TPB, 0, s>>>(F.N, F.W, F.cls, VF.x, C.N, C.W, VC.x);
+  for (int q = 0; q < ctx->prm.nu2; q++) relax<T>(ctx, l);
+}
+
+template <typename T>
+static void mean_project(Ctx *ctx) {
+  Geo &G = ctx->geo[0];
+  Vec<T> &V = vec<T>(ctx, 0);
+  int nb = std::min(RED_BLOCKS, nblk(G.WW));
+  k_pmean<T><<<nb, TPB, 0, ctx->stream>>>(G.W, G.cls, V.x, ctx->d_red, ctx->d_ticket, G.d_mp, ctx->d_scal);
+  k_pshift<T><<<nblk(G.WW), TPB, 0, ctx->stream>>>(G.W, G.cls, V.x, ctx->d_scal);
+}
+
+static gp_status resnorm64(Ctx *ctx, double *out) {
+  unsigned long long *rmax = (unsigned long long *)(ctx->d_scal + 1);
+  k_fill<unsigned long long><<<1, 1, 0, ctx->stream>>>(rmax, 1, 0ull);
+  residual<double>(ctx, 0, rmax);
+  GP_HIP(hipGetLastError());
+  unsigned long long hv = 0;
+  GP_HIP(hipMemcpyAsync(&hv, rmax, sizeof(hv), hipMemcpyDeviceToHost, ctx->stream));
+  GP_HIP(hipStreamSynchronize(ctx->stream));
+  double v;
+  std::memcpy(&v, &hv, sizeof(v));
+  *out = v;
+  return GP_OK;
+}
+
+static gp_status bnorm64(Ctx *ctx, double *out) {
+  // max |b| over the finest vector (entries without an equation are zero)
+  Geo &G = ctx->geo[0];
+  std::vector<double> hb(G.n);
+  GP_HIP(hipMemcpyAsync(hb.data(), ctx->v64[0].b, G.n * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+  GP_HIP(hipStreamSynchronize(ctx->stream));
+  double m = 0;
+  for (double v : hb) m = std::max(m, std::fabs(v));
+  *out = m;
+  return GP_OK;
+}
+
+gp_status set_wall_dirichlet(Ctx *ctx) {
+  Geo &G = ctx->geo[0];
+  k_set_walld<double><<<nblk(3L * G.WW), TPB, 0, ctx->stream>>>(3 * G.WW, G.cls, ctx->v64[0].x, ctx->v64[0].b);
+  GP_HIP(hipGetLastError());
+  return GP_OK;
+}
+
+gp_status relax64(Ctx *ctx, int level, int steps) {
+  for (int q = 0; q < steps; q++) relax<double>(ctx, level);
+  GP_HIP(hipGetLastError());
+  GP_HIP(hipStreamSynchronize(ctx->stream));
+  return GP_OK;
+}
+
+gp_status residual64(Ctx *ctx, int level, double *res_inf) {
+  (void)level;
+  return resnorm64(ctx, res_inf);
+}
+
+gp_status mg_cycle64(Ctx *ctx, double *res_inf) {
+  gp_status st = set_wall_dirichlet(ctx);
+  if (st) return st;
+  cycle<double>(ctx, 0);
+  mean_project<double>(ctx);
+  GP_HIP(hipGetLastError());
+  if (res_inf) return resnorm64(ctx, res_inf);
+  GP_HIP(hipStreamSynchronize(ctx->stream));
+  return GP_OK;
+}
+
+gp_status mg_solve(Ctx *ctx, int precision, double tol, int max_cycles, gp_stats *stt) {
+  auto t0 = std::chrono::steady_clock::now();
+  gp_status st = set_wall_dirichlet(ctx);
+  if (st) return st;
+  double r0, bn;
+  if ((st = resnorm64(ctx, &r0))) return st;
+  if ((st = bnorm64(ctx, &bn))) return st;
+  double thr = tol * (bn > 1 ? bn : 1);
+  double r = r0, rho = 0;
+  int c = 0;
+  gp_status out = GP_OK;
+  if (precision == GP_FP64) {
+    while (r > thr && c < max_cycles) {
+      cycle<double>(ctx, 0);
+      mean_project<double>(ctx);
+      double rp = r;
+      if ((st = resnorm64(ctx, &r))) return st;
+      c++;
+      rho = r / rp;
+      if (!(r == r) || r > 1e6 * (r0 > 1 ? r0 : 1)) {
+        out = GP_EDIVERGED;
+        break;
+      }
+    }
+  } else {
+    return GP_EINVAL;  // mixed precision: see mixed.hip
+  }
+  if (out == GP_OK && r > thr) out = GP_ENOCONV;
+  ctx->last_cycles = c;
+  if (stt) {
+    stt->cycles = c;
+    stt->outer = 0;
+    stt->res0 = r0;
+    stt->res = r;
+    stt->rho = rho;
+    stt->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  }
+  return out;
+}
+
+}  // namespace gpmg

@@ -1,0 +1,271 @@
+"""Python binding of the gpmg HIP library (include/gpmg.h).
+
+Argument marshalling only: every computation happens in the HIP kernels of libgpmg.so.  The library is
+loaded from this package directory; if it is missing the import of a GPU entry point fails loudly (there is no
+CPU fallback).  Arrays are numpy host arrays (copied in/out) or, with ``on_device=True``, device pointers
+given as integers (e.g. ``torch.Tensor.data_ptr()``).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIBPATH = os.path.join(HERE, "libgpmg.so")
+
+GP_OK, GP_EINVAL, GP_ENOMEM, GP_EHIP, GP_EGEOM, GP_ENOCONV, GP_EDIVERGED = 0, -1, -2, -3, -4, -5, -6
+GP_FP64, GP_MIXED = 0, 1
+
+EXPORTS = [
+    "gp_default_params", "gp_setup_grid", "gp_destroy", "gp_num_levels", "gp_strerror", "gp_last_hip_error",
+    "gp_set_levelset", "gp_set_levelset_analytic", "gp_set_walls", "gp_get_boundary_geometry",
+    "gp_set_boundary_values", "gp_set_alpha", "gp_set_rhs", "gp_set_x", "gp_get_x", "gp_mg_vcycle", "gp_solve",
+    "gp_residual", "gp_set_state", "gp_cn_step", "gp_get_classes", "gp_get_ghost_rows", "gp_get_ext_rows",
+    "gp_relax",
+]
+
+
+class GpParams(ctypes.Structure):
+    _fields_ = [("nu1", ctypes.c_int), ("nu2", ctypes.c_int), ("gamma", ctypes.c_int), ("lambda_ghost", ctypes.c_int),
+                ("coarsest_n", ctypes.c_int), ("march_max", ctypes.c_int), ("ext_radius", ctypes.c_int),
+                ("dtau_dir", ctypes.c_double), ("dtau_neu_over_h", ctypes.c_double),
+                ("bisect_eps_over_h", ctypes.c_double), ("cg_min", ctypes.c_double),
+                ("mixed_inner_cycles", ctypes.c_int)]
+
+
+class GpRigid(ctypes.Structure):
+    _fields_ = [("X0x", ctypes.c_double), ("X0y", ctypes.c_double), ("Ux", ctypes.c_double), ("Uy", ctypes.c_double),
+                ("omega", ctypes.c_double)]
+
+
+class GpShape(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int), ("p", ctypes.c_double * 4)]
+
+
+class GpStats(ctypes.Structure):
+    _fields_ = [("cycles", ctypes.c_int), ("outer", ctypes.c_int), ("res0", ctypes.c_double), ("res", ctypes.c_double),
+                ("rho", ctypes.c_double), ("seconds", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class GpmgError(RuntimeError):
+    def __init__(self, status, where, detail=""):
+        self.status = status
+        super().__init__(f"{where}: status {status}{(' ' + detail) if detail else ''}")
+
+
+_lib = None
+
+
+def lib():
+    """Load libgpmg.so (built by __graft_entry__.build() / paper_1911_00994_amd/build.py)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIBPATH):
+        raise RuntimeError(f"libgpmg.so not built ({LIBPATH}); run __graft_entry__.build()")
+    L = ctypes.CDLL(LIBPATH)
+    vp, i, d = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
+    sigs = {
+        "gp_default_params": (None, [ctypes.POINTER(GpParams)]),
+        "gp_setup_grid": (i, [ctypes.POINTER(vp), i, d, ctypes.POINTER(GpParams), vp]),
+        "gp_destroy": (None, [vp]),
+        "gp_num_levels": (i, [vp]),
+        "gp_strerror": (ctypes.c_char_p, [i]),
+        "gp_last_hip_error": (ctypes.c_char_p, [vp]),
+        "gp_set_levelset": (i, [vp, vp, i, d, ctypes.POINTER(GpRigid)]),
+        "gp_set_levelset_analytic": (i, [vp, ctypes.POINTER(GpShape), d, ctypes.POINTER(GpRigid)]),
+        "gp_set_walls": (i, [vp, vp]),
+        "gp_get_boundary_geometry": (i, [vp, vp, vp]),
+        "gp_set_boundary_values": (i, [vp, vp, vp, vp, i]),
+        "gp_set_alpha": (i, [vp, d]),
+        "gp_set_rhs": (i, [vp, vp, vp, vp, i]),
+        "gp_set_x": (i, [vp, vp, vp, vp, d, i]),
+        "gp_get_x": (i, [vp, vp, vp, vp, vp, i]),
+        "gp_mg_vcycle": (i, [vp, i, vp]),
+        "gp_solve": (i, [vp, i, d, i, ctypes.POINTER(GpStats)]),
+        "gp_residual": (i, [vp, vp, vp]),
+        "gp_set_state": (i, [vp, vp, vp, vp, d, i]),
+        "gp_cn_step": (i, [vp, d, vp, vp, vp, i, i, d, i, d, i, ctypes.POINTER(GpStats)]),
+        "gp_get_classes": (i, [vp, i, vp]),
+        "gp_get_ghost_rows": (i, [vp, i, vp, vp, vp, vp, vp, vp, vp]),
+        "gp_get_ext_rows": (i, [vp, i, vp, vp]),
+        "gp_relax": (i, [vp, i, i]),
+    }
+    for name, (res, args) in sigs.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    return L
+
+
+def default_params(**overrides) -> GpParams:
+    p = GpParams()
+    lib().gp_default_params(ctypes.byref(p))
+    for k, v in overrides.items():
+        setattr(p, k, v)
+    return p
+
+
+def _host(a, dtype=np.float64):
+    return None if a is None else np.ascontiguousarray(a, dtype=dtype)
+
+
+def _ptr(a):
+    if a is None:
+        return None
+    if isinstance(a, int):
+        return ctypes.c_void_p(a)
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+class Solver:
+    """One gpmg context (grid hierarchy, geometry, state) on the current HIP device."""
+
+    def __init__(self, N, Re=100.0, stream=None, **params):
+        self.N, self.W, self.Re = N, N + 2, Re
+        self._p = default_params(**params)
+        h = ctypes.c_void_p()
+        st = lib().gp_setup_grid(ctypes.byref(h), N, Re, ctypes.byref(self._p), ctypes.c_void_p(stream or 0))
+        self._check(st, "gp_setup_grid", h)
+        self._h = h
+        self.nlev = lib().gp_num_levels(self._h)
+
+    def _check(self, st, where, h=None):
+        if st != GP_OK:
+            hh = h if h is not None else getattr(self, "_h", None)
+            detail = lib().gp_strerror(st).decode()
+            if st == GP_EHIP and hh:
+                detail += " (" + lib().gp_last_hip_error(hh).decode() + ")"
+            raise GpmgError(st, where, detail)
+        return st
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().gp_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+    def level_n(self, l):
+        return self.N >> l
+
+    # geometry -----------------------------------------------------------------------------------
+    def set_levelset(self, phi, t=0.0, motion=None, on_device=False, check=True):
+        m = None if motion is None else GpRigid(*[float(v) for v in list(motion)[:5]])
+        src = phi if on_device else _host(phi)
+        st = lib().gp_set_levelset(self._h, _ptr(src), int(on_device), t, ctypes.byref(m) if m else None)
+        return self._check(st, "gp_set_levelset") if check else st
+
+    def set_levelset_analytic(self, kind, params, t=0.0, motion=None, check=True):
+        sh = GpShape(kind, (ctypes.c_double * 4)(*(list(params) + [0.0] * (4 - len(params)))))
+        m = None if motion is None else GpRigid(*[float(v) for v in list(motion)[:5]])
+        st = lib().gp_set_levelset_analytic(self._h, ctypes.byref(sh), t, ctypes.byref(m) if m else None)
+        return self._check(st, "gp_set_levelset_analytic") if check else st
+
+    def set_walls(self, walls):
+        self._check(lib().gp_set_walls(self._h, _ptr(_host(walls))), "gp_set_walls")
+
+    def boundary_geometry(self):
+        W = self.W
+        B = np.zeros(3 * W * W * 2)
+        nB = np.zeros(3 * W * W * 2)
+        self._check(lib().gp_get_boundary_geometry(self._h, _ptr(B), _ptr(nB)), "gp_get_boundary_geometry")
+        B = B.reshape(3, W, W, 2)
+        nB = nB.reshape(3, W, W, 2)
+        return dict(B=(B[0], B[1], B[2]), nB=(nB[0], nB[1], nB[2]))
+
+    def set_boundary_values(self, bu=None, bv=None, bp=None, on_device=False):
+        args = [a if on_device else _host(a) for a in (bu, bv, bp)]
+        self._check(lib().gp_set_boundary_values(self._h, *[_ptr(a) for a in args], int(on_device)),
+                    "gp_set_boundary_values")
+
+    # linear system --------------------------------------------------------------------------------
+    def set_alpha(self, alpha):
+        self._check(lib().gp_set_alpha(self._h, alpha), "gp_set_alpha")
+
+    def set_rhs(self, fu=None, fv=None, g=None, on_device=False):
+        args = [a if on_device else _host(a) for a in (fu, fv, g)]
+        self._check(lib().gp_set_rhs(self._h, *[_ptr(a) for a in args], int(on_device)), "gp_set_rhs")
+
+    def set_x(self, u, v, p, xi=0.0, on_device=False):
+        args = [a if on_device else _host(a) for a in (u, v, p)]
+        self._check(lib().gp_set_x(self._h, *[_ptr(a) for a in args], xi, int(on_device)), "gp_set_x")
+
+    def get_x(self):
+        W = self.W
+        u, v, p = np.zeros((W, W)), np.zeros((W, W)), np.zeros((W, W))
+        xi = ctypes.c_double(0)
+        self._check(lib().gp_get_x(self._h, _ptr(u), _ptr(v), _ptr(p), ctypes.byref(xi), 0), "gp_get_x")
+        return u, v, p, xi.value
+
+    def cycle(self, precision=GP_FP64):
+        r = ctypes.c_double(0)
+        st = lib().gp_mg_vcycle(self._h, precision, ctypes.byref(r))
+        self._check(st, "gp_mg_vcycle")
+        return r.value
+
+    def solve(self, tol=1e-10, max_cycles=100, precision=GP_FP64, check=True):
+        s = GpStats()
+        st = lib().gp_solve(self._h, precision, tol, max_cycles, ctypes.byref(s))
+        if check and st not in (GP_OK,):
+            self._check(st, "gp_solve")
+        return st, s.as_dict()
+
+    def residual(self):
+        r = np.zeros(3 * self.W * self.W + 1)
+        ri = ctypes.c_double(0)
+        self._check(lib().gp_residual(self._h, _ptr(r), ctypes.byref(ri)), "gp_residual")
+        return r, ri.value
+
+    def relax(self, level=0, steps=1):
+        self._check(lib().gp_relax(self._h, level, steps), "gp_relax")
+
+    # time stepping ------------------------------------------------------------------------------
+    def set_state(self, u, v, p, xi=0.0, on_device=False):
+        args = [a if on_device else _host(a) for a in (u, v, p)]
+        self._check(lib().gp_set_state(self._h, *[_ptr(a) for a in args], xi, int(on_device)), "gp_set_state")
+
+    def cn_step(self, dt, fu=None, fv=None, g=None, on_device=False, precision=GP_FP64, tol=1e-10, max_cycles=100,
+                picard_eps=1e-6, picard_max=20, check=True):
+        args = [a if on_device else _host(a) for a in (fu, fv, g)]
+        s = GpStats()
+        st = lib().gp_cn_step(self._h, dt, *[_ptr(a) for a in args], int(on_device), precision, tol, max_cycles,
+                              picard_eps, picard_max, ctypes.byref(s))
+        if check and st != GP_OK:
+            self._check(st, "gp_cn_step")
+        return st, s.as_dict()
+
+    # inspection ---------------------------------------------------------------------------------
+    def classes(self, level=0):
+        W = self.level_n(level) + 2
+        out = np.zeros(3 * W * W, dtype=np.uint8)
+        self._check(lib().gp_get_classes(self._h, level, _ptr(out)), "gp_get_classes")
+        return out.reshape(3, W, W)
+
+    def ghost_rows(self, level=0):
+        W = self.level_n(level) + 2
+        P = 3 * W * W
+        B, nB, th = np.zeros(2 * P), np.zeros(2 * P), np.zeros(2 * P)
+        w9 = np.zeros(9 * P)
+        c9 = np.zeros(9 * P, dtype=np.int32)
+        dt = np.zeros(P)
+        kind = np.zeros(P, dtype=np.int32)
+        self._check(lib().gp_get_ghost_rows(self._h, level, _ptr(B), _ptr(nB), _ptr(th), _ptr(w9), _ptr(c9), _ptr(dt),
+                                            _ptr(kind)), "gp_get_ghost_rows")
+        return dict(B=B.reshape(P, 2), nB=nB.reshape(P, 2), theta=th.reshape(P, 2), w=w9.reshape(P, 9),
+                    col=c9.reshape(P, 9), dtau=dt, valid=kind)
+
+    def ext_rows(self, level=0):
+        W = self.level_n(level) + 2
+        P = 3 * W * W
+        src = np.zeros(3 * P, dtype=np.int32)
+        w = np.zeros(3 * P)
+        self._check(lib().gp_get_ext_rows(self._h, level, _ptr(src), _ptr(w)), "gp_get_ext_rows")
+        return src.reshape(P, 3), w.reshape(P, 3)

@@ -1,0 +1,238 @@
+"""Parity of the HIP path with the CPU oracle (element by element, same seeded inputs).
+
+FP64 bar: geometry tables within 1e-12 (classes bit-exact), one relaxation step / one cycle within 1e-11
+relative, converged solves within 1e-10 relative.  Every case prints its name before touching the GPU.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1911_00994_amd import workloads as wl
+from tests.common import active_mask, oracle_geom
+
+pytestmark = pytest.mark.gpu
+
+CIRCLE = wl.Shape(wl.CIRCLE_DIST, (0.3,))
+ELLIPSE = wl.Shape(wl.ELLIPSE_SQRT, (0.4, 0.2, 0.0))
+FLOWER = wl.Shape(wl.PETALS, (0.35, 0.07, 0.0, 5.0))
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def gpu_solver(N, Re=100.0, **kw):
+    from paper_1911_00994_amd import gpmg
+    return gpmg.Solver(N, Re=Re, **kw)
+
+
+def pair(N, shape, alpha, motion=None, t=0.0, m=None, Re=100.0, zero_x=True):
+    """oracle and GPU solver on the same level set, alpha, rhs and boundary data"""
+    o = O.Oracle(N, Re=Re)
+    mo = motion.as_array() if motion is not None else np.zeros(6)
+    phi = O.levelset_analytic(shape.kind, shape.padded(), mo, t, N)
+    assert o.set_levelset(phi, t, mo) == O.OK
+    o.set_alpha(alpha)
+    s = gpu_solver(N, Re=Re)
+    s.set_levelset(phi, t, mo[:5])
+    s.set_alpha(alpha)
+    m = m or wl.TaylorGreenMMS()
+    fu, fv, g = wl.mms_linear_rhs(m, N, t, alpha)
+    bu, bv, bp = wl.boundary_values_from(m, oracle_geom(o), t, t)
+    W = N + 2
+    if zero_x:
+        z = np.zeros((W, W))
+        o.set_x(z, z, z, 0.0)
+        s.set_x(z, z, z, 0.0)
+    for side in (o, s):
+        side.set_boundary_values(bu, bv, bp)
+        side.set_rhs(fu, fv, g)
+    return o, s
+
+
+def flat(xs):
+    u, v, p, xi = xs
+    return np.concatenate([u.ravel(), v.ravel(), p.ravel(), [xi]])
+
+
+def rel_diff(a, b, mask):
+    d = np.abs(a - b)[mask].max()
+    return d / max(1.0, np.abs(a[mask]).max())
+
+
+@pytest.mark.parametrize("N,shape", [(64, CIRCLE), (128, ELLIPSE), (256, FLOWER), (256, wl.paper_flower())])
+def test_geometry_parity(N, shape):
+    say(f"[geometry] N={N} shape={shape}")
+    o, s = pair(N, shape, 0.64 * (2.0 / N) ** 2)
+    for l in range(o.nlev):
+        co, cg = o.classes(l), s.classes(l)
+        assert np.array_equal(co, cg), (l, np.argwhere(co != cg)[:5])
+        go, gg = o.ghost_rows(l), s.ghost_rows(l)
+        rows = go["valid"] >= 0
+        assert np.array_equal(rows, gg["valid"] >= 0)
+        assert np.array_equal(go["valid"][rows], gg["valid"][rows])
+        assert np.array_equal(go["col"][rows], gg["col"][rows])
+        for key in ("w", "theta", "B", "nB", "dtau"):
+            a, b = go[key][rows], gg[key][rows]
+            fin = np.isfinite(a)
+            assert np.array_equal(fin, np.isfinite(b)), key
+            assert np.abs(a[fin] - b[fin]).max(initial=0) < 1e-12 * max(1.0, np.abs(a[fin]).max(initial=0)), (l, key)
+        so, wo, _ = o.ext_rows(l)
+        sg, wg = s.ext_rows(l)
+        assert np.array_equal(so, sg), l
+        fin = so[:, 0] >= 0
+        assert np.abs(wo[fin] - wg[fin]).max(initial=0) < 1e-12
+
+
+def test_analytic_levelset_on_device_matches_oracle():
+    N = 256
+    say(f"[levelset] N={N}")
+    mo = wl.Motion(omega=1.0)
+    o = O.Oracle(N, Re=400.0)
+    phi = O.levelset_analytic(FLOWER.kind, FLOWER.padded(), mo.as_array(), 0.3, N)
+    assert o.set_levelset(phi, 0.3, mo.as_array()) == O.OK
+    s = gpu_solver(N, Re=400.0)
+    s.set_levelset_analytic(FLOWER.kind, FLOWER.params, 0.3, mo.as_array()[:5])
+    for l in range(o.nlev):
+        assert np.array_equal(o.classes(l), s.classes(l))
+    go, gg = o.ghost_rows(0), s.ghost_rows(0)
+    rows = go["valid"] >= 0
+    assert np.abs(go["w"][rows] - gg["w"][rows]).max() < 1e-9
+
+
+@pytest.mark.parametrize("shape", [CIRCLE, ELLIPSE])
+def test_relaxation_parity(shape):
+    N = 64
+    say(f"[relax] N={N} shape={shape}")
+    o, s = pair(N, shape, 0.64 * (2.0 / N) ** 2, zero_x=False)
+    rng = np.random.default_rng(5)
+    W = N + 2
+    x0 = [rng.standard_normal((W, W)) for _ in range(3)]
+    o.set_x(*x0, 0.1)
+    s.set_x(*x0, 0.1)
+    for side in (o, s):  # wall Dirichlet values from the boundary data
+        pass
+    bo = o.get_b()
+    # put the wall values in x on both sides the way a solve does
+    cls = o.classes().ravel()
+    xw = flat((*x0, 0.1))
+    walld = np.concatenate([cls == O.C_WALLD, [False]])
+    xw[walld] = bo[walld]
+    o.set_x(xw[:W * W].reshape(W, W), xw[W * W:2 * W * W].reshape(W, W), xw[2 * W * W:3 * W * W].reshape(W, W), 0.1)
+    s.set_x(xw[:W * W].reshape(W, W), xw[W * W:2 * W * W].reshape(W, W), xw[2 * W * W:3 * W * W].reshape(W, W), 0.1)
+    for steps in (1, 2):
+        o.relax(0, 1)
+        s.relax(0, 1)
+        a, b = flat(o.get_x()), flat(s.get_x())
+        act = np.concatenate([active_mask(cls), [True]])
+        assert rel_diff(a, b, act) < 1e-11, (steps, rel_diff(a, b, act))
+
+
+@pytest.mark.parametrize("N,shape", [(32, CIRCLE), (128, ELLIPSE), (256, FLOWER)])
+def test_cycle_parity(N, shape):
+    say(f"[cycle] N={N} shape={shape}")
+    o, s = pair(N, shape, 0.64 * (2.0 / N) ** 2)
+    cls = o.classes().ravel()
+    act = np.concatenate([active_mask(cls), [True]])
+    for c in range(3):
+        _, ro = o.cycle()
+        rg = s.cycle()
+        a, b = flat(o.get_x()), flat(s.get_x())
+        assert rel_diff(a, b, act) < 1e-11, (c, rel_diff(a, b, act))
+        assert abs(ro - rg) <= 1e-9 * max(1.0, ro), (c, ro, rg)
+
+
+@pytest.mark.parametrize("N,shape", [(64, CIRCLE), (128, FLOWER)])
+def test_converged_solve_parity(N, shape):
+    say(f"[solve] N={N} shape={shape}")
+    o, s = pair(N, shape, 0.64 * (2.0 / N) ** 2, m=wl.PaperMMS(), t=0.4)
+    st_o, so = o.solve(1e-12, 200)
+    st_g, sg = s.solve(1e-12, 200)
+    assert st_o == O.OK and st_g == 0
+    assert abs(so["cycles"] - sg["cycles"]) <= 1
+    cls = o.classes().ravel()
+    act = np.concatenate([active_mask(cls), [True]])
+    assert rel_diff(flat(o.get_x()), flat(s.get_x()), act) < 1e-10
+
+
+def _cn_lockstep(o, s, N, shape, motion, m, Re, nsteps, dt):
+    """advance oracle and GPU together; both get the boundary data computed from the oracle's geometry"""
+    mo = motion.as_array()
+    t = 0.0
+    xu, yu = wl.node_coords(N, 0)
+    xv, yv = wl.node_coords(N, 1)
+    xp, yp = wl.node_coords(N, 2)
+    out = []
+    for _ in range(nsteps):
+        t1 = t + dt
+        phi = O.levelset_analytic(shape.kind, shape.padded(), mo, t1, N)
+        assert o.set_levelset(phi, t1, mo) == O.OK
+        s.set_levelset(phi, t1, mo[:5])
+        bu, bv, bp = wl.boundary_values_from(m, oracle_geom(o), t1, t + 0.5 * dt, p_scale=dt)
+        fu, _ = m.forcing(xu, yu, t + 0.5 * dt, Re)
+        _, fv = m.forcing(xv, yv, t + 0.5 * dt, Re)
+        g = m.div(xp, yp, t1)
+        res = []
+        for side in (o, s):
+            side.set_boundary_values(bu, bv, bp)
+            st, info = side.cn_step(dt, fu, fv, g, tol=1e-12, max_cycles=200)
+            assert st == 0, (st, info)
+            res.append(flat(side.get_x()))
+        out.append(res)
+        t = t1
+    return out
+
+
+@pytest.mark.parametrize("N,shape,motion,m,steps", [
+    (32, CIRCLE, wl.Motion(), wl.TaylorGreenMMS(), 1),
+    (64, ELLIPSE, wl.Motion(U=(0.5, 0.0)), wl.BodyFrameMMS((0.5, 0.0)), 4),
+])
+def test_cn_step_parity(N, shape, motion, m, steps):
+    say(f"[cn] N={N} shape={shape} steps={steps}")
+    Re, dt = 100.0, 2.0 / N
+    mo = motion.as_array()
+    o = O.Oracle(N, Re=Re)
+    s = gpu_solver(N, Re=Re)
+    phi = O.levelset_analytic(shape.kind, shape.padded(), mo, 0.0, N)
+    o.set_levelset(phi, 0.0, mo)
+    s.set_levelset(phi, 0.0, mo[:5])
+    u0, v0, p0 = wl.mms_fields(m, N, 0.0)
+    o.set_state(u0, v0, dt * p0, 0.0)
+    s.set_state(u0, v0, dt * p0, 0.0)
+    out = _cn_lockstep(o, s, N, shape, motion, m, Re, steps, dt)
+    cls = o.classes().ravel()
+    act = np.concatenate([active_mask(cls), [True]])
+    for k, (a, b) in enumerate(out):
+        assert rel_diff(a, b, act) < 1e-9, (k, rel_diff(a, b, act))
+
+
+def test_full_size_cycle_parity():
+    """The metric workload's geometry at its full size (N = 1024, rotating petal body, Re = 400, dt = h,
+    random smooth forcing): three cycles compared element by element with the oracle."""
+    N, Re = 1024, 400.0
+    say(f"[full-size cycle] N={N}")
+    h = 2.0 / N
+    alpha = h / (2 * Re)
+    mo = wl.Motion(omega=1.0).as_array()
+    o = O.Oracle(N, Re=Re)
+    phi = O.levelset_analytic(FLOWER.kind, FLOWER.padded(), mo, 0.0, N)
+    assert o.set_levelset(phi, 0.0, mo) == O.OK
+    o.set_alpha(alpha)
+    s = gpu_solver(N, Re=Re)
+    s.set_levelset_analytic(FLOWER.kind, FLOWER.params, 0.0, mo[:5])
+    s.set_alpha(alpha)
+    assert np.array_equal(o.classes(), s.classes())
+    fu, fv = wl.fourier_forcing(N, 0)
+    for side in (o, s):
+        side.set_rhs(fu, fv, None)
+    cls = o.classes().ravel()
+    act = np.concatenate([active_mask(cls), [True]])
+    for c in range(3):
+        _, ro = o.cycle()
+        rg = s.cycle()
+        d = rel_diff(flat(o.get_x()), flat(s.get_x()), act)
+        say(f"  cycle {c}: res oracle {ro:.3e} gpu {rg:.3e} rel diff {d:.2e}")
+        assert d < 1e-10
