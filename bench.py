@@ -1,0 +1,212 @@
+"""Benchmark of the hot path: Crank-Nicolson steps of the rotating-flower workload on one MI355X.
+
+Workload (N = 1024): 1024 x 1024-cell MAC grid on (-1, 1)^2, five-petal body r = 0.35 (1 + 0.2 cos 5 theta)
+rotating at omega = 1, Re = 400, dt = h, seeded random smooth forcing (10 Fourier modes, amplitude 1), each step
+solved to a max-norm residual of 1e-8 (relative to max(1, ||b||)).  One step = device level-set sampling +
+geometry + CN right-hand side + multigrid solve (all of it in the HIP library).
+
+Prints one JSON line: MG unknowns/s = (unknowns of the system) x (V-cycles) / (wall time), whole job.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+
+
+def box_launch_bytes(cls, N, colour, elem=8):
+    """Algorithmic bytes of one box-relaxation launch (one colour): every distinct array element the launch
+    reads or writes, counted once (reads: the class bytes of the five box unknowns, the values of the
+    stencils of the box rows, the right-hand sides; writes: the five box unknowns).  Computed for the boxes
+    that have at least one internal unknown, as the kernel skips the others."""
+    import numpy as np
+    W = N + 2
+    I, J = np.meshgrid(np.arange(N), np.arange(N))
+    sel = ((I + 2 * J) % 5) == colour
+    i, j = I[sel], J[sel]
+    c = (j + 1) * W + (i + 1)
+    u, v, p = cls[0].ravel(), cls[1].ravel(), cls[2].ravel()
+    act = (u[c] == 1) | (u[c + 1] == 1) | (v[c] == 1) | (v[c + W] == 1) | (p[c] == 1)
+    c = c[act]
+    reads = {"cls_u": [c, c + 1], "cls_v": [c, c + W], "cls_p": [c],
+             "u": [c - 1, c, c + 1, c + 2, c - W, c + W, c + 1 - W, c + 1 + W],
+             "v": [c - W, c, c + W, c + 2 * W, c - 1, c + 1, c + W - 1, c + W + 1],
+             "p": [c - 1, c, c + 1, c - W, c + W],
+             "bu": [c, c + 1], "bv": [c, c + W], "bp": [c]}
+    total = 0
+    for k, lst in reads.items():
+        n = np.unique(np.concatenate(lst)).size
+        total += n * (1 if k.startswith("cls") else elem)
+    writes = np.unique(np.concatenate([c, c + 1])).size + np.unique(np.concatenate([c, c + W])).size + c.size
+    return total + writes * elem
+
+
+def cpu_baseline(wk, N, cycles):
+    """The oracle (plain C, one thread) on the same system: geometry at t = 0, then `cycles` V(2,2) cycles."""
+    import numpy as np
+    import oracle as O
+    from paper_1911_00994_amd import workloads as wl
+    h = 2.0 / N
+    o = O.Oracle(N, Re=wk.Re)
+    mo = wk.motion.as_array()
+    phi = O.levelset_analytic(wk.shape.kind, wk.shape.padded(), mo, 0.0, N)
+    assert o.set_levelset(phi, 0.0, mo) == O.OK
+    o.set_alpha(h / (2.0 * wk.Re))
+    fu, fv = wl.fourier_forcing(N, seed=0)
+    o.set_rhs(fu, fv, None)
+    o.cycle()  # first cycle also factorises the coarsest system; not timed
+    cls = o.classes(0)
+    n_unk = int(((cls == 1) | (cls == 2) | (cls == 4) | (cls == 7)).sum()) + 1
+    t0 = time.perf_counter()
+    for _ in range(cycles):
+        o.cycle()
+    sec = time.perf_counter() - t0
+    return {"value": n_unk * cycles / sec, "unit": "unknowns/s", "cores": 1, "kind": "oracle",
+            "sample": f"{cycles} V(2,2) cycles of the N={N} rotating-flower system (FP64, single thread, "
+                      f"{sec:.1f} s)"}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--N", type=int, default=1024)
+    ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
+    ap.add_argument("--tol", type=float, default=1e-8)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-cycles", type=int, default=3)
+    ap.add_argument("--no-kernel-timing", action="store_true")
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU decomposition is a "
+              f"design note, not part of this build", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_1911_00994_amd import gpmg
+    from paper_1911_00994_amd import workloads as wl
+
+    wk = wl.config_flower1024()
+    N = args.N
+    Re = wk.Re
+    h = 2.0 / N
+    dt = h
+    prec = gpmg.GP_MIXED if args.precision == "mixed" else gpmg.GP_FP64
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+    solver = gpmg.Solver(N, Re=Re, stream=stream.cuda_stream)
+    fu, fv = wl.fourier_forcing(N, seed=0)
+    fu_d = torch.from_numpy(fu).to(dev)
+    fv_d = torch.from_numpy(fv).to(dev)
+    motion = wk.motion.as_array()[:5]
+    shape = wk.shape
+    W = N + 2
+    z = np.zeros((W, W))
+    solver.set_levelset_analytic(shape.kind, shape.params, 0.0, motion)
+    solver.set_state(z, z, z, 0.0)
+    t = 0.0
+
+    def step():
+        nonlocal t
+        t1 = t + dt
+        solver.set_levelset_analytic(shape.kind, shape.params, t1, motion)
+        st, info = solver.cn_step(dt, fu_d.data_ptr(), fv_d.data_ptr(), None, on_device=True, precision=prec,
+                                  tol=args.tol, max_cycles=200, check=False)
+        if st != 0:
+            raise RuntimeError(f"cn_step status {st} at t={t1}: {info}")
+        t = t1
+        return info
+
+    for _ in range(args.warmup):
+        step()
+    cls = solver.classes(0)
+    n_unk = int(((cls == 1) | (cls == 2) | (cls == 4) | (cls == 7)).sum()) + 1
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    cycles = 0
+    picard = 0
+    t_wall0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(args.steps):
+        info = step()
+        cycles += info["cycles"]
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_wall0
+    ms = e0.elapsed_time(e1)
+    sec = ms / 1000.0
+    value = n_unk * cycles / sec
+    # algorithmic bytes of one V(2,2) cycle on the FP64 hierarchy: about 417 B per fine cell
+    cyc_bytes = 417.0 * N * N
+    cyc_gbs = cyc_bytes * cycles / sec / 1e9
+    roofline = None
+    if not args.no_kernel_timing:
+        # dominant kernel: box relaxation on the finest level, one colour per launch
+        avg_us = solver.time_kernel(0, level=0, reps=10)
+        nbytes = sum(box_launch_bytes(cls, N, c) for c in range(5)) / 5.0
+        achieved = nbytes / (avg_us * 1e-6) / 1e9
+        roofline = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                    "frac": achieved / PEAK_HBM_GBS, "traffic": None, "kernel": "k_box<double> finest level",
+                    "bytes_per_launch": nbytes, "avg_launch_us": avg_us}
+    # time to 1e-8 from x = 0 on the last step's system: FP64 cycles against FP32 cycles in FP64 refinement
+    u, v, p, xi = solver.get_x()
+    z = np.zeros((W, W))
+    ttt = {}
+    sols = {}
+    for name, pr in (("fp64", gpmg.GP_FP64), ("mixed", gpmg.GP_MIXED)):
+        solver.set_x(z, z, z, 0.0)
+        torch.cuda.synchronize()
+        a0 = time.perf_counter()
+        st, info = solver.solve(args.tol, 400, precision=pr, check=False)
+        ttt[name] = {"ms": 1000 * (time.perf_counter() - a0), "cycles": info["cycles"], "outer": info["outer"],
+                     "res": info["res"], "status": st}
+        sols[name] = np.concatenate([a.ravel() for a in solver.get_x()[:3]])
+    act = ((cls == 1) | (cls == 2) | (cls == 4) | (cls == 7)).ravel()
+    diff = float(np.abs(sols["fp64"] - sols["mixed"])[act].max() / max(1.0, np.abs(sols["fp64"][act]).max()))
+    solver.set_x(u, v, p, xi)
+    mixed_vs_fp64 = {"tol": args.tol, "fp64": ttt["fp64"], "mixed": ttt["mixed"],
+                     "speedup": ttt["fp64"]["ms"] / ttt["mixed"]["ms"], "max_rel_diff_mixed_vs_fp64": diff}
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(wk, N, args.cpu_cycles)
+    out = {
+        "metric": "MG unknowns/s at N=1024 (% HBM peak); mixed vs FP64 time-to-1e-8 residual",
+        "value": value,
+        "unit": "unknowns/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if prec == gpmg.GP_FP64 else "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": wk.name, "N": N, "Re": Re, "dt": "h", "tol": args.tol, "cycle": "V(2,2)",
+                   "precision": args.precision, "unknowns": n_unk, "cycles": cycles,
+                   "cycles_per_step": cycles / args.steps, "wall_s": wall,
+                   "cycle_level_hbm_fraction": cyc_gbs / PEAK_HBM_GBS},
+        "roofline": roofline,
+        "mixed_vs_fp64_time_to_tol": mixed_vs_fp64,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    del picard
+
+
+if __name__ == "__main__":
+    main()

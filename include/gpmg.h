@@ -158,6 +158,12 @@ gp_status gp_get_ext_rows(gp_ctx *ctx, int level, int *src3, double *w3);
 /* relaxation steps (Alg. relax with nu = steps) on one level in FP64, on that level's current x and b */
 gp_status gp_relax(gp_ctx *ctx, int level, int steps);
 
+/* measurement: average device time in microseconds of one launch of a kernel of the FP64 cycle, recorded
+ * with HIP events on the context's stream around reps repetitions on the given level's current data (the data
+ * are relaxed further by the box kernel; nothing else changes).  which: 0 = box relaxation (one colour per
+ * launch), 1 = residual of the internal rows, 2 = restriction, 3 = prolongation, 4 = ghost sweeps. */
+gp_status gp_time_kernel(gp_ctx *ctx, int which, int level, int reps, double *avg_us);
+
 #ifdef __cplusplus
 }
 #endif

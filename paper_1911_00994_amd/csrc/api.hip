@@ -474,4 +474,9 @@ gp_status gp_relax(gp_ctx *ctx, int level, int steps) {
   return relax64(ctx, level, steps);
 }
 
+gp_status gp_time_kernel(gp_ctx *ctx, int which, int level, int reps, double *avg_us) {
+  if (!ctx || !ctx->have_geom || level < 0 || level >= ctx->L || reps < 1 || !avg_us) return GP_EINVAL;
+  return time_kernel(ctx, which, level, reps, avg_us);
+}
+
 }  // extern "C"

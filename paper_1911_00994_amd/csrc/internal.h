@@ -111,6 +111,7 @@ gp_status mg_solve(Ctx *ctx, int precision, double tol, int max_cycles, gp_stats
 gp_status relax64(Ctx *ctx, int level, int steps);
 gp_status residual64(Ctx *ctx, int level, double *res_inf);
 gp_status set_wall_dirichlet(Ctx *ctx);
+gp_status time_kernel(Ctx *ctx, int which, int level, int reps, double *avg_us);
 
 // time stepping (cn.hip)
 gp_status cn_set_state_finish(Ctx *ctx);

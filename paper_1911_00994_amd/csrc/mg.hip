@@ -109,6 +109,26 @@ __global__ void k_ghost_b(const int *__restrict__ pt, int ng, const double *__re
   if (r < ng) x[pt[r]] = (T)tmp[r];
 }
 
+// all lambda sweeps in one workgroup: Jacobi phases separated by barriers (global memory, same CU)
+constexpr int GH_T = 1024;
+template <typename T>
+__global__ void __launch_bounds__(GH_T) k_ghost_sweeps(const int *__restrict__ pt, const int *__restrict__ col,
+                                                       const double *__restrict__ w, const double *__restrict__ dtau, int ng,
+                                                       T *x, const T *__restrict__ b, double *tmp, int sweeps) {
+  for (int it = 0; it < sweeps; it++) {
+    for (int r = threadIdx.x; r < ng; r += GH_T) {
+      int k = pt[r];
+      double s = 0;
+#pragma unroll
+      for (int q = 0; q < 9; q++) s += w[9 * r + q] * (double)x[col[9 * r + q]];
+      tmp[r] = (double)x[k] + dtau[r] * ((double)b[k] - s);
+    }
+    __syncthreads();
+    for (int r = threadIdx.x; r < ng; r += GH_T) x[pt[r]] = (T)tmp[r];
+    __syncthreads();
+  }
+}
+
 // ---------------------------------------------------------------------------------------------------------
 // deterministic grid reductions: fixed grid, fixed per-thread ranges, tree in LDS, the last block sums the
 // block partials in a fixed order
@@ -186,9 +206,15 @@ __global__ void k_pshift(int W, const uint8_t *__restrict__ cls, T *__restrict__
 // ---------------------------------------------------------------------------------------------------------
 // residual r = b - M x
 // ---------------------------------------------------------------------------------------------------------
+// max-norm accumulation: wavefront maximum first, then one atomic per wavefront (|v| as raw bits orders like
+// the value for non-negative doubles, and NaN sorts above everything)
 __device__ __forceinline__ void max_abs(unsigned long long *m, double v) {
-  double a = fabs(v);
-  atomicMax(m, (unsigned long long)__double_as_longlong(a));
+  unsigned long long a = (unsigned long long)__double_as_longlong(fabs(v));
+  for (int o = 32; o > 0; o >>= 1) {
+    unsigned long long b = __shfl_xor(a, o, 64);
+    a = b > a ? b : a;
+  }
+  if ((threadIdx.x & 63) == 0 && a) atomicMax(m, a);
 }
 
 template <typename T>
@@ -216,7 +242,36 @@ __global__ void __launch_bounds__(TPB) k_resid_pts(int N, int W, double h, doubl
     res = (double)b[t] - (double)x[t];
   }
   r[t] = (T)res;
-  if (rmax && res != 0.0) max_abs(rmax, res);
+  (void)N;
+}
+// variant with the max norm (all lanes of a wavefront take part in the reduction)
+template <typename T>
+__global__ void __launch_bounds__(TPB) k_resid_pts_norm(int N, int W, double h, double a, double d,
+                                                        const uint8_t *__restrict__ cls, const T *__restrict__ x,
+                                                        const T *__restrict__ b, T *__restrict__ r, unsigned long long *rmax) {
+  const int WW = W * W;
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  double res = 0;
+  if (t < 3 * WW) {
+    uint8_t c = cls[t];
+    if (c == K_INT) {
+      int g = t / WW, q = t - g * WW;
+      const T *u = x, *v = x + WW, *p = x + 2 * WW;
+      double ih = 1.0 / h;
+      if (g == 0)
+        res = (double)b[t] - (d * (double)u[q] - a * ((double)u[q - 1] + (double)u[q + 1] + (double)u[q - W] + (double)u[q + W]) +
+                              ((double)p[q] - (double)p[q - 1]) * ih);
+      else if (g == 1)
+        res = (double)b[t] - (d * (double)v[q] - a * ((double)v[q - 1] + (double)v[q + 1] + (double)v[q - W] + (double)v[q + W]) +
+                              ((double)p[q] - (double)p[q - W]) * ih);
+      else
+        res = (double)b[t] - (((double)u[q + 1] - (double)u[q] + (double)v[q + W] - (double)v[q]) * ih - (double)x[3 * WW]);
+    } else if (c == K_WALLD) {
+      res = (double)b[t] - (double)x[t];
+    }
+    r[t] = (T)res;
+  }
+  max_abs(rmax, res);
   (void)N;
 }
 template <typename T>
@@ -230,14 +285,37 @@ __global__ void k_resid_ghost(const int *__restrict__ pt, const int *__restrict_
   for (int z = 0; z < 9; z++) s += w[9 * q + z] * (double)x[col[9 * q + z]];
   double res = (double)b[k] - s;
   r[k] = (T)res;
-  if (rmax) max_abs(rmax, res);
+}
+template <typename T>
+__global__ void k_resid_ghost_norm(const int *__restrict__ pt, const int *__restrict__ col, const double *__restrict__ w,
+                                   int ng, const T *__restrict__ x, const T *__restrict__ b, T *__restrict__ r,
+                                   unsigned long long *rmax) {
+  int q = blockIdx.x * blockDim.x + threadIdx.x;
+  double res = 0;
+  if (q < ng) {
+    int k = pt[q];
+    double s = 0;
+#pragma unroll
+    for (int z = 0; z < 9; z++) s += w[9 * q + z] * (double)x[col[9 * q + z]];
+    res = (double)b[k] - s;
+    r[k] = (T)res;
+  }
+  max_abs(rmax, res);
 }
 // mean row residual 0 - mean(p) into r[3WW] and the norm
 template <typename T>
 __global__ void k_resid_mean(int W, const double *mean, T *r, unsigned long long *rmax) {
   double res = -*mean;
   r[3 * W * W] = (T)res;
-  if (rmax) max_abs(rmax, res);
+  atomicMax(rmax, (unsigned long long)__double_as_longlong(fabs(res)));
+}
+// max |b| over a vector (wavefront reduction, one atomic per wavefront)
+template <typename T>
+__global__ void k_absmax(const T *__restrict__ v, long n, unsigned long long *out) {
+  long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  double a = 0;
+  for (; t < n; t += (long)gridDim.x * blockDim.x) a = fmax(a, fabs((double)v[t]));
+  max_abs(out, a);
 }
 
 template <typename T>
@@ -436,6 +514,25 @@ Vec<float> &vec<float>(Ctx *ctx, int l) {
 static inline double coef_a(Ctx *ctx, int l) { return ctx->alpha / (ctx->geo[l].h * ctx->geo[l].h); }
 
 template <typename T>
+static void relax_ghosts(Ctx *ctx, int l) {
+  Geo &G = ctx->geo[l];
+  Vec<T> &V = vec<T>(ctx, l);
+  hipStream_t s = ctx->stream;
+  if (G.ng && ctx->prm.lambda_ghost > 0) {
+    if (G.ng <= 4 * GH_T) {
+      k_ghost_sweeps<T><<<1, GH_T, 0, s>>>(G.g_pt, G.g_col, G.g_w, G.g_dtau, G.ng, V.x, V.b, ctx->gtmp,
+                                           ctx->prm.lambda_ghost);
+    } else {
+      for (int it = 0; it < ctx->prm.lambda_ghost; it++) {
+        k_ghost_a<T><<<nblk(G.ng), TPB, 0, s>>>(G.g_pt, G.g_col, G.g_w, G.g_dtau, G.ng, V.x, V.b, ctx->gtmp);
+        k_ghost_b<T><<<nblk(G.ng), TPB, 0, s>>>(G.g_pt, G.ng, ctx->gtmp, V.x);
+      }
+    }
+  }
+}
+static void relax_ghost_only(Ctx *ctx, int l) { relax_ghosts<double>(ctx, l); }
+
+template <typename T>
 static void relax(Ctx *ctx, int l) {
   Geo &G = ctx->geo[l];
   Vec<T> &V = vec<T>(ctx, l);
@@ -443,11 +540,7 @@ static void relax(Ctx *ctx, int l) {
   double a = coef_a(ctx, l), d = 1.0 + 4.0 * a;
   int K = G.N / 5 + 1;
   for (int col = 0; col < 5; col++) k_box<T><<<nblk((long)K * G.N), TPB, 0, s>>>(G.N, G.W, G.h, a, d, G.cls, V.x, V.b, col);
-  if (G.ng)
-    for (int it = 0; it < ctx->prm.lambda_ghost; it++) {
-      k_ghost_a<T><<<nblk(G.ng), TPB, 0, s>>>(G.g_pt, G.g_col, G.g_w, G.g_dtau, G.ng, V.x, V.b, ctx->gtmp);
-      k_ghost_b<T><<<nblk(G.ng), TPB, 0, s>>>(G.g_pt, G.ng, ctx->gtmp, V.x);
-    }
+  relax_ghosts<T>(ctx, l);
   int nb = std::min(RED_BLOCKS, nblk((long)G.N * G.N));
   k_xi<T><<<nb, TPB, 0, s>>>(G.N, G.W, G.h, G.cls, V.x, V.b, ctx->d_red, ctx->d_ticket, G.d_mp);
 }
@@ -458,8 +551,13 @@ static void residual(Ctx *ctx, int l, unsigned long long *rmax) {
   Vec<T> &V = vec<T>(ctx, l);
   hipStream_t s = ctx->stream;
   double a = coef_a(ctx, l), d = 1.0 + 4.0 * a;
-  k_resid_pts<T><<<nblk(3L * G.WW), TPB, 0, s>>>(G.N, G.W, G.h, a, d, G.cls, V.x, V.b, V.r, rmax);
-  if (G.ng) k_resid_ghost<T><<<nblk(G.ng), TPB, 0, s>>>(G.g_pt, G.g_col, G.g_w, G.ng, V.x, V.b, V.r, rmax);
+  if (rmax) {
+    k_resid_pts_norm<T><<<nblk(3L * G.WW), TPB, 0, s>>>(G.N, G.W, G.h, a, d, G.cls, V.x, V.b, V.r, rmax);
+    if (G.ng) k_resid_ghost_norm<T><<<nblk(G.ng), TPB, 0, s>>>(G.g_pt, G.g_col, G.g_w, G.ng, V.x, V.b, V.r, rmax);
+  } else {
+    k_resid_pts<T><<<nblk(3L * G.WW), TPB, 0, s>>>(G.N, G.W, G.h, a, d, G.cls, V.x, V.b, V.r, nullptr);
+    if (G.ng) k_resid_ghost<T><<<nblk(G.ng), TPB, 0, s>>>(G.g_pt, G.g_col, G.g_w, G.ng, V.x, V.b, V.r, nullptr);
+  }
   if (rmax) {
     int nb = std::min(RED_BLOCKS, nblk(G.WW));
     k_pmean<T><<<nb, TPB, 0, s>>>(G.W, G.cls, V.x, ctx->d_red, ctx->d_ticket, G.d_mp, ctx->d_scal + 2);
@@ -520,12 +618,14 @@ static gp_status resnorm64(Ctx *ctx, double *out) {
 static gp_status bnorm64(Ctx *ctx, double *out) {
   // max |b| over the finest vector (entries without an equation are zero)
   Geo &G = ctx->geo[0];
-  std::vector<double> hb(G.n);
-  GP_HIP(hipMemcpyAsync(hb.data(), ctx->v64[0].b, G.n * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+  unsigned long long *m = (unsigned long long *)(ctx->d_scal + 3);
+  k_fill<unsigned long long><<<1, 1, 0, ctx->stream>>>(m, 1, 0ull);
+  k_absmax<double><<<std::min(1024, nblk(G.n)), TPB, 0, ctx->stream>>>(ctx->v64[0].b, G.n, m);
+  GP_HIP(hipGetLastError());
+  unsigned long long hv = 0;
+  GP_HIP(hipMemcpyAsync(&hv, m, sizeof(hv), hipMemcpyDeviceToHost, ctx->stream));
   GP_HIP(hipStreamSynchronize(ctx->stream));
-  double m = 0;
-  for (double v : hb) m = std::max(m, std::fabs(v));
-  *out = m;
+  std::memcpy(out, &hv, sizeof(double));
   return GP_OK;
 }
 
@@ -540,6 +640,51 @@ gp_status relax64(Ctx *ctx, int level, int steps) {
   for (int q = 0; q < steps; q++) relax<double>(ctx, level);
   GP_HIP(hipGetLastError());
   GP_HIP(hipStreamSynchronize(ctx->stream));
+  return GP_OK;
+}
+
+gp_status time_kernel(Ctx *ctx, int which, int l, int reps, double *avg_us) {
+  Geo &G = ctx->geo[l];
+  Vec<double> &V = ctx->v64[l];
+  hipStream_t s = ctx->stream;
+  double a = coef_a(ctx, l), d = 1.0 + 4.0 * a;
+  hipEvent_t e0, e1;
+  GP_HIP(hipEventCreate(&e0));
+  GP_HIP(hipEventCreate(&e1));
+  int K = G.N / 5 + 1;
+  int launches = 0;
+  GP_HIP(hipEventRecord(e0, s));
+  for (int q = 0; q < reps; q++) {
+    if (which == 0) {
+      for (int col = 0; col < 5; col++)
+        k_box<double><<<nblk((long)K * G.N), TPB, 0, s>>>(G.N, G.W, G.h, a, d, G.cls, V.x, V.b, col);
+      launches += 5;
+    } else if (which == 1) {
+      k_resid_pts<double><<<nblk(3L * G.WW), TPB, 0, s>>>(G.N, G.W, G.h, a, d, G.cls, V.x, V.b, V.r, nullptr);
+      launches++;
+    } else if (which == 2 && l + 1 < ctx->L) {
+      Geo &C = ctx->geo[l + 1];
+      k_restrict<double, double><<<nblk(3L * C.WW + 1), TPB, 0, s>>>(G.N, G.W, G.cls, V.r, C.N, C.W, C.cls, ctx->v64[l + 1].b);
+      launches++;
+    } else if (which == 3 && l + 1 < ctx->L) {
+      Geo &C = ctx->geo[l + 1];
+      k_fill<double><<<nblk(C.n), TPB, 0, s>>>(ctx->v64[l + 1].x, C.n, 0.0);  // zero correction: x unchanged
+      k_prolong<double, double><<<nblk(3L * G.WW + 1), TPB, 0, s>>>(G.N, G.W, G.cls, V.x, C.N, C.W, ctx->v64[l + 1].x);
+      launches++;
+    } else if (which == 4) {
+      relax_ghost_only(ctx, l);
+      launches++;
+    } else {
+      return GP_EINVAL;
+    }
+  }
+  GP_HIP(hipEventRecord(e1, s));
+  GP_HIP(hipEventSynchronize(e1));
+  float ms = 0;
+  GP_HIP(hipEventElapsedTime(&ms, e0, e1));
+  GP_HIP(hipEventDestroy(e0));
+  GP_HIP(hipEventDestroy(e1));
+  *avg_us = launches ? 1000.0 * ms / launches : 0.0;
   return GP_OK;
 }
 
@@ -559,6 +704,56 @@ gp_status mg_cycle64(Ctx *ctx, double *res_inf) {
   return GP_OK;
 }
 
+// ---------------------------------------------------------------------------------------------------------
+// mixed precision: FP64 iterative refinement around FP32 cycles
+//   r = b - M x (FP64), solve M e = r approximately by k FP32 cycles (FP64 arithmetic inside the kernels,
+//   FP64 ghost coefficients, FP64 reductions and coarsest solve), x += e, p <- p - mean(p) (FP64)
+// ---------------------------------------------------------------------------------------------------------
+__global__ void k_cast_rhs(const double *__restrict__ r, float *__restrict__ b, long n) {
+  long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (t < n) b[t] = (t == n - 1) ? 0.0f : (float)r[t];  // the mean row is restored by the FP64 projection
+}
+__global__ void k_add_correction(const uint8_t *__restrict__ cls, long n, const float *__restrict__ e, double *__restrict__ x) {
+  long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  if (t == n - 1) {
+    x[t] += (double)e[t];
+    return;
+  }
+  uint8_t c = cls[t];
+  if (c == K_INT || c == K_GHOST || c == K_GHOSTX || c == K_WALLG) x[t] += (double)e[t];
+}
+
+static gp_status ensure_fp32(Ctx *ctx) {
+  for (int l = 0; l < ctx->L; l++) {
+    Vec<float> &V = ctx->v32[l];
+    if (V.x) continue;
+    size_t n = ctx->geo[l].n;
+    GP_HIP(hipMalloc((void **)&V.x, n * sizeof(float)));
+    GP_HIP(hipMalloc((void **)&V.b, n * sizeof(float)));
+    GP_HIP(hipMalloc((void **)&V.r, n * sizeof(float)));
+    GP_HIP(hipMemsetAsync(V.x, 0, n * sizeof(float), ctx->stream));
+    GP_HIP(hipMemsetAsync(V.b, 0, n * sizeof(float), ctx->stream));
+    GP_HIP(hipMemsetAsync(V.r, 0, n * sizeof(float), ctx->stream));
+  }
+  return GP_OK;
+}
+
+// one refinement step; the FP64 residual of the current x must be in v64[0].r
+static void refine_step(Ctx *ctx, int inner) {
+  Geo &G = ctx->geo[0];
+  hipStream_t s = ctx->stream;
+  Vec<float> &E = ctx->v32[0];
+  k_cast_rhs<<<nblk(G.n), TPB, 0, s>>>(ctx->v64[0].r, E.b, G.n);
+  k_fill<float><<<nblk(G.n), TPB, 0, s>>>(E.x, G.n, 0.0f);
+  for (int q = 0; q < inner; q++) {
+    cycle<float>(ctx, 0);
+    mean_project<float>(ctx);
+  }
+  k_add_correction<<<nblk(G.n), TPB, 0, s>>>(G.cls, G.n, E.x, ctx->v64[0].x);
+  mean_project<double>(ctx);
+}
+
 gp_status mg_solve(Ctx *ctx, int precision, double tol, int max_cycles, gp_stats *stt) {
   auto t0 = std::chrono::steady_clock::now();
   gp_status st = set_wall_dirichlet(ctx);
@@ -568,7 +763,7 @@ gp_status mg_solve(Ctx *ctx, int precision, double tol, int max_cycles, gp_stats
   if ((st = bnorm64(ctx, &bn))) return st;
   double thr = tol * (bn > 1 ? bn : 1);
   double r = r0, rho = 0;
-  int c = 0;
+  int c = 0, outer = 0;
   gp_status out = GP_OK;
   if (precision == GP_FP64) {
     while (r > thr && c < max_cycles) {
@@ -584,13 +779,26 @@ gp_status mg_solve(Ctx *ctx, int precision, double tol, int max_cycles, gp_stats
       }
     }
   } else {
-    return GP_EINVAL;  // mixed precision: see mixed.hip
+    if ((st = ensure_fp32(ctx))) return st;
+    int k = ctx->prm.mixed_inner_cycles;
+    while (r > thr && c < max_cycles) {
+      refine_step(ctx, k);  // v64[0].r holds the residual of the last resnorm64
+      double rp = r;
+      if ((st = resnorm64(ctx, &r))) return st;
+      c += k;
+      outer++;
+      rho = r / rp;
+      if (!(r == r) || r > 1e6 * (r0 > 1 ? r0 : 1)) {
+        out = GP_EDIVERGED;
+        break;
+      }
+    }
   }
   if (out == GP_OK && r > thr) out = GP_ENOCONV;
   ctx->last_cycles = c;
   if (stt) {
     stt->cycles = c;
-    stt->outer = 0;
+    stt->outer = outer;
     stt->res0 = r0;
     stt->res = r;
     stt->rho = rho;

@@ -23,7 +23,7 @@ EXPORTS = [
     "gp_set_levelset", "gp_set_levelset_analytic", "gp_set_walls", "gp_get_boundary_geometry",
     "gp_set_boundary_values", "gp_set_alpha", "gp_set_rhs", "gp_set_x", "gp_get_x", "gp_mg_vcycle", "gp_solve",
     "gp_residual", "gp_set_state", "gp_cn_step", "gp_get_classes", "gp_get_ghost_rows", "gp_get_ext_rows",
-    "gp_relax",
+    "gp_relax", "gp_time_kernel",
 ]
 
 
@@ -95,6 +95,7 @@ def lib():
         "gp_get_ghost_rows": (i, [vp, i, vp, vp, vp, vp, vp, vp, vp]),
         "gp_get_ext_rows": (i, [vp, i, vp, vp]),
         "gp_relax": (i, [vp, i, i]),
+        "gp_time_kernel": (i, [vp, i, i, i, vp]),
     }
     for name, (res, args) in sigs.items():
         f = getattr(L, name)
@@ -223,6 +224,12 @@ class Solver:
         ri = ctypes.c_double(0)
         self._check(lib().gp_residual(self._h, _ptr(r), ctypes.byref(ri)), "gp_residual")
         return r, ri.value
+
+    def time_kernel(self, which, level=0, reps=10):
+        """average device microseconds of one launch (HIP events on the context's stream)"""
+        us = ctypes.c_double(0)
+        self._check(lib().gp_time_kernel(self._h, which, level, reps, ctypes.byref(us)), "gp_time_kernel")
+        return us.value
 
     def relax(self, level=0, steps=1):
         self._check(lib().gp_relax(self._h, level, steps), "gp_relax")

@@ -236,3 +236,31 @@ def test_full_size_cycle_parity():
         d = rel_diff(flat(o.get_x()), flat(s.get_x()), act)
         say(f"  cycle {c}: res oracle {ro:.3e} gpu {rg:.3e} rel diff {d:.2e}")
         assert d < 1e-10
+
+
+@pytest.mark.parametrize("N,shape", [(128, ELLIPSE), (256, FLOWER)])
+def test_mixed_precision_solve_against_oracle(N, shape):
+    """FP32 cycles inside FP64 iterative refinement: at tolerance 1e-8 the solution differs from the converged
+    FP64 oracle solution by no more than the FP64 solver at the same tolerance does, times 10 (stated bound),
+    and the FP64 residual meets the tolerance."""
+    say(f"[mixed] N={N} shape={shape}")
+    from paper_1911_00994_amd import gpmg
+    alpha = 0.64 * (2.0 / N) ** 2
+    o, s = pair(N, shape, alpha, m=wl.PaperMMS(), t=0.4)
+    st_o, _ = o.solve(1e-11, 300)
+    assert st_o == O.OK
+    xo = flat(o.get_x())
+    cls = o.classes().ravel()
+    act = np.concatenate([active_mask(cls), [True]])
+    W = N + 2
+    z = np.zeros((W, W))
+    s.set_x(z, z, z, 0.0)
+    st64, i64 = s.solve(1e-8, 200, precision=gpmg.GP_FP64)
+    e64 = rel_diff(xo, flat(s.get_x()), act)
+    s.set_x(z, z, z, 0.0)
+    stm, im = s.solve(1e-8, 200, precision=gpmg.GP_MIXED)
+    em = rel_diff(xo, flat(s.get_x()), act)
+    say(f"  fp64: {i64['cycles']} cycles err {e64:.2e}; mixed: {im['cycles']} cycles ({im['outer']} outer) err {em:.2e}")
+    assert st64 == 0 and stm == 0
+    assert im["res"] <= 1e-8 * max(1.0, 1.0) * 1e3  # residual is relative to max(1, ||b||)
+    assert em <= 10 * e64 + 1e-10
