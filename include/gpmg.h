@@ -64,11 +64,14 @@ enum { GP_INACTIVE = 0, GP_INTERNAL = 1, GP_GHOST = 2, GP_WALL_DIRICHLET = 3, GP
  * W cycle is gamma = 2, Sect. 4.3), lambda_ghost = 2 ghost sweeps per box sweep (Alg. relax), coarsest grid
  * 8 x 8 cells solved exactly (Sect. 4.3), Alg. 1 march limit 8 steps and bisection accuracy 0.01 h (Sect. 3.3),
  * fictitious time steps 0.9 (Dirichlet) and 0.9 h (normal derivative) (Sect. 4.1.2), extension band of 4
- * grid steps, minimum ghost-row diagonal 0.1 (below it the ghost takes an extrapolation row). */
+ * grid steps, minimum ghost-row diagonal 0.1 (below it the ghost takes an extrapolation row), and after each
+ * relaxation step bnd_sweeps = 1 extra box sweep (same colour order, each followed by lambda_ghost ghost
+ * sweeps) over the cells within bnd_radius = 2 cells of a cell touching the body. */
 typedef struct {
   int nu1, nu2, gamma, lambda_ghost, coarsest_n, march_max, ext_radius;
   double dtau_dir, dtau_neu_over_h, bisect_eps_over_h, cg_min;
   int mixed_inner_cycles; /* FP32 cycles per FP64 refinement step in GP_MIXED solves */
+  int bnd_sweeps, bnd_radius;
 } gp_params;
 
 /* rigid motion: the body frame point of x at time t is R(-omega t) (x - X0 - U t); the boundary velocity at a

@@ -91,7 +91,7 @@ typedef struct {
   OLevel lev[MAXLEV];
   double Re, alpha;
   /* parameters */
-  int nu1, nu2, gamma, lambda, coarsest_n, march_max, nbis, ext_radius, colour_perm_seed;
+  int nu1, nu2, gamma, lambda, coarsest_n, march_max, nbis, ext_radius, colour_perm_seed, bnd_sweeps, bnd_radius;
   double dtau_dir, dtau_neu_over_h, eps_over_h, cg_min;
   /* geometry / boundary data */
   double *phi; /* (2N+1)^2 fine half lattice */
@@ -312,6 +312,8 @@ void *or_create(int N, double Re, const int *ip, const double *dp) {
   S->march_max = ip[5];
   S->ext_radius = ip[6];
   S->colour_perm_seed = ip[7];
+  S->bnd_sweeps = ip[8];
+  S->bnd_radius = ip[9];
 
   S->dtau_dir = dp[0];
   S->dtau_neu_over_h = dp[1];
@@ -1142,14 +1144,46 @@ static void box_relax(OLevel *L, int i, int j) {
   for (int a = 0; a < m; a++) L->x[U[a]] = rhs[a];
 }
 
+/* cells touching the body: one of the five box unknowns is neither internal nor a wall point */
+static int cut_cell(const OLevel *L, int i, int j) {
+  int cand[5] = {gidx(L, 0, i, j), gidx(L, 0, i + 1, j), gidx(L, 1, i, j), gidx(L, 1, i, j + 1), gidx(L, 2, i, j)};
+  for (int q = 0; q < 5; q++) {
+    unsigned char c = L->cls[cand[q]];
+    if (c != C_INT && c != C_WALLD) return 1;
+  }
+  return 0;
+}
+static int in_band(const OLevel *L, int i, int j, int R) {
+  for (int dj = -R; dj <= R; dj++)
+    for (int di = -R; di <= R; di++) {
+      int a = i + di, b = j + dj;
+      if (a < 0 || b < 0 || a >= L->N || b >= L->N) continue;
+      if (cut_cell(L, a, b)) return 1;
+    }
+  return 0;
+}
+static void ghost_sweeps(OSolver *S, OLevel *L) {
+  double *nv = (double *)calloc(L->ng ? L->ng : 1, sizeof(double));
+  for (int it = 0; it < S->lambda; it++) {
+    for (int r = 0; r < L->ng; r++) {
+      int k = L->g_pt[r];
+      nv[r] = L->x[k] + L->g_dtau[r] * (L->b[k] - row_dot(L, k, L->x));
+    }
+    for (int r = 0; r < L->ng; r++) L->x[L->g_pt[r]] = nv[r];
+  }
+  free(nv);
+}
+
 static uint64_t lcg_next(uint64_t *s) {
   *s = *s * 6364136223846793005ULL + 1442695040888963407ULL;
   return *s >> 33;
 }
 
 /* one relaxation step (Alg. relax with nu = 1): box sweep in the colour order (i + 2j) mod 5 = 0..4,
- * lambda simultaneous ghost sweeps (eq. ghostrelax), then the average-divergence unknown xi is set so
- * that the continuity residuals sum to zero. */
+ * lambda simultaneous ghost sweeps (eq. ghostrelax), then bnd_sweeps extra box sweeps restricted to the
+ * cells within bnd_radius cells of a cell touching the body, each followed by lambda ghost sweeps (boundary
+ * relaxation: the slowest error components of this discretisation sit at the body), then the
+ * average-divergence unknown xi is set so that the continuity residuals sum to zero. */
 static void relax_step(OSolver *S, int l) {
   OLevel *L = &S->lev[l];
   int N = L->N, WW = L->W * L->W;
@@ -1179,15 +1213,14 @@ static void relax_step(OSolver *S, int l) {
       free(list);
     }
   }
-  double *nv = (double *)xcalloc(L->ng, sizeof(double));
-  for (int it = 0; it < S->lambda; it++) {
-    for (int r = 0; r < L->ng; r++) {
-      int k = L->g_pt[r];
-      nv[r] = L->x[k] + L->g_dtau[r] * (L->b[k] - row_dot(L, k, L->x));
-    }
-    for (int r = 0; r < L->ng; r++) L->x[L->g_pt[r]] = nv[r];
+  ghost_sweeps(S, L);
+  for (int q = 0; q < S->bnd_sweeps; q++) {
+    for (int col = 0; col < 5; col++)
+      for (int j = 0; j < N; j++)
+        for (int i = 0; i < N; i++)
+          if ((i + 2 * j) % 5 == col && in_band(L, i, j, S->bnd_radius)) box_relax(L, i, j);
+    ghost_sweeps(S, L);
   }
-  free(nv);
   /* xi <- xi - mean(continuity residual) */
   double s = 0;
   for (int k = 2 * WW; k < 3 * WW; k++)

@@ -85,6 +85,8 @@ void gp_default_params(gp_params *p) {
   p->bisect_eps_over_h = 0.01;
   p->cg_min = 0.1;
   p->mixed_inner_cycles = 2;
+  p->bnd_sweeps = 1;
+  p->bnd_radius = 2;
 }
 
 const char *gp_strerror(gp_status st) {
@@ -122,6 +124,8 @@ void gp_destroy(gp_ctx *ctx) {
     dfree(G.e_src);
     dfree(G.e_w);
     dfree(G.d_mp);
+    dfree(G.band);
+    dfree(G.d_band_off);
     dfree(ctx->v64[l].x);
     dfree(ctx->v64[l].b);
     dfree(ctx->v64[l].r);
@@ -160,7 +164,8 @@ gp_status gp_setup_grid(gp_ctx **out, int N, double Re, const gp_params *prm, vo
   else
     gp_default_params(&P);
   if (!pow2(N) || N < 16 || !pow2(P.coarsest_n) || P.coarsest_n < 4 || P.coarsest_n > N / 2 || P.nu1 < 0 || P.nu2 < 0 ||
-      P.gamma < 1 || P.lambda_ghost < 0 || P.march_max < 1 || P.ext_radius < 1 || !(Re > 0) || P.mixed_inner_cycles < 1)
+      P.gamma < 1 || P.lambda_ghost < 0 || P.march_max < 1 || P.ext_radius < 1 || !(Re > 0) || P.mixed_inner_cycles < 1 ||
+      P.bnd_sweeps < 0 || P.bnd_radius < 0)
     return GP_EINVAL;
   gp_ctx *ctx = new gp_ctx();
   ctx->N = N;
@@ -203,6 +208,8 @@ gp_status gp_setup_grid(gp_ctx **out, int N, double Re, const gp_params *prm, vo
     ALLOC(G.e_src, (size_t)3 * G.ecap);
     ALLOC(G.e_w, (size_t)3 * G.ecap);
     ALLOC(G.d_mp, 1);
+    ALLOC(G.band, (size_t)G.N * G.N);
+    ALLOC(G.d_band_off, 8);
     ALLOC(ctx->v64[l].x, (size_t)G.n);
     ALLOC(ctx->v64[l].b, (size_t)G.n);
     ALLOC(ctx->v64[l].r, (size_t)G.n);

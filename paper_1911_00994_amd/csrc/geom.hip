@@ -482,6 +482,37 @@ __global__ void k_empty_cells(const uint8_t *cls, int N, int W, int *flags) {
   if (nf == 0) atomicOr(&flags[1], 2);
 }
 
+// boundary band: cells with at least one internal box unknown within R cells (max norm) of a cell touching the
+// body (one of its five box unknowns is neither internal nor a wall point); counted / listed per colour
+__device__ bool cut_cell(const uint8_t *cls, int W, int i, int j) {
+  int WW = W * W, c = (j + 1) * W + (i + 1);
+  uint8_t k[5] = {cls[c], cls[c + 1], cls[WW + c], cls[WW + c + W], cls[2 * WW + c]};
+  for (int q = 0; q < 5; q++)
+    if (k[q] != K_INT && k[q] != K_WALLD) return true;
+  return false;
+}
+__global__ void k_band(const uint8_t *cls, int N, int W, int R, int pass, int *off, int *band) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= N * N) return;
+  int i = t % N, j = t / N, WW = W * W, c = (j + 1) * W + (i + 1);
+  bool any = cls[c] == K_INT || cls[c + 1] == K_INT || cls[WW + c] == K_INT || cls[WW + c + W] == K_INT ||
+             cls[2 * WW + c] == K_INT;
+  if (!any) return;
+  bool near = false;
+  for (int dj = -R; dj <= R && !near; dj++)
+    for (int di = -R; di <= R && !near; di++) {
+      int a = i + di, b = j + dj;
+      if (a < 0 || b < 0 || a >= N || b >= N) continue;
+      if (cut_cell(cls, W, a, b)) near = true;
+    }
+  if (!near) return;
+  int col = (i + 2 * j) % 5;
+  if (pass == 0)
+    atomicAdd(&off[col + 1], 1);  // counts, turned into offsets on the host side of the pass
+  else
+    band[atomicAdd(&off[col], 1)] = t;
+}
+
 // ---------------------------------------------------------------------------------------------------------
 // boundary data of the finest level
 // ---------------------------------------------------------------------------------------------------------
@@ -604,6 +635,23 @@ static gp_status build_level(Ctx *ctx, int l) {
   }
   GP_HIP(hipMemsetAsync(G.d_mp, 0, sizeof(int), s));
   k_count_mp<<<nblk(W * W), TPB, 0, s>>>(G.cls, W, G.d_mp);
+  // boundary band lists (two passes: counts, then fill from the offsets)
+  {
+    int hoff[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    GP_HIP(hipMemsetAsync(G.d_band_off, 0, 8 * sizeof(int), s));
+    if (ctx->prm.bnd_sweeps > 0)
+      k_band<<<nblk(G.N * G.N), TPB, 0, s>>>(G.cls, G.N, W, ctx->prm.bnd_radius, 0, G.d_band_off, G.band);
+    GP_HIP(hipMemcpyAsync(hoff, G.d_band_off, 8 * sizeof(int), hipMemcpyDeviceToHost, s));
+    GP_HIP(hipStreamSynchronize(s));
+    for (int c = 1; c <= 5; c++) hoff[c] += hoff[c - 1];
+    G.nband = hoff[5];
+    GP_HIP(hipMemcpyAsync(G.d_band_off, hoff, 8 * sizeof(int), hipMemcpyHostToDevice, s));
+    if (G.nband)
+      k_band<<<nblk(G.N * G.N), TPB, 0, s>>>(G.cls, G.N, W, ctx->prm.bnd_radius, 1, G.d_band_off, G.band);
+    // the fill pass advanced each start offset to the next one: restore the offsets
+    GP_HIP(hipMemcpyAsync(G.d_band_off, hoff, 8 * sizeof(int), hipMemcpyHostToDevice, s));
+    GP_HIP(hipStreamSynchronize(s));
+  }
   if (l == 0) k_empty_cells<<<nblk(G.N * G.N), TPB, 0, s>>>(G.cls, G.N, W, ctx->d_flags);
   GP_HIP(hipGetLastError());
   GP_HIP(hipMemcpyAsync(&G.mp, G.d_mp, sizeof(int), hipMemcpyDeviceToHost, s));

@@ -45,6 +45,10 @@ struct Geo {
   double *e_w = nullptr;
   int *d_mp = nullptr;              // device: number of internal pressure points
   int mp = 0;                       // host copy
+  // cells of the boundary band, grouped by colour: band[band_off[c] .. band_off[c+1]) (cell index j*N + i)
+  int *band = nullptr;
+  int *d_band_off = nullptr;        // device: 6 offsets
+  int nband = 0;                    // host copy of the total
 };
 
 // one precision's vectors on one level

@@ -23,29 +23,29 @@ __device__ __forceinline__ int pidx(int W, int i, int j) { return (j + 1) * W + 
 // and the continuity row fixes p.
 // ---------------------------------------------------------------------------------------------------------
 template <typename T>
-__global__ void __launch_bounds__(TPB) k_box(int N, int W, double h, double a, double d, const uint8_t *__restrict__ cls,
-                                             T *__restrict__ x, const T *__restrict__ b, int colour) {
-  const int K = N / 5 + 1;
-  int t = blockIdx.x * blockDim.x + threadIdx.x;
-  int j = t / K, kk = t - j * K;
-  if (j >= N) return;
-  int i = ((colour - 2 * j) % 5 + 5) % 5 + 5 * kk;
-  if (i >= N) return;
+__device__ __forceinline__ void box_update(int N, int W, double h, double a, double d, const uint8_t *__restrict__ cls,
+                                           T *__restrict__ x, const T *__restrict__ b, int i, int j) {
   const int WW = W * W;
   T *u = x, *v = x + WW, *p = x + 2 * WW;
   const T *bu = b, *bv = b + WW, *bp = b + 2 * WW;
-  const int c = pidx(W, i, j);
-  const bool fW = cls[c] == K_INT, fE = cls[c + 1] == K_INT, fS = cls[WW + c] == K_INT, fN = cls[WW + c + W] == K_INT,
-             fP = cls[2 * WW + c] == K_INT;
+  const int c = (j + 1) * W + (i + 1);
+  // every load is issued up front (all indices stay inside the padded arrays for 0 <= i, j < N); the
+  // classes then decide which values enter the box
+  const uint8_t kW = cls[c], kE = cls[c + 1], kS = cls[WW + c], kN = cls[WW + c + W], kP = cls[2 * WW + c];
+  const double uW = u[c], uE = u[c + 1], vS = v[c], vN = v[c + W], pc = p[c];
+  const double uWW = u[c - 1], uEE = u[c + 2], uWS = u[c - W], uWN = u[c + W], uES = u[c + 1 - W], uEN = u[c + 1 + W];
+  const double vSS = v[c - W], vNN = v[c + 2 * W], vSW = v[c - 1], vSE = v[c + 1], vNW = v[c + W - 1], vNE = v[c + W + 1];
+  const double pW = p[c - 1], pE = p[c + 1], pS = p[c - W], pN = p[c + W];
+  const double bW_ = bu[c], bE_ = bu[c + 1], bS_ = bv[c], bN_ = bv[c + W], bP_ = bp[c];
+  const double xi = (double)x[3 * WW];
+  const bool fW = kW == K_INT, fE = kE == K_INT, fS = kS == K_INT, fN = kN == K_INT, fP = kP == K_INT;
   if (!(fW || fE || fS || fN || fP)) return;
   const double ih = 1.0 / h;
-  const double uW = u[c], uE = u[c + 1], vS = v[c], vN = v[c + W], pc = p[c];
   double aW = uW, bW = 0, aE = uE, bE = 0, aS = vS, bS = 0, aN = vN, bN = 0;
   const double det = d * d - a * a;
-  if (fW || fE) {
-    double RW = 0, RE = 0;
-    if (fW) RW = (double)bu[c] + a * ((double)u[c - 1] + (double)u[c - W] + (double)u[c + W]) + (double)p[c - 1] * ih;
-    if (fE) RE = (double)bu[c + 1] + a * ((double)u[c + 2] + (double)u[c + 1 - W] + (double)u[c + 1 + W]) - (double)p[c + 1] * ih;
+  {
+    const double RW = bW_ + a * (uWW + uWS + uWN) + pW * ih;
+    const double RE = bE_ + a * (uEE + uES + uEN) - pE * ih;
     if (fW && fE) {
       aW = (d * RW + a * RE) / det;
       bW = -ih / (d + a);
@@ -54,15 +54,14 @@ __global__ void __launch_bounds__(TPB) k_box(int N, int W, double h, double a, d
     } else if (fW) {
       aW = (RW + a * uE) / d;
       bW = -ih / d;
-    } else {
+    } else if (fE) {
       aE = (RE + a * uW) / d;
       bE = ih / d;
     }
   }
-  if (fS || fN) {
-    double RS = 0, RN = 0;
-    if (fS) RS = (double)bv[c] + a * ((double)v[c - W] + (double)v[c - 1] + (double)v[c + 1]) + (double)p[c - W] * ih;
-    if (fN) RN = (double)bv[c + W] + a * ((double)v[c + 2 * W] + (double)v[c + W - 1] + (double)v[c + W + 1]) - (double)p[c + W] * ih;
+  {
+    const double RS = bS_ + a * (vSS + vSW + vSE) + pS * ih;
+    const double RN = bN_ + a * (vNN + vNW + vNE) - pN * ih;
     if (fS && fN) {
       aS = (d * RS + a * RN) / det;
       bS = -ih / (d + a);
@@ -71,23 +70,38 @@ __global__ void __launch_bounds__(TPB) k_box(int N, int W, double h, double a, d
     } else if (fS) {
       aS = (RS + a * vN) / d;
       bS = -ih / d;
-    } else {
+    } else if (fN) {
       aN = (RN + a * vS) / d;
       bN = ih / d;
     }
   }
   double pn = pc;
   if (fP) {
-    double den = bE - bW + bN - bS;
+    const double den = bE - bW + bN - bS;
     if (den == 0.0) return;  // no free face: the block is singular, the box is skipped
-    double xi = (double)x[3 * WW];
-    pn = (h * (xi + (double)bp[c]) - (aE - aW + aN - aS)) / den;
+    pn = (h * (xi + bP_) - (aE - aW + aN - aS)) / den;
     p[c] = (T)pn;
   }
   if (fW) u[c] = (T)(aW + bW * pn);
   if (fE) u[c + 1] = (T)(aE + bE * pn);
   if (fS) v[c] = (T)(aS + bS * pn);
   if (fN) v[c + W] = (T)(aN + bN * pn);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(TPB) k_box(int N, int W, double h, double a, double d, const uint8_t *__restrict__ cls,
+                                             T *__restrict__ x, const T *__restrict__ b, int colour) {
+  const int K = N / 5 + 1;
+  // workgroups are dealt to the 8 XCDs round robin: remap so that each XCD works on one contiguous band of
+  // rows and its L2 sees the row halos of its own band
+  const int nb = gridDim.x, per = (nb + 7) / 8;
+  const int lb = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+  int t = lb * blockDim.x + threadIdx.x;
+  int j = t / K, kk = t - j * K;
+  if (j >= N) return;
+  int i = ((colour - 2 * j) % 5 + 5) % 5 + 5 * kk;
+  if (i >= N) return;
+  box_update<T>(N, W, h, a, d, cls, x, b, i, j);
 }
 
 // fictitious-time relaxation of every ghost row at once (eq. ghostrelax, Jacobi): w += dtau (g - B w)
@@ -126,6 +140,54 @@ __global__ void __launch_bounds__(GH_T) k_ghost_sweeps(const int *__restrict__ p
     __syncthreads();
     for (int r = threadIdx.x; r < ng; r += GH_T) x[pt[r]] = (T)tmp[r];
     __syncthreads();
+  }
+}
+
+// extra relaxation of the boundary band (one workgroup): `sweeps` times the box sweep over the band cells in
+// the colour order, each followed by lambda ghost sweeps
+constexpr int BAND_T = 1024;
+template <typename T>
+__global__ void __launch_bounds__(BAND_T) k_band_sweeps(int N, int W, double h, double a, double d,
+                                                        const uint8_t *__restrict__ cls, T *x, const T *__restrict__ b,
+                                                        const int *__restrict__ band, const int *__restrict__ off,
+                                                        const int *__restrict__ pt, const int *__restrict__ col,
+                                                        const double *__restrict__ w, const double *__restrict__ dtau,
+                                                        int ng, double *tmp, int sweeps, int lambda, int ghosts_first) {
+  if (ghosts_first) {
+    for (int it = 0; it < lambda; it++) {
+      for (int r = threadIdx.x; r < ng; r += BAND_T) {
+        int k = pt[r];
+        double sum = 0;
+#pragma unroll
+        for (int z = 0; z < 9; z++) sum += w[9 * r + z] * (double)x[col[9 * r + z]];
+        tmp[r] = (double)x[k] + dtau[r] * ((double)b[k] - sum);
+      }
+      __syncthreads();
+      for (int r = threadIdx.x; r < ng; r += BAND_T) x[pt[r]] = (T)tmp[r];
+      __syncthreads();
+    }
+  }
+  for (int s = 0; s < sweeps; s++) {
+    for (int c = 0; c < 5; c++) {
+      int lo = off[c], hi = off[c + 1];
+      for (int q = lo + threadIdx.x; q < hi; q += BAND_T) {
+        int cell = band[q];
+        box_update<T>(N, W, h, a, d, cls, x, b, cell % N, cell / N);
+      }
+      __syncthreads();
+    }
+    for (int it = 0; it < lambda; it++) {
+      for (int r = threadIdx.x; r < ng; r += BAND_T) {
+        int k = pt[r];
+        double sum = 0;
+#pragma unroll
+        for (int z = 0; z < 9; z++) sum += w[9 * r + z] * (double)x[col[9 * r + z]];
+        tmp[r] = (double)x[k] + dtau[r] * ((double)b[k] - sum);
+      }
+      __syncthreads();
+      for (int r = threadIdx.x; r < ng; r += BAND_T) x[pt[r]] = (T)tmp[r];
+      __syncthreads();
+    }
   }
 }
 
@@ -245,14 +307,30 @@ __global__ void __launch_bounds__(TPB) k_resid_pts(int N, int W, double h, doubl
   (void)N;
 }
 // variant with the max norm (all lanes of a wavefront take part in the reduction)
+__device__ __forceinline__ void block_max_atomic(unsigned long long *m, double v) {
+  __shared__ unsigned long long sm[TPB / 64];
+  unsigned long long a = (unsigned long long)__double_as_longlong(fabs(v));
+  for (int o = 32; o > 0; o >>= 1) {
+    unsigned long long b = __shfl_xor(a, o, 64);
+    a = b > a ? b : a;
+  }
+  if ((threadIdx.x & 63) == 0) sm[threadIdx.x >> 6] = a;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long z = 0;
+    for (int q = 0; q < TPB / 64; q++) z = sm[q] > z ? sm[q] : z;
+    if (z) atomicMax(m, z);
+  }
+}
+
 template <typename T>
 __global__ void __launch_bounds__(TPB) k_resid_pts_norm(int N, int W, double h, double a, double d,
                                                         const uint8_t *__restrict__ cls, const T *__restrict__ x,
                                                         const T *__restrict__ b, T *__restrict__ r, unsigned long long *rmax) {
   const int WW = W * W;
-  int t = blockIdx.x * blockDim.x + threadIdx.x;
-  double res = 0;
-  if (t < 3 * WW) {
+  double mx = 0;
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < 3 * WW; t += gridDim.x * blockDim.x) {
+    double res = 0;
     uint8_t c = cls[t];
     if (c == K_INT) {
       int g = t / WW, q = t - g * WW;
@@ -270,8 +348,10 @@ __global__ void __launch_bounds__(TPB) k_resid_pts_norm(int N, int W, double h, 
       res = (double)b[t] - (double)x[t];
     }
     r[t] = (T)res;
+    double ar = fabs(res);
+    mx = (ar > mx || ar != ar) ? ar : mx;
   }
-  max_abs(rmax, res);
+  block_max_atomic(rmax, mx);
   (void)N;
 }
 template <typename T>
@@ -511,6 +591,8 @@ Vec<float> &vec<float>(Ctx *ctx, int l) {
   return ctx->v32[l];
 }
 
+static inline int box_grid(int K, int N) { return ((nblk((long)K * N) + 7) / 8) * 8; }
+
 static inline double coef_a(Ctx *ctx, int l) { return ctx->alpha / (ctx->geo[l].h * ctx->geo[l].h); }
 
 template <typename T>
@@ -539,8 +621,18 @@ static void relax(Ctx *ctx, int l) {
   hipStream_t s = ctx->stream;
   double a = coef_a(ctx, l), d = 1.0 + 4.0 * a;
   int K = G.N / 5 + 1;
-  for (int col = 0; col < 5; col++) k_box<T><<<nblk((long)K * G.N), TPB, 0, s>>>(G.N, G.W, G.h, a, d, G.cls, V.x, V.b, col);
-  relax_ghosts<T>(ctx, l);
+  for (int col = 0; col < 5; col++) k_box<T><<<box_grid(K, G.N), TPB, 0, s>>>(G.N, G.W, G.h, a, d, G.cls, V.x, V.b, col);
+  const bool band = ctx->prm.bnd_sweeps > 0 && G.nband > 0;
+  if (band && G.ng <= 4 * GH_T) {
+    // ghost sweeps and the band sweeps in one workgroup
+    k_band_sweeps<T><<<1, BAND_T, 0, s>>>(G.N, G.W, G.h, a, d, G.cls, V.x, V.b, G.band, G.d_band_off, G.g_pt, G.g_col,
+                                          G.g_w, G.g_dtau, G.ng, ctx->gtmp, ctx->prm.bnd_sweeps, ctx->prm.lambda_ghost, 1);
+  } else {
+    relax_ghosts<T>(ctx, l);
+    if (band)
+      k_band_sweeps<T><<<1, BAND_T, 0, s>>>(G.N, G.W, G.h, a, d, G.cls, V.x, V.b, G.band, G.d_band_off, G.g_pt, G.g_col,
+                                            G.g_w, G.g_dtau, G.ng, ctx->gtmp, ctx->prm.bnd_sweeps, ctx->prm.lambda_ghost, 0);
+  }
   int nb = std::min(RED_BLOCKS, nblk((long)G.N * G.N));
   k_xi<T><<<nb, TPB, 0, s>>>(G.N, G.W, G.h, G.cls, V.x, V.b, ctx->d_red, ctx->d_ticket, G.d_mp);
 }
@@ -552,7 +644,7 @@ static void residual(Ctx *ctx, int l, unsigned long long *rmax) {
   hipStream_t s = ctx->stream;
   double a = coef_a(ctx, l), d = 1.0 + 4.0 * a;
   if (rmax) {
-    k_resid_pts_norm<T><<<nblk(3L * G.WW), TPB, 0, s>>>(G.N, G.W, G.h, a, d, G.cls, V.x, V.b, V.r, rmax);
+    k_resid_pts_norm<T><<<std::min(2048, nblk(3L * G.WW)), TPB, 0, s>>>(G.N, G.W, G.h, a, d, G.cls, V.x, V.b, V.r, rmax);
     if (G.ng) k_resid_ghost_norm<T><<<nblk(G.ng), TPB, 0, s>>>(G.g_pt, G.g_col, G.g_w, G.ng, V.x, V.b, V.r, rmax);
   } else {
     k_resid_pts<T><<<nblk(3L * G.WW), TPB, 0, s>>>(G.N, G.W, G.h, a, d, G.cls, V.x, V.b, V.r, nullptr);
@@ -657,7 +749,7 @@ gp_status time_kernel(Ctx *ctx, int which, int l, int reps, double *avg_us) {
   for (int q = 0; q < reps; q++) {
     if (which == 0) {
       for (int col = 0; col < 5; col++)
-        k_box<double><<<nblk((long)K * G.N), TPB, 0, s>>>(G.N, G.W, G.h, a, d, G.cls, V.x, V.b, col);
+        k_box<double><<<box_grid(K, G.N), TPB, 0, s>>>(G.N, G.W, G.h, a, d, G.cls, V.x, V.b, col);
       launches += 5;
     } else if (which == 1) {
       k_resid_pts<double><<<nblk(3L * G.WW), TPB, 0, s>>>(G.N, G.W, G.h, a, d, G.cls, V.x, V.b, V.r, nullptr);
