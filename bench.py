@@ -84,6 +84,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-cycles", type=int, default=3)
     ap.add_argument("--no-kernel-timing", action="store_true")
+    ap.add_argument("--profile-kernel", action="store_true",
+                    help="set up the N=1024 system, run 2 x 5 box-relaxation launches on the finest level and a "
+                         "plain 64 MiB device copy (counter calibration), then exit (for rocprofv3 --pmc runs)")
     return ap.parse_args()
 
 
@@ -130,6 +133,20 @@ def main():
         t = t1
         return info
 
+    if args.profile_kernel:
+        src = torch.ones(8 << 20, dtype=torch.float64, device=dev)  # 64 MiB
+        dst = torch.empty_like(src)
+        flush = torch.empty(64 << 20, dtype=torch.float64, device=dev)  # 512 MiB: evicts L2 and MALL
+        for _ in range(3):
+            flush.fill_(1.0)
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del flush
+        solver.set_alpha(dt / (2.0 * Re))
+        solver.set_rhs(fu, fv, None)
+        us = solver.time_kernel(0, level=0, reps=2)
+        print(json.dumps({"profile_kernel": "k_box<double> finest", "avg_launch_us": us, "copy_bytes": 2 * (64 << 20)}))
+        return
     for _ in range(args.warmup):
         step()
     cls = solver.classes(0)
