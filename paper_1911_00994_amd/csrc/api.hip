@@ -126,6 +126,12 @@ void gp_destroy(gp_ctx *ctx) {
     dfree(G.d_mp);
     dfree(G.band);
     dfree(G.d_band_off);
+    dfree(G.reg_map);
+    dfree(G.reg_pt);
+    dfree(G.bbox);
+    dfree(G.bg_rows);
+    dfree(G.bg_loc);
+    dfree(G.wg_rows);
     dfree(ctx->v64[l].x);
     dfree(ctx->v64[l].b);
     dfree(ctx->v64[l].r);
@@ -210,6 +216,12 @@ gp_status gp_setup_grid(gp_ctx **out, int N, double Re, const gp_params *prm, vo
     ALLOC(G.d_mp, 1);
     ALLOC(G.band, (size_t)G.N * G.N);
     ALLOC(G.d_band_off, 8);
+    ALLOC(G.reg_map, (size_t)3 * G.WW + 1);
+    ALLOC(G.reg_pt, (size_t)G.gcap * 12 + (size_t)32 * G.N + 4096);
+    ALLOC(G.bbox, (size_t)22 * (G.N * 24 + 4096));
+    ALLOC(G.bg_rows, (size_t)G.gcap);
+    ALLOC(G.bg_loc, (size_t)10 * G.gcap);
+    ALLOC(G.wg_rows, (size_t)G.gcap);
     ALLOC(ctx->v64[l].x, (size_t)G.n);
     ALLOC(ctx->v64[l].b, (size_t)G.n);
     ALLOC(ctx->v64[l].r, (size_t)G.n);
@@ -220,7 +232,7 @@ gp_status gp_setup_grid(gp_ctx **out, int N, double Re, const gp_params *prm, vo
   }
   ALLOC(ctx->phi, (size_t)(2 * N + 1) * (2 * N + 1));
   ALLOC(ctx->gtmp, gmax);
-  ALLOC(ctx->d_red, 1024);
+  ALLOC(ctx->d_red, 8192);
   ALLOC(ctx->d_ticket, 4);
   ALLOC(ctx->d_scal, 16);
   ALLOC(ctx->d_flags, 16);
@@ -241,6 +253,12 @@ gp_status gp_setup_grid(gp_ctx **out, int N, double Re, const gp_params *prm, vo
   ALLOC(ctx->ckv, (size_t)WW);
   ALLOC(ctx->fwork, (size_t)3 * WW + 1);
 #undef ALLOC
+  {
+    int dev = 0, lds = 0;
+    GP_HIP(hipGetDevice(&dev));
+    GP_HIP(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+    ctx->max_lds = (size_t)lds;
+  }
   GP_HIP(hipStreamSynchronize(ctx->stream));
   *out = ctx;
   return GP_OK;

@@ -513,6 +513,114 @@ __global__ void k_band(const uint8_t *cls, int N, int W, int R, int pass, int *o
     band[atomicAdd(&off[col], 1)] = t;
 }
 
+// ---- boundary region tables for the LDS band kernel ----
+// the 21 values a box update reads around cell index c (u: W E WW EE WS WN ES EN; v: S N SS NN SW SE NW NE;
+// p: c W E S N) as global indices
+__device__ __forceinline__ void box_points(int W, int c, int out[21]) {
+  int WW = W * W;
+  int q = 0;
+  out[q++] = c;          // uW
+  out[q++] = c + 1;      // uE
+  out[q++] = c - 1;      // uWW
+  out[q++] = c + 2;      // uEE
+  out[q++] = c - W;      // uWS
+  out[q++] = c + W;      // uWN
+  out[q++] = c + 1 - W;  // uES
+  out[q++] = c + 1 + W;  // uEN
+  out[q++] = WW + c;          // vS
+  out[q++] = WW + c + W;      // vN
+  out[q++] = WW + c - W;      // vSS
+  out[q++] = WW + c + 2 * W;  // vNN
+  out[q++] = WW + c - 1;      // vSW
+  out[q++] = WW + c + 1;      // vSE
+  out[q++] = WW + c + W - 1;  // vNW
+  out[q++] = WW + c + W + 1;  // vNE
+  out[q++] = 2 * WW + c;      // p
+  out[q++] = 2 * WW + c - 1;  // pW
+  out[q++] = 2 * WW + c + 1;  // pE
+  out[q++] = 2 * WW + c - W;  // pS
+  out[q++] = 2 * WW + c + W;  // pN
+}
+
+__global__ void k_region_clear(int *map, int n) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n) map[t] = -1;
+}
+// mark: map[k] = -2 for every point the band kernel writes (the five unknowns of a band box, body ghost points);
+// every other point it reads is constant during the kernel and is read from global memory
+__global__ void k_region_mark(const uint8_t *cls, int N, int W, const int *band, int nband, const int *g_pt,
+                              const int *g_col, int ng, int *map) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  int WW = W * W;
+  if (t < nband) {
+    int cell = band[t], i = cell % N, j = cell / N, c = (j + 1) * W + (i + 1);
+    map[c] = -2;
+    map[c + 1] = -2;
+    map[WW + c] = -2;
+    map[WW + c + W] = -2;
+    map[2 * WW + c] = -2;
+  } else if (t < nband + ng) {
+    int r = t - nband;
+    if (cls[g_pt[r]] == K_WALLG) return;
+    map[g_pt[r]] = -2;
+  }
+  (void)g_col;
+}
+__global__ void k_region_compact(int *map, int n, int *reg_pt, int cap, int *count) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n || map[t] != -2) return;
+  int slot = atomicAdd(count, 1);
+  if (slot < cap) {
+    reg_pt[slot] = t;
+    map[t] = slot;
+  } else
+    map[t] = -1;
+}
+// per band box: local indices of its 21 values, then the flags of its free unknowns (bits W E S N P)
+__global__ void k_region_boxes(const uint8_t *cls, int N, int W, const int *band, int nband, const int *map, int *bbox,
+                               int *bad) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nband) return;
+  int cell = band[t], i = cell % N, j = cell / N, WW = W * W, c = (j + 1) * W + (i + 1);
+  int pts[21];
+  box_points(W, c, pts);
+  for (int q = 0; q < 21; q++) {
+    int l = map[pts[q]];
+    // local LDS slot, or -(global index + 1) for a point the kernel only reads
+    bbox[22 * t + q] = l >= 0 ? l : -(pts[q] + 1);
+    if (cls[pts[q]] == K_WALLG) atomicOr(bad, 8);  // wall ghosts are swept before the band kernel
+  }
+  int f = (cls[c] == K_INT ? 1 : 0) | (cls[c + 1] == K_INT ? 2 : 0) | (cls[WW + c] == K_INT ? 4 : 0) |
+          (cls[WW + c + W] == K_INT ? 8 : 0) | (cls[2 * WW + c] == K_INT ? 16 : 0);
+  bbox[22 * t + 21] = f;
+}
+// ghost rows split into body rows (with local indices) and wall rows; a wall row whose nodes a band box writes
+// or whose stencil holds another ghost is reported (the LDS kernel then does not apply)
+__global__ void k_region_rows(const uint8_t *cls, const int *g_pt, const int *g_col, int ng, const int *map, int *bg_rows,
+                              int *bg_loc, int *wg_rows, int *counts, int *bad) {
+  int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= ng) return;
+  int k = g_pt[r];
+  if (cls[k] == K_WALLG) {
+    for (int q = 1; q < 9; q++) {
+      int c = g_col[9 * r + q];
+      if (c != k && (map[c] >= 0 || cls[c] == K_GHOST || cls[c] == K_GHOSTX || cls[c] == K_WALLG)) atomicOr(bad, 2);
+    if (map[k] >= 0) atomicOr(bad, 2);
+    }
+    wg_rows[atomicAdd(&counts[1], 1)] = r;
+    return;
+  }
+  for (int q = 0; q < 9; q++)
+    if (cls[g_col[9 * r + q]] == K_WALLG) atomicOr(bad, 4);  // a body row would see a wall ghost: keep the order
+  int s = atomicAdd(&counts[0], 1);
+  bg_rows[s] = r;
+  bg_loc[10 * s] = map[k];
+  for (int q = 0; q < 9; q++) {
+    int c = g_col[9 * r + q], l = map[c];
+    bg_loc[10 * s + 1 + q] = l >= 0 ? l : -(c + 1);
+  }
+}
+
 // ---------------------------------------------------------------------------------------------------------
 // boundary data of the finest level
 // ---------------------------------------------------------------------------------------------------------
@@ -651,6 +759,28 @@ static gp_status build_level(Ctx *ctx, int l) {
     // the fill pass advanced each start offset to the next one: restore the offsets
     GP_HIP(hipMemcpyAsync(G.d_band_off, hoff, 8 * sizeof(int), hipMemcpyHostToDevice, s));
     GP_HIP(hipStreamSynchronize(s));
+    for (int c = 0; c < 8; c++) G.hband_off[c] = hoff[c];
+  }
+  // boundary region of the LDS band kernel
+  G.lds_ok = 0;
+  if (G.nband > 0 && G.nband <= G.N * 24 + 4096) {
+    int regcap = G.gcap * 12 + 32 * G.N + 4096;
+    k_region_clear<<<nblk(3 * W * W + 1), TPB, 0, s>>>(G.reg_map, 3 * W * W + 1);
+    k_region_mark<<<nblk(G.nband + G.ng), TPB, 0, s>>>(G.cls, G.N, W, G.band, G.nband, G.g_pt, G.g_col, G.ng, G.reg_map);
+    GP_HIP(hipMemsetAsync(ctx->d_flags + 8, 0, 4 * sizeof(int), s));
+    k_region_compact<<<nblk(3 * W * W), TPB, 0, s>>>(G.reg_map, 3 * W * W, G.reg_pt, regcap, ctx->d_flags + 8);
+    k_region_boxes<<<nblk(G.nband), TPB, 0, s>>>(G.cls, G.N, W, G.band, G.nband, G.reg_map, G.bbox, ctx->d_flags + 11);
+    if (G.ng)
+      k_region_rows<<<nblk(G.ng), TPB, 0, s>>>(G.cls, G.g_pt, G.g_col, G.ng, G.reg_map, G.bg_rows, G.bg_loc, G.wg_rows,
+                                               ctx->d_flags + 9, ctx->d_flags + 11);
+    GP_HIP(hipGetLastError());
+    int hr[4];
+    GP_HIP(hipMemcpyAsync(hr, ctx->d_flags + 8, 4 * sizeof(int), hipMemcpyDeviceToHost, s));
+    GP_HIP(hipStreamSynchronize(s));
+    G.nreg = hr[0];
+    G.nbg = hr[1];
+    G.nwg = hr[2];
+    G.lds_ok = (hr[3] == 0 && G.nreg <= regcap) ? 1 : 0;
   }
   if (l == 0) k_empty_cells<<<nblk(G.N * G.N), TPB, 0, s>>>(G.cls, G.N, W, ctx->d_flags);
   GP_HIP(hipGetLastError());

@@ -49,6 +49,13 @@ struct Geo {
   int *band = nullptr;
   int *d_band_off = nullptr;        // device: 6 offsets
   int nband = 0;                    // host copy of the total
+  int hband_off[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  // boundary region staged in LDS by the band kernel: region points (global index), global -> local map,
+  // per band box the local indices of its 21 values and its 5 free-unknown flags, body ghost rows (row id and
+  // 10 local indices), wall ghost rows (row ids)
+  int *reg_pt = nullptr, *reg_map = nullptr, *bbox = nullptr, *bg_rows = nullptr, *bg_loc = nullptr, *wg_rows = nullptr;
+  int nreg = 0, nbg = 0, nwg = 0;
+  int lds_ok = 0;                   // 1 when the LDS band kernel applies to this level
 };
 
 // one precision's vectors on one level
@@ -89,6 +96,7 @@ struct Ctx {
   double *lapu = nullptr, *lapv = nullptr, *fbase = nullptr, *cku = nullptr, *ckv = nullptr;
   double *fwork = nullptr;          // 3*WW staging for inputs
   int last_cycles = 0;
+  size_t max_lds = 65536;           // dynamic LDS a workgroup may use on this device
 };
 
 // error handling

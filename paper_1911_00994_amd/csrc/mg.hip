@@ -191,6 +191,144 @@ __global__ void __launch_bounds__(BAND_T) k_band_sweeps(int N, int W, double h, 
   }
 }
 
+// Same work as k_band_sweeps for the body ghost rows and the band boxes, with the values of the boundary
+// region staged in LDS (one global round trip per phase for the constant data only).  The wall ghost rows are
+// done before by k_wall_ghosts (they read only internal points next to the walls, which no band box writes,
+// so their 2 x lambda sweeps can run at once).  Body ghost rows per thread are limited to MAXR.
+constexpr int MAXR = 8;
+template <typename T>
+__global__ void __launch_bounds__(BAND_T) k_band_lds(int N, int W, double h, double a, double d, T *x, const T *__restrict__ b,
+                                                     const int *__restrict__ band, const int *__restrict__ off,
+                                                     const int *__restrict__ bbox, const int *__restrict__ reg_pt, int nreg,
+                                                     const int *__restrict__ bg_rows, const int *__restrict__ bg_loc, int nbg,
+                                                     const int *__restrict__ g_pt, const double *__restrict__ g_w,
+                                                     const double *__restrict__ g_dtau, int sweeps, int lambda) {
+  extern __shared__ unsigned char lds_raw[];
+  T *xs = reinterpret_cast<T *>(lds_raw);
+  const int WW = W * W;
+  // value of a table entry: local LDS slot (written by this kernel) or -(global index + 1) (read only)
+  auto val = [&](int e) -> double { return e >= 0 ? (double)xs[e] : (double)x[-e - 1]; };
+  const int tid = threadIdx.x;
+  for (int q = tid; q < nreg; q += BAND_T) xs[q] = x[reg_pt[q]];
+  const double xi = (double)x[3 * WW];
+  const double ih = 1.0 / h, det = d * d - a * a;
+  __syncthreads();
+  auto ghost_block = [&]() {
+    for (int it = 0; it < lambda; it++) {
+      double nv[MAXR];
+#pragma unroll
+      for (int m = 0; m < MAXR; m++) {
+        int s2 = tid + m * BAND_T;
+        if (s2 < nbg) {
+          int r = bg_rows[s2];
+          const int *lc = bg_loc + 10 * s2;
+          double sum = 0;
+#pragma unroll
+          for (int z = 0; z < 9; z++) sum += g_w[9 * r + z] * val(lc[1 + z]);
+          nv[m] = (double)xs[lc[0]] + g_dtau[r] * ((double)b[g_pt[r]] - sum);
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int m = 0; m < MAXR; m++) {
+        int s2 = tid + m * BAND_T;
+        if (s2 < nbg) xs[bg_loc[10 * s2]] = (T)nv[m];
+      }
+      __syncthreads();
+    }
+  };
+  ghost_block();
+  for (int sw = 0; sw < sweeps; sw++) {
+    for (int c = 0; c < 5; c++) {
+      for (int q = off[c] + tid; q < off[c + 1]; q += BAND_T) {
+        const int *tb = bbox + 22 * q;
+        int cell = band[q], i = cell % N, j = cell / N, cg = (j + 1) * W + (i + 1);
+        int f = tb[21];
+        bool fW = f & 1, fE = f & 2, fS = f & 4, fN = f & 8, fP = f & 16;
+        double uW = val(tb[0]), uE = val(tb[1]), uWW = val(tb[2]), uEE = val(tb[3]), uWS = val(tb[4]), uWN = val(tb[5]),
+               uES = val(tb[6]), uEN = val(tb[7]);
+        double vS = val(tb[8]), vN = val(tb[9]), vSS = val(tb[10]), vNN = val(tb[11]), vSW = val(tb[12]),
+               vSE = val(tb[13]), vNW = val(tb[14]), vNE = val(tb[15]);
+        double pc = val(tb[16]), pW = val(tb[17]), pE = val(tb[18]), pS = val(tb[19]), pN = val(tb[20]);
+        double bW_ = b[cg], bE_ = b[cg + 1], bS_ = b[WW + cg], bN_ = b[WW + cg + W], bP_ = b[2 * WW + cg];
+        double aW = uW, bW = 0, aE = uE, bE = 0, aS = vS, bS = 0, aN = vN, bN = 0;
+        {
+          double RW = bW_ + a * (uWW + uWS + uWN) + pW * ih, RE = bE_ + a * (uEE + uES + uEN) - pE * ih;
+          if (fW && fE) {
+            aW = (d * RW + a * RE) / det;
+            bW = -ih / (d + a);
+            aE = (a * RW + d * RE) / det;
+            bE = ih / (d + a);
+          } else if (fW) {
+            aW = (RW + a * uE) / d;
+            bW = -ih / d;
+          } else if (fE) {
+            aE = (RE + a * uW) / d;
+            bE = ih / d;
+          }
+        }
+        {
+          double RS = bS_ + a * (vSS + vSW + vSE) + pS * ih, RN = bN_ + a * (vNN + vNW + vNE) - pN * ih;
+          if (fS && fN) {
+            aS = (d * RS + a * RN) / det;
+            bS = -ih / (d + a);
+            aN = (a * RS + d * RN) / det;
+            bN = ih / (d + a);
+          } else if (fS) {
+            aS = (RS + a * vN) / d;
+            bS = -ih / d;
+          } else if (fN) {
+            aN = (RN + a * vS) / d;
+            bN = ih / d;
+          }
+        }
+        double pn = pc;
+        bool skip = false;
+        if (fP) {
+          double den = bE - bW + bN - bS;
+          if (den == 0.0)
+            skip = true;
+          else {
+            pn = (h * (xi + bP_) - (aE - aW + aN - aS)) / den;
+            xs[tb[16]] = (T)pn;
+          }
+        }
+        if (!skip) {
+          if (fW) xs[tb[0]] = (T)(aW + bW * pn);
+          if (fE) xs[tb[1]] = (T)(aE + bE * pn);
+          if (fS) xs[tb[8]] = (T)(aS + bS * pn);
+          if (fN) xs[tb[9]] = (T)(aN + bN * pn);
+        }
+      }
+      __syncthreads();
+    }
+    ghost_block();
+  }
+  for (int q = tid; q < nreg; q += BAND_T) x[reg_pt[q]] = xs[q];
+}
+
+// wall ghost rows: 2 x lambda (or lambda) Jacobi sweeps at once, each row independent of every other ghost
+template <typename T>
+__global__ void k_wall_ghosts(const int *__restrict__ rows, int nwg, const int *__restrict__ g_pt, const int *__restrict__ g_col,
+                              const double *__restrict__ g_w, const double *__restrict__ g_dtau, T *x, const T *__restrict__ b,
+                              int sweeps) {
+  int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= nwg) return;
+  int r = rows[q], k = g_pt[r];
+  double rest = 0, w0 = 0;
+#pragma unroll
+  for (int z = 0; z < 9; z++) {
+    int c = g_col[9 * r + z];
+    if (c == k)
+      w0 += g_w[9 * r + z];
+    else
+      rest += g_w[9 * r + z] * (double)x[c];
+  }
+  double xv = (double)x[k], bb = (double)b[k], dt = g_dtau[r];
+  for (int it = 0; it < sweeps; it++) xv = xv + dt * (bb - (w0 * xv + rest));
+  x[k] = (T)xv;
+}
+
 // ---------------------------------------------------------------------------------------------------------
 // deterministic grid reductions: fixed grid, fixed per-thread ranges, tree in LDS, the last block sums the
 // block partials in a fixed order
@@ -623,7 +761,15 @@ static void relax(Ctx *ctx, int l) {
   int K = G.N / 5 + 1;
   for (int col = 0; col < 5; col++) k_box<T><<<box_grid(K, G.N), TPB, 0, s>>>(G.N, G.W, G.h, a, d, G.cls, V.x, V.b, col);
   const bool band = ctx->prm.bnd_sweeps > 0 && G.nband > 0;
-  if (band && G.ng <= 4 * GH_T) {
+  const size_t lds_bytes = (size_t)G.nreg * sizeof(T);
+  if (band && G.lds_ok && lds_bytes + 1024 <= ctx->max_lds && G.nbg <= MAXR * BAND_T) {
+    if (G.nwg)
+      k_wall_ghosts<T><<<nblk(G.nwg), TPB, 0, s>>>(G.wg_rows, G.nwg, G.g_pt, G.g_col, G.g_w, G.g_dtau, V.x, V.b,
+                                                    ctx->prm.lambda_ghost * (1 + ctx->prm.bnd_sweeps));
+    k_band_lds<T><<<1, BAND_T, lds_bytes, s>>>(G.N, G.W, G.h, a, d, V.x, V.b, G.band, G.d_band_off, G.bbox, G.reg_pt, G.nreg,
+                                               G.bg_rows, G.bg_loc, G.nbg, G.g_pt, G.g_w, G.g_dtau, ctx->prm.bnd_sweeps,
+                                               ctx->prm.lambda_ghost);
+  } else if (band && G.ng <= 4 * GH_T) {
     // ghost sweeps and the band sweeps in one workgroup
     k_band_sweeps<T><<<1, BAND_T, 0, s>>>(G.N, G.W, G.h, a, d, G.cls, V.x, V.b, G.band, G.d_band_off, G.g_pt, G.g_col,
                                           G.g_w, G.g_dtau, G.ng, ctx->gtmp, ctx->prm.bnd_sweeps, ctx->prm.lambda_ghost, 1);
