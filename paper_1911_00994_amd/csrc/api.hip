@@ -129,9 +129,13 @@ void gp_destroy(gp_ctx *ctx) {
     dfree(G.reg_map);
     dfree(G.reg_pt);
     dfree(G.bbox);
-    dfree(G.bg_rows);
+    dfree(G.bg_k);
     dfree(G.bg_loc);
+    dfree(G.bg_w);
+    dfree(G.bg_dt);
     dfree(G.wg_rows);
+    dfree(G.f_code);
+    dfree(G.f_loc);
     dfree(ctx->v64[l].x);
     dfree(ctx->v64[l].b);
     dfree(ctx->v64[l].r);
@@ -144,9 +148,13 @@ void gp_destroy(gp_ctx *ctx) {
   dfree(ctx->d_red);
   dfree(ctx->d_ticket);
   dfree(ctx->d_scal);
+  dfree(ctx->d_lev);
+  dfree(ctx->d_bcnt);
+  dfree(ctx->d_iscr);
   dfree(ctx->d_flags);
   dfree(ctx->c_map);
   dfree(ctx->c_A);
+  dfree(ctx->c_bmap);
   dfree(ctx->c_work);
   for (int k = 0; k < 3; k++) {
     dfree(ctx->cu[k]);
@@ -189,6 +197,8 @@ gp_status gp_setup_grid(gp_ctx **out, int N, double Re, const gp_params *prm, vo
     G.lstride = N / n;
     G.gcap = 48 * n + 4096;
     G.ecap = 96 * n + 4096;
+    G.fcap = 4 * G.gcap + 8 * n + 4096;
+    G.bcap = 24 * n + 4096;
     L++;
   }
   ctx->L = L;
@@ -218,10 +228,14 @@ gp_status gp_setup_grid(gp_ctx **out, int N, double Re, const gp_params *prm, vo
     ALLOC(G.d_band_off, 8);
     ALLOC(G.reg_map, (size_t)3 * G.WW + 1);
     ALLOC(G.reg_pt, (size_t)G.gcap * 12 + (size_t)32 * G.N + 4096);
-    ALLOC(G.bbox, (size_t)22 * (G.N * 24 + 4096));
-    ALLOC(G.bg_rows, (size_t)G.gcap);
+    ALLOC(G.bbox, (size_t)23 * G.bcap);
+    ALLOC(G.bg_k, (size_t)G.gcap);
     ALLOC(G.bg_loc, (size_t)10 * G.gcap);
+    ALLOC(G.bg_w, (size_t)9 * G.gcap);
+    ALLOC(G.bg_dt, (size_t)G.gcap);
     ALLOC(G.wg_rows, (size_t)G.gcap);
+    ALLOC(G.f_code, (size_t)G.fcap);
+    ALLOC(G.f_loc, (size_t)G.fcap);
     ALLOC(ctx->v64[l].x, (size_t)G.n);
     ALLOC(ctx->v64[l].b, (size_t)G.n);
     ALLOC(ctx->v64[l].r, (size_t)G.n);
@@ -235,11 +249,16 @@ gp_status gp_setup_grid(gp_ctx **out, int N, double Re, const gp_params *prm, vo
   ALLOC(ctx->d_red, 8192);
   ALLOC(ctx->d_ticket, 4);
   ALLOC(ctx->d_scal, 16);
+  ALLOC(ctx->d_lev, 2 * MAXLEV);
+  ALLOC(ctx->d_bcnt, (size_t)5 * nblk((long)(N + 2) * (N + 2)) + 8);
+  ALLOC(ctx->d_iscr, (size_t)3 * (N + 2) * (N + 2) + 1);
   ALLOC(ctx->d_flags, 16);
   GP_HIP(hipMemsetAsync(ctx->d_ticket, 0, 4 * sizeof(unsigned), ctx->stream));
+  GP_HIP(hipMemsetAsync(ctx->d_lev, 0, 2 * MAXLEV * sizeof(double), ctx->stream));
   Geo &C = ctx->geo[L - 1];
   ALLOC(ctx->c_map, (size_t)3 * C.WW + 2);
   ALLOC(ctx->c_A, (size_t)1024 * 1024);
+  ALLOC(ctx->c_bmap, 1024);
   ALLOC(ctx->c_work, (size_t)4 * (3 * C.WW + 1) + 2048);
   int WW = ctx->geo[0].WW;
   for (int k = 0; k < 3; k++) {

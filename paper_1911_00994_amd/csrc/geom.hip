@@ -491,26 +491,62 @@ __device__ bool cut_cell(const uint8_t *cls, int W, int i, int j) {
     if (k[q] != K_INT && k[q] != K_WALLD) return true;
   return false;
 }
-__global__ void k_band(const uint8_t *cls, int N, int W, int R, int pass, int *off, int *band) {
-  int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= N * N) return;
+__device__ int block_excl_scan(int v, int *total) {
+  __shared__ int s[TPB];
+  s[threadIdx.x] = v;
+  __syncthreads();
+  for (int o = 1; o < TPB; o <<= 1) {
+    int a = threadIdx.x >= o ? s[threadIdx.x - o] : 0;
+    __syncthreads();
+    s[threadIdx.x] += a;
+    __syncthreads();
+  }
+  int incl = s[threadIdx.x];
+  *total = s[TPB - 1];
+  __syncthreads();
+  return incl - v;
+}
+__device__ __forceinline__ int band_colour(const uint8_t *cls, int N, int W, int R, int t) {
   int i = t % N, j = t / N, WW = W * W, c = (j + 1) * W + (i + 1);
   bool any = cls[c] == K_INT || cls[c + 1] == K_INT || cls[WW + c] == K_INT || cls[WW + c + W] == K_INT ||
              cls[2 * WW + c] == K_INT;
-  if (!any) return;
-  bool near = false;
-  for (int dj = -R; dj <= R && !near; dj++)
-    for (int di = -R; di <= R && !near; di++) {
+  if (!any) return -1;
+  for (int dj = -R; dj <= R; dj++)
+    for (int di = -R; di <= R; di++) {
       int a = i + di, b = j + dj;
       if (a < 0 || b < 0 || a >= N || b >= N) continue;
-      if (cut_cell(cls, W, a, b)) near = true;
+      if (cut_cell(cls, W, a, b)) return (i + 2 * j) % 5;
     }
-  if (!near) return;
-  int col = (i + 2 * j) % 5;
-  if (pass == 0)
-    atomicAdd(&off[col + 1], 1);  // counts, turned into offsets on the host side of the pass
-  else
-    band[atomicAdd(&off[col], 1)] = t;
+  return -1;
+}
+
+// deterministic compaction: per-block counts (block_excl_scan), one scan of the block counts (k_scan_blocks),
+// fill in index order
+__global__ void __launch_bounds__(TPB) k_band_count(const uint8_t *cls, int N, int W, int R, int nb, int *bcnt) {
+  int t = blockIdx.x * TPB + threadIdx.x;
+  int col = t < N * N ? band_colour(cls, N, W, R, t) : -1;
+  for (int c = 0; c < 5; c++) {
+    int tot;
+    block_excl_scan(col == c ? 1 : 0, &tot);
+    if (threadIdx.x == 0) bcnt[c * nb + blockIdx.x] = tot;
+  }
+}
+// band cells grouped by colour, ascending cell index within a colour
+__global__ void __launch_bounds__(TPB) k_band_fill(const uint8_t *cls, int N, int W, int R, int nb, const int *boff,
+                                                   int *band) {
+  int t = blockIdx.x * TPB + threadIdx.x;
+  int col = t < N * N ? band_colour(cls, N, W, R, t) : -1;
+  for (int c = 0; c < 5; c++) {
+    int tot;
+    int q = boff[c * nb + blockIdx.x] + block_excl_scan(col == c ? 1 : 0, &tot);
+    if (col == c) band[q] = t;
+  }
+}
+// colour offsets of the band (from the scanned counts) into out[0..5]
+__global__ void k_band_offsets(const int *boff, int nb, int *out) {
+  int c = threadIdx.x;
+  if (c < 5) out[c] = boff[c * nb];
+  if (c == 5) out[5] = boff[5 * nb];
 }
 
 // ---- boundary region tables for the LDS band kernel ----
@@ -542,14 +578,18 @@ __device__ __forceinline__ void box_points(int W, int c, int out[21]) {
   out[q++] = 2 * WW + c + W;  // pN
 }
 
+__global__ void k_row_of(const int *g_pt, int ng, int *row_of) {
+  int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r < ng) row_of[g_pt[r]] = r;
+}
 __global__ void k_region_clear(int *map, int n) {
   int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t < n) map[t] = -1;
 }
 // mark: map[k] = -2 for every point the band kernel writes (the five unknowns of a band box, body ghost points);
 // every other point it reads is constant during the kernel and is read from global memory
-__global__ void k_region_mark(const uint8_t *cls, int N, int W, const int *band, int nband, const int *g_pt,
-                              const int *g_col, int ng, int *map) {
+__global__ void k_region_mark(const uint8_t *cls, int N, int W, const int *band, int nband, const int *g_pt, int ng,
+                              int *map) {
   int t = blockIdx.x * blockDim.x + threadIdx.x;
   int WW = W * W;
   if (t < nband) {
@@ -564,21 +604,34 @@ __global__ void k_region_mark(const uint8_t *cls, int N, int W, const int *band,
     if (cls[g_pt[r]] == K_WALLG) return;
     map[g_pt[r]] = -2;
   }
-  (void)g_col;
 }
-__global__ void k_region_compact(int *map, int n, int *reg_pt, int cap, int *count) {
-  int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= n || map[t] != -2) return;
-  int slot = atomicAdd(count, 1);
-  if (slot < cap) {
-    reg_pt[slot] = t;
-    map[t] = slot;
-  } else
-    map[t] = -1;
+// region points and body ghost points in ascending index order
+__device__ __forceinline__ bool region_pred(int mode, const int *map, const uint8_t *cls, int t) {
+  return mode == 0 ? map[t] == -2 : (cls[t] == K_GHOST || cls[t] == K_GHOSTX);
 }
-// per band box: local indices of its 21 values, then the flags of its free unknowns (bits W E S N P)
-__global__ void k_region_boxes(const uint8_t *cls, int N, int W, const int *band, int nband, const int *map, int *bbox,
-                               int *bad) {
+__global__ void __launch_bounds__(TPB) k_pred_count(int mode, int n, const int *map, const uint8_t *cls, int *bcnt) {
+  int t = blockIdx.x * TPB + threadIdx.x;
+  int tot;
+  block_excl_scan(t < n && region_pred(mode, map, cls, t) ? 1 : 0, &tot);
+  if (threadIdx.x == 0) bcnt[blockIdx.x] = tot;
+}
+__global__ void __launch_bounds__(TPB) k_pred_fill(int mode, int n, const int *map, const uint8_t *cls, const int *boff,
+                                                   int cap, int *out) {
+  int t = blockIdx.x * TPB + threadIdx.x;
+  bool take = t < n && region_pred(mode, map, cls, t);
+  int tot;
+  int q = boff[blockIdx.x] + block_excl_scan(take ? 1 : 0, &tot);
+  if (take && q < cap) out[q] = t;
+}
+__global__ void k_region_slots(const int *reg_pt, int nreg, int *map) {
+  int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q < nreg) map[reg_pt[q]] = q;
+}
+// per band box, fields stored field-major (field f of box q at f * cap + q): the local indices of its 21 values
+// (LDS slot, or -(global index + 1) for a point the kernel only reads), the flags of its free unknowns (bits
+// W E S N P) and its cell index
+__global__ void k_region_boxes(const uint8_t *cls, int N, int W, const int *band, int nband, const int *map, int cap,
+                               int *bbox, int *bad) {
   int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= nband) return;
   int cell = band[t], i = cell % N, j = cell / N, WW = W * W, c = (j + 1) * W + (i + 1);
@@ -586,39 +639,110 @@ __global__ void k_region_boxes(const uint8_t *cls, int N, int W, const int *band
   box_points(W, c, pts);
   for (int q = 0; q < 21; q++) {
     int l = map[pts[q]];
-    // local LDS slot, or -(global index + 1) for a point the kernel only reads
-    bbox[22 * t + q] = l >= 0 ? l : -(pts[q] + 1);
-    if (cls[pts[q]] == K_WALLG) atomicOr(bad, 8);  // wall ghosts are swept before the band kernel
+    bbox[q * cap + t] = l >= 0 ? l : -(pts[q] + 1);
+    if (cls[pts[q]] == K_WALLG) atomicOr(bad, 8);  // wall ghosts are swept apart from the band
   }
   int f = (cls[c] == K_INT ? 1 : 0) | (cls[c + 1] == K_INT ? 2 : 0) | (cls[WW + c] == K_INT ? 4 : 0) |
           (cls[WW + c + W] == K_INT ? 8 : 0) | (cls[2 * WW + c] == K_INT ? 16 : 0);
-  bbox[22 * t + 21] = f;
+  bbox[21 * cap + t] = f;
+  bbox[22 * cap + t] = cell;
 }
-// ghost rows split into body rows (with local indices) and wall rows; a wall row whose nodes a band box writes
-// or whose stencil holds another ghost is reported (the LDS kernel then does not apply)
-__global__ void k_region_rows(const uint8_t *cls, const int *g_pt, const int *g_col, int ng, const int *map, int *bg_rows,
-                              int *bg_loc, int *wg_rows, int *counts, int *bad) {
+// body ghost rows in point order, fields stored field-major: bg_loc (own slot, then the 9 stencil entries as
+// local indices), bg_w (9 weights), bg_dt, and bg_k (the point, for its right-hand side); a body row that would
+// read a wall ghost is reported (the LDS kernel then does not apply)
+__global__ void k_region_rows(const uint8_t *cls, const int *g_col, const double *g_w, const double *g_dtau,
+                              const int *row_of, const int *map, int nbg, int cap, const int *bg_k, int *bg_loc,
+                              double *bg_w, double *bg_dt, int *bad) {
+  int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= nbg) return;
+  int k = bg_k[s], r = row_of[k];
+  bg_loc[s] = map[k];
+  for (int q = 0; q < 9; q++) {
+    int c = g_col[9 * r + q], l = map[c];
+    if (cls[c] == K_WALLG) atomicOr(bad, 4);
+    bg_loc[(1 + q) * cap + s] = l >= 0 ? l : -(c + 1);
+    bg_w[q * cap + s] = g_w[9 * r + q];
+  }
+  bg_dt[s] = g_dtau[r];
+}
+// wall ghost rows (order free: each is relaxed on its own); a wall row whose nodes a band box writes or whose
+// stencil holds another ghost is reported
+__global__ void k_wall_rows(const uint8_t *cls, const int *g_pt, const int *g_col, int ng, const int *map, int *wg_rows,
+                            int *count, int *bad) {
   int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= ng) return;
   int k = g_pt[r];
-  if (cls[k] == K_WALLG) {
-    for (int q = 1; q < 9; q++) {
-      int c = g_col[9 * r + q];
-      if (c != k && (map[c] >= 0 || cls[c] == K_GHOST || cls[c] == K_GHOSTX || cls[c] == K_WALLG)) atomicOr(bad, 2);
-    if (map[k] >= 0) atomicOr(bad, 2);
-    }
-    wg_rows[atomicAdd(&counts[1], 1)] = r;
-    return;
-  }
-  for (int q = 0; q < 9; q++)
-    if (cls[g_col[9 * r + q]] == K_WALLG) atomicOr(bad, 4);  // a body row would see a wall ghost: keep the order
-  int s = atomicAdd(&counts[0], 1);
-  bg_rows[s] = r;
-  bg_loc[10 * s] = map[k];
+  if (cls[k] != K_WALLG) return;
   for (int q = 0; q < 9; q++) {
-    int c = g_col[9 * r + q], l = map[c];
-    bg_loc[10 * s + 1 + q] = l >= 0 ? l : -(c + 1);
+    int c = g_col[9 * r + q];
+    if (c != k && (map[c] >= 0 || cls[c] == K_GHOST || cls[c] == K_GHOSTX || cls[c] == K_WALLG)) atomicOr(bad, 2);
   }
+  if (map[k] >= 0) atomicOr(bad, 2);
+  wg_rows[atomicAdd(count, 1)] = r;
+}
+
+// ---- faces on the boundary of the internal pressure cells ----
+// The divergences of the internal cells sum to (sum over these faces of +-u) / h: every face shared by two
+// internal cells enters twice with opposite signs.  The list is built in a fixed order (cell index, then E W N S)
+// by a per-block count, a scan of the block counts and a fill.
+// Wall Dirichlet faces are left out: their values are fixed during a solve, and their part of the sum is added
+// to the sum of the continuity right-hand sides instead.
+__device__ __forceinline__ int face_mask(const uint8_t *cls, int W, int i, int j) {
+  const int WW = W * W, c = (j + 1) * W + (i + 1), cp = 2 * WW + c;
+  if (cls[cp] != K_INT) return 0;
+  return (cls[cp + 1] != K_INT && cls[c + 1] != K_WALLD ? 1 : 0) | (cls[cp - 1] != K_INT && cls[c] != K_WALLD ? 2 : 0) |
+         (cls[cp + W] != K_INT && cls[WW + c + W] != K_WALLD ? 4 : 0) |
+         (cls[cp - W] != K_INT && cls[WW + c] != K_WALLD ? 8 : 0);
+}
+__global__ void __launch_bounds__(TPB) k_face_count(const uint8_t *cls, int N, int W, int *bcnt) {
+  int t = blockIdx.x * TPB + threadIdx.x;
+  int m = t < N * N ? face_mask(cls, W, t % N, t / N) : 0;
+  int tot;
+  block_excl_scan(__popc(m), &tot);
+  if (threadIdx.x == 0) bcnt[blockIdx.x] = tot;
+}
+// exclusive scan of nb block counts in place (one workgroup); the total goes to bcnt[nb]
+constexpr int SCAN_T = 1024;
+__global__ void __launch_bounds__(SCAN_T) k_scan_blocks(int *bcnt, int nb) {
+  __shared__ int s[SCAN_T];
+  int per = (nb + SCAN_T - 1) / SCAN_T, lo = threadIdx.x * per, hi = min(nb, lo + per);
+  int sum = 0;
+  for (int q = lo; q < hi; q++) sum += bcnt[q];
+  s[threadIdx.x] = sum;
+  __syncthreads();
+  for (int o = 1; o < SCAN_T; o <<= 1) {
+    int a = threadIdx.x >= o ? s[threadIdx.x - o] : 0;
+    __syncthreads();
+    s[threadIdx.x] += a;
+    __syncthreads();
+  }
+  int run = s[threadIdx.x] - sum;
+  for (int q = lo; q < hi; q++) {
+    int c = bcnt[q];
+    bcnt[q] = run;
+    run += c;
+  }
+  if (threadIdx.x == SCAN_T - 1) bcnt[nb] = s[SCAN_T - 1];
+}
+__global__ void __launch_bounds__(TPB) k_face_fill(const uint8_t *cls, int N, int W, const int *boff, int cap, int *f_code) {
+  int t = blockIdx.x * TPB + threadIdx.x;
+  int i = t % N, j = t / N;
+  int m = t < N * N ? face_mask(cls, W, i, j) : 0;
+  int tot;
+  int q = boff[blockIdx.x] + block_excl_scan(__popc(m), &tot);
+  if (!m) return;
+  const int WW = W * W, c = (j + 1) * W + (i + 1);
+  // E (u, +), W (u, -), N (v, +), S (v, -)
+  if ((m & 1) && q < cap) f_code[q++] = 2 * (c + 1);
+  if ((m & 2) && q < cap) f_code[q++] = 2 * c + 1;
+  if ((m & 4) && q < cap) f_code[q++] = 2 * (WW + c + W);
+  if ((m & 8) && q < cap) f_code[q++] = 2 * (WW + c) + 1;
+}
+__global__ void k_face_loc(const int *f_code, int nf, const int *map, int *f_loc) {
+  int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= nf) return;
+  int g = f_code[q] >> 1, l = map[g];
+  f_loc[q] = l >= 0 ? l : -(g + 1);
 }
 
 // ---------------------------------------------------------------------------------------------------------
@@ -743,44 +867,75 @@ static gp_status build_level(Ctx *ctx, int l) {
   }
   GP_HIP(hipMemsetAsync(G.d_mp, 0, sizeof(int), s));
   k_count_mp<<<nblk(W * W), TPB, 0, s>>>(G.cls, W, G.d_mp);
-  // boundary band lists (two passes: counts, then fill from the offsets)
+  // boundary band: cells grouped by colour, ascending cell index within a colour
   {
+    int nb = nblk((long)G.N * G.N);
     int hoff[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    GP_HIP(hipMemsetAsync(G.d_band_off, 0, 8 * sizeof(int), s));
-    if (ctx->prm.bnd_sweeps > 0)
-      k_band<<<nblk(G.N * G.N), TPB, 0, s>>>(G.cls, G.N, W, ctx->prm.bnd_radius, 0, G.d_band_off, G.band);
-    GP_HIP(hipMemcpyAsync(hoff, G.d_band_off, 8 * sizeof(int), hipMemcpyDeviceToHost, s));
-    GP_HIP(hipStreamSynchronize(s));
-    for (int c = 1; c <= 5; c++) hoff[c] += hoff[c - 1];
+    if (ctx->prm.bnd_sweeps > 0) {
+      k_band_count<<<nb, TPB, 0, s>>>(G.cls, G.N, W, ctx->prm.bnd_radius, nb, ctx->d_bcnt);
+      k_scan_blocks<<<1, SCAN_T, 0, s>>>(ctx->d_bcnt, 5 * nb);
+      k_band_offsets<<<1, 64, 0, s>>>(ctx->d_bcnt, nb, G.d_band_off);
+      k_band_fill<<<nb, TPB, 0, s>>>(G.cls, G.N, W, ctx->prm.bnd_radius, nb, ctx->d_bcnt, G.band);
+      GP_HIP(hipGetLastError());
+      GP_HIP(hipMemcpyAsync(hoff, G.d_band_off, 6 * sizeof(int), hipMemcpyDeviceToHost, s));
+      GP_HIP(hipStreamSynchronize(s));
+    }
     G.nband = hoff[5];
-    GP_HIP(hipMemcpyAsync(G.d_band_off, hoff, 8 * sizeof(int), hipMemcpyHostToDevice, s));
-    if (G.nband)
-      k_band<<<nblk(G.N * G.N), TPB, 0, s>>>(G.cls, G.N, W, ctx->prm.bnd_radius, 1, G.d_band_off, G.band);
-    // the fill pass advanced each start offset to the next one: restore the offsets
-    GP_HIP(hipMemcpyAsync(G.d_band_off, hoff, 8 * sizeof(int), hipMemcpyHostToDevice, s));
-    GP_HIP(hipStreamSynchronize(s));
     for (int c = 0; c < 8; c++) G.hband_off[c] = hoff[c];
   }
   // boundary region of the LDS band kernel
   G.lds_ok = 0;
-  if (G.nband > 0 && G.nband <= G.N * 24 + 4096) {
-    int regcap = G.gcap * 12 + 32 * G.N + 4096;
-    k_region_clear<<<nblk(3 * W * W + 1), TPB, 0, s>>>(G.reg_map, 3 * W * W + 1);
-    k_region_mark<<<nblk(G.nband + G.ng), TPB, 0, s>>>(G.cls, G.N, W, G.band, G.nband, G.g_pt, G.g_col, G.ng, G.reg_map);
-    GP_HIP(hipMemsetAsync(ctx->d_flags + 8, 0, 4 * sizeof(int), s));
-    k_region_compact<<<nblk(3 * W * W), TPB, 0, s>>>(G.reg_map, 3 * W * W, G.reg_pt, regcap, ctx->d_flags + 8);
-    k_region_boxes<<<nblk(G.nband), TPB, 0, s>>>(G.cls, G.N, W, G.band, G.nband, G.reg_map, G.bbox, ctx->d_flags + 11);
-    if (G.ng)
-      k_region_rows<<<nblk(G.ng), TPB, 0, s>>>(G.cls, G.g_pt, G.g_col, G.ng, G.reg_map, G.bg_rows, G.bg_loc, G.wg_rows,
-                                               ctx->d_flags + 9, ctx->d_flags + 11);
+  G.nreg = G.nbg = G.nwg = 0;
+  if (G.nband > 0 && G.nband <= G.bcap) {
+    const int P3 = 3 * W * W, nbr = nblk(P3);
+    const int regcap = G.gcap * 12 + 32 * G.N + 4096;
+    k_region_clear<<<nblk(P3 + 1), TPB, 0, s>>>(G.reg_map, P3 + 1);
+    k_region_mark<<<nblk(G.nband + G.ng), TPB, 0, s>>>(G.cls, G.N, W, G.band, G.nband, G.g_pt, G.ng, G.reg_map);
+    k_pred_count<<<nbr, TPB, 0, s>>>(0, P3, G.reg_map, G.cls, ctx->d_bcnt);
+    k_scan_blocks<<<1, SCAN_T, 0, s>>>(ctx->d_bcnt, nbr);
+    k_pred_fill<<<nbr, TPB, 0, s>>>(0, P3, G.reg_map, G.cls, ctx->d_bcnt, regcap, G.reg_pt);
     GP_HIP(hipGetLastError());
-    int hr[4];
-    GP_HIP(hipMemcpyAsync(hr, ctx->d_flags + 8, 4 * sizeof(int), hipMemcpyDeviceToHost, s));
+    GP_HIP(hipMemcpyAsync(&G.nreg, ctx->d_bcnt + nbr, sizeof(int), hipMemcpyDeviceToHost, s));
     GP_HIP(hipStreamSynchronize(s));
-    G.nreg = hr[0];
-    G.nbg = hr[1];
-    G.nwg = hr[2];
-    G.lds_ok = (hr[3] == 0 && G.nreg <= regcap) ? 1 : 0;
+    if (G.nreg <= regcap) {
+      GP_HIP(hipMemsetAsync(ctx->d_flags + 10, 0, 2 * sizeof(int), s));
+      k_region_slots<<<nblk(G.nreg), TPB, 0, s>>>(G.reg_pt, G.nreg, G.reg_map);
+      k_region_boxes<<<nblk(G.nband), TPB, 0, s>>>(G.cls, G.N, W, G.band, G.nband, G.reg_map, G.bcap, G.bbox,
+                                                   ctx->d_flags + 11);
+      // body ghost rows in point order
+      k_pred_count<<<nbr, TPB, 0, s>>>(1, P3, G.reg_map, G.cls, ctx->d_bcnt);
+      k_scan_blocks<<<1, SCAN_T, 0, s>>>(ctx->d_bcnt, nbr);
+      k_pred_fill<<<nbr, TPB, 0, s>>>(1, P3, G.reg_map, G.cls, ctx->d_bcnt, G.gcap, G.bg_k);
+      if (G.ng) k_row_of<<<nblk(G.ng), TPB, 0, s>>>(G.g_pt, G.ng, ctx->d_iscr);
+      GP_HIP(hipGetLastError());
+      GP_HIP(hipMemcpyAsync(&G.nbg, ctx->d_bcnt + nbr, sizeof(int), hipMemcpyDeviceToHost, s));
+      GP_HIP(hipStreamSynchronize(s));
+      if (G.nbg > G.gcap) return GP_ENOMEM;
+      if (G.nbg)
+        k_region_rows<<<nblk(G.nbg), TPB, 0, s>>>(G.cls, G.g_col, G.g_w, G.g_dtau, ctx->d_iscr, G.reg_map, G.nbg, G.gcap,
+                                                  G.bg_k, G.bg_loc, G.bg_w, G.bg_dt, ctx->d_flags + 11);
+      if (G.ng)
+        k_wall_rows<<<nblk(G.ng), TPB, 0, s>>>(G.cls, G.g_pt, G.g_col, G.ng, G.reg_map, G.wg_rows, ctx->d_flags + 10,
+                                               ctx->d_flags + 11);
+      GP_HIP(hipGetLastError());
+      int hr[2];
+      GP_HIP(hipMemcpyAsync(hr, ctx->d_flags + 10, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+      GP_HIP(hipStreamSynchronize(s));
+      G.nwg = hr[0];
+      G.lds_ok = hr[1] == 0 ? 1 : 0;
+    }
+  }
+  // boundary faces of the internal pressure cells (and their band-region entries)
+  {
+    int nb = nblk((long)G.N * G.N);
+    k_face_count<<<nb, TPB, 0, s>>>(G.cls, G.N, W, ctx->d_bcnt);
+    k_scan_blocks<<<1, SCAN_T, 0, s>>>(ctx->d_bcnt, nb);
+    k_face_fill<<<nb, TPB, 0, s>>>(G.cls, G.N, W, ctx->d_bcnt, G.fcap, G.f_code);
+    GP_HIP(hipGetLastError());
+    GP_HIP(hipMemcpyAsync(&G.nf, ctx->d_bcnt + nb, sizeof(int), hipMemcpyDeviceToHost, s));
+    GP_HIP(hipStreamSynchronize(s));
+    if (G.nf > G.fcap) return GP_ENOMEM;
+    if (G.lds_ok && G.nf) k_face_loc<<<nblk(G.nf), TPB, 0, s>>>(G.f_code, G.nf, G.reg_map, G.f_loc);
   }
   if (l == 0) k_empty_cells<<<nblk(G.N * G.N), TPB, 0, s>>>(G.cls, G.N, W, ctx->d_flags);
   GP_HIP(hipGetLastError());
@@ -890,89 +1045,101 @@ __global__ void k_coarse_fill(const uint8_t *cls, int N, int W, double h, double
   (void)N;
 }
 
-__global__ void k_row_of(const int *g_pt, int ng, int *row_of) {
-  int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r < ng) row_of[g_pt[r]] = r;
-}
 
 // in-place Gauss-Jordan inversion with partial pivoting, one workgroup; A (n x n) becomes A^{-1}
 constexpr int GJ_T = 1024;
-__global__ void __launch_bounds__(GJ_T) k_gauss_jordan(double *A, int n, int *piv, int *fail) {
-  __shared__ double sval[GJ_T];
-  __shared__ int sidx[GJ_T];
-  __shared__ double prow_s[1024];
-  __shared__ double pcol_s[1024];
-  int tid = threadIdx.x;
+// Gauss-Jordan inversion with partial pivoting (ties: smallest row), in place, one workgroup.  Per pivot step the
+// two interchanged rows are staged in LDS and every other element is updated once (wavefront per row, lanes
+// along the row); the next pivot column is written to LDS by the update itself.  The row interchanges are not undone on the matrix: the column order of the result is folded into
+// bmap, so that x[map[q]] = sum_j A[q][j] b[bmap[j]] applies the inverse.
+__global__ void __launch_bounds__(GJ_T) k_gauss_jordan(double *A, int n, const int *__restrict__ map, int *bmap, int *fail) {
+  __shared__ double rowk[1024], rowp[1024], colbuf[2][1024];
+  __shared__ double wbest[GJ_T / 64];
+  __shared__ int wbi[GJ_T / 64], spv[1024], lab[1024];
+  __shared__ int sp;
+  __shared__ double sabs;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  for (int i = tid; i < n; i += GJ_T) colbuf[0][i] = A[(size_t)i * n];
+  __syncthreads();
   for (int k = 0; k < n; k++) {
-    // pivot search in column k, rows k..n-1 (ties: smallest row)
+    const double *colk = colbuf[k & 1];
+    double *coln = colbuf[(k + 1) & 1];
     double best = -1;
-    int bi = k;
+    int bi = n;
     for (int i = k + tid; i < n; i += GJ_T) {
-      double v = fabs(A[(size_t)i * n + k]);
-      if (v > best) {
-        best = v;
+      double av = fabs(colk[i]);
+      if (av > best) {
+        best = av;
         bi = i;
       }
     }
-    sval[tid] = best;
-    sidx[tid] = bi;
-    __syncthreads();
-    for (int s = GJ_T / 2; s > 0; s >>= 1) {
-      if (tid < s) {
-        double o = sval[tid + s];
-        int oi = sidx[tid + s];
-        if (o > sval[tid] || (o == sval[tid] && oi < sidx[tid])) {
-          sval[tid] = o;
-          sidx[tid] = oi;
-        }
+    for (int o = 32; o > 0; o >>= 1) {
+      double ob = __shfl_xor(best, o, 64);
+      int oi = __shfl_xor(bi, o, 64);
+      if (ob > best || (ob == best && oi < bi)) {
+        best = ob;
+        bi = oi;
       }
-      __syncthreads();
     }
-    int p = sidx[0];
-    if (sval[0] == 0.0) {
+    if (lane == 0) {
+      wbest[wv] = best;
+      wbi[wv] = bi;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      double bb = -1;
+      int p = n;
+      for (int w = 0; w < GJ_T / 64; w++)
+        if (wbest[w] > bb || (wbest[w] == bb && wbi[w] < p)) {
+          bb = wbest[w];
+          p = wbi[w];
+        }
+      sp = p;
+      sabs = bb;
+      spv[k] = p;
+    }
+    __syncthreads();
+    const int p = sp;
+    if (!(sabs > 0) || p >= n) {
       if (tid == 0) *fail = 1;
       return;
     }
-    if (tid == 0) piv[k] = p;
-    // swap rows k and p
-    if (p != k)
-      for (int c = tid; c < n; c += GJ_T) {
-        double t = A[(size_t)k * n + c];
-        A[(size_t)k * n + c] = A[(size_t)p * n + c];
-        A[(size_t)p * n + c] = t;
-      }
-    __syncthreads();
-    double inv_p = 1.0 / A[(size_t)k * n + k];
-    // pivot row (scaled) and pivot column into shared memory
     for (int c = tid; c < n; c += GJ_T) {
-      prow_s[c] = (c == k) ? inv_p : A[(size_t)k * n + c] * inv_p;
-      pcol_s[c] = A[(size_t)c * n + k];
+      rowk[c] = A[(size_t)k * n + c];
+      rowp[c] = A[(size_t)p * n + c];
     }
     __syncthreads();
-    for (int c = tid; c < n; c += GJ_T) A[(size_t)k * n + c] = prow_s[c];
-    // eliminate column k from every other row
-    for (long e = tid; e < (long)n * n; e += GJ_T) {
-      int i = (int)(e / n), c = (int)(e % n);
-      if (i == k) continue;
-      double f = pcol_s[i];
-      if (c == k)
-        A[e] = -f * inv_p;
-      else
-        A[e] -= f * prow_s[c];
-    }
-    __syncthreads();
-  }
-  // undo the row interchanges as column interchanges, in reverse order
-  for (int k = n - 1; k >= 0; k--) {
-    int p = piv[k];
-    if (p != k)
-      for (int i = tid; i < n; i += GJ_T) {
-        double t = A[(size_t)i * n + k];
-        A[(size_t)i * n + k] = A[(size_t)i * n + p];
-        A[(size_t)i * n + p] = t;
+    const double inv_p = 1.0 / rowp[k];
+    // after the interchange row k holds old row p and row p holds old row k
+    for (int i = wv; i < n; i += GJ_T / 64) {
+      const int src = (i == k) ? p : (i == p ? k : i);
+      const double f = colk[src];
+      for (int c = lane; c < n; c += 64) {
+        const double nk = (c == k) ? inv_p : rowp[c] * inv_p;
+        double out;
+        if (i == k) {
+          out = nk;
+        } else {
+          const double a = (src == k) ? rowk[c] : A[(size_t)i * n + c];
+          out = (c == k) ? -f * inv_p : a - f * nk;
+        }
+        A[(size_t)i * n + c] = out;
+        if (c == k + 1) coln[i] = out;
       }
+    }
     __syncthreads();
   }
+  // undoing the interchanges as column interchanges in reverse order puts result column c at column lab[c]
+  if (tid == 0) {
+    for (int c = 0; c < n; c++) lab[c] = c;
+    for (int k = n - 1; k >= 0; k--) {
+      int t = lab[k];
+      lab[k] = lab[spv[k]];
+      lab[spv[k]] = t;
+    }
+  }
+  __syncthreads();
+  for (int c = tid; c < n; c += GJ_T) bmap[lab[c]] = map[c];
 }
 
 gp_status coarse_factor(Ctx *ctx) {
@@ -993,7 +1160,7 @@ gp_status coarse_factor(Ctx *ctx) {
   k_coarse_fill<<<nblk(ctx->nc), TPB, 0, s>>>(G.cls, G.N, W, G.h, a, d, ctx->c_map, inv, ctx->nc, row_of, G.g_col, G.g_w,
                                              G.mp, ctx->c_A);
   GP_HIP(hipMemsetAsync(ctx->d_flags + 6, 0, sizeof(int), s));
-  k_gauss_jordan<<<1, GJ_T, 0, s>>>(ctx->c_A, ctx->nc, (int *)(ctx->c_work) + 2 * (P + 1), ctx->d_flags + 6);
+  k_gauss_jordan<<<1, GJ_T, 0, s>>>(ctx->c_A, ctx->nc, ctx->c_map, ctx->c_bmap, ctx->d_flags + 6);
   GP_HIP(hipGetLastError());
   st = read_flags(ctx, hf);
   if (st) return st;

@@ -50,12 +50,19 @@ struct Geo {
   int *d_band_off = nullptr;        // device: 6 offsets
   int nband = 0;                    // host copy of the total
   int hband_off[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  // boundary region staged in LDS by the band kernel: region points (global index), global -> local map,
-  // per band box the local indices of its 21 values and its 5 free-unknown flags, body ghost rows (row id and
-  // 10 local indices), wall ghost rows (row ids)
-  int *reg_pt = nullptr, *reg_map = nullptr, *bbox = nullptr, *bg_rows = nullptr, *bg_loc = nullptr, *wg_rows = nullptr;
+  // boundary region staged in LDS by the band kernel: region points (global index, ascending), global -> local
+  // map, per band box (field-major, stride bcap) the local indices of its 21 values, its free-unknown flags and
+  // its cell, body ghost rows in point order (field-major, stride gcap: point, 10 local indices, 9 weights,
+  // fictitious time step), wall ghost rows (row ids)
+  int *reg_pt = nullptr, *reg_map = nullptr, *bbox = nullptr, *bg_k = nullptr, *bg_loc = nullptr, *wg_rows = nullptr;
+  double *bg_w = nullptr, *bg_dt = nullptr;
+  int bcap = 0;
   int nreg = 0, nbg = 0, nwg = 0;
   int lds_ok = 0;                   // 1 when the LDS band kernel applies to this level
+  // faces on the boundary of the internal pressure cells, cell-major order: code = 2 * (u or v index) + (1 if the
+  // face enters the cell's divergence with a minus sign); f_loc = the same face as an LDS band-region entry
+  int *f_code = nullptr, *f_loc = nullptr;
+  int nf = 0, fcap = 0;
 };
 
 // one precision's vectors on one level
@@ -78,6 +85,9 @@ struct Ctx {
   // reductions / flags
   double *d_red = nullptr;          // partial sums (blocks) scratch
   unsigned int *d_ticket = nullptr; // last-block tickets
+  double *d_lev = nullptr;          // per level: [l] sum of the continuity right-hand sides over internal cells
+  int *d_bcnt = nullptr;            // per-block counts of the deterministic compactions
+  int *d_iscr = nullptr;            // point-indexed int scratch (finest size)
   double *d_scal = nullptr;         // device scalars: [0] mean p, [1] res max (as bits), [2..] misc
   int *d_flags = nullptr;           // device flags: [0] changed, [1] geometry error bits, [2] ghost count, [3] ext count, [4] bad rows
   int have_geom = 0;
@@ -87,6 +97,7 @@ struct Ctx {
   // coarsest exact solve: compacted active unknowns and explicit inverse (FP64)
   int nc = 0;                       // number of active unknowns on the coarsest level
   int *c_map = nullptr;             // nc: global index of each active unknown
+  int *c_bmap = nullptr;            // nc: right-hand side index for each column of the stored inverse
   double *c_A = nullptr;            // nc*nc matrix, then overwritten by its inverse
   double *c_work = nullptr;         // nc*nc scratch
   int c_ok = 0;

@@ -191,65 +191,114 @@ __global__ void __launch_bounds__(BAND_T) k_band_sweeps(int N, int W, double h, 
   }
 }
 
-// Same work as k_band_sweeps for the body ghost rows and the band boxes, with the values of the boundary
-// region staged in LDS (one global round trip per phase for the constant data only).  The wall ghost rows are
-// done before by k_wall_ghosts (they read only internal points next to the walls, which no band box writes,
-// so their 2 x lambda sweeps can run at once).  Body ghost rows per thread are limited to MAXR.
-constexpr int MAXR = 8;
+// wall ghost rows: all their Jacobi sweeps at once, each row independent of every other ghost
+template <typename T>
+__device__ __forceinline__ void wall_ghost_row(int r, const int *__restrict__ g_pt, const int *__restrict__ g_col,
+                                               const double *__restrict__ g_w, const double *__restrict__ g_dtau, T *x,
+                                               const T *__restrict__ b, int sweeps) {
+  int k = g_pt[r];
+  double rest = 0, w0 = 0;
+#pragma unroll
+  for (int z = 0; z < 9; z++) {
+    int c = g_col[9 * r + z];
+    if (c == k)
+      w0 += g_w[9 * r + z];
+    else
+      rest += g_w[9 * r + z] * (double)x[c];
+  }
+  double xv = (double)x[k], bb = (double)b[k], dt = g_dtau[r];
+  for (int it = 0; it < sweeps; it++) xv = xv + dt * (bb - (w0 * xv + rest));
+  x[k] = (T)xv;
+}
+// sum over a workgroup of BAND_T threads (every thread gets the total; fixed order)
+__device__ double band_block_sum(double v) {
+  __shared__ double s[BAND_T / 64];
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) s[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double t = 0;
+  for (int q = 0; q < BAND_T / 64; q++) t += s[q];
+  return t;
+}
+
+// One relaxation step's work after the five box sweeps, in one workgroup:
+//  - workgroup 0: the body ghost rows and the band boxes as in k_band_sweeps, with the values the kernel writes
+//    staged in LDS (every other value it reads is constant during the kernel and comes from global memory), then
+//    xi <- mean over internal cells of (div u - g) from the boundary faces of the internal cells;
+//  - the other workgroups: the wall ghost rows, all lambda (1 + sweeps) of their Jacobi sweeps at once (they read
+//    only internal points next to the walls, which no band box writes, and neither a body ghost row nor a listed
+//    face reads them).
+constexpr int BATCH = 8;
+struct BandOff {
+  int o[6];
+};
 template <typename T>
 __global__ void __launch_bounds__(BAND_T) k_band_lds(int N, int W, double h, double a, double d, T *x, const T *__restrict__ b,
-                                                     const int *__restrict__ band, const int *__restrict__ off,
-                                                     const int *__restrict__ bbox, const int *__restrict__ reg_pt, int nreg,
-                                                     const int *__restrict__ bg_rows, const int *__restrict__ bg_loc, int nbg,
-                                                     const int *__restrict__ g_pt, const double *__restrict__ g_w,
-                                                     const double *__restrict__ g_dtau, int sweeps, int lambda) {
+                                                     BandOff off, const int *__restrict__ bbox, int bcap,
+                                                     const int *__restrict__ reg_pt, int nreg, const int *__restrict__ bg_k,
+                                                     const int *__restrict__ bg_loc, const double *__restrict__ bg_w,
+                                                     const double *__restrict__ bg_dt, int nbg, int gcap, double *nvbuf,
+                                                     const int *__restrict__ g_pt, const int *__restrict__ g_col,
+                                                     const double *__restrict__ g_w, const double *__restrict__ g_dtau,
+                                                     const int *__restrict__ wg_rows, int nwg, int sweeps, int lambda,
+                                                     const int *__restrict__ f_code, const int *__restrict__ f_loc, int nf,
+                                                     const double *__restrict__ gsum, const int *__restrict__ mp) {
   extern __shared__ unsigned char lds_raw[];
   T *xs = reinterpret_cast<T *>(lds_raw);
   const int WW = W * W;
   // value of a table entry: local LDS slot (written by this kernel) or -(global index + 1) (read only)
   auto val = [&](int e) -> double { return e >= 0 ? (double)xs[e] : (double)x[-e - 1]; };
   const int tid = threadIdx.x;
-  for (int q = tid; q < nreg; q += BAND_T) xs[q] = x[reg_pt[q]];
+  if (blockIdx.x > 0) {
+    // the other workgroups of the launch take the wall ghost rows, on other compute units
+    for (int q = (blockIdx.x - 1) * BAND_T + tid; q < nwg; q += (gridDim.x - 1) * BAND_T)
+      wall_ghost_row<T>(wg_rows[q], g_pt, g_col, g_w, g_dtau, x, b, lambda * (1 + sweeps));
+    return;
+  }
+  // stage the region: batches of BATCH loads in flight per thread
+  for (int q0 = tid; q0 < nreg; q0 += BATCH * BAND_T) {
+    int gi[BATCH];
+    T vv[BATCH];
+#pragma unroll
+    for (int u = 0; u < BATCH; u++) gi[u] = q0 + u * BAND_T < nreg ? reg_pt[q0 + u * BAND_T] : 0;
+#pragma unroll
+    for (int u = 0; u < BATCH; u++) vv[u] = x[gi[u]];
+#pragma unroll
+    for (int u = 0; u < BATCH; u++)
+      if (q0 + u * BAND_T < nreg) xs[q0 + u * BAND_T] = vv[u];
+  }
   const double xi = (double)x[3 * WW];
   const double ih = 1.0 / h, det = d * d - a * a;
   __syncthreads();
+  // Jacobi sweeps of the body ghost rows; each new value goes through nvbuf (written and read back by the same
+  // thread), so no row data is held across the barrier
   auto ghost_block = [&]() {
     for (int it = 0; it < lambda; it++) {
-      double nv[MAXR];
+      for (int s2 = tid; s2 < nbg; s2 += BAND_T) {
+        double sum = 0;
 #pragma unroll
-      for (int m = 0; m < MAXR; m++) {
-        int s2 = tid + m * BAND_T;
-        if (s2 < nbg) {
-          int r = bg_rows[s2];
-          const int *lc = bg_loc + 10 * s2;
-          double sum = 0;
-#pragma unroll
-          for (int z = 0; z < 9; z++) sum += g_w[9 * r + z] * val(lc[1 + z]);
-          nv[m] = (double)xs[lc[0]] + g_dtau[r] * ((double)b[g_pt[r]] - sum);
-        }
+        for (int z = 0; z < 9; z++) sum += bg_w[z * gcap + s2] * val(bg_loc[(1 + z) * gcap + s2]);
+        nvbuf[s2] = (double)xs[bg_loc[s2]] + bg_dt[s2] * ((double)b[bg_k[s2]] - sum);
       }
       __syncthreads();
-#pragma unroll
-      for (int m = 0; m < MAXR; m++) {
-        int s2 = tid + m * BAND_T;
-        if (s2 < nbg) xs[bg_loc[10 * s2]] = (T)nv[m];
-      }
+      for (int s2 = tid; s2 < nbg; s2 += BAND_T) xs[bg_loc[s2]] = (T)nvbuf[s2];
       __syncthreads();
     }
   };
   ghost_block();
   for (int sw = 0; sw < sweeps; sw++) {
     for (int c = 0; c < 5; c++) {
-      for (int q = off[c] + tid; q < off[c + 1]; q += BAND_T) {
-        const int *tb = bbox + 22 * q;
-        int cell = band[q], i = cell % N, j = cell / N, cg = (j + 1) * W + (i + 1);
-        int f = tb[21];
+      for (int q = off.o[c] + tid; q < off.o[c + 1]; q += BAND_T) {
+        auto TB = [&](int fld) { return bbox[fld * bcap + q]; };
+        int cell = TB(22), i = cell % N, j = cell / N, cg = (j + 1) * W + (i + 1);
+        int f = TB(21);
         bool fW = f & 1, fE = f & 2, fS = f & 4, fN = f & 8, fP = f & 16;
-        double uW = val(tb[0]), uE = val(tb[1]), uWW = val(tb[2]), uEE = val(tb[3]), uWS = val(tb[4]), uWN = val(tb[5]),
-               uES = val(tb[6]), uEN = val(tb[7]);
-        double vS = val(tb[8]), vN = val(tb[9]), vSS = val(tb[10]), vNN = val(tb[11]), vSW = val(tb[12]),
-               vSE = val(tb[13]), vNW = val(tb[14]), vNE = val(tb[15]);
-        double pc = val(tb[16]), pW = val(tb[17]), pE = val(tb[18]), pS = val(tb[19]), pN = val(tb[20]);
+        double uW = val(TB(0)), uE = val(TB(1)), uWW = val(TB(2)), uEE = val(TB(3)), uWS = val(TB(4)), uWN = val(TB(5)),
+               uES = val(TB(6)), uEN = val(TB(7));
+        double vS = val(TB(8)), vN = val(TB(9)), vSS = val(TB(10)), vNN = val(TB(11)), vSW = val(TB(12)),
+               vSE = val(TB(13)), vNW = val(TB(14)), vNE = val(TB(15));
+        double pc = val(TB(16)), pW = val(TB(17)), pE = val(TB(18)), pS = val(TB(19)), pN = val(TB(20));
         double bW_ = b[cg], bE_ = b[cg + 1], bS_ = b[WW + cg], bN_ = b[WW + cg + W], bP_ = b[2 * WW + cg];
         double aW = uW, bW = 0, aE = uE, bE = 0, aS = vS, bS = 0, aN = vN, bN = 0;
         {
@@ -290,44 +339,61 @@ __global__ void __launch_bounds__(BAND_T) k_band_lds(int N, int W, double h, dou
             skip = true;
           else {
             pn = (h * (xi + bP_) - (aE - aW + aN - aS)) / den;
-            xs[tb[16]] = (T)pn;
+            xs[TB(16)] = (T)pn;
           }
         }
         if (!skip) {
-          if (fW) xs[tb[0]] = (T)(aW + bW * pn);
-          if (fE) xs[tb[1]] = (T)(aE + bE * pn);
-          if (fS) xs[tb[8]] = (T)(aS + bS * pn);
-          if (fN) xs[tb[9]] = (T)(aN + bN * pn);
+          if (fW) xs[TB(0)] = (T)(aW + bW * pn);
+          if (fE) xs[TB(1)] = (T)(aE + bE * pn);
+          if (fS) xs[TB(8)] = (T)(aS + bS * pn);
+          if (fN) xs[TB(9)] = (T)(aN + bN * pn);
         }
       }
       __syncthreads();
     }
     ghost_block();
   }
-  for (int q = tid; q < nreg; q += BAND_T) x[reg_pt[q]] = xs[q];
+  double fs = 0;
+  for (int q0 = tid; q0 < nf; q0 += BATCH * BAND_T) {
+    int e[BATCH], cd[BATCH];
+    double v[BATCH];
+#pragma unroll
+    for (int u = 0; u < BATCH; u++) {
+      bool in = q0 + u * BAND_T < nf;
+      e[u] = in ? f_loc[q0 + u * BAND_T] : 0;
+      cd[u] = in ? f_code[q0 + u * BAND_T] : -1;
+    }
+#pragma unroll
+    for (int u = 0; u < BATCH; u++) v[u] = val(e[u]);
+#pragma unroll
+    for (int u = 0; u < BATCH; u++)
+      if (cd[u] >= 0) fs += (cd[u] & 1) ? -v[u] : v[u];
+  }
+  fs = band_block_sum(fs);
+  for (int q0 = tid; q0 < nreg; q0 += BATCH * BAND_T) {
+    int gi[BATCH];
+#pragma unroll
+    for (int u = 0; u < BATCH; u++) gi[u] = q0 + u * BAND_T < nreg ? reg_pt[q0 + u * BAND_T] : -1;
+#pragma unroll
+    for (int u = 0; u < BATCH; u++)
+      if (gi[u] >= 0) x[gi[u]] = xs[q0 + u * BAND_T];
+  }
+  if (tid == 0) x[3 * WW] = (T)((fs / h - *gsum) / *mp);
 }
 
-// wall ghost rows: 2 x lambda (or lambda) Jacobi sweeps at once, each row independent of every other ghost
+// xi <- mean over internal cells of (div u - g), from the boundary faces of the internal cells (one workgroup)
 template <typename T>
-__global__ void k_wall_ghosts(const int *__restrict__ rows, int nwg, const int *__restrict__ g_pt, const int *__restrict__ g_col,
-                              const double *__restrict__ g_w, const double *__restrict__ g_dtau, T *x, const T *__restrict__ b,
-                              int sweeps) {
-  int q = blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= nwg) return;
-  int r = rows[q], k = g_pt[r];
-  double rest = 0, w0 = 0;
-#pragma unroll
-  for (int z = 0; z < 9; z++) {
-    int c = g_col[9 * r + z];
-    if (c == k)
-      w0 += g_w[9 * r + z];
-    else
-      rest += g_w[9 * r + z] * (double)x[c];
+__global__ void __launch_bounds__(BAND_T) k_xi_faces(int WW, double h, T *x, const int *__restrict__ f_code, int nf,
+                                                     const double *__restrict__ gsum, const int *__restrict__ mp) {
+  double fs = 0;
+  for (int q = threadIdx.x; q < nf; q += BAND_T) {
+    double v = (double)x[f_code[q] >> 1];
+    fs += (f_code[q] & 1) ? -v : v;
   }
-  double xv = (double)x[k], bb = (double)b[k], dt = g_dtau[r];
-  for (int it = 0; it < sweeps; it++) xv = xv + dt * (bb - (w0 * xv + rest));
-  x[k] = (T)xv;
+  fs = band_block_sum(fs);
+  if (threadIdx.x == 0) x[3 * WW] = (T)((fs / h - *gsum) / *mp);
 }
+
 
 // ---------------------------------------------------------------------------------------------------------
 // deterministic grid reductions: fixed grid, fixed per-thread ranges, tree in LDS, the last block sums the
@@ -368,19 +434,24 @@ __device__ bool last_block_total(double mine, double *part, unsigned *ticket, do
   return true;
 }
 
-// xi = mean over internal cells of (div_h u - g): the value that makes the continuity residuals sum to zero
+// G = sum over the internal cells of (g - (wall Dirichlet faces of the cell, with their divergence signs) / h); the
+// xi update then needs only the faces of the boundary list: xi = (sum over the listed faces of +-u / h - G) / mp
 template <typename T>
-__global__ void __launch_bounds__(TPB) k_xi(int N, int W, double h, const uint8_t *__restrict__ cls, T *__restrict__ x,
-                                            const T *__restrict__ b, double *part, unsigned *ticket, const int *mp) {
+__global__ void __launch_bounds__(TPB) k_gsum(int W, double h, const uint8_t *__restrict__ cls, const T *__restrict__ x,
+                                              const T *__restrict__ b, double *part, unsigned *ticket, double *out) {
   const int WW = W * W;
   double s = 0;
-  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < N * N; t += gridDim.x * blockDim.x) {
-    int i = t % N, j = t / N, c = pidx(W, i, j);
-    if (cls[2 * WW + c] != K_INT) continue;
-    s += ((double)x[c + 1] - (double)x[c] + (double)x[WW + c + W] - (double)x[WW + c]) / h - (double)b[2 * WW + c];
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < WW; t += gridDim.x * blockDim.x) {
+    if (cls[2 * WW + t] != K_INT) continue;
+    double wf = 0;
+    if (cls[t + 1] == K_WALLD) wf += (double)x[t + 1];
+    if (cls[t] == K_WALLD) wf -= (double)x[t];
+    if (cls[WW + t + W] == K_WALLD) wf += (double)x[WW + t + W];
+    if (cls[WW + t] == K_WALLD) wf -= (double)x[WW + t];
+    s += (double)b[2 * WW + t] - wf / h;
   }
   double tot;
-  if (last_block_total(s, part, ticket, &tot) && threadIdx.x == 0) x[3 * WW] = (T)(tot / *mp);
+  if (last_block_total(s, part, ticket, &tot) && threadIdx.x == 0) *out = tot;
 }
 
 // mean of the internal pressure (row eq:midpoint); result in *out
@@ -706,11 +777,12 @@ __global__ void __launch_bounds__(TPB) k_prolong(int Nf, int Wf, const uint8_t *
 
 // exact coarsest solve with the stored inverse: x[map[q]] = sum_r Ainv[q][r] b[map[r]] (one wavefront per row)
 template <typename T>
-__global__ void __launch_bounds__(64) k_coarse_apply(const double *__restrict__ Ainv, const int *__restrict__ map, int nc,
-                                                     const T *__restrict__ b, T *__restrict__ x) {
+__global__ void __launch_bounds__(64) k_coarse_apply(const double *__restrict__ Ainv, const int *__restrict__ map,
+                                                     const int *__restrict__ bmap, int nc, const T *__restrict__ b,
+                                                     T *__restrict__ x) {
   int q = blockIdx.x;
   double s = 0;
-  for (int r = threadIdx.x; r < nc; r += 64) s += Ainv[(size_t)q * nc + r] * (double)b[map[r]];
+  for (int r = threadIdx.x; r < nc; r += 64) s += Ainv[(size_t)q * nc + r] * (double)b[bmap[r]];
   for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
   if (threadIdx.x == 0) x[map[q]] = (T)s;
 }
@@ -762,14 +834,19 @@ static void relax(Ctx *ctx, int l) {
   for (int col = 0; col < 5; col++) k_box<T><<<box_grid(K, G.N), TPB, 0, s>>>(G.N, G.W, G.h, a, d, G.cls, V.x, V.b, col);
   const bool band = ctx->prm.bnd_sweeps > 0 && G.nband > 0;
   const size_t lds_bytes = (size_t)G.nreg * sizeof(T);
-  if (band && G.lds_ok && lds_bytes + 1024 <= ctx->max_lds && G.nbg <= MAXR * BAND_T) {
-    if (G.nwg)
-      k_wall_ghosts<T><<<nblk(G.nwg), TPB, 0, s>>>(G.wg_rows, G.nwg, G.g_pt, G.g_col, G.g_w, G.g_dtau, V.x, V.b,
-                                                    ctx->prm.lambda_ghost * (1 + ctx->prm.bnd_sweeps));
-    k_band_lds<T><<<1, BAND_T, lds_bytes, s>>>(G.N, G.W, G.h, a, d, V.x, V.b, G.band, G.d_band_off, G.bbox, G.reg_pt, G.nreg,
-                                               G.bg_rows, G.bg_loc, G.nbg, G.g_pt, G.g_w, G.g_dtau, ctx->prm.bnd_sweeps,
-                                               ctx->prm.lambda_ghost);
-  } else if (band && G.ng <= 4 * GH_T) {
+  if (band && G.lds_ok && lds_bytes + 1024 <= ctx->max_lds) {
+    // wall ghosts, body ghosts, band boxes and xi in one workgroup
+    int nwb = (G.nwg + BAND_T - 1) / BAND_T;
+    BandOff bo;
+    for (int c = 0; c < 6; c++) bo.o[c] = G.hband_off[c];
+    k_band_lds<T><<<1 + nwb, BAND_T, lds_bytes, s>>>(G.N, G.W, G.h, a, d, V.x, V.b, bo, G.bbox, G.bcap, G.reg_pt, G.nreg,
+                                                     G.bg_k, G.bg_loc, G.bg_w, G.bg_dt, G.nbg, G.gcap, ctx->gtmp, G.g_pt, G.g_col,
+                                                     G.g_w, G.g_dtau, G.wg_rows,
+                                               G.nwg, ctx->prm.bnd_sweeps, ctx->prm.lambda_ghost, G.f_code, G.f_loc, G.nf,
+                                               ctx->d_lev + l, G.d_mp);
+    return;
+  }
+  if (band && G.ng <= 4 * GH_T) {
     // ghost sweeps and the band sweeps in one workgroup
     k_band_sweeps<T><<<1, BAND_T, 0, s>>>(G.N, G.W, G.h, a, d, G.cls, V.x, V.b, G.band, G.d_band_off, G.g_pt, G.g_col,
                                           G.g_w, G.g_dtau, G.ng, ctx->gtmp, ctx->prm.bnd_sweeps, ctx->prm.lambda_ghost, 1);
@@ -779,8 +856,16 @@ static void relax(Ctx *ctx, int l) {
       k_band_sweeps<T><<<1, BAND_T, 0, s>>>(G.N, G.W, G.h, a, d, G.cls, V.x, V.b, G.band, G.d_band_off, G.g_pt, G.g_col,
                                             G.g_w, G.g_dtau, G.ng, ctx->gtmp, ctx->prm.bnd_sweeps, ctx->prm.lambda_ghost, 0);
   }
-  int nb = std::min(RED_BLOCKS, nblk((long)G.N * G.N));
-  k_xi<T><<<nb, TPB, 0, s>>>(G.N, G.W, G.h, G.cls, V.x, V.b, ctx->d_red, ctx->d_ticket, G.d_mp);
+  k_xi_faces<T><<<1, BAND_T, 0, s>>>(G.WW, G.h, V.x, G.f_code, G.nf, ctx->d_lev + l, G.d_mp);
+}
+
+// sum of the continuity right-hand sides of level l (read by the xi updates of its relaxation steps)
+template <typename T>
+static void gsum(Ctx *ctx, int l) {
+  Geo &G = ctx->geo[l];
+  int nb = std::min(RED_BLOCKS, nblk(G.WW));
+  k_gsum<T><<<nb, TPB, 0, ctx->stream>>>(G.W, G.h, G.cls, vec<T>(ctx, l).x, vec<T>(ctx, l).b, ctx->d_red, ctx->d_ticket,
+                                         ctx->d_lev + l);
 }
 
 template <typename T>
@@ -807,7 +892,7 @@ template <typename T>
 static void coarse_solve(Ctx *ctx) {
   int l = ctx->L - 1;
   Vec<T> &V = vec<T>(ctx, l);
-  k_coarse_apply<T><<<ctx->nc, 64, 0, ctx->stream>>>(ctx->c_A, ctx->c_map, ctx->nc, V.b, V.x);
+  k_coarse_apply<T><<<ctx->nc, 64, 0, ctx->stream>>>(ctx->c_A, ctx->c_map, ctx->c_bmap, ctx->nc, V.b, V.x);
 }
 
 template <typename T>
@@ -819,9 +904,11 @@ static void cycle(Ctx *ctx, int l) {
   Geo &F = ctx->geo[l], &C = ctx->geo[l + 1];
   Vec<T> &VF = vec<T>(ctx, l), &VC = vec<T>(ctx, l + 1);
   hipStream_t s = ctx->stream;
+  if (l == 0) gsum<T>(ctx, 0);
   for (int q = 0; q < ctx->prm.nu1; q++) relax<T>(ctx, l);
   residual<T>(ctx, l, nullptr);
   k_restrict<T, T><<<nblk(3L * C.WW + 1), TPB, 0, s>>>(F.N, F.W, F.cls, VF.r, C.N, C.W, C.cls, VC.b);
+  if (l + 1 < ctx->L - 1) gsum<T>(ctx, l + 1);
   k_fill<T><<<nblk(C.n), TPB, 0, s>>>(VC.x, C.n, (T)0);
   int reps = (l + 1 == ctx->L - 1) ? 1 : ctx->prm.gamma;
   for (int q = 0; q < reps; q++) cycle<T>(ctx, l + 1);
@@ -875,6 +962,7 @@ gp_status set_wall_dirichlet(Ctx *ctx) {
 }
 
 gp_status relax64(Ctx *ctx, int level, int steps) {
+  gsum<double>(ctx, level);
   for (int q = 0; q < steps; q++) relax<double>(ctx, level);
   GP_HIP(hipGetLastError());
   GP_HIP(hipStreamSynchronize(ctx->stream));
