@@ -167,6 +167,25 @@ gp_status gp_relax(gp_ctx *ctx, int level, int steps);
  * launch), 1 = residual of the internal rows, 2 = restriction, 3 = prolongation, 4 = ghost sweeps. */
 gp_status gp_time_kernel(gp_ctx *ctx, int which, int level, int reps, double *avg_us);
 
+/* ---- transposed system (the adjoint of the augmented system of Sect. 3.3, eq. (spaceprobaug)) ----
+ * Vectors are full unknown vectors of the finest level, n = 3*W*W + 1 doubles: the u, v and p grids (W*W each,
+ * same layout as gp_set_x) and then xi, or, for right-hand sides, the rows of the same points and then the
+ * mean-pressure row.  Host arrays when on_device = 0, device arrays on the context's device otherwise; the
+ * caller owns them, the library copies in and out.  The matrix is the one of the current geometry and alpha.
+ *
+ * gp_apply_mt: y = M^T lam.
+ * gp_adjoint_solve: solves M^T lam = g by lam <- lam + B'^T (g - M^T lam), where B'^T is the exact transpose of
+ *   one FP64 cycle (the transposed cycle: every step of the cycle transposed, in reverse order), until
+ *   ||g - M^T lam||_inf <= tol * max(1, ||g||_inf) or max_cycles (GP_ENOCONV, lam still written).  Entries of g
+ *   at points that are not unknowns (extension and inactive points) are ignored.
+ * gp_apply_cycle, gp_apply_cycle_t (test hooks for the transposition): x = B' b, one FP64 cycle from x = 0 with
+ *   the mean-row shift (this overwrites the context's current x and b), and bbar = B'^T xbar. */
+gp_status gp_apply_mt(gp_ctx *ctx, const double *lam, double *y, int on_device);
+gp_status gp_adjoint_solve(gp_ctx *ctx, const double *g, double *lam, int on_device, double tol, int max_cycles,
+                           gp_stats *st);
+gp_status gp_apply_cycle(gp_ctx *ctx, const double *b, double *x, int on_device);
+gp_status gp_apply_cycle_t(gp_ctx *ctx, const double *xbar, double *bbar, int on_device);
+
 #ifdef __cplusplus
 }
 #endif

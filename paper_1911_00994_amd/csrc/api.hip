@@ -142,7 +142,12 @@ void gp_destroy(gp_ctx *ctx) {
     dfree(ctx->v32[l].x);
     dfree(ctx->v32[l].b);
     dfree(ctx->v32[l].r);
+    dfree(ctx->adj[l].x);
+    dfree(ctx->adj[l].b);
+    dfree(ctx->adj[l].r);
   }
+  dfree(ctx->a_g);
+  dfree(ctx->a_lam);
   dfree(ctx->phi);
   dfree(ctx->gtmp);
   dfree(ctx->d_red);

@@ -80,6 +80,8 @@ struct Ctx {
   Geo geo[MAXLEV];
   Vec<double> v64[MAXLEV];
   Vec<float> v32[MAXLEV];
+  Vec<double> adj[MAXLEV];          // transposed cycle: x = adjoint of x, b = adjoint of b, r = adjoint of r
+  double *a_g = nullptr, *a_lam = nullptr;  // transposed solve: right-hand side and solution (finest)
   double *phi = nullptr;            // fine half lattice (2N+1)^2
   double *gtmp = nullptr;           // ghost Jacobi scratch (max gcap)
   // reductions / flags
@@ -135,6 +137,10 @@ gp_status relax64(Ctx *ctx, int level, int steps);
 gp_status residual64(Ctx *ctx, int level, double *res_inf);
 gp_status set_wall_dirichlet(Ctx *ctx);
 gp_status time_kernel(Ctx *ctx, int which, int level, int reps, double *avg_us);
+
+// adjoint (adjoint.hip)
+gp_status adjoint_alloc(Ctx *ctx);
+gp_status adjoint_solve_dev(Ctx *ctx, double tol, int max_cycles, gp_stats *st);
 
 // time stepping (cn.hip)
 gp_status cn_set_state_finish(Ctx *ctx);

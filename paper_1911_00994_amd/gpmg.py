@@ -23,7 +23,7 @@ EXPORTS = [
     "gp_set_levelset", "gp_set_levelset_analytic", "gp_set_walls", "gp_get_boundary_geometry",
     "gp_set_boundary_values", "gp_set_alpha", "gp_set_rhs", "gp_set_x", "gp_get_x", "gp_mg_vcycle", "gp_solve",
     "gp_residual", "gp_set_state", "gp_cn_step", "gp_get_classes", "gp_get_ghost_rows", "gp_get_ext_rows",
-    "gp_relax", "gp_time_kernel",
+    "gp_relax", "gp_time_kernel", "gp_apply_mt", "gp_adjoint_solve", "gp_apply_cycle", "gp_apply_cycle_t",
 ]
 
 
@@ -96,6 +96,10 @@ def lib():
         "gp_get_ext_rows": (i, [vp, i, vp, vp]),
         "gp_relax": (i, [vp, i, i]),
         "gp_time_kernel": (i, [vp, i, i, i, vp]),
+        "gp_apply_mt": (i, [vp, vp, vp, i]),
+        "gp_adjoint_solve": (i, [vp, vp, vp, i, d, i, ctypes.POINTER(GpStats)]),
+        "gp_apply_cycle": (i, [vp, vp, vp, i]),
+        "gp_apply_cycle_t": (i, [vp, vp, vp, i]),
     }
     for name, (res, args) in sigs.items():
         f = getattr(L, name)
@@ -276,3 +280,35 @@ class Solver:
         w = np.zeros(3 * P)
         self._check(lib().gp_get_ext_rows(self._h, level, _ptr(src), _ptr(w)), "gp_get_ext_rows")
         return src.reshape(P, 3), w.reshape(P, 3)
+
+    # transposed system ----------------------------------------------------------------------------
+    def nvec(self):
+        return 3 * self.W * self.W + 1
+
+    def _vec_op(self, name, v):
+        v = _host(v)
+        assert v.size == self.nvec()
+        out = np.zeros(self.nvec())
+        self._check(getattr(lib(), name)(self._h, _ptr(v), _ptr(out), 0), name)
+        return out
+
+    def apply_mt(self, lam):
+        """y = M^T lam (full unknown vectors of length 3 W^2 + 1)."""
+        return self._vec_op("gp_apply_mt", lam)
+
+    def apply_cycle(self, b):
+        """x = B' b: one FP64 cycle from x = 0 (overwrites the current x and b)."""
+        return self._vec_op("gp_apply_cycle", b)
+
+    def apply_cycle_t(self, xbar):
+        """bbar = B'^T xbar (the transposed cycle)."""
+        return self._vec_op("gp_apply_cycle_t", xbar)
+
+    def adjoint_solve(self, g, tol=1e-10, max_cycles=200, check=True):
+        g = _host(g)
+        lam = np.zeros(self.nvec())
+        s = GpStats()
+        st = lib().gp_adjoint_solve(self._h, _ptr(g), _ptr(lam), 0, tol, max_cycles, ctypes.byref(s))
+        if check and st != GP_OK:
+            self._check(st, "gp_adjoint_solve")
+        return lam, st, s.as_dict()
