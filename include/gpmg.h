@@ -186,6 +186,26 @@ gp_status gp_adjoint_solve(gp_ctx *ctx, const double *g, double *lam, int on_dev
 gp_status gp_apply_cycle(gp_ctx *ctx, const double *b, double *x, int on_device);
 gp_status gp_apply_cycle_t(gp_ctx *ctx, const double *xbar, double *bbar, int on_device);
 
+/* ---- reverse mode of a run of Crank-Nicolson steps (gradients of a function J of the final velocity) ----
+ * gp_tape_forward runs nsteps FP64 steps of size dt from the current state (gp_set_state, geometry at t0 set),
+ * the geometry of step n being the analytic shape at t0 + (n+1) dt under motion, with constant forcing fu, fv
+ * (W*W grid arrays, NULL = 0) and the continuity right-hand side 0.  The body rows take the rigid boundary
+ * velocity of motion plus ub_offset (host [2], NULL = 0): the body path is that of motion alone, so ub_offset is a
+ * boundary-velocity parameter with the geometry held fixed.  The state before every checkpoint_every-th step is
+ * kept on the device (about 11 W*W doubles each) and the context is left at the end of the run.
+ * gp_tape_backward takes seed = dJ/du, dJ/dv at the end of the run (W*W grid arrays) and returns dJ/dfu, dJ/dfv
+ * (W*W), dJ/d(ub_offset) (host [2]) and dJ/du, dJ/dv of the initial state (W*W; any output may be NULL).  It
+ * replays each segment from its checkpoint and runs the adjoint of every step backwards: the transposed
+ * convection Jacobian, extension fill and solve (gp_adjoint_solve with tol, max_cycles), and for the first two
+ * steps the adjoint of the converged fixed-point iteration.  Arrays are host or device per on_device (dJdU always
+ * host).  Errors: GP_EINVAL without a preceding gp_tape_forward on this context. */
+gp_status gp_tape_forward(gp_ctx *ctx, const gp_shape *shape, const gp_rigid *motion, double t0, double dt, int nsteps,
+                          const double *fu, const double *fv, int on_device, const double *ub_offset, double tol,
+                          int max_cycles, double picard_eps, int picard_max, int checkpoint_every, gp_stats *st);
+gp_status gp_tape_backward(gp_ctx *ctx, const double *seed_u, const double *seed_v, int on_device, double tol,
+                           int max_cycles, double *dJdfu, double *dJdfv, double *dJdU, double *dJdu0, double *dJdv0,
+                           gp_stats *st);
+
 #ifdef __cplusplus
 }
 #endif

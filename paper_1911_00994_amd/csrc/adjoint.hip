@@ -721,6 +721,360 @@ gp_status adjoint_solve_dev(Ctx *ctx, double tol, int max_cycles, gp_stats *stt)
   return out;
 }
 
+
+// ---------------------------------------------------------------------------------------------------------
+// reverse mode of the Crank-Nicolson step (Sect. 2): the right-hand side of step n on the internal momentum
+// rows of Omega^{n+1} is u^n + alpha lap u^n + dt f - dt C with C = c^n + c^{n-1}/2 - c^{n-2}/2 (extrapolation)
+// or C = (c^n + c(u^{n+1}))/2 (converged fixed-point iteration of the first two steps)
+// ---------------------------------------------------------------------------------------------------------
+namespace {
+
+// xb += J_c(y)^T cbar: transpose of the Jacobian of c(u) = u du/dx + vbar du/dy (and its v counterpart) at the
+// state y, gathered at every u and v node from the convection nodes whose stencil holds it
+__global__ void k_conv_jt(int N, int W, double h, const double *__restrict__ y, const double *__restrict__ cbu,
+                          const double *__restrict__ cbv, double *xb) {
+  const int WW = W * W;
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= 2 * WW) return;
+  const int g = t / WW, q = t - g * WW, b = q / W - 1, a = q % W - 1;
+  const double *U = y, *V = y + WW;
+  auto in = [&](int i, int j) { return i >= -1 && i <= N && j >= -1 && j <= N; };
+  auto CU = [&](int i, int j) { return in(i, j) ? cbu[aix(W, i, j)] : 0.0; };
+  auto CV = [&](int i, int j) { return in(i, j) ? cbv[aix(W, i, j)] : 0.0; };
+  auto Uv = [&](int i, int j) { return in(i, j) ? U[aix(W, i, j)] : 0.0; };
+  auto Vv = [&](int i, int j) { return in(i, j) ? V[aix(W, i, j)] : 0.0; };
+  auto vbar = [&](int i, int j) { return 0.25 * (Vv(i - 1, j) + Vv(i, j) + Vv(i - 1, j + 1) + Vv(i, j + 1)); };
+  auto ubar = [&](int i, int j) { return 0.25 * (Uv(i, j - 1) + Uv(i + 1, j - 1) + Uv(i, j) + Uv(i + 1, j)); };
+  const double i2h = 0.5 / h;
+  double s = 0, c;
+  if (g == 0) {
+    if ((c = CU(a, b)) != 0.0) s += c * (Uv(a + 1, b) - Uv(a - 1, b)) * i2h;
+    if ((c = CU(a - 1, b)) != 0.0) s += c * Uv(a - 1, b) * i2h;
+    if ((c = CU(a + 1, b)) != 0.0) s -= c * Uv(a + 1, b) * i2h;
+    if ((c = CU(a, b - 1)) != 0.0) s += c * vbar(a, b - 1) * i2h;
+    if ((c = CU(a, b + 1)) != 0.0) s -= c * vbar(a, b + 1) * i2h;
+    const int ci[4] = {a, a - 1, a, a - 1}, cj[4] = {b + 1, b + 1, b, b};
+    for (int z = 0; z < 4; z++)
+      if ((c = CV(ci[z], cj[z])) != 0.0) s += c * 0.25 * (Vv(ci[z] + 1, cj[z]) - Vv(ci[z] - 1, cj[z])) * i2h;
+  } else {
+    if ((c = CV(a, b)) != 0.0) s += c * (Vv(a, b + 1) - Vv(a, b - 1)) * i2h;
+    if ((c = CV(a - 1, b)) != 0.0) s += c * ubar(a - 1, b) * i2h;
+    if ((c = CV(a + 1, b)) != 0.0) s -= c * ubar(a + 1, b) * i2h;
+    if ((c = CV(a, b - 1)) != 0.0) s += c * Vv(a, b - 1) * i2h;
+    if ((c = CV(a, b + 1)) != 0.0) s -= c * Vv(a, b + 1) * i2h;
+    const int ci[4] = {a + 1, a, a + 1, a}, cj[4] = {b, b, b - 1, b - 1};
+    for (int z = 0; z < 4; z++)
+      if ((c = CU(ci[z], cj[z])) != 0.0) s += c * 0.25 * (Uv(ci[z], cj[z] + 1) - Uv(ci[z], cj[z] - 1)) * i2h;
+  }
+  if (s != 0.0) xb[t] += s;
+}
+
+// from the adjoint lam of the step's right-hand side (P lam = lam on the internal momentum rows):
+// xbn = P lam + alpha lap^T (P lam) (adjoint of u^n), fb += dt P lam, and the convection-history adjoints
+__global__ void k_step_adj(int N, int W, double h, double alpha, double dt, const uint8_t *__restrict__ cls,
+                           const double *__restrict__ lam, double *xbn, double *fb, double *r1, double *r2, double *r3,
+                           int extrap) {
+  const int WW = W * W;
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= 2 * WW) return;
+  const int g = t / WW, q = t - g * WW, j = q / W - 1, i = q % W - 1;
+  const uint8_t *cg = cls + g * WW;
+  const double *lg = lam + g * WW;
+  auto P = [&](int a, int b) {
+    return (a >= -1 && a <= N && b >= -1 && b <= N && cg[aix(W, a, b)] == K_INT) ? lg[aix(W, a, b)] : 0.0;
+  };
+  const double pc = P(i, j);
+  const double lapt = P(i - 1, j) + P(i + 1, j) + P(i, j - 1) + P(i, j + 1) - 4.0 * pc;
+  xbn[t] = pc + alpha / (h * h) * lapt;
+  if (pc == 0.0) return;
+  fb[t] += dt * pc;
+  if (extrap) {
+    r1[t] -= dt * pc;
+    r2[t] -= 0.5 * dt * pc;
+    r3[t] += 0.5 * dt * pc;
+  } else {
+    r1[t] -= 0.5 * dt * pc;
+  }
+}
+
+// cb = scale * P lam (u and v)
+__global__ void k_pscale(int W, const uint8_t *__restrict__ cls, const double *__restrict__ lam, double scale, double *cb) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= 2 * W * W) return;
+  cb[t] = cls[t] == K_INT ? scale * lam[t] : 0.0;
+}
+
+// ub[comp] += sum of lam over the body boundary-condition rows of grid comp
+__global__ void __launch_bounds__(TPB) k_ub_sum(int W, int comp, const uint8_t *__restrict__ cls, const double *__restrict__ lam,
+                                                double *part, unsigned *ticket, double *ub) {
+  const int WW = W * W;
+  double s = 0;
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < WW; t += gridDim.x * blockDim.x)
+    if (cls[comp * WW + t] == K_GHOST) s += lam[comp * WW + t];
+  double tot;
+  if (alast_total(s, part, ticket, &tot) && threadIdx.x == 0) ub[comp] += tot;
+}
+
+__global__ void k_diffmax(const double *__restrict__ a, const double *__restrict__ b, long n, unsigned long long *out) {
+  double m = 0;
+  for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < n; t += (long)gridDim.x * blockDim.x) {
+    double d = fabs(a[t] - b[t]);
+    m = (d > m || d != d) ? d : m;
+  }
+  unsigned long long bb = (unsigned long long)__double_as_longlong(m);
+  for (int o = 32; o > 0; o >>= 1) {
+    unsigned long long c = __shfl_xor(bb, o, 64);
+    bb = c > bb ? c : bb;
+  }
+  if ((threadIdx.x & 63) == 0 && bb) atomicMax(out, bb);
+}
+
+}  // namespace
+
+// ---- tape ----
+static size_t snap_len(const Ctx *ctx) { return 11 * (size_t)ctx->geo[0].WW + 1; }
+
+static gp_status snap_alloc(Ctx *ctx, CnSnap &sn) {
+  if (!sn.buf) GP_HIP(hipMalloc((void **)&sn.buf, snap_len(ctx) * sizeof(double)));
+  return GP_OK;
+}
+static gp_status snap_save(Ctx *ctx, CnSnap &sn) {
+  gp_status st = snap_alloc(ctx, sn);
+  if (st) return st;
+  const size_t WW = ctx->geo[0].WW, n = 3 * WW + 1;
+  hipStream_t s = ctx->stream;
+  GP_HIP(hipMemcpyAsync(sn.buf, ctx->v64[0].x, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+  for (int k = 0; k < 3; k++) {
+    GP_HIP(hipMemcpyAsync(sn.buf + n + (2 * k) * WW, ctx->cu[k], WW * sizeof(double), hipMemcpyDeviceToDevice, s));
+    GP_HIP(hipMemcpyAsync(sn.buf + n + (2 * k + 1) * WW, ctx->cv[k], WW * sizeof(double), hipMemcpyDeviceToDevice, s));
+  }
+  GP_HIP(hipMemcpyAsync(sn.buf + n + 6 * WW, ctx->lapu, WW * sizeof(double), hipMemcpyDeviceToDevice, s));
+  GP_HIP(hipMemcpyAsync(sn.buf + n + 7 * WW, ctx->lapv, WW * sizeof(double), hipMemcpyDeviceToDevice, s));
+  sn.nstep = ctx->nstep;
+  return GP_OK;
+}
+static gp_status snap_restore(Ctx *ctx, const CnSnap &sn) {
+  const size_t WW = ctx->geo[0].WW, n = 3 * WW + 1;
+  hipStream_t s = ctx->stream;
+  GP_HIP(hipMemcpyAsync(ctx->v64[0].x, sn.buf, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+  for (int k = 0; k < 3; k++) {
+    GP_HIP(hipMemcpyAsync(ctx->cu[k], sn.buf + n + (2 * k) * WW, WW * sizeof(double), hipMemcpyDeviceToDevice, s));
+    GP_HIP(hipMemcpyAsync(ctx->cv[k], sn.buf + n + (2 * k + 1) * WW, WW * sizeof(double), hipMemcpyDeviceToDevice, s));
+  }
+  GP_HIP(hipMemcpyAsync(ctx->lapu, sn.buf + n + 6 * WW, WW * sizeof(double), hipMemcpyDeviceToDevice, s));
+  GP_HIP(hipMemcpyAsync(ctx->lapv, sn.buf + n + 7 * WW, WW * sizeof(double), hipMemcpyDeviceToDevice, s));
+  ctx->nstep = sn.nstep;
+  return GP_OK;
+}
+
+void tape_free(Ctx *ctx) {
+  Tape &T = ctx->tape;
+  for (auto &sn : T.ckpt) (void)hipFree(sn.buf);
+  for (auto &sn : T.seg) (void)hipFree(sn.buf);
+  (void)hipFree(T.last.buf);
+  T.last.buf = nullptr;
+  T.ckpt.clear();
+  T.seg.clear();
+  for (double **p : {&T.fu, &T.fv, &T.xb, &T.yb, &T.xbn, &T.lamp, &T.ring, &T.fb, &T.tcb, &T.ub})
+    if (*p) {
+      (void)hipFree(*p);
+      *p = nullptr;
+    }
+  T.valid = 0;
+}
+
+// geometry of step n (t^{n+1}) with the tape's boundary-velocity offset
+static gp_status tape_geometry(Ctx *ctx, int n) {
+  Tape &T = ctx->tape;
+  ctx->ub_off[0] = T.ub_off[0];
+  ctx->ub_off[1] = T.ub_off[1];
+  return gp_set_levelset_analytic(static_cast<gp_ctx *>(ctx), &T.shape, T.t0 + (n + 1) * T.dt, &T.motion);
+}
+
+static gp_status tape_step(Ctx *ctx, int n, gp_stats *st) {
+  Tape &T = ctx->tape;
+  gp_status s = tape_geometry(ctx, n);
+  if (s) return s;
+  return gp_cn_step(static_cast<gp_ctx *>(ctx), T.dt, T.fu, T.fv, nullptr, 1, GP_FP64, T.tol, T.max_cycles, T.picard_eps,
+                    T.picard_max, st);
+}
+
+// reverse of step n; the context holds the geometry of t^{n+1}, post = the state after step n, pre.nstep tells
+// which convection form the step used
+static gp_status adjoint_step(Ctx *ctx, const CnSnap &pre, const CnSnap &post, double tol, int max_cycles,
+                              gp_stats *acc) {
+  Tape &T = ctx->tape;
+  Geo &G = ctx->geo[0];
+  hipStream_t s = ctx->stream;
+  const size_t WW = G.WW, n = G.n;
+  gp_status st = GP_OK;
+  ctx->alpha = T.dt / (2.0 * ctx->Re);
+  ctx->c_ok = 0;
+  if ((st = ready(ctx))) return st;
+  const double *y = post.buf;  // x^{n+1} (extension values filled)
+  double *R[4];  // adjoints of c^{n+1}, c^n, c^{n-1}, c^{n-2} (u grid, then v grid)
+  for (int k = 0; k < 4; k++) R[k] = T.ring + (size_t)((T.ring_head + k) & 3) * 2 * WW;
+  const int extrap = pre.nstep >= 2;
+  // adjoint of c^{n+1} = c(x^{n+1})
+  k_conv_jt<<<nblk(2L * WW), TPB, 0, s>>>(G.N, G.W, G.h, y, R[0], R[0] + WW, T.xb);
+  if (!extrap) k_copy<<<nblk(n), TPB, 0, s>>>(T.yb, T.xb, n);
+  // adjoint of the extension fill, then of the solve
+  if (G.ne) k_ext_adj<<<nblk(G.ne), TPB, 0, s>>>(G.e_pt, G.e_src, G.e_w, G.ne, T.xb);
+  k_copy<<<nblk(n), TPB, 0, s>>>(ctx->a_g, T.xb, n);
+  k_fill0<<<nblk(n), TPB, 0, s>>>(ctx->a_lam, n);
+  gp_stats sub{};
+  st = adjoint_solve_dev(ctx, tol, max_cycles, &sub);
+  if (st != GP_OK && st != GP_ENOCONV) return st;
+  acc->cycles += sub.cycles;
+  acc->outer++;
+  if (!extrap) {
+    // fixed point lam = M^{-T} E^T (ybar - dt/2 J_c^T P lam)
+    for (int it = 0; it < T.picard_max; it++) {
+      k_pscale<<<nblk(2L * WW), TPB, 0, s>>>(G.W, G.cls, ctx->a_lam, -0.5 * T.dt, T.tcb);
+      k_copy<<<nblk(n), TPB, 0, s>>>(ctx->a_g, T.yb, n);
+      k_conv_jt<<<nblk(2L * WW), TPB, 0, s>>>(G.N, G.W, G.h, y, T.tcb, T.tcb + WW, ctx->a_g);
+      if (G.ne) k_ext_adj<<<nblk(G.ne), TPB, 0, s>>>(G.e_pt, G.e_src, G.e_w, G.ne, ctx->a_g);
+      k_copy<<<nblk(n), TPB, 0, s>>>(T.lamp, ctx->a_lam, n);
+      st = adjoint_solve_dev(ctx, tol, max_cycles, &sub);  // warm start from the previous lam
+      if (st != GP_OK && st != GP_ENOCONV) return st;
+      acc->cycles += sub.cycles;
+      acc->outer++;
+      unsigned long long *m = (unsigned long long *)(ctx->d_scal + 11);
+      k_fill0<<<1, 1, 0, s>>>((double *)m, 1);
+      k_diffmax<<<std::min(1024, nblk(n)), TPB, 0, s>>>(ctx->a_lam, T.lamp, n, m);
+      double dl, ln;
+      unsigned long long hv;
+      GP_HIP(hipMemcpyAsync(&hv, m, sizeof(hv), hipMemcpyDeviceToHost, s));
+      GP_HIP(hipStreamSynchronize(s));
+      std::memcpy(&dl, &hv, sizeof(double));
+      if ((st = absmax_dev(ctx, ctx->a_lam, n, &ln))) return st;
+      if (!(dl == dl)) return GP_EDIVERGED;
+      if (dl <= T.picard_eps * (ln > 1 ? ln : 1)) break;
+    }
+  }
+  // adjoints of u^n, of the forcing, of the convection history and of the boundary velocity
+  k_step_adj<<<nblk(2L * WW), TPB, 0, s>>>(G.N, G.W, G.h, ctx->alpha, T.dt, G.cls, ctx->a_lam, T.xbn, T.fb, R[1], R[2],
+                                          R[3], extrap);
+  for (int comp = 0; comp < 2; comp++)
+    k_ub_sum<<<std::min(ARED, nblk(WW)), TPB, 0, s>>>(G.W, comp, G.cls, ctx->a_lam, ctx->d_red, ctx->d_ticket, T.ub);
+  // rotate the ring: c^{n+1} is done (its slot becomes the zeroed c^{n-3}), c^n is the next step's first entry
+  k_fill0<<<nblk(2L * WW), TPB, 0, s>>>(R[0], 2 * WW);
+  T.ring_head = (T.ring_head + 1) & 3;
+  k_fill0<<<nblk(n), TPB, 0, s>>>(T.xb, n);
+  k_copy<<<nblk(2L * WW), TPB, 0, s>>>(T.xb, T.xbn, 2 * WW);
+  GP_HIP(hipGetLastError());
+  return GP_OK;
+}
+
+
+static gp_status dalloc0(Ctx *ctx, double **p, size_t n) {
+  if (!*p) GP_HIP(hipMalloc((void **)p, n * sizeof(double)));
+  k_fill0<<<nblk((long)n), TPB, 0, ctx->stream>>>(*p, (long)n);
+  return GP_OK;
+}
+
+gp_status tape_forward(Ctx *ctx, const gp_shape *shape, const gp_rigid *motion, double t0, double dt, int nsteps,
+                       const double *fu, const double *fv, int on_device, const double *ub_off, double tol, int max_cycles,
+                       double picard_eps, int picard_max, int K, gp_stats *stt) {
+  Tape &T = ctx->tape;
+  const size_t WW = ctx->geo[0].WW;
+  T.valid = 0;
+  if (T.K != K || (int)T.ckpt.size() < (nsteps + K - 1) / K) {
+    for (auto &sn : T.seg) (void)hipFree(sn.buf);
+    T.seg.clear();
+  }
+  T.nsteps = nsteps;
+  T.K = K;
+  T.shape = *shape;
+  T.motion = motion ? *motion : gp_rigid{0, 0, 0, 0, 0};
+  T.t0 = t0;
+  T.dt = dt;
+  T.ub_off[0] = ub_off ? ub_off[0] : 0.0;
+  T.ub_off[1] = ub_off ? ub_off[1] : 0.0;
+  T.tol = tol;
+  T.max_cycles = max_cycles;
+  T.picard_eps = picard_eps;
+  T.picard_max = picard_max;
+  gp_status st;
+  if ((st = dalloc0(ctx, &T.fu, WW)) || (st = dalloc0(ctx, &T.fv, WW))) return st;
+  hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+  if (fu) GP_HIP(hipMemcpyAsync(T.fu, fu, WW * sizeof(double), kind, ctx->stream));
+  if (fv) GP_HIP(hipMemcpyAsync(T.fv, fv, WW * sizeof(double), kind, ctx->stream));
+  const int nseg = (nsteps + K - 1) / K;
+  if ((int)T.ckpt.size() < nseg) T.ckpt.resize(nseg);
+  gp_stats acc{}, sub{};
+  auto t0c = std::chrono::steady_clock::now();
+  for (int n = 0; n < nsteps; n++) {
+    if (n % K == 0 && (st = snap_save(ctx, T.ckpt[n / K]))) return st;
+    st = tape_step(ctx, n, &sub);
+    if (st) return st;
+    acc.cycles += sub.cycles;
+    acc.outer += sub.outer;
+    acc.res = sub.res;
+  }
+  if ((st = snap_save(ctx, T.last))) return st;
+  ctx->ub_off[0] = ctx->ub_off[1] = 0.0;
+  GP_HIP(hipStreamSynchronize(ctx->stream));
+  acc.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0c).count();
+  if (stt) *stt = acc;
+  T.valid = 1;
+  return GP_OK;
+}
+
+gp_status tape_backward(Ctx *ctx, const double *seed_u, const double *seed_v, int on_device, double tol, int max_cycles,
+                        double *dfu, double *dfv, double *dU, double *du0, double *dv0, gp_stats *stt) {
+  Tape &T = ctx->tape;
+  Geo &G = ctx->geo[0];
+  const size_t WW = G.WW, n = G.n;
+  hipStream_t s = ctx->stream;
+  gp_status st;
+  if (!T.valid) return GP_EINVAL;
+  if ((st = adjoint_alloc(ctx))) return st;
+  if ((st = dalloc0(ctx, &T.xb, n)) || (st = dalloc0(ctx, &T.yb, n)) || (st = dalloc0(ctx, &T.xbn, 2 * WW)) ||
+      (st = dalloc0(ctx, &T.lamp, n)) || (st = dalloc0(ctx, &T.ring, 8 * WW)) || (st = dalloc0(ctx, &T.fb, 2 * WW)) ||
+      (st = dalloc0(ctx, &T.tcb, 2 * WW)) || (st = dalloc0(ctx, &T.ub, 2)))
+    return st;
+  T.ring_head = 0;
+  hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+  if (seed_u) GP_HIP(hipMemcpyAsync(T.xb, seed_u, WW * sizeof(double), kind, s));
+  if (seed_v) GP_HIP(hipMemcpyAsync(T.xb + WW, seed_v, WW * sizeof(double), kind, s));
+  const int K = T.K, nseg = (T.nsteps + K - 1) / K;
+  if ((int)T.seg.size() < K + 1) T.seg.resize(K + 1);
+  gp_stats acc{}, sub{};
+  auto t0c = std::chrono::steady_clock::now();
+  for (int sg = nseg - 1; sg >= 0; sg--) {
+    const int s0 = sg * K, s1 = std::min(s0 + K, T.nsteps);
+    if ((st = snap_restore(ctx, T.ckpt[sg]))) return st;
+    for (int m = s0; m < s1; m++) {
+      if ((st = snap_save(ctx, T.seg[m - s0]))) return st;
+      if ((st = tape_step(ctx, m, &sub))) return st;
+    }
+    if ((st = snap_save(ctx, T.seg[s1 - s0]))) return st;
+    for (int m = s1 - 1; m >= s0; m--) {
+      if ((st = tape_geometry(ctx, m))) return st;
+      if ((st = adjoint_step(ctx, T.seg[m - s0], T.seg[m + 1 - s0], tol, max_cycles, &acc))) return st;
+    }
+  }
+  // c^0 = c(u^0) entered the first steps: its adjoint goes to u^0
+  {
+    double *R0 = T.ring + (size_t)(T.ring_head & 3) * 2 * WW;
+    k_conv_jt<<<nblk(2L * WW), TPB, 0, s>>>(G.N, G.W, G.h, T.ckpt[0].buf, R0, R0 + WW, T.xb);
+  }
+  // the context is left at the end of the run
+  if ((st = tape_geometry(ctx, T.nsteps - 1)) || (st = snap_restore(ctx, T.last))) return st;
+  ctx->ub_off[0] = ctx->ub_off[1] = 0.0;
+  hipMemcpyKind ok = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+  if (dfu) GP_HIP(hipMemcpyAsync(dfu, T.fb, WW * sizeof(double), ok, s));
+  if (dfv) GP_HIP(hipMemcpyAsync(dfv, T.fb + WW, WW * sizeof(double), ok, s));
+  if (du0) GP_HIP(hipMemcpyAsync(du0, T.xb, WW * sizeof(double), ok, s));
+  if (dv0) GP_HIP(hipMemcpyAsync(dv0, T.xb + WW, WW * sizeof(double), ok, s));
+  if (dU) GP_HIP(hipMemcpyAsync(dU, T.ub, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+  GP_HIP(hipStreamSynchronize(s));
+  acc.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0c).count();
+  if (stt) *stt = acc;
+  return GP_OK;
+}
+
 }  // namespace gpmg
 
 using namespace gpmg;
@@ -787,4 +1141,22 @@ extern "C" gp_status gp_adjoint_solve(gp_ctx *ctx, const double *g, double *lam,
   if (out != GP_OK && out != GP_ENOCONV) return out;
   if ((st = copy_out(ctx, lam, ctx->a_lam, G.n, on_device))) return st;
   return out;
+}
+
+extern "C" gp_status gp_tape_forward(gp_ctx *ctx, const gp_shape *shape, const gp_rigid *motion, double t0, double dt,
+                                     int nsteps, const double *fu, const double *fv, int on_device, const double *ub_offset,
+                                     double tol, int max_cycles, double picard_eps, int picard_max, int checkpoint_every,
+                                     gp_stats *st) {
+  if (!ctx || !shape || !ctx->have_geom || !(dt > 0) || nsteps < 1 || checkpoint_every < 1 || !(tol > 0) ||
+      max_cycles < 1 || picard_max < 1)
+    return GP_EINVAL;
+  return tape_forward(ctx, shape, motion, t0, dt, nsteps, fu, fv, on_device, ub_offset, tol, max_cycles, picard_eps,
+                      picard_max, checkpoint_every, st);
+}
+
+extern "C" gp_status gp_tape_backward(gp_ctx *ctx, const double *seed_u, const double *seed_v, int on_device, double tol,
+                                      int max_cycles, double *dJdfu, double *dJdfv, double *dJdU, double *dJdu0,
+                                      double *dJdv0, gp_stats *st) {
+  if (!ctx || !(tol > 0) || max_cycles < 1) return GP_EINVAL;
+  return tape_backward(ctx, seed_u, seed_v, on_device, tol, max_cycles, dJdfu, dJdfv, dJdU, dJdu0, dJdv0, st);
 }

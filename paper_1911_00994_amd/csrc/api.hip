@@ -148,6 +148,7 @@ void gp_destroy(gp_ctx *ctx) {
   }
   dfree(ctx->a_g);
   dfree(ctx->a_lam);
+  tape_free(ctx);
   dfree(ctx->phi);
   dfree(ctx->gtmp);
   dfree(ctx->d_red);

@@ -748,8 +748,9 @@ __global__ void k_face_loc(const int *f_code, int nf, const int *map, int *f_loc
 // ---------------------------------------------------------------------------------------------------------
 // boundary data of the finest level
 // ---------------------------------------------------------------------------------------------------------
+// body rows: u_b(B) = V + omega x (B - X(t)) with the path X(t) = X0 + U t (V = U plus the boundary-velocity offset)
 __global__ void k_bvals_rows(const uint8_t *cls, int W, RowArgs R, double *b, double X0x, double X0y, double Ux, double Uy,
-                             double om, double t, double wbu, double wtu, double wlv, double wrv) {
+                             double om, double t, double Vx, double Vy, double wbu, double wtu, double wlv, double wrv) {
   int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= R.ng) return;
   int k = R.g_pt[r];
@@ -759,8 +760,8 @@ __global__ void k_bvals_rows(const uint8_t *cls, int W, RowArgs R, double *b, do
   if (c == K_GHOST) {
     double X = X0x + Ux * t, Y = X0y + Uy * t;
     double Bx = R.g_B[2 * r], By = R.g_B[2 * r + 1];
-    if (g == 0) val = Ux - om * (By - Y);
-    if (g == 1) val = Uy + om * (Bx - X);
+    if (g == 0) val = Vx - om * (By - Y);
+    if (g == 1) val = Vy + om * (Bx - X);
   } else if (c == K_WALLG) {
     if (g == 0) val = (j == -1) ? wbu : wtu;
     if (g == 1) val = (i == -1) ? wlv : wrv;
@@ -965,7 +966,8 @@ gp_status default_boundary_values(Ctx *ctx) {
   const gp_rigid &m = ctx->motion;
   if (G.ng)
     k_bvals_rows<<<nblk(G.ng), TPB, 0, ctx->stream>>>(G.cls, W, R, ctx->v64[0].b, m.X0x, m.X0y, m.Ux, m.Uy, m.omega,
-                                                      ctx->t_geom, w[0], w[4], w[7], w[3]);
+                                                      ctx->t_geom, m.Ux + ctx->ub_off[0], m.Uy + ctx->ub_off[1], w[0],
+                                                      w[4], w[7], w[3]);
   k_bvals_points<<<nblk(3 * W * W), TPB, 0, ctx->stream>>>(G.cls, G.N, W, ctx->v64[0].b, ctx->v64[0].x, w[6], w[2], w[1],
                                                            w[5]);
   GP_HIP(hipGetLastError());

@@ -71,6 +71,32 @@ struct Vec {
   T *x = nullptr, *b = nullptr, *r = nullptr;
 };
 
+// saved time-stepping state of the finest level: x (3*WW + 1), then the convection history c^n, c^{n-1},
+// c^{n-2} (u and v grids) and the Laplacian of u^n (u and v): 11*WW + 1 doubles
+struct CnSnap {
+  double *buf = nullptr;
+  int nstep = 0;
+};
+
+// record of a run of Crank-Nicolson steps for the reverse pass (checkpoints every K steps)
+struct Tape {
+  int valid = 0, nsteps = 0, K = 8;
+  gp_shape shape{};
+  gp_rigid motion{};
+  double t0 = 0, dt = 0, ub_off[2] = {0, 0};
+  double tol = 1e-10, picard_eps = 1e-6;
+  int max_cycles = 100, picard_max = 20;
+  double *fu = nullptr, *fv = nullptr;  // forcing (device, W*W each)
+  std::vector<CnSnap> ckpt;             // state before steps 0, K, 2K, ...
+  std::vector<CnSnap> seg;              // K + 1 states of the segment being reversed
+  CnSnap last;                          // state after the last step
+  // reverse pass: adjoint of the state (full vector), of the filled state of a fixed-point step, ring of the
+  // convection-history adjoints (c^{n+1}, c^n, c^{n-1}, c^{n-2}; u and v), forcing adjoint, scratch
+  double *xb = nullptr, *yb = nullptr, *xbn = nullptr, *lamp = nullptr, *ring = nullptr, *fb = nullptr, *tcb = nullptr;
+  double *ub = nullptr;                 // device [2]: adjoint of the boundary-velocity offset
+  int ring_head = 0;
+};
+
 struct Ctx {
   int N = 0, L = 0;
   double Re = 100, alpha = 0;
@@ -82,6 +108,7 @@ struct Ctx {
   Vec<float> v32[MAXLEV];
   Vec<double> adj[MAXLEV];          // transposed cycle: x = adjoint of x, b = adjoint of b, r = adjoint of r
   double *a_g = nullptr, *a_lam = nullptr;  // transposed solve: right-hand side and solution (finest)
+  Tape tape;
   double *phi = nullptr;            // fine half lattice (2N+1)^2
   double *gtmp = nullptr;           // ghost Jacobi scratch (max gcap)
   // reductions / flags
@@ -95,6 +122,7 @@ struct Ctx {
   int have_geom = 0;
   double t_geom = 0;
   gp_rigid motion{};
+  double ub_off[2] = {0, 0};        // offset added to the rigid boundary velocity of the body rows (path unchanged)
   double walls[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   // coarsest exact solve: compacted active unknowns and explicit inverse (FP64)
   int nc = 0;                       // number of active unknowns on the coarsest level
@@ -141,6 +169,7 @@ gp_status time_kernel(Ctx *ctx, int which, int level, int reps, double *avg_us);
 // adjoint (adjoint.hip)
 gp_status adjoint_alloc(Ctx *ctx);
 gp_status adjoint_solve_dev(Ctx *ctx, double tol, int max_cycles, gp_stats *st);
+void tape_free(Ctx *ctx);
 
 // time stepping (cn.hip)
 gp_status cn_set_state_finish(Ctx *ctx);

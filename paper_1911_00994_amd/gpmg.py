@@ -24,6 +24,7 @@ EXPORTS = [
     "gp_set_boundary_values", "gp_set_alpha", "gp_set_rhs", "gp_set_x", "gp_get_x", "gp_mg_vcycle", "gp_solve",
     "gp_residual", "gp_set_state", "gp_cn_step", "gp_get_classes", "gp_get_ghost_rows", "gp_get_ext_rows",
     "gp_relax", "gp_time_kernel", "gp_apply_mt", "gp_adjoint_solve", "gp_apply_cycle", "gp_apply_cycle_t",
+    "gp_tape_forward", "gp_tape_backward",
 ]
 
 
@@ -100,6 +101,9 @@ def lib():
         "gp_adjoint_solve": (i, [vp, vp, vp, i, d, i, ctypes.POINTER(GpStats)]),
         "gp_apply_cycle": (i, [vp, vp, vp, i]),
         "gp_apply_cycle_t": (i, [vp, vp, vp, i]),
+        "gp_tape_forward": (i, [vp, ctypes.POINTER(GpShape), ctypes.POINTER(GpRigid), d, d, i, vp, vp, i, vp, d, i, d, i,
+                                i, ctypes.POINTER(GpStats)]),
+        "gp_tape_backward": (i, [vp, vp, vp, i, d, i, vp, vp, vp, vp, vp, ctypes.POINTER(GpStats)]),
     }
     for name, (res, args) in sigs.items():
         f = getattr(L, name)
@@ -312,3 +316,29 @@ class Solver:
         if check and st != GP_OK:
             self._check(st, "gp_adjoint_solve")
         return lam, st, s.as_dict()
+
+    # reverse mode of a run of steps ---------------------------------------------------------------
+    def tape_forward(self, kind, params, motion, t0, dt, nsteps, fu=None, fv=None, ub_offset=None, tol=1e-10,
+                     max_cycles=100, picard_eps=1e-6, picard_max=20, checkpoint_every=8):
+        sh = GpShape()
+        sh.kind = kind
+        for q, v in enumerate(list(params)[:4]):
+            sh.p[q] = v
+        mo = GpRigid(*[float(v) for v in motion[:5]])
+        off = None if ub_offset is None else np.ascontiguousarray(ub_offset, dtype=np.float64)
+        s = GpStats()
+        st = lib().gp_tape_forward(self._h, ctypes.byref(sh), ctypes.byref(mo), t0, dt, nsteps, _ptr(_host(fu)),
+                                   _ptr(_host(fv)), 0, _ptr(off), tol, max_cycles, picard_eps, picard_max,
+                                   checkpoint_every, ctypes.byref(s))
+        self._check(st, "gp_tape_forward")
+        return s.as_dict()
+
+    def tape_backward(self, seed_u, seed_v, tol=1e-10, max_cycles=200):
+        W = self.W
+        dfu, dfv, du0, dv0 = (np.zeros((W, W)) for _ in range(4))
+        dU = np.zeros(2)
+        s = GpStats()
+        st = lib().gp_tape_backward(self._h, _ptr(_host(seed_u)), _ptr(_host(seed_v)), 0, tol, max_cycles, _ptr(dfu),
+                                    _ptr(dfv), _ptr(dU), _ptr(du0), _ptr(dv0), ctypes.byref(s))
+        self._check(st, "gp_tape_backward")
+        return dict(dfu=dfu, dfv=dfv, dU=dU, du0=du0, dv0=dv0, stats=s.as_dict())
