@@ -19,6 +19,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
+# HBM bytes per launch of the finest-level box kernel from the two rocprofv3 counter runs (FETCH_SIZE x 1.9992 +
+# WRITE_SIZE x 1.0, scaled by a 64 MiB device copy); the kernel is unchanged since they were taken
+BOX_TRAFFIC_BYTES = 71.87e6
+BOX_TRAFFIC_SOURCE = "profiles/k_box_flower1024_hbm_traffic.md"
 
 
 def box_launch_bytes(cls, N, colour, elem=8):
@@ -73,6 +77,42 @@ def cpu_baseline(wk, N, cycles):
                       f"{sec:.1f} s)"}
 
 
+def adjoint_run(gpmg, wl, N=512, steps=40, K=8, tol=1e-8):
+    """Reverse mode of the moving-circle run (N = 512, r = 0.25 translating at (0.5, 0), Re = 100, 40 steps of
+    dt = h, stream-function forcing of 64 modes): J = h^2 sum of the internal u^2 + v^2 at the end, gradients with
+    respect to the 64 forcing coefficients and the boundary-velocity offset, checkpoints every 8 steps."""
+    import numpy as np
+    import torch
+    wk = wl.config_circle512_adjoint()
+    h = 2.0 / N
+    s = gpmg.Solver(N, Re=wk.Re, stream=torch.cuda.current_stream().cuda_stream)
+    mo = wk.motion.as_array()
+    s.set_levelset_analytic(wk.shape.kind, wk.shape.params, 0.0, mo[:5])
+    W = N + 2
+    z = np.zeros((W, W))
+    s.set_state(z, z, z, 0.0)
+    coeffs = wl.adjoint_coeffs(seed=1)
+    fu, fv = wl.streamfunction_forcing(N, coeffs)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    fwd = s.tape_forward(wk.shape.kind, wk.shape.params, mo, 0.0, h, steps, fu, fv, tol=tol, max_cycles=200,
+                         picard_eps=1e-10, picard_max=40, checkpoint_every=K)
+    t1 = time.perf_counter()
+    u, v, _, _ = s.get_x()
+    cls = s.classes()
+    J = h * h * (float((u[cls[0] == 1] ** 2).sum()) + float((v[cls[1] == 1] ** 2).sum()))
+    seed_u = np.where(cls[0] == 1, 2 * h * h * u, 0.0)
+    seed_v = np.where(cls[1] == 1, 2 * h * h * v, 0.0)
+    t2 = time.perf_counter()
+    out = s.tape_backward(seed_u, seed_v, tol=tol, max_cycles=300)
+    t3 = time.perf_counter()
+    return {"workload": wk.name, "N": N, "steps": steps, "checkpoint_every": K, "tol": tol, "J": J,
+            "forward_ms": 1000 * (t1 - t0), "forward_cycles": fwd["cycles"], "backward_ms": 1000 * (t3 - t2),
+            "adjoint_cycles": out["stats"]["cycles"], "adjoint_solves": out["stats"]["outer"],
+            "backward_over_forward": (t3 - t2) / (t1 - t0), "dJdU": [float(x) for x in out["dU"]],
+            "grad_forcing_inf": float(max(np.abs(out["dfu"]).max(), np.abs(out["dfv"]).max()))}
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -82,8 +122,9 @@ def parse():
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-cycles", type=int, default=3)
+    ap.add_argument("--cpu-cycles", type=int, default=8)
     ap.add_argument("--no-kernel-timing", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--profile-kernel", action="store_true",
                     help="set up the N=1024 system, run 2 x 5 box-relaxation launches on the finest level and a "
                          "plain 64 MiB device copy (counter calibration), then exit (for rocprofv3 --pmc runs)")
@@ -177,8 +218,10 @@ def main():
         nbytes = sum(box_launch_bytes(cls, N, c) for c in range(5)) / 5.0
         achieved = nbytes / (avg_us * 1e-6) / 1e9
         roofline = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                    "frac": achieved / PEAK_HBM_GBS, "traffic": None, "kernel": "k_box<double> finest level",
-                    "bytes_per_launch": nbytes, "avg_launch_us": avg_us}
+                    "frac": achieved / PEAK_HBM_GBS, "traffic": BOX_TRAFFIC_BYTES if N == 1024 else None,
+                    "kernel": "k_box<double> finest level", "bytes_per_launch": nbytes, "avg_launch_us": avg_us,
+                    "traffic_gbs": BOX_TRAFFIC_BYTES / (avg_us * 1e-6) / 1e9 if N == 1024 else None,
+                    "traffic_source": BOX_TRAFFIC_SOURCE}
     # time to 1e-8 from x = 0 on the last step's system: FP64 cycles against FP32 cycles in FP64 refinement
     u, v, p, xi = solver.get_x()
     z = np.zeros((W, W))
@@ -197,6 +240,7 @@ def main():
     solver.set_x(u, v, p, xi)
     mixed_vs_fp64 = {"tol": args.tol, "fp64": ttt["fp64"], "mixed": ttt["mixed"],
                      "speedup": ttt["fp64"]["ms"] / ttt["mixed"]["ms"], "max_rel_diff_mixed_vs_fp64": diff}
+    adjoint = None if args.no_adjoint else adjoint_run(gpmg, wl)
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(wk, N, args.cpu_cycles)
@@ -219,6 +263,7 @@ def main():
                    "cycle_level_hbm_fraction": cyc_gbs / PEAK_HBM_GBS},
         "roofline": roofline,
         "mixed_vs_fp64_time_to_tol": mixed_vs_fp64,
+        "adjoint": adjoint,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
