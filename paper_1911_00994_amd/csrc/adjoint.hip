@@ -628,7 +628,7 @@ static void cycle_t(Ctx *ctx, int l) {
   hipStream_t s = ctx->stream;
   if (l == ctx->L - 1) {
     Vec<double> &A = ctx->adj[l];
-    k_coarse_t<<<ctx->nc, 64, 0, s>>>(ctx->c_A, ctx->c_map, ctx->c_bmap, ctx->nc, A.x, A.b);
+    k_coarse_t<<<ctx->nc, 64, 0, s>>>(ctx->c_inv, ctx->c_map, ctx->c_bmap, ctx->nc, A.x, A.b);
     k_zero_at<<<nblk(ctx->nc), TPB, 0, s>>>(ctx->c_map, ctx->nc, A.x);
     return;
   }

@@ -87,6 +87,8 @@ void gp_default_params(gp_params *p) {
   p->mixed_inner_cycles = 2;
   p->bnd_sweeps = 1;
   p->bnd_radius = 2;
+  p->fuse_small_levels = 1;
+  p->band_split_min = 3000;
 }
 
 const char *gp_strerror(gp_status st) {
@@ -160,6 +162,7 @@ void gp_destroy(gp_ctx *ctx) {
   dfree(ctx->d_flags);
   dfree(ctx->c_map);
   dfree(ctx->c_A);
+  dfree(ctx->c_B);
   dfree(ctx->c_bmap);
   dfree(ctx->c_work);
   for (int k = 0; k < 3; k++) {
@@ -185,12 +188,14 @@ gp_status gp_setup_grid(gp_ctx **out, int N, double Re, const gp_params *prm, vo
     gp_default_params(&P);
   if (!pow2(N) || N < 16 || !pow2(P.coarsest_n) || P.coarsest_n < 4 || P.coarsest_n > N / 2 || P.nu1 < 0 || P.nu2 < 0 ||
       P.gamma < 1 || P.lambda_ghost < 0 || P.march_max < 1 || P.ext_radius < 1 || !(Re > 0) || P.mixed_inner_cycles < 1 ||
-      P.bnd_sweeps < 0 || P.bnd_radius < 0)
+      P.bnd_sweeps < 0 || P.bnd_radius < 0 || P.band_split_min < 1)
     return GP_EINVAL;
   gp_ctx *ctx = new gp_ctx();
   ctx->N = N;
   ctx->Re = Re;
   ctx->prm = P;
+  ctx->small_cycles = P.fuse_small_levels ? 1 : 0;
+  ctx->band_split_min = P.band_split_min;
   ctx->stream = (hipStream_t)hip_stream;
   int L = 0;
   for (int n = N; n >= P.coarsest_n; n /= 2) {
@@ -264,6 +269,7 @@ gp_status gp_setup_grid(gp_ctx **out, int N, double Re, const gp_params *prm, vo
   Geo &C = ctx->geo[L - 1];
   ALLOC(ctx->c_map, (size_t)3 * C.WW + 2);
   ALLOC(ctx->c_A, (size_t)1024 * 1024);
+  ALLOC(ctx->c_B, (size_t)1024 * 1024);
   ALLOC(ctx->c_bmap, 1024);
   ALLOC(ctx->c_work, (size_t)4 * (3 * C.WW + 1) + 2048);
   int WW = ctx->geo[0].WW;

@@ -1048,28 +1048,41 @@ __global__ void k_coarse_fill(const uint8_t *cls, int N, int W, double h, double
 }
 
 
-// in-place Gauss-Jordan inversion with partial pivoting, one workgroup; A (n x n) becomes A^{-1}
+// Blocked Gauss-Jordan inversion with partial pivoting (ties: smallest row).  The matrix is kept in the current
+// row order (row interchanges applied); per panel of nb columns [k0, k0+nb):
+//  - k_gj_panel (one workgroup, the n x nb panel in LDS) runs the nb elimination steps on the panel columns: pivot
+//    search, interchange, the pivot row scaled, every other row eliminated, the pivot column replaced by the
+//    inverse column (-f/piv, and 1/piv at the pivot);
+//  - k_gj_trail applies the same nb steps to every other column at once: with P the nb pivot rows before the
+//    panel, new column = (rows outside P: old row through the interchanges) + K_new * old(P rows of the column),
+//    K_new being the panel's new columns.
+// The interchanges are not undone on the matrix: the column order of the result is folded into bmap, so that
+// x[map[q]] = sum_j A[q][j] b[bmap[j]] applies the inverse.
 constexpr int GJ_T = 1024;
-// Gauss-Jordan inversion with partial pivoting (ties: smallest row), in place, one workgroup.  Per pivot step the
-// two interchanged rows are staged in LDS and every other element is updated once (wavefront per row, lanes
-// along the row); the next pivot column is written to LDS by the update itself.  The row interchanges are not undone on the matrix: the column order of the result is folded into
-// bmap, so that x[map[q]] = sum_j A[q][j] b[bmap[j]] applies the inverse.
-__global__ void __launch_bounds__(GJ_T) k_gauss_jordan(double *A, int n, const int *__restrict__ map, int *bmap, int *fail) {
-  __shared__ double rowk[1024], rowp[1024], colbuf[2][1024];
+__global__ void __launch_bounds__(GJ_T) k_gj_panel(const double *__restrict__ Ain, double *Aout, int n, int k0, int nb,
+                                                   int *spv, int *perm, int *fail) {
+  extern __shared__ double pl[];  // panel, column-major: column j at pl[j * n]; then fcol (n), rowk (nb)
+  __shared__ int lperm[1024];
   __shared__ double wbest[GJ_T / 64];
-  __shared__ int wbi[GJ_T / 64], spv[1024], lab[1024];
+  __shared__ int wbi[GJ_T / 64];
   __shared__ int sp;
   __shared__ double sabs;
+  double *fcol = pl + (size_t)nb * n, *rowk = fcol + n;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  for (int i = tid; i < n; i += GJ_T) colbuf[0][i] = A[(size_t)i * n];
+  if (*fail) return;  // an earlier panel found no pivot
+  for (int e = tid; e < n * nb; e += GJ_T) {
+    int i = e / nb, j = e - i * nb;
+    pl[j * n + i] = Ain[(size_t)i * n + k0 + j];
+  }
+  for (int i = tid; i < n; i += GJ_T) lperm[i] = i;
   __syncthreads();
-  for (int k = 0; k < n; k++) {
-    const double *colk = colbuf[k & 1];
-    double *coln = colbuf[(k + 1) & 1];
+  for (int j = 0; j < nb; j++) {
+    const int k = k0 + j;
+    double *cj = pl + (size_t)j * n;
     double best = -1;
     int bi = n;
     for (int i = k + tid; i < n; i += GJ_T) {
-      double av = fabs(colk[i]);
+      double av = fabs(cj[i]);
       if (av > best) {
         best = av;
         bi = i;
@@ -1090,15 +1103,15 @@ __global__ void __launch_bounds__(GJ_T) k_gauss_jordan(double *A, int n, const i
     __syncthreads();
     if (tid == 0) {
       double bb = -1;
-      int p = n;
+      int pp = n;
       for (int w = 0; w < GJ_T / 64; w++)
-        if (wbest[w] > bb || (wbest[w] == bb && wbi[w] < p)) {
+        if (wbest[w] > bb || (wbest[w] == bb && wbi[w] < pp)) {
           bb = wbest[w];
-          p = wbi[w];
+          pp = wbi[w];
         }
-      sp = p;
+      sp = pp;
       sabs = bb;
-      spv[k] = p;
+      spv[k] = pp;
     }
     __syncthreads();
     const int p = sp;
@@ -1106,33 +1119,54 @@ __global__ void __launch_bounds__(GJ_T) k_gauss_jordan(double *A, int n, const i
       if (tid == 0) *fail = 1;
       return;
     }
-    for (int c = tid; c < n; c += GJ_T) {
-      rowk[c] = A[(size_t)k * n + c];
-      rowp[c] = A[(size_t)p * n + c];
-    }
-    __syncthreads();
-    const double inv_p = 1.0 / rowp[k];
-    // after the interchange row k holds old row p and row p holds old row k
-    for (int i = wv; i < n; i += GJ_T / 64) {
-      const int src = (i == k) ? p : (i == p ? k : i);
-      const double f = colk[src];
-      for (int c = lane; c < n; c += 64) {
-        const double nk = (c == k) ? inv_p : rowp[c] * inv_p;
-        double out;
-        if (i == k) {
-          out = nk;
-        } else {
-          const double a = (src == k) ? rowk[c] : A[(size_t)i * n + c];
-          out = (c == k) ? -f * inv_p : a - f * nk;
-        }
-        A[(size_t)i * n + c] = out;
-        if (c == k + 1) coln[i] = out;
+    if (p != k) {
+      for (int jj = tid; jj < nb; jj += GJ_T) {
+        double t = pl[jj * n + k];
+        pl[jj * n + k] = pl[jj * n + p];
+        pl[jj * n + p] = t;
+      }
+      if (tid == 0) {
+        int t = lperm[k];
+        lperm[k] = lperm[p];
+        lperm[p] = t;
       }
     }
     __syncthreads();
+    const double inv = 1.0 / cj[k];
+    for (int i = tid; i < n; i += GJ_T) fcol[i] = cj[i];
+    for (int jj = tid; jj < nb; jj += GJ_T) rowk[jj] = (jj == j) ? inv : pl[jj * n + k] * inv;
+    __syncthreads();
+    for (int e = tid; e < n * nb; e += GJ_T) {
+      int jj = e / n, i = e - jj * n;
+      if (i == k)
+        pl[e] = rowk[jj];
+      else
+        pl[e] = (jj == j) ? -fcol[i] * inv : pl[e] - fcol[i] * rowk[jj];
+    }
+    __syncthreads();
   }
-  // undoing the interchanges as column interchanges in reverse order puts result column c at column lab[c]
-  if (tid == 0) {
+  for (int e = tid; e < n * nb; e += GJ_T) {
+    int i = e / nb, j = e - i * nb;
+    Aout[(size_t)i * n + k0 + j] = pl[j * n + i];
+  }
+  for (int i = tid; i < n; i += GJ_T) perm[i] = lperm[i];
+}
+__global__ void k_gj_trail(const double *__restrict__ Ain, double *Aout, int n, int k0, int nb, const int *__restrict__ perm,
+                           const int *__restrict__ fail) {
+  long e = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (e >= (long)n * n || *fail) return;
+  int i = (int)(e / n), c = (int)(e - (long)i * n);
+  if (c >= k0 && c < k0 + nb) return;
+  double s = (i < k0 || i >= k0 + nb) ? Ain[(size_t)perm[i] * n + c] : 0.0;
+  for (int t = 0; t < nb; t++) s += Aout[(size_t)i * n + k0 + t] * Ain[(size_t)perm[k0 + t] * n + c];
+  Aout[(size_t)i * n + c] = s;
+}
+// undoing the interchanges as column interchanges in reverse order puts result column c at column lab[c]
+__global__ void __launch_bounds__(GJ_T) k_gj_finish(const int *__restrict__ spv, int n, const int *__restrict__ map,
+                                                    int *bmap, const int *__restrict__ fail) {
+  __shared__ int lab[1024];
+  if (*fail) return;
+  if (threadIdx.x == 0) {
     for (int c = 0; c < n; c++) lab[c] = c;
     for (int k = n - 1; k >= 0; k--) {
       int t = lab[k];
@@ -1141,7 +1175,7 @@ __global__ void __launch_bounds__(GJ_T) k_gauss_jordan(double *A, int n, const i
     }
   }
   __syncthreads();
-  for (int c = tid; c < n; c += GJ_T) bmap[lab[c]] = map[c];
+  for (int c = threadIdx.x; c < n; c += GJ_T) bmap[lab[c]] = map[c];
 }
 
 gp_status coarse_factor(Ctx *ctx) {
@@ -1162,7 +1196,21 @@ gp_status coarse_factor(Ctx *ctx) {
   k_coarse_fill<<<nblk(ctx->nc), TPB, 0, s>>>(G.cls, G.N, W, G.h, a, d, ctx->c_map, inv, ctx->nc, row_of, G.g_col, G.g_w,
                                              G.mp, ctx->c_A);
   GP_HIP(hipMemsetAsync(ctx->d_flags + 6, 0, sizeof(int), s));
-  k_gauss_jordan<<<1, GJ_T, 0, s>>>(ctx->c_A, ctx->nc, ctx->c_map, ctx->c_bmap, ctx->d_flags + 6);
+  {
+    const int n = ctx->nc;
+    int nb = std::min(32, std::max(1, 15000 / n - 1));
+    int *spv = (int *)(ctx->c_work) + 2 * (P + 1), *perm = spv + 1024;
+    double *Ain = ctx->c_A, *Aout = ctx->c_B;
+    for (int k0 = 0; k0 < n; k0 += nb) {
+      int w = std::min(nb, n - k0);
+      size_t lds = ((size_t)w * n + n + w) * sizeof(double);
+      k_gj_panel<<<1, GJ_T, lds, s>>>(Ain, Aout, n, k0, w, spv, perm, ctx->d_flags + 6);
+      k_gj_trail<<<nblk((long)n * n), TPB, 0, s>>>(Ain, Aout, n, k0, w, perm, ctx->d_flags + 6);
+      std::swap(Ain, Aout);
+    }
+    ctx->c_inv = Ain;
+    k_gj_finish<<<1, GJ_T, 0, s>>>(spv, n, ctx->c_map, ctx->c_bmap, ctx->d_flags + 6);
+  }
   GP_HIP(hipGetLastError());
   st = read_flags(ctx, hf);
   if (st) return st;

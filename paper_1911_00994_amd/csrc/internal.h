@@ -128,7 +128,8 @@ struct Ctx {
   int nc = 0;                       // number of active unknowns on the coarsest level
   int *c_map = nullptr;             // nc: global index of each active unknown
   int *c_bmap = nullptr;            // nc: right-hand side index for each column of the stored inverse
-  double *c_A = nullptr;            // nc*nc matrix, then overwritten by its inverse
+  double *c_A = nullptr, *c_B = nullptr;  // nc*nc matrix and a second buffer (the blocked inversion alternates)
+  double *c_inv = nullptr;          // the buffer holding the inverse (c_A or c_B)
   double *c_work = nullptr;         // nc*nc scratch
   int c_ok = 0;
   // time-stepping state (finest level)
@@ -138,6 +139,8 @@ struct Ctx {
   double *fwork = nullptr;          // 3*WW staging for inputs
   int last_cycles = 0;
   size_t max_lds = 65536;           // dynamic LDS a workgroup may use on this device
+  int small_cycles = 1;             // run the levels with N <= 32 as one workgroup when they fit in LDS
+  int band_split_min = 3000;        // bands with at least this many cells use device-wide launches
 };
 
 // error handling

@@ -104,6 +104,17 @@ __global__ void __launch_bounds__(TPB) k_box(int N, int W, double h, double a, d
   box_update<T>(N, W, h, a, d, cls, x, b, i, j);
 }
 
+// box relaxation of the band cells band[lo, hi) (one colour), spread over the whole device
+template <typename T>
+__global__ void __launch_bounds__(TPB) k_box_list(int N, int W, double h, double a, double d, const uint8_t *__restrict__ cls,
+                                                  T *__restrict__ x, const T *__restrict__ b, const int *__restrict__ band,
+                                                  int lo, int hi) {
+  int t = lo + blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= hi) return;
+  int cell = band[t];
+  box_update<T>(N, W, h, a, d, cls, x, b, cell % N, cell / N);
+}
+
 // fictitious-time relaxation of every ghost row at once (eq. ghostrelax, Jacobi): w += dtau (g - B w)
 template <typename T>
 __global__ void k_ghost_a(const int *__restrict__ pt, const int *__restrict__ col, const double *__restrict__ w,
@@ -488,32 +499,37 @@ __device__ __forceinline__ void max_abs(unsigned long long *m, double v) {
   if ((threadIdx.x & 63) == 0 && a) atomicMax(m, a);
 }
 
+// residual of the point rows (internal momentum and continuity rows, wall identity rows; 0 for every other
+// point, whose row, if any, is a ghost row handled by k_resid_ghost)
 template <typename T>
-__global__ void __launch_bounds__(TPB) k_resid_pts(int N, int W, double h, double a, double d,
-                                                   const uint8_t *__restrict__ cls, const T *__restrict__ x,
-                                                   const T *__restrict__ b, T *__restrict__ r, unsigned long long *rmax) {
+__device__ __forceinline__ double resid_point(int W, double h, double a, double d, const uint8_t *__restrict__ cls,
+                                              const T *__restrict__ x, const T *__restrict__ b, int t) {
   const int WW = W * W;
-  int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= 3 * WW) return;
   uint8_t c = cls[t];
-  double res = 0;
   if (c == K_INT) {
     int g = t / WW, q = t - g * WW;
     const T *u = x, *v = x + WW, *p = x + 2 * WW;
     double ih = 1.0 / h;
     if (g == 0)
-      res = (double)b[t] - (d * (double)u[q] - a * ((double)u[q - 1] + (double)u[q + 1] + (double)u[q - W] + (double)u[q + W]) +
-                            ((double)p[q] - (double)p[q - 1]) * ih);
-    else if (g == 1)
-      res = (double)b[t] - (d * (double)v[q] - a * ((double)v[q - 1] + (double)v[q + 1] + (double)v[q - W] + (double)v[q + W]) +
-                            ((double)p[q] - (double)p[q - W]) * ih);
-    else
-      res = (double)b[t] - (((double)u[q + 1] - (double)u[q] + (double)v[q + W] - (double)v[q]) * ih - (double)x[3 * WW]);
-  } else if (c == K_WALLD) {
-    res = (double)b[t] - (double)x[t];
+      return (double)b[t] - (d * (double)u[q] - a * ((double)u[q - 1] + (double)u[q + 1] + (double)u[q - W] + (double)u[q + W]) +
+                             ((double)p[q] - (double)p[q - 1]) * ih);
+    if (g == 1)
+      return (double)b[t] - (d * (double)v[q] - a * ((double)v[q - 1] + (double)v[q + 1] + (double)v[q - W] + (double)v[q + W]) +
+                             ((double)p[q] - (double)p[q - W]) * ih);
+    return (double)b[t] - (((double)u[q + 1] - (double)u[q] + (double)v[q + W] - (double)v[q]) * ih - (double)x[3 * WW]);
   }
-  r[t] = (T)res;
+  if (c == K_WALLD) return (double)b[t] - (double)x[t];
+  return 0.0;
+}
+template <typename T>
+__global__ void __launch_bounds__(TPB) k_resid_pts(int N, int W, double h, double a, double d,
+                                                   const uint8_t *__restrict__ cls, const T *__restrict__ x,
+                                                   const T *__restrict__ b, T *__restrict__ r, unsigned long long *rmax) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= 3 * W * W) return;
+  r[t] = (T)resid_point<T>(W, h, a, d, cls, x, b, t);
   (void)N;
+  (void)rmax;
 }
 // variant with the max norm (all lanes of a wavefront take part in the reduction)
 __device__ __forceinline__ void block_max_atomic(unsigned long long *m, double v) {
@@ -531,7 +547,6 @@ __device__ __forceinline__ void block_max_atomic(unsigned long long *m, double v
     if (z) atomicMax(m, z);
   }
 }
-
 template <typename T>
 __global__ void __launch_bounds__(TPB) k_resid_pts_norm(int N, int W, double h, double a, double d,
                                                         const uint8_t *__restrict__ cls, const T *__restrict__ x,
@@ -539,23 +554,7 @@ __global__ void __launch_bounds__(TPB) k_resid_pts_norm(int N, int W, double h, 
   const int WW = W * W;
   double mx = 0;
   for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < 3 * WW; t += gridDim.x * blockDim.x) {
-    double res = 0;
-    uint8_t c = cls[t];
-    if (c == K_INT) {
-      int g = t / WW, q = t - g * WW;
-      const T *u = x, *v = x + WW, *p = x + 2 * WW;
-      double ih = 1.0 / h;
-      if (g == 0)
-        res = (double)b[t] - (d * (double)u[q] - a * ((double)u[q - 1] + (double)u[q + 1] + (double)u[q - W] + (double)u[q + W]) +
-                              ((double)p[q] - (double)p[q - 1]) * ih);
-      else if (g == 1)
-        res = (double)b[t] - (d * (double)v[q] - a * ((double)v[q - 1] + (double)v[q + 1] + (double)v[q - W] + (double)v[q + W]) +
-                              ((double)p[q] - (double)p[q - W]) * ih);
-      else
-        res = (double)b[t] - (((double)u[q + 1] - (double)u[q] + (double)v[q + W] - (double)v[q]) * ih - (double)x[3 * WW]);
-    } else if (c == K_WALLD) {
-      res = (double)b[t] - (double)x[t];
-    }
+    double res = resid_point<T>(W, h, a, d, cls, x, b, t);
     r[t] = (T)res;
     double ar = fabs(res);
     mx = (ar > mx || ar != ar) ? ar : mx;
@@ -622,22 +621,15 @@ __global__ void k_fill(T *x, long n, T val) {
 // ---------------------------------------------------------------------------------------------------------
 // boundary-aware restriction (eqs. restop, restop5)
 // ---------------------------------------------------------------------------------------------------------
-template <typename TF, typename TC>
-__global__ void __launch_bounds__(TPB) k_restrict(int Nf, int Wf, const uint8_t *__restrict__ clsf, const TF *__restrict__ rf,
-                                                  int Nc, int Wc, const uint8_t *__restrict__ clsc, TC *__restrict__ bc) {
+// boundary-aware restriction of the fine residual to coarse entry t (t = 3 WWc is the mean row: 0)
+template <typename TF>
+__device__ __forceinline__ double restrict_value(int Nf, int Wf, const uint8_t *__restrict__ clsf, const TF *__restrict__ rf,
+                                                 int Nc, int Wc, const uint8_t *__restrict__ clsc, int t) {
   const int WWc = Wc * Wc, WWf = Wf * Wf;
-  int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t == 3 * WWc) {
-    bc[t] = (TC)0;
-    return;
-  }
-  if (t > 3 * WWc) return;
+  if (t == 3 * WWc) return 0.0;
   int g = t / WWc, q = t - g * WWc, jc = q / Wc - 1, ic = q % Wc - 1;
   uint8_t cc = clsc[t];
-  if (!(cc == K_INT || cc == K_GHOST || cc == K_WALLG)) {
-    bc[t] = (TC)0;
-    return;
-  }
+  if (!(cc == K_INT || cc == K_GHOST || cc == K_WALLG)) return 0.0;
   int fi[6], fj[6];
   double fw[6];
   int m = 0;
@@ -683,7 +675,14 @@ __global__ void __launch_bounds__(TPB) k_restrict(int Nf, int Wf, const uint8_t 
     } else
       all = false;
   }
-  bc[t] = (TC)(all ? sw : (cnt ? sa / cnt : 0.0));
+  return all ? sw : (cnt ? sa / cnt : 0.0);
+}
+template <typename TF, typename TC>
+__global__ void __launch_bounds__(TPB) k_restrict(int Nf, int Wf, const uint8_t *__restrict__ clsf, const TF *__restrict__ rf,
+                                                  int Nc, int Wc, const uint8_t *__restrict__ clsc, TC *__restrict__ bc) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t > 3 * Wc * Wc) return;
+  bc[t] = (TC)restrict_value<TF>(Nf, Wf, clsf, rf, Nc, Wc, clsc, t);
 }
 
 // extension values: quadratic extrapolation from the sources
@@ -699,18 +698,15 @@ __global__ void k_ext_fill(const int *__restrict__ e_pt, const int *__restrict__
 }
 
 // bilinear prolongation of the coarse correction to fine internal and ghost points, x += e (Sect. 4.3)
-template <typename TC, typename TF>
-__global__ void __launch_bounds__(TPB) k_prolong(int Nf, int Wf, const uint8_t *__restrict__ clsf, TF *__restrict__ xf,
-                                                 int Nc, int Wc, const TC *__restrict__ xc) {
+// bilinear prolongation of the coarse correction to fine entry t (internal, ghost, extrapolated and wall-ghost
+// points and xi; 0 elsewhere), coarse pressure mirrored outside the box
+template <typename TC>
+__device__ __forceinline__ double prolong_value(int Nf, int Wf, const uint8_t *__restrict__ clsf, int Nc, int Wc,
+                                                const TC *__restrict__ xc, int t) {
   const int WWf = Wf * Wf, WWc = Wc * Wc;
-  int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t == 3 * WWf) {
-    xf[t] = (TF)((double)xf[t] + (double)xc[3 * WWc]);
-    return;
-  }
-  if (t > 3 * WWf) return;
+  if (t == 3 * WWf) return (double)xc[3 * WWc];
   uint8_t c = clsf[t];
-  if (!(c == K_INT || c == K_GHOST || c == K_GHOSTX || c == K_WALLG)) return;
+  if (!(c == K_INT || c == K_GHOST || c == K_GHOSTX || c == K_WALLG)) return 0.0;
   int g = t / WWf, q = t - g * WWf, j = q / Wf - 1, i = q % Wf - 1;
   int xi_[2], yi_[2];
   double xw[2], yw[2];
@@ -772,7 +768,15 @@ __global__ void __launch_bounds__(TPB) k_prolong(int Nf, int Wf, const uint8_t *
       if (ic < -1 || ic > Nc || jc < -1 || jc > Nc) continue;
       e += xw[bb] * yw[aa] * (double)xc[g * WWc + pidx(Wc, ic, jc)];
     }
-  xf[t] = (TF)((double)xf[t] + e);
+  return e;
+}
+template <typename TC, typename TF>
+__global__ void __launch_bounds__(TPB) k_prolong(int Nf, int Wf, const uint8_t *__restrict__ clsf, TF *__restrict__ xf,
+                                                 int Nc, int Wc, const TC *__restrict__ xc) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t > 3 * Wf * Wf) return;
+  double e = prolong_value<TC>(Nf, Wf, clsf, Nc, Wc, xc, t);
+  if (e != 0.0 || t == 3 * Wf * Wf) xf[t] = (TF)((double)xf[t] + e);
 }
 
 // exact coarsest solve with the stored inverse: x[map[q]] = sum_r Ainv[q][r] b[map[r]] (one wavefront per row)
@@ -785,6 +789,190 @@ __global__ void __launch_bounds__(64) k_coarse_apply(const double *__restrict__ 
   for (int r = threadIdx.x; r < nc; r += 64) s += Ainv[(size_t)q * nc + r] * (double)b[bmap[r]];
   for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
   if (threadIdx.x == 0) x[map[q]] = (T)s;
+}
+
+
+// ---------------------------------------------------------------------------------------------------------
+// the small levels in one workgroup: the whole V cycle from level l0 (N <= 32 at the default sizes) down to the
+// coarsest, with x, b, r and the classes of every level in LDS.  Same operations and arithmetic as the per-level
+// kernels (the box update, residual, restriction, prolongation and coarsest product are shared); xi is taken
+// from the direct sum over the internal cells.
+// ---------------------------------------------------------------------------------------------------------
+constexpr int SC_T = 1024;
+constexpr int SC_MAXL = 4;
+struct SmallLevel {
+  int N, W, n, ng, ne, nband, mp;
+  double h, a, d;
+  const uint8_t *cls;
+  const int *g_pt, *g_col, *e_pt, *e_src, *band;
+  const double *g_w, *g_dtau, *e_w;
+  int boff[6];
+  int ox, ob, orr, oc;  // LDS offsets (bytes) of x, b, r and the classes
+  int ogw, ogc, ogp, ogd;  // LDS offsets of the ghost rows, field-major: 9 weights, 9 columns, point, dtau
+};
+struct SmallCycle {
+  int nl;  // fused levels; the last one is the coarsest
+  SmallLevel lv[SC_MAXL];
+  const double *Ainv;
+  const int *map, *bmap;
+  int nc, nu1, nu2, lambda, bnd, onv;
+};
+
+__device__ double sc_block_sum(double v) {
+  __shared__ double s[SC_T / 64];
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) s[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double t = 0;
+  for (int q = 0; q < SC_T / 64; q++) t += s[q];
+  return t;
+}
+
+// ghost rows of a level staged in LDS, field-major
+struct ScRows {
+  const double *w, *dt;
+  const int *col, *pt;
+};
+
+template <typename T>
+__device__ void sc_ghosts(const SmallLevel &L, const ScRows &G, T *x, const T *b, double *nv, int lambda) {
+  const int ng = L.ng;
+  for (int it = 0; it < lambda; it++) {
+    for (int r = threadIdx.x; r < ng; r += SC_T) {
+      double sum = 0;
+#pragma unroll
+      for (int z = 0; z < 9; z++) sum += G.w[z * ng + r] * (double)x[G.col[z * ng + r]];
+      int k = G.pt[r];
+      nv[r] = (double)x[k] + G.dt[r] * ((double)b[k] - sum);
+    }
+    __syncthreads();
+    for (int r = threadIdx.x; r < ng; r += SC_T) x[G.pt[r]] = (T)nv[r];
+    __syncthreads();
+  }
+}
+
+template <typename T>
+__device__ void sc_relax(const SmallCycle &P, const SmallLevel &L, const ScRows &G, T *x, const T *b, const uint8_t *cls,
+                         double *nv) {
+  const int K = L.N / 5 + 1;
+  for (int c = 0; c < 5; c++) {
+    for (int t = threadIdx.x; t < K * L.N; t += SC_T) {
+      int j = t / K, kk = t - j * K;
+      int i = ((c - 2 * j) % 5 + 5) % 5 + 5 * kk;
+      if (i < L.N) box_update<T>(L.N, L.W, L.h, L.a, L.d, cls, x, b, i, j);
+    }
+    __syncthreads();
+  }
+  sc_ghosts<T>(L, G, x, b, nv, P.lambda);
+  if (P.bnd > 0 && L.nband > 0) {
+    for (int q = 0; q < P.bnd; q++) {
+      for (int c = 0; c < 5; c++) {
+        for (int t = L.boff[c] + threadIdx.x; t < L.boff[c + 1]; t += SC_T) {
+          int cell = L.band[t];
+          box_update<T>(L.N, L.W, L.h, L.a, L.d, cls, x, b, cell % L.N, cell / L.N);
+        }
+        __syncthreads();
+      }
+      sc_ghosts<T>(L, G, x, b, nv, P.lambda);
+    }
+  }
+  // xi <- mean over internal cells of (div u - g)
+  const int WW = L.W * L.W;
+  double s = 0;
+  for (int t = threadIdx.x; t < L.N * L.N; t += SC_T) {
+    int i = t % L.N, j = t / L.N, c = pidx(L.W, i, j);
+    if (cls[2 * WW + c] != K_INT) continue;
+    s += ((double)x[c + 1] - (double)x[c] + (double)x[WW + c + L.W] - (double)x[WW + c]) / L.h - (double)b[2 * WW + c];
+  }
+  s = sc_block_sum(s);
+  if (threadIdx.x == 0) x[3 * WW] = (T)(s / L.mp);
+  __syncthreads();
+}
+
+template <typename T>
+__global__ void __launch_bounds__(SC_T) k_small_cycle(SmallCycle P, T *xg, const T *__restrict__ bg) {
+  extern __shared__ unsigned char lds_raw[];
+  auto X = [&](int m) { return reinterpret_cast<T *>(lds_raw + P.lv[m].ox); };
+  auto B = [&](int m) { return reinterpret_cast<T *>(lds_raw + P.lv[m].ob); };
+  auto R = [&](int m) { return reinterpret_cast<T *>(lds_raw + P.lv[m].orr); };
+  auto C = [&](int m) { return reinterpret_cast<uint8_t *>(lds_raw + P.lv[m].oc); };
+  double *nv = reinterpret_cast<double *>(lds_raw + P.onv);
+  auto GR = [&](int m) {
+    const SmallLevel &L = P.lv[m];
+    return ScRows{reinterpret_cast<const double *>(lds_raw + L.ogw), reinterpret_cast<const double *>(lds_raw + L.ogd),
+                  reinterpret_cast<const int *>(lds_raw + L.ogc), reinterpret_cast<const int *>(lds_raw + L.ogp)};
+  };
+  const int tid = threadIdx.x;
+  for (int m = 0; m < P.nl; m++) {
+    const SmallLevel &L = P.lv[m];
+    for (int t = tid; t < 3 * L.W * L.W; t += SC_T) C(m)[t] = L.cls[t];
+    if (m < P.nl - 1) {
+      double *gw = reinterpret_cast<double *>(lds_raw + L.ogw), *gd = reinterpret_cast<double *>(lds_raw + L.ogd);
+      int *gc = reinterpret_cast<int *>(lds_raw + L.ogc), *gp = reinterpret_cast<int *>(lds_raw + L.ogp);
+      for (int e = tid; e < 9 * L.ng; e += SC_T) {  // contiguous reads of the row-major tables
+        int r = e / 9, z = e - 9 * r;
+        gw[z * L.ng + r] = L.g_w[e];
+        gc[z * L.ng + r] = L.g_col[e];
+      }
+      for (int r = tid; r < L.ng; r += SC_T) {
+        gp[r] = L.g_pt[r];
+        gd[r] = L.g_dtau[r];
+      }
+    }
+    for (int t = tid; t < L.n; t += SC_T) {
+      X(m)[t] = m == 0 ? xg[t] : (T)0;
+      B(m)[t] = m == 0 ? bg[t] : (T)0;
+    }
+  }
+  __syncthreads();
+  const int bot = P.nl - 1;
+  for (int m = 0; m < bot; m++) {
+    const SmallLevel &L = P.lv[m], &Cl = P.lv[m + 1];
+    const ScRows G = GR(m);
+    for (int q = 0; q < P.nu1; q++) sc_relax<T>(P, L, G, X(m), B(m), C(m), nv);
+    for (int t = tid; t < 3 * L.W * L.W; t += SC_T) R(m)[t] = (T)resid_point<T>(L.W, L.h, L.a, L.d, C(m), X(m), B(m), t);
+    __syncthreads();
+    for (int r = tid; r < L.ng; r += SC_T) {
+      double sum = 0;
+#pragma unroll
+      for (int z = 0; z < 9; z++) sum += G.w[z * L.ng + r] * (double)X(m)[G.col[z * L.ng + r]];
+      int k = G.pt[r];
+      R(m)[k] = (T)((double)B(m)[k] - sum);
+    }
+    __syncthreads();
+    for (int t = tid; t <= 3 * Cl.W * Cl.W; t += SC_T)
+      B(m + 1)[t] = (T)restrict_value<T>(L.N, L.W, C(m), R(m), Cl.N, Cl.W, C(m + 1), t);
+    __syncthreads();
+  }
+  // coarsest: x[map[q]] = sum_j Ainv[q][j] b[bmap[j]], one wavefront per row
+  {
+    const int lane = tid & 63;
+    for (int q = tid >> 6; q < P.nc; q += SC_T / 64) {
+      double s = 0;
+      for (int r = lane; r < P.nc; r += 64) s += P.Ainv[(size_t)q * P.nc + r] * (double)B(bot)[P.bmap[r]];
+      for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
+      if (lane == 0) X(bot)[P.map[q]] = (T)s;
+    }
+    __syncthreads();
+  }
+  for (int m = bot - 1; m >= 0; m--) {
+    const SmallLevel &L = P.lv[m], &Cl = P.lv[m + 1];
+    T *xc = X(m + 1);
+    for (int e = tid; e < Cl.ne; e += SC_T) {
+      if (Cl.e_src[3 * e] < 0) continue;
+      xc[Cl.e_pt[e]] = (T)(Cl.e_w[3 * e] * (double)xc[Cl.e_src[3 * e]] + Cl.e_w[3 * e + 1] * (double)xc[Cl.e_src[3 * e + 1]] +
+                           Cl.e_w[3 * e + 2] * (double)xc[Cl.e_src[3 * e + 2]]);
+    }
+    __syncthreads();
+    for (int t = tid; t <= 3 * L.W * L.W; t += SC_T) {
+      double e = prolong_value<T>(L.N, L.W, C(m), Cl.N, Cl.W, xc, t);
+      if (e != 0.0 || t == 3 * L.W * L.W) X(m)[t] = (T)((double)X(m)[t] + e);
+    }
+    __syncthreads();
+    for (int q = 0; q < P.nu2; q++) sc_relax<T>(P, L, GR(m), X(m), B(m), C(m), nv);
+  }
+  for (int t = tid; t < P.lv[0].n; t += SC_T) xg[t] = X(0)[t];
 }
 
 // ---------------------------------------------------------------------------------------------------------
@@ -834,6 +1022,25 @@ static void relax(Ctx *ctx, int l) {
   for (int col = 0; col < 5; col++) k_box<T><<<box_grid(K, G.N), TPB, 0, s>>>(G.N, G.W, G.h, a, d, G.cls, V.x, V.b, col);
   const bool band = ctx->prm.bnd_sweeps > 0 && G.nband > 0;
   const size_t lds_bytes = (size_t)G.nreg * sizeof(T);
+  if (band && G.nband >= ctx->band_split_min) {
+    // a large band: ghost sweeps and band colours as device-wide launches
+    auto sweeps = [&]() {
+      for (int it = 0; it < ctx->prm.lambda_ghost; it++) {
+        k_ghost_a<T><<<nblk(G.ng), TPB, 0, s>>>(G.g_pt, G.g_col, G.g_w, G.g_dtau, G.ng, V.x, V.b, ctx->gtmp);
+        k_ghost_b<T><<<nblk(G.ng), TPB, 0, s>>>(G.g_pt, G.ng, ctx->gtmp, V.x);
+      }
+    };
+    if (G.ng) sweeps();
+    for (int q = 0; q < ctx->prm.bnd_sweeps; q++) {
+      for (int c = 0; c < 5; c++) {
+        int lo = G.hband_off[c], hi = G.hband_off[c + 1];
+        if (hi > lo) k_box_list<T><<<nblk(hi - lo), TPB, 0, s>>>(G.N, G.W, G.h, a, d, G.cls, V.x, V.b, G.band, lo, hi);
+      }
+      if (G.ng) sweeps();
+    }
+    k_xi_faces<T><<<1, BAND_T, 0, s>>>(G.WW, G.h, V.x, G.f_code, G.nf, ctx->d_lev + l, G.d_mp);
+    return;
+  }
   if (band && G.lds_ok && lds_bytes + 1024 <= ctx->max_lds) {
     // wall ghosts, body ghosts, band boxes and xi in one workgroup
     int nwb = (G.nwg + BAND_T - 1) / BAND_T;
@@ -892,7 +1099,67 @@ template <typename T>
 static void coarse_solve(Ctx *ctx) {
   int l = ctx->L - 1;
   Vec<T> &V = vec<T>(ctx, l);
-  k_coarse_apply<T><<<ctx->nc, 64, 0, ctx->stream>>>(ctx->c_A, ctx->c_map, ctx->c_bmap, ctx->nc, V.b, V.x);
+  k_coarse_apply<T><<<ctx->nc, 64, 0, ctx->stream>>>(ctx->c_inv, ctx->c_map, ctx->c_bmap, ctx->nc, V.b, V.x);
+}
+
+// the V cycle from level l down in one workgroup, if those levels fit in LDS (gamma = 1 only)
+template <typename T>
+static size_t small_cycle_setup(Ctx *ctx, int l, SmallCycle &P) {
+  if (ctx->prm.gamma != 1 || ctx->nc <= 0 || !ctx->c_ok) return 0;
+  P.nl = ctx->L - l;
+  if (P.nl < 2 || P.nl > SC_MAXL) return 0;
+  size_t off = 0;
+  int maxng = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off += (bytes + 15) & ~(size_t)15;
+    return (int)o;
+  };
+  for (int m = 0; m < P.nl; m++) {
+    Geo &G = ctx->geo[l + m];
+    SmallLevel &S = P.lv[m];
+    S.N = G.N;
+    S.W = G.W;
+    S.n = G.n;
+    S.ng = G.ng;
+    S.ne = G.ne;
+    S.nband = (ctx->prm.bnd_sweeps > 0) ? G.nband : 0;
+    S.mp = G.mp;
+    S.h = G.h;
+    S.a = ctx->alpha / (G.h * G.h);
+    S.d = 1.0 + 4.0 * S.a;
+    S.cls = G.cls;
+    S.g_pt = G.g_pt;
+    S.g_col = G.g_col;
+    S.g_w = G.g_w;
+    S.g_dtau = G.g_dtau;
+    S.e_pt = G.e_pt;
+    S.e_src = G.e_src;
+    S.e_w = G.e_w;
+    S.band = G.band;
+    for (int c = 0; c < 6; c++) S.boff[c] = G.hband_off[c];
+    const bool bottom = m == P.nl - 1;
+    S.ox = take((size_t)G.n * sizeof(T));
+    S.ob = take((size_t)G.n * sizeof(T));
+    S.orr = bottom ? 0 : take((size_t)G.n * sizeof(T));
+    S.oc = take((size_t)3 * G.WW);
+    S.ogw = bottom ? 0 : take((size_t)9 * G.ng * sizeof(double));
+    S.ogd = bottom ? 0 : take((size_t)G.ng * sizeof(double));
+    S.ogc = bottom ? 0 : take((size_t)9 * G.ng * sizeof(int));
+    S.ogp = bottom ? 0 : take((size_t)G.ng * sizeof(int));
+    if (!bottom) maxng = std::max(maxng, G.ng);
+  }
+  P.onv = take((size_t)maxng * sizeof(double));
+  if (off + 2048 > ctx->max_lds) return 0;
+  P.Ainv = ctx->c_inv;
+  P.map = ctx->c_map;
+  P.bmap = ctx->c_bmap;
+  P.nc = ctx->nc;
+  P.nu1 = ctx->prm.nu1;
+  P.nu2 = ctx->prm.nu2;
+  P.lambda = ctx->prm.lambda_ghost;
+  P.bnd = ctx->prm.bnd_sweeps;
+  return off;
 }
 
 template <typename T>
@@ -900,6 +1167,15 @@ static void cycle(Ctx *ctx, int l) {
   if (l == ctx->L - 1) {
     coarse_solve<T>(ctx);
     return;
+  }
+  if (ctx->small_cycles && ctx->geo[l].N <= 32) {
+    SmallCycle P{};
+    size_t lds = small_cycle_setup<T>(ctx, l, P);
+    if (lds) {
+      Vec<T> &V = vec<T>(ctx, l);
+      k_small_cycle<T><<<1, SC_T, lds, ctx->stream>>>(P, V.x, V.b);
+      return;
+    }
   }
   Geo &F = ctx->geo[l], &C = ctx->geo[l + 1];
   Vec<T> &VF = vec<T>(ctx, l), &VC = vec<T>(ctx, l + 1);

@@ -33,7 +33,8 @@ class GpParams(ctypes.Structure):
                 ("coarsest_n", ctypes.c_int), ("march_max", ctypes.c_int), ("ext_radius", ctypes.c_int),
                 ("dtau_dir", ctypes.c_double), ("dtau_neu_over_h", ctypes.c_double),
                 ("bisect_eps_over_h", ctypes.c_double), ("cg_min", ctypes.c_double),
-                ("mixed_inner_cycles", ctypes.c_int), ("bnd_sweeps", ctypes.c_int), ("bnd_radius", ctypes.c_int)]
+                ("mixed_inner_cycles", ctypes.c_int), ("bnd_sweeps", ctypes.c_int), ("bnd_radius", ctypes.c_int),
+                ("fuse_small_levels", ctypes.c_int), ("band_split_min", ctypes.c_int)]
 
 
 class GpRigid(ctypes.Structure):

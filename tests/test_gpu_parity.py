@@ -29,14 +29,14 @@ def gpu_solver(N, Re=100.0, **kw):
     return gpmg.Solver(N, Re=Re, **kw)
 
 
-def pair(N, shape, alpha, motion=None, t=0.0, m=None, Re=100.0, zero_x=True):
+def pair(N, shape, alpha, motion=None, t=0.0, m=None, Re=100.0, zero_x=True, **gpu_params):
     """oracle and GPU solver on the same level set, alpha, rhs and boundary data"""
     o = O.Oracle(N, Re=Re)
     mo = motion.as_array() if motion is not None else np.zeros(6)
     phi = O.levelset_analytic(shape.kind, shape.padded(), mo, t, N)
     assert o.set_levelset(phi, t, mo) == O.OK
     o.set_alpha(alpha)
-    s = gpu_solver(N, Re=Re)
+    s = gpu_solver(N, Re=Re, **gpu_params)
     s.set_levelset(phi, t, mo[:5])
     s.set_alpha(alpha)
     m = m or wl.TaylorGreenMMS()
@@ -135,6 +135,21 @@ def test_relaxation_parity(shape):
 def test_cycle_parity(N, shape):
     say(f"[cycle] N={N} shape={shape}")
     o, s = pair(N, shape, 0.64 * (2.0 / N) ** 2)
+    check_cycles(o, s)
+
+
+# device layouts of the same cycle: levels N <= 32 per level or in one workgroup; the band in one workgroup or
+# in device-wide launches
+@pytest.mark.parametrize("fuse,split", [(0, 3000), (1, 1), (0, 1)])
+def test_cycle_parity_layouts(fuse, split):
+    N = 128
+    say(f"[cycle layout] N={N} fuse_small_levels={fuse} band_split_min={split}")
+    o, s = pair(N, FLOWER, 0.64 * (2.0 / N) ** 2, motion=wl.Motion(omega=1.0), t=0.2, fuse_small_levels=fuse,
+                band_split_min=split)
+    check_cycles(o, s)
+
+
+def check_cycles(o, s):
     cls = o.classes().ravel()
     act = np.concatenate([active_mask(cls), [True]])
     for c in range(3):
