@@ -141,6 +141,8 @@ void gp_destroy(gp_ctx *ctx) {
     dfree(ctx->v64[l].x);
     dfree(ctx->v64[l].b);
     dfree(ctx->v64[l].r);
+    dfree(ctx->v64[l].y);
+    dfree(ctx->v32[l].y);
     dfree(ctx->v32[l].x);
     dfree(ctx->v32[l].b);
     dfree(ctx->v32[l].r);
@@ -250,6 +252,7 @@ gp_status gp_setup_grid(gp_ctx **out, int N, double Re, const gp_params *prm, vo
     ALLOC(ctx->v64[l].x, (size_t)G.n);
     ALLOC(ctx->v64[l].b, (size_t)G.n);
     ALLOC(ctx->v64[l].r, (size_t)G.n);
+    if (G.N >= 64) ALLOC(ctx->v64[l].y, (size_t)G.n);
     gmax = std::max(gmax, (size_t)G.gcap);
     GP_HIP(hipMemsetAsync(ctx->v64[l].x, 0, G.n * sizeof(double), ctx->stream));
     GP_HIP(hipMemsetAsync(ctx->v64[l].b, 0, G.n * sizeof(double), ctx->stream));

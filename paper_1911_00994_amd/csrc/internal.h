@@ -69,6 +69,7 @@ struct Geo {
 template <typename T>
 struct Vec {
   T *x = nullptr, *b = nullptr, *r = nullptr;
+  T *y = nullptr;  // second buffer of x for sweeps that read one copy and write the other (swapped afterwards)
 };
 
 // saved time-stepping state of the finest level: x (3*WW + 1), then the convection history c^n, c^{n-1},
@@ -141,6 +142,7 @@ struct Ctx {
   size_t max_lds = 65536;           // dynamic LDS a workgroup may use on this device
   int small_cycles = 1;             // run the levels with N <= 32 as one workgroup when they fit in LDS
   int band_split_min = 3000;        // bands with at least this many cells use device-wide launches
+  int box_tiles = 1;                // all five colours of a box sweep in one launch (LDS tiles with halos)
 };
 
 // error handling

@@ -22,9 +22,102 @@ __device__ __forceinline__ int pidx(int W, int i, int j) { return (j + 1) * W + 
 //   one free:   d uW = RW + a uE - p/h   (resp. d uE = RE + a uW + p/h)
 // and the continuity row fixes p.
 // ---------------------------------------------------------------------------------------------------------
+// per-level constants of the box solve (the quotients by d, d + a and d^2 - a^2 and the nine possible
+// denominators of the pressure, which depend only on which faces of the box are free)
+struct BoxK {
+  double h, ih, a, q1, q2, bp, id, ihd;  // q1 = d / det, q2 = a / det, bp = (1/h) / (d + a), id = 1 / d, ihd = (1/h) / d
+  double iden[9];                        // 1 / (Du + Dv), Du, Dv in {0, ihd, 2 bp} (index 3 iu + iv); 0 if Du + Dv = 0
+};
+inline BoxK box_consts(double h, double a, double d) {
+  BoxK K;
+  const double det = d * d - a * a;
+  K.h = h;
+  K.ih = 1.0 / h;
+  K.a = a;
+  K.q1 = d / det;
+  K.q2 = a / det;
+  K.bp = K.ih / (d + a);
+  K.id = 1.0 / d;
+  K.ihd = K.ih / d;
+  const double D[3] = {0.0, K.ihd, 2.0 * K.bp};
+  for (int iu = 0; iu < 3; iu++)
+    for (int iv = 0; iv < 3; iv++) K.iden[3 * iu + iv] = (iu || iv) ? 1.0 / (D[iu] + D[iv]) : 0.0;
+  return K;
+}
+
+// new values of a box from its 21 neighbouring values and 5 right-hand sides; skip = the box is left unchanged
+struct BoxNew {
+  double p, uW, uE, vS, vN;
+  bool skip;
+};
+__device__ __forceinline__ BoxNew box_core(const BoxK &K, bool fW, bool fE, bool fS, bool fN, bool fP, double uW, double uE,
+                                           double uWW, double uEE, double uWS, double uWN, double uES, double uEN, double vS,
+                                           double vN, double vSS, double vNN, double vSW, double vSE, double vNW, double vNE,
+                                           double pc, double pW, double pE, double pS, double pN, double bW_, double bE_,
+                                           double bS_, double bN_, double bP_, double xi) {
+  BoxNew o;
+  o.skip = false;
+  const double a = K.a, ih = K.ih;
+  double aW = uW, bW = 0, aE = uE, bE = 0, aS = vS, bS = 0, aN = vN, bN = 0;
+  int iu = 0, iv = 0;
+  {
+    const double RW = bW_ + a * (uWW + uWS + uWN) + pW * ih;
+    const double RE = bE_ + a * (uEE + uES + uEN) - pE * ih;
+    if (fW && fE) {
+      aW = K.q1 * RW + K.q2 * RE;
+      bW = -K.bp;
+      aE = K.q2 * RW + K.q1 * RE;
+      bE = K.bp;
+      iu = 2;
+    } else if (fW) {
+      aW = (RW + a * uE) * K.id;
+      bW = -K.ihd;
+      iu = 1;
+    } else if (fE) {
+      aE = (RE + a * uW) * K.id;
+      bE = K.ihd;
+      iu = 1;
+    }
+  }
+  {
+    const double RS = bS_ + a * (vSS + vSW + vSE) + pS * ih;
+    const double RN = bN_ + a * (vNN + vNW + vNE) - pN * ih;
+    if (fS && fN) {
+      aS = K.q1 * RS + K.q2 * RN;
+      bS = -K.bp;
+      aN = K.q2 * RS + K.q1 * RN;
+      bN = K.bp;
+      iv = 2;
+    } else if (fS) {
+      aS = (RS + a * vN) * K.id;
+      bS = -K.ihd;
+      iv = 1;
+    } else if (fN) {
+      aN = (RN + a * vS) * K.id;
+      bN = K.ihd;
+      iv = 1;
+    }
+  }
+  double pn = pc;
+  if (fP) {
+    const double idn = K.iden[3 * iu + iv];
+    if (idn == 0.0) {  // no free face: the block is singular, the box is skipped
+      o.skip = true;
+      return o;
+    }
+    pn = (K.h * (xi + bP_) - (aE - aW + aN - aS)) * idn;
+  }
+  o.p = pn;
+  o.uW = aW + bW * pn;
+  o.uE = aE + bE * pn;
+  o.vS = aS + bS * pn;
+  o.vN = aN + bN * pn;
+  return o;
+}
+
 template <typename T>
-__device__ __forceinline__ void box_update(int N, int W, double h, double a, double d, const uint8_t *__restrict__ cls,
-                                           T *__restrict__ x, const T *__restrict__ b, int i, int j) {
+__device__ __forceinline__ void box_update(int W, const BoxK &K, const uint8_t *__restrict__ cls, T *__restrict__ x,
+                                           const T *__restrict__ b, int i, int j) {
   const int WW = W * W;
   T *u = x, *v = x + WW, *p = x + 2 * WW;
   const T *bu = b, *bv = b + WW, *bp = b + 2 * WW;
@@ -40,56 +133,18 @@ __device__ __forceinline__ void box_update(int N, int W, double h, double a, dou
   const double xi = (double)x[3 * WW];
   const bool fW = kW == K_INT, fE = kE == K_INT, fS = kS == K_INT, fN = kN == K_INT, fP = kP == K_INT;
   if (!(fW || fE || fS || fN || fP)) return;
-  const double ih = 1.0 / h;
-  double aW = uW, bW = 0, aE = uE, bE = 0, aS = vS, bS = 0, aN = vN, bN = 0;
-  const double det = d * d - a * a;
-  {
-    const double RW = bW_ + a * (uWW + uWS + uWN) + pW * ih;
-    const double RE = bE_ + a * (uEE + uES + uEN) - pE * ih;
-    if (fW && fE) {
-      aW = (d * RW + a * RE) / det;
-      bW = -ih / (d + a);
-      aE = (a * RW + d * RE) / det;
-      bE = ih / (d + a);
-    } else if (fW) {
-      aW = (RW + a * uE) / d;
-      bW = -ih / d;
-    } else if (fE) {
-      aE = (RE + a * uW) / d;
-      bE = ih / d;
-    }
-  }
-  {
-    const double RS = bS_ + a * (vSS + vSW + vSE) + pS * ih;
-    const double RN = bN_ + a * (vNN + vNW + vNE) - pN * ih;
-    if (fS && fN) {
-      aS = (d * RS + a * RN) / det;
-      bS = -ih / (d + a);
-      aN = (a * RS + d * RN) / det;
-      bN = ih / (d + a);
-    } else if (fS) {
-      aS = (RS + a * vN) / d;
-      bS = -ih / d;
-    } else if (fN) {
-      aN = (RN + a * vS) / d;
-      bN = ih / d;
-    }
-  }
-  double pn = pc;
-  if (fP) {
-    const double den = bE - bW + bN - bS;
-    if (den == 0.0) return;  // no free face: the block is singular, the box is skipped
-    pn = (h * (xi + bP_) - (aE - aW + aN - aS)) / den;
-    p[c] = (T)pn;
-  }
-  if (fW) u[c] = (T)(aW + bW * pn);
-  if (fE) u[c + 1] = (T)(aE + bE * pn);
-  if (fS) v[c] = (T)(aS + bS * pn);
-  if (fN) v[c + W] = (T)(aN + bN * pn);
+  const BoxNew o = box_core(K, fW, fE, fS, fN, fP, uW, uE, uWW, uEE, uWS, uWN, uES, uEN, vS, vN, vSS, vNN, vSW, vSE, vNW,
+                            vNE, pc, pW, pE, pS, pN, bW_, bE_, bS_, bN_, bP_, xi);
+  if (o.skip) return;
+  if (fP) p[c] = (T)o.p;
+  if (fW) u[c] = (T)o.uW;
+  if (fE) u[c + 1] = (T)o.uE;
+  if (fS) v[c] = (T)o.vS;
+  if (fN) v[c + W] = (T)o.vN;
 }
 
 template <typename T>
-__global__ void __launch_bounds__(TPB) k_box(int N, int W, double h, double a, double d, const uint8_t *__restrict__ cls,
+__global__ void __launch_bounds__(TPB) k_box(int N, int W, BoxK BK, const uint8_t *__restrict__ cls,
                                              T *__restrict__ x, const T *__restrict__ b, int colour) {
   const int K = N / 5 + 1;
   // workgroups are dealt to the 8 XCDs round robin: remap so that each XCD works on one contiguous band of
@@ -101,18 +156,85 @@ __global__ void __launch_bounds__(TPB) k_box(int N, int W, double h, double a, d
   if (j >= N) return;
   int i = ((colour - 2 * j) % 5 + 5) % 5 + 5 * kk;
   if (i >= N) return;
-  box_update<T>(N, W, h, a, d, cls, x, b, i, j);
+  box_update<T>(W, BK, cls, x, b, i, j);
+}
+
+// ---------------------------------------------------------------------------------------------------------
+// all five colours of a box sweep in one launch (temporal blocking).  A workgroup owns a BT x BT tile of cells
+// and stages the points of the tile widened by BH = 10 cells (x, b, classes) in LDS.  Pass k (colour k) updates
+// the boxes of colour k within 1 + 2 (4 - k) cells of the tile: a box depends only on boxes within 2 cells
+// written in earlier passes, so every box computed in pass k sees exactly the values the colour-by-colour sweep
+// gives it, and the boxes that write the tile's own points (u, v, p of its cells: the west and south faces and
+// the centre) are all computed in every pass.  The sweep reads x and writes a second buffer y: every point is
+// owned by one tile (the border rows and columns -1 and N by the tiles next to them), so y receives every point
+// once, and no workgroup can see another one's new values while staging its halo.  The caller swaps x and y.
+// ---------------------------------------------------------------------------------------------------------
+constexpr int BT = 32, BH = 10, BRW = BT + 2 * BH + 1, BRWW = BRW * BRW;  // 53 x 53 staged points
+constexpr int B5_T = 512;
+template <typename T>
+__host__ __device__ constexpr size_t box5_lds() {
+  return ((3 * BRWW + 1) * sizeof(T) + 15) / 16 * 16 + (3 * BRWW * sizeof(T) + 15) / 16 * 16 + 3 * BRWW;
+}
+template <typename T>
+__global__ void __launch_bounds__(B5_T) k_box5(int N, int W, BoxK K, const uint8_t *__restrict__ cls,
+                                               const T *__restrict__ x, const T *__restrict__ b, T *__restrict__ y) {
+  extern __shared__ unsigned char lds_raw[];
+  T *xs = reinterpret_cast<T *>(lds_raw);
+  T *bs = reinterpret_cast<T *>(lds_raw + ((3 * BRWW + 1) * sizeof(T) + 15) / 16 * 16);
+  uint8_t *cs = lds_raw + ((3 * BRWW + 1) * sizeof(T) + 15) / 16 * 16 + (3 * BRWW * sizeof(T) + 15) / 16 * 16;
+  const int WW = W * W, nt = (N + BT - 1) / BT;
+  const int i0 = (blockIdx.x % nt) * BT, j0 = (blockIdx.x / nt) * BT;
+  const int gi0 = i0 - BH, gj0 = j0 - BH;  // point (gi0, gj0) sits at LDS point (0, 0)
+  for (int e = threadIdx.x; e < 3 * BRWW; e += B5_T) {
+    int g = e / BRWW, q = e - g * BRWW, pj = q / BRW, pi = q - pj * BRW;
+    int gi = gi0 + pi, gj = gj0 + pj;
+    if (gi >= -1 && gi <= N && gj >= -1 && gj <= N) {
+      int k = g * WW + (gj + 1) * W + (gi + 1);
+      xs[e] = x[k];
+      bs[e] = b[k];
+      cs[e] = cls[k];
+    } else {
+      xs[e] = (T)0;
+      bs[e] = (T)0;
+      cs[e] = K_INACTIVE;
+    }
+  }
+  if (threadIdx.x == 0) xs[3 * BRWW] = x[3 * WW];
+  __syncthreads();
+  for (int k = 0; k < 5; k++) {
+    const int ex = 1 + 2 * (4 - k);
+    const int ilo = max(0, i0 - ex), ihi = min(N, i0 + BT + ex), jlo = max(0, j0 - ex), jhi = min(N, j0 + BT + ex);
+    const int per = (ihi - ilo + 4) / 5 + 1;  // colour-k cells per row, at most
+    for (int t = threadIdx.x; t < per * (jhi - jlo); t += B5_T) {
+      int r = t / per, m = t - r * per, j = jlo + r;
+      int i = ilo + ((k - (ilo + 2 * j)) % 5 + 5) % 5 + 5 * m;
+      if (i >= ihi) continue;
+      // LDS cell coordinates: point index of cell i is i - gi0, and box_update takes the cell as point - 1
+      box_update<T>(BRW, K, cs, xs, bs, i - gi0 - 1, j - gj0 - 1);
+    }
+    __syncthreads();
+  }
+  // owned points: the tile's cells, plus the border row / column -1 or N next to it
+  const int ib = i0 == 0 ? -1 : i0, ie = min(N, i0 + BT) + (i0 + BT >= N ? 1 : 0);
+  const int jb = j0 == 0 ? -1 : j0, je = min(N, j0 + BT) + (j0 + BT >= N ? 1 : 0);
+  const int ow = ie - ib, oh = je - jb;
+  for (int e = threadIdx.x; e < 3 * ow * oh; e += B5_T) {
+    int g = e / (ow * oh), q = e - g * ow * oh, lj = q / ow, li = q - lj * ow;
+    int gi = ib + li, gj = jb + lj;
+    y[g * WW + (gj + 1) * W + (gi + 1)] = xs[g * BRWW + (gj - gj0) * BRW + (gi - gi0)];
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) y[3 * WW] = xs[3 * BRWW];
 }
 
 // box relaxation of the band cells band[lo, hi) (one colour), spread over the whole device
 template <typename T>
-__global__ void __launch_bounds__(TPB) k_box_list(int N, int W, double h, double a, double d, const uint8_t *__restrict__ cls,
+__global__ void __launch_bounds__(TPB) k_box_list(int N, int W, BoxK K, const uint8_t *__restrict__ cls,
                                                   T *__restrict__ x, const T *__restrict__ b, const int *__restrict__ band,
                                                   int lo, int hi) {
   int t = lo + blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= hi) return;
   int cell = band[t];
-  box_update<T>(N, W, h, a, d, cls, x, b, cell % N, cell / N);
+  box_update<T>(W, K, cls, x, b, cell % N, cell / N);
 }
 
 // fictitious-time relaxation of every ghost row at once (eq. ghostrelax, Jacobi): w += dtau (g - B w)
@@ -158,7 +280,7 @@ __global__ void __launch_bounds__(GH_T) k_ghost_sweeps(const int *__restrict__ p
 // the colour order, each followed by lambda ghost sweeps
 constexpr int BAND_T = 1024;
 template <typename T>
-__global__ void __launch_bounds__(BAND_T) k_band_sweeps(int N, int W, double h, double a, double d,
+__global__ void __launch_bounds__(BAND_T) k_band_sweeps(int N, int W, BoxK K,
                                                         const uint8_t *__restrict__ cls, T *x, const T *__restrict__ b,
                                                         const int *__restrict__ band, const int *__restrict__ off,
                                                         const int *__restrict__ pt, const int *__restrict__ col,
@@ -183,7 +305,7 @@ __global__ void __launch_bounds__(BAND_T) k_band_sweeps(int N, int W, double h, 
       int lo = off[c], hi = off[c + 1];
       for (int q = lo + threadIdx.x; q < hi; q += BAND_T) {
         int cell = band[q];
-        box_update<T>(N, W, h, a, d, cls, x, b, cell % N, cell / N);
+        box_update<T>(W, K, cls, x, b, cell % N, cell / N);
       }
       __syncthreads();
     }
@@ -245,7 +367,7 @@ struct BandOff {
   int o[6];
 };
 template <typename T>
-__global__ void __launch_bounds__(BAND_T) k_band_lds(int N, int W, double h, double a, double d, T *x, const T *__restrict__ b,
+__global__ void __launch_bounds__(BAND_T) k_band_lds(int N, int W, BoxK K, T *x, const T *__restrict__ b,
                                                      BandOff off, const int *__restrict__ bbox, int bcap,
                                                      const int *__restrict__ reg_pt, int nreg, const int *__restrict__ bg_k,
                                                      const int *__restrict__ bg_loc, const double *__restrict__ bg_w,
@@ -280,7 +402,6 @@ __global__ void __launch_bounds__(BAND_T) k_band_lds(int N, int W, double h, dou
       if (q0 + u * BAND_T < nreg) xs[q0 + u * BAND_T] = vv[u];
   }
   const double xi = (double)x[3 * WW];
-  const double ih = 1.0 / h, det = d * d - a * a;
   __syncthreads();
   // Jacobi sweeps of the body ghost rows; each new value goes through nvbuf (written and read back by the same
   // thread), so no row data is held across the barrier
@@ -311,53 +432,14 @@ __global__ void __launch_bounds__(BAND_T) k_band_lds(int N, int W, double h, dou
                vSE = val(TB(13)), vNW = val(TB(14)), vNE = val(TB(15));
         double pc = val(TB(16)), pW = val(TB(17)), pE = val(TB(18)), pS = val(TB(19)), pN = val(TB(20));
         double bW_ = b[cg], bE_ = b[cg + 1], bS_ = b[WW + cg], bN_ = b[WW + cg + W], bP_ = b[2 * WW + cg];
-        double aW = uW, bW = 0, aE = uE, bE = 0, aS = vS, bS = 0, aN = vN, bN = 0;
-        {
-          double RW = bW_ + a * (uWW + uWS + uWN) + pW * ih, RE = bE_ + a * (uEE + uES + uEN) - pE * ih;
-          if (fW && fE) {
-            aW = (d * RW + a * RE) / det;
-            bW = -ih / (d + a);
-            aE = (a * RW + d * RE) / det;
-            bE = ih / (d + a);
-          } else if (fW) {
-            aW = (RW + a * uE) / d;
-            bW = -ih / d;
-          } else if (fE) {
-            aE = (RE + a * uW) / d;
-            bE = ih / d;
-          }
-        }
-        {
-          double RS = bS_ + a * (vSS + vSW + vSE) + pS * ih, RN = bN_ + a * (vNN + vNW + vNE) - pN * ih;
-          if (fS && fN) {
-            aS = (d * RS + a * RN) / det;
-            bS = -ih / (d + a);
-            aN = (a * RS + d * RN) / det;
-            bN = ih / (d + a);
-          } else if (fS) {
-            aS = (RS + a * vN) / d;
-            bS = -ih / d;
-          } else if (fN) {
-            aN = (RN + a * vS) / d;
-            bN = ih / d;
-          }
-        }
-        double pn = pc;
-        bool skip = false;
-        if (fP) {
-          double den = bE - bW + bN - bS;
-          if (den == 0.0)
-            skip = true;
-          else {
-            pn = (h * (xi + bP_) - (aE - aW + aN - aS)) / den;
-            xs[TB(16)] = (T)pn;
-          }
-        }
-        if (!skip) {
-          if (fW) xs[TB(0)] = (T)(aW + bW * pn);
-          if (fE) xs[TB(1)] = (T)(aE + bE * pn);
-          if (fS) xs[TB(8)] = (T)(aS + bS * pn);
-          if (fN) xs[TB(9)] = (T)(aN + bN * pn);
+        const BoxNew o = box_core(K, fW, fE, fS, fN, fP, uW, uE, uWW, uEE, uWS, uWN, uES, uEN, vS, vN, vSS, vNN, vSW, vSE,
+                                  vNW, vNE, pc, pW, pE, pS, pN, bW_, bE_, bS_, bN_, bP_, xi);
+        if (!o.skip) {
+          if (fP) xs[TB(16)] = (T)o.p;
+          if (fW) xs[TB(0)] = (T)o.uW;
+          if (fE) xs[TB(1)] = (T)o.uE;
+          if (fS) xs[TB(8)] = (T)o.vS;
+          if (fN) xs[TB(9)] = (T)o.vN;
         }
       }
       __syncthreads();
@@ -389,7 +471,7 @@ __global__ void __launch_bounds__(BAND_T) k_band_lds(int N, int W, double h, dou
     for (int u = 0; u < BATCH; u++)
       if (gi[u] >= 0) x[gi[u]] = xs[q0 + u * BAND_T];
   }
-  if (tid == 0) x[3 * WW] = (T)((fs / h - *gsum) / *mp);
+  if (tid == 0) x[3 * WW] = (T)((fs / K.h - *gsum) / *mp);
 }
 
 // xi <- mean over internal cells of (div u - g), from the boundary faces of the internal cells (one workgroup)
@@ -803,6 +885,7 @@ constexpr int SC_MAXL = 4;
 struct SmallLevel {
   int N, W, n, ng, ne, nband, mp;
   double h, a, d;
+  BoxK K;
   const uint8_t *cls;
   const int *g_pt, *g_col, *e_pt, *e_src, *band;
   const double *g_w, *g_dtau, *e_w;
@@ -860,7 +943,7 @@ __device__ void sc_relax(const SmallCycle &P, const SmallLevel &L, const ScRows 
     for (int t = threadIdx.x; t < K * L.N; t += SC_T) {
       int j = t / K, kk = t - j * K;
       int i = ((c - 2 * j) % 5 + 5) % 5 + 5 * kk;
-      if (i < L.N) box_update<T>(L.N, L.W, L.h, L.a, L.d, cls, x, b, i, j);
+      if (i < L.N) box_update<T>(L.W, L.K, cls, x, b, i, j);
     }
     __syncthreads();
   }
@@ -870,7 +953,7 @@ __device__ void sc_relax(const SmallCycle &P, const SmallLevel &L, const ScRows 
       for (int c = 0; c < 5; c++) {
         for (int t = L.boff[c] + threadIdx.x; t < L.boff[c + 1]; t += SC_T) {
           int cell = L.band[t];
-          box_update<T>(L.N, L.W, L.h, L.a, L.d, cls, x, b, cell % L.N, cell / L.N);
+          box_update<T>(L.W, L.K, cls, x, b, cell % L.N, cell / L.N);
         }
         __syncthreads();
       }
@@ -1018,8 +1101,15 @@ static void relax(Ctx *ctx, int l) {
   Vec<T> &V = vec<T>(ctx, l);
   hipStream_t s = ctx->stream;
   double a = coef_a(ctx, l), d = 1.0 + 4.0 * a;
+  const BoxK BK = box_consts(G.h, a, d);
   int K = G.N / 5 + 1;
-  for (int col = 0; col < 5; col++) k_box<T><<<box_grid(K, G.N), TPB, 0, s>>>(G.N, G.W, G.h, a, d, G.cls, V.x, V.b, col);
+  if (ctx->box_tiles && V.y && box5_lds<T>() + 1024 <= ctx->max_lds) {
+    int nt = (G.N + BT - 1) / BT;
+    k_box5<T><<<nt * nt, B5_T, box5_lds<T>(), s>>>(G.N, G.W, BK, G.cls, V.x, V.b, V.y);
+    std::swap(V.x, V.y);
+  } else {
+    for (int col = 0; col < 5; col++) k_box<T><<<box_grid(K, G.N), TPB, 0, s>>>(G.N, G.W, BK, G.cls, V.x, V.b, col);
+  }
   const bool band = ctx->prm.bnd_sweeps > 0 && G.nband > 0;
   const size_t lds_bytes = (size_t)G.nreg * sizeof(T);
   if (band && G.nband >= ctx->band_split_min) {
@@ -1034,7 +1124,7 @@ static void relax(Ctx *ctx, int l) {
     for (int q = 0; q < ctx->prm.bnd_sweeps; q++) {
       for (int c = 0; c < 5; c++) {
         int lo = G.hband_off[c], hi = G.hband_off[c + 1];
-        if (hi > lo) k_box_list<T><<<nblk(hi - lo), TPB, 0, s>>>(G.N, G.W, G.h, a, d, G.cls, V.x, V.b, G.band, lo, hi);
+        if (hi > lo) k_box_list<T><<<nblk(hi - lo), TPB, 0, s>>>(G.N, G.W, BK, G.cls, V.x, V.b, G.band, lo, hi);
       }
       if (G.ng) sweeps();
     }
@@ -1046,7 +1136,7 @@ static void relax(Ctx *ctx, int l) {
     int nwb = (G.nwg + BAND_T - 1) / BAND_T;
     BandOff bo;
     for (int c = 0; c < 6; c++) bo.o[c] = G.hband_off[c];
-    k_band_lds<T><<<1 + nwb, BAND_T, lds_bytes, s>>>(G.N, G.W, G.h, a, d, V.x, V.b, bo, G.bbox, G.bcap, G.reg_pt, G.nreg,
+    k_band_lds<T><<<1 + nwb, BAND_T, lds_bytes, s>>>(G.N, G.W, BK, V.x, V.b, bo, G.bbox, G.bcap, G.reg_pt, G.nreg,
                                                      G.bg_k, G.bg_loc, G.bg_w, G.bg_dt, G.nbg, G.gcap, ctx->gtmp, G.g_pt, G.g_col,
                                                      G.g_w, G.g_dtau, G.wg_rows,
                                                G.nwg, ctx->prm.bnd_sweeps, ctx->prm.lambda_ghost, G.f_code, G.f_loc, G.nf,
@@ -1055,12 +1145,12 @@ static void relax(Ctx *ctx, int l) {
   }
   if (band && G.ng <= 4 * GH_T) {
     // ghost sweeps and the band sweeps in one workgroup
-    k_band_sweeps<T><<<1, BAND_T, 0, s>>>(G.N, G.W, G.h, a, d, G.cls, V.x, V.b, G.band, G.d_band_off, G.g_pt, G.g_col,
+    k_band_sweeps<T><<<1, BAND_T, 0, s>>>(G.N, G.W, BK, G.cls, V.x, V.b, G.band, G.d_band_off, G.g_pt, G.g_col,
                                           G.g_w, G.g_dtau, G.ng, ctx->gtmp, ctx->prm.bnd_sweeps, ctx->prm.lambda_ghost, 1);
   } else {
     relax_ghosts<T>(ctx, l);
     if (band)
-      k_band_sweeps<T><<<1, BAND_T, 0, s>>>(G.N, G.W, G.h, a, d, G.cls, V.x, V.b, G.band, G.d_band_off, G.g_pt, G.g_col,
+      k_band_sweeps<T><<<1, BAND_T, 0, s>>>(G.N, G.W, BK, G.cls, V.x, V.b, G.band, G.d_band_off, G.g_pt, G.g_col,
                                             G.g_w, G.g_dtau, G.ng, ctx->gtmp, ctx->prm.bnd_sweeps, ctx->prm.lambda_ghost, 0);
   }
   k_xi_faces<T><<<1, BAND_T, 0, s>>>(G.WW, G.h, V.x, G.f_code, G.nf, ctx->d_lev + l, G.d_mp);
@@ -1128,6 +1218,7 @@ static size_t small_cycle_setup(Ctx *ctx, int l, SmallCycle &P) {
     S.h = G.h;
     S.a = ctx->alpha / (G.h * G.h);
     S.d = 1.0 + 4.0 * S.a;
+    S.K = box_consts(S.h, S.a, S.d);
     S.cls = G.cls;
     S.g_pt = G.g_pt;
     S.g_col = G.g_col;
@@ -1259,7 +1350,7 @@ gp_status time_kernel(Ctx *ctx, int which, int l, int reps, double *avg_us) {
   for (int q = 0; q < reps; q++) {
     if (which == 0) {
       for (int col = 0; col < 5; col++)
-        k_box<double><<<box_grid(K, G.N), TPB, 0, s>>>(G.N, G.W, G.h, a, d, G.cls, V.x, V.b, col);
+        k_box<double><<<box_grid(K, G.N), TPB, 0, s>>>(G.N, G.W, box_consts(G.h, a, d), G.cls, V.x, V.b, col);
       launches += 5;
     } else if (which == 1) {
       k_resid_pts<double><<<nblk(3L * G.WW), TPB, 0, s>>>(G.N, G.W, G.h, a, d, G.cls, V.x, V.b, V.r, nullptr);
@@ -1334,6 +1425,7 @@ static gp_status ensure_fp32(Ctx *ctx) {
     GP_HIP(hipMalloc((void **)&V.x, n * sizeof(float)));
     GP_HIP(hipMalloc((void **)&V.b, n * sizeof(float)));
     GP_HIP(hipMalloc((void **)&V.r, n * sizeof(float)));
+    if (ctx->geo[l].N >= 64) GP_HIP(hipMalloc((void **)&V.y, n * sizeof(float)));
     GP_HIP(hipMemsetAsync(V.x, 0, n * sizeof(float), ctx->stream));
     GP_HIP(hipMemsetAsync(V.b, 0, n * sizeof(float), ctx->stream));
     GP_HIP(hipMemsetAsync(V.r, 0, n * sizeof(float), ctx->stream));
