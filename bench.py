@@ -19,37 +19,47 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
-# HBM bytes per launch of the finest-level box kernel from the two rocprofv3 counter runs (FETCH_SIZE x 1.9992 +
-# WRITE_SIZE x 1.0, scaled by a 64 MiB device copy); the kernel is unchanged since they were taken
-BOX_TRAFFIC_BYTES = 71.87e6
-BOX_TRAFFIC_SOURCE = "profiles/k_box_flower1024_hbm_traffic.md"
+# HBM bytes per launch of the finest-level five-colour box kernel from the two rocprofv3 counter runs (FETCH_SIZE
+# and WRITE_SIZE, each scaled by what it reads for a 64 MiB device copy); None until taken for the current kernel
+BOX_TRAFFIC_BYTES = 89.67e6
+BOX_TRAFFIC_SOURCE = "profiles/k_box5_flower1024_hbm_traffic.md"
 
 
-def box_launch_bytes(cls, N, colour, elem=8):
-    """Algorithmic bytes of one box-relaxation launch (one colour): every distinct array element the launch
-    reads or writes, counted once (reads: the class bytes of the five box unknowns, the values of the
-    stencils of the box rows, the right-hand sides; writes: the five box unknowns).  Computed for the boxes
-    that have at least one internal unknown, as the kernel skips the others."""
+def box_sweep_bytes(cls, N, elem=8):
+    """Algorithmic bytes of one launch of the five-colour box sweep: the distinct array elements that the five
+    colours read or write together, each counted once.  Reads: the class bytes of the box unknowns, and for every
+    internal unknown of a box its row's stencil values and its right-hand side; writes: the internal unknowns.
+    (A u row takes the 5-point u stencil and the two pressures beside the face, a v row likewise, a continuity
+    row the four velocities of its cell.)  Boxes with no internal unknown are skipped by the kernel."""
     import numpy as np
     W = N + 2
     I, J = np.meshgrid(np.arange(N), np.arange(N))
-    sel = ((I + 2 * J) % 5) == colour
-    i, j = I[sel], J[sel]
-    c = (j + 1) * W + (i + 1)
+    c = ((J + 1) * W + (I + 1)).ravel()
     u, v, p = cls[0].ravel(), cls[1].ravel(), cls[2].ravel()
     act = (u[c] == 1) | (u[c + 1] == 1) | (v[c] == 1) | (v[c + W] == 1) | (p[c] == 1)
     c = c[act]
-    reads = {"cls_u": [c, c + 1], "cls_v": [c, c + W], "cls_p": [c],
-             "u": [c - 1, c, c + 1, c + 2, c - W, c + W, c + 1 - W, c + 1 + W],
-             "v": [c - W, c, c + W, c + 2 * W, c - 1, c + 1, c + W - 1, c + W + 1],
-             "p": [c - 1, c, c + 1, c - W, c + W],
-             "bu": [c, c + 1], "bv": [c, c + W], "bp": [c]}
+    seen = {f: np.zeros(W * W, dtype=bool) for f in "uvp"}
     total = 0
-    for k, lst in reads.items():
-        n = np.unique(np.concatenate(lst)).size
-        total += n * (1 if k.startswith("cls") else elem)
-    writes = np.unique(np.concatenate([c, c + 1])).size + np.unique(np.concatenate([c, c + W])).size + c.size
-    return total + writes * elem
+    box = {"u": [0, 1], "v": [0, W], "p": [0]}
+    for f, cf in zip("uvp", (u, v, p)):
+        m = np.zeros(W * W, dtype=bool)
+        for o in box[f]:
+            m[c + o] = True
+        total += int(m.sum())  # class bytes
+        k = np.flatnonzero(m & (cf == 1))  # internal unknowns of the boxes
+        total += k.size * 2 * elem  # right-hand side read, value written
+        if f == "u":
+            for o in (-1, 0, 1, -W, W):
+                seen["u"][k + o] = True
+            seen["p"][k - 1] = seen["p"][k] = True
+        elif f == "v":
+            for o in (-1, 0, 1, -W, W):
+                seen["v"][k + o] = True
+            seen["p"][k - W] = seen["p"][k] = True
+        else:
+            seen["u"][k] = seen["u"][k + 1] = True
+            seen["v"][k] = seen["v"][k + W] = True
+    return total + sum(int(x.sum()) for x in seen.values()) * elem
 
 
 def cpu_baseline(wk, N, cycles):
@@ -124,18 +134,20 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-cycles", type=int, default=8)
     ap.add_argument("--no-kernel-timing", action="store_true")
+    ap.add_argument("--no-graphs", action="store_true", help="issue every launch from the host (no HIP graphs)")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--profile-kernel", action="store_true",
-                    help="set up the N=1024 system, run 2 x 5 box-relaxation launches on the finest level and a "
-                         "plain 64 MiB device copy (counter calibration), then exit (for rocprofv3 --pmc runs)")
+                    help="set up the N=1024 system, run a plain 64 MiB device copy (counter calibration) and 10 "
+                         "launches of the five-colour box sweep on the finest level, then exit (for rocprofv3 "
+                         "--pmc runs)")
     return ap.parse_args()
 
 
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU decomposition is a "
-              f"design note, not part of this build", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): the solver has no multi-GPU "
+              f"decomposition", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch
@@ -151,7 +163,7 @@ def main():
     prec = gpmg.GP_MIXED if args.precision == "mixed" else gpmg.GP_FP64
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream(dev)
-    solver = gpmg.Solver(N, Re=Re, stream=stream.cuda_stream)
+    solver = gpmg.Solver(N, Re=Re, stream=stream.cuda_stream, graph_iterations=0 if args.no_graphs else 1)
     fu, fv = wl.fourier_forcing(N, seed=0)
     fu_d = torch.from_numpy(fu).to(dev)
     fv_d = torch.from_numpy(fv).to(dev)
@@ -185,8 +197,9 @@ def main():
         del flush
         solver.set_alpha(dt / (2.0 * Re))
         solver.set_rhs(fu, fv, None)
-        us = solver.time_kernel(0, level=0, reps=2)
-        print(json.dumps({"profile_kernel": "k_box<double> finest", "avg_launch_us": us, "copy_bytes": 2 * (64 << 20)}))
+        us = solver.time_kernel(5, level=0, reps=10)
+        print(json.dumps({"profile_kernel": "k_box5<double> finest", "launches": 10, "avg_launch_us": us,
+                          "copy_bytes": 2 * (64 << 20)}))
         return
     for _ in range(args.warmup):
         step()
@@ -197,6 +210,8 @@ def main():
     e1 = torch.cuda.Event(enable_timing=True)
     cycles = 0
     picard = 0
+    if not args.no_kernel_timing:
+        solver.probe_start(4096)
     t_wall0 = time.perf_counter()
     e0.record(stream)
     for _ in range(args.steps):
@@ -213,15 +228,19 @@ def main():
     cyc_gbs = cyc_bytes * cycles / sec / 1e9
     roofline = None
     if not args.no_kernel_timing:
-        # dominant kernel: box relaxation on the finest level, one colour per launch
-        avg_us = solver.time_kernel(0, level=0, reps=10)
-        nbytes = sum(box_launch_bytes(cls, N, c) for c in range(5)) / 5.0
+        # dominant kernel: the finest-level box relaxation, all five colours per launch; its launches inside the
+        # timed steps were bracketed by HIP events on the solver's stream
+        avg_us, nprobe = solver.probe_stop()
+        iso_us = solver.time_kernel(5, level=0, reps=10)
+        nbytes = box_sweep_bytes(cls, N)
         achieved = nbytes / (avg_us * 1e-6) / 1e9
+        traffic = BOX_TRAFFIC_BYTES if N == 1024 else None
         roofline = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                    "frac": achieved / PEAK_HBM_GBS, "traffic": BOX_TRAFFIC_BYTES if N == 1024 else None,
-                    "kernel": "k_box<double> finest level", "bytes_per_launch": nbytes, "avg_launch_us": avg_us,
-                    "traffic_gbs": BOX_TRAFFIC_BYTES / (avg_us * 1e-6) / 1e9 if N == 1024 else None,
-                    "traffic_source": BOX_TRAFFIC_SOURCE}
+                    "frac": achieved / PEAK_HBM_GBS, "traffic": traffic,
+                    "kernel": "k_box5<double> finest level (five colours per launch)", "bytes_per_launch": nbytes,
+                    "avg_launch_us": avg_us, "launches_timed": nprobe, "isolated_launch_us": iso_us,
+                    "traffic_gbs": traffic / (avg_us * 1e-6) / 1e9 if traffic else None,
+                    "traffic_source": BOX_TRAFFIC_SOURCE if traffic else None}
     # time to 1e-8 from x = 0 on the last step's system: FP64 cycles against FP32 cycles in FP64 refinement
     u, v, p, xi = solver.get_x()
     z = np.zeros((W, W))

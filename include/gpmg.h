@@ -66,16 +66,19 @@ enum { GP_INACTIVE = 0, GP_INTERNAL = 1, GP_GHOST = 2, GP_WALL_DIRICHLET = 3, GP
  * fictitious time steps 0.9 (Dirichlet) and 0.9 h (normal derivative) (Sect. 4.1.2), extension band of 4
  * grid steps, minimum ghost-row diagonal 0.1 (below it the ghost takes an extrapolation row), and after each
  * relaxation step bnd_sweeps = 1 extra box sweep (same colour order, each followed by lambda_ghost ghost
- * sweeps) over the cells within bnd_radius = 2 cells of a cell touching the body.  The last two fields choose
- * how the same computation is laid out on the device (results agree to rounding): fuse_small_levels = 1 runs
- * the cycle of the levels with N <= 32 in one workgroup with their data in LDS, band_split_min = 3000: a
- * boundary band with at least that many cells is relaxed with device-wide launches instead of one workgroup. */
+ * sweeps) over the cells within bnd_radius = 2 cells of a cell touching the body.  The last three fields
+ * choose how the same computation is laid out on the device (results agree to rounding): fuse_small_levels = 1
+ * runs the cycle of the levels with N <= 32 in one workgroup with their data in LDS, band_split_min = 3000: a
+ * boundary band with at least that many cells is relaxed with device-wide launches instead of one workgroup,
+ * graph_iterations = 0; 1 captures the launches of one solver iteration (cycle, mean projection, residual
+ * norm) into a HIP graph at the start of each gp_solve / gp_cn_step solve and replays it every iteration
+ * (gp_probe_start turns it off while its events are live). */
 typedef struct {
   int nu1, nu2, gamma, lambda_ghost, coarsest_n, march_max, ext_radius;
   double dtau_dir, dtau_neu_over_h, bisect_eps_over_h, cg_min;
   int mixed_inner_cycles; /* FP32 cycles per FP64 refinement step in GP_MIXED solves */
   int bnd_sweeps, bnd_radius;
-  int fuse_small_levels, band_split_min;
+  int fuse_small_levels, band_split_min, graph_iterations;
 } gp_params;
 
 /* rigid motion: the body frame point of x at time t is R(-omega t) (x - X0 - U t); the boundary velocity at a
@@ -104,7 +107,9 @@ typedef struct {
 void gp_default_params(gp_params *prm);
 
 /* Create a context for an N x N cell grid and Reynolds number Re (used by gp_cn_step).  prm may be NULL
- * (defaults).  hip_stream is a hipStream_t (NULL = the default stream).  *out is NULL on error. */
+ * (defaults).  hip_stream is the hipStream_t all work of the context goes to; NULL makes the context create
+ * its own (blocking, default priority, so it orders with the null stream; destroyed by gp_destroy).  *out is
+ * NULL on error. */
 gp_status gp_setup_grid(gp_ctx **out, int N, double Re, const gp_params *prm, void *hip_stream);
 void gp_destroy(gp_ctx *ctx);
 int gp_num_levels(const gp_ctx *ctx);
@@ -168,8 +173,19 @@ gp_status gp_relax(gp_ctx *ctx, int level, int steps);
 /* measurement: average device time in microseconds of one launch of a kernel of the FP64 cycle, recorded
  * with HIP events on the context's stream around reps repetitions on the given level's current data (the data
  * are relaxed further by the box kernel; nothing else changes).  which: 0 = box relaxation (one colour per
- * launch), 1 = residual of the internal rows, 2 = restriction, 3 = prolongation, 4 = ghost sweeps. */
+ * launch), 1 = residual of the internal rows, 2 = restriction, 3 = prolongation, 4 = ghost sweeps, 5 = box
+ * relaxation, all five colours in one launch (tiles in LDS; GP_EINVAL where the level does not use it). */
 gp_status gp_time_kernel(gp_ctx *ctx, int which, int level, int reps, double *avg_us);
+
+/* measurement inside a run: gp_probe_start creates 2*max_launches HIP events (1 <= max_launches <= 65536) and
+ * from then on the FP64 cycle launches each finest-level five-colour box sweep with a pair of them that take the
+ * start and end times of that dispatch on the context's stream (hipExtLaunchKernel), up to max_launches
+ * launches (later launches are not recorded).  gp_probe_stop waits for the last
+ * recorded event, writes the average device time of the recorded launches in microseconds (0 if none) and
+ * their number, and destroys the events.  A second gp_probe_start discards the pairs of the first.  GP_EHIP
+ * if the events fail. */
+gp_status gp_probe_start(gp_ctx *ctx, int max_launches);
+gp_status gp_probe_stop(gp_ctx *ctx, double *avg_us, int *launches);
 
 /* ---- transposed system (the adjoint of the augmented system of Sect. 3.3, eq. (spaceprobaug)) ----
  * Vectors are full unknown vectors of the finest level, n = 3*W*W + 1 doubles: the u, v and p grids (W*W each,

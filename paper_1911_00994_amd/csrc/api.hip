@@ -89,6 +89,7 @@ void gp_default_params(gp_params *p) {
   p->bnd_radius = 2;
   p->fuse_small_levels = 1;
   p->band_split_min = 3000;
+  p->graph_iterations = 0;
 }
 
 const char *gp_strerror(gp_status st) {
@@ -116,6 +117,7 @@ void gp_destroy(gp_ctx *ctx) {
     dfree(G.cls);
     dfree(G.g_pt);
     dfree(G.g_col);
+    dfree(G.g_colr);
     dfree(G.g_w);
     dfree(G.g_dtau);
     dfree(G.g_B);
@@ -153,8 +155,14 @@ void gp_destroy(gp_ctx *ctx) {
   dfree(ctx->a_g);
   dfree(ctx->a_lam);
   tape_free(ctx);
+  for (auto &g : ctx->g_iter)
+    if (g) (void)hipGraphExecDestroy(g);
+  for (auto e : ctx->probe_ev)
+    if (e) (void)hipEventDestroy(e);
+  ctx->probe_ev.clear();
   dfree(ctx->phi);
   dfree(ctx->gtmp);
+  dfree(ctx->gtmp2);
   dfree(ctx->d_red);
   dfree(ctx->d_ticket);
   dfree(ctx->d_scal);
@@ -177,6 +185,7 @@ void gp_destroy(gp_ctx *ctx) {
   dfree(ctx->cku);
   dfree(ctx->ckv);
   dfree(ctx->fwork);
+  if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
   delete ctx;
 }
 
@@ -198,7 +207,15 @@ gp_status gp_setup_grid(gp_ctx **out, int N, double Re, const gp_params *prm, vo
   ctx->prm = P;
   ctx->small_cycles = P.fuse_small_levels ? 1 : 0;
   ctx->band_split_min = P.band_split_min;
+  ctx->graphs = P.graph_iterations ? 1 : 0;
   ctx->stream = (hipStream_t)hip_stream;
+  if (!ctx->stream) {  // graphs are captured from the context's stream, which cannot be the null stream
+    if (hipStreamCreate(&ctx->stream) != hipSuccess) {
+      delete ctx;
+      return GP_EHIP;
+    }
+    ctx->own_stream = true;
+  }
   int L = 0;
   for (int n = N; n >= P.coarsest_n; n /= 2) {
     Geo &G = ctx->geo[L];
@@ -227,6 +244,7 @@ gp_status gp_setup_grid(gp_ctx **out, int N, double Re, const gp_params *prm, vo
     ALLOC(G.cls, (size_t)3 * G.WW);
     ALLOC(G.g_pt, (size_t)G.gcap);
     ALLOC(G.g_col, (size_t)9 * G.gcap);
+    ALLOC(G.g_colr, (size_t)9 * G.gcap);
     ALLOC(G.g_w, (size_t)9 * G.gcap);
     ALLOC(G.g_dtau, (size_t)G.gcap);
     ALLOC(G.g_B, (size_t)2 * G.gcap);
@@ -260,11 +278,12 @@ gp_status gp_setup_grid(gp_ctx **out, int N, double Re, const gp_params *prm, vo
   }
   ALLOC(ctx->phi, (size_t)(2 * N + 1) * (2 * N + 1));
   ALLOC(ctx->gtmp, gmax);
+  ALLOC(ctx->gtmp2, gmax);
   ALLOC(ctx->d_red, 8192);
   ALLOC(ctx->d_ticket, 4);
   ALLOC(ctx->d_scal, 16);
   ALLOC(ctx->d_lev, 2 * MAXLEV);
-  ALLOC(ctx->d_bcnt, (size_t)5 * nblk((long)(N + 2) * (N + 2)) + 8);
+  ALLOC(ctx->d_bcnt, (size_t)8 * nblk((long)(N + 2) * (N + 2)) + 16);  // two scans of 3 (N+2)^2 points, or 5 colours
   ALLOC(ctx->d_iscr, (size_t)3 * (N + 2) * (N + 2) + 1);
   ALLOC(ctx->d_flags, 16);
   GP_HIP(hipMemsetAsync(ctx->d_ticket, 0, 4 * sizeof(unsigned), ctx->stream));
@@ -536,6 +555,16 @@ gp_status gp_relax(gp_ctx *ctx, int level, int steps) {
 gp_status gp_time_kernel(gp_ctx *ctx, int which, int level, int reps, double *avg_us) {
   if (!ctx || !ctx->have_geom || level < 0 || level >= ctx->L || reps < 1 || !avg_us) return GP_EINVAL;
   return time_kernel(ctx, which, level, reps, avg_us);
+}
+
+gp_status gp_probe_start(gp_ctx *ctx, int max_launches) {
+  if (!ctx || max_launches < 1 || max_launches > (1 << 16)) return GP_EINVAL;
+  return probe_start(ctx, max_launches);
+}
+
+gp_status gp_probe_stop(gp_ctx *ctx, double *avg_us, int *launches) {
+  if (!ctx || !avg_us || !launches) return GP_EINVAL;
+  return probe_stop(ctx, avg_us, launches);
 }
 
 }  // extern "C"

@@ -582,12 +582,51 @@ __global__ void k_row_of(const int *g_pt, int ng, int *row_of) {
   int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r < ng) row_of[g_pt[r]] = r;
 }
+// the columns of the ghost rows with every ghost point replaced by -(its row + 1) (row_of from k_row_of; every
+// ghost, extrapolated-ghost and wall-ghost point has a row; a column whose row cannot be confirmed is reported)
+__global__ void k_colr(const uint8_t *cls, const int *g_pt, const int *g_col, int ng, const int *row_of, int *g_colr,
+                       int *bad) {
+  int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= 9 * ng) return;
+  int c = g_col[e];
+  uint8_t k = cls[c];
+  if (k == K_GHOST || k == K_GHOSTX || k == K_WALLG) {
+    int r = row_of[c];
+    if (r >= 0 && r < ng && g_pt[r] == c) {
+      g_colr[e] = -(r + 1);
+      return;
+    }
+    atomicOr(bad, 1);
+  }
+  g_colr[e] = c;
+}
 __global__ void k_region_clear(int *map, int n) {
   int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t < n) map[t] = -1;
 }
+// mark: map[k] = -3 for every point the band kernel reads (the 21 values of a band box, the 9 columns of a body
+// ghost row), wall ghost points excluded: the kernel's other workgroups write them.  Launched before k_region_mark,
+// which marks the written points over these.
+__global__ void k_region_mark_reads(const uint8_t *cls, int N, int W, const int *band, int nband, const int *g_pt,
+                                    const int *g_col, int ng, int *map) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < nband) {
+    int cell = band[t], i = cell % N, j = cell / N, c = (j + 1) * W + (i + 1);
+    int pts[21];
+    box_points(W, c, pts);
+    for (int q = 0; q < 21; q++)
+      if (cls[pts[q]] != K_WALLG) map[pts[q]] = -3;
+  } else if (t < nband + ng) {
+    int r = t - nband;
+    if (cls[g_pt[r]] == K_WALLG) return;
+    for (int q = 0; q < 9; q++) {
+      int c = g_col[9 * r + q];
+      if (cls[c] != K_WALLG) map[c] = -3;
+    }
+  }
+}
 // mark: map[k] = -2 for every point the band kernel writes (the five unknowns of a band box, body ghost points);
-// every other point it reads is constant during the kernel and is read from global memory
+// the points it only reads are constant during the kernel
 __global__ void k_region_mark(const uint8_t *cls, int N, int W, const int *band, int nband, const int *g_pt, int ng,
                               int *map) {
   int t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -605,9 +644,10 @@ __global__ void k_region_mark(const uint8_t *cls, int N, int W, const int *band,
     map[g_pt[r]] = -2;
   }
 }
-// region points and body ghost points in ascending index order
+// written region points (mode 0), body ghost points (mode 1) and read-only region points (mode 2), each in
+// ascending index order
 __device__ __forceinline__ bool region_pred(int mode, const int *map, const uint8_t *cls, int t) {
-  return mode == 0 ? map[t] == -2 : (cls[t] == K_GHOST || cls[t] == K_GHOSTX);
+  return mode == 0 ? map[t] == -2 : mode == 2 ? map[t] == -3 : (cls[t] == K_GHOST || cls[t] == K_GHOSTX);
 }
 __global__ void __launch_bounds__(TPB) k_pred_count(int mode, int n, const int *map, const uint8_t *cls, int *bcnt) {
   int t = blockIdx.x * TPB + threadIdx.x;
@@ -615,12 +655,13 @@ __global__ void __launch_bounds__(TPB) k_pred_count(int mode, int n, const int *
   block_excl_scan(t < n && region_pred(mode, map, cls, t) ? 1 : 0, &tot);
   if (threadIdx.x == 0) bcnt[blockIdx.x] = tot;
 }
+// out[*base + rank] = t for the points that satisfy the predicate (base: a device count, or null for 0)
 __global__ void __launch_bounds__(TPB) k_pred_fill(int mode, int n, const int *map, const uint8_t *cls, const int *boff,
-                                                   int cap, int *out) {
+                                                   int cap, int *out, const int *base) {
   int t = blockIdx.x * TPB + threadIdx.x;
   bool take = t < n && region_pred(mode, map, cls, t);
   int tot;
-  int q = boff[blockIdx.x] + block_excl_scan(take ? 1 : 0, &tot);
+  int q = (base ? *base : 0) + boff[blockIdx.x] + block_excl_scan(take ? 1 : 0, &tot);
   if (take && q < cap) out[q] = t;
 }
 __global__ void k_region_slots(const int *reg_pt, int nreg, int *map) {
@@ -667,17 +708,18 @@ __global__ void k_region_rows(const uint8_t *cls, const int *g_col, const double
 }
 // wall ghost rows (order free: each is relaxed on its own); a wall row whose nodes a band box writes or whose
 // stencil holds another ghost is reported
-__global__ void k_wall_rows(const uint8_t *cls, const int *g_pt, const int *g_col, int ng, const int *map, int *wg_rows,
-                            int *count, int *bad) {
+__global__ void k_wall_rows(const uint8_t *cls, const int *g_pt, const int *g_col, int ng, const int *map, int nw,
+                            int *wg_rows, int *count, int *bad) {
   int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= ng) return;
   int k = g_pt[r];
   if (cls[k] != K_WALLG) return;
+  auto written = [&](int c) { return map[c] >= 0 && map[c] < nw; };  // slots past nw are only read
   for (int q = 0; q < 9; q++) {
     int c = g_col[9 * r + q];
-    if (c != k && (map[c] >= 0 || cls[c] == K_GHOST || cls[c] == K_GHOSTX || cls[c] == K_WALLG)) atomicOr(bad, 2);
+    if (c != k && (written(c) || cls[c] == K_GHOST || cls[c] == K_GHOSTX || cls[c] == K_WALLG)) atomicOr(bad, 2);
   }
-  if (map[k] >= 0) atomicOr(bad, 2);
+  if (map[k] >= 0) atomicOr(bad, 2);  // no wall ghost point is in the region
   wg_rows[atomicAdd(count, 1)] = r;
 }
 
@@ -886,18 +928,32 @@ static gp_status build_level(Ctx *ctx, int l) {
   }
   // boundary region of the LDS band kernel
   G.lds_ok = 0;
-  G.nreg = G.nbg = G.nwg = 0;
+  G.nreg = G.nregw = G.nbg = G.nwg = 0;
   if (G.nband > 0 && G.nband <= G.bcap) {
     const int P3 = 3 * W * W, nbr = nblk(P3);
     const int regcap = G.gcap * 12 + 32 * G.N + 4096;
+    int *cnt2 = ctx->d_bcnt + nbr + 1;  // block counts of the read-only points
     k_region_clear<<<nblk(P3 + 1), TPB, 0, s>>>(G.reg_map, P3 + 1);
+    k_region_mark_reads<<<nblk(G.nband + G.ng), TPB, 0, s>>>(G.cls, G.N, W, G.band, G.nband, G.g_pt, G.g_col, G.ng,
+                                                             G.reg_map);
     k_region_mark<<<nblk(G.nband + G.ng), TPB, 0, s>>>(G.cls, G.N, W, G.band, G.nband, G.g_pt, G.ng, G.reg_map);
+    // the written points, then the read-only points after them
     k_pred_count<<<nbr, TPB, 0, s>>>(0, P3, G.reg_map, G.cls, ctx->d_bcnt);
     k_scan_blocks<<<1, SCAN_T, 0, s>>>(ctx->d_bcnt, nbr);
-    k_pred_fill<<<nbr, TPB, 0, s>>>(0, P3, G.reg_map, G.cls, ctx->d_bcnt, regcap, G.reg_pt);
+    k_pred_fill<<<nbr, TPB, 0, s>>>(0, P3, G.reg_map, G.cls, ctx->d_bcnt, regcap, G.reg_pt, nullptr);
+    k_pred_count<<<nbr, TPB, 0, s>>>(2, P3, G.reg_map, G.cls, cnt2);
+    k_scan_blocks<<<1, SCAN_T, 0, s>>>(cnt2, nbr);
+    k_pred_fill<<<nbr, TPB, 0, s>>>(2, P3, G.reg_map, G.cls, cnt2, regcap, G.reg_pt, ctx->d_bcnt + nbr);
     GP_HIP(hipGetLastError());
-    GP_HIP(hipMemcpyAsync(&G.nreg, ctx->d_bcnt + nbr, sizeof(int), hipMemcpyDeviceToHost, s));
+    int nr = 0;
+    GP_HIP(hipMemcpyAsync(&G.nregw, ctx->d_bcnt + nbr, sizeof(int), hipMemcpyDeviceToHost, s));
+    GP_HIP(hipMemcpyAsync(&nr, cnt2 + nbr, sizeof(int), hipMemcpyDeviceToHost, s));
     GP_HIP(hipStreamSynchronize(s));
+    // the read-only points are staged too when they fit (FP64 values and the body ghost rows' new values in LDS);
+    // otherwise their map entries stay negative and the kernel reads them from global memory
+    const bool rd = G.nregw + nr <= regcap &&
+                    (size_t)(G.nregw + nr) * sizeof(double) + (size_t)G.ng * sizeof(double) + 2048 <= ctx->max_lds;
+    G.nreg = rd ? G.nregw + nr : G.nregw;
     if (G.nreg <= regcap) {
       GP_HIP(hipMemsetAsync(ctx->d_flags + 10, 0, 2 * sizeof(int), s));
       k_region_slots<<<nblk(G.nreg), TPB, 0, s>>>(G.reg_pt, G.nreg, G.reg_map);
@@ -906,7 +962,7 @@ static gp_status build_level(Ctx *ctx, int l) {
       // body ghost rows in point order
       k_pred_count<<<nbr, TPB, 0, s>>>(1, P3, G.reg_map, G.cls, ctx->d_bcnt);
       k_scan_blocks<<<1, SCAN_T, 0, s>>>(ctx->d_bcnt, nbr);
-      k_pred_fill<<<nbr, TPB, 0, s>>>(1, P3, G.reg_map, G.cls, ctx->d_bcnt, G.gcap, G.bg_k);
+      k_pred_fill<<<nbr, TPB, 0, s>>>(1, P3, G.reg_map, G.cls, ctx->d_bcnt, G.gcap, G.bg_k, nullptr);
       if (G.ng) k_row_of<<<nblk(G.ng), TPB, 0, s>>>(G.g_pt, G.ng, ctx->d_iscr);
       GP_HIP(hipGetLastError());
       GP_HIP(hipMemcpyAsync(&G.nbg, ctx->d_bcnt + nbr, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -916,8 +972,8 @@ static gp_status build_level(Ctx *ctx, int l) {
         k_region_rows<<<nblk(G.nbg), TPB, 0, s>>>(G.cls, G.g_col, G.g_w, G.g_dtau, ctx->d_iscr, G.reg_map, G.nbg, G.gcap,
                                                   G.bg_k, G.bg_loc, G.bg_w, G.bg_dt, ctx->d_flags + 11);
       if (G.ng)
-        k_wall_rows<<<nblk(G.ng), TPB, 0, s>>>(G.cls, G.g_pt, G.g_col, G.ng, G.reg_map, G.wg_rows, ctx->d_flags + 10,
-                                               ctx->d_flags + 11);
+        k_wall_rows<<<nblk(G.ng), TPB, 0, s>>>(G.cls, G.g_pt, G.g_col, G.ng, G.reg_map, G.nregw, G.wg_rows,
+                                               ctx->d_flags + 10, ctx->d_flags + 11);
       GP_HIP(hipGetLastError());
       int hr[2];
       GP_HIP(hipMemcpyAsync(hr, ctx->d_flags + 10, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
@@ -926,6 +982,12 @@ static gp_status build_level(Ctx *ctx, int l) {
       G.lds_ok = hr[1] == 0 ? 1 : 0;
     }
   }
+  // ghost columns by row (the double-buffered ghost sweeps of the device-wide band path)
+  if (G.ng) {
+    GP_HIP(hipMemsetAsync(ctx->d_flags + 12, 0, sizeof(int), s));
+    k_row_of<<<nblk(G.ng), TPB, 0, s>>>(G.g_pt, G.ng, ctx->d_iscr);
+    k_colr<<<nblk(9L * G.ng), TPB, 0, s>>>(G.cls, G.g_pt, G.g_col, G.ng, ctx->d_iscr, G.g_colr, ctx->d_flags + 12);
+  }
   // boundary faces of the internal pressure cells (and their band-region entries)
   {
     int nb = nblk((long)G.N * G.N);
@@ -933,8 +995,11 @@ static gp_status build_level(Ctx *ctx, int l) {
     k_scan_blocks<<<1, SCAN_T, 0, s>>>(ctx->d_bcnt, nb);
     k_face_fill<<<nb, TPB, 0, s>>>(G.cls, G.N, W, ctx->d_bcnt, G.fcap, G.f_code);
     GP_HIP(hipGetLastError());
+    int cb = 1;
     GP_HIP(hipMemcpyAsync(&G.nf, ctx->d_bcnt + nb, sizeof(int), hipMemcpyDeviceToHost, s));
+    if (G.ng) GP_HIP(hipMemcpyAsync(&cb, ctx->d_flags + 12, sizeof(int), hipMemcpyDeviceToHost, s));
     GP_HIP(hipStreamSynchronize(s));
+    G.colr_ok = G.ng > 0 && cb == 0;
     if (G.nf > G.fcap) return GP_ENOMEM;
     if (G.lds_ok && G.nf) k_face_loc<<<nblk(G.nf), TPB, 0, s>>>(G.f_code, G.nf, G.reg_map, G.f_loc);
   }

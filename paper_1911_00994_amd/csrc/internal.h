@@ -35,6 +35,7 @@ struct Geo {
   int ng = 0, gcap = 0;
   int *g_pt = nullptr;              // global unknown index
   int *g_col = nullptr;             // 9 per row
+  int *g_colr = nullptr;            // g_col with every ghost point given as -(its row + 1)
   double *g_w = nullptr;            // 9 per row
   double *g_dtau = nullptr;
   double *g_B = nullptr, *g_nB = nullptr, *g_th = nullptr;  // 2 per row
@@ -57,8 +58,9 @@ struct Geo {
   int *reg_pt = nullptr, *reg_map = nullptr, *bbox = nullptr, *bg_k = nullptr, *bg_loc = nullptr, *wg_rows = nullptr;
   double *bg_w = nullptr, *bg_dt = nullptr;
   int bcap = 0;
-  int nreg = 0, nbg = 0, nwg = 0;
+  int nreg = 0, nregw = 0, nbg = 0, nwg = 0;  // region points (the first nregw are written), body and wall rows
   int lds_ok = 0;                   // 1 when the LDS band kernel applies to this level
+  int colr_ok = 0;                  // 1 when g_colr holds the row of every ghost column
   // faces on the boundary of the internal pressure cells, cell-major order: code = 2 * (u or v index) + (1 if the
   // face enters the cell's divergence with a minus sign); f_loc = the same face as an LDS band-region entry
   int *f_code = nullptr, *f_loc = nullptr;
@@ -103,6 +105,7 @@ struct Ctx {
   double Re = 100, alpha = 0;
   gp_params prm{};
   hipStream_t stream = nullptr;
+  bool own_stream = false;  // created by the context (the caller passed none)
   std::string hip_err;
   Geo geo[MAXLEV];
   Vec<double> v64[MAXLEV];
@@ -111,7 +114,7 @@ struct Ctx {
   double *a_g = nullptr, *a_lam = nullptr;  // transposed solve: right-hand side and solution (finest)
   Tape tape;
   double *phi = nullptr;            // fine half lattice (2N+1)^2
-  double *gtmp = nullptr;           // ghost Jacobi scratch (max gcap)
+  double *gtmp = nullptr, *gtmp2 = nullptr;  // ghost Jacobi scratch, row-indexed (max gcap each)
   // reductions / flags
   double *d_red = nullptr;          // partial sums (blocks) scratch
   unsigned int *d_ticket = nullptr; // last-block tickets
@@ -143,6 +146,12 @@ struct Ctx {
   int small_cycles = 1;             // run the levels with N <= 32 as one workgroup when they fit in LDS
   int band_split_min = 3000;        // bands with at least this many cells use device-wide launches
   int box_tiles = 1;                // all five colours of a box sweep in one launch (LDS tiles with halos)
+  // launch probe: HIP event pairs around the finest-level five-colour box launches of the FP64 cycle
+  std::vector<hipEvent_t> probe_ev;
+  int probe_n = 0;
+  // one solver iteration as an executable HIP graph, per precision (captured per solve, updated in place)
+  int graphs = 1;
+  hipGraphExec_t g_iter[2] = {nullptr, nullptr};
 };
 
 // error handling
@@ -170,6 +179,8 @@ gp_status relax64(Ctx *ctx, int level, int steps);
 gp_status residual64(Ctx *ctx, int level, double *res_inf);
 gp_status set_wall_dirichlet(Ctx *ctx);
 gp_status time_kernel(Ctx *ctx, int which, int level, int reps, double *avg_us);
+gp_status probe_start(Ctx *ctx, int max_launches);
+gp_status probe_stop(Ctx *ctx, double *avg_us, int *launches);
 
 // adjoint (adjoint.hip)
 gp_status adjoint_alloc(Ctx *ctx);

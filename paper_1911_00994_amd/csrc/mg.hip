@@ -7,6 +7,8 @@
 #include <cmath>
 #include <cstring>
 
+#include <hip/hip_ext.h>
+
 #include "internal.h"
 
 namespace gpmg {
@@ -143,6 +145,31 @@ __device__ __forceinline__ void box_update(int W, const BoxK &K, const uint8_t *
   if (fN) v[c + W] = (T)o.vN;
 }
 
+// the same update with the five right-hand sides of the box passed in (W E S N P)
+template <typename T>
+__device__ __forceinline__ void box_update_rb(int W, const BoxK &K, const uint8_t *__restrict__ cls, T *__restrict__ x,
+                                              const double (&bb)[5], int i, int j) {
+  const int WW = W * W;
+  T *u = x, *v = x + WW, *p = x + 2 * WW;
+  const int c = (j + 1) * W + (i + 1);
+  const uint8_t kW = cls[c], kE = cls[c + 1], kS = cls[WW + c], kN = cls[WW + c + W], kP = cls[2 * WW + c];
+  const double uW = u[c], uE = u[c + 1], vS = v[c], vN = v[c + W], pc = p[c];
+  const double uWW = u[c - 1], uEE = u[c + 2], uWS = u[c - W], uWN = u[c + W], uES = u[c + 1 - W], uEN = u[c + 1 + W];
+  const double vSS = v[c - W], vNN = v[c + 2 * W], vSW = v[c - 1], vSE = v[c + 1], vNW = v[c + W - 1], vNE = v[c + W + 1];
+  const double pW = p[c - 1], pE = p[c + 1], pS = p[c - W], pN = p[c + W];
+  const double xi = (double)x[3 * WW];
+  const bool fW = kW == K_INT, fE = kE == K_INT, fS = kS == K_INT, fN = kN == K_INT, fP = kP == K_INT;
+  if (!(fW || fE || fS || fN || fP)) return;
+  const BoxNew o = box_core(K, fW, fE, fS, fN, fP, uW, uE, uWW, uEE, uWS, uWN, uES, uEN, vS, vN, vSS, vNN, vSW, vSE, vNW,
+                            vNE, pc, pW, pE, pS, pN, bb[0], bb[1], bb[2], bb[3], bb[4], xi);
+  if (o.skip) return;
+  if (fP) p[c] = (T)o.p;
+  if (fW) u[c] = (T)o.uW;
+  if (fE) u[c + 1] = (T)o.uE;
+  if (fS) v[c] = (T)o.vS;
+  if (fN) v[c + W] = (T)o.vN;
+}
+
 template <typename T>
 __global__ void __launch_bounds__(TPB) k_box(int N, int W, BoxK BK, const uint8_t *__restrict__ cls,
                                              T *__restrict__ x, const T *__restrict__ b, int colour) {
@@ -161,57 +188,89 @@ __global__ void __launch_bounds__(TPB) k_box(int N, int W, BoxK BK, const uint8_
 
 // ---------------------------------------------------------------------------------------------------------
 // all five colours of a box sweep in one launch (temporal blocking).  A workgroup owns a BT x BT tile of cells
-// and stages the points of the tile widened by BH = 10 cells (x, b, classes) in LDS.  Pass k (colour k) updates
-// the boxes of colour k within 1 + 2 (4 - k) cells of the tile: a box depends only on boxes within 2 cells
-// written in earlier passes, so every box computed in pass k sees exactly the values the colour-by-colour sweep
-// gives it, and the boxes that write the tile's own points (u, v, p of its cells: the west and south faces and
-// the centre) are all computed in every pass.  The sweep reads x and writes a second buffer y: every point is
-// owned by one tile (the border rows and columns -1 and N by the tiles next to them), so y receives every point
-// once, and no workgroup can see another one's new values while staging its halo.  The caller swaps x and y.
+// and stages x and the classes of the points of the tile widened by BH = 10 cells in LDS.  Pass k (colour k)
+// updates the boxes of colour k within 1 + 2 (4 - k) cells of the tile: a box depends only on boxes within 2
+// cells written in earlier passes, so every box computed in pass k sees exactly the values the colour-by-colour
+// sweep gives it, and the boxes that write the tile's own points (u, v, p of its cells: the west and south faces
+// and the centre) are all computed in every pass.  A pass has at most 500 boxes, one per thread, so each thread
+// loads the right-hand sides of its five boxes into registers while the tile is staged (b needs no LDS, and two
+// workgroups fit on a compute unit).  The sweep reads x and writes a second buffer y: every point is owned by
+// one tile (the border rows and columns -1 and N by the tiles next to them), so y receives every point once,
+// and no workgroup can see another one's new values while staging its halo.  The caller swaps x and y.
+// Tiles are dealt to the 8 XCDs in contiguous runs (when their number is a multiple of 8), so the halos that
+// neighbouring tiles share are fetched into the same L2.
 // ---------------------------------------------------------------------------------------------------------
 constexpr int BT = 32, BH = 10, BRW = BT + 2 * BH + 1, BRWW = BRW * BRW;  // 53 x 53 staged points
 constexpr int B5_T = 512;
+static_assert((BT + 2 * (1 + 2 * 4) + 4) / 5 * (BT + 2 * (1 + 2 * 4)) <= B5_T, "one box per thread and pass");
 template <typename T>
 __host__ __device__ constexpr size_t box5_lds() {
-  return ((3 * BRWW + 1) * sizeof(T) + 15) / 16 * 16 + (3 * BRWW * sizeof(T) + 15) / 16 * 16 + 3 * BRWW;
+  return ((3 * BRWW + 1) * sizeof(T) + 15) / 16 * 16 + 3 * BRWW;
 }
 template <typename T>
-__global__ void __launch_bounds__(B5_T) k_box5(int N, int W, BoxK K, const uint8_t *__restrict__ cls,
-                                               const T *__restrict__ x, const T *__restrict__ b, T *__restrict__ y) {
+__global__ void __launch_bounds__(B5_T, 2) k_box5(int N, int W, BoxK K, const uint8_t *__restrict__ cls,
+                                                  const T *__restrict__ x, const T *__restrict__ b, T *__restrict__ y) {
   extern __shared__ unsigned char lds_raw[];
   T *xs = reinterpret_cast<T *>(lds_raw);
-  T *bs = reinterpret_cast<T *>(lds_raw + ((3 * BRWW + 1) * sizeof(T) + 15) / 16 * 16);
-  uint8_t *cs = lds_raw + ((3 * BRWW + 1) * sizeof(T) + 15) / 16 * 16 + (3 * BRWW * sizeof(T) + 15) / 16 * 16;
-  const int WW = W * W, nt = (N + BT - 1) / BT;
-  const int i0 = (blockIdx.x % nt) * BT, j0 = (blockIdx.x / nt) * BT;
+  uint8_t *cs = lds_raw + ((3 * BRWW + 1) * sizeof(T) + 15) / 16 * 16;
+  const int WW = W * W, nt = (N + BT - 1) / BT, ntt = nt * nt;
+  const int tile = (ntt & 7) ? blockIdx.x : (blockIdx.x & 7) * (ntt >> 3) + (blockIdx.x >> 3);
+  const int i0 = (tile % nt) * BT, j0 = (tile / nt) * BT;
   const int gi0 = i0 - BH, gj0 = j0 - BH;  // point (gi0, gj0) sits at LDS point (0, 0)
-  for (int e = threadIdx.x; e < 3 * BRWW; e += B5_T) {
-    int g = e / BRWW, q = e - g * BRWW, pj = q / BRW, pi = q - pj * BRW;
-    int gi = gi0 + pi, gj = gj0 + pj;
-    if (gi >= -1 && gi <= N && gj >= -1 && gj <= N) {
-      int k = g * WW + (gj + 1) * W + (gi + 1);
-      xs[e] = x[k];
-      bs[e] = b[k];
-      cs[e] = cls[k];
-    } else {
-      xs[e] = (T)0;
-      bs[e] = (T)0;
-      cs[e] = K_INACTIVE;
+  // this thread's box in each pass (cell i, j; i = -1 for none) and its right-hand sides
+  int bi[5], bj[5];
+  double bb[5][5];
+#pragma unroll
+  for (int k = 0; k < 5; k++) {
+    const int ex = 1 + 2 * (4 - k);
+    const int ilo = max(0, i0 - ex), ihi = min(N, i0 + BT + ex), jlo = max(0, j0 - ex), jhi = min(N, j0 + BT + ex);
+    const int per = (ihi - ilo + 4) / 5;  // colour-k cells per row, at most
+    const int t = threadIdx.x, r = t / max(per, 1), m = t - r * per, j = jlo + r;
+    const int i = ilo + ((k - (ilo + 2 * j)) % 5 + 5) % 5 + 5 * m;
+    const bool on = per > 0 && j < jhi && i < ihi;
+    bi[k] = on ? i : -1;
+    bj[k] = j;
+    const int c = on ? (j + 1) * W + (i + 1) : 0;
+    bb[k][0] = (double)b[c];
+    bb[k][1] = (double)b[c + 1];
+    bb[k][2] = (double)b[WW + c];
+    bb[k][3] = (double)b[WW + c + W];
+    bb[k][4] = (double)b[2 * WW + c];
+  }
+  // staging: batches of B5_B points per thread, all their loads issued before any LDS store
+  constexpr int B5_B = 6;
+  for (int e0 = threadIdx.x; e0 < 3 * BRWW; e0 += B5_B * B5_T) {
+    int kk[B5_B];
+    T xv[B5_B];
+    uint8_t cv[B5_B];
+#pragma unroll
+    for (int u = 0; u < B5_B; u++) {
+      int e = e0 + u * B5_T;
+      int g = e / BRWW, q = e - g * BRWW, pj = q / BRW, pi = q - pj * BRW;
+      int gi = gi0 + pi, gj = gj0 + pj;
+      kk[u] = (e < 3 * BRWW && gi >= -1 && gi <= N && gj >= -1 && gj <= N) ? g * WW + (gj + 1) * W + (gi + 1) : -1;
+    }
+#pragma unroll
+    for (int u = 0; u < B5_B; u++) {
+      int k = kk[u] >= 0 ? kk[u] : 0;
+      xv[u] = x[k];
+      cv[u] = cls[k];
+    }
+#pragma unroll
+    for (int u = 0; u < B5_B; u++) {
+      int e = e0 + u * B5_T;
+      if (e >= 3 * BRWW) continue;
+      bool in = kk[u] >= 0;
+      xs[e] = in ? xv[u] : (T)0;
+      cs[e] = in ? cv[u] : (uint8_t)K_INACTIVE;
     }
   }
   if (threadIdx.x == 0) xs[3 * BRWW] = x[3 * WW];
   __syncthreads();
+#pragma unroll
   for (int k = 0; k < 5; k++) {
-    const int ex = 1 + 2 * (4 - k);
-    const int ilo = max(0, i0 - ex), ihi = min(N, i0 + BT + ex), jlo = max(0, j0 - ex), jhi = min(N, j0 + BT + ex);
-    const int per = (ihi - ilo + 4) / 5 + 1;  // colour-k cells per row, at most
-    for (int t = threadIdx.x; t < per * (jhi - jlo); t += B5_T) {
-      int r = t / per, m = t - r * per, j = jlo + r;
-      int i = ilo + ((k - (ilo + 2 * j)) % 5 + 5) % 5 + 5 * m;
-      if (i >= ihi) continue;
-      // LDS cell coordinates: point index of cell i is i - gi0, and box_update takes the cell as point - 1
-      box_update<T>(BRW, K, cs, xs, bs, i - gi0 - 1, j - gj0 - 1);
-    }
+    // LDS cell coordinates: point index of cell i is i - gi0, and the update takes the cell as point - 1
+    if (bi[k] >= 0) box_update_rb<T>(BRW, K, cs, xs, bb[k], bi[k] - gi0 - 1, bj[k] - gj0 - 1);
     __syncthreads();
   }
   // owned points: the tile's cells, plus the border row / column -1 or N next to it
@@ -254,6 +313,36 @@ template <typename T>
 __global__ void k_ghost_b(const int *__restrict__ pt, int ng, const double *__restrict__ tmp, T *__restrict__ x) {
   int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r < ng) x[pt[r]] = (T)tmp[r];
+}
+
+// one simultaneous sweep of every ghost row reading the old ghost values from prev (row-indexed; null: from x)
+// and writing the new ones to next (row-indexed, stored as T values; null: into x).  With prev given, every ghost
+// value the sweep reads comes from prev (colr gives ghost columns as -(row + 1)), so writing x in place is safe;
+// the arithmetic is that of k_ghost_a followed by k_ghost_b.
+template <typename T>
+__global__ void k_ghost_sweep2(const int *__restrict__ pt, const int *__restrict__ col, const int *__restrict__ colr,
+                               const double *__restrict__ w, const double *__restrict__ dtau, int ng, T *x,
+                               const T *__restrict__ b, const double *__restrict__ prev, double *__restrict__ next) {
+  int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= ng) return;
+  int k = pt[r];
+  double sum = 0;
+  if (prev) {
+#pragma unroll
+    for (int z = 0; z < 9; z++) {
+      int c = colr[9 * r + z];
+      sum += w[9 * r + z] * (c < 0 ? prev[-c - 1] : (double)x[c]);
+    }
+  } else {
+#pragma unroll
+    for (int z = 0; z < 9; z++) sum += w[9 * r + z] * (double)x[col[9 * r + z]];
+  }
+  const double old = prev ? prev[r] : (double)x[k];
+  const T nv = (T)(old + dtau[r] * ((double)b[k] - sum));
+  if (next)
+    next[r] = (double)nv;
+  else
+    x[k] = nv;
 }
 
 // all lambda sweeps in one workgroup: Jacobi phases separated by barriers (global memory, same CU)
@@ -357,7 +446,8 @@ __device__ double band_block_sum(double v) {
 
 // One relaxation step's work after the five box sweeps, in one workgroup:
 //  - workgroup 0: the body ghost rows and the band boxes as in k_band_sweeps, with the values the kernel writes
-//    staged in LDS (every other value it reads is constant during the kernel and comes from global memory), then
+//    staged in LDS (region slots [0, nregw), written back at the end) and, when they fit, the values it only reads
+//    (slots [nregw, nreg); they are constant during the kernel, and any others come from global memory), then
 //    xi <- mean over internal cells of (div u - g) from the boundary faces of the internal cells;
 //  - the other workgroups: the wall ghost rows, all lambda (1 + sweeps) of their Jacobi sweeps at once (they read
 //    only internal points next to the walls, which no band box writes, and neither a body ghost row nor a listed
@@ -369,9 +459,10 @@ struct BandOff {
 template <typename T>
 __global__ void __launch_bounds__(BAND_T) k_band_lds(int N, int W, BoxK K, T *x, const T *__restrict__ b,
                                                      BandOff off, const int *__restrict__ bbox, int bcap,
-                                                     const int *__restrict__ reg_pt, int nreg, const int *__restrict__ bg_k,
+                                                     const int *__restrict__ reg_pt, int nreg, int nregw,
+                                                     const int *__restrict__ bg_k,
                                                      const int *__restrict__ bg_loc, const double *__restrict__ bg_w,
-                                                     const double *__restrict__ bg_dt, int nbg, int gcap, double *nvbuf,
+                                                     const double *__restrict__ bg_dt, int nbg, int gcap,
                                                      const int *__restrict__ g_pt, const int *__restrict__ g_col,
                                                      const double *__restrict__ g_w, const double *__restrict__ g_dtau,
                                                      const int *__restrict__ wg_rows, int nwg, int sweeps, int lambda,
@@ -379,6 +470,8 @@ __global__ void __launch_bounds__(BAND_T) k_band_lds(int N, int W, BoxK K, T *x,
                                                      const double *__restrict__ gsum, const int *__restrict__ mp) {
   extern __shared__ unsigned char lds_raw[];
   T *xs = reinterpret_cast<T *>(lds_raw);
+  // new values of the body ghost rows, in LDS after the region (8-byte aligned)
+  double *nv = reinterpret_cast<double *>(lds_raw + ((nreg * sizeof(T) + 7) & ~(size_t)7));
   const int WW = W * W;
   // value of a table entry: local LDS slot (written by this kernel) or -(global index + 1) (read only)
   auto val = [&](int e) -> double { return e >= 0 ? (double)xs[e] : (double)x[-e - 1]; };
@@ -403,7 +496,7 @@ __global__ void __launch_bounds__(BAND_T) k_band_lds(int N, int W, BoxK K, T *x,
   }
   const double xi = (double)x[3 * WW];
   __syncthreads();
-  // Jacobi sweeps of the body ghost rows; each new value goes through nvbuf (written and read back by the same
+  // Jacobi sweeps of the body ghost rows; each new value goes through nv (written and read back by the same
   // thread), so no row data is held across the barrier
   auto ghost_block = [&]() {
     for (int it = 0; it < lambda; it++) {
@@ -411,10 +504,10 @@ __global__ void __launch_bounds__(BAND_T) k_band_lds(int N, int W, BoxK K, T *x,
         double sum = 0;
 #pragma unroll
         for (int z = 0; z < 9; z++) sum += bg_w[z * gcap + s2] * val(bg_loc[(1 + z) * gcap + s2]);
-        nvbuf[s2] = (double)xs[bg_loc[s2]] + bg_dt[s2] * ((double)b[bg_k[s2]] - sum);
+        nv[s2] = (double)xs[bg_loc[s2]] + bg_dt[s2] * ((double)b[bg_k[s2]] - sum);
       }
       __syncthreads();
-      for (int s2 = tid; s2 < nbg; s2 += BAND_T) xs[bg_loc[s2]] = (T)nvbuf[s2];
+      for (int s2 = tid; s2 < nbg; s2 += BAND_T) xs[bg_loc[s2]] = (T)nv[s2];
       __syncthreads();
     }
   };
@@ -463,10 +556,10 @@ __global__ void __launch_bounds__(BAND_T) k_band_lds(int N, int W, BoxK K, T *x,
       if (cd[u] >= 0) fs += (cd[u] & 1) ? -v[u] : v[u];
   }
   fs = band_block_sum(fs);
-  for (int q0 = tid; q0 < nreg; q0 += BATCH * BAND_T) {
+  for (int q0 = tid; q0 < nregw; q0 += BATCH * BAND_T) {  // only the written points go back
     int gi[BATCH];
 #pragma unroll
-    for (int u = 0; u < BATCH; u++) gi[u] = q0 + u * BAND_T < nreg ? reg_pt[q0 + u * BAND_T] : -1;
+    for (int u = 0; u < BATCH; u++) gi[u] = q0 + u * BAND_T < nregw ? reg_pt[q0 + u * BAND_T] : -1;
 #pragma unroll
     for (int u = 0; u < BATCH; u++)
       if (gi[u] >= 0) x[gi[u]] = xs[q0 + u * BAND_T];
@@ -629,20 +722,40 @@ __device__ __forceinline__ void block_max_atomic(unsigned long long *m, double v
     if (z) atomicMax(m, z);
   }
 }
+// residual of the point rows with its max norm; each block also leaves its sum of the internal pressures in
+// part[block] for k_resid_mean_row (no grid-wide fence here: the kernel writes the whole residual)
 template <typename T>
 __global__ void __launch_bounds__(TPB) k_resid_pts_norm(int N, int W, double h, double a, double d,
                                                         const uint8_t *__restrict__ cls, const T *__restrict__ x,
-                                                        const T *__restrict__ b, T *__restrict__ r, unsigned long long *rmax) {
+                                                        const T *__restrict__ b, T *__restrict__ r, unsigned long long *rmax,
+                                                        double *part) {
   const int WW = W * W;
-  double mx = 0;
+  double mx = 0, ps = 0;
   for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < 3 * WW; t += gridDim.x * blockDim.x) {
     double res = resid_point<T>(W, h, a, d, cls, x, b, t);
     r[t] = (T)res;
     double ar = fabs(res);
     mx = (ar > mx || ar != ar) ? ar : mx;
+    if (t >= 2 * WW && cls[t] == K_INT) ps += (double)x[t];
   }
   block_max_atomic(rmax, mx);
+  ps = block_sum(ps);
+  if (threadIdx.x == 0) part[blockIdx.x] = ps;
   (void)N;
+}
+// the mean-pressure row's residual -mean(p) from the block sums of k_resid_pts_norm (fixed order), into r[3WW]
+// and the norm
+template <typename T>
+__global__ void __launch_bounds__(TPB) k_resid_mean_row(const double *__restrict__ part, int nb, const int *mp,
+                                                        T *r3, unsigned long long *rmax) {
+  double v = 0;
+  for (int q = threadIdx.x; q < nb; q += TPB) v += part[q];
+  v = block_sum(v);
+  if (threadIdx.x == 0) {
+    double res = -v / *mp;
+    *r3 = (T)res;
+    atomicMax(rmax, (unsigned long long)__double_as_longlong(fabs(res)));
+  }
 }
 template <typename T>
 __global__ void k_resid_ghost(const int *__restrict__ pt, const int *__restrict__ col, const double *__restrict__ w, int ng,
@@ -671,13 +784,6 @@ __global__ void k_resid_ghost_norm(const int *__restrict__ pt, const int *__rest
     r[k] = (T)res;
   }
   max_abs(rmax, res);
-}
-// mean row residual 0 - mean(p) into r[3WW] and the norm
-template <typename T>
-__global__ void k_resid_mean(int W, const double *mean, T *r, unsigned long long *rmax) {
-  double res = -*mean;
-  r[3 * W * W] = (T)res;
-  atomicMax(rmax, (unsigned long long)__double_as_longlong(fabs(res)));
 }
 // max |b| over a vector (wavefront reduction, one atomic per wavefront)
 template <typename T>
@@ -1028,8 +1134,38 @@ __global__ void __launch_bounds__(SC_T) k_small_cycle(SmallCycle P, T *xg, const
       B(m + 1)[t] = (T)restrict_value<T>(L.N, L.W, C(m), R(m), Cl.N, Cl.W, C(m + 1), t);
     __syncthreads();
   }
-  // coarsest: x[map[q]] = sum_j Ainv[q][j] b[bmap[j]], one wavefront per row
-  {
+  // coarsest: x[map[q]] = sum_j Ainv[q][j] b[bmap[j]], one wavefront per row.  Up to 256 unknowns, a wavefront
+  // takes eight rows at a time with all 32 loads of a lane issued together (the rows' latencies overlap); the
+  // sum of each row is formed in the same order as in the one-row loop below and in k_coarse_apply.
+  if (P.nc <= 256) {
+    constexpr int CK = 4, RB = 8;
+    const int lane = tid & 63, wave = tid >> 6, last = P.nc - 1;
+    double bv[CK];
+#pragma unroll
+    for (int k = 0; k < CK; k++) {
+      int r = lane + 64 * k;
+      bv[k] = r < P.nc ? (double)B(bot)[P.bmap[r]] : 0.0;  // columns past the end add +0
+    }
+    for (int q0 = wave; q0 < P.nc; q0 += RB * (SC_T / 64)) {
+      double a[RB][CK];
+#pragma unroll
+      for (int g = 0; g < RB; g++) {
+        const int q = min(q0 + g * (SC_T / 64), last);
+#pragma unroll
+        for (int k = 0; k < CK; k++) a[g][k] = P.Ainv[(size_t)q * P.nc + min(lane + 64 * k, last)];
+      }
+#pragma unroll
+      for (int g = 0; g < RB; g++) {
+        double s = 0;
+#pragma unroll
+        for (int k = 0; k < CK; k++) s += a[g][k] * bv[k];
+        for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
+        const int q = q0 + g * (SC_T / 64);
+        if (lane == 0 && q < P.nc) X(bot)[P.map[q]] = (T)s;
+      }
+    }
+    __syncthreads();
+  } else {
     const int lane = tid & 63;
     for (int q = tid >> 6; q < P.nc; q += SC_T / 64) {
       double s = 0;
@@ -1105,7 +1241,15 @@ static void relax(Ctx *ctx, int l) {
   int K = G.N / 5 + 1;
   if (ctx->box_tiles && V.y && box5_lds<T>() + 1024 <= ctx->max_lds) {
     int nt = (G.N + BT - 1) / BT;
-    k_box5<T><<<nt * nt, B5_T, box5_lds<T>(), s>>>(G.N, G.W, BK, G.cls, V.x, V.b, V.y);
+    const bool probe = sizeof(T) == 8 && l == 0 && 2 * ctx->probe_n < (int)ctx->probe_ev.size();
+    if (probe) {  // the events take the start and end times of the dispatch itself
+      hipEvent_t e0 = ctx->probe_ev[2 * ctx->probe_n], e1 = ctx->probe_ev[2 * ctx->probe_n + 1];
+      ctx->probe_n++;
+      hipExtLaunchKernelGGL(k_box5<T>, dim3(nt * nt), dim3(B5_T), (std::uint32_t)box5_lds<T>(), s, e0, e1, 0u, G.N, G.W,
+                            BK, (const uint8_t *)G.cls, (const T *)V.x, (const T *)V.b, V.y);
+    } else {
+      k_box5<T><<<nt * nt, B5_T, box5_lds<T>(), s>>>(G.N, G.W, BK, G.cls, V.x, V.b, V.y);
+    }
     std::swap(V.x, V.y);
   } else {
     for (int col = 0; col < 5; col++) k_box<T><<<box_grid(K, G.N), TPB, 0, s>>>(G.N, G.W, BK, G.cls, V.x, V.b, col);
@@ -1115,7 +1259,18 @@ static void relax(Ctx *ctx, int l) {
   if (band && G.nband >= ctx->band_split_min) {
     // a large band: ghost sweeps and band colours as device-wide launches
     auto sweeps = [&]() {
-      for (int it = 0; it < ctx->prm.lambda_ghost; it++) {
+      const int lam = ctx->prm.lambda_ghost;
+      if (lam >= 2 && G.colr_ok) {  // one launch per sweep: the sweeps between go through two row buffers
+        double *buf[2] = {ctx->gtmp, ctx->gtmp2};
+        for (int it = 0; it < lam; it++) {
+          const double *prev = it == 0 ? nullptr : buf[(it - 1) & 1];
+          double *next = it == lam - 1 ? nullptr : buf[it & 1];
+          k_ghost_sweep2<T><<<nblk(G.ng), TPB, 0, s>>>(G.g_pt, G.g_col, G.g_colr, G.g_w, G.g_dtau, G.ng, V.x, V.b, prev,
+                                                     next);
+        }
+        return;
+      }
+      for (int it = 0; it < lam; it++) {
         k_ghost_a<T><<<nblk(G.ng), TPB, 0, s>>>(G.g_pt, G.g_col, G.g_w, G.g_dtau, G.ng, V.x, V.b, ctx->gtmp);
         k_ghost_b<T><<<nblk(G.ng), TPB, 0, s>>>(G.g_pt, G.ng, ctx->gtmp, V.x);
       }
@@ -1131,13 +1286,15 @@ static void relax(Ctx *ctx, int l) {
     k_xi_faces<T><<<1, BAND_T, 0, s>>>(G.WW, G.h, V.x, G.f_code, G.nf, ctx->d_lev + l, G.d_mp);
     return;
   }
-  if (band && G.lds_ok && lds_bytes + 1024 <= ctx->max_lds) {
+  const size_t nv_off = (lds_bytes + 7) & ~(size_t)7, with_nv = nv_off + (size_t)G.nbg * sizeof(double);
+  if (band && G.lds_ok && with_nv + 1024 <= ctx->max_lds) {
     // wall ghosts, body ghosts, band boxes and xi in one workgroup
     int nwb = (G.nwg + BAND_T - 1) / BAND_T;
     BandOff bo;
     for (int c = 0; c < 6; c++) bo.o[c] = G.hband_off[c];
-    k_band_lds<T><<<1 + nwb, BAND_T, lds_bytes, s>>>(G.N, G.W, BK, V.x, V.b, bo, G.bbox, G.bcap, G.reg_pt, G.nreg,
-                                                     G.bg_k, G.bg_loc, G.bg_w, G.bg_dt, G.nbg, G.gcap, ctx->gtmp, G.g_pt, G.g_col,
+    k_band_lds<T><<<1 + nwb, BAND_T, with_nv, s>>>(
+        G.N, G.W, BK, V.x, V.b, bo, G.bbox, G.bcap, G.reg_pt, G.nreg, G.nregw, G.bg_k, G.bg_loc, G.bg_w, G.bg_dt, G.nbg,
+        G.gcap, G.g_pt, G.g_col,
                                                      G.g_w, G.g_dtau, G.wg_rows,
                                                G.nwg, ctx->prm.bnd_sweeps, ctx->prm.lambda_ghost, G.f_code, G.f_loc, G.nf,
                                                ctx->d_lev + l, G.d_mp);
@@ -1172,17 +1329,16 @@ static void residual(Ctx *ctx, int l, unsigned long long *rmax) {
   hipStream_t s = ctx->stream;
   double a = coef_a(ctx, l), d = 1.0 + 4.0 * a;
   if (rmax) {
-    k_resid_pts_norm<T><<<std::min(2048, nblk(3L * G.WW)), TPB, 0, s>>>(G.N, G.W, G.h, a, d, G.cls, V.x, V.b, V.r, rmax);
+    // at most 2048 blocks: one partial sum each in d_red (8192 slots)
+    const int nb = std::min(2048, nblk(3L * G.WW));
+    k_resid_pts_norm<T><<<nb, TPB, 0, s>>>(G.N, G.W, G.h, a, d, G.cls, V.x, V.b, V.r, rmax, ctx->d_red);
+    k_resid_mean_row<T><<<1, TPB, 0, s>>>(ctx->d_red, nb, G.d_mp, V.r + 3L * G.WW, rmax);
     if (G.ng) k_resid_ghost_norm<T><<<nblk(G.ng), TPB, 0, s>>>(G.g_pt, G.g_col, G.g_w, G.ng, V.x, V.b, V.r, rmax);
   } else {
     k_resid_pts<T><<<nblk(3L * G.WW), TPB, 0, s>>>(G.N, G.W, G.h, a, d, G.cls, V.x, V.b, V.r, nullptr);
     if (G.ng) k_resid_ghost<T><<<nblk(G.ng), TPB, 0, s>>>(G.g_pt, G.g_col, G.g_w, G.ng, V.x, V.b, V.r, nullptr);
   }
-  if (rmax) {
-    int nb = std::min(RED_BLOCKS, nblk(G.WW));
-    k_pmean<T><<<nb, TPB, 0, s>>>(G.W, G.cls, V.x, ctx->d_red, ctx->d_ticket, G.d_mp, ctx->d_scal + 2);
-    k_resid_mean<T><<<1, 1, 0, s>>>(G.W, ctx->d_scal + 2, V.r, rmax);
-  }
+
 }
 
 template <typename T>
@@ -1271,7 +1427,6 @@ static void cycle(Ctx *ctx, int l) {
   Geo &F = ctx->geo[l], &C = ctx->geo[l + 1];
   Vec<T> &VF = vec<T>(ctx, l), &VC = vec<T>(ctx, l + 1);
   hipStream_t s = ctx->stream;
-  if (l == 0) gsum<T>(ctx, 0);
   for (int q = 0; q < ctx->prm.nu1; q++) relax<T>(ctx, l);
   residual<T>(ctx, l, nullptr);
   k_restrict<T, T><<<nblk(3L * C.WW + 1), TPB, 0, s>>>(F.N, F.W, F.cls, VF.r, C.N, C.W, C.cls, VC.b);
@@ -1367,6 +1522,11 @@ gp_status time_kernel(Ctx *ctx, int which, int l, int reps, double *avg_us) {
     } else if (which == 4) {
       relax_ghost_only(ctx, l);
       launches++;
+    } else if (which == 5 && V.y && box5_lds<double>() + 1024 <= ctx->max_lds) {
+      int nt = (G.N + BT - 1) / BT;
+      k_box5<double><<<nt * nt, B5_T, box5_lds<double>(), s>>>(G.N, G.W, box_consts(G.h, a, d), G.cls, V.x, V.b, V.y);
+      std::swap(V.x, V.y);
+      launches++;
     } else {
       return GP_EINVAL;
     }
@@ -1381,6 +1541,35 @@ gp_status time_kernel(Ctx *ctx, int which, int l, int reps, double *avg_us) {
   return GP_OK;
 }
 
+gp_status probe_start(Ctx *ctx, int max_launches) {
+  double dummy;
+  int n;
+  if (!ctx->probe_ev.empty()) probe_stop(ctx, &dummy, &n);
+  ctx->probe_ev.assign(2 * (size_t)max_launches, nullptr);
+  ctx->probe_n = 0;
+  for (auto &e : ctx->probe_ev) GP_HIP(hipEventCreate(&e));
+  return GP_OK;
+}
+
+gp_status probe_stop(Ctx *ctx, double *avg_us, int *launches) {
+  double total = 0;
+  gp_status st = GP_OK;
+  if (ctx->probe_n > 0 && hipEventSynchronize(ctx->probe_ev[2 * ctx->probe_n - 1]) != hipSuccess) st = GP_EHIP;
+  for (int q = 0; q < ctx->probe_n && st == GP_OK; q++) {
+    float ms = 0;
+    if (hipEventElapsedTime(&ms, ctx->probe_ev[2 * q], ctx->probe_ev[2 * q + 1]) != hipSuccess) st = GP_EHIP;
+    total += ms;
+  }
+  *launches = ctx->probe_n;
+  *avg_us = ctx->probe_n ? 1000.0 * total / ctx->probe_n : 0.0;
+  for (auto &e : ctx->probe_ev)
+    if (e) (void)hipEventDestroy(e);
+  ctx->probe_ev.clear();
+  ctx->probe_n = 0;
+  if (st) ctx->hip_err = "event timing of the probed launches failed";
+  return st;
+}
+
 gp_status residual64(Ctx *ctx, int level, double *res_inf) {
   (void)level;
   return resnorm64(ctx, res_inf);
@@ -1389,6 +1578,7 @@ gp_status residual64(Ctx *ctx, int level, double *res_inf) {
 gp_status mg_cycle64(Ctx *ctx, double *res_inf) {
   gp_status st = set_wall_dirichlet(ctx);
   if (st) return st;
+  gsum<double>(ctx, 0);
   cycle<double>(ctx, 0);
   mean_project<double>(ctx);
   GP_HIP(hipGetLastError());
@@ -1440,12 +1630,70 @@ static void refine_step(Ctx *ctx, int inner) {
   Vec<float> &E = ctx->v32[0];
   k_cast_rhs<<<nblk(G.n), TPB, 0, s>>>(ctx->v64[0].r, E.b, G.n);
   k_fill<float><<<nblk(G.n), TPB, 0, s>>>(E.x, G.n, 0.0f);
+  gsum<float>(ctx, 0);  // b of the inner cycles is fixed for the whole refinement step
   for (int q = 0; q < inner; q++) {
     cycle<float>(ctx, 0);
     mean_project<float>(ctx);
   }
   k_add_correction<<<nblk(G.n), TPB, 0, s>>>(G.cls, G.n, E.x, ctx->v64[0].x);
   mean_project<double>(ctx);
+}
+
+// The launches of one solver iteration (an FP64 cycle and the mean projection, or one refinement step) followed
+// by the residual norm into d_scal[1], captured as a graph: most launches of a cycle are a few microseconds
+// long, shorter than the host needs to issue them one by one.  Captured at the start of every solve (the
+// geometry, alpha and buffers may have changed since the last one); the executable graph of the previous solve
+// is updated in place when the launch sequence has the same shape, else instantiated anew.
+static void iteration_launches(Ctx *ctx, int precision) {
+  if (precision == GP_FP64) {
+    cycle<double>(ctx, 0);
+    mean_project<double>(ctx);
+  } else {
+    refine_step(ctx, ctx->prm.mixed_inner_cycles);
+  }
+  unsigned long long *rmax = (unsigned long long *)(ctx->d_scal + 1);
+  k_fill<unsigned long long><<<1, 1, 0, ctx->stream>>>(rmax, 1, 0ull);
+  residual<double>(ctx, 0, rmax);
+}
+
+static gp_status capture_iteration(Ctx *ctx, int precision) {
+  hipStream_t s = ctx->stream;
+  hipGraphExec_t &ex = ctx->g_iter[precision == GP_FP64 ? 0 : 1];
+  hipGraph_t g = nullptr;
+  GP_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+  iteration_launches(ctx, precision);
+  hipError_t el = hipGetLastError();
+  hipError_t ec = hipStreamEndCapture(s, &g);
+  if (el != hipSuccess || ec != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    ctx->hip_err = std::string("capture of a solver iteration: ") + hipGetErrorString(el != hipSuccess ? el : ec);
+    return GP_EHIP;
+  }
+  if (ex) {
+    hipGraphNode_t bad = nullptr;
+    hipGraphExecUpdateResult ur = hipGraphExecUpdateError;
+    if (hipGraphExecUpdate(ex, g, &bad, &ur) != hipSuccess || ur != hipGraphExecUpdateSuccess) {
+      (void)hipGetLastError();
+      (void)hipGraphExecDestroy(ex);
+      ex = nullptr;
+    }
+  }
+  hipError_t ei = ex ? hipSuccess : hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (ei != hipSuccess) {
+    ex = nullptr;
+    ctx->hip_err = std::string("hipGraphInstantiate: ") + hipGetErrorString(ei);
+    return GP_EHIP;
+  }
+  return GP_OK;
+}
+
+static gp_status read_rmax(Ctx *ctx, double *out) {
+  unsigned long long hv = 0;
+  GP_HIP(hipMemcpyAsync(&hv, ctx->d_scal + 1, sizeof(hv), hipMemcpyDeviceToHost, ctx->stream));
+  GP_HIP(hipStreamSynchronize(ctx->stream));
+  std::memcpy(out, &hv, sizeof(double));
+  return GP_OK;
 }
 
 gp_status mg_solve(Ctx *ctx, int precision, double tol, int max_cycles, gp_stats *stt) {
@@ -1459,12 +1707,23 @@ gp_status mg_solve(Ctx *ctx, int precision, double tol, int max_cycles, gp_stats
   double r = r0, rho = 0;
   int c = 0, outer = 0;
   gp_status out = GP_OK;
+  // the launch probe records events around launches, which a replayed graph would not repeat
+  const bool graph = ctx->graphs && ctx->probe_ev.empty() && r > thr && max_cycles > 0;
+  if (precision != GP_FP64 && (st = ensure_fp32(ctx))) return st;
+  if (precision == GP_FP64) gsum<double>(ctx, 0);  // b and the wall values are fixed during the solve
+  if (graph && (st = capture_iteration(ctx, precision))) return st;
+  hipGraphExec_t ex = ctx->g_iter[precision == GP_FP64 ? 0 : 1];
   if (precision == GP_FP64) {
     while (r > thr && c < max_cycles) {
-      cycle<double>(ctx, 0);
-      mean_project<double>(ctx);
       double rp = r;
-      if ((st = resnorm64(ctx, &r))) return st;
+      if (graph) {
+        GP_HIP(hipGraphLaunch(ex, ctx->stream));
+        if ((st = read_rmax(ctx, &r))) return st;
+      } else {
+        cycle<double>(ctx, 0);
+        mean_project<double>(ctx);
+        if ((st = resnorm64(ctx, &r))) return st;
+      }
       c++;
       rho = r / rp;
       if (!(r == r) || r > 1e6 * (r0 > 1 ? r0 : 1)) {
@@ -1473,12 +1732,16 @@ gp_status mg_solve(Ctx *ctx, int precision, double tol, int max_cycles, gp_stats
       }
     }
   } else {
-    if ((st = ensure_fp32(ctx))) return st;
     int k = ctx->prm.mixed_inner_cycles;
     while (r > thr && c < max_cycles) {
-      refine_step(ctx, k);  // v64[0].r holds the residual of the last resnorm64
       double rp = r;
-      if ((st = resnorm64(ctx, &r))) return st;
+      if (graph) {  // v64[0].r holds the residual of the last norm
+        GP_HIP(hipGraphLaunch(ex, ctx->stream));
+        if ((st = read_rmax(ctx, &r))) return st;
+      } else {
+        refine_step(ctx, k);
+        if ((st = resnorm64(ctx, &r))) return st;
+      }
       c += k;
       outer++;
       rho = r / rp;

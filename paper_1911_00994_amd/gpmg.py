@@ -23,7 +23,7 @@ EXPORTS = [
     "gp_set_levelset", "gp_set_levelset_analytic", "gp_set_walls", "gp_get_boundary_geometry",
     "gp_set_boundary_values", "gp_set_alpha", "gp_set_rhs", "gp_set_x", "gp_get_x", "gp_mg_vcycle", "gp_solve",
     "gp_residual", "gp_set_state", "gp_cn_step", "gp_get_classes", "gp_get_ghost_rows", "gp_get_ext_rows",
-    "gp_relax", "gp_time_kernel", "gp_apply_mt", "gp_adjoint_solve", "gp_apply_cycle", "gp_apply_cycle_t",
+    "gp_relax", "gp_time_kernel", "gp_probe_start", "gp_probe_stop", "gp_apply_mt", "gp_adjoint_solve", "gp_apply_cycle", "gp_apply_cycle_t",
     "gp_tape_forward", "gp_tape_backward",
 ]
 
@@ -34,7 +34,8 @@ class GpParams(ctypes.Structure):
                 ("dtau_dir", ctypes.c_double), ("dtau_neu_over_h", ctypes.c_double),
                 ("bisect_eps_over_h", ctypes.c_double), ("cg_min", ctypes.c_double),
                 ("mixed_inner_cycles", ctypes.c_int), ("bnd_sweeps", ctypes.c_int), ("bnd_radius", ctypes.c_int),
-                ("fuse_small_levels", ctypes.c_int), ("band_split_min", ctypes.c_int)]
+                ("fuse_small_levels", ctypes.c_int), ("band_split_min", ctypes.c_int),
+                ("graph_iterations", ctypes.c_int)]
 
 
 class GpRigid(ctypes.Structure):
@@ -98,6 +99,8 @@ def lib():
         "gp_get_ext_rows": (i, [vp, i, vp, vp]),
         "gp_relax": (i, [vp, i, i]),
         "gp_time_kernel": (i, [vp, i, i, i, vp]),
+        "gp_probe_start": (i, [vp, i]),
+        "gp_probe_stop": (i, [vp, vp, vp]),
         "gp_apply_mt": (i, [vp, vp, vp, i]),
         "gp_adjoint_solve": (i, [vp, vp, vp, i, d, i, ctypes.POINTER(GpStats)]),
         "gp_apply_cycle": (i, [vp, vp, vp, i]),
@@ -239,6 +242,17 @@ class Solver:
         us = ctypes.c_double(0)
         self._check(lib().gp_time_kernel(self._h, which, level, reps, ctypes.byref(us)), "gp_time_kernel")
         return us.value
+
+    def probe_start(self, max_launches=4096):
+        """record HIP events around each finest-level five-colour box launch of the FP64 cycle from now on"""
+        self._check(lib().gp_probe_start(self._h, max_launches), "gp_probe_start")
+
+    def probe_stop(self):
+        """(average device microseconds of the recorded launches, their number)"""
+        us = ctypes.c_double(0)
+        n = ctypes.c_int(0)
+        self._check(lib().gp_probe_stop(self._h, ctypes.byref(us), ctypes.byref(n)), "gp_probe_stop")
+        return us.value, n.value
 
     def relax(self, level=0, steps=1):
         self._check(lib().gp_relax(self._h, level, steps), "gp_relax")

@@ -173,6 +173,32 @@ def test_converged_solve_parity(N, shape):
     assert rel_diff(flat(o.get_x()), flat(s.get_x()), act) < 1e-10
 
 
+@pytest.mark.parametrize("mixed,split", [(0, 3000), (0, 1), (1, 3000)])
+def test_graph_replayed_solve_matches_issued_launches(mixed, split):
+    """the solver iterations replayed from a captured HIP graph give the same iterates as launches issued one by
+    one (same kernels, same arguments), and the converged solution agrees with the oracle's"""
+    from paper_1911_00994_amd import gpmg
+    N = 128
+    prec = gpmg.GP_MIXED if mixed else gpmg.GP_FP64
+    say(f"[graph solve] N={N} mixed={mixed} band_split_min={split}")
+    out = []
+    for g in (0, 1):
+        o, s = pair(N, FLOWER, 0.64 * (2.0 / N) ** 2, m=wl.PaperMMS(), t=0.4, graph_iterations=g,
+                    band_split_min=split)
+        for rep in range(2):  # the second solve updates the executable graph of the first
+            s.set_x(*[np.zeros((N + 2, N + 2))] * 3, 0.0)
+            st, info = s.solve(1e-10, 100, precision=prec)
+            assert st == 0, info
+        out.append((flat(s.get_x()), info["cycles"]))
+    assert out[0][1] == out[1][1]
+    assert np.array_equal(out[0][0], out[1][0])
+    st_o, _ = o.solve(1e-12, 200)
+    assert st_o == O.OK
+    cls = o.classes().ravel()
+    act = np.concatenate([active_mask(cls), [True]])
+    assert rel_diff(flat(o.get_x()), out[1][0], act) < 1e-7
+
+
 def _cn_lockstep(o, s, N, shape, motion, m, Re, nsteps, dt):
     """advance oracle and GPU together; both get the boundary data computed from the oracle's geometry"""
     mo = motion.as_array()
