@@ -949,10 +949,11 @@ static gp_status build_level(Ctx *ctx, int l) {
     GP_HIP(hipMemcpyAsync(&G.nregw, ctx->d_bcnt + nbr, sizeof(int), hipMemcpyDeviceToHost, s));
     GP_HIP(hipMemcpyAsync(&nr, cnt2 + nbr, sizeof(int), hipMemcpyDeviceToHost, s));
     GP_HIP(hipStreamSynchronize(s));
-    // the read-only points are staged too when they fit (FP64 values and the body ghost rows' new values in LDS);
-    // otherwise their map entries stay negative and the kernel reads them from global memory
+    // the read-only points are staged too when they fit (FP64 values, and the body ghost rows' new values and
+    // right-hand sides in LDS); otherwise their map entries stay negative and the kernel reads them from global
+    // memory
     const bool rd = G.nregw + nr <= regcap &&
-                    (size_t)(G.nregw + nr) * sizeof(double) + (size_t)G.ng * sizeof(double) + 2048 <= ctx->max_lds;
+                    (size_t)(G.nregw + nr) * sizeof(double) + 2 * (size_t)G.ng * sizeof(double) + 2048 <= ctx->max_lds;
     G.nreg = rd ? G.nregw + nr : G.nregw;
     if (G.nreg <= regcap) {
       GP_HIP(hipMemsetAsync(ctx->d_flags + 10, 0, 2 * sizeof(int), s));

@@ -238,7 +238,7 @@ __global__ void __launch_bounds__(B5_T, 2) k_box5(int N, int W, BoxK K, const ui
     bb[k][4] = (double)b[2 * WW + c];
   }
   // staging: batches of B5_B points per thread, all their loads issued before any LDS store
-  constexpr int B5_B = 6;
+  constexpr int B5_B = 9;
   for (int e0 = threadIdx.x; e0 < 3 * BRWW; e0 += B5_B * B5_T) {
     int kk[B5_B];
     T xv[B5_B];
@@ -456,7 +456,7 @@ constexpr int BATCH = 8;
 struct BandOff {
   int o[6];
 };
-template <typename T>
+template <typename T, bool ALL_LDS>
 __global__ void __launch_bounds__(BAND_T) k_band_lds(int N, int W, BoxK K, T *x, const T *__restrict__ b,
                                                      BandOff off, const int *__restrict__ bbox, int bcap,
                                                      const int *__restrict__ reg_pt, int nreg, int nregw,
@@ -470,11 +470,14 @@ __global__ void __launch_bounds__(BAND_T) k_band_lds(int N, int W, BoxK K, T *x,
                                                      const double *__restrict__ gsum, const int *__restrict__ mp) {
   extern __shared__ unsigned char lds_raw[];
   T *xs = reinterpret_cast<T *>(lds_raw);
-  // new values of the body ghost rows, in LDS after the region (8-byte aligned)
+  // after the region (8-byte aligned): the new values of the body ghost rows, then their right-hand sides
   double *nv = reinterpret_cast<double *>(lds_raw + ((nreg * sizeof(T) + 7) & ~(size_t)7));
+  double *gb = nv + nbg;
   const int WW = W * W;
-  // value of a table entry: local LDS slot (written by this kernel) or -(global index + 1) (read only)
+  // value of a table entry: local LDS slot (written by this kernel) or -(global index + 1) (read only).  With
+  // ALL_LDS every point the box and ghost tables name is staged (the face list may still name others).
   auto val = [&](int e) -> double { return e >= 0 ? (double)xs[e] : (double)x[-e - 1]; };
+  auto tval = [&](int e) -> double { return ALL_LDS ? (double)xs[e] : val(e); };
   const int tid = threadIdx.x;
   if (blockIdx.x > 0) {
     // the other workgroups of the launch take the wall ghost rows, on other compute units
@@ -494,17 +497,26 @@ __global__ void __launch_bounds__(BAND_T) k_band_lds(int N, int W, BoxK K, T *x,
     for (int u = 0; u < BATCH; u++)
       if (q0 + u * BAND_T < nreg) xs[q0 + u * BAND_T] = vv[u];
   }
+  for (int s2 = tid; s2 < nbg; s2 += BAND_T) gb[s2] = (double)b[bg_k[s2]];
+  // the cell of this thread's first box of the next colour is loaded one colour ahead, so that the right-hand
+  // sides of the box can be loaded together with its table
+  int next_cell = off.o[0] + tid < off.o[1] ? bbox[22 * bcap + off.o[0] + tid] : 0;
   const double xi = (double)x[3 * WW];
   __syncthreads();
   // Jacobi sweeps of the body ghost rows; each new value goes through nv (written and read back by the same
   // thread), so no row data is held across the barrier
   auto ghost_block = [&]() {
     for (int it = 0; it < lambda; it++) {
-      for (int s2 = tid; s2 < nbg; s2 += BAND_T) {
-        double sum = 0;
+      for (int s0 = tid; s0 < nbg; s0 += 2 * BAND_T) {  // two rows per thread at a time: their loads overlap
+        const int s1 = s0 + BAND_T, t1 = s1 < nbg ? s1 : s0;
+        double sum0 = 0, sum1 = 0;
 #pragma unroll
-        for (int z = 0; z < 9; z++) sum += bg_w[z * gcap + s2] * val(bg_loc[(1 + z) * gcap + s2]);
-        nv[s2] = (double)xs[bg_loc[s2]] + bg_dt[s2] * ((double)b[bg_k[s2]] - sum);
+        for (int z = 0; z < 9; z++) {
+          sum0 += bg_w[z * gcap + s0] * tval(bg_loc[(1 + z) * gcap + s0]);
+          sum1 += bg_w[z * gcap + t1] * tval(bg_loc[(1 + z) * gcap + t1]);
+        }
+        nv[s0] = (double)xs[bg_loc[s0]] + bg_dt[s0] * (gb[s0] - sum0);
+        if (s1 < nbg) nv[s1] = (double)xs[bg_loc[s1]] + bg_dt[s1] * (gb[s1] - sum1);
       }
       __syncthreads();
       for (int s2 = tid; s2 < nbg; s2 += BAND_T) xs[bg_loc[s2]] = (T)nv[s2];
@@ -514,16 +526,18 @@ __global__ void __launch_bounds__(BAND_T) k_band_lds(int N, int W, BoxK K, T *x,
   ghost_block();
   for (int sw = 0; sw < sweeps; sw++) {
     for (int c = 0; c < 5; c++) {
+      const int first_cell = next_cell, cn = c == 4 ? 0 : c + 1;
+      next_cell = off.o[cn] + tid < off.o[cn + 1] ? bbox[22 * bcap + off.o[cn] + tid] : 0;
       for (int q = off.o[c] + tid; q < off.o[c + 1]; q += BAND_T) {
         auto TB = [&](int fld) { return bbox[fld * bcap + q]; };
-        int cell = TB(22), i = cell % N, j = cell / N, cg = (j + 1) * W + (i + 1);
+        int cell = q == off.o[c] + tid ? first_cell : TB(22), i = cell % N, j = cell / N, cg = (j + 1) * W + (i + 1);
         int f = TB(21);
         bool fW = f & 1, fE = f & 2, fS = f & 4, fN = f & 8, fP = f & 16;
-        double uW = val(TB(0)), uE = val(TB(1)), uWW = val(TB(2)), uEE = val(TB(3)), uWS = val(TB(4)), uWN = val(TB(5)),
-               uES = val(TB(6)), uEN = val(TB(7));
-        double vS = val(TB(8)), vN = val(TB(9)), vSS = val(TB(10)), vNN = val(TB(11)), vSW = val(TB(12)),
-               vSE = val(TB(13)), vNW = val(TB(14)), vNE = val(TB(15));
-        double pc = val(TB(16)), pW = val(TB(17)), pE = val(TB(18)), pS = val(TB(19)), pN = val(TB(20));
+        double uW = tval(TB(0)), uE = tval(TB(1)), uWW = tval(TB(2)), uEE = tval(TB(3)), uWS = tval(TB(4)),
+               uWN = tval(TB(5)), uES = tval(TB(6)), uEN = tval(TB(7));
+        double vS = tval(TB(8)), vN = tval(TB(9)), vSS = tval(TB(10)), vNN = tval(TB(11)), vSW = tval(TB(12)),
+               vSE = tval(TB(13)), vNW = tval(TB(14)), vNE = tval(TB(15));
+        double pc = tval(TB(16)), pW = tval(TB(17)), pE = tval(TB(18)), pS = tval(TB(19)), pN = tval(TB(20));
         double bW_ = b[cg], bE_ = b[cg + 1], bS_ = b[WW + cg], bN_ = b[WW + cg + W], bP_ = b[2 * WW + cg];
         const BoxNew o = box_core(K, fW, fE, fS, fN, fP, uW, uE, uWW, uEE, uWS, uWN, uES, uEN, vS, vN, vSS, vNN, vSW, vSE,
                                   vNW, vNE, pc, pW, pE, pS, pN, bW_, bE_, bS_, bN_, bP_, xi);
@@ -1286,18 +1300,17 @@ static void relax(Ctx *ctx, int l) {
     k_xi_faces<T><<<1, BAND_T, 0, s>>>(G.WW, G.h, V.x, G.f_code, G.nf, ctx->d_lev + l, G.d_mp);
     return;
   }
-  const size_t nv_off = (lds_bytes + 7) & ~(size_t)7, with_nv = nv_off + (size_t)G.nbg * sizeof(double);
+  const size_t nv_off = (lds_bytes + 7) & ~(size_t)7, with_nv = nv_off + 2 * (size_t)G.nbg * sizeof(double);
   if (band && G.lds_ok && with_nv + 1024 <= ctx->max_lds) {
     // wall ghosts, body ghosts, band boxes and xi in one workgroup
     int nwb = (G.nwg + BAND_T - 1) / BAND_T;
     BandOff bo;
     for (int c = 0; c < 6; c++) bo.o[c] = G.hband_off[c];
-    k_band_lds<T><<<1 + nwb, BAND_T, with_nv, s>>>(
-        G.N, G.W, BK, V.x, V.b, bo, G.bbox, G.bcap, G.reg_pt, G.nreg, G.nregw, G.bg_k, G.bg_loc, G.bg_w, G.bg_dt, G.nbg,
-        G.gcap, G.g_pt, G.g_col,
-                                                     G.g_w, G.g_dtau, G.wg_rows,
-                                               G.nwg, ctx->prm.bnd_sweeps, ctx->prm.lambda_ghost, G.f_code, G.f_loc, G.nf,
-                                               ctx->d_lev + l, G.d_mp);
+    auto kern = G.nreg > G.nregw ? k_band_lds<T, true> : k_band_lds<T, false>;
+    kern<<<1 + nwb, BAND_T, with_nv, s>>>(G.N, G.W, BK, V.x, V.b, bo, G.bbox, G.bcap, G.reg_pt, G.nreg, G.nregw, G.bg_k,
+                                          G.bg_loc, G.bg_w, G.bg_dt, G.nbg, G.gcap, G.g_pt, G.g_col, G.g_w, G.g_dtau,
+                                          G.wg_rows, G.nwg, ctx->prm.bnd_sweeps, ctx->prm.lambda_ghost, G.f_code, G.f_loc,
+                                          G.nf, ctx->d_lev + l, G.d_mp);
     return;
   }
   if (band && G.ng <= 4 * GH_T) {
