@@ -200,16 +200,21 @@ __global__ void __launch_bounds__(TPB) k_box(int N, int W, BoxK BK, const uint8_
 // Tiles are dealt to the 8 XCDs in contiguous runs (when their number is a multiple of 8), so the halos that
 // neighbouring tiles share are fetched into the same L2.
 // ---------------------------------------------------------------------------------------------------------
-constexpr int BT = 32, BH = 10, BRW = BT + 2 * BH + 1, BRWW = BRW * BRW;  // 53 x 53 staged points
+// BT = 32 on the large levels (53 x 53 staged points), 16 where 32-cell tiles would leave most compute units idle
+constexpr int BH = 10;
 constexpr int B5_T = 512;
-static_assert((BT + 2 * (1 + 2 * 4) + 4) / 5 * (BT + 2 * (1 + 2 * 4)) <= B5_T, "one box per thread and pass");
-template <typename T>
+template <int BT>
+constexpr int box5_rw() { return BT + 2 * BH + 1; }
+static_assert((32 + 2 * (1 + 2 * 4) + 4) / 5 * (32 + 2 * (1 + 2 * 4)) <= B5_T, "one box per thread and pass");
+template <typename T, int BT>
 __host__ __device__ constexpr size_t box5_lds() {
-  return ((3 * BRWW + 1) * sizeof(T) + 15) / 16 * 16 + 3 * BRWW;
+  return ((3 * box5_rw<BT>() * box5_rw<BT>() + 1) * sizeof(T) + 15) / 16 * 16 + 3 * box5_rw<BT>() * box5_rw<BT>();
 }
-template <typename T>
+static inline int box5_tile(int N) { return (N / 16) * (N / 16) <= 512 ? 16 : 32; }
+template <typename T, int BT>
 __global__ void __launch_bounds__(B5_T, 2) k_box5(int N, int W, BoxK K, const uint8_t *__restrict__ cls,
                                                   const T *__restrict__ x, const T *__restrict__ b, T *__restrict__ y) {
+  constexpr int BRW = box5_rw<BT>(), BRWW = BRW * BRW;
   extern __shared__ unsigned char lds_raw[];
   T *xs = reinterpret_cast<T *>(lds_raw);
   uint8_t *cs = lds_raw + ((3 * BRWW + 1) * sizeof(T) + 15) / 16 * 16;
@@ -1012,6 +1017,7 @@ struct SmallLevel {
   int boff[6];
   int ox, ob, orr, oc;  // LDS offsets (bytes) of x, b, r and the classes
   int ogw, ogc, ogp, ogd;  // LDS offsets of the ghost rows, field-major: 9 weights, 9 columns, point, dtau
+  int obl;                 // LDS offset of the band cells
 };
 struct SmallCycle {
   int nl;  // fused levels; the last one is the coarsest
@@ -1057,7 +1063,7 @@ __device__ void sc_ghosts(const SmallLevel &L, const ScRows &G, T *x, const T *b
 
 template <typename T>
 __device__ void sc_relax(const SmallCycle &P, const SmallLevel &L, const ScRows &G, T *x, const T *b, const uint8_t *cls,
-                         double *nv) {
+                         double *nv, const int *band) {
   const int K = L.N / 5 + 1;
   for (int c = 0; c < 5; c++) {
     for (int t = threadIdx.x; t < K * L.N; t += SC_T) {
@@ -1072,7 +1078,7 @@ __device__ void sc_relax(const SmallCycle &P, const SmallLevel &L, const ScRows 
     for (int q = 0; q < P.bnd; q++) {
       for (int c = 0; c < 5; c++) {
         for (int t = L.boff[c] + threadIdx.x; t < L.boff[c + 1]; t += SC_T) {
-          int cell = L.band[t];
+          int cell = band[t];
           box_update<T>(L.W, L.K, cls, x, b, cell % L.N, cell / L.N);
         }
         __syncthreads();
@@ -1122,6 +1128,8 @@ __global__ void __launch_bounds__(SC_T) k_small_cycle(SmallCycle P, T *xg, const
         gp[r] = L.g_pt[r];
         gd[r] = L.g_dtau[r];
       }
+      int *bl = reinterpret_cast<int *>(lds_raw + L.obl);
+      for (int q = tid; q < L.nband; q += SC_T) bl[q] = L.band[q];
     }
     for (int t = tid; t < L.n; t += SC_T) {
       X(m)[t] = m == 0 ? xg[t] : (T)0;
@@ -1133,7 +1141,8 @@ __global__ void __launch_bounds__(SC_T) k_small_cycle(SmallCycle P, T *xg, const
   for (int m = 0; m < bot; m++) {
     const SmallLevel &L = P.lv[m], &Cl = P.lv[m + 1];
     const ScRows G = GR(m);
-    for (int q = 0; q < P.nu1; q++) sc_relax<T>(P, L, G, X(m), B(m), C(m), nv);
+    const int *bl = reinterpret_cast<const int *>(lds_raw + L.obl);
+    for (int q = 0; q < P.nu1; q++) sc_relax<T>(P, L, G, X(m), B(m), C(m), nv, bl);
     for (int t = tid; t < 3 * L.W * L.W; t += SC_T) R(m)[t] = (T)resid_point<T>(L.W, L.h, L.a, L.d, C(m), X(m), B(m), t);
     __syncthreads();
     for (int r = tid; r < L.ng; r += SC_T) {
@@ -1203,7 +1212,8 @@ __global__ void __launch_bounds__(SC_T) k_small_cycle(SmallCycle P, T *xg, const
       if (e != 0.0 || t == 3 * L.W * L.W) X(m)[t] = (T)((double)X(m)[t] + e);
     }
     __syncthreads();
-    for (int q = 0; q < P.nu2; q++) sc_relax<T>(P, L, GR(m), X(m), B(m), C(m), nv);
+    for (int q = 0; q < P.nu2; q++)
+      sc_relax<T>(P, L, GR(m), X(m), B(m), C(m), nv, reinterpret_cast<const int *>(lds_raw + L.obl));
   }
   for (int t = tid; t < P.lv[0].n; t += SC_T) xg[t] = X(0)[t];
 }
@@ -1245,6 +1255,19 @@ static void relax_ghosts(Ctx *ctx, int l) {
 }
 static void relax_ghost_only(Ctx *ctx, int l) { relax_ghosts<double>(ctx, l); }
 
+// one five-colour sweep x -> y; with events, they take the start and end times of the dispatch
+template <typename T>
+static void box5_launch(const Geo &G, const BoxK &BK, const Vec<T> &V, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+  const int bt = box5_tile(G.N), nt = (G.N + bt - 1) / bt;
+  auto kern = bt == 16 ? k_box5<T, 16> : k_box5<T, 32>;
+  const std::uint32_t lds = (std::uint32_t)(bt == 16 ? box5_lds<T, 16>() : box5_lds<T, 32>());
+  if (e0)
+    hipExtLaunchKernelGGL(kern, dim3(nt * nt), dim3(B5_T), lds, s, e0, e1, 0u, G.N, G.W, BK, (const uint8_t *)G.cls,
+                          (const T *)V.x, (const T *)V.b, V.y);
+  else
+    kern<<<nt * nt, B5_T, lds, s>>>(G.N, G.W, BK, G.cls, V.x, V.b, V.y);
+}
+
 template <typename T>
 static void relax(Ctx *ctx, int l) {
   Geo &G = ctx->geo[l];
@@ -1253,16 +1276,14 @@ static void relax(Ctx *ctx, int l) {
   double a = coef_a(ctx, l), d = 1.0 + 4.0 * a;
   const BoxK BK = box_consts(G.h, a, d);
   int K = G.N / 5 + 1;
-  if (ctx->box_tiles && V.y && box5_lds<T>() + 1024 <= ctx->max_lds) {
-    int nt = (G.N + BT - 1) / BT;
+  if (ctx->box_tiles && V.y && box5_lds<T, 32>() + 1024 <= ctx->max_lds) {
     const bool probe = sizeof(T) == 8 && l == 0 && 2 * ctx->probe_n < (int)ctx->probe_ev.size();
     if (probe) {  // the events take the start and end times of the dispatch itself
       hipEvent_t e0 = ctx->probe_ev[2 * ctx->probe_n], e1 = ctx->probe_ev[2 * ctx->probe_n + 1];
       ctx->probe_n++;
-      hipExtLaunchKernelGGL(k_box5<T>, dim3(nt * nt), dim3(B5_T), (std::uint32_t)box5_lds<T>(), s, e0, e1, 0u, G.N, G.W,
-                            BK, (const uint8_t *)G.cls, (const T *)V.x, (const T *)V.b, V.y);
+      box5_launch<T>(G, BK, V, s, e0, e1);
     } else {
-      k_box5<T><<<nt * nt, B5_T, box5_lds<T>(), s>>>(G.N, G.W, BK, G.cls, V.x, V.b, V.y);
+      box5_launch<T>(G, BK, V, s, nullptr, nullptr);
     }
     std::swap(V.x, V.y);
   } else {
@@ -1407,6 +1428,7 @@ static size_t small_cycle_setup(Ctx *ctx, int l, SmallCycle &P) {
     S.ogd = bottom ? 0 : take((size_t)G.ng * sizeof(double));
     S.ogc = bottom ? 0 : take((size_t)9 * G.ng * sizeof(int));
     S.ogp = bottom ? 0 : take((size_t)G.ng * sizeof(int));
+    S.obl = bottom ? 0 : take((size_t)S.nband * sizeof(int));
     if (!bottom) maxng = std::max(maxng, G.ng);
   }
   P.onv = take((size_t)maxng * sizeof(double));
@@ -1535,9 +1557,8 @@ gp_status time_kernel(Ctx *ctx, int which, int l, int reps, double *avg_us) {
     } else if (which == 4) {
       relax_ghost_only(ctx, l);
       launches++;
-    } else if (which == 5 && V.y && box5_lds<double>() + 1024 <= ctx->max_lds) {
-      int nt = (G.N + BT - 1) / BT;
-      k_box5<double><<<nt * nt, B5_T, box5_lds<double>(), s>>>(G.N, G.W, box_consts(G.h, a, d), G.cls, V.x, V.b, V.y);
+    } else if (which == 5 && V.y && box5_lds<double, 32>() + 1024 <= ctx->max_lds) {
+      box5_launch<double>(G, box_consts(G.h, a, d), V, s, nullptr, nullptr);
       std::swap(V.x, V.y);
       launches++;
     } else {
