@@ -490,16 +490,17 @@ __global__ void __launch_bounds__(BAND_T) k_band_lds(int N, int W, BoxK K, T *x,
       wall_ghost_row<T>(wg_rows[q], g_pt, g_col, g_w, g_dtau, x, b, lambda * (1 + sweeps));
     return;
   }
-  // stage the region: batches of BATCH loads in flight per thread
-  for (int q0 = tid; q0 < nreg; q0 += BATCH * BAND_T) {
-    int gi[BATCH];
-    T vv[BATCH];
+  // stage the region: batches of SB loads in flight per thread (16 at once measured slower on one CU)
+  constexpr int SB = BATCH;
+  for (int q0 = tid; q0 < nreg; q0 += SB * BAND_T) {
+    int gi[SB];
+    T vv[SB];
 #pragma unroll
-    for (int u = 0; u < BATCH; u++) gi[u] = q0 + u * BAND_T < nreg ? reg_pt[q0 + u * BAND_T] : 0;
+    for (int u = 0; u < SB; u++) gi[u] = q0 + u * BAND_T < nreg ? reg_pt[q0 + u * BAND_T] : 0;
 #pragma unroll
-    for (int u = 0; u < BATCH; u++) vv[u] = x[gi[u]];
+    for (int u = 0; u < SB; u++) vv[u] = x[gi[u]];
 #pragma unroll
-    for (int u = 0; u < BATCH; u++)
+    for (int u = 0; u < SB; u++)
       if (q0 + u * BAND_T < nreg) xs[q0 + u * BAND_T] = vv[u];
   }
   for (int s2 = tid; s2 < nbg; s2 += BAND_T) gb[s2] = (double)b[bg_k[s2]];
@@ -885,11 +886,14 @@ __device__ __forceinline__ double restrict_value(int Nf, int Wf, const uint8_t *
   return all ? sw : (cnt ? sa / cnt : 0.0);
 }
 template <typename TF, typename TC>
+// (and, when xc is given, the zero initial guess of the coarse correction)
 __global__ void __launch_bounds__(TPB) k_restrict(int Nf, int Wf, const uint8_t *__restrict__ clsf, const TF *__restrict__ rf,
-                                                  int Nc, int Wc, const uint8_t *__restrict__ clsc, TC *__restrict__ bc) {
+                                                  int Nc, int Wc, const uint8_t *__restrict__ clsc, TC *__restrict__ bc,
+                                                  TC *__restrict__ xc) {
   int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t > 3 * Wc * Wc) return;
   bc[t] = (TC)restrict_value<TF>(Nf, Wf, clsf, rf, Nc, Wc, clsc, t);
+  if (xc) xc[t] = (TC)0;
 }
 
 // extension values: quadratic extrapolation from the sources
@@ -1464,9 +1468,8 @@ static void cycle(Ctx *ctx, int l) {
   hipStream_t s = ctx->stream;
   for (int q = 0; q < ctx->prm.nu1; q++) relax<T>(ctx, l);
   residual<T>(ctx, l, nullptr);
-  k_restrict<T, T><<<nblk(3L * C.WW + 1), TPB, 0, s>>>(F.N, F.W, F.cls, VF.r, C.N, C.W, C.cls, VC.b);
+  k_restrict<T, T><<<nblk(3L * C.WW + 1), TPB, 0, s>>>(F.N, F.W, F.cls, VF.r, C.N, C.W, C.cls, VC.b, VC.x);
   if (l + 1 < ctx->L - 1) gsum<T>(ctx, l + 1);
-  k_fill<T><<<nblk(C.n), TPB, 0, s>>>(VC.x, C.n, (T)0);
   int reps = (l + 1 == ctx->L - 1) ? 1 : ctx->prm.gamma;
   for (int q = 0; q < reps; q++) cycle<T>(ctx, l + 1);
   if (C.ne) k_ext_fill<T><<<nblk(C.ne), TPB, 0, s>>>(C.e_pt, C.e_src, C.e_w, C.ne, VC.x);
@@ -1547,7 +1550,8 @@ gp_status time_kernel(Ctx *ctx, int which, int l, int reps, double *avg_us) {
       launches++;
     } else if (which == 2 && l + 1 < ctx->L) {
       Geo &C = ctx->geo[l + 1];
-      k_restrict<double, double><<<nblk(3L * C.WW + 1), TPB, 0, s>>>(G.N, G.W, G.cls, V.r, C.N, C.W, C.cls, ctx->v64[l + 1].b);
+      k_restrict<double, double><<<nblk(3L * C.WW + 1), TPB, 0, s>>>(G.N, G.W, G.cls, V.r, C.N, C.W, C.cls, ctx->v64[l + 1].b,
+                                                                     nullptr);
       launches++;
     } else if (which == 3 && l + 1 < ctx->L) {
       Geo &C = ctx->geo[l + 1];
