@@ -461,7 +461,21 @@ constexpr int BATCH = 8;
 struct BandOff {
   int o[6];
 };
-template <typename T, bool ALL_LDS>
+// Staging modes of k_band_lds, each one also staging what the ones before it stage:
+//   0: the written points only (every other point comes from global memory);
+//   1: also the points the box and ghost tables only read (every table entry is an LDS slot);
+//   2: also the body ghost rows' tables (slots as 16-bit numbers, weights, dtau);
+//   3: also the band boxes' tables (slots, flags, cell) and their right-hand sides.
+// LDS after the region, 8-byte aligned: nv, gb (new values and right-hand sides of the ghost rows), then for mode
+// >= 2: gw (9 nbg), gdt (nbg), gl (10 nbg 16-bit), and for mode 3: bbv (5 nb), bcl (nb), bfl (nb), bsl (21 nb 16-bit)
+__host__ __device__ inline size_t band_lds_bytes(int mode, size_t region_bytes, int nbg, int nb) {
+  size_t o = (region_bytes + 7) & ~(size_t)7;
+  o += 2 * (size_t)nbg * 8;
+  if (mode >= 2) o = (o + 10 * (size_t)nbg * 8 + 10 * (size_t)nbg * 2 + 7) & ~(size_t)7;
+  if (mode >= 3) o += 5 * (size_t)nb * 8 + 2 * (size_t)nb * 4 + 21 * (size_t)nb * 2;
+  return o;
+}
+template <typename T, int MODE>
 __global__ void __launch_bounds__(BAND_T) k_band_lds(int N, int W, BoxK K, T *x, const T *__restrict__ b,
                                                      BandOff off, const int *__restrict__ bbox, int bcap,
                                                      const int *__restrict__ reg_pt, int nreg, int nregw,
@@ -475,14 +489,19 @@ __global__ void __launch_bounds__(BAND_T) k_band_lds(int N, int W, BoxK K, T *x,
                                                      const double *__restrict__ gsum, const int *__restrict__ mp) {
   extern __shared__ unsigned char lds_raw[];
   T *xs = reinterpret_cast<T *>(lds_raw);
-  // after the region (8-byte aligned): the new values of the body ghost rows, then their right-hand sides
+  const int nb = off.o[5];
   double *nv = reinterpret_cast<double *>(lds_raw + ((nreg * sizeof(T) + 7) & ~(size_t)7));
   double *gb = nv + nbg;
+  double *gw = gb + nbg, *gdt = gw + 9 * nbg;
+  uint16_t *gl = reinterpret_cast<uint16_t *>(gdt + nbg);
+  double *bbv = reinterpret_cast<double *>(lds_raw + band_lds_bytes(2, nreg * sizeof(T), nbg, nb));
+  int *bcl = reinterpret_cast<int *>(bbv + 5 * nb), *bfl = bcl + nb;
+  uint16_t *bsl = reinterpret_cast<uint16_t *>(bfl + nb);
   const int WW = W * W;
-  // value of a table entry: local LDS slot (written by this kernel) or -(global index + 1) (read only).  With
-  // ALL_LDS every point the box and ghost tables name is staged (the face list may still name others).
+  // value of a table entry: local LDS slot (written by this kernel) or -(global index + 1) (read only).  From
+  // mode 1 on every point the box and ghost tables name is staged (the face list may still name others).
   auto val = [&](int e) -> double { return e >= 0 ? (double)xs[e] : (double)x[-e - 1]; };
-  auto tval = [&](int e) -> double { return ALL_LDS ? (double)xs[e] : val(e); };
+  auto tval = [&](int e) -> double { return MODE >= 1 ? (double)xs[e] : val(e); };
   const int tid = threadIdx.x;
   if (blockIdx.x > 0) {
     // the other workgroups of the launch take the wall ghost rows, on other compute units
@@ -490,69 +509,111 @@ __global__ void __launch_bounds__(BAND_T) k_band_lds(int N, int W, BoxK K, T *x,
       wall_ghost_row<T>(wg_rows[q], g_pt, g_col, g_w, g_dtau, x, b, lambda * (1 + sweeps));
     return;
   }
-  // stage the region: batches of SB loads in flight per thread (16 at once measured slower on one CU)
-  constexpr int SB = BATCH;
-  for (int q0 = tid; q0 < nreg; q0 += SB * BAND_T) {
-    int gi[SB];
-    T vv[SB];
+  // stage the region: batches of BATCH loads in flight per thread (16 at once measured slower on one CU)
+  for (int q0 = tid; q0 < nreg; q0 += BATCH * BAND_T) {
+    int gi[BATCH];
+    T vv[BATCH];
 #pragma unroll
-    for (int u = 0; u < SB; u++) gi[u] = q0 + u * BAND_T < nreg ? reg_pt[q0 + u * BAND_T] : 0;
+    for (int u = 0; u < BATCH; u++) gi[u] = q0 + u * BAND_T < nreg ? reg_pt[q0 + u * BAND_T] : 0;
 #pragma unroll
-    for (int u = 0; u < SB; u++) vv[u] = x[gi[u]];
+    for (int u = 0; u < BATCH; u++) vv[u] = x[gi[u]];
 #pragma unroll
-    for (int u = 0; u < SB; u++)
+    for (int u = 0; u < BATCH; u++)
       if (q0 + u * BAND_T < nreg) xs[q0 + u * BAND_T] = vv[u];
   }
-  for (int s2 = tid; s2 < nbg; s2 += BAND_T) gb[s2] = (double)b[bg_k[s2]];
+  for (int s2 = tid; s2 < nbg; s2 += BAND_T) {
+    gb[s2] = (double)b[bg_k[s2]];
+    if (MODE >= 2) {
+#pragma unroll
+      for (int z = 0; z < 9; z++) gw[z * nbg + s2] = bg_w[z * gcap + s2];
+      gdt[s2] = bg_dt[s2];
+#pragma unroll
+      for (int z = 0; z < 10; z++) gl[z * nbg + s2] = (uint16_t)bg_loc[z * gcap + s2];
+    }
+  }
+  if (MODE >= 3) {
+    for (int q = tid; q < nb; q += BAND_T) {
+      const int cell = bbox[22 * bcap + q], i = cell % N, j = cell / N, cg = (j + 1) * W + (i + 1);
+      bcl[q] = cell;
+      bfl[q] = bbox[21 * bcap + q];
+#pragma unroll
+      for (int z = 0; z < 21; z++) bsl[z * nb + q] = (uint16_t)bbox[z * bcap + q];
+      bbv[q] = (double)b[cg];
+      bbv[nb + q] = (double)b[cg + 1];
+      bbv[2 * nb + q] = (double)b[WW + cg];
+      bbv[3 * nb + q] = (double)b[WW + cg + W];
+      bbv[4 * nb + q] = (double)b[2 * WW + cg];
+    }
+  }
   // the cell of this thread's first box of the next colour is loaded one colour ahead, so that the right-hand
   // sides of the box can be loaded together with its table
-  int next_cell = off.o[0] + tid < off.o[1] ? bbox[22 * bcap + off.o[0] + tid] : 0;
+  int next_cell = MODE < 3 && off.o[0] + tid < off.o[1] ? bbox[22 * bcap + off.o[0] + tid] : 0;
   const double xi = (double)x[3 * WW];
   __syncthreads();
   // Jacobi sweeps of the body ghost rows; each new value goes through nv (written and read back by the same
   // thread), so no row data is held across the barrier
   auto ghost_block = [&]() {
     for (int it = 0; it < lambda; it++) {
-      for (int s0 = tid; s0 < nbg; s0 += 2 * BAND_T) {  // two rows per thread at a time: their loads overlap
-        const int s1 = s0 + BAND_T, t1 = s1 < nbg ? s1 : s0;
-        double sum0 = 0, sum1 = 0;
+      if (MODE >= 2) {
+        for (int s2 = tid; s2 < nbg; s2 += BAND_T) {
+          double sum = 0;
 #pragma unroll
-        for (int z = 0; z < 9; z++) {
-          sum0 += bg_w[z * gcap + s0] * tval(bg_loc[(1 + z) * gcap + s0]);
-          sum1 += bg_w[z * gcap + t1] * tval(bg_loc[(1 + z) * gcap + t1]);
+          for (int z = 0; z < 9; z++) sum += gw[z * nbg + s2] * (double)xs[gl[(1 + z) * nbg + s2]];
+          nv[s2] = (double)xs[gl[s2]] + gdt[s2] * (gb[s2] - sum);
         }
-        nv[s0] = (double)xs[bg_loc[s0]] + bg_dt[s0] * (gb[s0] - sum0);
-        if (s1 < nbg) nv[s1] = (double)xs[bg_loc[s1]] + bg_dt[s1] * (gb[s1] - sum1);
+      } else {
+        for (int s0 = tid; s0 < nbg; s0 += 2 * BAND_T) {  // two rows per thread at a time: their loads overlap
+          const int s1 = s0 + BAND_T, t1 = s1 < nbg ? s1 : s0;
+          double sum0 = 0, sum1 = 0;
+#pragma unroll
+          for (int z = 0; z < 9; z++) {
+            sum0 += bg_w[z * gcap + s0] * tval(bg_loc[(1 + z) * gcap + s0]);
+            sum1 += bg_w[z * gcap + t1] * tval(bg_loc[(1 + z) * gcap + t1]);
+          }
+          nv[s0] = (double)xs[bg_loc[s0]] + bg_dt[s0] * (gb[s0] - sum0);
+          if (s1 < nbg) nv[s1] = (double)xs[bg_loc[s1]] + bg_dt[s1] * (gb[s1] - sum1);
+        }
       }
       __syncthreads();
-      for (int s2 = tid; s2 < nbg; s2 += BAND_T) xs[bg_loc[s2]] = (T)nv[s2];
+      for (int s2 = tid; s2 < nbg; s2 += BAND_T) xs[MODE >= 2 ? (int)gl[s2] : bg_loc[s2]] = (T)nv[s2];
       __syncthreads();
+    }
+  };
+  // one band box: table entry fld (0..20 slots, 21 flags) and right-hand side k (W E S N P)
+  auto band_box = [&](auto TB, auto RB) {
+    const int f = TB(21);
+    const bool fW = f & 1, fE = f & 2, fS = f & 4, fN = f & 8, fP = f & 16;
+    double uW = tval(TB(0)), uE = tval(TB(1)), uWW = tval(TB(2)), uEE = tval(TB(3)), uWS = tval(TB(4)),
+           uWN = tval(TB(5)), uES = tval(TB(6)), uEN = tval(TB(7));
+    double vS = tval(TB(8)), vN = tval(TB(9)), vSS = tval(TB(10)), vNN = tval(TB(11)), vSW = tval(TB(12)),
+           vSE = tval(TB(13)), vNW = tval(TB(14)), vNE = tval(TB(15));
+    double pc = tval(TB(16)), pW = tval(TB(17)), pE = tval(TB(18)), pS = tval(TB(19)), pN = tval(TB(20));
+    const BoxNew o = box_core(K, fW, fE, fS, fN, fP, uW, uE, uWW, uEE, uWS, uWN, uES, uEN, vS, vN, vSS, vNN, vSW, vSE,
+                              vNW, vNE, pc, pW, pE, pS, pN, RB(0), RB(1), RB(2), RB(3), RB(4), xi);
+    if (!o.skip) {
+      if (fP) xs[TB(16)] = (T)o.p;
+      if (fW) xs[TB(0)] = (T)o.uW;
+      if (fE) xs[TB(1)] = (T)o.uE;
+      if (fS) xs[TB(8)] = (T)o.vS;
+      if (fN) xs[TB(9)] = (T)o.vN;
     }
   };
   ghost_block();
   for (int sw = 0; sw < sweeps; sw++) {
     for (int c = 0; c < 5; c++) {
-      const int first_cell = next_cell, cn = c == 4 ? 0 : c + 1;
-      next_cell = off.o[cn] + tid < off.o[cn + 1] ? bbox[22 * bcap + off.o[cn] + tid] : 0;
-      for (int q = off.o[c] + tid; q < off.o[c + 1]; q += BAND_T) {
-        auto TB = [&](int fld) { return bbox[fld * bcap + q]; };
-        int cell = q == off.o[c] + tid ? first_cell : TB(22), i = cell % N, j = cell / N, cg = (j + 1) * W + (i + 1);
-        int f = TB(21);
-        bool fW = f & 1, fE = f & 2, fS = f & 4, fN = f & 8, fP = f & 16;
-        double uW = tval(TB(0)), uE = tval(TB(1)), uWW = tval(TB(2)), uEE = tval(TB(3)), uWS = tval(TB(4)),
-               uWN = tval(TB(5)), uES = tval(TB(6)), uEN = tval(TB(7));
-        double vS = tval(TB(8)), vN = tval(TB(9)), vSS = tval(TB(10)), vNN = tval(TB(11)), vSW = tval(TB(12)),
-               vSE = tval(TB(13)), vNW = tval(TB(14)), vNE = tval(TB(15));
-        double pc = tval(TB(16)), pW = tval(TB(17)), pE = tval(TB(18)), pS = tval(TB(19)), pN = tval(TB(20));
-        double bW_ = b[cg], bE_ = b[cg + 1], bS_ = b[WW + cg], bN_ = b[WW + cg + W], bP_ = b[2 * WW + cg];
-        const BoxNew o = box_core(K, fW, fE, fS, fN, fP, uW, uE, uWW, uEE, uWS, uWN, uES, uEN, vS, vN, vSS, vNN, vSW, vSE,
-                                  vNW, vNE, pc, pW, pE, pS, pN, bW_, bE_, bS_, bN_, bP_, xi);
-        if (!o.skip) {
-          if (fP) xs[TB(16)] = (T)o.p;
-          if (fW) xs[TB(0)] = (T)o.uW;
-          if (fE) xs[TB(1)] = (T)o.uE;
-          if (fS) xs[TB(8)] = (T)o.vS;
-          if (fN) xs[TB(9)] = (T)o.vN;
+      if (MODE >= 3) {
+        for (int q = off.o[c] + tid; q < off.o[c + 1]; q += BAND_T)
+          band_box([&](int fld) { return fld == 21 ? bfl[q] : (int)bsl[fld * nb + q]; },
+                   [&](int k) { return bbv[k * nb + q]; });
+      } else {
+        const int first_cell = next_cell, cn = c == 4 ? 0 : c + 1;
+        next_cell = off.o[cn] + tid < off.o[cn + 1] ? bbox[22 * bcap + off.o[cn] + tid] : 0;
+        for (int q = off.o[c] + tid; q < off.o[c + 1]; q += BAND_T) {
+          const int cell = q == off.o[c] + tid ? first_cell : bbox[22 * bcap + q];
+          const int i = cell % N, j = cell / N, cg = (j + 1) * W + (i + 1);
+          const double rb[5] = {(double)b[cg], (double)b[cg + 1], (double)b[WW + cg], (double)b[WW + cg + W],
+                                (double)b[2 * WW + cg]};
+          band_box([&](int fld) { return bbox[fld * bcap + q]; }, [&](int k) { return rb[k]; });
         }
       }
       __syncthreads();
@@ -1325,14 +1386,22 @@ static void relax(Ctx *ctx, int l) {
     k_xi_faces<T><<<1, BAND_T, 0, s>>>(G.WW, G.h, V.x, G.f_code, G.nf, ctx->d_lev + l, G.d_mp);
     return;
   }
-  const size_t nv_off = (lds_bytes + 7) & ~(size_t)7, with_nv = nv_off + 2 * (size_t)G.nbg * sizeof(double);
+  const size_t with_nv = band_lds_bytes(1, lds_bytes, G.nbg, G.nband);
   if (band && G.lds_ok && with_nv + 1024 <= ctx->max_lds) {
-    // wall ghosts, body ghosts, band boxes and xi in one workgroup
+    // wall ghosts, body ghosts, band boxes and xi in one workgroup; the most staging that fits in LDS (16-bit
+    // slot numbers need fewer than 65536 region points)
     int nwb = (G.nwg + BAND_T - 1) / BAND_T;
     BandOff bo;
     for (int c = 0; c < 6; c++) bo.o[c] = G.hband_off[c];
-    auto kern = G.nreg > G.nregw ? k_band_lds<T, true> : k_band_lds<T, false>;
-    kern<<<1 + nwb, BAND_T, with_nv, s>>>(G.N, G.W, BK, V.x, V.b, bo, G.bbox, G.bcap, G.reg_pt, G.nreg, G.nregw, G.bg_k,
+    int mode = G.nreg > G.nregw ? 1 : 0;
+    if (mode == 1 && G.nreg < 65536) {
+      if (band_lds_bytes(3, lds_bytes, G.nbg, G.nband) + 1024 <= ctx->max_lds)
+        mode = 3;
+      else if (band_lds_bytes(2, lds_bytes, G.nbg, G.nband) + 1024 <= ctx->max_lds)
+        mode = 2;
+    }
+    auto kern = mode == 3 ? k_band_lds<T, 3> : mode == 2 ? k_band_lds<T, 2> : mode == 1 ? k_band_lds<T, 1> : k_band_lds<T, 0>;
+    kern<<<1 + nwb, BAND_T, band_lds_bytes(mode, lds_bytes, G.nbg, G.nband), s>>>(G.N, G.W, BK, V.x, V.b, bo, G.bbox, G.bcap, G.reg_pt, G.nreg, G.nregw, G.bg_k,
                                           G.bg_loc, G.bg_w, G.bg_dt, G.nbg, G.gcap, G.g_pt, G.g_col, G.g_w, G.g_dtau,
                                           G.wg_rows, G.nwg, ctx->prm.bnd_sweeps, ctx->prm.lambda_ghost, G.f_code, G.f_loc,
                                           G.nf, ctx->d_lev + l, G.d_mp);
