@@ -21,7 +21,7 @@ sys.path.insert(0, ROOT)
 PEAK_HBM_GBS = 8000.0
 # HBM bytes per launch of the finest-level five-colour box kernel from the two rocprofv3 counter runs (FETCH_SIZE
 # and WRITE_SIZE, each scaled by what it reads for a 64 MiB device copy); None until taken for the current kernel
-BOX_TRAFFIC_BYTES = 89.67e6
+BOX_TRAFFIC_BYTES = 88.66e6
 BOX_TRAFFIC_SOURCE = "profiles/k_box5_flower1024_hbm_traffic.md"
 
 
@@ -198,7 +198,7 @@ def main():
         solver.set_alpha(dt / (2.0 * Re))
         solver.set_rhs(fu, fv, None)
         us = solver.time_kernel(5, level=0, reps=10)
-        print(json.dumps({"profile_kernel": "k_box5<double> finest", "launches": 10, "avg_launch_us": us,
+        print(json.dumps({"profile_kernel": "k_box5<double, 32> finest", "launches": 10, "avg_launch_us": us,
                           "copy_bytes": 2 * (64 << 20)}))
         return
     for _ in range(args.warmup):
@@ -237,7 +237,7 @@ def main():
         traffic = BOX_TRAFFIC_BYTES if N == 1024 else None
         roofline = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                     "frac": achieved / PEAK_HBM_GBS, "traffic": traffic,
-                    "kernel": "k_box5<double> finest level (five colours per launch)", "bytes_per_launch": nbytes,
+                    "kernel": "k_box5<double, 32> finest level (five colours per launch)", "bytes_per_launch": nbytes,
                     "avg_launch_us": avg_us, "launches_timed": nprobe, "isolated_launch_us": iso_us,
                     "traffic_gbs": traffic / (avg_us * 1e-6) / 1e9 if traffic else None,
                     "traffic_source": BOX_TRAFFIC_SOURCE if traffic else None}
