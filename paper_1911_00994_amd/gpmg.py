@@ -164,7 +164,10 @@ class Solver:
             self._h = None
 
     def __del__(self):
-        self.close()
+        try:
+            self.close()
+        except TypeError:  # interpreter shutdown: module globals already cleared, the process frees the device
+            pass
 
     def level_n(self, l):
         return self.N >> l
