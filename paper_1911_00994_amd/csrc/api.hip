@@ -279,7 +279,7 @@ gp_status gp_setup_grid(gp_ctx **out, int N, double Re, const gp_params *prm, vo
   ALLOC(ctx->phi, (size_t)(2 * N + 1) * (2 * N + 1));
   ALLOC(ctx->gtmp, gmax);
   ALLOC(ctx->gtmp2, gmax);
-  ALLOC(ctx->d_red, 8192);
+  ALLOC(ctx->d_red, std::max<size_t>(8192, 2 * (size_t)nblk(3L * (N + 2) * (N + 2)) + 16));  // block partials
   ALLOC(ctx->d_ticket, 4);
   ALLOC(ctx->d_scal, 16);
   ALLOC(ctx->d_lev, 2 * MAXLEV);

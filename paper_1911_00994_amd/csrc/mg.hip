@@ -788,54 +788,61 @@ __global__ void __launch_bounds__(TPB) k_resid_pts(int N, int W, double h, doubl
   (void)rmax;
 }
 // variant with the max norm (all lanes of a wavefront take part in the reduction)
-__device__ __forceinline__ void block_max_atomic(unsigned long long *m, double v) {
-  __shared__ unsigned long long sm[TPB / 64];
-  unsigned long long a = (unsigned long long)__double_as_longlong(fabs(v));
-  for (int o = 32; o > 0; o >>= 1) {
-    unsigned long long b = __shfl_xor(a, o, 64);
-    a = b > a ? b : a;
-  }
-  if ((threadIdx.x & 63) == 0) sm[threadIdx.x >> 6] = a;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    unsigned long long z = 0;
-    for (int q = 0; q < TPB / 64; q++) z = sm[q] > z ? sm[q] : z;
-    if (z) atomicMax(m, z);
-  }
-}
-// residual of the point rows with its max norm; each block also leaves its sum of the internal pressures in
-// part[block] for k_resid_mean_row (no grid-wide fence here: the kernel writes the whole residual)
+// residual of the point rows, one point per thread; each block leaves the largest |residual| (as the bits of the
+// double, which order like the values; NaN above everything) in part[nb + block] and its sum of the internal
+// pressures in part[block], for k_resid_mean_row (no atomics and no grid-wide fence: the kernel writes the
+// whole residual)
 template <typename T>
-__global__ void __launch_bounds__(TPB) k_resid_pts_norm(int N, int W, double h, double a, double d,
+__global__ void __launch_bounds__(TPB) k_resid_pts_norm(int W, double h, double a, double d,
                                                         const uint8_t *__restrict__ cls, const T *__restrict__ x,
-                                                        const T *__restrict__ b, T *__restrict__ r, unsigned long long *rmax,
-                                                        double *part) {
+                                                        const T *__restrict__ b, T *__restrict__ r, double *part) {
+  __shared__ unsigned long long sm[TPB / 64];
   const int WW = W * W;
-  double mx = 0, ps = 0;
-  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < 3 * WW; t += gridDim.x * blockDim.x) {
-    double res = resid_point<T>(W, h, a, d, cls, x, b, t);
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  double res = 0, ps = 0;
+  if (t < 3 * WW) {
+    res = resid_point<T>(W, h, a, d, cls, x, b, t);
     r[t] = (T)res;
-    double ar = fabs(res);
-    mx = (ar > mx || ar != ar) ? ar : mx;
     if (t >= 2 * WW && cls[t] == K_INT) ps += (double)x[t];
   }
-  block_max_atomic(rmax, mx);
-  ps = block_sum(ps);
-  if (threadIdx.x == 0) part[blockIdx.x] = ps;
-  (void)N;
+  unsigned long long m = (unsigned long long)__double_as_longlong(fabs(res));
+  for (int o = 32; o > 0; o >>= 1) {
+    unsigned long long q = __shfl_xor(m, o, 64);
+    m = q > m ? q : m;
+  }
+  if ((threadIdx.x & 63) == 0) sm[threadIdx.x >> 6] = m;
+  ps = block_sum(ps);  // its barriers also publish sm
+  if (threadIdx.x == 0) {
+    for (int q = 0; q < TPB / 64; q++) m = sm[q] > m ? sm[q] : m;
+    part[blockIdx.x] = ps;
+    part[gridDim.x + blockIdx.x] = __longlong_as_double((long long)m);
+  }
 }
-// the mean-pressure row's residual -mean(p) from the block sums of k_resid_pts_norm (fixed order), into r[3WW]
-// and the norm
+// the mean-pressure row's residual -mean(p) from the block sums of k_resid_pts_norm (fixed order), into r[3WW], and
+// the max norm of the whole residual into *rmax (as bits)
 template <typename T>
 __global__ void __launch_bounds__(TPB) k_resid_mean_row(const double *__restrict__ part, int nb, const int *mp,
                                                         T *r3, unsigned long long *rmax) {
+  __shared__ unsigned long long sm[TPB / 64];
   double v = 0;
-  for (int q = threadIdx.x; q < nb; q += TPB) v += part[q];
+  unsigned long long m = 0;
+  for (int q = threadIdx.x; q < nb; q += TPB) {
+    v += part[q];
+    unsigned long long z = (unsigned long long)__double_as_longlong(part[nb + q]);
+    m = z > m ? z : m;
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    unsigned long long q = __shfl_xor(m, o, 64);
+    m = q > m ? q : m;
+  }
+  if ((threadIdx.x & 63) == 0) sm[threadIdx.x >> 6] = m;
   v = block_sum(v);
   if (threadIdx.x == 0) {
-    double res = -v / *mp;
+    for (int q = 0; q < TPB / 64; q++) m = sm[q] > m ? sm[q] : m;
+    const double res = -v / *mp;
     *r3 = (T)res;
-    atomicMax(rmax, (unsigned long long)__double_as_longlong(fabs(res)));
+    const unsigned long long z = (unsigned long long)__double_as_longlong(fabs(res));
+    *rmax = z > m ? z : m;
   }
 }
 template <typename T>
@@ -890,10 +897,11 @@ __global__ void k_fill(T *x, long n, T val) {
 // ---------------------------------------------------------------------------------------------------------
 // boundary-aware restriction (eqs. restop, restop5)
 // ---------------------------------------------------------------------------------------------------------
-// boundary-aware restriction of the fine residual to coarse entry t (t = 3 WWc is the mean row: 0)
-template <typename TF>
-__device__ __forceinline__ double restrict_value(int Nf, int Wf, const uint8_t *__restrict__ clsf, const TF *__restrict__ rf,
-                                                 int Nc, int Wc, const uint8_t *__restrict__ clsc, int t) {
+// boundary-aware restriction of the fine residual to coarse entry t (t = 3 WWc is the mean row: 0); the fine
+// residual at point kf of class cc is rv(kf, cc)
+template <typename RV>
+__device__ __forceinline__ double restrict_core(int Nf, int Wf, const uint8_t *__restrict__ clsf, int Nc, int Wc,
+                                                const uint8_t *__restrict__ clsc, int t, RV rvf) {
   const int WWc = Wc * Wc, WWf = Wf * Wf;
   if (t == 3 * WWc) return 0.0;
   int g = t / WWc, q = t - g * WWc, jc = q / Wc - 1, ic = q % Wc - 1;
@@ -937,7 +945,7 @@ __device__ __forceinline__ double restrict_value(int Nf, int Wf, const uint8_t *
     }
     int kf = g * WWf + pidx(Wf, fi[z], fj[z]);
     if (clsf[kf] == cc) {
-      double rv = (double)rf[kf];
+      double rv = rvf(kf, cc);
       cnt++;
       sw += fw[z] * rv;
       sa += rv;
@@ -946,8 +954,29 @@ __device__ __forceinline__ double restrict_value(int Nf, int Wf, const uint8_t *
   }
   return all ? sw : (cnt ? sa / cnt : 0.0);
 }
+template <typename TF>
+__device__ __forceinline__ double restrict_value(int Nf, int Wf, const uint8_t *__restrict__ clsf, const TF *__restrict__ rf,
+                                                 int Nc, int Wc, const uint8_t *__restrict__ clsc, int t) {
+  return restrict_core(Nf, Wf, clsf, Nc, Wc, clsc, t, [&](int kf, uint8_t) { return (double)rf[kf]; });
+}
+// residual and restriction in one pass: the residual of an internal fine row is formed where the restriction
+// needs it (rounded to T, as the stored residual would be); ghost and wall-ghost residuals come from rf, written
+// before by k_resid_ghost.  Also the zero initial guess of the coarse correction.
+template <typename T>
+__global__ void __launch_bounds__(TPB) k_resid_restrict(int Nf, int Wf, double h, double a, double d,
+                                                        const uint8_t *__restrict__ clsf, const T *__restrict__ xf,
+                                                        const T *__restrict__ bf, const T *__restrict__ rf, int Nc, int Wc,
+                                                        const uint8_t *__restrict__ clsc, T *__restrict__ bc,
+                                                        T *__restrict__ xc) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t > 3 * Wc * Wc) return;
+  bc[t] = (T)restrict_core(Nf, Wf, clsf, Nc, Wc, clsc, t, [&](int kf, uint8_t cc) {
+    return cc == K_INT ? (double)(T)resid_point<T>(Wf, h, a, d, clsf, xf, bf, kf) : (double)rf[kf];
+  });
+  xc[t] = (T)0;
+}
+// restriction of a stored residual (and, when xc is given, the zero initial guess of the coarse correction)
 template <typename TF, typename TC>
-// (and, when xc is given, the zero initial guess of the coarse correction)
 __global__ void __launch_bounds__(TPB) k_restrict(int Nf, int Wf, const uint8_t *__restrict__ clsf, const TF *__restrict__ rf,
                                                   int Nc, int Wc, const uint8_t *__restrict__ clsc, TC *__restrict__ bc,
                                                   TC *__restrict__ xc) {
@@ -1436,9 +1465,9 @@ static void residual(Ctx *ctx, int l, unsigned long long *rmax) {
   hipStream_t s = ctx->stream;
   double a = coef_a(ctx, l), d = 1.0 + 4.0 * a;
   if (rmax) {
-    // at most 2048 blocks: one partial sum each in d_red (8192 slots)
-    const int nb = std::min(2048, nblk(3L * G.WW));
-    k_resid_pts_norm<T><<<nb, TPB, 0, s>>>(G.N, G.W, G.h, a, d, G.cls, V.x, V.b, V.r, rmax, ctx->d_red);
+    // two partials per block in d_red (2 nblk(3 (N+2)^2) + 16 slots)
+    const int nb = nblk(3L * G.WW);
+    k_resid_pts_norm<T><<<nb, TPB, 0, s>>>(G.W, G.h, a, d, G.cls, V.x, V.b, V.r, ctx->d_red);
     k_resid_mean_row<T><<<1, TPB, 0, s>>>(ctx->d_red, nb, G.d_mp, V.r + 3L * G.WW, rmax);
     if (G.ng) k_resid_ghost_norm<T><<<nblk(G.ng), TPB, 0, s>>>(G.g_pt, G.g_col, G.g_w, G.ng, V.x, V.b, V.r, rmax);
   } else {
@@ -1536,8 +1565,12 @@ static void cycle(Ctx *ctx, int l) {
   Vec<T> &VF = vec<T>(ctx, l), &VC = vec<T>(ctx, l + 1);
   hipStream_t s = ctx->stream;
   for (int q = 0; q < ctx->prm.nu1; q++) relax<T>(ctx, l);
-  residual<T>(ctx, l, nullptr);
-  k_restrict<T, T><<<nblk(3L * C.WW + 1), TPB, 0, s>>>(F.N, F.W, F.cls, VF.r, C.N, C.W, C.cls, VC.b, VC.x);
+  {
+    const double a = coef_a(ctx, l), d = 1.0 + 4.0 * a;
+    if (F.ng) k_resid_ghost<T><<<nblk(F.ng), TPB, 0, s>>>(F.g_pt, F.g_col, F.g_w, F.ng, VF.x, VF.b, VF.r, nullptr);
+    k_resid_restrict<T><<<nblk(3L * C.WW + 1), TPB, 0, s>>>(F.N, F.W, F.h, a, d, F.cls, VF.x, VF.b, VF.r, C.N, C.W, C.cls,
+                                                          VC.b, VC.x);
+  }
   if (l + 1 < ctx->L - 1) gsum<T>(ctx, l + 1);
   int reps = (l + 1 == ctx->L - 1) ? 1 : ctx->prm.gamma;
   for (int q = 0; q < reps; q++) cycle<T>(ctx, l + 1);
