@@ -24,11 +24,9 @@ __device__ __forceinline__ int pidx(int W, int i, int j) { return (j + 1) * W + 
 //   one free:   d uW = RW + a uE - p/h   (resp. d uE = RE + a uW + p/h)
 // and the continuity row fixes p.
 // ---------------------------------------------------------------------------------------------------------
-// per-level constants of the box solve (the quotients by d, d + a and d^2 - a^2 and the nine possible
-// denominators of the pressure, which depend only on which faces of the box are free)
+// per-level constants of the box solve (the quotients by d, d + a and d^2 - a^2)
 struct BoxK {
   double h, ih, a, q1, q2, bp, id, ihd;  // q1 = d / det, q2 = a / det, bp = (1/h) / (d + a), id = 1 / d, ihd = (1/h) / d
-  double iden[9];                        // 1 / (Du + Dv), Du, Dv in {0, ihd, 2 bp} (index 3 iu + iv); 0 if Du + Dv = 0
 };
 inline BoxK box_consts(double h, double a, double d) {
   BoxK K;
@@ -41,9 +39,6 @@ inline BoxK box_consts(double h, double a, double d) {
   K.bp = K.ih / (d + a);
   K.id = 1.0 / d;
   K.ihd = K.ih / d;
-  const double D[3] = {0.0, K.ihd, 2.0 * K.bp};
-  for (int iu = 0; iu < 3; iu++)
-    for (int iv = 0; iv < 3; iv++) K.iden[3 * iu + iv] = (iu || iv) ? 1.0 / (D[iu] + D[iv]) : 0.0;
   return K;
 }
 
@@ -57,58 +52,29 @@ __device__ __forceinline__ BoxNew box_core(const BoxK &K, bool fW, bool fE, bool
                                            double vN, double vSS, double vNN, double vSW, double vSE, double vNW, double vNE,
                                            double pc, double pW, double pE, double pS, double pN, double bW_, double bE_,
                                            double bS_, double bN_, double bP_, double xi) {
+  // written without branches: every candidate is formed and the classes select (the same arithmetic for each
+  // selected value).  The pressure's denominator Du + Dv (each 0, ihd or 2 bp, by the free faces of the pair)
+  // is divided here: a table indexed by lane-varying values would be a memory load on the critical path.
   BoxNew o;
-  o.skip = false;
   const double a = K.a, ih = K.ih;
-  double aW = uW, bW = 0, aE = uE, bE = 0, aS = vS, bS = 0, aN = vN, bN = 0;
-  int iu = 0, iv = 0;
-  {
-    const double RW = bW_ + a * (uWW + uWS + uWN) + pW * ih;
-    const double RE = bE_ + a * (uEE + uES + uEN) - pE * ih;
-    if (fW && fE) {
-      aW = K.q1 * RW + K.q2 * RE;
-      bW = -K.bp;
-      aE = K.q2 * RW + K.q1 * RE;
-      bE = K.bp;
-      iu = 2;
-    } else if (fW) {
-      aW = (RW + a * uE) * K.id;
-      bW = -K.ihd;
-      iu = 1;
-    } else if (fE) {
-      aE = (RE + a * uW) * K.id;
-      bE = K.ihd;
-      iu = 1;
-    }
-  }
-  {
-    const double RS = bS_ + a * (vSS + vSW + vSE) + pS * ih;
-    const double RN = bN_ + a * (vNN + vNW + vNE) - pN * ih;
-    if (fS && fN) {
-      aS = K.q1 * RS + K.q2 * RN;
-      bS = -K.bp;
-      aN = K.q2 * RS + K.q1 * RN;
-      bN = K.bp;
-      iv = 2;
-    } else if (fS) {
-      aS = (RS + a * vN) * K.id;
-      bS = -K.ihd;
-      iv = 1;
-    } else if (fN) {
-      aN = (RN + a * vS) * K.id;
-      bN = K.ihd;
-      iv = 1;
-    }
-  }
-  double pn = pc;
-  if (fP) {
-    const double idn = K.iden[3 * iu + iv];
-    if (idn == 0.0) {  // no free face: the block is singular, the box is skipped
-      o.skip = true;
-      return o;
-    }
-    pn = (K.h * (xi + bP_) - (aE - aW + aN - aS)) * idn;
-  }
+  const double RW = bW_ + a * (uWW + uWS + uWN) + pW * ih;
+  const double RE = bE_ + a * (uEE + uES + uEN) - pE * ih;
+  const double RS = bS_ + a * (vSS + vSW + vSE) + pS * ih;
+  const double RN = bN_ + a * (vNN + vNW + vNE) - pN * ih;
+  const bool u2 = fW && fE, v2 = fS && fN;
+  const double aW = u2 ? K.q1 * RW + K.q2 * RE : fW ? (RW + a * uE) * K.id : uW;
+  const double aE = u2 ? K.q2 * RW + K.q1 * RE : fE ? (RE + a * uW) * K.id : uE;
+  const double bW = u2 ? -K.bp : fW ? -K.ihd : 0.0;
+  const double bE = u2 ? K.bp : fE ? K.ihd : 0.0;
+  const double aS = v2 ? K.q1 * RS + K.q2 * RN : fS ? (RS + a * vN) * K.id : vS;
+  const double aN = v2 ? K.q2 * RS + K.q1 * RN : fN ? (RN + a * vS) * K.id : vN;
+  const double bS = v2 ? -K.bp : fS ? -K.ihd : 0.0;
+  const double bN = v2 ? K.bp : fN ? K.ihd : 0.0;
+  const double Du = u2 ? 2.0 * K.bp : (fW || fE) ? K.ihd : 0.0;
+  const double Dv = v2 ? 2.0 * K.bp : (fS || fN) ? K.ihd : 0.0;
+  const double den = Du + Dv;
+  o.skip = fP && den == 0.0;  // no free face: the block is singular, the box is skipped
+  const double pn = fP ? (K.h * (xi + bP_) - (aE - aW + aN - aS)) * (1.0 / den) : pc;
   o.p = pn;
   o.uW = aW + bW * pn;
   o.uE = aE + bE * pn;
@@ -819,27 +785,47 @@ __global__ void __launch_bounds__(TPB) k_resid_pts_norm(int W, double h, double 
   }
 }
 // the mean-pressure row's residual -mean(p) from the block sums of k_resid_pts_norm (fixed order), into r[3WW], and
-// the max norm of the whole residual into *rmax (as bits)
+// the max norm of the whole residual into *rmax (as bits).  1024 threads, eight loads in flight per thread.
+constexpr int RM_T = 1024;
 template <typename T>
-__global__ void __launch_bounds__(TPB) k_resid_mean_row(const double *__restrict__ part, int nb, const int *mp,
-                                                        T *r3, unsigned long long *rmax) {
-  __shared__ unsigned long long sm[TPB / 64];
+__global__ void __launch_bounds__(RM_T) k_resid_mean_row(const double *__restrict__ part, int nb, const int *mp,
+                                                         T *r3, unsigned long long *rmax) {
+  __shared__ double ssum[RM_T / 64];
+  __shared__ unsigned long long smax[RM_T / 64];
   double v = 0;
   unsigned long long m = 0;
-  for (int q = threadIdx.x; q < nb; q += TPB) {
-    v += part[q];
-    unsigned long long z = (unsigned long long)__double_as_longlong(part[nb + q]);
-    m = z > m ? z : m;
+  for (int q0 = threadIdx.x; q0 < nb; q0 += 8 * RM_T) {
+    double ps[8], pm[8];
+#pragma unroll
+    for (int u = 0; u < 8; u++) {
+      const int q = q0 + u * RM_T;
+      ps[u] = q < nb ? part[q] : 0.0;
+      pm[u] = q < nb ? part[nb + q] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; u++) {
+      v += ps[u];
+      const unsigned long long z = (unsigned long long)__double_as_longlong(pm[u]);
+      m = z > m ? z : m;
+    }
   }
   for (int o = 32; o > 0; o >>= 1) {
-    unsigned long long q = __shfl_xor(m, o, 64);
+    v += __shfl_xor(v, o, 64);
+    const unsigned long long q = __shfl_xor(m, o, 64);
     m = q > m ? q : m;
   }
-  if ((threadIdx.x & 63) == 0) sm[threadIdx.x >> 6] = m;
-  v = block_sum(v);
+  if ((threadIdx.x & 63) == 0) {
+    ssum[threadIdx.x >> 6] = v;
+    smax[threadIdx.x >> 6] = m;
+  }
+  __syncthreads();
   if (threadIdx.x == 0) {
-    for (int q = 0; q < TPB / 64; q++) m = sm[q] > m ? sm[q] : m;
-    const double res = -v / *mp;
+    double tot = 0;
+    for (int q = 0; q < RM_T / 64; q++) {
+      tot += ssum[q];
+      m = smax[q] > m ? smax[q] : m;
+    }
+    const double res = -tot / *mp;
     *r3 = (T)res;
     const unsigned long long z = (unsigned long long)__double_as_longlong(fabs(res));
     *rmax = z > m ? z : m;
@@ -1468,7 +1454,7 @@ static void residual(Ctx *ctx, int l, unsigned long long *rmax) {
     // two partials per block in d_red (2 nblk(3 (N+2)^2) + 16 slots)
     const int nb = nblk(3L * G.WW);
     k_resid_pts_norm<T><<<nb, TPB, 0, s>>>(G.W, G.h, a, d, G.cls, V.x, V.b, V.r, ctx->d_red);
-    k_resid_mean_row<T><<<1, TPB, 0, s>>>(ctx->d_red, nb, G.d_mp, V.r + 3L * G.WW, rmax);
+    k_resid_mean_row<T><<<1, RM_T, 0, s>>>(ctx->d_red, nb, G.d_mp, V.r + 3L * G.WW, rmax);
     if (G.ng) k_resid_ghost_norm<T><<<nblk(G.ng), TPB, 0, s>>>(G.g_pt, G.g_col, G.g_w, G.ng, V.x, V.b, V.r, rmax);
   } else {
     k_resid_pts<T><<<nblk(3L * G.WW), TPB, 0, s>>>(G.N, G.W, G.h, a, d, G.cls, V.x, V.b, V.r, nullptr);
