@@ -52,29 +52,59 @@ __device__ __forceinline__ BoxNew box_core(const BoxK &K, bool fW, bool fE, bool
                                            double vN, double vSS, double vNN, double vSW, double vSE, double vNW, double vNE,
                                            double pc, double pW, double pE, double pS, double pN, double bW_, double bE_,
                                            double bS_, double bN_, double bP_, double xi) {
-  // written without branches: every candidate is formed and the classes select (the same arithmetic for each
-  // selected value).  The pressure's denominator Du + Dv (each 0, ihd or 2 bp, by the free faces of the pair)
-  // is divided here: a table indexed by lane-varying values would be a memory load on the critical path.
+  // the pressure's denominator is Du + Dv, each 0, ihd or 2 bp by the free faces of the pair; it is divided
+  // here (a table indexed by lane-varying values would be a memory load on the critical path)
   BoxNew o;
+  o.skip = false;
   const double a = K.a, ih = K.ih;
-  const double RW = bW_ + a * (uWW + uWS + uWN) + pW * ih;
-  const double RE = bE_ + a * (uEE + uES + uEN) - pE * ih;
-  const double RS = bS_ + a * (vSS + vSW + vSE) + pS * ih;
-  const double RN = bN_ + a * (vNN + vNW + vNE) - pN * ih;
-  const bool u2 = fW && fE, v2 = fS && fN;
-  const double aW = u2 ? K.q1 * RW + K.q2 * RE : fW ? (RW + a * uE) * K.id : uW;
-  const double aE = u2 ? K.q2 * RW + K.q1 * RE : fE ? (RE + a * uW) * K.id : uE;
-  const double bW = u2 ? -K.bp : fW ? -K.ihd : 0.0;
-  const double bE = u2 ? K.bp : fE ? K.ihd : 0.0;
-  const double aS = v2 ? K.q1 * RS + K.q2 * RN : fS ? (RS + a * vN) * K.id : vS;
-  const double aN = v2 ? K.q2 * RS + K.q1 * RN : fN ? (RN + a * vS) * K.id : vN;
-  const double bS = v2 ? -K.bp : fS ? -K.ihd : 0.0;
-  const double bN = v2 ? K.bp : fN ? K.ihd : 0.0;
-  const double Du = u2 ? 2.0 * K.bp : (fW || fE) ? K.ihd : 0.0;
-  const double Dv = v2 ? 2.0 * K.bp : (fS || fN) ? K.ihd : 0.0;
-  const double den = Du + Dv;
-  o.skip = fP && den == 0.0;  // no free face: the block is singular, the box is skipped
-  const double pn = fP ? (K.h * (xi + bP_) - (aE - aW + aN - aS)) * (1.0 / den) : pc;
+  double aW = uW, bW = 0, aE = uE, bE = 0, aS = vS, bS = 0, aN = vN, bN = 0, Du = 0, Dv = 0;
+  {
+    const double RW = bW_ + a * (uWW + uWS + uWN) + pW * ih;
+    const double RE = bE_ + a * (uEE + uES + uEN) - pE * ih;
+    if (fW && fE) {
+      aW = K.q1 * RW + K.q2 * RE;
+      bW = -K.bp;
+      aE = K.q2 * RW + K.q1 * RE;
+      bE = K.bp;
+      Du = 2.0 * K.bp;
+    } else if (fW) {
+      aW = (RW + a * uE) * K.id;
+      bW = -K.ihd;
+      Du = K.ihd;
+    } else if (fE) {
+      aE = (RE + a * uW) * K.id;
+      bE = K.ihd;
+      Du = K.ihd;
+    }
+  }
+  {
+    const double RS = bS_ + a * (vSS + vSW + vSE) + pS * ih;
+    const double RN = bN_ + a * (vNN + vNW + vNE) - pN * ih;
+    if (fS && fN) {
+      aS = K.q1 * RS + K.q2 * RN;
+      bS = -K.bp;
+      aN = K.q2 * RS + K.q1 * RN;
+      bN = K.bp;
+      Dv = 2.0 * K.bp;
+    } else if (fS) {
+      aS = (RS + a * vN) * K.id;
+      bS = -K.ihd;
+      Dv = K.ihd;
+    } else if (fN) {
+      aN = (RN + a * vS) * K.id;
+      bN = K.ihd;
+      Dv = K.ihd;
+    }
+  }
+  double pn = pc;
+  if (fP) {
+    const double den = Du + Dv;
+    if (den == 0.0) {  // no free face: the block is singular, the box is skipped
+      o.skip = true;
+      return o;
+    }
+    pn = (K.h * (xi + bP_) - (aE - aW + aN - aS)) * (1.0 / den);
+  }
   o.p = pn;
   o.uW = aW + bW * pn;
   o.uE = aE + bE * pn;
