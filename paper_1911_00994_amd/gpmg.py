@@ -214,10 +214,15 @@ class Solver:
         args = [a if on_device else _host(a) for a in (u, v, p)]
         self._check(lib().gp_set_x(self._h, *[_ptr(a) for a in args], xi, int(on_device)), "gp_set_x")
 
-    def get_x(self):
+    def get_x(self, device_out=None):
+        """(u, v, p, xi) as host arrays; with device_out = (u, v, p) device addresses (W*W doubles each), the grids
+        are copied there instead and only xi is returned"""
         W = self.W
-        u, v, p = np.zeros((W, W)), np.zeros((W, W)), np.zeros((W, W))
         xi = ctypes.c_double(0)
+        if device_out is not None:
+            self._check(lib().gp_get_x(self._h, *[_ptr(int(a)) for a in device_out], ctypes.byref(xi), 1), "gp_get_x")
+            return xi.value
+        u, v, p = np.zeros((W, W)), np.zeros((W, W)), np.zeros((W, W))
         self._check(lib().gp_get_x(self._h, _ptr(u), _ptr(v), _ptr(p), ctypes.byref(xi), 0), "gp_get_x")
         return u, v, p, xi.value
 
@@ -337,7 +342,8 @@ class Solver:
 
     # reverse mode of a run of steps ---------------------------------------------------------------
     def tape_forward(self, kind, params, motion, t0, dt, nsteps, fu=None, fv=None, ub_offset=None, tol=1e-10,
-                     max_cycles=100, picard_eps=1e-6, picard_max=20, checkpoint_every=8):
+                     max_cycles=100, picard_eps=1e-6, picard_max=20, checkpoint_every=8, on_device=False):
+        """fu, fv: host arrays, or device addresses when on_device"""
         sh = GpShape()
         sh.kind = kind
         for q, v in enumerate(list(params)[:4]):
@@ -345,17 +351,26 @@ class Solver:
         mo = GpRigid(*[float(v) for v in motion[:5]])
         off = None if ub_offset is None else np.ascontiguousarray(ub_offset, dtype=np.float64)
         s = GpStats()
-        st = lib().gp_tape_forward(self._h, ctypes.byref(sh), ctypes.byref(mo), t0, dt, nsteps, _ptr(_host(fu)),
-                                   _ptr(_host(fv)), 0, _ptr(off), tol, max_cycles, picard_eps, picard_max,
+        f = [_ptr(None if a is None else int(a)) if on_device else _ptr(_host(a)) for a in (fu, fv)]
+        st = lib().gp_tape_forward(self._h, ctypes.byref(sh), ctypes.byref(mo), t0, dt, nsteps, f[0], f[1],
+                                   int(on_device), _ptr(off), tol, max_cycles, picard_eps, picard_max,
                                    checkpoint_every, ctypes.byref(s))
         self._check(st, "gp_tape_forward")
         return s.as_dict()
 
-    def tape_backward(self, seed_u, seed_v, tol=1e-10, max_cycles=200):
+    def tape_backward(self, seed_u, seed_v, tol=1e-10, max_cycles=200, device_out=None):
+        """host seeds and outputs; with device_out = (dfu, dfv, du0, dv0) device addresses (any may be None), the
+        seeds are device addresses too and the grids go there (the dict then holds dU and stats only)"""
         W = self.W
-        dfu, dfv, du0, dv0 = (np.zeros((W, W)) for _ in range(4))
         dU = np.zeros(2)
         s = GpStats()
+        if device_out is not None:
+            outs = [_ptr(None if a is None else int(a)) for a in device_out]
+            st = lib().gp_tape_backward(self._h, _ptr(int(seed_u)), _ptr(int(seed_v)), 1, tol, max_cycles, outs[0],
+                                        outs[1], _ptr(dU), outs[2], outs[3], ctypes.byref(s))
+            self._check(st, "gp_tape_backward")
+            return dict(dU=dU, stats=s.as_dict())
+        dfu, dfv, du0, dv0 = (np.zeros((W, W)) for _ in range(4))
         st = lib().gp_tape_backward(self._h, _ptr(_host(seed_u)), _ptr(_host(seed_v)), 0, tol, max_cycles, _ptr(dfu),
                                     _ptr(dfv), _ptr(dU), _ptr(du0), _ptr(dv0), ctypes.byref(s))
         self._check(st, "gp_tape_backward")
