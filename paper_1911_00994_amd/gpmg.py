@@ -71,6 +71,10 @@ def lib():
         return _lib
     if not os.path.exists(LIBPATH):
         raise RuntimeError(f"libgpmg.so not built ({LIBPATH}); run __graft_entry__.build()")
+    # PyTorch carries its own HIP runtime under the same soname: loading it first makes it the one runtime of
+    # the process, shared by the library (device pointers and streams pass between the two).  Loaded the other
+    # way round, PyTorch finds no GPU.
+    import torch  # noqa: F401
     L = ctypes.CDLL(LIBPATH)
     vp, i, d = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
     sigs = {

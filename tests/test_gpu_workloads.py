@@ -1,0 +1,128 @@
+"""The remaining workload shapes at the sizes they are quoted at, on the HIP path.
+
+* Lid-driven cavity around a fixed circle (r = 0.2, top lid u = 1, Re = 1000, dt = h): four CN steps in lockstep
+  with the oracle at N = 64; at the full N = 2048, mixed precision against FP64 on the GPU (the oracle cannot run
+  there; the two must agree to the tolerance the solves are taken to).
+* Reverse mode at the full adjoint size (N = 512, circle r = 0.25 moving at (0.5, 0), Re = 100, 40 steps,
+  checkpoints every 8): the gradient with respect to the boundary-velocity offset and to the forcing along a
+  random direction, against central differences of the HIP forward model (eps = 1e-5, solves to 1e-11: with
+  finer steps the solver's own tolerance dominates the difference quotient at this size).
+Every case prints its name before touching the GPU.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1911_00994_amd import workloads as wl
+from tests.common import active_mask
+
+pytestmark = pytest.mark.gpu
+
+LID = (0.0, 0.0, 0.0, 0.0, 1.0, 0.0, 0.0, 0.0)
+CAV = wl.Shape(wl.CIRCLE_DIST, (0.2,))
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def flat(xs):
+    u, v, p, xi = xs
+    return np.concatenate([u.ravel(), v.ravel(), p.ravel(), [xi]])
+
+
+def cavity_gpu(N, Re, **params):
+    from paper_1911_00994_amd import gpmg
+    s = gpmg.Solver(N, Re=Re, **params)
+    s.set_walls(LID)
+    s.set_levelset_analytic(CAV.kind, CAV.params, 0.0, None)
+    z = np.zeros((N + 2, N + 2))
+    s.set_state(z, z, z, 0.0)
+    return s
+
+
+def test_cavity_lockstep_parity():
+    N, Re, nsteps = 64, 1000.0, 4
+    say(f"[cavity lockstep] N={N} steps={nsteps}")
+    dt = 2.0 / N
+    o = O.Oracle(N, Re=Re)
+    o.set_walls(LID)
+    phi = O.levelset_analytic(CAV.kind, CAV.padded(), np.zeros(6), 0.0, N)
+    assert o.set_levelset(phi, 0.0, np.zeros(6)) == O.OK
+    z = np.zeros((N + 2, N + 2))
+    assert o.set_state(z, z, z, 0.0) == O.OK
+    s = cavity_gpu(N, Re)
+    assert np.array_equal(o.classes(), s.classes())
+    act = np.concatenate([active_mask(o.classes().ravel()), [True]])
+    for n in range(nsteps):
+        st, info = o.cn_step(dt, None, None, None, tol=1e-12, max_cycles=300, picard_eps=1e-12, picard_max=40)
+        assert st == O.OK, info
+        st, ginfo = s.cn_step(dt, None, None, None, tol=1e-12, max_cycles=300, picard_eps=1e-12, picard_max=40)
+        assert st == 0, ginfo
+        a, b = flat(o.get_x()), flat(s.get_x())
+        d = np.abs(a - b)[act].max() / max(1.0, np.abs(a[act]).max())
+        say(f"  step {n}: max |u| {np.abs(b[act]).max():.3f} rel diff {d:.2e}")
+        assert d < 1e-9
+
+
+def test_cavity_full_size_mixed_matches_fp64():
+    from paper_1911_00994_amd import gpmg
+    N, Re, nsteps, tol = 2048, 1000.0, 4, 1e-8
+    say(f"[cavity full size] N={N} steps={nsteps}")
+    dt = 2.0 / N
+    out = {}
+    for name, prec in (("fp64", gpmg.GP_FP64), ("mixed", gpmg.GP_MIXED)):
+        s = cavity_gpu(N, Re)
+        for n in range(nsteps):
+            st, info = s.cn_step(dt, None, None, None, precision=prec, tol=tol, max_cycles=200, picard_eps=1e-8,
+                                 picard_max=40)
+            assert st == 0, (name, n, info)  # converged to tol
+        out[name] = flat(s.get_x())
+        cls = s.classes().ravel()
+        s.close()
+    act = np.concatenate([active_mask(cls), [True]])
+    a, b = out["fp64"], out["mixed"]
+    d = np.abs(a - b)[act].max() / max(1.0, np.abs(a[act]).max())
+    say(f"  mixed vs fp64 rel diff {d:.2e}")
+    assert d < 1e-6
+
+
+def test_adjoint_full_size_against_gpu_finite_differences():
+    import torch
+    from paper_1911_00994_amd import gpmg
+    wk = wl.config_circle512_adjoint()
+    N, nsteps, K, tol, eps = wk.N, wk.steps, 8, 1e-11, 1e-5
+    say(f"[adjoint full size] N={N} steps={nsteps}")
+    h = 2.0 / N
+    mo = wk.motion.as_array()
+    coeffs = wl.adjoint_coeffs(seed=1)
+    fu0, fv0 = wl.streamfunction_forcing(N, coeffs)
+    s = gpmg.Solver(N, Re=wk.Re, stream=torch.cuda.current_stream().cuda_stream)
+    W = N + 2
+    z = np.zeros((W, W))
+
+    def run(fu, fv, off):
+        s.set_levelset_analytic(wk.shape.kind, wk.shape.params, 0.0, mo[:5])
+        s.set_state(z, z, z, 0.0)
+        s.tape_forward(wk.shape.kind, wk.shape.params, mo, 0.0, h, nsteps, fu, fv, ub_offset=off, tol=tol,
+                       max_cycles=400, picard_eps=1e-11, picard_max=60, checkpoint_every=K)
+        u, v, _, _ = s.get_x()
+        return u, v
+
+    u, v = run(fu0, fv0, [0.0, 0.0])
+    cls = s.classes()
+    mu, mv = cls[0] == 1, cls[1] == 1
+    J = lambda uu, vv: h * h * (float((uu[mu] ** 2).sum()) + float((vv[mv] ** 2).sum()))  # noqa: E731
+    g = s.tape_backward(2 * h * h * u * mu, 2 * h * h * v * mv, tol=tol, max_cycles=400)
+    fd = (J(*run(fu0, fv0, [eps, 0.0])) - J(*run(fu0, fv0, [-eps, 0.0]))) / (2 * eps)
+    say(f"  U offset x: fd {fd:.10e} adjoint {g['dU'][0]:.10e}")
+    assert abs(fd - g["dU"][0]) <= 1e-6 * abs(fd)
+    rng = np.random.default_rng(3)
+    eu, ev = rng.standard_normal(fu0.shape), rng.standard_normal(fv0.shape)
+    fd = (J(*run(fu0 + eps * eu, fv0 + eps * ev, [0.0, 0.0])) - J(*run(fu0 - eps * eu, fv0 - eps * ev, [0.0, 0.0]))) / (2 * eps)
+    ad = float((g["dfu"] * eu).sum() + (g["dfv"] * ev).sum())
+    say(f"  forcing direction: fd {fd:.10e} adjoint {ad:.10e}")
+    assert abs(fd - ad) <= 1e-6 * abs(fd)
