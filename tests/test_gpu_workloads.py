@@ -126,3 +126,64 @@ def test_adjoint_full_size_against_gpu_finite_differences():
     ad = float((g["dfu"] * eu).sum() + (g["dfv"] * ev).sum())
     say(f"  forcing direction: fd {fd:.10e} adjoint {ad:.10e}")
     assert abs(fd - ad) <= 1e-6 * abs(fd)
+
+
+def gpu_geom(s):
+    """boundary points / normals of every boundary row of the GPU geometry, as per-grid (W, W, 2) arrays (wall
+    Dirichlet points use the node itself), for the manufactured boundary data"""
+    N = s.N
+    W = N + 2
+    gr = s.ghost_rows()
+    cls = s.classes()
+    B = gr["B"].reshape(3, W, W, 2).copy()
+    nB = gr["nB"].reshape(3, W, W, 2).copy()
+    for g in range(3):
+        x, y = wl.node_coords(N, g)
+        m = cls[g] == O.C_WALLD
+        B[g][m, 0] = x[m]
+        B[g][m, 1] = y[m]
+    return dict(B=(B[0], B[1], B[2]), nB=(nB[0], nB[1], nB[2]))
+
+
+def test_translating_ellipse_second_order_on_gpu():
+    """The translating ellipse with the body-frame manufactured solution, run on the GPU alone to t = 0.25 with
+    dt = h at N = 64, 128, 256: the max velocity error at the internal points falls at second order."""
+    from paper_1911_00994_amd import gpmg
+    shape = wl.Shape(wl.ELLIPSE_SQRT, (0.4, 0.2, 0.0))
+    motion = wl.Motion(U=(0.5, 0.0))
+    m = wl.BodyFrameMMS((0.5, 0.0))
+    Re, T = 100.0, 0.25
+    mo = motion.as_array()
+    errs = []
+    for N in (64, 128, 256):
+        say(f"[ellipse order] N={N}")
+        dt = 2.0 / N
+        s = gpmg.Solver(N, Re=Re)
+        s.set_levelset_analytic(shape.kind, shape.params, 0.0, mo[:5])
+        u0, v0, p0 = wl.mms_fields(m, N, 0.0)
+        s.set_state(u0, v0, dt * p0, 0.0)
+        xu, yu = wl.node_coords(N, 0)
+        xv, yv = wl.node_coords(N, 1)
+        xp, yp = wl.node_coords(N, 2)
+        t = 0.0
+        for n in range(int(round(T / dt))):
+            t1 = t + dt
+            s.set_levelset_analytic(shape.kind, shape.params, t1, mo[:5])
+            bu, bv, bp = wl.boundary_values_from(m, gpu_geom(s), t1, t + 0.5 * dt, p_scale=dt)
+            s.set_boundary_values(bu, bv, bp)
+            fu, _ = m.forcing(xu, yu, t + 0.5 * dt, Re)
+            _, fv = m.forcing(xv, yv, t + 0.5 * dt, Re)
+            st, info = s.cn_step(dt, fu, fv, m.div(xp, yp, t1), tol=1e-10, max_cycles=200, picard_eps=1e-10,
+                                 picard_max=40)
+            assert st == 0, (N, n, info)
+            t = t1
+        u, v, _, _ = s.get_x()
+        cls = s.classes()
+        ue, ve = m.u(xu, yu, t), m.v(xv, yv, t)
+        e = max(np.abs(u - ue)[cls[0] == 1].max(), np.abs(v - ve)[cls[1] == 1].max())
+        say(f"  t = {t:.3f}: max velocity error {e:.3e}")
+        errs.append(e)
+        s.close()
+    r1, r2 = errs[0] / errs[1], errs[1] / errs[2]
+    say(f"  ratios {r1:.2f} {r2:.2f}")
+    assert r1 > 3.0 and r2 > 3.0
