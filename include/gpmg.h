@@ -66,10 +66,12 @@ enum { GP_INACTIVE = 0, GP_INTERNAL = 1, GP_GHOST = 2, GP_WALL_DIRICHLET = 3, GP
  * fictitious time steps 0.9 (Dirichlet) and 0.9 h (normal derivative) (Sect. 4.1.2), extension band of 4
  * grid steps, minimum ghost-row diagonal 0.1 (below it the ghost takes an extrapolation row), and after each
  * relaxation step bnd_sweeps = 1 extra box sweep (same colour order, each followed by lambda_ghost ghost
- * sweeps) over the cells within bnd_radius = 2 cells of a cell touching the body.  The last three fields
+ * sweeps) over the cells within bnd_radius = 2 cells of a cell touching the body.  The last four fields
  * choose how the same computation is laid out on the device (results agree to rounding): fuse_small_levels = 1
  * runs the cycle of the levels with N <= 32 in one workgroup with their data in LDS, band_split_min = 3000: a
  * boundary band with at least that many cells is relaxed with device-wide launches instead of one workgroup,
+ * band_sector_min = 1500: a band with at least that many cells is relaxed by angular sectors, one workgroup each
+ * (where the band lies far enough from its centre; otherwise as above),
  * graph_iterations = 0; 1 captures the launches of one solver iteration (cycle, mean projection, residual
  * norm) into a HIP graph at the start of each gp_solve / gp_cn_step solve and replays it every iteration
  * (gp_probe_start turns it off while its events are live). */
@@ -78,7 +80,7 @@ typedef struct {
   double dtau_dir, dtau_neu_over_h, bisect_eps_over_h, cg_min;
   int mixed_inner_cycles; /* FP32 cycles per FP64 refinement step in GP_MIXED solves */
   int bnd_sweeps, bnd_radius;
-  int fuse_small_levels, band_split_min, graph_iterations;
+  int fuse_small_levels, band_split_min, graph_iterations, band_sector_min;
 } gp_params;
 
 /* rigid motion: the body frame point of x at time t is R(-omega t) (x - X0 - U t); the boundary velocity at a

@@ -90,6 +90,7 @@ void gp_default_params(gp_params *p) {
   p->fuse_small_levels = 1;
   p->band_split_min = 3000;
   p->graph_iterations = 0;
+  p->band_sector_min = 1500;
 }
 
 const char *gp_strerror(gp_status st) {
@@ -115,6 +116,19 @@ void gp_destroy(gp_ctx *ctx) {
   for (int l = 0; l < ctx->L; l++) {
     Geo &G = ctx->geo[l];
     dfree(G.cls);
+    dfree(G.sec_pt);
+    dfree(G.sec_bfl);
+    dfree(G.sec_bcell);
+    dfree(G.sec_gk);
+    dfree(G.sec_own_loc);
+    dfree(G.sec_own_g);
+    dfree(G.sec_mask);
+    dfree(G.sec_lmap);
+    dfree(G.sec_bsl);
+    dfree(G.sec_gl);
+    dfree(G.sec_gw);
+    dfree(G.sec_gdt);
+    dfree(G.sec_out);
     dfree(G.g_pt);
     dfree(G.g_col);
     dfree(G.g_colr);
@@ -199,7 +213,7 @@ gp_status gp_setup_grid(gp_ctx **out, int N, double Re, const gp_params *prm, vo
     gp_default_params(&P);
   if (!pow2(N) || N < 16 || !pow2(P.coarsest_n) || P.coarsest_n < 4 || P.coarsest_n > N / 2 || P.nu1 < 0 || P.nu2 < 0 ||
       P.gamma < 1 || P.lambda_ghost < 0 || P.march_max < 1 || P.ext_radius < 1 || !(Re > 0) || P.mixed_inner_cycles < 1 ||
-      P.bnd_sweeps < 0 || P.bnd_radius < 0 || P.band_split_min < 1)
+      P.bnd_sweeps < 0 || P.bnd_radius < 0 || P.band_split_min < 1 || P.band_sector_min < 1)
     return GP_EINVAL;
   gp_ctx *ctx = new gp_ctx();
   ctx->N = N;
@@ -208,6 +222,7 @@ gp_status gp_setup_grid(gp_ctx **out, int N, double Re, const gp_params *prm, vo
   ctx->small_cycles = P.fuse_small_levels ? 1 : 0;
   ctx->band_split_min = P.band_split_min;
   ctx->graphs = P.graph_iterations ? 1 : 0;
+  ctx->band_sector_min = P.band_sector_min;
   ctx->stream = (hipStream_t)hip_stream;
   if (!ctx->stream) {  // graphs are captured from the context's stream, which cannot be the null stream
     if (hipStreamCreate(&ctx->stream) != hipSuccess) {
@@ -266,6 +281,26 @@ gp_status gp_setup_grid(gp_ctx **out, int N, double Re, const gp_params *prm, vo
     ALLOC(G.bg_dt, (size_t)G.gcap);
     ALLOC(G.wg_rows, (size_t)G.gcap);
     ALLOC(G.f_code, (size_t)G.fcap);
+    if (G.N >= 256) {  // band sectors (large bands only)
+      const size_t regcap = (size_t)G.gcap * 12 + (size_t)32 * G.N + 4096;
+      G.sec_rcap = (int)regcap;
+      G.sec_pcap = (int)(4 * regcap);
+      G.sec_bcap = 4 * G.bcap;
+      G.sec_gcap = 4 * G.gcap;
+      ALLOC(G.sec_pt, (size_t)G.sec_pcap);
+      ALLOC(G.sec_mask, regcap);
+      ALLOC(G.sec_lmap, 4 * regcap);
+      ALLOC(G.sec_out, regcap);
+      ALLOC(G.sec_own_loc, regcap);
+      ALLOC(G.sec_own_g, regcap);
+      ALLOC(G.sec_bsl, (size_t)21 * G.sec_bcap);
+      ALLOC(G.sec_bfl, (size_t)G.sec_bcap);
+      ALLOC(G.sec_bcell, (size_t)G.sec_bcap);
+      ALLOC(G.sec_gl, (size_t)10 * G.sec_gcap);
+      ALLOC(G.sec_gw, (size_t)9 * G.sec_gcap);
+      ALLOC(G.sec_gdt, (size_t)G.sec_gcap);
+      ALLOC(G.sec_gk, (size_t)G.sec_gcap);
+    }
     ALLOC(G.f_loc, (size_t)G.fcap);
     ALLOC(ctx->v64[l].x, (size_t)G.n);
     ALLOC(ctx->v64[l].b, (size_t)G.n);

@@ -869,6 +869,316 @@ static gp_status read_flags(Ctx *ctx, int *h) {
   return GP_OK;
 }
 
+// ---------------------------------------------------------------------------------------------------------
+// angular sectors of a large boundary band (one workgroup each in the band relaxation).  Angles are taken about
+// the mean of the band cells' centres.  A relaxation step's band work reaches R cells from a written point (the
+// reach of each ghost sweep and each band colour, summed); two points within Euclidean distance d, both at least
+// r_min from the centre, differ in angle by at most 2 asin(d / (2 r_min)), so with Delta that bound for
+// d = R sqrt(2) h, a sector whose workgroup computes every band box and ghost row within Delta of its angles
+// (redundantly with its neighbours) gets its own points exactly as the whole band would.
+// ---------------------------------------------------------------------------------------------------------
+__device__ __forceinline__ void sec_xy(int k, int W, double h, double &x, double &y) {
+  const int q = k % (W * W), j = q / W - 1, i = q % W - 1;
+  x = -1.0 + (i + 0.5) * h;
+  y = -1.0 + (j + 0.5) * h;
+}
+__device__ __forceinline__ int sec_cheb(int a, int b, int W) {
+  const int WW = W * W, qa = a % WW, qb = b % WW;
+  return max(abs(qa / W - qb / W), abs(qa % W - qb % W));
+}
+struct SecGeo {
+  double cx, cy, delta, w;
+  int S;
+};
+__device__ __forceinline__ int sec_of(double x, double y, const SecGeo &sg) {
+  const double th = atan2(y - sg.cy, x - sg.cx) + M_PI;
+  int s = (int)floor(th / sg.w);
+  return ((s % sg.S) + sg.S) % sg.S;
+}
+// bit mask of the sectors within delta of angle at (x, y)
+__device__ __forceinline__ unsigned sec_bits(double x, double y, const SecGeo &sg) {
+  const double th = atan2(y - sg.cy, x - sg.cx) + M_PI;
+  const int lo = (int)floor((th - sg.delta) / sg.w), hi = (int)floor((th + sg.delta) / sg.w);
+  unsigned m = 0;
+  for (int k = lo; k <= hi; k++) m |= 1u << (((k % sg.S) + sg.S) % sg.S);
+  return m;
+}
+// sums of the band cells' centres (acc[0], acc[1]); reach of the body ghost rows in cells (reach)
+__global__ void k_sec_centre(const int *band, int nband, int N, double h, const int *bg_k, const int *bg_loc, int nbg,
+                             int gcap, const int *reg_pt, int W, double *acc, int *reach) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < nband) {
+    const int cell = band[t];
+    atomicAdd(&acc[0], -1.0 + (cell % N + 0.5) * h);
+    atomicAdd(&acc[1], -1.0 + (cell / N + 0.5) * h);
+  } else if (t < nband + nbg) {
+    const int s2 = t - nband, k = bg_k[s2];
+    int m = 0;
+    for (int z = 1; z < 10; z++) m = max(m, sec_cheb(k, reg_pt[bg_loc[z * gcap + s2]], W));
+    atomicMax(reach, m);
+  }
+}
+// smallest distance from the centre over the region points (as the bits of a non-negative double)
+__global__ void k_sec_rmin(const int *reg_pt, int nreg, int W, double h, double cx, double cy, unsigned long long *out) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= nreg) return;
+  double x, y;
+  sec_xy(reg_pt[g], W, h, x, y);
+  atomicMin(out, (unsigned long long)__double_as_longlong(sqrt((x - cx) * (x - cx) + (y - cy) * (y - cy))));
+}
+__device__ __forceinline__ int band_colour_of(int q, const int *off) {
+  int c = 0;
+  while (c < 4 && q >= off[c + 1]) c++;
+  return c;
+}
+struct SecOff {
+  int p[SEC_MAX + 1], b[5 * SEC_MAX + 1], g[SEC_MAX + 1], o[SEC_MAX + 1];
+};
+// Counters per sector are aggregated per workgroup in LDS (one global atomic per sector and workgroup); the
+// fills reserve a range per workgroup and sector the same way (the order within a sector is free: nothing
+// depends on it but LDS slot numbers).
+constexpr int SEC_CNT = 6 * SEC_MAX;  // 5 per sector for boxes by colour, 1 for rows
+// memberships of the band boxes and body ghost rows, marked on the region points they name; counts per sector
+__global__ void __launch_bounds__(TPB) k_sec_mark(const int *band, int nband, const int *boff, const int *bbox, int bcap,
+                                                  int N, double h, const int *bg_k, const int *bg_loc, int nbg, int gcap,
+                                                  int W, SecGeo sg, int *smask, int *cnt_b, int *cnt_g) {
+  __shared__ int lc[SEC_CNT];
+  for (int q = threadIdx.x; q < SEC_CNT; q += TPB) lc[q] = 0;
+  __syncthreads();
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < nband) {
+    const int cell = band[t];
+    const unsigned m = sec_bits(-1.0 + (cell % N + 0.5) * h, -1.0 + (cell / N + 0.5) * h, sg);
+    const int c = band_colour_of(t, boff);
+    for (int s = 0; s < sg.S; s++)
+      if (m >> s & 1u) atomicAdd(&lc[5 * s + c], 1);
+    for (int z = 0; z < 21; z++) atomicOr(&smask[bbox[z * bcap + t]], (int)m);
+  } else if (t < nband + nbg) {
+    const int s2 = t - nband;
+    double x, y;
+    sec_xy(bg_k[s2], W, h, x, y);
+    const unsigned m = sec_bits(x, y, sg);
+    for (int s = 0; s < sg.S; s++)
+      if (m >> s & 1u) atomicAdd(&lc[5 * SEC_MAX + s], 1);
+    for (int z = 0; z < 10; z++) atomicOr(&smask[bg_loc[z * gcap + s2]], (int)m);
+  }
+  __syncthreads();
+  for (int q = threadIdx.x; q < 5 * sg.S; q += TPB)
+    if (lc[q]) atomicAdd(&cnt_b[q], lc[q]);
+  for (int q = threadIdx.x; q < sg.S; q += TPB)
+    if (lc[5 * SEC_MAX + q]) atomicAdd(&cnt_g[q], lc[5 * SEC_MAX + q]);
+}
+// points per sector, owned written points per sector (the sector of the point's own angle); bad: a point in more
+// than four sectors, or a written point outside the region of its owner
+__global__ void __launch_bounds__(TPB) k_sec_count(const int *smask, int nreg, int nregw, const int *reg_pt, int W,
+                                                   double h, SecGeo sg, int *cnt_p, int *cnt_o, int *bad) {
+  __shared__ int lp[SEC_MAX], lo[SEC_MAX];
+  if (threadIdx.x < SEC_MAX) lp[threadIdx.x] = lo[threadIdx.x] = 0;
+  __syncthreads();
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g < nreg) {
+    const unsigned m = (unsigned)smask[g];
+    if (__popc(m) > 4) atomicOr(bad, 1);
+    for (int s = 0; s < sg.S; s++)
+      if (m >> s & 1u) atomicAdd(&lp[s], 1);
+    if (g < nregw) {
+      double x, y;
+      sec_xy(reg_pt[g], W, h, x, y);
+      const int o = sec_of(x, y, sg);
+      if (!(m >> o & 1u)) atomicOr(bad, 2);
+      atomicAdd(&lo[o], 1);
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < sg.S) {
+    if (lp[threadIdx.x]) atomicAdd(&cnt_p[threadIdx.x], lp[threadIdx.x]);
+    if (lo[threadIdx.x]) atomicAdd(&cnt_o[threadIdx.x], lo[threadIdx.x]);
+  }
+}
+__global__ void __launch_bounds__(TPB) k_sec_fill_pts(const int *smask, int nreg, int nregw, const int *reg_pt, int W,
+                                                      double h, SecGeo sg, SecOff off, int *cur_p, int *cur_o,
+                                                      int *sec_pt, int *lmap, int *own_loc, int *own_g) {
+  __shared__ int lc[2 * SEC_MAX], base[2 * SEC_MAX];
+  for (int q = threadIdx.x; q < 2 * SEC_MAX; q += TPB) lc[q] = 0;
+  __syncthreads();
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  unsigned m = 0;
+  int o = -1;
+  if (g < nreg) {
+    m = (unsigned)smask[g];
+    for (int s = 0; s < sg.S; s++)
+      if (m >> s & 1u) atomicAdd(&lc[s], 1);
+    if (g < nregw) {
+      double x, y;
+      sec_xy(reg_pt[g], W, h, x, y);
+      o = sec_of(x, y, sg);
+      atomicAdd(&lc[SEC_MAX + o], 1);
+    }
+  }
+  // one reservation per counter: points (cur_p) then owned (cur_o)
+  __syncthreads();
+  for (int q = threadIdx.x; q < 2 * SEC_MAX; q += TPB) {
+    base[q] = (q % SEC_MAX < sg.S && lc[q]) ? atomicAdd(q < SEC_MAX ? &cur_p[q] : &cur_o[q - SEC_MAX], lc[q]) : 0;
+    lc[q] = 0;
+  }
+  __syncthreads();
+  if (g < nreg) {
+    int r = 0;
+    for (int s = 0; s < sg.S; s++)
+      if (m >> s & 1u) {
+        const int k = base[s] + atomicAdd(&lc[s], 1);
+        sec_pt[off.p[s] + k] = reg_pt[g];
+        lmap[4 * g + r++] = k;
+      }
+    if (o >= 0) {
+      const int k = base[SEC_MAX + o] + atomicAdd(&lc[SEC_MAX + o], 1);
+      own_loc[off.o[o] + k] = lmap[4 * g + __popc(m & ((1u << o) - 1u))];
+      own_g[off.o[o] + k] = g;
+    }
+  }
+}
+__device__ __forceinline__ int sec_local(const int *smask, const int *lmap, int g, int s) {
+  return lmap[4 * g + __popc((unsigned)smask[g] & ((1u << s) - 1u))];
+}
+__global__ void __launch_bounds__(TPB) k_sec_fill_tabs(const int *band, int nband, const int *boff, const int *bbox,
+                                                       int bcap, int N, double h, const int *bg_k, const int *bg_loc,
+                                                       const double *bg_w, const double *bg_dt, int nbg, int gcap, int W,
+                                                       SecGeo sg, SecOff off, const int *smask, const int *lmap,
+                                                       int *cur_b, int *cur_g, uint16_t *bsl, int *bfl, int *bcell,
+                                                       int bstride, uint16_t *gl, double *gw, double *gdt, int *gk,
+                                                       int gstride) {
+  __shared__ int lc[SEC_CNT], base[SEC_CNT];
+  for (int q = threadIdx.x; q < SEC_CNT; q += TPB) lc[q] = 0;
+  __syncthreads();
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  unsigned m = 0;
+  int c = 0, s2 = -1;
+  double x = 0, y = 0;
+  if (t < nband) {
+    const int cell = band[t];
+    x = -1.0 + (cell % N + 0.5) * h;
+    y = -1.0 + (cell / N + 0.5) * h;
+    m = sec_bits(x, y, sg);
+    c = band_colour_of(t, boff);
+    for (int s = 0; s < sg.S; s++)
+      if (m >> s & 1u) atomicAdd(&lc[5 * s + c], 1);
+  } else if (t < nband + nbg) {
+    s2 = t - nband;
+    sec_xy(bg_k[s2], W, h, x, y);
+    m = sec_bits(x, y, sg);
+    for (int s = 0; s < sg.S; s++)
+      if (m >> s & 1u) atomicAdd(&lc[5 * SEC_MAX + s], 1);
+  }
+  __syncthreads();
+  for (int q = threadIdx.x; q < SEC_CNT; q += TPB) {
+    const bool box = q < 5 * SEC_MAX;
+    const bool live = box ? q < 5 * sg.S : q - 5 * SEC_MAX < sg.S;
+    base[q] = (live && lc[q]) ? atomicAdd(box ? &cur_b[q] : &cur_g[q - 5 * SEC_MAX], lc[q]) : 0;
+    lc[q] = 0;
+  }
+  __syncthreads();
+  if (t < nband) {
+    for (int s = 0; s < sg.S; s++)
+      if (m >> s & 1u) {
+        const int idx = off.b[5 * s + c] + base[5 * s + c] + atomicAdd(&lc[5 * s + c], 1);
+        for (int z = 0; z < 21; z++) bsl[z * bstride + idx] = (uint16_t)sec_local(smask, lmap, bbox[z * bcap + t], s);
+        bfl[idx] = bbox[21 * bcap + t];
+        bcell[idx] = band[t];
+      }
+  } else if (s2 >= 0) {
+    for (int s = 0; s < sg.S; s++)
+      if (m >> s & 1u) {
+        const int idx = off.g[s] + base[5 * SEC_MAX + s] + atomicAdd(&lc[5 * SEC_MAX + s], 1);
+        for (int z = 0; z < 10; z++) gl[z * gstride + idx] = (uint16_t)sec_local(smask, lmap, bg_loc[z * gcap + s2], s);
+        for (int z = 0; z < 9; z++) gw[z * gstride + idx] = bg_w[z * gcap + s2];
+        gdt[idx] = bg_dt[s2];
+        gk[idx] = bg_k[s2];
+      }
+  }
+}
+
+// the sectors of level l, or sec_S = 0 where they do not apply (too close to the centre, a point in more than four
+// sectors, a table over its capacity, a sector too large for LDS)
+gp_status sector_build(Ctx *ctx, int l) {
+  Geo &G = ctx->geo[l];
+  hipStream_t s = ctx->stream;
+  const int W = G.W, nt = G.nband + G.nbg;
+  G.sec_S = 0;
+  double *acc = ctx->d_red;  // [0], [1] centre sums, [2] r_min bits
+  int *ic = ctx->d_bcnt;     // int counters
+  GP_HIP(hipMemsetAsync(acc, 0, 2 * sizeof(double), s));
+  GP_HIP(hipMemsetAsync(ic, 0, 4 * sizeof(int), s));
+  k_sec_centre<<<nblk(nt), TPB, 0, s>>>(G.band, G.nband, G.N, G.h, G.bg_k, G.bg_loc, G.nbg, G.gcap, G.reg_pt, W, acc, ic);
+  GP_HIP(hipGetLastError());
+  double hacc[2];
+  int reach = 0;
+  GP_HIP(hipMemcpyAsync(hacc, acc, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+  GP_HIP(hipMemcpyAsync(&reach, ic, sizeof(int), hipMemcpyDeviceToHost, s));
+  GP_HIP(hipStreamSynchronize(s));
+  SecGeo sg;
+  sg.cx = hacc[0] / G.nband;
+  sg.cy = hacc[1] / G.nband;
+  const unsigned long long big = 0x7ff0000000000000ull;  // +inf
+  GP_HIP(hipMemcpyAsync(acc + 2, &big, sizeof(big), hipMemcpyHostToDevice, s));
+  k_sec_rmin<<<nblk(G.nreg), TPB, 0, s>>>(G.reg_pt, G.nreg, W, G.h, sg.cx, sg.cy, (unsigned long long *)(acc + 2));
+  GP_HIP(hipGetLastError());
+  double rmin = 0;
+  GP_HIP(hipMemcpyAsync(&rmin, acc + 2, sizeof(double), hipMemcpyDeviceToHost, s));
+  GP_HIP(hipStreamSynchronize(s));
+  // reach of one relaxation step's band work in cells: each ghost sweep the ghost rows' reach (+1 for the
+  // staggering), each band colour 3 (a box reads 2 cells away, +1), and 2 more for the written points themselves
+  const int lam = ctx->prm.lambda_ghost, nsw = ctx->prm.bnd_sweeps;
+  const double R = (lam * (reach + 1) + nsw * (5 * 3 + lam * (reach + 1)) + 2) * std::sqrt(2.0) * G.h;
+  if (!(rmin > 0) || R >= 2.0 * rmin) return GP_OK;
+  sg.delta = 2.0 * std::asin(R / (2.0 * rmin));
+  sg.S = 8;
+  sg.w = 2.0 * M_PI / sg.S;
+  if (2.0 * sg.delta > 2.5 * sg.w) return GP_OK;  // more than four sectors per point
+  const int S = sg.S;
+  int *cnt_b = ic, *cnt_g = ic + 5 * S, *cnt_p = ic + 6 * S, *cnt_o = ic + 7 * S, *bad = ic + 8 * S;
+  int *cur = ic + 8 * S + 1;  // 8 S cursors
+  GP_HIP(hipMemsetAsync(ic, 0, (16 * S + 1) * sizeof(int), s));
+  GP_HIP(hipMemsetAsync(G.sec_mask, 0, (size_t)G.nreg * sizeof(int), s));
+  k_sec_mark<<<nblk(nt), TPB, 0, s>>>(G.band, G.nband, G.d_band_off, G.bbox, G.bcap, G.N, G.h, G.bg_k, G.bg_loc, G.nbg,
+                                      G.gcap, W, sg, G.sec_mask, cnt_b, cnt_g);
+  k_sec_count<<<nblk(G.nreg), TPB, 0, s>>>(G.sec_mask, G.nreg, G.nregw, G.reg_pt, W, G.h, sg, cnt_p, cnt_o, bad);
+  GP_HIP(hipGetLastError());
+  std::vector<int> hc(8 * S + 1);
+  GP_HIP(hipMemcpyAsync(hc.data(), ic, hc.size() * sizeof(int), hipMemcpyDeviceToHost, s));
+  GP_HIP(hipStreamSynchronize(s));
+  if (hc[8 * S]) return GP_OK;
+  SecOff off{};
+  int maxreg = 0, maxrow = 0;
+  for (int q = 0; q < S; q++) {
+    off.p[q + 1] = off.p[q] + hc[6 * S + q];
+    off.g[q + 1] = off.g[q] + hc[5 * S + q];
+    off.o[q + 1] = off.o[q] + hc[7 * S + q];
+    maxreg = std::max(maxreg, hc[6 * S + q]);
+    maxrow = std::max(maxrow, hc[5 * S + q]);
+  }
+  for (int q = 0; q < 5 * S; q++) off.b[q + 1] = off.b[q] + hc[q];
+  if (off.p[S] > G.sec_pcap || off.b[5 * S] > G.sec_bcap || off.g[S] > G.sec_gcap || off.o[S] != G.nregw ||
+      maxreg >= 65536 || (size_t)maxreg * sizeof(double) + 2 * (size_t)maxrow * sizeof(double) + 2048 > ctx->max_lds)
+    return GP_OK;
+  k_sec_fill_pts<<<nblk(G.nreg), TPB, 0, s>>>(G.sec_mask, G.nreg, G.nregw, G.reg_pt, W, G.h, sg, off, cur, cur + S,
+                                              G.sec_pt, G.sec_lmap, G.sec_own_loc, G.sec_own_g);
+  k_sec_fill_tabs<<<nblk(nt), TPB, 0, s>>>(G.band, G.nband, G.d_band_off, G.bbox, G.bcap, G.N, G.h, G.bg_k, G.bg_loc,
+                                           G.bg_w, G.bg_dt, G.nbg, G.gcap, W, sg, off, G.sec_mask, G.sec_lmap,
+                                           cur + 2 * S, cur + 7 * S, G.sec_bsl, G.sec_bfl, G.sec_bcell, G.sec_bcap,
+                                           G.sec_gl, G.sec_gw, G.sec_gdt, G.sec_gk, G.sec_gcap);
+  GP_HIP(hipGetLastError());
+  for (int q = 0; q <= S; q++) {
+    G.sec_poff[q] = off.p[q];
+    G.sec_goff[q] = off.g[q];
+    G.sec_ooff[q] = off.o[q];
+  }
+  for (int q = 0; q <= 5 * S; q++) G.sec_boff[q] = off.b[q];
+  G.sec_maxreg = maxreg;
+  G.sec_maxrow = maxrow;
+  G.sec_S = S;
+  return GP_OK;
+}
+
 static gp_status build_level(Ctx *ctx, int l) {
   Geo &G = ctx->geo[l];
   Lat L = make_lat(ctx, l);
@@ -952,8 +1262,10 @@ static gp_status build_level(Ctx *ctx, int l) {
     // the read-only points are staged too when they fit (FP64 values, and the body ghost rows' new values and
     // right-hand sides in LDS); otherwise their map entries stay negative and the kernel reads them from global
     // memory
+    const bool want_sec = G.sec_pcap > 0 && G.nband >= ctx->band_sector_min;  // sectors need every point staged
     const bool rd = G.nregw + nr <= regcap &&
-                    (size_t)(G.nregw + nr) * sizeof(double) + 2 * (size_t)G.ng * sizeof(double) + 2048 <= ctx->max_lds;
+                    (want_sec || (size_t)(G.nregw + nr) * sizeof(double) + 2 * (size_t)G.ng * sizeof(double) + 2048 <=
+                                     ctx->max_lds);
     G.nreg = rd ? G.nregw + nr : G.nregw;
     if (G.nreg <= regcap) {
       GP_HIP(hipMemsetAsync(ctx->d_flags + 10, 0, 2 * sizeof(int), s));
@@ -982,6 +1294,11 @@ static gp_status build_level(Ctx *ctx, int l) {
       G.nwg = hr[0];
       G.lds_ok = hr[1] == 0 ? 1 : 0;
     }
+  }
+  G.sec_S = 0;
+  if (G.lds_ok && G.sec_pcap > 0 && G.nband >= ctx->band_sector_min && G.nreg > G.nregw && G.nbg > 0) {
+    gp_status sst = sector_build(ctx, l);
+    if (sst) return sst;
   }
   // ghost columns by row (the double-buffered ghost sweeps of the device-wide band path)
   if (G.ng) {

@@ -22,6 +22,7 @@ enum : uint8_t {
   K_GHOSTX = 7
 };
 
+constexpr int SEC_MAX = 16;  // angular sectors of a band, at most
 constexpr int MAXLEV = 16;
 constexpr int TPB = 256;
 
@@ -60,6 +61,21 @@ struct Geo {
   int bcap = 0;
   int nreg = 0, nregw = 0, nbg = 0, nwg = 0;  // region points (the first nregw are written), body and wall rows
   int lds_ok = 0;                   // 1 when the LDS band kernel applies to this level
+  // angular sectors of the band, one workgroup each (see sector_build): per sector s its region points
+  // (sec_pt, global index; local slot = position), band boxes by colour (sec_bsl 21 local slots as 16-bit numbers,
+  // field-major; sec_bfl flags; sec_bcell cell), body ghost rows (sec_gl own + 9 column local slots, 16-bit; sec_gw
+  // 9 weights; sec_gdt; sec_gk the point, for its right-hand side) and owned written points (sec_own_loc local
+  // slot, sec_own_g region index, whose value goes to sec_out[region index]); all field-major with the totals
+  // as strides
+  int sec_S = 0;
+  int sec_poff[SEC_MAX + 1] = {0}, sec_boff[5 * SEC_MAX + 1] = {0}, sec_goff[SEC_MAX + 1] = {0},
+      sec_ooff[SEC_MAX + 1] = {0};
+  int sec_maxreg = 0, sec_maxrow = 0;  // largest region and row count of a sector
+  int *sec_pt = nullptr, *sec_bfl = nullptr, *sec_bcell = nullptr, *sec_gk = nullptr, *sec_own_loc = nullptr,
+      *sec_own_g = nullptr, *sec_mask = nullptr, *sec_lmap = nullptr;
+  uint16_t *sec_bsl = nullptr, *sec_gl = nullptr;
+  double *sec_gw = nullptr, *sec_gdt = nullptr, *sec_out = nullptr;
+  int sec_pcap = 0, sec_bcap = 0, sec_gcap = 0, sec_rcap = 0;
   int colr_ok = 0;                  // 1 when g_colr holds the row of every ghost column
   // faces on the boundary of the internal pressure cells, cell-major order: code = 2 * (u or v index) + (1 if the
   // face enters the cell's divergence with a minus sign); f_loc = the same face as an LDS band-region entry
@@ -145,6 +161,7 @@ struct Ctx {
   size_t max_lds = 65536;           // dynamic LDS a workgroup may use on this device
   int small_cycles = 1;             // run the levels with N <= 32 as one workgroup when they fit in LDS
   int band_split_min = 3000;        // bands with at least this many cells use device-wide launches
+  int band_sector_min = 1500;       // bands with at least this many cells use angular sectors where possible
   int box_tiles = 1;                // all five colours of a box sweep in one launch (LDS tiles with halos)
   // launch probe: HIP event pairs around the finest-level five-colour box launches of the FP64 cycle
   std::vector<hipEvent_t> probe_ev;
@@ -171,6 +188,7 @@ gp_status geometry_build(Ctx *ctx);
 gp_status levelset_analytic(Ctx *ctx, const gp_shape *shape, double t, const gp_rigid *mo);
 gp_status default_boundary_values(Ctx *ctx);
 gp_status coarse_factor(Ctx *ctx);
+gp_status sector_build(Ctx *ctx, int l);
 
 // multigrid (mg.hip)
 gp_status mg_cycle64(Ctx *ctx, double *res_inf);

@@ -657,6 +657,122 @@ __global__ void __launch_bounds__(BAND_T) k_xi_faces(int WW, double h, T *x, con
   if (threadIdx.x == 0) x[3 * WW] = (T)((fs / h - *gsum) / *mp);
 }
 
+// One relaxation step's band work over angular sectors (built by sector_build), one workgroup per sector: the
+// sector's region is staged in LDS, its ghost rows and band boxes (those within reach of its own points, some
+// also computed by the neighbouring sectors) are relaxed as in k_band_lds, and the values of the written points
+// it owns go to out (by region index); workgroups S and on take the wall ghost rows.  k_band_sec_fin then moves
+// out into x and updates xi.  Nothing reads x while this kernel writes it: the sectors write out only.
+struct SecTabs {
+  int poff[SEC_MAX + 1], boff[5 * SEC_MAX + 1], goff[SEC_MAX + 1], ooff[SEC_MAX + 1];
+};
+template <typename T>
+__global__ void __launch_bounds__(BAND_T) k_band_sec(int N, int W, BoxK K, const T *x, T *xw,
+                                                     const T *__restrict__ b, int S, SecTabs tb,
+                                                     const int *__restrict__ spt, const uint16_t *__restrict__ bsl,
+                                                     const int *__restrict__ bfl, const int *__restrict__ bcell,
+                                                     int bstride, const uint16_t *__restrict__ gl,
+                                                     const double *__restrict__ gw, const double *__restrict__ gdt,
+                                                     const int *__restrict__ gk, int gstride,
+                                                     const int *__restrict__ own_loc, const int *__restrict__ own_g,
+                                                     double *__restrict__ out, const int *__restrict__ g_pt,
+                                                     const int *__restrict__ g_col, const double *__restrict__ g_w,
+                                                     const double *__restrict__ g_dtau, const int *__restrict__ wg_rows,
+                                                     int nwg, int sweeps, int lambda) {
+  extern __shared__ unsigned char lds_raw[];
+  const int tid = threadIdx.x, sec = blockIdx.x;
+  if (sec >= S) {
+    for (int q = (sec - S) * BAND_T + tid; q < nwg; q += (gridDim.x - S) * BAND_T)
+      wall_ghost_row<T>(wg_rows[q], g_pt, g_col, g_w, g_dtau, xw, b, lambda * (1 + sweeps));
+    return;
+  }
+  const int p0 = tb.poff[sec], np = tb.poff[sec + 1] - p0, g0 = tb.goff[sec], ng = tb.goff[sec + 1] - g0;
+  const int WW = W * W;
+  T *xs = reinterpret_cast<T *>(lds_raw);
+  double *nv = reinterpret_cast<double *>(lds_raw + ((np * sizeof(T) + 7) & ~(size_t)7));
+  double *gb = nv + ng;
+  for (int q0 = tid; q0 < np; q0 += BATCH * BAND_T) {
+    int gi[BATCH];
+    T vv[BATCH];
+#pragma unroll
+    for (int u = 0; u < BATCH; u++) gi[u] = q0 + u * BAND_T < np ? spt[p0 + q0 + u * BAND_T] : 0;
+#pragma unroll
+    for (int u = 0; u < BATCH; u++) vv[u] = x[gi[u]];
+#pragma unroll
+    for (int u = 0; u < BATCH; u++)
+      if (q0 + u * BAND_T < np) xs[q0 + u * BAND_T] = vv[u];
+  }
+  for (int k = tid; k < ng; k += BAND_T) gb[k] = (double)b[gk[g0 + k]];
+  const double xi = (double)x[3 * WW];
+  __syncthreads();
+  auto ghost_block = [&]() {
+    for (int it = 0; it < lambda; it++) {
+      for (int k = tid; k < ng; k += BAND_T) {
+        const int idx = g0 + k;
+        double sum = 0;
+#pragma unroll
+        for (int z = 0; z < 9; z++) sum += gw[z * gstride + idx] * (double)xs[gl[(1 + z) * gstride + idx]];
+        nv[k] = (double)xs[gl[idx]] + gdt[idx] * (gb[k] - sum);
+      }
+      __syncthreads();
+      for (int k = tid; k < ng; k += BAND_T) xs[gl[g0 + k]] = (T)nv[k];
+      __syncthreads();
+    }
+  };
+  ghost_block();
+  for (int sw = 0; sw < sweeps; sw++) {
+    for (int c = 0; c < 5; c++) {
+      for (int q = tb.boff[5 * sec + c] + tid; q < tb.boff[5 * sec + c + 1]; q += BAND_T) {
+        auto TB = [&](int fld) { return (int)bsl[fld * bstride + q]; };
+        const int cell = bcell[q], i = cell % N, j = cell / N, cg = (j + 1) * W + (i + 1);
+        const int f = bfl[q];
+        const bool fW = f & 1, fE = f & 2, fS = f & 4, fN = f & 8, fP = f & 16;
+        const double bW_ = b[cg], bE_ = b[cg + 1], bS_ = b[WW + cg], bN_ = b[WW + cg + W], bP_ = b[2 * WW + cg];
+        double uW = xs[TB(0)], uE = xs[TB(1)], uWW = xs[TB(2)], uEE = xs[TB(3)], uWS = xs[TB(4)], uWN = xs[TB(5)],
+               uES = xs[TB(6)], uEN = xs[TB(7)];
+        double vS = xs[TB(8)], vN = xs[TB(9)], vSS = xs[TB(10)], vNN = xs[TB(11)], vSW = xs[TB(12)],
+               vSE = xs[TB(13)], vNW = xs[TB(14)], vNE = xs[TB(15)];
+        double pc = xs[TB(16)], pW = xs[TB(17)], pE = xs[TB(18)], pS = xs[TB(19)], pN = xs[TB(20)];
+        const BoxNew o = box_core(K, fW, fE, fS, fN, fP, uW, uE, uWW, uEE, uWS, uWN, uES, uEN, vS, vN, vSS, vNN, vSW, vSE,
+                                  vNW, vNE, pc, pW, pE, pS, pN, bW_, bE_, bS_, bN_, bP_, xi);
+        if (!o.skip) {
+          if (fP) xs[TB(16)] = (T)o.p;
+          if (fW) xs[TB(0)] = (T)o.uW;
+          if (fE) xs[TB(1)] = (T)o.uE;
+          if (fS) xs[TB(8)] = (T)o.vS;
+          if (fN) xs[TB(9)] = (T)o.vN;
+        }
+      }
+      __syncthreads();
+    }
+    ghost_block();
+  }
+  for (int k = tb.ooff[sec] + tid; k < tb.ooff[sec + 1]; k += BAND_T) out[own_g[k]] = (double)xs[own_loc[k]];
+}
+// the written points from out into x (region index -> point; workgroups 1 and on), and xi from the boundary
+// faces of the internal cells as in k_xi_faces (workgroup 0; a written face takes its value from out, as the
+// others write it into x)
+template <typename T>
+__global__ void __launch_bounds__(BAND_T) k_band_sec_fin(const int *__restrict__ reg_pt, int nregw,
+                                                         const double *__restrict__ out, T *x, int WW, double h,
+                                                         const int *__restrict__ f_code, const int *__restrict__ f_loc,
+                                                         int nf, const double *__restrict__ gsum,
+                                                         const int *__restrict__ mp) {
+  if (blockIdx.x > 0) {
+    for (int g = (blockIdx.x - 1) * BAND_T + threadIdx.x; g < nregw; g += (gridDim.x - 1) * BAND_T)
+      x[reg_pt[g]] = (T)out[g];
+    return;
+  }
+  double fs = 0;
+  for (int q = threadIdx.x; q < nf; q += BAND_T) {
+    const int e = f_loc[q];
+    const double v = (e >= 0 && e < nregw) ? (double)(T)out[e] : (double)x[f_code[q] >> 1];
+    fs += (f_code[q] & 1) ? -v : v;
+  }
+  fs = band_block_sum(fs);
+  if (threadIdx.x == 0) x[3 * WW] = (T)((fs / h - *gsum) / *mp);
+}
+
+
 
 // ---------------------------------------------------------------------------------------------------------
 // deterministic grid reductions: fixed grid, fixed per-thread ranges, tree in LDS, the last block sums the
@@ -1401,6 +1517,27 @@ static void relax(Ctx *ctx, int l) {
   }
   const bool band = ctx->prm.bnd_sweeps > 0 && G.nband > 0;
   const size_t lds_bytes = (size_t)G.nreg * sizeof(T);
+  if (band && G.sec_S > 0 &&
+      (size_t)G.sec_maxreg * sizeof(T) + 2 * (size_t)G.sec_maxrow * sizeof(double) + 1024 <= ctx->max_lds) {
+    // a large band over angular sectors, one workgroup each, plus the wall rows; then write-back and xi
+    SecTabs tb;
+    for (int q = 0; q <= G.sec_S; q++) {
+      tb.poff[q] = G.sec_poff[q];
+      tb.goff[q] = G.sec_goff[q];
+      tb.ooff[q] = G.sec_ooff[q];
+    }
+    for (int q = 0; q <= 5 * G.sec_S; q++) tb.boff[q] = G.sec_boff[q];
+    const size_t lds = ((G.sec_maxreg * sizeof(T) + 7) & ~(size_t)7) + 2 * (size_t)G.sec_maxrow * sizeof(double);
+    const int nwb = (G.nwg + BAND_T - 1) / BAND_T;
+    k_band_sec<T><<<G.sec_S + nwb, BAND_T, lds, s>>>(
+        G.N, G.W, BK, V.x, V.x, V.b, G.sec_S, tb, G.sec_pt, G.sec_bsl, G.sec_bfl, G.sec_bcell, G.sec_bcap, G.sec_gl,
+        G.sec_gw, G.sec_gdt, G.sec_gk, G.sec_gcap, G.sec_own_loc, G.sec_own_g, G.sec_out, G.g_pt, G.g_col, G.g_w,
+        G.g_dtau, G.wg_rows, G.nwg, ctx->prm.bnd_sweeps, ctx->prm.lambda_ghost);
+    const int nfb = 1 + std::min(64, (G.nregw + BAND_T - 1) / BAND_T);
+    k_band_sec_fin<T><<<nfb, BAND_T, 0, s>>>(G.reg_pt, G.nregw, G.sec_out, V.x, G.WW, G.h, G.f_code, G.f_loc, G.nf,
+                                             ctx->d_lev + l, G.d_mp);
+    return;
+  }
   if (band && G.nband >= ctx->band_split_min) {
     // a large band: ghost sweeps and band colours as device-wide launches
     auto sweeps = [&]() {

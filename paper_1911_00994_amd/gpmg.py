@@ -35,7 +35,7 @@ class GpParams(ctypes.Structure):
                 ("bisect_eps_over_h", ctypes.c_double), ("cg_min", ctypes.c_double),
                 ("mixed_inner_cycles", ctypes.c_int), ("bnd_sweeps", ctypes.c_int), ("bnd_radius", ctypes.c_int),
                 ("fuse_small_levels", ctypes.c_int), ("band_split_min", ctypes.c_int),
-                ("graph_iterations", ctypes.c_int)]
+                ("graph_iterations", ctypes.c_int), ("band_sector_min", ctypes.c_int)]
 
 
 class GpRigid(ctypes.Structure):

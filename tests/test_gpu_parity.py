@@ -160,6 +160,33 @@ def check_cycles(o, s):
         assert abs(ro - rg) <= 1e-9 * max(1.0, ro), (c, ro, rg)
 
 
+@pytest.mark.parametrize("N", [512, 1024])
+def test_band_sectors_against_single_band_layouts(N):
+    """The boundary band relaxed over angular sectors (one workgroup each, redundant near the sector edges) against
+    the one-workgroup and device-wide layouts: three cycles of the rotating flower, same iterates to rounding (the
+    wall ghost rows sum their terms in another order in the device-wide layout)."""
+    from paper_1911_00994_amd import gpmg
+    say(f"[band sectors] N={N}")
+    h = 2.0 / N
+    mo = wl.Motion(omega=1.0).as_array()
+    fu, fv = wl.fourier_forcing(N, 0)
+    out = []
+    for smin in (1500, 1 << 30):
+        s = gpu_solver(N, Re=400.0, band_sector_min=smin)
+        s.set_levelset_analytic(FLOWER.kind, FLOWER.params, 0.0, mo[:5])
+        s.set_alpha(h / 800.0)
+        s.set_rhs(fu, fv, None)
+        res = [s.cycle() for _ in range(3)]
+        out.append((flat(s.get_x()), res))
+        cls = s.classes().ravel()
+        s.close()
+    act = np.concatenate([active_mask(cls), [True]])
+    d = rel_diff(out[0][0], out[1][0], act)
+    say(f"  residuals {out[0][1]} vs {out[1][1]}, rel diff {d:.2e}")
+    assert d < 1e-12
+    assert np.all(np.isfinite(out[0][0]))
+
+
 @pytest.mark.parametrize("N,shape", [(64, CIRCLE), (128, FLOWER)])
 def test_converged_solve_parity(N, shape):
     say(f"[solve] N={N} shape={shape}")
