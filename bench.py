@@ -23,6 +23,9 @@ PEAK_HBM_GBS = 8000.0
 # and WRITE_SIZE, each scaled by what it reads for a 64 MiB device copy); None until taken for the current kernel
 BOX_TRAFFIC_BYTES = 89.34e6
 BOX_TRAFFIC_SOURCE = "profiles/k_box5_flower1024_hbm_traffic.md"
+# the launch probe times every 5th finest box sweep (5 is prime to the 4 finest sweeps of a V(2,2) cycle, so all
+# four positions are sampled in turn); each timed dispatch leaves the device idle for several microseconds
+PROBE_EVERY = 5
 
 
 def box_sweep_bytes(cls, N, elem=8):
@@ -134,7 +137,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-cycles", type=int, default=8)
     ap.add_argument("--no-kernel-timing", action="store_true")
-    ap.add_argument("--no-graphs", action="store_true", help="issue every launch from the host (no HIP graphs)")
+    ap.add_argument("--graphs", action="store_true",
+                    help="replay each solver iteration from a HIP graph (by default the launches are issued from the "
+                         "host, with the next cycle's first sweep queued ahead of the convergence test)")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--profile-kernel", action="store_true",
                     help="set up the N=1024 system, run a plain 64 MiB device copy (counter calibration) and 10 "
@@ -163,7 +168,7 @@ def main():
     prec = gpmg.GP_MIXED if args.precision == "mixed" else gpmg.GP_FP64
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream(dev)
-    solver = gpmg.Solver(N, Re=Re, stream=stream.cuda_stream, graph_iterations=0 if args.no_graphs else 1)
+    solver = gpmg.Solver(N, Re=Re, stream=stream.cuda_stream, graph_iterations=1 if args.graphs else 0)
     fu, fv = wl.fourier_forcing(N, seed=0)
     fu_d = torch.from_numpy(fu).to(dev)
     fv_d = torch.from_numpy(fv).to(dev)
@@ -211,7 +216,7 @@ def main():
     cycles = 0
     picard = 0
     if not args.no_kernel_timing:
-        solver.probe_start(4096)
+        solver.probe_start(4096, every=PROBE_EVERY)
     t_wall0 = time.perf_counter()
     e0.record(stream)
     for _ in range(args.steps):
@@ -238,7 +243,8 @@ def main():
         roofline = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                     "frac": achieved / PEAK_HBM_GBS, "traffic": traffic,
                     "kernel": "k_box5<double, 32> finest level (five colours per launch)", "bytes_per_launch": nbytes,
-                    "avg_launch_us": avg_us, "launches_timed": nprobe, "isolated_launch_us": iso_us,
+                    "avg_launch_us": avg_us, "launches_timed": nprobe, "probe_every": PROBE_EVERY,
+                    "isolated_launch_us": iso_us,
                     "traffic_gbs": traffic / (avg_us * 1e-6) / 1e9 if traffic else None,
                     "traffic_source": BOX_TRAFFIC_SOURCE if traffic else None}
     # time to 1e-8 from x = 0 on the last step's system: FP64 cycles against FP32 cycles in FP64 refinement

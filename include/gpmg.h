@@ -66,7 +66,7 @@ enum { GP_INACTIVE = 0, GP_INTERNAL = 1, GP_GHOST = 2, GP_WALL_DIRICHLET = 3, GP
  * fictitious time steps 0.9 (Dirichlet) and 0.9 h (normal derivative) (Sect. 4.1.2), extension band of 4
  * grid steps, minimum ghost-row diagonal 0.1 (below it the ghost takes an extrapolation row), and after each
  * relaxation step bnd_sweeps = 1 extra box sweep (same colour order, each followed by lambda_ghost ghost
- * sweeps) over the cells within bnd_radius = 2 cells of a cell touching the body.  The last four fields
+ * sweeps) over the cells within bnd_radius = 2 cells of a cell touching the body.  The last five fields
  * choose how the same computation is laid out on the device (results agree to rounding): fuse_small_levels = 1
  * runs the cycle of the levels with N <= 32 in one workgroup with their data in LDS, band_split_min = 3000: a
  * boundary band with at least that many cells is relaxed with device-wide launches instead of one workgroup,
@@ -74,13 +74,16 @@ enum { GP_INACTIVE = 0, GP_INTERNAL = 1, GP_GHOST = 2, GP_WALL_DIRICHLET = 3, GP
  * (where the band lies far enough from its centre; otherwise as above),
  * graph_iterations = 0; 1 captures the launches of one solver iteration (cycle, mean projection, residual
  * norm) into a HIP graph at the start of each gp_solve / gp_cn_step solve and replays it every iteration
- * (gp_probe_start turns it off while its events are live). */
+ * (gp_probe_start turns it off while its events are live), queue_ahead = 1: in FP64 solves without graphs the
+ * first box sweep of the next cycle is queued before the host has read the residual norm of the current one,
+ * and its workgroups return at once when that norm ends the solve (so the device does not wait for the host
+ * between cycles; the iterates are the same). */
 typedef struct {
   int nu1, nu2, gamma, lambda_ghost, coarsest_n, march_max, ext_radius;
   double dtau_dir, dtau_neu_over_h, bisect_eps_over_h, cg_min;
   int mixed_inner_cycles; /* FP32 cycles per FP64 refinement step in GP_MIXED solves */
   int bnd_sweeps, bnd_radius;
-  int fuse_small_levels, band_split_min, graph_iterations, band_sector_min;
+  int fuse_small_levels, band_split_min, graph_iterations, band_sector_min, queue_ahead;
 } gp_params;
 
 /* rigid motion: the body frame point of x at time t is R(-omega t) (x - X0 - U t); the boundary velocity at a
@@ -180,13 +183,16 @@ gp_status gp_relax(gp_ctx *ctx, int level, int steps);
 gp_status gp_time_kernel(gp_ctx *ctx, int which, int level, int reps, double *avg_us);
 
 /* measurement inside a run: gp_probe_start creates 2*max_launches HIP events (1 <= max_launches <= 65536) and
- * from then on the FP64 cycle launches each finest-level five-colour box sweep with a pair of them that take the
- * start and end times of that dispatch on the context's stream (hipExtLaunchKernel), up to max_launches
- * launches (later launches are not recorded).  gp_probe_stop waits for the last
+ * from then on the FP64 cycle launches every every-th finest-level five-colour box sweep (the first, then every
+ * every-th after it; 1 <= every <= 64) with a pair of them that take the start and end times of that dispatch on
+ * the context's stream (hipExtLaunchKernel), up to max_launches launches (later launches are not recorded).  A
+ * recorded launch leaves the device idle for several microseconds around it, so every > 1 samples a run with
+ * less of that cost; every prime to the four finest sweeps of a V(2,2) cycle samples all four of them in turn.
+ * gp_probe_stop waits for the last
  * recorded event, writes the average device time of the recorded launches in microseconds (0 if none) and
  * their number, and destroys the events.  A second gp_probe_start discards the pairs of the first.  GP_EHIP
  * if the events fail. */
-gp_status gp_probe_start(gp_ctx *ctx, int max_launches);
+gp_status gp_probe_start(gp_ctx *ctx, int max_launches, int every);
 gp_status gp_probe_stop(gp_ctx *ctx, double *avg_us, int *launches);
 
 /* ---- transposed system (the adjoint of the augmented system of Sect. 3.3, eq. (spaceprobaug)) ----

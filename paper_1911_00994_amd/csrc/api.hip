@@ -91,6 +91,7 @@ void gp_default_params(gp_params *p) {
   p->band_split_min = 3000;
   p->graph_iterations = 0;
   p->band_sector_min = 1500;
+  p->queue_ahead = 1;
 }
 
 const char *gp_strerror(gp_status st) {
@@ -174,6 +175,7 @@ void gp_destroy(gp_ctx *ctx) {
   for (auto e : ctx->probe_ev)
     if (e) (void)hipEventDestroy(e);
   ctx->probe_ev.clear();
+  if (ctx->h_rmax) (void)hipHostFree(ctx->h_rmax);
   dfree(ctx->phi);
   dfree(ctx->gtmp);
   dfree(ctx->gtmp2);
@@ -223,6 +225,7 @@ gp_status gp_setup_grid(gp_ctx **out, int N, double Re, const gp_params *prm, vo
   ctx->band_split_min = P.band_split_min;
   ctx->graphs = P.graph_iterations ? 1 : 0;
   ctx->band_sector_min = P.band_sector_min;
+  ctx->queue_ahead = P.queue_ahead ? 1 : 0;
   ctx->stream = (hipStream_t)hip_stream;
   if (!ctx->stream) {  // graphs are captured from the context's stream, which cannot be the null stream
     if (hipStreamCreate(&ctx->stream) != hipSuccess) {
@@ -314,7 +317,13 @@ gp_status gp_setup_grid(gp_ctx **out, int N, double Re, const gp_params *prm, vo
   ALLOC(ctx->phi, (size_t)(2 * N + 1) * (2 * N + 1));
   ALLOC(ctx->gtmp, gmax);
   ALLOC(ctx->gtmp2, gmax);
-  ALLOC(ctx->d_red, std::max<size_t>(8192, 2 * (size_t)nblk(3L * (N + 2) * (N + 2)) + 16));  // block partials
+  // block partials: two per block of the finest residual norm (points and ghost rows)
+  ALLOC(ctx->d_red, std::max<size_t>(8192, 2 * ((size_t)nblk(3L * (N + 2) * (N + 2)) + (size_t)nblk((long)gmax)) + 16));
+  {
+    void *hp = nullptr;
+    GP_HIP(hipHostMalloc(&hp, 64, hipHostMallocCoherent));
+    ctx->h_rmax = (unsigned long long *)hp;
+  }
   ALLOC(ctx->d_ticket, 4);
   ALLOC(ctx->d_scal, 16);
   ALLOC(ctx->d_lev, 2 * MAXLEV);
@@ -592,9 +601,9 @@ gp_status gp_time_kernel(gp_ctx *ctx, int which, int level, int reps, double *av
   return time_kernel(ctx, which, level, reps, avg_us);
 }
 
-gp_status gp_probe_start(gp_ctx *ctx, int max_launches) {
-  if (!ctx || max_launches < 1 || max_launches > (1 << 16)) return GP_EINVAL;
-  return probe_start(ctx, max_launches);
+gp_status gp_probe_start(gp_ctx *ctx, int max_launches, int every) {
+  if (!ctx || max_launches < 1 || max_launches > (1 << 16) || every < 1 || every > 64) return GP_EINVAL;
+  return probe_start(ctx, max_launches, every);
 }
 
 gp_status gp_probe_stop(gp_ctx *ctx, double *avg_us, int *launches) {

@@ -166,9 +166,17 @@ struct Ctx {
   // launch probe: HIP event pairs around the finest-level five-colour box launches of the FP64 cycle
   std::vector<hipEvent_t> probe_ev;
   int probe_n = 0;
+  int probe_every = 1, probe_seq = 0;  // events on launch probe_seq = 0, every, 2 every, ... (seq counts them all)
   // one solver iteration as an executable HIP graph, per precision (captured per solve, updated in place)
   int graphs = 1;
   hipGraphExec_t g_iter[2] = {nullptr, nullptr};
+  // the finest residual norm for the host: k_resid_mean_row also stores it in pinned host memory (h_rmax), which
+  // the solver polls
+  unsigned long long *h_rmax = nullptr;
+  // the first box sweep of the next FP64 cycle, queued before the host has the norm (queue_head); the device
+  // skips it when the solve stops there
+  int queue_ahead = 1;
+  bool head_queued = false, head_probe = false;
 };
 
 // error handling
@@ -197,7 +205,7 @@ gp_status relax64(Ctx *ctx, int level, int steps);
 gp_status residual64(Ctx *ctx, int level, double *res_inf);
 gp_status set_wall_dirichlet(Ctx *ctx);
 gp_status time_kernel(Ctx *ctx, int which, int level, int reps, double *avg_us);
-gp_status probe_start(Ctx *ctx, int max_launches);
+gp_status probe_start(Ctx *ctx, int max_launches, int every);
 gp_status probe_stop(Ctx *ctx, double *avg_us, int *launches);
 
 // adjoint (adjoint.hip)

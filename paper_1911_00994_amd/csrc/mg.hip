@@ -209,7 +209,13 @@ __host__ __device__ constexpr size_t box5_lds() {
 static inline int box5_tile(int N) { return (N / 16) * (N / 16) <= 512 ? 16 : 32; }
 template <typename T, int BT>
 __global__ void __launch_bounds__(B5_T, 2) k_box5(int N, int W, BoxK K, const uint8_t *__restrict__ cls,
-                                                  const T *__restrict__ x, const T *__restrict__ b, T *__restrict__ y) {
+                                                  const T *__restrict__ x, const T *__restrict__ b, T *__restrict__ y,
+                                                  const unsigned long long *__restrict__ go, double go_lo,
+                                                  double go_hi) {
+  if (go) {  // queued before the host's convergence test: run only if go_lo < norm <= go_hi (norm as bits)
+    const double r = __longlong_as_double((long long)*go);
+    if (!(r > go_lo && r <= go_hi)) return;
+  }
   constexpr int BRW = box5_rw<BT>(), BRWW = BRW * BRW;
   extern __shared__ unsigned char lds_raw[];
   T *xs = reinterpret_cast<T *>(lds_raw);
@@ -778,7 +784,6 @@ __global__ void __launch_bounds__(BAND_T) k_band_sec_fin(const int *__restrict__
 // deterministic grid reductions: fixed grid, fixed per-thread ranges, tree in LDS, the last block sums the
 // block partials in a fixed order
 // ---------------------------------------------------------------------------------------------------------
-constexpr int RED_BLOCKS = 512;
 
 __device__ double block_sum(double v) {
   __shared__ double s[TPB];
@@ -793,22 +798,28 @@ __device__ double block_sum(double v) {
   return r;
 }
 
-// returns true in the last block (all partials visible); *total valid there
-__device__ bool last_block_total(double mine, double *part, unsigned *ticket, double *total) {
+// The reductions of whole levels below run on at most RD_B workgroups of RD_T threads, each thread with RD_U
+// elements' loads in flight: the ticket of last_block_total costs one contended atomic (and a fence) per
+// workgroup, which at 512 workgroups took longer than reading the data.
+constexpr int RD_T = 1024, RD_B = 64, RD_U = 4;
+static inline int rd_blocks(long n) {
+  return (int)std::max(1L, std::min((long)RD_B, (n + (long)RD_T * RD_U - 1) / ((long)RD_T * RD_U)));
+}
+__device__ bool rd_last_total(double mine, double *part, unsigned *ticket, double *total) {
   __shared__ bool last;
-  double bs = block_sum(mine);
+  const double bs = band_block_sum(mine);
   if (threadIdx.x == 0) {
     part[blockIdx.x] = bs;
     __threadfence();
-    unsigned tk = atomicAdd(ticket, 1u);
-    last = (tk == gridDim.x - 1);
+    last = atomicAdd(ticket, 1u) == gridDim.x - 1;
   }
   __syncthreads();
   if (!last) return false;
   __threadfence();
-  double v = 0;
-  for (int q = threadIdx.x; q < (int)gridDim.x; q += TPB) v += __hip_atomic_load(&part[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  *total = block_sum(v);
+  const double v = threadIdx.x < gridDim.x
+                       ? __hip_atomic_load(&part[threadIdx.x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                       : 0.0;
+  *total = band_block_sum(v);
   if (threadIdx.x == 0) *ticket = 0;
   return true;
 }
@@ -816,33 +827,56 @@ __device__ bool last_block_total(double mine, double *part, unsigned *ticket, do
 // G = sum over the internal cells of (g - (wall Dirichlet faces of the cell, with their divergence signs) / h); the
 // xi update then needs only the faces of the boundary list: xi = (sum over the listed faces of +-u / h - G) / mp
 template <typename T>
-__global__ void __launch_bounds__(TPB) k_gsum(int W, double h, const uint8_t *__restrict__ cls, const T *__restrict__ x,
-                                              const T *__restrict__ b, double *part, unsigned *ticket, double *out) {
-  const int WW = W * W;
+__global__ void __launch_bounds__(RD_T) k_gsum(int W, double h, const uint8_t *__restrict__ cls, const T *__restrict__ x,
+                                               const T *__restrict__ b, double *part, unsigned *ticket, double *out) {
+  const int WW = W * W, stride = gridDim.x * RD_T;
   double s = 0;
-  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < WW; t += gridDim.x * blockDim.x) {
-    if (cls[2 * WW + t] != K_INT) continue;
-    double wf = 0;
-    if (cls[t + 1] == K_WALLD) wf += (double)x[t + 1];
-    if (cls[t] == K_WALLD) wf -= (double)x[t];
-    if (cls[WW + t + W] == K_WALLD) wf += (double)x[WW + t + W];
-    if (cls[WW + t] == K_WALLD) wf -= (double)x[WW + t];
-    s += (double)b[2 * WW + t] - wf / h;
+  for (int t0 = blockIdx.x * RD_T + threadIdx.x; t0 < WW; t0 += RD_U * stride) {
+    uint8_t c[RD_U];
+    double g[RD_U];
+#pragma unroll
+    for (int u = 0; u < RD_U; u++) {
+      const int t = t0 + u * stride;
+      c[u] = t < WW ? cls[2 * WW + t] : (uint8_t)K_INACTIVE;
+      g[u] = t < WW ? (double)b[2 * WW + t] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < RD_U; u++) {
+      if (c[u] != K_INT) continue;
+      const int t = t0 + u * stride;
+      double wf = 0;
+      if (cls[t + 1] == K_WALLD) wf += (double)x[t + 1];
+      if (cls[t] == K_WALLD) wf -= (double)x[t];
+      if (cls[WW + t + W] == K_WALLD) wf += (double)x[WW + t + W];
+      if (cls[WW + t] == K_WALLD) wf -= (double)x[WW + t];
+      s += g[u] - wf / h;
+    }
   }
   double tot;
-  if (last_block_total(s, part, ticket, &tot) && threadIdx.x == 0) *out = tot;
+  if (rd_last_total(s, part, ticket, &tot) && threadIdx.x == 0) *out = tot;
 }
 
 // mean of the internal pressure (row eq:midpoint); result in *out
 template <typename T>
-__global__ void __launch_bounds__(TPB) k_pmean(int W, const uint8_t *__restrict__ cls, const T *__restrict__ x,
-                                               double *part, unsigned *ticket, const int *mp, double *out) {
-  const int WW = W * W;
+__global__ void __launch_bounds__(RD_T) k_pmean(int W, const uint8_t *__restrict__ cls, const T *__restrict__ x,
+                                                double *part, unsigned *ticket, const int *mp, double *out) {
+  const int WW = W * W, stride = gridDim.x * RD_T;
   double s = 0;
-  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < WW; t += gridDim.x * blockDim.x)
-    if (cls[2 * WW + t] == K_INT) s += (double)x[2 * WW + t];
+  for (int t0 = blockIdx.x * RD_T + threadIdx.x; t0 < WW; t0 += RD_U * stride) {
+    uint8_t c[RD_U];
+    double v[RD_U];
+#pragma unroll
+    for (int u = 0; u < RD_U; u++) {
+      const int t = t0 + u * stride;
+      c[u] = t < WW ? cls[2 * WW + t] : (uint8_t)K_INACTIVE;
+      v[u] = t < WW ? (double)x[2 * WW + t] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < RD_U; u++)
+      if (c[u] == K_INT) s += v[u];
+  }
   double tot;
-  if (last_block_total(s, part, ticket, &tot) && threadIdx.x == 0) *out = tot / *mp;
+  if (rd_last_total(s, part, ticket, &tot) && threadIdx.x == 0) *out = tot / *mp;
 }
 template <typename T>
 __global__ void k_pshift(int W, const uint8_t *__restrict__ cls, T *__restrict__ x, const double *mean) {
@@ -899,23 +933,40 @@ __global__ void __launch_bounds__(TPB) k_resid_pts(int N, int W, double h, doubl
   (void)N;
   (void)rmax;
 }
-// variant with the max norm (all lanes of a wavefront take part in the reduction)
-// residual of the point rows, one point per thread; each block leaves the largest |residual| (as the bits of the
-// double, which order like the values; NaN above everything) in part[nb + block] and its sum of the internal
-// pressures in part[block], for k_resid_mean_row (no atomics and no grid-wide fence: the kernel writes the
-// whole residual)
+// residual of the point rows, one point per thread in the first nbp blocks, and of the ghost rows (pt, col, w:
+// ng rows of nine columns), one row per thread in the blocks after them (the point blocks leave those points'
+// entries to them); each block leaves the largest |residual| (as the bits of the double, which order like the
+// values; NaN above everything) in part[gridDim + block] and its sum of the internal pressures in part[block],
+// for k_resid_mean_row (no atomics and no grid-wide fence: the kernel writes the whole residual)
 template <typename T>
 __global__ void __launch_bounds__(TPB) k_resid_pts_norm(int W, double h, double a, double d,
                                                         const uint8_t *__restrict__ cls, const T *__restrict__ x,
-                                                        const T *__restrict__ b, T *__restrict__ r, double *part) {
+                                                        const T *__restrict__ b, T *__restrict__ r, int nbp,
+                                                        const int *__restrict__ pt, const int *__restrict__ col,
+                                                        const double *__restrict__ w, int ng, double *part) {
   __shared__ unsigned long long sm[TPB / 64];
   const int WW = W * W;
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
   double res = 0, ps = 0;
-  if (t < 3 * WW) {
-    res = resid_point<T>(W, h, a, d, cls, x, b, t);
-    r[t] = (T)res;
-    if (t >= 2 * WW && cls[t] == K_INT) ps += (double)x[t];
+  if ((int)blockIdx.x < nbp) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < 3 * WW) {
+      const uint8_t c = cls[t];
+      if (c != K_GHOST && c != K_GHOSTX && c != K_WALLG) {
+        res = resid_point<T>(W, h, a, d, cls, x, b, t);
+        r[t] = (T)res;
+        if (t >= 2 * WW && c == K_INT) ps += (double)x[t];
+      }
+    }
+  } else {
+    const int q = (blockIdx.x - nbp) * blockDim.x + threadIdx.x;
+    if (q < ng) {
+      const int k = pt[q];
+      double sw = 0;
+#pragma unroll
+      for (int z = 0; z < 9; z++) sw += w[9 * q + z] * (double)x[col[9 * q + z]];
+      res = (double)b[k] - sw;
+      r[k] = (T)res;
+    }
   }
   unsigned long long m = (unsigned long long)__double_as_longlong(fabs(res));
   for (int o = 32; o > 0; o >>= 1) {
@@ -931,11 +982,13 @@ __global__ void __launch_bounds__(TPB) k_resid_pts_norm(int W, double h, double 
   }
 }
 // the mean-pressure row's residual -mean(p) from the block sums of k_resid_pts_norm (fixed order), into r[3WW], and
-// the max norm of the whole residual into *rmax (as bits).  1024 threads, eight loads in flight per thread.
+// the max norm of the whole residual into *rmax (as bits), and into *hmax when given (pinned host memory, so that
+// the host can poll it without a copy).  1024 threads, eight loads in flight per thread.
 constexpr int RM_T = 1024;
 template <typename T>
 __global__ void __launch_bounds__(RM_T) k_resid_mean_row(const double *__restrict__ part, int nb, const int *mp,
-                                                         T *r3, unsigned long long *rmax) {
+                                                         T *r3, unsigned long long *rmax,
+                                                         unsigned long long *hmax) {
   __shared__ double ssum[RM_T / 64];
   __shared__ unsigned long long smax[RM_T / 64];
   double v = 0;
@@ -975,6 +1028,7 @@ __global__ void __launch_bounds__(RM_T) k_resid_mean_row(const double *__restric
     *r3 = (T)res;
     const unsigned long long z = (unsigned long long)__double_as_longlong(fabs(res));
     *rmax = z > m ? z : m;
+    if (hmax) *hmax = z > m ? z : m;  // host memory the solver polls
   }
 }
 template <typename T>
@@ -988,22 +1042,6 @@ __global__ void k_resid_ghost(const int *__restrict__ pt, const int *__restrict_
   for (int z = 0; z < 9; z++) s += w[9 * q + z] * (double)x[col[9 * q + z]];
   double res = (double)b[k] - s;
   r[k] = (T)res;
-}
-template <typename T>
-__global__ void k_resid_ghost_norm(const int *__restrict__ pt, const int *__restrict__ col, const double *__restrict__ w,
-                                   int ng, const T *__restrict__ x, const T *__restrict__ b, T *__restrict__ r,
-                                   unsigned long long *rmax) {
-  int q = blockIdx.x * blockDim.x + threadIdx.x;
-  double res = 0;
-  if (q < ng) {
-    int k = pt[q];
-    double s = 0;
-#pragma unroll
-    for (int z = 0; z < 9; z++) s += w[9 * q + z] * (double)x[col[9 * q + z]];
-    res = (double)b[k] - s;
-    r[k] = (T)res;
-  }
-  max_abs(rmax, res);
 }
 // max |b| over a vector (wavefront reduction, one atomic per wavefront)
 template <typename T>
@@ -1483,15 +1521,35 @@ static void relax_ghost_only(Ctx *ctx, int l) { relax_ghosts<double>(ctx, l); }
 
 // one five-colour sweep x -> y; with events, they take the start and end times of the dispatch
 template <typename T>
-static void box5_launch(const Geo &G, const BoxK &BK, const Vec<T> &V, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+static void box5_launch(const Geo &G, const BoxK &BK, const Vec<T> &V, hipStream_t s, hipEvent_t e0, hipEvent_t e1,
+                        const unsigned long long *go = nullptr, double go_lo = 0, double go_hi = 0) {
   const int bt = box5_tile(G.N), nt = (G.N + bt - 1) / bt;
   auto kern = bt == 16 ? k_box5<T, 16> : k_box5<T, 32>;
   const std::uint32_t lds = (std::uint32_t)(bt == 16 ? box5_lds<T, 16>() : box5_lds<T, 32>());
   if (e0)
     hipExtLaunchKernelGGL(kern, dim3(nt * nt), dim3(B5_T), lds, s, e0, e1, 0u, G.N, G.W, BK, (const uint8_t *)G.cls,
-                          (const T *)V.x, (const T *)V.b, V.y);
+                          (const T *)V.x, (const T *)V.b, V.y, go, go_lo, go_hi);
   else
-    kern<<<nt * nt, B5_T, lds, s>>>(G.N, G.W, BK, G.cls, V.x, V.b, V.y);
+    kern<<<nt * nt, B5_T, lds, s>>>(G.N, G.W, BK, G.cls, V.x, V.b, V.y, go, go_lo, go_hi);
+}
+template <typename T>
+static bool box5_applies(Ctx *ctx, int l) {
+  return ctx->box_tiles && vec<T>(ctx, l).y && box5_lds<T, 32>() + 1024 <= ctx->max_lds;
+}
+// the finest five-colour sweep of a relaxation step (through the launch probe while it has events left); with
+// go, the guarded launch of queue_head
+static void box5_finest(Ctx *ctx, const BoxK &BK, const unsigned long long *go, double lo, double hi, bool *probed) {
+  Geo &G = ctx->geo[0];
+  const bool probe = 2 * ctx->probe_n < (int)ctx->probe_ev.size() && ctx->probe_seq % ctx->probe_every == 0;
+  if (!ctx->probe_ev.empty()) ctx->probe_seq++;
+  if (probe) {  // the events take the start and end times of the dispatch itself
+    hipEvent_t e0 = ctx->probe_ev[2 * ctx->probe_n], e1 = ctx->probe_ev[2 * ctx->probe_n + 1];
+    ctx->probe_n++;
+    box5_launch<double>(G, BK, ctx->v64[0], ctx->stream, e0, e1, go, lo, hi);
+  } else {
+    box5_launch<double>(G, BK, ctx->v64[0], ctx->stream, nullptr, nullptr, go, lo, hi);
+  }
+  if (probed) *probed = probe;
 }
 
 template <typename T>
@@ -1502,12 +1560,12 @@ static void relax(Ctx *ctx, int l) {
   double a = coef_a(ctx, l), d = 1.0 + 4.0 * a;
   const BoxK BK = box_consts(G.h, a, d);
   int K = G.N / 5 + 1;
-  if (ctx->box_tiles && V.y && box5_lds<T, 32>() + 1024 <= ctx->max_lds) {
-    const bool probe = sizeof(T) == 8 && l == 0 && 2 * ctx->probe_n < (int)ctx->probe_ev.size();
-    if (probe) {  // the events take the start and end times of the dispatch itself
-      hipEvent_t e0 = ctx->probe_ev[2 * ctx->probe_n], e1 = ctx->probe_ev[2 * ctx->probe_n + 1];
-      ctx->probe_n++;
-      box5_launch<T>(G, BK, V, s, e0, e1);
+  if (box5_applies<T>(ctx, l)) {
+    if (sizeof(T) == 8 && l == 0) {
+      if (ctx->head_queued)  // issued ahead by queue_head (the host has seen that the solve goes on)
+        ctx->head_queued = false;
+      else
+        box5_finest(ctx, BK, nullptr, 0, 0, nullptr);
     } else {
       box5_launch<T>(G, BK, V, s, nullptr, nullptr);
     }
@@ -1606,23 +1664,22 @@ static void relax(Ctx *ctx, int l) {
 template <typename T>
 static void gsum(Ctx *ctx, int l) {
   Geo &G = ctx->geo[l];
-  int nb = std::min(RED_BLOCKS, nblk(G.WW));
-  k_gsum<T><<<nb, TPB, 0, ctx->stream>>>(G.W, G.h, G.cls, vec<T>(ctx, l).x, vec<T>(ctx, l).b, ctx->d_red, ctx->d_ticket,
+  k_gsum<T><<<rd_blocks(G.WW), RD_T, 0, ctx->stream>>>(G.W, G.h, G.cls, vec<T>(ctx, l).x, vec<T>(ctx, l).b, ctx->d_red, ctx->d_ticket,
                                          ctx->d_lev + l);
 }
 
 template <typename T>
-static void residual(Ctx *ctx, int l, unsigned long long *rmax) {
+static void residual(Ctx *ctx, int l, unsigned long long *rmax, unsigned long long *hmax = nullptr) {
   Geo &G = ctx->geo[l];
   Vec<T> &V = vec<T>(ctx, l);
   hipStream_t s = ctx->stream;
   double a = coef_a(ctx, l), d = 1.0 + 4.0 * a;
   if (rmax) {
-    // two partials per block in d_red (2 nblk(3 (N+2)^2) + 16 slots)
-    const int nb = nblk(3L * G.WW);
-    k_resid_pts_norm<T><<<nb, TPB, 0, s>>>(G.W, G.h, a, d, G.cls, V.x, V.b, V.r, ctx->d_red);
-    k_resid_mean_row<T><<<1, RM_T, 0, s>>>(ctx->d_red, nb, G.d_mp, V.r + 3L * G.WW, rmax);
-    if (G.ng) k_resid_ghost_norm<T><<<nblk(G.ng), TPB, 0, s>>>(G.g_pt, G.g_col, G.g_w, G.ng, V.x, V.b, V.r, rmax);
+    // two partials per block in d_red (2 (nblk(3 (N+2)^2) + nblk(gcap)) + 16 slots)
+    const int nbp = nblk(3L * G.WW), nb = nbp + (G.ng ? nblk(G.ng) : 0);
+    k_resid_pts_norm<T><<<nb, TPB, 0, s>>>(G.W, G.h, a, d, G.cls, V.x, V.b, V.r, nbp, G.g_pt, G.g_col, G.g_w, G.ng,
+                                           ctx->d_red);
+    k_resid_mean_row<T><<<1, RM_T, 0, s>>>(ctx->d_red, nb, G.d_mp, V.r + 3L * G.WW, rmax, hmax);
   } else {
     k_resid_pts<T><<<nblk(3L * G.WW), TPB, 0, s>>>(G.N, G.W, G.h, a, d, G.cls, V.x, V.b, V.r, nullptr);
     if (G.ng) k_resid_ghost<T><<<nblk(G.ng), TPB, 0, s>>>(G.g_pt, G.g_col, G.g_w, G.ng, V.x, V.b, V.r, nullptr);
@@ -1736,23 +1793,42 @@ template <typename T>
 static void mean_project(Ctx *ctx) {
   Geo &G = ctx->geo[0];
   Vec<T> &V = vec<T>(ctx, 0);
-  int nb = std::min(RED_BLOCKS, nblk(G.WW));
-  k_pmean<T><<<nb, TPB, 0, ctx->stream>>>(G.W, G.cls, V.x, ctx->d_red, ctx->d_ticket, G.d_mp, ctx->d_scal);
+  k_pmean<T><<<rd_blocks(G.WW), RD_T, 0, ctx->stream>>>(G.W, G.cls, V.x, ctx->d_red, ctx->d_ticket, G.d_mp, ctx->d_scal);
   k_pshift<T><<<nblk(G.WW), TPB, 0, ctx->stream>>>(G.W, G.cls, V.x, ctx->d_scal);
 }
 
-static gp_status resnorm64(Ctx *ctx, double *out) {
-  unsigned long long *rmax = (unsigned long long *)(ctx->d_scal + 1);
-  k_fill<unsigned long long><<<1, 1, 0, ctx->stream>>>(rmax, 1, 0ull);
-  residual<double>(ctx, 0, rmax);
-  GP_HIP(hipGetLastError());
-  unsigned long long hv = 0;
-  GP_HIP(hipMemcpyAsync(&hv, rmax, sizeof(hv), hipMemcpyDeviceToHost, ctx->stream));
-  GP_HIP(hipStreamSynchronize(ctx->stream));
-  double v;
-  std::memcpy(&v, &hv, sizeof(v));
-  *out = v;
+// The finest residual norm reaches the host through pinned memory: norm_launch clears the host slot to a value no
+// norm has (the bits of a negative NaN; the kernel stores |r| as bits) and issues the residual kernels, whose last
+// one also stores the norm there; wait_norm polls the slot, and now and then the stream, so that a failed launch
+// ends the wait (once the stream is idle the store has landed; else the device copy is read).
+constexpr unsigned long long NORM_PENDING = ~0ull;
+static void norm_launch(Ctx *ctx) {
+  __atomic_store_n(ctx->h_rmax, NORM_PENDING, __ATOMIC_RELEASE);
+  residual<double>(ctx, 0, (unsigned long long *)(ctx->d_scal + 1), ctx->h_rmax);
+}
+static gp_status wait_norm(Ctx *ctx, double *out) {
+  unsigned long long v = NORM_PENDING;
+  for (long it = 1;; it++) {
+    v = __atomic_load_n(ctx->h_rmax, __ATOMIC_ACQUIRE);
+    if (v != NORM_PENDING) break;
+    if ((it & 255) == 0) {
+      const hipError_t e = hipStreamQuery(ctx->stream);
+      if (e == hipSuccess) {
+        v = __atomic_load_n(ctx->h_rmax, __ATOMIC_ACQUIRE);
+        if (v == NORM_PENDING)
+          GP_HIP(hipMemcpy(&v, ctx->d_scal + 1, sizeof(v), hipMemcpyDeviceToHost));
+        break;
+      }
+      if (e != hipErrorNotReady) GP_HIP(e);
+    }
+  }
+  std::memcpy(out, &v, sizeof(double));
   return GP_OK;
+}
+static gp_status resnorm64(Ctx *ctx, double *out) {
+  norm_launch(ctx);
+  GP_HIP(hipGetLastError());
+  return wait_norm(ctx, out);
 }
 
 static gp_status bnorm64(Ctx *ctx, double *out) {
@@ -1834,12 +1910,14 @@ gp_status time_kernel(Ctx *ctx, int which, int l, int reps, double *avg_us) {
   return GP_OK;
 }
 
-gp_status probe_start(Ctx *ctx, int max_launches) {
+gp_status probe_start(Ctx *ctx, int max_launches, int every) {
   double dummy;
   int n;
   if (!ctx->probe_ev.empty()) probe_stop(ctx, &dummy, &n);
   ctx->probe_ev.assign(2 * (size_t)max_launches, nullptr);
   ctx->probe_n = 0;
+  ctx->probe_every = every;
+  ctx->probe_seq = 0;
   for (auto &e : ctx->probe_ev) GP_HIP(hipEventCreate(&e));
   return GP_OK;
 }
@@ -1944,9 +2022,7 @@ static void iteration_launches(Ctx *ctx, int precision) {
   } else {
     refine_step(ctx, ctx->prm.mixed_inner_cycles);
   }
-  unsigned long long *rmax = (unsigned long long *)(ctx->d_scal + 1);
-  k_fill<unsigned long long><<<1, 1, 0, ctx->stream>>>(rmax, 1, 0ull);
-  residual<double>(ctx, 0, rmax);
+  residual<double>(ctx, 0, (unsigned long long *)(ctx->d_scal + 1), ctx->h_rmax);
 }
 
 static gp_status capture_iteration(Ctx *ctx, int precision) {
@@ -1981,12 +2057,21 @@ static gp_status capture_iteration(Ctx *ctx, int precision) {
   return GP_OK;
 }
 
-static gp_status read_rmax(Ctx *ctx, double *out) {
-  unsigned long long hv = 0;
-  GP_HIP(hipMemcpyAsync(&hv, ctx->d_scal + 1, sizeof(hv), hipMemcpyDeviceToHost, ctx->stream));
-  GP_HIP(hipStreamSynchronize(ctx->stream));
-  std::memcpy(out, &hv, sizeof(double));
-  return GP_OK;
+// The first box sweep of the next FP64 cycle, queued behind the residual norm of this one before the host has
+// read it: its workgroups return at once unless lo < norm <= hi, the condition under which the solve goes on, so
+// the device need not wait for the host's test and its next launches.  relax() takes it as its first sweep when
+// the host goes on; when the solve stops, drop_head() forgets it (and its probe events).
+static void queue_head(Ctx *ctx, double lo, double hi) {
+  Geo &G = ctx->geo[0];
+  const double a = coef_a(ctx, 0), d = 1.0 + 4.0 * a;
+  box5_finest(ctx, box_consts(G.h, a, d), (const unsigned long long *)(ctx->d_scal + 1), lo, hi, &ctx->head_probe);
+  ctx->head_queued = true;
+}
+static void drop_head(Ctx *ctx) {
+  if (!ctx->head_queued) return;
+  ctx->head_queued = false;
+  if (!ctx->probe_ev.empty()) ctx->probe_seq--;
+  if (ctx->head_probe) ctx->probe_n--;
 }
 
 gp_status mg_solve(Ctx *ctx, int precision, double tol, int max_cycles, gp_stats *stt) {
@@ -2006,20 +2091,35 @@ gp_status mg_solve(Ctx *ctx, int precision, double tol, int max_cycles, gp_stats
   if (precision == GP_FP64) gsum<double>(ctx, 0);  // b and the wall values are fixed during the solve
   if (graph && (st = capture_iteration(ctx, precision))) return st;
   hipGraphExec_t ex = ctx->g_iter[precision == GP_FP64 ? 0 : 1];
+  const double lim = 1e6 * (r0 > 1 ? r0 : 1);  // divergence
   if (precision == GP_FP64) {
+    // the loop goes on while thr < r <= lim (r not NaN) and c < max_cycles: the guard of queue_head
+    const bool ahead = ctx->queue_ahead && !graph && ctx->prm.nu1 > 0 && ctx->L > 1 &&
+                       !(ctx->small_cycles && ctx->geo[0].N <= 32) && box5_applies<double>(ctx, 0);
     while (r > thr && c < max_cycles) {
       double rp = r;
       if (graph) {
+        __atomic_store_n(ctx->h_rmax, NORM_PENDING, __ATOMIC_RELEASE);
         GP_HIP(hipGraphLaunch(ex, ctx->stream));
-        if ((st = read_rmax(ctx, &r))) return st;
+        if ((st = wait_norm(ctx, &r))) return st;
       } else {
         cycle<double>(ctx, 0);
         mean_project<double>(ctx);
-        if ((st = resnorm64(ctx, &r))) return st;
+        norm_launch(ctx);
+        GP_HIP(hipGetLastError());
+        if (ahead && c + 1 < max_cycles) queue_head(ctx, thr, lim);
+        GP_HIP(hipGetLastError());
+        st = wait_norm(ctx, &r);
+        if (st) {
+          drop_head(ctx);
+          return st;
+        }
       }
       c++;
       rho = r / rp;
-      if (!(r == r) || r > 1e6 * (r0 > 1 ? r0 : 1)) {
+      const bool diverged = !(r == r) || r > lim;
+      if (diverged || !(r > thr) || c >= max_cycles) drop_head(ctx);
+      if (diverged) {
         out = GP_EDIVERGED;
         break;
       }
@@ -2029,8 +2129,9 @@ gp_status mg_solve(Ctx *ctx, int precision, double tol, int max_cycles, gp_stats
     while (r > thr && c < max_cycles) {
       double rp = r;
       if (graph) {  // v64[0].r holds the residual of the last norm
+        __atomic_store_n(ctx->h_rmax, NORM_PENDING, __ATOMIC_RELEASE);
         GP_HIP(hipGraphLaunch(ex, ctx->stream));
-        if ((st = read_rmax(ctx, &r))) return st;
+        if ((st = wait_norm(ctx, &r))) return st;
       } else {
         refine_step(ctx, k);
         if ((st = resnorm64(ctx, &r))) return st;
@@ -2038,7 +2139,7 @@ gp_status mg_solve(Ctx *ctx, int precision, double tol, int max_cycles, gp_stats
       c += k;
       outer++;
       rho = r / rp;
-      if (!(r == r) || r > 1e6 * (r0 > 1 ? r0 : 1)) {
+      if (!(r == r) || r > lim) {
         out = GP_EDIVERGED;
         break;
       }

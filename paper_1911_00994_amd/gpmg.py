@@ -35,7 +35,8 @@ class GpParams(ctypes.Structure):
                 ("bisect_eps_over_h", ctypes.c_double), ("cg_min", ctypes.c_double),
                 ("mixed_inner_cycles", ctypes.c_int), ("bnd_sweeps", ctypes.c_int), ("bnd_radius", ctypes.c_int),
                 ("fuse_small_levels", ctypes.c_int), ("band_split_min", ctypes.c_int),
-                ("graph_iterations", ctypes.c_int), ("band_sector_min", ctypes.c_int)]
+                ("graph_iterations", ctypes.c_int), ("band_sector_min", ctypes.c_int),
+                ("queue_ahead", ctypes.c_int)]
 
 
 class GpRigid(ctypes.Structure):
@@ -103,7 +104,7 @@ def lib():
         "gp_get_ext_rows": (i, [vp, i, vp, vp]),
         "gp_relax": (i, [vp, i, i]),
         "gp_time_kernel": (i, [vp, i, i, i, vp]),
-        "gp_probe_start": (i, [vp, i]),
+        "gp_probe_start": (i, [vp, i, i]),
         "gp_probe_stop": (i, [vp, vp, vp]),
         "gp_apply_mt": (i, [vp, vp, vp, i]),
         "gp_adjoint_solve": (i, [vp, vp, vp, i, d, i, ctypes.POINTER(GpStats)]),
@@ -255,9 +256,10 @@ class Solver:
         self._check(lib().gp_time_kernel(self._h, which, level, reps, ctypes.byref(us)), "gp_time_kernel")
         return us.value
 
-    def probe_start(self, max_launches=4096):
-        """record HIP events around each finest-level five-colour box launch of the FP64 cycle from now on"""
-        self._check(lib().gp_probe_start(self._h, max_launches), "gp_probe_start")
+    def probe_start(self, max_launches=4096, every=1):
+        """record HIP events around every every-th finest-level five-colour box launch of the FP64 cycle from now
+        on"""
+        self._check(lib().gp_probe_start(self._h, max_launches, every), "gp_probe_start")
 
     def probe_stop(self):
         """(average device microseconds of the recorded launches, their number)"""

@@ -226,6 +226,34 @@ def test_graph_replayed_solve_matches_issued_launches(mixed, split):
     assert rel_diff(flat(o.get_x()), out[1][0], act) < 1e-7
 
 
+@pytest.mark.gpu
+def test_queued_first_sweep_gives_the_same_iterates():
+    """queuing the next cycle's first box sweep before the host has read the residual norm (its workgroups return
+    at once when the solve stops there) leaves the iterates, the cycle counts and the launch probe's count as
+    when the host issues that sweep after its test: a solve cut off by max_cycles, the solve that goes on from it
+    to convergence, and a solve that starts converged"""
+    from paper_1911_00994_amd import gpmg
+    N = 256
+    say(f"[queued first sweep] N={N}")
+    out = []
+    for q in (0, 1):
+        _, s = pair(N, FLOWER, 0.64 * (2.0 / N) ** 2, m=wl.PaperMMS(), t=0.4, queue_ahead=q)
+        s.probe_start(4096)
+        rec = []
+        for tol, mc in ((1e-10, 3), (1e-10, 100), (1e-10, 100)):
+            st, info = s.solve(tol, mc, precision=gpmg.GP_FP64, check=False)
+            rec.append((st, info["cycles"], flat(s.get_x())))
+        _, n = s.probe_stop()
+        out.append((rec, n))
+    (r0, n0), (r1, n1) = out
+    assert r0[0][0] != 0 and r0[0][1] == 3  # cut off
+    assert r0[1][0] == 0 and r0[1][1] > 0 and r0[2][1] == 0
+    for a, b in zip(r0, r1):
+        assert a[0] == b[0] and a[1] == b[1]
+        assert np.array_equal(a[2], b[2])
+    assert n0 == n1 == 4 * (r0[0][1] + r0[1][1])  # nu1 + nu2 = 4 finest sweeps per cycle
+
+
 def _cn_lockstep(o, s, N, shape, motion, m, Re, nsteps, dt):
     """advance oracle and GPU together; both get the boundary data computed from the oracle's geometry"""
     mo = motion.as_array()
