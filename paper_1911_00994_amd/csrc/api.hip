@@ -183,6 +183,7 @@ void gp_destroy(gp_ctx *ctx) {
   dfree(ctx->d_ticket);
   dfree(ctx->d_scal);
   dfree(ctx->d_lev);
+  dfree(ctx->d_gpart);
   dfree(ctx->d_bcnt);
   dfree(ctx->d_iscr);
   dfree(ctx->d_flags);
@@ -327,6 +328,20 @@ gp_status gp_setup_grid(gp_ctx **out, int N, double Re, const gp_params *prm, vo
   ALLOC(ctx->d_ticket, 4);
   ALLOC(ctx->d_scal, 16);
   ALLOC(ctx->d_lev, 2 * MAXLEV);
+  {  // block partials of G written by the restriction onto each coarse level (see k_resid_restrict)
+    size_t tot = 16;
+    for (int l = 1; l < L; l++) {
+      Geo &G = ctx->geo[l];
+      G.gp_off = (int)tot;
+      G.gp_n = nblk(3L * G.WW + 1) - 2 * G.WW / TPB;
+      tot += (size_t)G.gp_n + 16;
+    }
+    ALLOC(ctx->d_gpart, tot);
+    for (int l = 0; l < L; l++) {
+      ctx->gs_ptr[l] = ctx->d_lev + l;
+      ctx->gs_n[l] = 1;
+    }
+  }
   ALLOC(ctx->d_bcnt, (size_t)8 * nblk((long)(N + 2) * (N + 2)) + 16);  // two scans of 3 (N+2)^2 points, or 5 colours
   ALLOC(ctx->d_iscr, (size_t)3 * (N + 2) * (N + 2) + 1);
   ALLOC(ctx->d_flags, 16);

@@ -77,6 +77,7 @@ struct Geo {
   double *sec_gw = nullptr, *sec_gdt = nullptr, *sec_out = nullptr;
   int sec_pcap = 0, sec_bcap = 0, sec_gcap = 0, sec_rcap = 0;
   int colr_ok = 0;                  // 1 when g_colr holds the row of every ghost column
+  int gp_off = 0, gp_n = 0;         // this level's block partials of G in Ctx::d_gpart (written by the restriction)
   // faces on the boundary of the internal pressure cells, cell-major order: code = 2 * (u or v index) + (1 if the
   // face enters the cell's divergence with a minus sign); f_loc = the same face as an LDS band-region entry
   int *f_code = nullptr, *f_loc = nullptr;
@@ -176,6 +177,11 @@ struct Ctx {
   // the first box sweep of the next FP64 cycle, queued before the host has the norm (queue_head); the device
   // skips it when the solve stops there
   int queue_ahead = 1;
+  // G of each level (see gp_start): its partials and their number; d_lev + l (one) after gsum(l), the block sums
+  // of the restriction onto level l after it (d_gpart + gp_off, gp_n)
+  double *d_gpart = nullptr;
+  const double *gs_ptr[MAXLEV] = {nullptr};
+  int gs_n[MAXLEV] = {0};
   bool head_queued = false, head_probe = false;
 };
 

@@ -451,6 +451,24 @@ __device__ double band_block_sum(double v) {
   return t;
 }
 
+// G, the sum over a level's internal cells of the continuity right-hand sides (less the wall Dirichlet faces'
+// share), which every xi update of the level subtracts, comes as ngp partial sums: one (k_gsum) on a level whose
+// right-hand side the caller set, the block sums of k_resid_restrict on a coarse level.  A 1024-thread workgroup
+// issues its loads early (gp_start: two per thread, in flight with what the kernel loads next) and sums them in
+// a fixed order when it needs G (gp_total).
+struct GpPre {
+  double a, b;
+};
+__device__ __forceinline__ GpPre gp_start(const double *__restrict__ gp, int ngp) {
+  const int t = threadIdx.x;
+  return {t < ngp ? gp[t] : 0.0, t + BAND_T < ngp ? gp[t + BAND_T] : 0.0};
+}
+__device__ __forceinline__ double gp_total(GpPre pre, const double *__restrict__ gp, int ngp) {
+  double v = pre.a + pre.b;
+  for (int q = threadIdx.x + 2 * BAND_T; q < ngp; q += BAND_T) v += gp[q];
+  return band_block_sum(v);
+}
+
 // One relaxation step's work after the five box sweeps, in one workgroup:
 //  - workgroup 0: the body ghost rows and the band boxes as in k_band_sweeps, with the values the kernel writes
 //    staged in LDS (region slots [0, nregw), written back at the end) and, when they fit, the values it only reads
@@ -488,7 +506,7 @@ __global__ void __launch_bounds__(BAND_T) k_band_lds(int N, int W, BoxK K, T *x,
                                                      const double *__restrict__ g_w, const double *__restrict__ g_dtau,
                                                      const int *__restrict__ wg_rows, int nwg, int sweeps, int lambda,
                                                      const int *__restrict__ f_code, const int *__restrict__ f_loc, int nf,
-                                                     const double *__restrict__ gsum, const int *__restrict__ mp) {
+                                                     const double *__restrict__ gp, int ngp, const int *__restrict__ mp) {
   extern __shared__ unsigned char lds_raw[];
   T *xs = reinterpret_cast<T *>(lds_raw);
   const int nb = off.o[5];
@@ -511,6 +529,8 @@ __global__ void __launch_bounds__(BAND_T) k_band_lds(int N, int W, BoxK K, T *x,
       wall_ghost_row<T>(wg_rows[q], g_pt, g_col, g_w, g_dtau, x, b, lambda * (1 + sweeps));
     return;
   }
+  // G's partials early where registers allow (modes 0 and 1 hold more of the region's values in registers)
+  const GpPre gpre = MODE >= 2 ? gp_start(gp, ngp) : GpPre{0.0, 0.0};
   // stage the region: batches of BATCH loads in flight per thread (16 at once measured slower on one CU)
   for (int q0 = tid; q0 < nreg; q0 += BATCH * BAND_T) {
     int gi[BATCH];
@@ -639,6 +659,7 @@ __global__ void __launch_bounds__(BAND_T) k_band_lds(int N, int W, BoxK K, T *x,
       if (cd[u] >= 0) fs += (cd[u] & 1) ? -v[u] : v[u];
   }
   fs = band_block_sum(fs);
+  const double gsum = gp_total(MODE >= 2 ? gpre : gp_start(gp, ngp), gp, ngp);
   for (int q0 = tid; q0 < nregw; q0 += BATCH * BAND_T) {  // only the written points go back
     int gi[BATCH];
 #pragma unroll
@@ -647,20 +668,22 @@ __global__ void __launch_bounds__(BAND_T) k_band_lds(int N, int W, BoxK K, T *x,
     for (int u = 0; u < BATCH; u++)
       if (gi[u] >= 0) x[gi[u]] = xs[q0 + u * BAND_T];
   }
-  if (tid == 0) x[3 * WW] = (T)((fs / K.h - *gsum) / *mp);
+  if (tid == 0) x[3 * WW] = (T)((fs / K.h - gsum) / *mp);
 }
 
 // xi <- mean over internal cells of (div u - g), from the boundary faces of the internal cells (one workgroup)
 template <typename T>
 __global__ void __launch_bounds__(BAND_T) k_xi_faces(int WW, double h, T *x, const int *__restrict__ f_code, int nf,
-                                                     const double *__restrict__ gsum, const int *__restrict__ mp) {
+                                                     const double *__restrict__ gp, int ngp, const int *__restrict__ mp) {
+  const GpPre gpre = gp_start(gp, ngp);
   double fs = 0;
   for (int q = threadIdx.x; q < nf; q += BAND_T) {
     double v = (double)x[f_code[q] >> 1];
     fs += (f_code[q] & 1) ? -v : v;
   }
   fs = band_block_sum(fs);
-  if (threadIdx.x == 0) x[3 * WW] = (T)((fs / h - *gsum) / *mp);
+  const double gsum = gp_total(gpre, gp, ngp);
+  if (threadIdx.x == 0) x[3 * WW] = (T)((fs / h - gsum) / *mp);
 }
 
 // One relaxation step's band work over angular sectors (built by sector_build), one workgroup per sector: the
@@ -761,13 +784,14 @@ template <typename T>
 __global__ void __launch_bounds__(BAND_T) k_band_sec_fin(const int *__restrict__ reg_pt, int nregw,
                                                          const double *__restrict__ out, T *x, int WW, double h,
                                                          const int *__restrict__ f_code, const int *__restrict__ f_loc,
-                                                         int nf, const double *__restrict__ gsum,
+                                                         int nf, const double *__restrict__ gp, int ngp,
                                                          const int *__restrict__ mp) {
   if (blockIdx.x > 0) {
     for (int g = (blockIdx.x - 1) * BAND_T + threadIdx.x; g < nregw; g += (gridDim.x - 1) * BAND_T)
       x[reg_pt[g]] = (T)out[g];
     return;
   }
+  const GpPre gpre = gp_start(gp, ngp);
   double fs = 0;
   for (int q = threadIdx.x; q < nf; q += BAND_T) {
     const int e = f_loc[q];
@@ -775,7 +799,8 @@ __global__ void __launch_bounds__(BAND_T) k_band_sec_fin(const int *__restrict__
     fs += (f_code[q] & 1) ? -v : v;
   }
   fs = band_block_sum(fs);
-  if (threadIdx.x == 0) x[3 * WW] = (T)((fs / h - *gsum) / *mp);
+  const double gsum = gp_total(gpre, gp, ngp);
+  if (threadIdx.x == 0) x[3 * WW] = (T)((fs / h - gsum) / *mp);
 }
 
 
@@ -1131,19 +1156,31 @@ __device__ __forceinline__ double restrict_value(int Nf, int Wf, const uint8_t *
 }
 // residual and restriction in one pass: the residual of an internal fine row is formed where the restriction
 // needs it (rounded to T, as the stored residual would be); ghost and wall-ghost residuals come from rf, written
-// before by k_resid_ghost.  Also the zero initial guess of the coarse correction.
+// before by k_resid_ghost.  Also the zero initial guess of the coarse correction, and the coarse level's G (see
+// gp_start) as block partials: gpart[block - b0] = the sum of the restricted continuity right-hand sides of the
+// block's internal cells, for the blocks b0 = 2 Wc^2 / TPB and on (those holding pressure entries; with x = 0
+// the wall Dirichlet faces add nothing).
 template <typename T>
 __global__ void __launch_bounds__(TPB) k_resid_restrict(int Nf, int Wf, double h, double a, double d,
                                                         const uint8_t *__restrict__ clsf, const T *__restrict__ xf,
                                                         const T *__restrict__ bf, const T *__restrict__ rf, int Nc, int Wc,
                                                         const uint8_t *__restrict__ clsc, T *__restrict__ bc,
-                                                        T *__restrict__ xc) {
-  int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t > 3 * Wc * Wc) return;
-  bc[t] = (T)restrict_core(Nf, Wf, clsf, Nc, Wc, clsc, t, [&](int kf, uint8_t cc) {
-    return cc == K_INT ? (double)(T)resid_point<T>(Wf, h, a, d, clsf, xf, bf, kf) : (double)rf[kf];
-  });
-  xc[t] = (T)0;
+                                                        T *__restrict__ xc, double *__restrict__ gpart) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x, WWc = Wc * Wc;
+  double gs = 0;
+  if (t <= 3 * WWc) {
+    const T v = (T)restrict_core(Nf, Wf, clsf, Nc, Wc, clsc, t, [&](int kf, uint8_t cc) {
+      return cc == K_INT ? (double)(T)resid_point<T>(Wf, h, a, d, clsf, xf, bf, kf) : (double)rf[kf];
+    });
+    bc[t] = v;
+    xc[t] = (T)0;
+    if (t >= 2 * WWc && t < 3 * WWc && clsc[t] == K_INT) gs = (double)v;
+  }
+  const int b0 = 2 * WWc / TPB;
+  if ((int)blockIdx.x >= b0) {  // the same for the whole block
+    gs = block_sum(gs);
+    if (threadIdx.x == 0) gpart[blockIdx.x - b0] = gs;
+  }
 }
 // restriction of a stored residual (and, when xc is given, the zero initial guess of the coarse correction)
 template <typename TF, typename TC>
@@ -1593,7 +1630,7 @@ static void relax(Ctx *ctx, int l) {
         G.g_dtau, G.wg_rows, G.nwg, ctx->prm.bnd_sweeps, ctx->prm.lambda_ghost);
     const int nfb = 1 + std::min(64, (G.nregw + BAND_T - 1) / BAND_T);
     k_band_sec_fin<T><<<nfb, BAND_T, 0, s>>>(G.reg_pt, G.nregw, G.sec_out, V.x, G.WW, G.h, G.f_code, G.f_loc, G.nf,
-                                             ctx->d_lev + l, G.d_mp);
+                                             ctx->gs_ptr[l], ctx->gs_n[l], G.d_mp);
     return;
   }
   if (band && G.nband >= ctx->band_split_min) {
@@ -1623,7 +1660,7 @@ static void relax(Ctx *ctx, int l) {
       }
       if (G.ng) sweeps();
     }
-    k_xi_faces<T><<<1, BAND_T, 0, s>>>(G.WW, G.h, V.x, G.f_code, G.nf, ctx->d_lev + l, G.d_mp);
+    k_xi_faces<T><<<1, BAND_T, 0, s>>>(G.WW, G.h, V.x, G.f_code, G.nf, ctx->gs_ptr[l], ctx->gs_n[l], G.d_mp);
     return;
   }
   const size_t with_nv = band_lds_bytes(1, lds_bytes, G.nbg, G.nband);
@@ -1644,7 +1681,7 @@ static void relax(Ctx *ctx, int l) {
     kern<<<1 + nwb, BAND_T, band_lds_bytes(mode, lds_bytes, G.nbg, G.nband), s>>>(G.N, G.W, BK, V.x, V.b, bo, G.bbox, G.bcap, G.reg_pt, G.nreg, G.nregw, G.bg_k,
                                           G.bg_loc, G.bg_w, G.bg_dt, G.nbg, G.gcap, G.g_pt, G.g_col, G.g_w, G.g_dtau,
                                           G.wg_rows, G.nwg, ctx->prm.bnd_sweeps, ctx->prm.lambda_ghost, G.f_code, G.f_loc,
-                                          G.nf, ctx->d_lev + l, G.d_mp);
+                                          G.nf, ctx->gs_ptr[l], ctx->gs_n[l], G.d_mp);
     return;
   }
   if (band && G.ng <= 4 * GH_T) {
@@ -1657,13 +1694,15 @@ static void relax(Ctx *ctx, int l) {
       k_band_sweeps<T><<<1, BAND_T, 0, s>>>(G.N, G.W, BK, G.cls, V.x, V.b, G.band, G.d_band_off, G.g_pt, G.g_col,
                                             G.g_w, G.g_dtau, G.ng, ctx->gtmp, ctx->prm.bnd_sweeps, ctx->prm.lambda_ghost, 0);
   }
-  k_xi_faces<T><<<1, BAND_T, 0, s>>>(G.WW, G.h, V.x, G.f_code, G.nf, ctx->d_lev + l, G.d_mp);
+  k_xi_faces<T><<<1, BAND_T, 0, s>>>(G.WW, G.h, V.x, G.f_code, G.nf, ctx->gs_ptr[l], ctx->gs_n[l], G.d_mp);
 }
 
 // sum of the continuity right-hand sides of level l (read by the xi updates of its relaxation steps)
 template <typename T>
 static void gsum(Ctx *ctx, int l) {
   Geo &G = ctx->geo[l];
+  ctx->gs_ptr[l] = ctx->d_lev + l;
+  ctx->gs_n[l] = 1;
   k_gsum<T><<<rd_blocks(G.WW), RD_T, 0, ctx->stream>>>(G.W, G.h, G.cls, vec<T>(ctx, l).x, vec<T>(ctx, l).b, ctx->d_red, ctx->d_ticket,
                                          ctx->d_lev + l);
 }
@@ -1779,9 +1818,10 @@ static void cycle(Ctx *ctx, int l) {
     const double a = coef_a(ctx, l), d = 1.0 + 4.0 * a;
     if (F.ng) k_resid_ghost<T><<<nblk(F.ng), TPB, 0, s>>>(F.g_pt, F.g_col, F.g_w, F.ng, VF.x, VF.b, VF.r, nullptr);
     k_resid_restrict<T><<<nblk(3L * C.WW + 1), TPB, 0, s>>>(F.N, F.W, F.h, a, d, F.cls, VF.x, VF.b, VF.r, C.N, C.W, C.cls,
-                                                          VC.b, VC.x);
+                                                          VC.b, VC.x, ctx->d_gpart + C.gp_off);
+    ctx->gs_ptr[l + 1] = ctx->d_gpart + C.gp_off;
+    ctx->gs_n[l + 1] = C.gp_n;
   }
-  if (l + 1 < ctx->L - 1) gsum<T>(ctx, l + 1);
   int reps = (l + 1 == ctx->L - 1) ? 1 : ctx->prm.gamma;
   for (int q = 0; q < reps; q++) cycle<T>(ctx, l + 1);
   if (C.ne) k_ext_fill<T><<<nblk(C.ne), TPB, 0, s>>>(C.e_pt, C.e_src, C.e_w, C.ne, VC.x);
