@@ -155,6 +155,8 @@ void gp_destroy(gp_ctx *ctx) {
     dfree(G.wg_rows);
     dfree(G.f_code);
     dfree(G.f_loc);
+    dfree(G.g_rowof);
+    dfree(G.e_rowof);
     dfree(ctx->v64[l].x);
     dfree(ctx->v64[l].b);
     dfree(ctx->v64[l].r);
@@ -306,6 +308,8 @@ gp_status gp_setup_grid(gp_ctx **out, int N, double Re, const gp_params *prm, vo
       ALLOC(G.sec_gk, (size_t)G.sec_gcap);
     }
     ALLOC(G.f_loc, (size_t)G.fcap);
+    ALLOC(G.g_rowof, (size_t)G.n);
+    ALLOC(G.e_rowof, (size_t)G.n);
     ALLOC(ctx->v64[l].x, (size_t)G.n);
     ALLOC(ctx->v64[l].b, (size_t)G.n);
     ALLOC(ctx->v64[l].r, (size_t)G.n);

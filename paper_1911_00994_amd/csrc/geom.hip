@@ -1217,7 +1217,9 @@ static gp_status build_level(Ctx *ctx, int l) {
   if (G.ne) {
     k_ext_rows<<<nblk(G.ne), TPB, 0, s>>>(L, G.cls, W, G.e_pt, G.ne, G.e_src, G.e_w);
     k_ext_fail<<<nblk(G.ne), TPB, 0, s>>>(G.cls, G.e_pt, G.ne, G.e_src);
+    k_row_of<<<nblk(G.ne), TPB, 0, s>>>(G.e_pt, G.ne, G.e_rowof);
   }
+  if (G.ng) k_row_of<<<nblk(G.ng), TPB, 0, s>>>(G.g_pt, G.ng, G.g_rowof);
   GP_HIP(hipMemsetAsync(G.d_mp, 0, sizeof(int), s));
   k_count_mp<<<nblk(W * W), TPB, 0, s>>>(G.cls, W, G.d_mp);
   // boundary band: cells grouped by colour, ascending cell index within a colour

@@ -78,6 +78,8 @@ struct Geo {
   int sec_pcap = 0, sec_bcap = 0, sec_gcap = 0, sec_rcap = 0;
   int colr_ok = 0;                  // 1 when g_colr holds the row of every ghost column
   int gp_off = 0, gp_n = 0;         // this level's block partials of G in Ctx::d_gpart (written by the restriction)
+  // row of each ghost point in g_pt and of each extension point in e_pt (3 W^2 + 1 entries; others undefined)
+  int *g_rowof = nullptr, *e_rowof = nullptr;
   // faces on the boundary of the internal pressure cells, cell-major order: code = 2 * (u or v index) + (1 if the
   // face enters the cell's divergence with a minus sign); f_loc = the same face as an LDS band-region entry
   int *f_code = nullptr, *f_loc = nullptr;

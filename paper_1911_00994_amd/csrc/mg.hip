@@ -1154,23 +1154,30 @@ __device__ __forceinline__ double restrict_value(int Nf, int Wf, const uint8_t *
                                                  int Nc, int Wc, const uint8_t *__restrict__ clsc, int t) {
   return restrict_core(Nf, Wf, clsf, Nc, Wc, clsc, t, [&](int kf, uint8_t) { return (double)rf[kf]; });
 }
-// residual and restriction in one pass: the residual of an internal fine row is formed where the restriction
-// needs it (rounded to T, as the stored residual would be); ghost and wall-ghost residuals come from rf, written
-// before by k_resid_ghost.  Also the zero initial guess of the coarse correction, and the coarse level's G (see
+// residual and restriction in one pass: the residual of an internal, ghost or wall-ghost fine row is formed where
+// the restriction needs it (rounded to T, as the stored residual would be; growof: the ghost row of each ghost
+// point, whose residual is formed as in k_resid_ghost).  Also the zero initial guess of the coarse correction,
+// and the coarse level's G (see
 // gp_start) as block partials: gpart[block - b0] = the sum of the restricted continuity right-hand sides of the
 // block's internal cells, for the blocks b0 = 2 Wc^2 / TPB and on (those holding pressure entries; with x = 0
 // the wall Dirichlet faces add nothing).
 template <typename T>
 __global__ void __launch_bounds__(TPB) k_resid_restrict(int Nf, int Wf, double h, double a, double d,
                                                         const uint8_t *__restrict__ clsf, const T *__restrict__ xf,
-                                                        const T *__restrict__ bf, const T *__restrict__ rf, int Nc, int Wc,
-                                                        const uint8_t *__restrict__ clsc, T *__restrict__ bc,
-                                                        T *__restrict__ xc, double *__restrict__ gpart) {
+                                                        const T *__restrict__ bf, const int *__restrict__ growof,
+                                                        const int *__restrict__ gcol, const double *__restrict__ gw,
+                                                        int Nc, int Wc, const uint8_t *__restrict__ clsc,
+                                                        T *__restrict__ bc, T *__restrict__ xc, double *__restrict__ gpart) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x, WWc = Wc * Wc;
   double gs = 0;
   if (t <= 3 * WWc) {
-    const T v = (T)restrict_core(Nf, Wf, clsf, Nc, Wc, clsc, t, [&](int kf, uint8_t cc) {
-      return cc == K_INT ? (double)(T)resid_point<T>(Wf, h, a, d, clsf, xf, bf, kf) : (double)rf[kf];
+    const T v = (T)restrict_core(Nf, Wf, clsf, Nc, Wc, clsc, t, [&](int kf, uint8_t cc) -> double {
+      if (cc == K_INT) return (double)(T)resid_point<T>(Wf, h, a, d, clsf, xf, bf, kf);
+      const int r = growof[kf];
+      double sw = 0;
+#pragma unroll
+      for (int z = 0; z < 9; z++) sw += gw[9 * r + z] * (double)xf[gcol[9 * r + z]];
+      return (double)(T)((double)bf[kf] - sw);
     });
     bc[t] = v;
     xc[t] = (T)0;
@@ -1193,7 +1200,7 @@ __global__ void __launch_bounds__(TPB) k_restrict(int Nf, int Wf, const uint8_t 
   if (xc) xc[t] = (TC)0;
 }
 
-// extension values: quadratic extrapolation from the sources
+// extension values: quadratic extrapolation from the sources (Sect. 4.3)
 template <typename T>
 __global__ void k_ext_fill(const int *__restrict__ e_pt, const int *__restrict__ e_src, const double *__restrict__ e_w, int ne,
                            T *__restrict__ x) {
@@ -1205,14 +1212,13 @@ __global__ void k_ext_fill(const int *__restrict__ e_pt, const int *__restrict__
   x[e_pt[e]] = (T)v;
 }
 
-// bilinear prolongation of the coarse correction to fine internal and ghost points, x += e (Sect. 4.3)
 // bilinear prolongation of the coarse correction to fine entry t (internal, ghost, extrapolated and wall-ghost
-// points and xi; 0 elsewhere), coarse pressure mirrored outside the box
-template <typename TC>
+// points and xi; 0 elsewhere), coarse pressure mirrored outside the box (Sect. 4.3); xcv(kc) is the coarse value
+template <typename XV>
 __device__ __forceinline__ double prolong_value(int Nf, int Wf, const uint8_t *__restrict__ clsf, int Nc, int Wc,
-                                                const TC *__restrict__ xc, int t) {
+                                                XV xcv, int t) {
   const int WWf = Wf * Wf, WWc = Wc * Wc;
-  if (t == 3 * WWf) return (double)xc[3 * WWc];
+  if (t == 3 * WWf) return xcv(3 * WWc);
   uint8_t c = clsf[t];
   if (!(c == K_INT || c == K_GHOST || c == K_GHOSTX || c == K_WALLG)) return 0.0;
   int g = t / WWf, q = t - g * WWf, j = q / Wf - 1, i = q % Wf - 1;
@@ -1274,16 +1280,29 @@ __device__ __forceinline__ double prolong_value(int Nf, int Wf, const uint8_t *_
         jc = jc < 0 ? 0 : (jc > Nc - 1 ? Nc - 1 : jc);
       }
       if (ic < -1 || ic > Nc || jc < -1 || jc > Nc) continue;
-      e += xw[bb] * yw[aa] * (double)xc[g * WWc + pidx(Wc, ic, jc)];
+      e += xw[bb] * yw[aa] * xcv(g * WWc + pidx(Wc, ic, jc));
     }
   return e;
 }
+// With erow, the coarse extension points take their extrapolation from the sources here, rounded to TC as
+// k_ext_fill stores it (erow: the extension row of each such point); without, xc already holds them.  The
+// class test costs more than the k_ext_fill launch on the largest fine levels (PROLONG_EXT_INLINE_MAX cells).
+constexpr long PROLONG_EXT_INLINE_MAX = 1L << 19;
 template <typename TC, typename TF>
 __global__ void __launch_bounds__(TPB) k_prolong(int Nf, int Wf, const uint8_t *__restrict__ clsf, TF *__restrict__ xf,
-                                                 int Nc, int Wc, const TC *__restrict__ xc) {
+                                                 int Nc, int Wc, const TC *__restrict__ xc, const uint8_t *__restrict__ clsc,
+                                                 const int *__restrict__ erow, const int *__restrict__ esrc,
+                                                 const double *__restrict__ ew) {
   int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t > 3 * Wf * Wf) return;
-  double e = prolong_value<TC>(Nf, Wf, clsf, Nc, Wc, xc, t);
+  const double e = prolong_value(Nf, Wf, clsf, Nc, Wc, [&](int kc) -> double {
+    if (erow && clsc[kc] == K_EXT) {
+      const int r = erow[kc];
+      return (double)(TC)(ew[3 * r] * (double)xc[esrc[3 * r]] + ew[3 * r + 1] * (double)xc[esrc[3 * r + 1]] +
+                          ew[3 * r + 2] * (double)xc[esrc[3 * r + 2]]);
+    }
+    return (double)xc[kc];
+  }, t);
   if (e != 0.0 || t == 3 * Wf * Wf) xf[t] = (TF)((double)xf[t] + e);
 }
 
@@ -1509,7 +1528,7 @@ __global__ void __launch_bounds__(SC_T) k_small_cycle(SmallCycle P, T *xg, const
     }
     __syncthreads();
     for (int t = tid; t <= 3 * L.W * L.W; t += SC_T) {
-      double e = prolong_value<T>(L.N, L.W, C(m), Cl.N, Cl.W, xc, t);
+      double e = prolong_value(L.N, L.W, C(m), Cl.N, Cl.W, [&](int kc) -> double { return (double)xc[kc]; }, t);
       if (e != 0.0 || t == 3 * L.W * L.W) X(m)[t] = (T)((double)X(m)[t] + e);
     }
     __syncthreads();
@@ -1816,16 +1835,17 @@ static void cycle(Ctx *ctx, int l) {
   for (int q = 0; q < ctx->prm.nu1; q++) relax<T>(ctx, l);
   {
     const double a = coef_a(ctx, l), d = 1.0 + 4.0 * a;
-    if (F.ng) k_resid_ghost<T><<<nblk(F.ng), TPB, 0, s>>>(F.g_pt, F.g_col, F.g_w, F.ng, VF.x, VF.b, VF.r, nullptr);
-    k_resid_restrict<T><<<nblk(3L * C.WW + 1), TPB, 0, s>>>(F.N, F.W, F.h, a, d, F.cls, VF.x, VF.b, VF.r, C.N, C.W, C.cls,
-                                                          VC.b, VC.x, ctx->d_gpart + C.gp_off);
+    k_resid_restrict<T><<<nblk(3L * C.WW + 1), TPB, 0, s>>>(F.N, F.W, F.h, a, d, F.cls, VF.x, VF.b, F.g_rowof, F.g_col,
+                                                          F.g_w, C.N, C.W, C.cls, VC.b, VC.x, ctx->d_gpart + C.gp_off);
     ctx->gs_ptr[l + 1] = ctx->d_gpart + C.gp_off;
     ctx->gs_n[l + 1] = C.gp_n;
   }
   int reps = (l + 1 == ctx->L - 1) ? 1 : ctx->prm.gamma;
   for (int q = 0; q < reps; q++) cycle<T>(ctx, l + 1);
-  if (C.ne) k_ext_fill<T><<<nblk(C.ne), TPB, 0, s>>>(C.e_pt, C.e_src, C.e_w, C.ne, VC.x);
-  k_prolong<T, T><<<nblk(3L * F.WW + 1), TPB, 0, s>>>(F.N, F.W, F.cls, VF.x, C.N, C.W, VC.x);
+  const bool ext_inline = (long)F.N * F.N <= PROLONG_EXT_INLINE_MAX;
+  if (C.ne && !ext_inline) k_ext_fill<T><<<nblk(C.ne), TPB, 0, s>>>(C.e_pt, C.e_src, C.e_w, C.ne, VC.x);
+  k_prolong<T, T><<<nblk(3L * F.WW + 1), TPB, 0, s>>>(F.N, F.W, F.cls, VF.x, C.N, C.W, VC.x, C.cls,
+                                                     C.ne && ext_inline ? C.e_rowof : nullptr, C.e_src, C.e_w);
   for (int q = 0; q < ctx->prm.nu2; q++) relax<T>(ctx, l);
 }
 
@@ -1927,7 +1947,8 @@ gp_status time_kernel(Ctx *ctx, int which, int l, int reps, double *avg_us) {
     } else if (which == 3 && l + 1 < ctx->L) {
       Geo &C = ctx->geo[l + 1];
       k_fill<double><<<nblk(C.n), TPB, 0, s>>>(ctx->v64[l + 1].x, C.n, 0.0);  // zero correction: x unchanged
-      k_prolong<double, double><<<nblk(3L * G.WW + 1), TPB, 0, s>>>(G.N, G.W, G.cls, V.x, C.N, C.W, ctx->v64[l + 1].x);
+      k_prolong<double, double><<<nblk(3L * G.WW + 1), TPB, 0, s>>>(G.N, G.W, G.cls, V.x, C.N, C.W, ctx->v64[l + 1].x,
+                                                                    C.cls, C.ne ? C.e_rowof : nullptr, C.e_src, C.e_w);
       launches++;
     } else if (which == 4) {
       relax_ghost_only(ctx, l);
