@@ -824,9 +824,9 @@ __device__ double block_sum(double v) {
 }
 
 // The reductions of whole levels below run on at most RD_B workgroups of RD_T threads, each thread with RD_U
-// elements' loads in flight: the ticket of last_block_total costs one contended atomic (and a fence) per
-// workgroup, which at 512 workgroups took longer than reading the data.
-constexpr int RD_T = 1024, RD_B = 64, RD_U = 4;
+// elements' loads in flight: the ticket (rd_last_total) costs one contended atomic and a fence per workgroup,
+// which with 512 workgroups of 256 threads took longer than reading the data.
+constexpr int RD_T = 1024, RD_B = 128, RD_U = 8;
 static inline int rd_blocks(long n) {
   return (int)std::max(1L, std::min((long)RD_B, (n + (long)RD_T * RD_U - 1) / ((long)RD_T * RD_U)));
 }
@@ -960,7 +960,7 @@ __global__ void __launch_bounds__(TPB) k_resid_pts(int N, int W, double h, doubl
 }
 // residual of the point rows, one point per thread in the first nbp blocks, and of the ghost rows (pt, col, w:
 // ng rows of nine columns), one row per thread in the blocks after them (the point blocks leave those points'
-// entries to them); each block leaves the largest |residual| (as the bits of the double, which order like the
+// entries to them), stored in r when store is set (an FP64 solve needs only the norm); each block leaves the largest |residual| (as the bits of the double, which order like the
 // values; NaN above everything) in part[gridDim + block] and its sum of the internal pressures in part[block],
 // for k_resid_mean_row (no atomics and no grid-wide fence: the kernel writes the whole residual)
 template <typename T>
@@ -968,7 +968,7 @@ __global__ void __launch_bounds__(TPB) k_resid_pts_norm(int W, double h, double 
                                                         const uint8_t *__restrict__ cls, const T *__restrict__ x,
                                                         const T *__restrict__ b, T *__restrict__ r, int nbp,
                                                         const int *__restrict__ pt, const int *__restrict__ col,
-                                                        const double *__restrict__ w, int ng, double *part) {
+                                                        const double *__restrict__ w, int ng, double *part, int store) {
   __shared__ unsigned long long sm[TPB / 64];
   const int WW = W * W;
   double res = 0, ps = 0;
@@ -978,7 +978,7 @@ __global__ void __launch_bounds__(TPB) k_resid_pts_norm(int W, double h, double 
       const uint8_t c = cls[t];
       if (c != K_GHOST && c != K_GHOSTX && c != K_WALLG) {
         res = resid_point<T>(W, h, a, d, cls, x, b, t);
-        r[t] = (T)res;
+        if (store) r[t] = (T)res;
         if (t >= 2 * WW && c == K_INT) ps += (double)x[t];
       }
     }
@@ -990,7 +990,7 @@ __global__ void __launch_bounds__(TPB) k_resid_pts_norm(int W, double h, double 
 #pragma unroll
       for (int z = 0; z < 9; z++) sw += w[9 * q + z] * (double)x[col[9 * q + z]];
       res = (double)b[k] - sw;
-      r[k] = (T)res;
+      if (store) r[k] = (T)res;
     }
   }
   unsigned long long m = (unsigned long long)__double_as_longlong(fabs(res));
@@ -1727,7 +1727,7 @@ static void gsum(Ctx *ctx, int l) {
 }
 
 template <typename T>
-static void residual(Ctx *ctx, int l, unsigned long long *rmax, unsigned long long *hmax = nullptr) {
+static void residual(Ctx *ctx, int l, unsigned long long *rmax, unsigned long long *hmax = nullptr, bool store = true) {
   Geo &G = ctx->geo[l];
   Vec<T> &V = vec<T>(ctx, l);
   hipStream_t s = ctx->stream;
@@ -1736,7 +1736,7 @@ static void residual(Ctx *ctx, int l, unsigned long long *rmax, unsigned long lo
     // two partials per block in d_red (2 (nblk(3 (N+2)^2) + nblk(gcap)) + 16 slots)
     const int nbp = nblk(3L * G.WW), nb = nbp + (G.ng ? nblk(G.ng) : 0);
     k_resid_pts_norm<T><<<nb, TPB, 0, s>>>(G.W, G.h, a, d, G.cls, V.x, V.b, V.r, nbp, G.g_pt, G.g_col, G.g_w, G.ng,
-                                           ctx->d_red);
+                                           ctx->d_red, store ? 1 : 0);
     k_resid_mean_row<T><<<1, RM_T, 0, s>>>(ctx->d_red, nb, G.d_mp, V.r + 3L * G.WW, rmax, hmax);
   } else {
     k_resid_pts<T><<<nblk(3L * G.WW), TPB, 0, s>>>(G.N, G.W, G.h, a, d, G.cls, V.x, V.b, V.r, nullptr);
@@ -1862,9 +1862,9 @@ static void mean_project(Ctx *ctx) {
 // one also stores the norm there; wait_norm polls the slot, and now and then the stream, so that a failed launch
 // ends the wait (once the stream is idle the store has landed; else the device copy is read).
 constexpr unsigned long long NORM_PENDING = ~0ull;
-static void norm_launch(Ctx *ctx) {
+static void norm_launch(Ctx *ctx, bool store = true) {
   __atomic_store_n(ctx->h_rmax, NORM_PENDING, __ATOMIC_RELEASE);
-  residual<double>(ctx, 0, (unsigned long long *)(ctx->d_scal + 1), ctx->h_rmax);
+  residual<double>(ctx, 0, (unsigned long long *)(ctx->d_scal + 1), ctx->h_rmax, store);
 }
 static gp_status wait_norm(Ctx *ctx, double *out) {
   unsigned long long v = NORM_PENDING;
@@ -2083,7 +2083,7 @@ static void iteration_launches(Ctx *ctx, int precision) {
   } else {
     refine_step(ctx, ctx->prm.mixed_inner_cycles);
   }
-  residual<double>(ctx, 0, (unsigned long long *)(ctx->d_scal + 1), ctx->h_rmax);
+  residual<double>(ctx, 0, (unsigned long long *)(ctx->d_scal + 1), ctx->h_rmax, precision != GP_FP64);
 }
 
 static gp_status capture_iteration(Ctx *ctx, int precision) {
@@ -2166,7 +2166,7 @@ gp_status mg_solve(Ctx *ctx, int precision, double tol, int max_cycles, gp_stats
       } else {
         cycle<double>(ctx, 0);
         mean_project<double>(ctx);
-        norm_launch(ctx);
+        norm_launch(ctx, false);  // the cycles form their own residuals; only the norm is needed
         GP_HIP(hipGetLastError());
         if (ahead && c + 1 < max_cycles) queue_head(ctx, thr, lim);
         GP_HIP(hipGetLastError());
