@@ -189,6 +189,16 @@ void gp_destroy(gp_ctx *ctx) {
   dfree(ctx->d_bcnt);
   dfree(ctx->d_iscr);
   dfree(ctx->d_flags);
+  for (int l = 0; l < MAXLEV; l++) {
+    BuildRes &B = ctx->bres[l];
+    if (B.ev) (void)hipEventDestroy(B.ev);
+    if (l == 0) continue;
+    dfree(B.flags);
+    dfree(B.bcnt);
+    dfree(B.iscr);
+    dfree(B.red);
+    if (B.s) (void)hipStreamDestroy(B.s);
+  }
   dfree(ctx->c_map);
   dfree(ctx->c_A);
   dfree(ctx->c_B);
@@ -349,6 +359,26 @@ gp_status gp_setup_grid(gp_ctx **out, int N, double Re, const gp_params *prm, vo
   ALLOC(ctx->d_bcnt, (size_t)8 * nblk((long)(N + 2) * (N + 2)) + 16);  // two scans of 3 (N+2)^2 points, or 5 colours
   ALLOC(ctx->d_iscr, (size_t)3 * (N + 2) * (N + 2) + 1);
   ALLOC(ctx->d_flags, 16);
+  // geometry build resources: level 0 the context's own, the others a stream, event and scratch each
+  GP_HIP(hipGetDevice(&ctx->device));
+  for (int l = 0; l < L; l++) {
+    BuildRes &B = ctx->bres[l];
+    GP_HIP(hipEventCreateWithFlags(&B.ev, hipEventDisableTiming));
+    if (l == 0) {
+      B.s = ctx->stream;
+      B.flags = ctx->d_flags;
+      B.bcnt = ctx->d_bcnt;
+      B.iscr = ctx->d_iscr;
+      B.red = ctx->d_red;
+      continue;
+    }
+    const long WWl = (long)ctx->geo[l].WW;
+    GP_HIP(hipStreamCreate(&B.s));
+    ALLOC(B.flags, 16);
+    ALLOC(B.bcnt, (size_t)8 * nblk(WWl) + 16);
+    ALLOC(B.iscr, (size_t)3 * WWl + 1);
+    ALLOC(B.red, 16);
+  }
   GP_HIP(hipMemsetAsync(ctx->d_ticket, 0, 4 * sizeof(unsigned), ctx->stream));
   GP_HIP(hipMemsetAsync(ctx->d_lev, 0, 2 * MAXLEV * sizeof(double), ctx->stream));
   Geo &C = ctx->geo[L - 1];

@@ -6,6 +6,8 @@
 #include <cmath>
 #include <cstdio>
 
+#include <thread>
+
 #include "internal.h"
 
 namespace gpmg {
@@ -868,6 +870,11 @@ static gp_status read_flags(Ctx *ctx, int *h) {
   GP_HIP(hipStreamSynchronize(ctx->stream));
   return GP_OK;
 }
+static gp_status read_flags(Ctx *ctx, const BuildRes &B, int *h) {
+  GP_HIP(hipMemcpyAsync(h, B.flags, 8 * sizeof(int), hipMemcpyDeviceToHost, B.s));
+  GP_HIP(hipStreamSynchronize(B.s));
+  return GP_OK;
+}
 
 // ---------------------------------------------------------------------------------------------------------
 // angular sectors of a large boundary band (one workgroup each in the band relaxation).  Angles are taken about
@@ -1101,11 +1108,12 @@ __global__ void __launch_bounds__(TPB) k_sec_fill_tabs(const int *band, int nban
 // sectors, a table over its capacity, a sector too large for LDS)
 gp_status sector_build(Ctx *ctx, int l) {
   Geo &G = ctx->geo[l];
-  hipStream_t s = ctx->stream;
+  const BuildRes &B = ctx->bres[l];
+  hipStream_t s = B.s;
   const int W = G.W, nt = G.nband + G.nbg;
   G.sec_S = 0;
-  double *acc = ctx->d_red;  // [0], [1] centre sums, [2] r_min bits
-  int *ic = ctx->d_bcnt;     // int counters
+  double *acc = B.red;  // [0], [1] centre sums, [2] r_min bits
+  int *ic = B.bcnt;     // int counters
   GP_HIP(hipMemsetAsync(acc, 0, 2 * sizeof(double), s));
   GP_HIP(hipMemsetAsync(ic, 0, 4 * sizeof(int), s));
   k_sec_centre<<<nblk(nt), TPB, 0, s>>>(G.band, G.nband, G.N, G.h, G.bg_k, G.bg_loc, G.nbg, G.gcap, G.reg_pt, W, acc, ic);
@@ -1181,17 +1189,18 @@ gp_status sector_build(Ctx *ctx, int l) {
 
 static gp_status build_level(Ctx *ctx, int l) {
   Geo &G = ctx->geo[l];
+  const BuildRes &B = ctx->bres[l];
   Lat L = make_lat(ctx, l);
   int W = G.W, P = 3 * W * W;
-  hipStream_t s = ctx->stream;
+  hipStream_t s = B.s;
   int hf[8];
-  GP_HIP(hipMemsetAsync(ctx->d_flags, 0, 8 * sizeof(int), s));
-  k_classify<<<nblk(P), TPB, 0, s>>>(L, G.cls, W, l == 0, ctx->d_flags);
+  GP_HIP(hipMemsetAsync(B.flags, 0, 8 * sizeof(int), s));
+  k_classify<<<nblk(P), TPB, 0, s>>>(L, G.cls, W, l == 0, B.flags);
   k_seed<<<nblk(P), TPB, 0, s>>>(G.cls, G.N, W);
   for (int it = 0;; it++) {
-    GP_HIP(hipMemsetAsync(ctx->d_flags, 0, sizeof(int), s));
-    k_closure<<<nblk(P), TPB, 0, s>>>(L, G.cls, W, ctx->d_flags);
-    gp_status st = read_flags(ctx, hf);
+    GP_HIP(hipMemsetAsync(B.flags, 0, sizeof(int), s));
+    k_closure<<<nblk(P), TPB, 0, s>>>(L, G.cls, W, B.flags);
+    gp_status st = read_flags(ctx, B, hf);
     if (st) return st;
     if (!hf[0]) break;
     if (it > 64) return GP_EGEOM;
@@ -1199,10 +1208,10 @@ static gp_status build_level(Ctx *ctx, int l) {
   k_ext_mark<<<nblk(P), TPB, 0, s>>>(G.cls, G.N, W, ctx->prm.ext_radius);
   k_body_to_inactive<<<nblk(P), TPB, 0, s>>>(G.cls, P);
   // ghost rows
-  GP_HIP(hipMemsetAsync(ctx->d_flags + 2, 0, 2 * sizeof(int), s));
-  k_compact<<<nblk(P), TPB, 0, s>>>(G.cls, P, 0, G.g_pt, G.gcap, ctx->d_flags + 2);
-  k_compact<<<nblk(P), TPB, 0, s>>>(G.cls, P, 1, G.e_pt, G.ecap, ctx->d_flags + 3);
-  gp_status st = read_flags(ctx, hf);
+  GP_HIP(hipMemsetAsync(B.flags + 2, 0, 2 * sizeof(int), s));
+  k_compact<<<nblk(P), TPB, 0, s>>>(G.cls, P, 0, G.g_pt, G.gcap, B.flags + 2);
+  k_compact<<<nblk(P), TPB, 0, s>>>(G.cls, P, 1, G.e_pt, G.ecap, B.flags + 3);
+  gp_status st = read_flags(ctx, B, hf);
   if (st) return st;
   if (hf[2] > G.gcap || hf[3] > G.ecap) return GP_ENOMEM;
   G.ng = hf[2];
@@ -1212,7 +1221,7 @@ static gp_status build_level(Ctx *ctx, int l) {
   if (G.ng) {
     k_ghost_rows<<<nblk(G.ng), TPB, 0, s>>>(L, G.cls, W, R, ctx->prm.march_max, (int)nbis_d, ctx->prm.cg_min,
                                             ctx->prm.dtau_dir, ctx->prm.dtau_neu_over_h * G.h);
-    k_ghostx_rows<<<nblk(G.ng), TPB, 0, s>>>(L, G.cls, W, R, l == 0, ctx->d_flags);
+    k_ghostx_rows<<<nblk(G.ng), TPB, 0, s>>>(L, G.cls, W, R, l == 0, B.flags);
   }
   if (G.ne) {
     k_ext_rows<<<nblk(G.ne), TPB, 0, s>>>(L, G.cls, W, G.e_pt, G.ne, G.e_src, G.e_w);
@@ -1227,10 +1236,10 @@ static gp_status build_level(Ctx *ctx, int l) {
     int nb = nblk((long)G.N * G.N);
     int hoff[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     if (ctx->prm.bnd_sweeps > 0) {
-      k_band_count<<<nb, TPB, 0, s>>>(G.cls, G.N, W, ctx->prm.bnd_radius, nb, ctx->d_bcnt);
-      k_scan_blocks<<<1, SCAN_T, 0, s>>>(ctx->d_bcnt, 5 * nb);
-      k_band_offsets<<<1, 64, 0, s>>>(ctx->d_bcnt, nb, G.d_band_off);
-      k_band_fill<<<nb, TPB, 0, s>>>(G.cls, G.N, W, ctx->prm.bnd_radius, nb, ctx->d_bcnt, G.band);
+      k_band_count<<<nb, TPB, 0, s>>>(G.cls, G.N, W, ctx->prm.bnd_radius, nb, B.bcnt);
+      k_scan_blocks<<<1, SCAN_T, 0, s>>>(B.bcnt, 5 * nb);
+      k_band_offsets<<<1, 64, 0, s>>>(B.bcnt, nb, G.d_band_off);
+      k_band_fill<<<nb, TPB, 0, s>>>(G.cls, G.N, W, ctx->prm.bnd_radius, nb, B.bcnt, G.band);
       GP_HIP(hipGetLastError());
       GP_HIP(hipMemcpyAsync(hoff, G.d_band_off, 6 * sizeof(int), hipMemcpyDeviceToHost, s));
       GP_HIP(hipStreamSynchronize(s));
@@ -1244,21 +1253,21 @@ static gp_status build_level(Ctx *ctx, int l) {
   if (G.nband > 0 && G.nband <= G.bcap) {
     const int P3 = 3 * W * W, nbr = nblk(P3);
     const int regcap = G.gcap * 12 + 32 * G.N + 4096;
-    int *cnt2 = ctx->d_bcnt + nbr + 1;  // block counts of the read-only points
+    int *cnt2 = B.bcnt + nbr + 1;  // block counts of the read-only points
     k_region_clear<<<nblk(P3 + 1), TPB, 0, s>>>(G.reg_map, P3 + 1);
     k_region_mark_reads<<<nblk(G.nband + G.ng), TPB, 0, s>>>(G.cls, G.N, W, G.band, G.nband, G.g_pt, G.g_col, G.ng,
                                                              G.reg_map);
     k_region_mark<<<nblk(G.nband + G.ng), TPB, 0, s>>>(G.cls, G.N, W, G.band, G.nband, G.g_pt, G.ng, G.reg_map);
     // the written points, then the read-only points after them
-    k_pred_count<<<nbr, TPB, 0, s>>>(0, P3, G.reg_map, G.cls, ctx->d_bcnt);
-    k_scan_blocks<<<1, SCAN_T, 0, s>>>(ctx->d_bcnt, nbr);
-    k_pred_fill<<<nbr, TPB, 0, s>>>(0, P3, G.reg_map, G.cls, ctx->d_bcnt, regcap, G.reg_pt, nullptr);
+    k_pred_count<<<nbr, TPB, 0, s>>>(0, P3, G.reg_map, G.cls, B.bcnt);
+    k_scan_blocks<<<1, SCAN_T, 0, s>>>(B.bcnt, nbr);
+    k_pred_fill<<<nbr, TPB, 0, s>>>(0, P3, G.reg_map, G.cls, B.bcnt, regcap, G.reg_pt, nullptr);
     k_pred_count<<<nbr, TPB, 0, s>>>(2, P3, G.reg_map, G.cls, cnt2);
     k_scan_blocks<<<1, SCAN_T, 0, s>>>(cnt2, nbr);
-    k_pred_fill<<<nbr, TPB, 0, s>>>(2, P3, G.reg_map, G.cls, cnt2, regcap, G.reg_pt, ctx->d_bcnt + nbr);
+    k_pred_fill<<<nbr, TPB, 0, s>>>(2, P3, G.reg_map, G.cls, cnt2, regcap, G.reg_pt, B.bcnt + nbr);
     GP_HIP(hipGetLastError());
     int nr = 0;
-    GP_HIP(hipMemcpyAsync(&G.nregw, ctx->d_bcnt + nbr, sizeof(int), hipMemcpyDeviceToHost, s));
+    GP_HIP(hipMemcpyAsync(&G.nregw, B.bcnt + nbr, sizeof(int), hipMemcpyDeviceToHost, s));
     GP_HIP(hipMemcpyAsync(&nr, cnt2 + nbr, sizeof(int), hipMemcpyDeviceToHost, s));
     GP_HIP(hipStreamSynchronize(s));
     // the read-only points are staged too when they fit (FP64 values, and the body ghost rows' new values and
@@ -1270,28 +1279,28 @@ static gp_status build_level(Ctx *ctx, int l) {
                                      ctx->max_lds);
     G.nreg = rd ? G.nregw + nr : G.nregw;
     if (G.nreg <= regcap) {
-      GP_HIP(hipMemsetAsync(ctx->d_flags + 10, 0, 2 * sizeof(int), s));
+      GP_HIP(hipMemsetAsync(B.flags + 10, 0, 2 * sizeof(int), s));
       k_region_slots<<<nblk(G.nreg), TPB, 0, s>>>(G.reg_pt, G.nreg, G.reg_map);
       k_region_boxes<<<nblk(G.nband), TPB, 0, s>>>(G.cls, G.N, W, G.band, G.nband, G.reg_map, G.bcap, G.bbox,
-                                                   ctx->d_flags + 11);
+                                                   B.flags + 11);
       // body ghost rows in point order
-      k_pred_count<<<nbr, TPB, 0, s>>>(1, P3, G.reg_map, G.cls, ctx->d_bcnt);
-      k_scan_blocks<<<1, SCAN_T, 0, s>>>(ctx->d_bcnt, nbr);
-      k_pred_fill<<<nbr, TPB, 0, s>>>(1, P3, G.reg_map, G.cls, ctx->d_bcnt, G.gcap, G.bg_k, nullptr);
-      if (G.ng) k_row_of<<<nblk(G.ng), TPB, 0, s>>>(G.g_pt, G.ng, ctx->d_iscr);
+      k_pred_count<<<nbr, TPB, 0, s>>>(1, P3, G.reg_map, G.cls, B.bcnt);
+      k_scan_blocks<<<1, SCAN_T, 0, s>>>(B.bcnt, nbr);
+      k_pred_fill<<<nbr, TPB, 0, s>>>(1, P3, G.reg_map, G.cls, B.bcnt, G.gcap, G.bg_k, nullptr);
+      if (G.ng) k_row_of<<<nblk(G.ng), TPB, 0, s>>>(G.g_pt, G.ng, B.iscr);
       GP_HIP(hipGetLastError());
-      GP_HIP(hipMemcpyAsync(&G.nbg, ctx->d_bcnt + nbr, sizeof(int), hipMemcpyDeviceToHost, s));
+      GP_HIP(hipMemcpyAsync(&G.nbg, B.bcnt + nbr, sizeof(int), hipMemcpyDeviceToHost, s));
       GP_HIP(hipStreamSynchronize(s));
       if (G.nbg > G.gcap) return GP_ENOMEM;
       if (G.nbg)
-        k_region_rows<<<nblk(G.nbg), TPB, 0, s>>>(G.cls, G.g_col, G.g_w, G.g_dtau, ctx->d_iscr, G.reg_map, G.nbg, G.gcap,
-                                                  G.bg_k, G.bg_loc, G.bg_w, G.bg_dt, ctx->d_flags + 11);
+        k_region_rows<<<nblk(G.nbg), TPB, 0, s>>>(G.cls, G.g_col, G.g_w, G.g_dtau, B.iscr, G.reg_map, G.nbg, G.gcap,
+                                                  G.bg_k, G.bg_loc, G.bg_w, G.bg_dt, B.flags + 11);
       if (G.ng)
         k_wall_rows<<<nblk(G.ng), TPB, 0, s>>>(G.cls, G.g_pt, G.g_col, G.ng, G.reg_map, G.nregw, G.wg_rows,
-                                               ctx->d_flags + 10, ctx->d_flags + 11);
+                                               B.flags + 10, B.flags + 11);
       GP_HIP(hipGetLastError());
       int hr[2];
-      GP_HIP(hipMemcpyAsync(hr, ctx->d_flags + 10, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+      GP_HIP(hipMemcpyAsync(hr, B.flags + 10, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
       GP_HIP(hipStreamSynchronize(s));
       G.nwg = hr[0];
       G.lds_ok = hr[1] == 0 ? 1 : 0;
@@ -1304,40 +1313,62 @@ static gp_status build_level(Ctx *ctx, int l) {
   }
   // ghost columns by row (the double-buffered ghost sweeps of the device-wide band path)
   if (G.ng) {
-    GP_HIP(hipMemsetAsync(ctx->d_flags + 12, 0, sizeof(int), s));
-    k_row_of<<<nblk(G.ng), TPB, 0, s>>>(G.g_pt, G.ng, ctx->d_iscr);
-    k_colr<<<nblk(9L * G.ng), TPB, 0, s>>>(G.cls, G.g_pt, G.g_col, G.ng, ctx->d_iscr, G.g_colr, ctx->d_flags + 12);
+    GP_HIP(hipMemsetAsync(B.flags + 12, 0, sizeof(int), s));
+    k_row_of<<<nblk(G.ng), TPB, 0, s>>>(G.g_pt, G.ng, B.iscr);
+    k_colr<<<nblk(9L * G.ng), TPB, 0, s>>>(G.cls, G.g_pt, G.g_col, G.ng, B.iscr, G.g_colr, B.flags + 12);
   }
   // boundary faces of the internal pressure cells (and their band-region entries)
   {
     int nb = nblk((long)G.N * G.N);
-    k_face_count<<<nb, TPB, 0, s>>>(G.cls, G.N, W, ctx->d_bcnt);
-    k_scan_blocks<<<1, SCAN_T, 0, s>>>(ctx->d_bcnt, nb);
-    k_face_fill<<<nb, TPB, 0, s>>>(G.cls, G.N, W, ctx->d_bcnt, G.fcap, G.f_code);
+    k_face_count<<<nb, TPB, 0, s>>>(G.cls, G.N, W, B.bcnt);
+    k_scan_blocks<<<1, SCAN_T, 0, s>>>(B.bcnt, nb);
+    k_face_fill<<<nb, TPB, 0, s>>>(G.cls, G.N, W, B.bcnt, G.fcap, G.f_code);
     GP_HIP(hipGetLastError());
     int cb = 1;
-    GP_HIP(hipMemcpyAsync(&G.nf, ctx->d_bcnt + nb, sizeof(int), hipMemcpyDeviceToHost, s));
-    if (G.ng) GP_HIP(hipMemcpyAsync(&cb, ctx->d_flags + 12, sizeof(int), hipMemcpyDeviceToHost, s));
+    GP_HIP(hipMemcpyAsync(&G.nf, B.bcnt + nb, sizeof(int), hipMemcpyDeviceToHost, s));
+    if (G.ng) GP_HIP(hipMemcpyAsync(&cb, B.flags + 12, sizeof(int), hipMemcpyDeviceToHost, s));
     GP_HIP(hipStreamSynchronize(s));
     G.colr_ok = G.ng > 0 && cb == 0;
     if (G.nf > G.fcap) return GP_ENOMEM;
     if (G.lds_ok && G.nf) k_face_loc<<<nblk(G.nf), TPB, 0, s>>>(G.f_code, G.nf, G.reg_map, G.f_loc);
   }
-  if (l == 0) k_empty_cells<<<nblk(G.N * G.N), TPB, 0, s>>>(G.cls, G.N, W, ctx->d_flags);
+  if (l == 0) k_empty_cells<<<nblk(G.N * G.N), TPB, 0, s>>>(G.cls, G.N, W, B.flags);
   GP_HIP(hipGetLastError());
   GP_HIP(hipMemcpyAsync(&G.mp, G.d_mp, sizeof(int), hipMemcpyDeviceToHost, s));
-  st = read_flags(ctx, hf);
+  st = read_flags(ctx, B, hf);
   if (st) return st;
   if (G.mp == 0) return GP_EGEOM;
   if (l == 0 && (hf[1] || hf[4])) return GP_EGEOM;
   return GP_OK;
 }
 
+// The levels are independent of each other (each samples the level set on its own lattice), so they are built
+// concurrently: level 0 on the context's stream by the calling thread, every other level on a stream of its own
+// by a host thread of its own, each with its own scratch (BuildRes).  Their many small launches and read-backs
+// then overlap instead of adding up.  The context's stream waits for all of them before anything after the build.
 gp_status geometry_build(Ctx *ctx) {
   ctx->have_geom = 0;
-  for (int l = 0; l < ctx->L; l++) {
-    gp_status st = build_level(ctx, l);
-    if (st) return st;
+  const int L = ctx->L;
+  GP_HIP(hipEventRecord(ctx->bres[0].ev, ctx->stream));  // the level set and anything before it
+  for (int l = 1; l < L; l++) GP_HIP(hipStreamWaitEvent(ctx->bres[l].s, ctx->bres[0].ev, 0));
+  std::vector<gp_status> st(L, GP_OK);
+  std::vector<std::thread> th;
+  th.reserve(L);
+  for (int l = 1; l < L; l++)
+    th.emplace_back([ctx, l, &st]() {
+      if (hipSetDevice(ctx->device) != hipSuccess) {
+        st[l] = GP_EHIP;
+        return;
+      }
+      st[l] = build_level(ctx, l);
+    });
+  st[0] = build_level(ctx, 0);
+  for (auto &t : th) t.join();
+  for (int l = 0; l < L; l++)
+    if (st[l]) return st[l];
+  for (int l = 1; l < L; l++) {
+    GP_HIP(hipEventRecord(ctx->bres[l].ev, ctx->bres[l].s));
+    GP_HIP(hipStreamWaitEvent(ctx->stream, ctx->bres[l].ev, 0));
   }
   ctx->have_geom = 1;
   return GP_OK;

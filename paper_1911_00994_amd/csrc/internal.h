@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -119,6 +120,14 @@ struct Tape {
   int ring_head = 0;
 };
 
+// a level's stream, event and scratch for the geometry build (level 0: the context's own)
+struct BuildRes {
+  hipStream_t s = nullptr;
+  hipEvent_t ev = nullptr;
+  int *flags = nullptr, *bcnt = nullptr, *iscr = nullptr;
+  double *red = nullptr;
+};
+
 struct Ctx {
   int N = 0, L = 0;
   double Re = 100, alpha = 0;
@@ -126,6 +135,9 @@ struct Ctx {
   hipStream_t stream = nullptr;
   bool own_stream = false;  // created by the context (the caller passed none)
   std::string hip_err;
+  std::mutex err_mu;
+  int device = 0;                   // the device the context was set up on
+  BuildRes bres[MAXLEV];
   Geo geo[MAXLEV];
   Vec<double> v64[MAXLEV];
   Vec<float> v32[MAXLEV];
@@ -187,14 +199,15 @@ struct Ctx {
   bool head_queued = false, head_probe = false;
 };
 
-// error handling
-#define GP_HIP(call)                                               \
-  do {                                                             \
-    hipError_t e_ = (call);                                        \
-    if (e_ != hipSuccess) {                                        \
-      ctx->hip_err = std::string(#call) + ": " + hipGetErrorString(e_); \
-      return GP_EHIP;                                              \
-    }                                                              \
+// error handling (the message under a lock: the geometry build runs one host thread per level)
+#define GP_HIP(call)                                                      \
+  do {                                                                    \
+    hipError_t e_ = (call);                                               \
+    if (e_ != hipSuccess) {                                               \
+      std::lock_guard<std::mutex> lk_(ctx->err_mu);                       \
+      ctx->hip_err = std::string(#call) + ": " + hipGetErrorString(e_);   \
+      return GP_EHIP;                                                     \
+    }                                                                     \
   } while (0)
 
 inline int nblk(long n) { return (int)((n + TPB - 1) / TPB); }
