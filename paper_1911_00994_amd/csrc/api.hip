@@ -59,8 +59,7 @@ gp_status ensure_coarse(Ctx *ctx) {
 }
 
 gp_status after_geometry(Ctx *ctx) {
-  gp_status st = geometry_build(ctx);
-  ctx->c_ok = 0;
+  gp_status st = geometry_build(ctx);  // also the coarsest inverse where it can (c_ok)
   if (st) return st;
   st = default_boundary_values(ctx);
   if (st) return st;

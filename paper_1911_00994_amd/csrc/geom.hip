@@ -211,13 +211,23 @@ __global__ void k_body_to_inactive(uint8_t *cls, int n) {
 
 // compaction (order does not matter: every consumer of these lists is order independent)
 __global__ void k_compact(const uint8_t *cls, int n, int mode, int *list, int cap, int *counter) {
-  int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= n) return;
-  uint8_t c = cls[t];
-  bool take = (mode == 0) ? (c == K_GHOST || c == K_WALLG) : (c == K_EXT);
-  if (!take) return;
-  int slot = atomicAdd(counter, 1);
-  if (slot < cap) list[slot] = t;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x, lane = threadIdx.x & 63;
+  bool take = false;
+  if (t < n) {
+    const uint8_t c = cls[t];
+    take = (mode == 0) ? (c == K_GHOST || c == K_WALLG) : (c == K_EXT);
+  }
+  // one atomic per wavefront: the lanes that take a slot get consecutive ones
+  const unsigned long long m = __ballot(take);
+  if (!m) return;
+  const int leader = __ffsll((long long)m) - 1;
+  int base = 0;
+  if (lane == leader) base = atomicAdd(counter, __popcll(m));
+  base = __shfl(base, leader, 64);
+  if (take) {
+    const int slot = base + __popcll(m & ((1ull << lane) - 1));
+    if (slot < cap) list[slot] = t;
+  }
 }
 
 // ---------------------------------------------------------------------------------------------------------
@@ -468,9 +478,18 @@ __global__ void k_ext_fail(uint8_t *cls, const int *e_pt, int ne, const int *e_s
 }
 
 __global__ void k_count_mp(const uint8_t *cls, int W, int *mp) {
-  int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= W * W) return;
-  if (cls[2 * W * W + t] == K_INT) atomicAdd(mp, 1);
+  int n = 0;
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < W * W; t += gridDim.x * blockDim.x)
+    n += cls[2 * W * W + t] == K_INT;
+  for (int o = 32; o > 0; o >>= 1) n += __shfl_xor(n, o, 64);
+  __shared__ int sn[TPB / 64];
+  if ((threadIdx.x & 63) == 0) sn[threadIdx.x >> 6] = n;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int c = 0;
+    for (int q = 0; q < TPB / 64; q++) c += sn[q];
+    if (c) atomicAdd(mp, c);
+  }
 }
 
 // finest level: every internal cell needs an internal face (else its box has no velocity unknown)
@@ -1230,7 +1249,7 @@ static gp_status build_level(Ctx *ctx, int l) {
   }
   if (G.ng) k_row_of<<<nblk(G.ng), TPB, 0, s>>>(G.g_pt, G.ng, G.g_rowof);
   GP_HIP(hipMemsetAsync(G.d_mp, 0, sizeof(int), s));
-  k_count_mp<<<nblk(W * W), TPB, 0, s>>>(G.cls, W, G.d_mp);
+  k_count_mp<<<std::min(256, nblk(W * W)), TPB, 0, s>>>(G.cls, W, G.d_mp);
   // boundary band: cells grouped by colour, ascending cell index within a colour
   {
     int nb = nblk((long)G.N * G.N);
@@ -1348,19 +1367,24 @@ static gp_status build_level(Ctx *ctx, int l) {
 // then overlap instead of adding up.  The context's stream waits for all of them before anything after the build.
 gp_status geometry_build(Ctx *ctx) {
   ctx->have_geom = 0;
+  ctx->c_ok = 0;
   const int L = ctx->L;
   GP_HIP(hipEventRecord(ctx->bres[0].ev, ctx->stream));  // the level set and anything before it
   for (int l = 1; l < L; l++) GP_HIP(hipStreamWaitEvent(ctx->bres[l].s, ctx->bres[0].ev, 0));
   std::vector<gp_status> st(L, GP_OK);
   std::vector<std::thread> th;
   th.reserve(L);
-  for (int l = 1; l < L; l++)
-    th.emplace_back([ctx, l, &st]() {
+  for (int l = L - 1; l >= 1; l--)  // the coarsest first: its exact inverse follows its build
+    th.emplace_back([ctx, l, L, &st]() {
       if (hipSetDevice(ctx->device) != hipSuccess) {
         st[l] = GP_EHIP;
         return;
       }
       st[l] = build_level(ctx, l);
+      // the coarsest level: its exact inverse for the current alpha too, while the finer levels still build (a
+      // failure leaves c_ok = 0, and the solver factors again and reports it)
+      if (l == L - 1 && st[l] == GP_OK && ctx->alpha > 0)
+        (void)coarse_factor(ctx, ctx->bres[l]);
     });
   st[0] = build_level(ctx, 0);
   for (auto &t : th) t.join();
@@ -1594,24 +1618,26 @@ __global__ void __launch_bounds__(GJ_T) k_gj_finish(const int *__restrict__ spv,
   for (int c = threadIdx.x; c < n; c += GJ_T) bmap[lab[c]] = map[c];
 }
 
-gp_status coarse_factor(Ctx *ctx) {
+gp_status coarse_factor(Ctx *ctx) { return coarse_factor(ctx, ctx->bres[0]); }
+// on the stream and flags of B (the coarsest level's, when the geometry build factors it early)
+gp_status coarse_factor(Ctx *ctx, const BuildRes &B) {
   int l = ctx->L - 1;
   Geo &G = ctx->geo[l];
   int W = G.W, P = 3 * W * W;
-  hipStream_t s = ctx->stream;
+  hipStream_t s = B.s;
   int *inv = (int *)ctx->c_work;  // scratch (P+1 ints fit easily)
   int *row_of = inv + (P + 1);
-  k_coarse_map<<<1, 1, 0, s>>>(G.cls, P, ctx->c_map, inv, ctx->d_flags + 5);
+  k_coarse_map<<<1, 1, 0, s>>>(G.cls, P, ctx->c_map, inv, B.flags + 5);
   if (G.ng) k_row_of<<<nblk(G.ng), TPB, 0, s>>>(G.g_pt, G.ng, row_of);
   int hf[8];
-  gp_status st = read_flags(ctx, hf);
+  gp_status st = read_flags(ctx, B, hf);
   if (st) return st;
   ctx->nc = hf[5];
   if (ctx->nc > 1024) return GP_EINVAL;
   double a = ctx->alpha / (G.h * G.h), d = 1.0 + 4.0 * a;
   k_coarse_fill<<<nblk(ctx->nc), TPB, 0, s>>>(G.cls, G.N, W, G.h, a, d, ctx->c_map, inv, ctx->nc, row_of, G.g_col, G.g_w,
                                              G.mp, ctx->c_A);
-  GP_HIP(hipMemsetAsync(ctx->d_flags + 6, 0, sizeof(int), s));
+  GP_HIP(hipMemsetAsync(B.flags + 6, 0, sizeof(int), s));
   {
     const int n = ctx->nc;
     int nb = std::min(32, std::max(1, 15000 / n - 1));
@@ -1620,15 +1646,15 @@ gp_status coarse_factor(Ctx *ctx) {
     for (int k0 = 0; k0 < n; k0 += nb) {
       int w = std::min(nb, n - k0);
       size_t lds = ((size_t)w * n + n + w) * sizeof(double);
-      k_gj_panel<<<1, GJ_T, lds, s>>>(Ain, Aout, n, k0, w, spv, perm, ctx->d_flags + 6);
-      k_gj_trail<<<nblk((long)n * n), TPB, 0, s>>>(Ain, Aout, n, k0, w, perm, ctx->d_flags + 6);
+      k_gj_panel<<<1, GJ_T, lds, s>>>(Ain, Aout, n, k0, w, spv, perm, B.flags + 6);
+      k_gj_trail<<<nblk((long)n * n), TPB, 0, s>>>(Ain, Aout, n, k0, w, perm, B.flags + 6);
       std::swap(Ain, Aout);
     }
     ctx->c_inv = Ain;
-    k_gj_finish<<<1, GJ_T, 0, s>>>(spv, n, ctx->c_map, ctx->c_bmap, ctx->d_flags + 6);
+    k_gj_finish<<<1, GJ_T, 0, s>>>(spv, n, ctx->c_map, ctx->c_bmap, B.flags + 6);
   }
   GP_HIP(hipGetLastError());
-  st = read_flags(ctx, hf);
+  st = read_flags(ctx, B, hf);
   if (st) return st;
   if (hf[6]) return GP_EGEOM;
   ctx->c_ok = 1;

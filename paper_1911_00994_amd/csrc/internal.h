@@ -217,6 +217,7 @@ gp_status geometry_build(Ctx *ctx);
 gp_status levelset_analytic(Ctx *ctx, const gp_shape *shape, double t, const gp_rigid *mo);
 gp_status default_boundary_values(Ctx *ctx);
 gp_status coarse_factor(Ctx *ctx);
+gp_status coarse_factor(Ctx *ctx, const BuildRes &B);
 gp_status sector_build(Ctx *ctx, int l);
 
 // multigrid (mg.hip)
