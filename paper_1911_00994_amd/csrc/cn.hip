@@ -52,25 +52,44 @@ __global__ void k_conv_lap(int N, int W, double h, const uint8_t *__restrict__ c
   if (lv) lv[t] = lvv;
 }
 
-__device__ __forceinline__ void bmax(unsigned long long *m, double v) {
-  atomicMax(m, (unsigned long long)__double_as_longlong(fabs(v)));
+// the largest |v| of a block into *m (as bits, which order like the values; NaN above everything): wavefront
+// maximum, then one atomic per block; the kernels below loop over their points with at most MAXB_BLOCKS blocks
+// (contended atomics on one address cost ~10 ns each; one per element took a third of a millisecond).  Every
+// thread of the block calls it.
+constexpr int MAXB_BLOCKS = 1024;
+__device__ __forceinline__ unsigned long long abits(double v) {
+  return (unsigned long long)__double_as_longlong(fabs(v));
+}
+__device__ __forceinline__ void bmax(unsigned long long *m, unsigned long long a) {
+  __shared__ unsigned long long sm[TPB / 64];
+  for (int o = 32; o > 0; o >>= 1) {
+    const unsigned long long b = __shfl_xor(a, o, 64);
+    a = b > a ? b : a;
+  }
+  if ((threadIdx.x & 63) == 0) sm[threadIdx.x >> 6] = a;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int q = 0; q < (int)(blockDim.x >> 6); q++) a = sm[q] > a ? sm[q] : a;
+    if (a) atomicMax(m, a);
+  }
 }
 
 // explicit part on the internal velocity points; NaN marks a missing history value
 __global__ void k_fbase(int W, const uint8_t *__restrict__ cls, const double *__restrict__ x, const double *__restrict__ lu,
                         const double *__restrict__ lv, const double *__restrict__ f, double alpha, double dt, double *fb,
                         unsigned long long *fmax) {
-  int WW = W * W;
-  int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= 2 * WW) return;
-  if (cls[t] != K_INT) {
-    fb[t] = 0;
-    return;
+  const int WW = W * W;
+  unsigned long long m = 0;
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < 2 * WW; t += gridDim.x * blockDim.x) {
+    double val = 0;
+    if (cls[t] == K_INT) {
+      const double lap = t < WW ? lu[t] : lv[t - WW];
+      val = x[t] + alpha * lap + dt * (f ? f[t] : 0.0);
+    }
+    fb[t] = val;
+    m = max(m, abits(val));
   }
-  double lap = t < WW ? lu[t] : lv[t - WW];
-  double val = x[t] + alpha * lap + dt * (f ? f[t] : 0.0);
-  fb[t] = val;
-  bmax(fmax, val);
+  bmax(fmax, m);
 }
 
 // momentum right-hand side with the extrapolated convection (n >= 2) or c^n (first Picard iterate)
@@ -93,19 +112,22 @@ __global__ void k_rhs_conv(int W, const uint8_t *__restrict__ cls, const double 
 __global__ void k_picard(int N, int W, double h, double a, double d, const uint8_t *__restrict__ cls,
                          const double *__restrict__ x, const double *__restrict__ fb, const double *c0u, const double *c0v,
                          const double *cku, const double *ckv, double dt, double *b, unsigned long long *rmax) {
-  int WW = W * W;
-  int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= 2 * WW) return;
-  if (cls[t] != K_INT) return;
-  int g = t < WW ? 0 : 1, q = t - g * WW;
-  double C = 0.5 * (g == 0 ? c0u[q] + cku[q] : c0v[q] + ckv[q]);
-  double bn = fb[t] - dt * C;
-  const double *u = x + g * WW, *p = x + 2 * WW;
-  double ih = 1.0 / h;
-  double Mx = d * u[q] - a * (u[q - 1] + u[q + 1] + u[q - W] + u[q + W]) + (p[q] - (g == 0 ? p[q - 1] : p[q - W])) * ih;
-  double r = bn - Mx;
-  b[t] = bn;
-  bmax(rmax, r);
+  const int WW = W * W;
+  unsigned long long m = 0;
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < 2 * WW; t += gridDim.x * blockDim.x) {
+    if (cls[t] != K_INT) continue;
+    const int g = t < WW ? 0 : 1, q = t - g * WW;
+    const double C = 0.5 * (g == 0 ? c0u[q] + cku[q] : c0v[q] + ckv[q]);
+    const double bn = fb[t] - dt * C;
+    const double *u = x + g * WW, *p = x + 2 * WW;
+    const double ih = 1.0 / h;
+    const double Mx =
+        d * u[q] - a * (u[q - 1] + u[q + 1] + u[q - W] + u[q + W]) + (p[q] - (g == 0 ? p[q - 1] : p[q - W])) * ih;
+    const double r = bn - Mx;
+    b[t] = bn;
+    m = max(m, abits(r));
+  }
+  bmax(rmax, m);
   (void)N;
 }
 
@@ -177,7 +199,7 @@ gp_status cn_step(Ctx *ctx, double dt, const double *fu, const double *fv, const
   // forcing staged in fwork by the caller: u grid, v grid, continuity right-hand side
   (void)fu;
   (void)fv;
-  k_fbase<<<nblk(2L * WW), TPB, 0, s>>>(G.W, G.cls, ctx->v64[0].x, ctx->lapu, ctx->lapv, ctx->fwork, alpha, dt,
+  k_fbase<<<std::min(MAXB_BLOCKS, nblk(2L * WW)), TPB, 0, s>>>(G.W, G.cls, ctx->v64[0].x, ctx->lapu, ctx->lapv, ctx->fwork, alpha, dt,
                                        ctx->fbase, flags);
   k_rhs_cont<<<nblk(WW + 1), TPB, 0, s>>>(G.W, G.cls, g ? ctx->fwork + 2 * (size_t)WW : nullptr, ctx->v64[0].b);
   int extrap = ctx->nstep >= 2;
@@ -205,7 +227,7 @@ gp_status cn_step(Ctx *ctx, double dt, const double *fu, const double *fv, const
       if (G.ne) k_ext_fill_cn<double><<<nblk(G.ne), TPB, 0, s>>>(G.e_pt, G.e_src, G.e_w, G.ne, ctx->v64[0].x);
       k_conv_lap<<<nblk(WW), TPB, 0, s>>>(G.N, G.W, G.h, G.cls, ctx->v64[0].x, ctx->cku, ctx->ckv, nullptr, nullptr);
       k_zero_u64<<<1, 1, 0, s>>>(flags + 2, 1);
-      k_picard<<<nblk(2L * WW), TPB, 0, s>>>(G.N, G.W, G.h, a, d, G.cls, ctx->v64[0].x, ctx->fbase, ctx->cu[0], ctx->cv[0],
+      k_picard<<<std::min(MAXB_BLOCKS, nblk(2L * WW)), TPB, 0, s>>>(G.N, G.W, G.h, a, d, G.cls, ctx->v64[0].x, ctx->fbase, ctx->cu[0], ctx->cv[0],
                                             ctx->cku, ctx->ckv, dt, ctx->v64[0].b, flags + 2);
       GP_HIP(hipGetLastError());
       unsigned long long rv;

@@ -915,17 +915,6 @@ __global__ void k_pshift(int W, const uint8_t *__restrict__ cls, T *__restrict__
 // ---------------------------------------------------------------------------------------------------------
 // residual r = b - M x
 // ---------------------------------------------------------------------------------------------------------
-// max-norm accumulation: wavefront maximum first, then one atomic per wavefront (|v| as raw bits orders like
-// the value for non-negative doubles, and NaN sorts above everything)
-__device__ __forceinline__ void max_abs(unsigned long long *m, double v) {
-  unsigned long long a = (unsigned long long)__double_as_longlong(fabs(v));
-  for (int o = 32; o > 0; o >>= 1) {
-    unsigned long long b = __shfl_xor(a, o, 64);
-    a = b > a ? b : a;
-  }
-  if ((threadIdx.x & 63) == 0 && a) atomicMax(m, a);
-}
-
 // residual of the point rows (internal momentum and continuity rows, wall identity rows; 0 for every other
 // point, whose row, if any, is a ghost row handled by k_resid_ghost)
 template <typename T>
@@ -1071,10 +1060,28 @@ __global__ void k_resid_ghost(const int *__restrict__ pt, const int *__restrict_
 // max |b| over a vector (wavefront reduction, one atomic per wavefront)
 template <typename T>
 __global__ void k_absmax(const T *__restrict__ v, long n, unsigned long long *out) {
-  long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  const long st = (long)gridDim.x * blockDim.x;
   double a = 0;
-  for (; t < n; t += (long)gridDim.x * blockDim.x) a = fmax(a, fabs((double)v[t]));
-  max_abs(out, a);
+  for (long t0 = blockIdx.x * (long)blockDim.x + threadIdx.x; t0 < n; t0 += 8 * st) {
+    double w[8];
+#pragma unroll
+    for (int u = 0; u < 8; u++) w[u] = t0 + u * st < n ? fabs((double)v[t0 + u * st]) : 0.0;
+#pragma unroll
+    for (int u = 0; u < 8; u++) a = fmax(a, w[u]);
+  }
+  // one atomic per block (contended atomics on one address cost ~10 ns each)
+  __shared__ unsigned long long sm[TPB / 64];
+  unsigned long long z = (unsigned long long)__double_as_longlong(a);
+  for (int o = 32; o > 0; o >>= 1) {
+    const unsigned long long q = __shfl_xor(z, o, 64);
+    z = q > z ? q : z;
+  }
+  if ((threadIdx.x & 63) == 0) sm[threadIdx.x >> 6] = z;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int q = 0; q < TPB / 64; q++) z = sm[q] > z ? sm[q] : z;
+    if (z) atomicMax(out, z);
+  }
 }
 
 template <typename T>
