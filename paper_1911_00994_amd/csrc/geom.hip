@@ -1383,8 +1383,7 @@ gp_status geometry_build(Ctx *ctx) {
       st[l] = build_level(ctx, l);
       // the coarsest level: its exact inverse for the current alpha too, while the finer levels still build (a
       // failure leaves c_ok = 0, and the solver factors again and reports it)
-      if (l == L - 1 && st[l] == GP_OK && ctx->alpha > 0)
-        (void)coarse_factor(ctx, ctx->bres[l]);
+      if (l == L - 1 && st[l] == GP_OK && ctx->alpha > 0) (void)coarse_factor(ctx, ctx->bres[l]);
     });
   st[0] = build_level(ctx, 0);
   for (auto &t : th) t.join();
@@ -1501,13 +1500,12 @@ __global__ void k_coarse_fill(const uint8_t *cls, int N, int W, double h, double
 constexpr int GJ_T = 1024;
 __global__ void __launch_bounds__(GJ_T) k_gj_panel(const double *__restrict__ Ain, double *Aout, int n, int k0, int nb,
                                                    int *spv, int *perm, int *fail) {
-  extern __shared__ double pl[];  // panel, column-major: column j at pl[j * n]; then fcol (n), rowk (nb)
+  // panel, column-major: column j at pl[j * n]; then fcol (n), rowk (nb), oldk (nb)
+  extern __shared__ double pl[];
   __shared__ int lperm[1024];
   __shared__ double wbest[GJ_T / 64];
   __shared__ int wbi[GJ_T / 64];
-  __shared__ int sp;
-  __shared__ double sabs;
-  double *fcol = pl + (size_t)nb * n, *rowk = fcol + n;
+  double *fcol = pl + (size_t)nb * n, *rowk = fcol + n, *oldk = rowk + nb;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   if (*fail) return;  // an earlier panel found no pivot
   for (int e = tid; e < n * nb; e += GJ_T) {
@@ -1516,9 +1514,12 @@ __global__ void __launch_bounds__(GJ_T) k_gj_panel(const double *__restrict__ Ai
   }
   for (int i = tid; i < n; i += GJ_T) lperm[i] = i;
   __syncthreads();
+  // the update's thread map: column uj, rows ui, ui + 32, ... (consecutive threads on consecutive rows)
+  const int uj = tid >> 5, ui = tid & 31;
   for (int j = 0; j < nb; j++) {
     const int k = k0 + j;
-    double *cj = pl + (size_t)j * n;
+    const double *cj = pl + (size_t)j * n;
+    // pivot: the largest |entry| of column j at or below k (ties to the smaller row)
     double best = -1;
     int bi = n;
     for (int i = k + tid; i < n; i += GJ_T) {
@@ -1541,47 +1542,41 @@ __global__ void __launch_bounds__(GJ_T) k_gj_panel(const double *__restrict__ Ai
       wbi[wv] = bi;
     }
     __syncthreads();
-    if (tid == 0) {
-      double bb = -1;
-      int pp = n;
-      for (int w = 0; w < GJ_T / 64; w++)
-        if (wbest[w] > bb || (wbest[w] == bb && wbi[w] < pp)) {
-          bb = wbest[w];
-          pp = wbi[w];
-        }
-      sp = pp;
-      sabs = bb;
-      spv[k] = pp;
-    }
-    __syncthreads();
-    const int p = sp;
-    if (!(sabs > 0) || p >= n) {
+    double bb = -1;
+    int p = n;
+    for (int w = 0; w < GJ_T / 64; w++)  // every thread, in the same order
+      if (wbest[w] > bb || (wbest[w] == bb && wbi[w] < p)) {
+        bb = wbest[w];
+        p = wbi[w];
+      }
+    if (!(bb > 0) || p >= n) {
       if (tid == 0) *fail = 1;
       return;
     }
-    if (p != k) {
-      for (int jj = tid; jj < nb; jj += GJ_T) {
-        double t = pl[jj * n + k];
-        pl[jj * n + k] = pl[jj * n + p];
-        pl[jj * n + p] = t;
-      }
-      if (tid == 0) {
-        int t = lperm[k];
-        lperm[k] = lperm[p];
-        lperm[p] = t;
-      }
+    // rows k and p interchanged (row p's values scaled into rowk, row k's kept in oldk for position p), and the
+    // pivot column after the interchange, all read before anything is written
+    const double cjk = cj[k], cjp = cj[p], inv = 1.0 / cjp;
+    for (int i = tid; i < n; i += GJ_T) fcol[i] = i == k ? cjp : (i == p ? cjk : cj[i]);
+    for (int jj = tid; jj < nb; jj += GJ_T) {
+      rowk[jj] = (jj == j) ? inv : pl[jj * n + p] * inv;
+      oldk[jj] = pl[jj * n + k];
+    }
+    if (tid == 0) {
+      spv[k] = p;
+      const int t = lperm[k];
+      lperm[k] = lperm[p];
+      lperm[p] = t;
     }
     __syncthreads();
-    const double inv = 1.0 / cj[k];
-    for (int i = tid; i < n; i += GJ_T) fcol[i] = cj[i];
-    for (int jj = tid; jj < nb; jj += GJ_T) rowk[jj] = (jj == j) ? inv : pl[jj * n + k] * inv;
-    __syncthreads();
-    for (int e = tid; e < n * nb; e += GJ_T) {
-      int jj = e / n, i = e - jj * n;
-      if (i == k)
-        pl[e] = rowk[jj];
-      else
-        pl[e] = (jj == j) ? -fcol[i] * inv : pl[e] - fcol[i] * rowk[jj];
+    if (uj < nb) {
+      double *col = pl + (size_t)uj * n;
+      const double rk = rowk[uj];
+      for (int i = ui; i < n; i += 32) {
+        if (i == k)
+          col[i] = rk;
+        else
+          col[i] = (uj == j) ? -fcol[i] * inv : (i == p ? oldk[uj] : col[i]) - fcol[i] * rk;
+      }
     }
     __syncthreads();
   }
@@ -1645,7 +1640,7 @@ gp_status coarse_factor(Ctx *ctx, const BuildRes &B) {
     double *Ain = ctx->c_A, *Aout = ctx->c_B;
     for (int k0 = 0; k0 < n; k0 += nb) {
       int w = std::min(nb, n - k0);
-      size_t lds = ((size_t)w * n + n + w) * sizeof(double);
+      size_t lds = ((size_t)w * n + n + 2 * w) * sizeof(double);
       k_gj_panel<<<1, GJ_T, lds, s>>>(Ain, Aout, n, k0, w, spv, perm, B.flags + 6);
       k_gj_trail<<<nblk((long)n * n), TPB, 0, s>>>(Ain, Aout, n, k0, w, perm, B.flags + 6);
       std::swap(Ain, Aout);
