@@ -191,6 +191,7 @@ void gp_destroy(gp_ctx *ctx) {
   for (int l = 0; l < MAXLEV; l++) {
     BuildRes &B = ctx->bres[l];
     if (B.ev) (void)hipEventDestroy(B.ev);
+    if (B.hbuf) (void)hipHostFree(B.hbuf);
     if (l == 0) continue;
     dfree(B.flags);
     dfree(B.bcnt);
@@ -363,6 +364,14 @@ gp_status gp_setup_grid(gp_ctx **out, int N, double Re, const gp_params *prm, vo
   for (int l = 0; l < L; l++) {
     BuildRes &B = ctx->bres[l];
     GP_HIP(hipEventCreateWithFlags(&B.ev, hipEventDisableTiming));
+    {
+      void *hp = nullptr;
+      GP_HIP(hipHostMalloc(&hp, 4096, hipHostMallocCoherent));
+      B.hbuf = (int *)hp;
+      B.hseq = (unsigned *)(B.hbuf + 1020);
+      *B.hseq = 0;
+      B.seq = 0;
+    }
     if (l == 0) {
       B.s = ctx->stream;
       B.flags = ctx->d_flags;

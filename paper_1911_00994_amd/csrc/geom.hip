@@ -5,6 +5,8 @@
 // decisions of the bisection see the same roundings as a plain IEEE evaluation.
 #include <cmath>
 #include <cstdio>
+#include <cstring>
+#include <initializer_list>
 
 #include <thread>
 
@@ -889,11 +891,57 @@ static gp_status read_flags(Ctx *ctx, int *h) {
   GP_HIP(hipStreamSynchronize(ctx->stream));
   return GP_OK;
 }
-static gp_status read_flags(Ctx *ctx, const BuildRes &B, int *h) {
-  GP_HIP(hipMemcpyAsync(h, B.flags, 8 * sizeof(int), hipMemcpyDeviceToHost, B.s));
-  GP_HIP(hipStreamSynchronize(B.s));
+// Read-backs of the build without a blocking runtime call: k_publish (one wavefront) copies up to four ranges
+// of device words into the level's pinned host buffer and then sets its sequence number there (system-scope
+// release); the host polls that number, and the stream now and then, so that a failed launch ends the wait.
+// (A copy to pageable memory and a stream synchronisation per read-back, a dozen per level and eight levels
+// building at once, kept the threads waiting on each other in the runtime.)
+struct PubSrc {
+  const int *p[4];
+  int n[4];
+  int k;
+};
+__global__ void __launch_bounds__(64) k_publish(PubSrc src, int *dst, unsigned *seqp, unsigned seq) {
+  int off = 0;
+  for (int q = 0; q < src.k; q++) {
+    for (int w = threadIdx.x; w < src.n[q]; w += 64) dst[off + w] = src.p[q][w];
+    off += src.n[q];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) __hip_atomic_store(seqp, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+struct Words {
+  const void *p;
+  int n;  // 4-byte words
+};
+static gp_status fetch(Ctx *ctx, BuildRes &B, std::initializer_list<Words> src, void *out) {
+  PubSrc ps{};
+  int tot = 0;
+  for (const Words &w : src) {
+    ps.p[ps.k] = static_cast<const int *>(w.p);
+    ps.n[ps.k] = w.n;
+    ps.k++;
+    tot += w.n;
+  }
+  const unsigned seq = ++B.seq;
+  k_publish<<<1, 64, 0, B.s>>>(ps, B.hbuf, B.hseq, seq);
+  GP_HIP(hipGetLastError());
+  for (long it = 1;; it++) {
+    if (__atomic_load_n(B.hseq, __ATOMIC_ACQUIRE) == seq) break;
+    if ((it & 255) == 0) {
+      const hipError_t e = hipStreamQuery(B.s);
+      if (e == hipSuccess && __atomic_load_n(B.hseq, __ATOMIC_ACQUIRE) != seq) {
+        std::lock_guard<std::mutex> lk(ctx->err_mu);
+        ctx->hip_err = "a read-back of the geometry build did not arrive";
+        return GP_EHIP;
+      }
+      if (e != hipSuccess && e != hipErrorNotReady) GP_HIP(e);
+    }
+  }
+  std::memcpy(out, B.hbuf, (size_t)tot * sizeof(int));
   return GP_OK;
 }
+static gp_status read_flags(Ctx *ctx, BuildRes &B, int *h) { return fetch(ctx, B, {{B.flags, 8}}, h); }
 
 // ---------------------------------------------------------------------------------------------------------
 // angular sectors of a large boundary band (one workgroup each in the band relaxation).  Angles are taken about
@@ -1127,7 +1175,7 @@ __global__ void __launch_bounds__(TPB) k_sec_fill_tabs(const int *band, int nban
 // sectors, a table over its capacity, a sector too large for LDS)
 gp_status sector_build(Ctx *ctx, int l) {
   Geo &G = ctx->geo[l];
-  const BuildRes &B = ctx->bres[l];
+  BuildRes &B = ctx->bres[l];
   hipStream_t s = B.s;
   const int W = G.W, nt = G.nband + G.nbg;
   G.sec_S = 0;
@@ -1139,9 +1187,13 @@ gp_status sector_build(Ctx *ctx, int l) {
   GP_HIP(hipGetLastError());
   double hacc[2];
   int reach = 0;
-  GP_HIP(hipMemcpyAsync(hacc, acc, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
-  GP_HIP(hipMemcpyAsync(&reach, ic, sizeof(int), hipMemcpyDeviceToHost, s));
-  GP_HIP(hipStreamSynchronize(s));
+  {
+    int w[5];
+    gp_status fs = fetch(ctx, B, {{acc, 4}, {ic, 1}}, w);
+    if (fs) return fs;
+    std::memcpy(hacc, w, 2 * sizeof(double));
+    reach = w[4];
+  }
   SecGeo sg;
   sg.cx = hacc[0] / G.nband;
   sg.cy = hacc[1] / G.nband;
@@ -1150,8 +1202,10 @@ gp_status sector_build(Ctx *ctx, int l) {
   k_sec_rmin<<<nblk(G.nreg), TPB, 0, s>>>(G.reg_pt, G.nreg, W, G.h, sg.cx, sg.cy, (unsigned long long *)(acc + 2));
   GP_HIP(hipGetLastError());
   double rmin = 0;
-  GP_HIP(hipMemcpyAsync(&rmin, acc + 2, sizeof(double), hipMemcpyDeviceToHost, s));
-  GP_HIP(hipStreamSynchronize(s));
+  {
+    gp_status fs = fetch(ctx, B, {{acc + 2, 2}}, &rmin);
+    if (fs) return fs;
+  }
   // reach of one relaxation step's band work in cells: each ghost sweep the ghost rows' reach (+1 for the
   // staggering), each band colour 3 (a box reads 2 cells away, +1), and 2 more for the written points themselves
   const int lam = ctx->prm.lambda_ghost, nsw = ctx->prm.bnd_sweeps;
@@ -1171,8 +1225,10 @@ gp_status sector_build(Ctx *ctx, int l) {
   k_sec_count<<<nblk(G.nreg), TPB, 0, s>>>(G.sec_mask, G.nreg, G.nregw, G.reg_pt, W, G.h, sg, cnt_p, cnt_o, bad);
   GP_HIP(hipGetLastError());
   std::vector<int> hc(8 * S + 1);
-  GP_HIP(hipMemcpyAsync(hc.data(), ic, hc.size() * sizeof(int), hipMemcpyDeviceToHost, s));
-  GP_HIP(hipStreamSynchronize(s));
+  {
+    gp_status fs = fetch(ctx, B, {{ic, (int)hc.size()}}, hc.data());
+    if (fs) return fs;
+  }
   if (hc[8 * S]) return GP_OK;
   SecOff off{};
   int maxreg = 0, maxrow = 0;
@@ -1208,7 +1264,7 @@ gp_status sector_build(Ctx *ctx, int l) {
 
 static gp_status build_level(Ctx *ctx, int l) {
   Geo &G = ctx->geo[l];
-  const BuildRes &B = ctx->bres[l];
+  BuildRes &B = ctx->bres[l];
   Lat L = make_lat(ctx, l);
   int W = G.W, P = 3 * W * W;
   hipStream_t s = B.s;
@@ -1260,8 +1316,8 @@ static gp_status build_level(Ctx *ctx, int l) {
       k_band_offsets<<<1, 64, 0, s>>>(B.bcnt, nb, G.d_band_off);
       k_band_fill<<<nb, TPB, 0, s>>>(G.cls, G.N, W, ctx->prm.bnd_radius, nb, B.bcnt, G.band);
       GP_HIP(hipGetLastError());
-      GP_HIP(hipMemcpyAsync(hoff, G.d_band_off, 6 * sizeof(int), hipMemcpyDeviceToHost, s));
-      GP_HIP(hipStreamSynchronize(s));
+      gp_status fs = fetch(ctx, B, {{G.d_band_off, 6}}, hoff);
+      if (fs) return fs;
     }
     G.nband = hoff[5];
     for (int c = 0; c < 8; c++) G.hband_off[c] = hoff[c];
@@ -1286,9 +1342,13 @@ static gp_status build_level(Ctx *ctx, int l) {
     k_pred_fill<<<nbr, TPB, 0, s>>>(2, P3, G.reg_map, G.cls, cnt2, regcap, G.reg_pt, B.bcnt + nbr);
     GP_HIP(hipGetLastError());
     int nr = 0;
-    GP_HIP(hipMemcpyAsync(&G.nregw, B.bcnt + nbr, sizeof(int), hipMemcpyDeviceToHost, s));
-    GP_HIP(hipMemcpyAsync(&nr, cnt2 + nbr, sizeof(int), hipMemcpyDeviceToHost, s));
-    GP_HIP(hipStreamSynchronize(s));
+    {
+      int w[2];
+      gp_status fs = fetch(ctx, B, {{B.bcnt + nbr, 1}, {cnt2 + nbr, 1}}, w);
+      if (fs) return fs;
+      G.nregw = w[0];
+      nr = w[1];
+    }
     // the read-only points are staged too when they fit (FP64 values, and the body ghost rows' new values and
     // right-hand sides in LDS); otherwise their map entries stay negative and the kernel reads them from global
     // memory
@@ -1308,8 +1368,8 @@ static gp_status build_level(Ctx *ctx, int l) {
       k_pred_fill<<<nbr, TPB, 0, s>>>(1, P3, G.reg_map, G.cls, B.bcnt, G.gcap, G.bg_k, nullptr);
       if (G.ng) k_row_of<<<nblk(G.ng), TPB, 0, s>>>(G.g_pt, G.ng, B.iscr);
       GP_HIP(hipGetLastError());
-      GP_HIP(hipMemcpyAsync(&G.nbg, B.bcnt + nbr, sizeof(int), hipMemcpyDeviceToHost, s));
-      GP_HIP(hipStreamSynchronize(s));
+      gp_status fs = fetch(ctx, B, {{B.bcnt + nbr, 1}}, &G.nbg);
+      if (fs) return fs;
       if (G.nbg > G.gcap) return GP_ENOMEM;
       if (G.nbg)
         k_region_rows<<<nblk(G.nbg), TPB, 0, s>>>(G.cls, G.g_col, G.g_w, G.g_dtau, B.iscr, G.reg_map, G.nbg, G.gcap,
@@ -1319,8 +1379,8 @@ static gp_status build_level(Ctx *ctx, int l) {
                                                B.flags + 10, B.flags + 11);
       GP_HIP(hipGetLastError());
       int hr[2];
-      GP_HIP(hipMemcpyAsync(hr, B.flags + 10, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
-      GP_HIP(hipStreamSynchronize(s));
+      fs = fetch(ctx, B, {{B.flags + 10, 2}}, hr);
+      if (fs) return fs;
       G.nwg = hr[0];
       G.lds_ok = hr[1] == 0 ? 1 : 0;
     }
@@ -1343,19 +1403,24 @@ static gp_status build_level(Ctx *ctx, int l) {
     k_scan_blocks<<<1, SCAN_T, 0, s>>>(B.bcnt, nb);
     k_face_fill<<<nb, TPB, 0, s>>>(G.cls, G.N, W, B.bcnt, G.fcap, G.f_code);
     GP_HIP(hipGetLastError());
-    int cb = 1;
-    GP_HIP(hipMemcpyAsync(&G.nf, B.bcnt + nb, sizeof(int), hipMemcpyDeviceToHost, s));
-    if (G.ng) GP_HIP(hipMemcpyAsync(&cb, B.flags + 12, sizeof(int), hipMemcpyDeviceToHost, s));
-    GP_HIP(hipStreamSynchronize(s));
+    int w[2];
+    gp_status fs = fetch(ctx, B, {{B.bcnt + nb, 1}, {B.flags + 12, 1}}, w);
+    if (fs) return fs;
+    G.nf = w[0];
+    const int cb = G.ng ? w[1] : 1;
     G.colr_ok = G.ng > 0 && cb == 0;
     if (G.nf > G.fcap) return GP_ENOMEM;
     if (G.lds_ok && G.nf) k_face_loc<<<nblk(G.nf), TPB, 0, s>>>(G.f_code, G.nf, G.reg_map, G.f_loc);
   }
   if (l == 0) k_empty_cells<<<nblk(G.N * G.N), TPB, 0, s>>>(G.cls, G.N, W, B.flags);
   GP_HIP(hipGetLastError());
-  GP_HIP(hipMemcpyAsync(&G.mp, G.d_mp, sizeof(int), hipMemcpyDeviceToHost, s));
-  st = read_flags(ctx, B, hf);
-  if (st) return st;
+  {
+    int w[9];
+    st = fetch(ctx, B, {{G.d_mp, 1}, {B.flags, 8}}, w);
+    if (st) return st;
+    G.mp = w[0];
+    for (int q = 0; q < 8; q++) hf[q] = w[1 + q];
+  }
   if (G.mp == 0) return GP_EGEOM;
   if (l == 0 && (hf[1] || hf[4])) return GP_EGEOM;
   return GP_OK;
@@ -1542,13 +1607,17 @@ __global__ void __launch_bounds__(GJ_T) k_gj_panel(const double *__restrict__ Ai
       wbi[wv] = bi;
     }
     __syncthreads();
-    double bb = -1;
-    int p = n;
-    for (int w = 0; w < GJ_T / 64; w++)  // every thread, in the same order
-      if (wbest[w] > bb || (wbest[w] == bb && wbi[w] < p)) {
-        bb = wbest[w];
-        p = wbi[w];
+    // every wavefront reduces the GJ_T / 64 wave results the same way (lane w holds result w % (GJ_T / 64))
+    double bb = wbest[lane % (GJ_T / 64)];
+    int p = wbi[lane % (GJ_T / 64)];
+    for (int o = GJ_T / 128; o > 0; o >>= 1) {
+      const double ob = __shfl_xor(bb, o, 64);
+      const int oi = __shfl_xor(p, o, 64);
+      if (ob > bb || (ob == bb && oi < p)) {
+        bb = ob;
+        p = oi;
       }
+    }
     if (!(bb > 0) || p >= n) {
       if (tid == 0) *fail = 1;
       return;
@@ -1570,12 +1639,21 @@ __global__ void __launch_bounds__(GJ_T) k_gj_panel(const double *__restrict__ Ai
     __syncthreads();
     if (uj < nb) {
       double *col = pl + (size_t)uj * n;
-      const double rk = rowk[uj];
-      for (int i = ui; i < n; i += 32) {
-        if (i == k)
-          col[i] = rk;
-        else
-          col[i] = (uj == j) ? -fcol[i] * inv : (i == p ? oldk[uj] : col[i]) - fcol[i] * rk;
+      const double rk = rowk[uj], ok = oldk[uj];
+      for (int i0 = ui; i0 < n; i0 += 8 * 32) {  // eight rows' loads before any store (col and fcol share pl)
+        double cv[8], fv[8];
+#pragma unroll
+        for (int u = 0; u < 8; u++) {
+          const int i = i0 + 32 * u;
+          cv[u] = i < n ? col[i] : 0.0;
+          fv[u] = i < n ? fcol[i] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; u++) {
+          const int i = i0 + 32 * u;
+          if (i >= n) break;
+          col[i] = i == k ? rk : ((uj == j) ? -fv[u] * inv : (i == p ? ok : cv[u]) - fv[u] * rk);
+        }
       }
     }
     __syncthreads();
@@ -1615,7 +1693,7 @@ __global__ void __launch_bounds__(GJ_T) k_gj_finish(const int *__restrict__ spv,
 
 gp_status coarse_factor(Ctx *ctx) { return coarse_factor(ctx, ctx->bres[0]); }
 // on the stream and flags of B (the coarsest level's, when the geometry build factors it early)
-gp_status coarse_factor(Ctx *ctx, const BuildRes &B) {
+gp_status coarse_factor(Ctx *ctx, BuildRes &B) {
   int l = ctx->L - 1;
   Geo &G = ctx->geo[l];
   int W = G.W, P = 3 * W * W;

@@ -126,6 +126,9 @@ struct BuildRes {
   hipEvent_t ev = nullptr;
   int *flags = nullptr, *bcnt = nullptr, *iscr = nullptr;
   double *red = nullptr;
+  int *hbuf = nullptr;        // pinned host words for the read-backs (fetch)
+  unsigned *hseq = nullptr;   // in hbuf: the sequence number of the last read-back that arrived
+  unsigned seq = 0;           // the last one issued
 };
 
 struct Ctx {
@@ -217,7 +220,7 @@ gp_status geometry_build(Ctx *ctx);
 gp_status levelset_analytic(Ctx *ctx, const gp_shape *shape, double t, const gp_rigid *mo);
 gp_status default_boundary_values(Ctx *ctx);
 gp_status coarse_factor(Ctx *ctx);
-gp_status coarse_factor(Ctx *ctx, const BuildRes &B);
+gp_status coarse_factor(Ctx *ctx, BuildRes &B);
 gp_status sector_build(Ctx *ctx, int l);
 
 // multigrid (mg.hip)
