@@ -886,11 +886,6 @@ gp_status levelset_analytic(Ctx *ctx, const gp_shape *sh, double t, const gp_rig
   return GP_OK;
 }
 
-static gp_status read_flags(Ctx *ctx, int *h) {
-  GP_HIP(hipMemcpyAsync(h, ctx->d_flags, 8 * sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
-  GP_HIP(hipStreamSynchronize(ctx->stream));
-  return GP_OK;
-}
 // Read-backs of the build without a blocking runtime call: k_publish (one wavefront) copies up to four ranges
 // of device words into the level's pinned host buffer and then sets its sequence number there (system-scope
 // release); the host polls that number, and the stream now and then, so that a failed launch ends the wait.
@@ -1197,8 +1192,7 @@ gp_status sector_build(Ctx *ctx, int l) {
   SecGeo sg;
   sg.cx = hacc[0] / G.nband;
   sg.cy = hacc[1] / G.nband;
-  const unsigned long long big = 0x7ff0000000000000ull;  // +inf
-  GP_HIP(hipMemcpyAsync(acc + 2, &big, sizeof(big), hipMemcpyHostToDevice, s));
+  GP_HIP(hipMemsetAsync(acc + 2, 0x7f, sizeof(double), s));  // 0x7f7f...: ~1.4e306, above any distance here
   k_sec_rmin<<<nblk(G.nreg), TPB, 0, s>>>(G.reg_pt, G.nreg, W, G.h, sg.cx, sg.cy, (unsigned long long *)(acc + 2));
   GP_HIP(hipGetLastError());
   double rmin = 0;
@@ -1481,22 +1475,46 @@ gp_status default_boundary_values(Ctx *ctx) {
 // ---------------------------------------------------------------------------------------------------------
 // coarsest level: dense matrix of the active unknowns and its inverse (Gauss-Jordan with partial pivoting)
 // ---------------------------------------------------------------------------------------------------------
-__global__ void k_coarse_map(const uint8_t *cls, int P, int *map, int *inv, int *count) {
-  // single thread: deterministic order of the active unknowns
-  if (blockIdx.x != 0 || threadIdx.x != 0) return;
-  int n = 0;
-  for (int k = 0; k < P; k++) {
-    uint8_t c = cls[k];
-    if (c == K_INT || c == K_GHOST || c == K_GHOSTX || c == K_WALLG) {
-      map[n] = k;
-      inv[k] = n;
-      n++;
-    } else
-      inv[k] = -1;
+// the active unknowns of the coarsest level in index order (one workgroup of CM_T threads, a chunk of CM_T
+// points at a time: wavefront ballots, then the wavefronts' offsets in order)
+constexpr int CM_T = 1024;
+__global__ void __launch_bounds__(CM_T) k_coarse_map(const uint8_t *cls, int P, int *map, int *inv, int *count) {
+  __shared__ int wcount[CM_T / 64];
+  __shared__ int base;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  if (tid == 0) base = 0;
+  __syncthreads();
+  for (int k0 = 0; k0 < P; k0 += CM_T) {
+    const int k = k0 + tid;
+    bool act = false;
+    if (k < P) {
+      const uint8_t c = cls[k];
+      act = c == K_INT || c == K_GHOST || c == K_GHOSTX || c == K_WALLG;
+    }
+    const unsigned long long m = __ballot(act);
+    if (lane == 0) wcount[wv] = __popcll(m);
+    __syncthreads();
+    int off = base;
+    for (int w = 0; w < wv; w++) off += wcount[w];
+    if (k < P) {
+      if (act) {
+        const int n = off + __popcll(m & ((1ull << lane) - 1));
+        map[n] = k;
+        inv[k] = n;
+      } else {
+        inv[k] = -1;
+      }
+    }
+    __syncthreads();
+    if (tid == 0)
+      for (int w = 0; w < CM_T / 64; w++) base += wcount[w];
+    __syncthreads();
   }
-  map[n] = P;  // xi
-  inv[P] = n;
-  *count = n + 1;
+  if (tid == 0) {
+    map[base] = P;  // xi
+    inv[P] = base;
+    *count = base + 1;
+  }
 }
 
 __global__ void k_coarse_fill(const uint8_t *cls, int N, int W, double h, double a, double d, const int *map,
@@ -1504,8 +1522,7 @@ __global__ void k_coarse_fill(const uint8_t *cls, int N, int W, double h, double
                               double *A) {
   int q = blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= nc) return;
-  double *row = A + (size_t)q * nc;
-  for (int c = 0; c < nc; c++) row[c] = 0;
+  double *row = A + (size_t)q * nc;  // zeroed before the launch
   int P = 3 * W * W;
   int k = map[q];
   auto put = [&](int col, double v) {
@@ -1700,7 +1717,7 @@ gp_status coarse_factor(Ctx *ctx, BuildRes &B) {
   hipStream_t s = B.s;
   int *inv = (int *)ctx->c_work;  // scratch (P+1 ints fit easily)
   int *row_of = inv + (P + 1);
-  k_coarse_map<<<1, 1, 0, s>>>(G.cls, P, ctx->c_map, inv, B.flags + 5);
+  k_coarse_map<<<1, CM_T, 0, s>>>(G.cls, P, ctx->c_map, inv, B.flags + 5);
   if (G.ng) k_row_of<<<nblk(G.ng), TPB, 0, s>>>(G.g_pt, G.ng, row_of);
   int hf[8];
   gp_status st = read_flags(ctx, B, hf);
@@ -1708,6 +1725,7 @@ gp_status coarse_factor(Ctx *ctx, BuildRes &B) {
   ctx->nc = hf[5];
   if (ctx->nc > 1024) return GP_EINVAL;
   double a = ctx->alpha / (G.h * G.h), d = 1.0 + 4.0 * a;
+  GP_HIP(hipMemsetAsync(ctx->c_A, 0, (size_t)ctx->nc * ctx->nc * sizeof(double), s));
   k_coarse_fill<<<nblk(ctx->nc), TPB, 0, s>>>(G.cls, G.N, W, G.h, a, d, ctx->c_map, inv, ctx->nc, row_of, G.g_col, G.g_w,
                                              G.mp, ctx->c_A);
   GP_HIP(hipMemsetAsync(B.flags + 6, 0, sizeof(int), s));
