@@ -514,56 +514,90 @@ __device__ bool cut_cell(const uint8_t *cls, int W, int i, int j) {
     if (k[q] != K_INT && k[q] != K_WALLD) return true;
   return false;
 }
+// exclusive prefix sum over the block (and the block's total): wavefront shuffles, then the wavefronts' sums
 __device__ int block_excl_scan(int v, int *total) {
-  __shared__ int s[TPB];
-  s[threadIdx.x] = v;
-  __syncthreads();
-  for (int o = 1; o < TPB; o <<= 1) {
-    int a = threadIdx.x >= o ? s[threadIdx.x - o] : 0;
-    __syncthreads();
-    s[threadIdx.x] += a;
-    __syncthreads();
+  __shared__ int ws[TPB / 64];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  int x = v;
+  for (int o = 1; o < 64; o <<= 1) {
+    const int y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
   }
-  int incl = s[threadIdx.x];
-  *total = s[TPB - 1];
+  if (lane == 63) ws[wv] = x;
   __syncthreads();
-  return incl - v;
+  int off = 0, tot = 0;
+  for (int w = 0; w < TPB / 64; w++) {
+    if (w < wv) off += ws[w];
+    tot += ws[w];
+  }
+  *total = tot;
+  __syncthreads();  // ws is reused by the next call
+  return off + x - v;
 }
-__device__ __forceinline__ int band_colour(const uint8_t *cls, int N, int W, int R, int t) {
+// cut flags of the cells (one byte each), then each cell's band colour from them (-1: not in the band)
+__global__ void k_band_cut(const uint8_t *cls, int N, int W, uint8_t *cut) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < N * N) cut[t] = cut_cell(cls, W, t % N, t / N) ? 1 : 0;
+}
+__device__ __forceinline__ int band_colour(const uint8_t *cls, const uint8_t *cut, int N, int W, int R, int t) {
   int i = t % N, j = t / N, WW = W * W, c = (j + 1) * W + (i + 1);
   bool any = cls[c] == K_INT || cls[c + 1] == K_INT || cls[WW + c] == K_INT || cls[WW + c + W] == K_INT ||
              cls[2 * WW + c] == K_INT;
   if (!any) return -1;
-  for (int dj = -R; dj <= R; dj++)
+  for (int dj = -R; dj <= R; dj++) {
+    const int b = j + dj;
+    if (b < 0 || b >= N) continue;
     for (int di = -R; di <= R; di++) {
-      int a = i + di, b = j + dj;
-      if (a < 0 || b < 0 || a >= N || b >= N) continue;
-      if (cut_cell(cls, W, a, b)) return (i + 2 * j) % 5;
+      const int a = i + di;
+      if (a >= 0 && a < N && cut[b * N + a]) return (i + 2 * j) % 5;
     }
+  }
   return -1;
 }
-
-// deterministic compaction: per-block counts (block_excl_scan), one scan of the block counts (k_scan_blocks),
-// fill in index order
-__global__ void __launch_bounds__(TPB) k_band_count(const uint8_t *cls, int N, int W, int R, int nb, int *bcnt) {
-  int t = blockIdx.x * TPB + threadIdx.x;
-  int col = t < N * N ? band_colour(cls, N, W, R, t) : -1;
+// this thread's rank among the block's cells of its colour (index order) and, in tot, the block's count per
+// colour: wavefront ballots, then the wavefronts' counts in order
+__device__ __forceinline__ int colour_rank(int col, int tot[5]) {
+  __shared__ int wc[5][TPB / 64];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  int rank = 0;
+  unsigned long long mine = 0;
   for (int c = 0; c < 5; c++) {
-    int tot;
-    block_excl_scan(col == c ? 1 : 0, &tot);
-    if (threadIdx.x == 0) bcnt[c * nb + blockIdx.x] = tot;
+    const unsigned long long m = __ballot(col == c);
+    if (lane == 0) wc[c][wv] = __popcll(m);
+    if (col == c) mine = m;
   }
+  __syncthreads();
+  for (int c = 0; c < 5; c++) {
+    int t = 0;
+    for (int w = 0; w < TPB / 64; w++) {
+      if (c == col && w < wv) rank += wc[c][w];
+      t += wc[c][w];
+    }
+    tot[c] = t;
+  }
+  __syncthreads();
+  return rank + (col >= 0 ? __popcll(mine & ((1ull << lane) - 1)) : 0);
+}
+
+// deterministic compaction: per-block counts, one scan of the block counts (k_scan_blocks), fill in index order;
+// the colours go to col8 between the two passes
+__global__ void __launch_bounds__(TPB) k_band_count(const uint8_t *cls, const uint8_t *cut, int N, int W, int R, int nb,
+                                                    int *bcnt, int8_t *col8) {
+  const int t = blockIdx.x * TPB + threadIdx.x;
+  const int col = t < N * N ? band_colour(cls, cut, N, W, R, t) : -1;
+  if (t < N * N) col8[t] = (int8_t)col;
+  int tot[5];
+  (void)colour_rank(col, tot);
+  if (threadIdx.x == 0)
+    for (int c = 0; c < 5; c++) bcnt[c * nb + blockIdx.x] = tot[c];
 }
 // band cells grouped by colour, ascending cell index within a colour
-__global__ void __launch_bounds__(TPB) k_band_fill(const uint8_t *cls, int N, int W, int R, int nb, const int *boff,
-                                                   int *band) {
-  int t = blockIdx.x * TPB + threadIdx.x;
-  int col = t < N * N ? band_colour(cls, N, W, R, t) : -1;
-  for (int c = 0; c < 5; c++) {
-    int tot;
-    int q = boff[c * nb + blockIdx.x] + block_excl_scan(col == c ? 1 : 0, &tot);
-    if (col == c) band[q] = t;
-  }
+__global__ void __launch_bounds__(TPB) k_band_fill(int N, int nb, const int8_t *col8, const int *boff, int *band) {
+  const int t = blockIdx.x * TPB + threadIdx.x;
+  const int col = t < N * N ? col8[t] : -1;
+  int tot[5];
+  const int r = colour_rank(col, tot);
+  if (col >= 0) band[boff[col * nb + blockIdx.x] + r] = t;
 }
 // colour offsets of the band (from the scanned counts) into out[0..5]
 __global__ void k_band_offsets(const int *boff, int nb, int *out) {
@@ -1305,10 +1339,13 @@ static gp_status build_level(Ctx *ctx, int l) {
     int nb = nblk((long)G.N * G.N);
     int hoff[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     if (ctx->prm.bnd_sweeps > 0) {
-      k_band_count<<<nb, TPB, 0, s>>>(G.cls, G.N, W, ctx->prm.bnd_radius, nb, B.bcnt);
+      uint8_t *cut = reinterpret_cast<uint8_t *>(B.iscr);  // N^2 cut flags, then N^2 colours
+      int8_t *col8 = reinterpret_cast<int8_t *>(cut + (size_t)G.N * G.N);
+      k_band_cut<<<nb, TPB, 0, s>>>(G.cls, G.N, W, cut);
+      k_band_count<<<nb, TPB, 0, s>>>(G.cls, cut, G.N, W, ctx->prm.bnd_radius, nb, B.bcnt, col8);
       k_scan_blocks<<<1, SCAN_T, 0, s>>>(B.bcnt, 5 * nb);
       k_band_offsets<<<1, 64, 0, s>>>(B.bcnt, nb, G.d_band_off);
-      k_band_fill<<<nb, TPB, 0, s>>>(G.cls, G.N, W, ctx->prm.bnd_radius, nb, B.bcnt, G.band);
+      k_band_fill<<<nb, TPB, 0, s>>>(G.N, nb, col8, B.bcnt, G.band);
       GP_HIP(hipGetLastError());
       gp_status fs = fetch(ctx, B, {{G.d_band_off, 6}}, hoff);
       if (fs) return fs;
