@@ -193,16 +193,24 @@ __global__ void k_closure(Lat L, uint8_t *cls, int W, int *changed) {
     for (int kx = 0; kx < 3; kx++) to_ghost(cls, N, W, g, i - sx * kx, j - sy * ky, changed);
 }
 
-// external points within R index steps of an internal point of the same grid carry extension values
-__global__ void k_ext_mark(uint8_t *cls, int N, int W, int R) {
+// external points within R index steps (max norm) of an internal point of the same grid carry extension values;
+// the window is taken in two passes: rowint = an internal point within R steps along the row (k_ext_rows_int),
+// then a body point is near if rowint holds within R steps along its column (k_ext_mark)
+__global__ void k_ext_rows_int(const uint8_t *cls, int N, int W, int R, uint8_t *rowint) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= 3 * W * W) return;
+  int g = t / (W * W), loc = t % (W * W), j = loc / W - 1, i = loc % W - 1;
+  bool any = false;
+  for (int di = -R; di <= R; di++) any = any || cls_of(cls, N, W, g, i + di, j) == K_INT;
+  rowint[t] = any ? 1 : 0;
+}
+__global__ void k_ext_mark(uint8_t *cls, int N, int W, int R, const uint8_t *rowint) {
   int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= 3 * W * W) return;
   if (cls[t] != K_BODY) return;
   int g = t / (W * W), loc = t % (W * W), j = loc / W - 1, i = loc % W - 1;
   bool near = false;
-  for (int dj = -R; dj <= R && !near; dj++)
-    for (int di = -R; di <= R && !near; di++)
-      if (cls_of(cls, N, W, g, i + di, j + dj) == K_INT) near = true;
+  for (int dj = -R; dj <= R && !near; dj++) near = inside(N, i, j + dj) && rowint[gix(W, g, i, j + dj)];
   // a point never reads another point's BODY/EXT state here, so the in-place update is race free
   cls[t] = near ? K_EXT : K_BODY;
 }
@@ -213,21 +221,30 @@ __global__ void k_body_to_inactive(uint8_t *cls, int n) {
 
 // compaction (order does not matter: every consumer of these lists is order independent)
 __global__ void k_compact(const uint8_t *cls, int n, int mode, int *list, int cap, int *counter) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x, lane = threadIdx.x & 63;
+  __shared__ int woff[TPB / 64];
+  __shared__ int bbase;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x, lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   bool take = false;
   if (t < n) {
     const uint8_t c = cls[t];
     take = (mode == 0) ? (c == K_GHOST || c == K_WALLG) : (c == K_EXT);
   }
-  // one atomic per wavefront: the lanes that take a slot get consecutive ones
+  // one atomic per block: the block's takers get consecutive slots, wavefront by wavefront
   const unsigned long long m = __ballot(take);
-  if (!m) return;
-  const int leader = __ffsll((long long)m) - 1;
-  int base = 0;
-  if (lane == leader) base = atomicAdd(counter, __popcll(m));
-  base = __shfl(base, leader, 64);
+  if (lane == 0) woff[wv] = __popcll(m);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int tot = 0;
+    for (int w = 0; w < TPB / 64; w++) {
+      const int c = woff[w];
+      woff[w] = tot;
+      tot += c;
+    }
+    bbase = tot ? atomicAdd(counter, tot) : 0;
+  }
+  __syncthreads();
   if (take) {
-    const int slot = base + __popcll(m & ((1ull << lane) - 1));
+    const int slot = bbase + woff[wv] + __popcll(m & ((1ull << lane) - 1));
     if (slot < cap) list[slot] = t;
   }
 }
@@ -1300,15 +1317,21 @@ static gp_status build_level(Ctx *ctx, int l) {
   GP_HIP(hipMemsetAsync(B.flags, 0, 8 * sizeof(int), s));
   k_classify<<<nblk(P), TPB, 0, s>>>(L, G.cls, W, l == 0, B.flags);
   k_seed<<<nblk(P), TPB, 0, s>>>(G.cls, G.N, W);
-  for (int it = 0;; it++) {
+  for (int it = 0;; it += 2) {  // two closure passes per read-back: a pass that changes nothing is a fixpoint
     GP_HIP(hipMemsetAsync(B.flags, 0, sizeof(int), s));
     k_closure<<<nblk(P), TPB, 0, s>>>(L, G.cls, W, B.flags);
+    GP_HIP(hipMemsetAsync(B.flags + 7, 0, sizeof(int), s));
+    k_closure<<<nblk(P), TPB, 0, s>>>(L, G.cls, W, B.flags + 7);
     gp_status st = read_flags(ctx, B, hf);
     if (st) return st;
-    if (!hf[0]) break;
+    if (!hf[7]) break;
     if (it > 64) return GP_EGEOM;
   }
-  k_ext_mark<<<nblk(P), TPB, 0, s>>>(G.cls, G.N, W, ctx->prm.ext_radius);
+  {
+    uint8_t *rowint = reinterpret_cast<uint8_t *>(B.iscr);  // 3 W^2 bytes
+    k_ext_rows_int<<<nblk(P), TPB, 0, s>>>(G.cls, G.N, W, ctx->prm.ext_radius, rowint);
+    k_ext_mark<<<nblk(P), TPB, 0, s>>>(G.cls, G.N, W, ctx->prm.ext_radius, rowint);
+  }
   k_body_to_inactive<<<nblk(P), TPB, 0, s>>>(G.cls, P);
   // ghost rows
   GP_HIP(hipMemsetAsync(B.flags + 2, 0, 2 * sizeof(int), s));
