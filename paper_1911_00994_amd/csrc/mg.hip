@@ -531,6 +531,17 @@ __global__ void __launch_bounds__(BAND_T) k_band_lds(int N, int W, BoxK K, T *x,
   }
   // G's partials early where registers allow (modes 0 and 1 hold more of the region's values in registers)
   const GpPre gpre = MODE >= 2 ? gp_start(gp, ngp) : GpPre{0.0, 0.0};
+  // mode 3 (small bands): this thread's face and written points' positions load with the staging, when there is
+  // at most one face and WB_PRE written points per thread
+  constexpr int WB_PRE = 4;
+  const bool fpre = MODE == 3 && nf <= BAND_T, wpre = MODE == 3 && nregw <= WB_PRE * BAND_T;
+  int pfe = 0, pfc = -1, pw[WB_PRE];
+  if (fpre && tid < nf) {
+    pfe = f_loc[tid];
+    pfc = f_code[tid];
+  }
+#pragma unroll
+  for (int u = 0; u < WB_PRE; u++) pw[u] = (wpre && tid + u * BAND_T < nregw) ? reg_pt[tid + u * BAND_T] : -1;
   // stage the region: batches of BATCH loads in flight per thread (16 at once measured slower on one CU)
   for (int q0 = tid; q0 < nreg; q0 += BATCH * BAND_T) {
     int gi[BATCH];
@@ -643,30 +654,43 @@ __global__ void __launch_bounds__(BAND_T) k_band_lds(int N, int W, BoxK K, T *x,
     ghost_block();
   }
   double fs = 0;
-  for (int q0 = tid; q0 < nf; q0 += BATCH * BAND_T) {
-    int e[BATCH], cd[BATCH];
-    double v[BATCH];
-#pragma unroll
-    for (int u = 0; u < BATCH; u++) {
-      bool in = q0 + u * BAND_T < nf;
-      e[u] = in ? f_loc[q0 + u * BAND_T] : 0;
-      cd[u] = in ? f_code[q0 + u * BAND_T] : -1;
+  if (fpre) {
+    if (pfc >= 0) {
+      const double v = val(pfe);
+      fs = (pfc & 1) ? -v : v;
     }
+  } else {
+    for (int q0 = tid; q0 < nf; q0 += BATCH * BAND_T) {
+      int e[BATCH], cd[BATCH];
+      double v[BATCH];
 #pragma unroll
-    for (int u = 0; u < BATCH; u++) v[u] = val(e[u]);
+      for (int u = 0; u < BATCH; u++) {
+        bool in = q0 + u * BAND_T < nf;
+        e[u] = in ? f_loc[q0 + u * BAND_T] : 0;
+        cd[u] = in ? f_code[q0 + u * BAND_T] : -1;
+      }
 #pragma unroll
-    for (int u = 0; u < BATCH; u++)
-      if (cd[u] >= 0) fs += (cd[u] & 1) ? -v[u] : v[u];
+      for (int u = 0; u < BATCH; u++) v[u] = val(e[u]);
+#pragma unroll
+      for (int u = 0; u < BATCH; u++)
+        if (cd[u] >= 0) fs += (cd[u] & 1) ? -v[u] : v[u];
+    }
   }
   fs = band_block_sum(fs);
   const double gsum = gp_total(MODE >= 2 ? gpre : gp_start(gp, ngp), gp, ngp);
-  for (int q0 = tid; q0 < nregw; q0 += BATCH * BAND_T) {  // only the written points go back
-    int gi[BATCH];
+  if (wpre) {
 #pragma unroll
-    for (int u = 0; u < BATCH; u++) gi[u] = q0 + u * BAND_T < nregw ? reg_pt[q0 + u * BAND_T] : -1;
+    for (int u = 0; u < WB_PRE; u++)
+      if (pw[u] >= 0) x[pw[u]] = xs[tid + u * BAND_T];
+  } else {
+    for (int q0 = tid; q0 < nregw; q0 += BATCH * BAND_T) {  // only the written points go back
+      int gi[BATCH];
 #pragma unroll
-    for (int u = 0; u < BATCH; u++)
-      if (gi[u] >= 0) x[gi[u]] = xs[q0 + u * BAND_T];
+      for (int u = 0; u < BATCH; u++) gi[u] = q0 + u * BAND_T < nregw ? reg_pt[q0 + u * BAND_T] : -1;
+#pragma unroll
+      for (int u = 0; u < BATCH; u++)
+        if (gi[u] >= 0) x[gi[u]] = xs[q0 + u * BAND_T];
+    }
   }
   if (tid == 0) x[3 * WW] = (T)((fs / K.h - gsum) / *mp);
 }
