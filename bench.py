@@ -137,6 +137,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-cycles", type=int, default=8)
     ap.add_argument("--no-kernel-timing", action="store_true")
+    ap.add_argument("--no-prepare", action="store_true",
+                    help="build each step's geometry when the step starts (by default the next step's geometry is "
+                         "built in the background during the current step)")
     ap.add_argument("--graphs", action="store_true",
                     help="replay each solver iteration from a HIP graph (by default the launches are issued from the "
                          "host, with the next cycle's first sweep queued ahead of the convergence test)")
@@ -184,6 +187,8 @@ def main():
         nonlocal t
         t1 = t + dt
         solver.set_levelset_analytic(shape.kind, shape.params, t1, motion)
+        if not args.no_prepare:  # the body's motion is prescribed: the next geometry builds during this step
+            solver.prepare_levelset_analytic(shape.kind, shape.params, t1 + dt, motion)
         st, info = solver.cn_step(dt, fu_d.data_ptr(), fv_d.data_ptr(), None, on_device=True, precision=prec,
                                   tol=args.tol, max_cycles=200, check=False)
         if st != 0:

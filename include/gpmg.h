@@ -129,6 +129,16 @@ const char *gp_last_hip_error(const gp_ctx *ctx);
 gp_status gp_set_levelset(gp_ctx *ctx, const double *phi_half, int on_device, double t, const gp_rigid *motion);
 gp_status gp_set_levelset_analytic(gp_ctx *ctx, const gp_shape *shape, double t, const gp_rigid *motion);
 
+/* Start building, in the background, the geometry gp_set_levelset_analytic(ctx, shape, t, motion) would build
+ * (a moving body's next step is known in advance).  The build runs on a host thread and on streams of a second,
+ * internal context (created at the first call: a second copy of the context's buffers), so it overlaps whatever
+ * the caller runs meanwhile, and it touches neither the context's vectors nor its current geometry.  The next
+ * gp_set_levelset_analytic with the same shape, t and motion (bitwise) takes the prepared geometry instead of
+ * building: it waits for the build, exchanges the two geometries and sets the default boundary data.  Any other
+ * geometry call, and gp_destroy, waits for the build and discards it.  Errors of the background build are not
+ * reported here: gp_set_levelset_analytic then builds as usual and reports them. */
+gp_status gp_prepare_levelset_analytic(gp_ctx *ctx, const gp_shape *shape, double t, const gp_rigid *motion);
+
 /* wall velocities: {bottom u, bottom v, right u, right v, top u, top v, left u, left v} (host array of 8) */
 gp_status gp_set_walls(gp_ctx *ctx, const double *walls8);
 

@@ -58,6 +58,36 @@ gp_status ensure_coarse(Ctx *ctx) {
   return coarse_factor(ctx);
 }
 
+// wait for a background geometry build (gp_prepare_levelset_analytic) and forget it
+void prep_discard(Ctx *ctx) {
+  if (!ctx->prep_active) return;
+  ctx->prep.join();
+  ctx->prep_active = false;
+}
+bool same_shape(const gp_shape &a, const gp_shape &b) {
+  return a.kind == b.kind && a.p[0] == b.p[0] && a.p[1] == b.p[1] && a.p[2] == b.p[2] && a.p[3] == b.p[3];
+}
+bool same_motion(const gp_rigid &a, const gp_rigid &b) {
+  return a.X0x == b.X0x && a.X0y == b.X0y && a.Ux == b.Ux && a.Uy == b.Uy && a.omega == b.omega;
+}
+// the prepared geometry becomes the context's: the two contexts exchange their levels' tables, level set and
+// coarsest inverse (the shadow keeps the old ones, which the next preparation overwrites)
+void take_prepared(Ctx *ctx) {
+  Ctx *sh = ctx->shadow;
+  for (int l = 0; l < ctx->L; l++) std::swap(ctx->geo[l], sh->geo[l]);
+  std::swap(ctx->phi, sh->phi);
+  std::swap(ctx->nc, sh->nc);
+  std::swap(ctx->c_map, sh->c_map);
+  std::swap(ctx->c_bmap, sh->c_bmap);
+  std::swap(ctx->c_A, sh->c_A);
+  std::swap(ctx->c_B, sh->c_B);
+  std::swap(ctx->c_inv, sh->c_inv);
+  std::swap(ctx->c_work, sh->c_work);
+  std::swap(ctx->c_ok, sh->c_ok);
+  ctx->c_ok = ctx->c_ok && ctx->prep_alpha == ctx->alpha;  // factored for the alpha of the time of preparation
+  ctx->have_geom = 1;
+}
+
 gp_status after_geometry(Ctx *ctx) {
   gp_status st = geometry_build(ctx);  // also the coarsest inverse where it can (c_ok)
   if (st) return st;
@@ -112,6 +142,10 @@ int gp_num_levels(const gp_ctx *ctx) { return ctx ? ctx->L : 0; }
 
 void gp_destroy(gp_ctx *ctx) {
   if (!ctx) return;
+  prep_discard(ctx);
+  if (ctx->shadow) gp_destroy(static_cast<gp_ctx *>(ctx->shadow));
+  if (ctx->prep_start) (void)hipEventDestroy(ctx->prep_start);
+  if (ctx->prep_done) (void)hipEventDestroy(ctx->prep_done);
   (void)hipStreamSynchronize(ctx->stream);
   for (int l = 0; l < ctx->L; l++) {
     Geo &G = ctx->geo[l];
@@ -420,6 +454,7 @@ gp_status gp_setup_grid(gp_ctx **out, int N, double Re, const gp_params *prm, vo
 
 gp_status gp_set_levelset(gp_ctx *ctx, const double *phi, int on_device, double t, const gp_rigid *motion) {
   if (!ctx || !phi) return GP_EINVAL;
+  prep_discard(ctx);
   size_t n = (size_t)(2 * ctx->N + 1) * (2 * ctx->N + 1);
   gp_status st = stage_in(ctx, phi, on_device, ctx->phi, n);
   if (st) return st;
@@ -430,11 +465,57 @@ gp_status gp_set_levelset(gp_ctx *ctx, const double *phi, int on_device, double 
 
 gp_status gp_set_levelset_analytic(gp_ctx *ctx, const gp_shape *shape, double t, const gp_rigid *motion) {
   if (!ctx || !shape || shape->kind < 0 || shape->kind > 5) return GP_EINVAL;
+  if (ctx->prep_active) {
+    prep_discard(ctx);
+    const gp_rigid mo = motion ? *motion : gp_rigid{0, 0, 0, 0, 0};
+    if (ctx->prep_status == GP_OK && same_shape(*shape, ctx->prep_shape) && t == ctx->prep_t &&
+        same_motion(mo, ctx->prep_motion)) {
+      GP_HIP(hipStreamWaitEvent(ctx->stream, ctx->prep_done, 0));
+      take_prepared(ctx);
+      ctx->t_geom = t;
+      ctx->motion = mo;
+      return default_boundary_values(ctx);
+    }
+  }
   gp_status st = levelset_analytic(ctx, shape, t, motion);
   if (st) return st;
   ctx->t_geom = t;
   ctx->motion = motion ? *motion : gp_rigid{0, 0, 0, 0, 0};
   return after_geometry(ctx);
+}
+
+gp_status gp_prepare_levelset_analytic(gp_ctx *ctx, const gp_shape *shape, double t, const gp_rigid *motion) {
+  if (!ctx || !shape || shape->kind < 0 || shape->kind > 5) return GP_EINVAL;
+  prep_discard(ctx);
+  if (!ctx->shadow) {
+    gp_ctx *sh = nullptr;
+    gp_status st = gp_setup_grid(&sh, ctx->N, ctx->Re, &ctx->prm, nullptr);
+    if (st) return st;
+    ctx->shadow = sh;
+    GP_HIP(hipEventCreateWithFlags(&ctx->prep_start, hipEventDisableTiming));
+    GP_HIP(hipEventCreateWithFlags(&ctx->prep_done, hipEventDisableTiming));
+  }
+  Ctx *sh = ctx->shadow;
+  sh->alpha = ctx->alpha;  // for its early coarsest factorisation
+  ctx->prep_shape = *shape;
+  ctx->prep_t = t;
+  ctx->prep_motion = motion ? *motion : gp_rigid{0, 0, 0, 0, 0};
+  ctx->prep_alpha = ctx->alpha;
+  // after all work queued on the context's stream so far: it may still read the geometry the shadow holds
+  GP_HIP(hipEventRecord(ctx->prep_start, ctx->stream));
+  GP_HIP(hipStreamWaitEvent(sh->stream, ctx->prep_start, 0));
+  ctx->prep_status = GP_OK;
+  ctx->prep_active = true;
+  const gp_shape shp = *shape;
+  const gp_rigid mo = ctx->prep_motion;
+  ctx->prep = std::thread([ctx, sh, shp, t, mo]() {
+    gp_status st = hipSetDevice(ctx->device) == hipSuccess ? GP_OK : GP_EHIP;
+    if (!st) st = levelset_analytic(sh, &shp, t, &mo);
+    if (!st) st = geometry_build(sh);
+    if (!st && hipEventRecord(ctx->prep_done, sh->stream) != hipSuccess) st = GP_EHIP;
+    ctx->prep_status = st;
+  });
+  return GP_OK;
 }
 
 gp_status gp_set_walls(gp_ctx *ctx, const double *w) {

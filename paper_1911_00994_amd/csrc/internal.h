@@ -4,6 +4,7 @@
 
 #include <cstdint>
 #include <mutex>
+#include <thread>
 #include <string>
 #include <vector>
 
@@ -200,6 +201,15 @@ struct Ctx {
   const double *gs_ptr[MAXLEV] = {nullptr};
   int gs_n[MAXLEV] = {0};
   bool head_queued = false, head_probe = false;
+  // the geometry of a later time built in the background (gp_prepare_levelset_analytic) in a second context
+  Ctx *shadow = nullptr;
+  std::thread prep;
+  bool prep_active = false;
+  gp_status prep_status = GP_OK;
+  gp_shape prep_shape{};
+  double prep_t = 0, prep_alpha = 0;
+  gp_rigid prep_motion{};
+  hipEvent_t prep_start = nullptr, prep_done = nullptr;
 };
 
 // error handling (the message under a lock: the geometry build runs one host thread per level)

@@ -20,7 +20,8 @@ GP_FP64, GP_MIXED = 0, 1
 
 EXPORTS = [
     "gp_default_params", "gp_setup_grid", "gp_destroy", "gp_num_levels", "gp_strerror", "gp_last_hip_error",
-    "gp_set_levelset", "gp_set_levelset_analytic", "gp_set_walls", "gp_get_boundary_geometry",
+    "gp_set_levelset", "gp_set_levelset_analytic", "gp_prepare_levelset_analytic", "gp_set_walls",
+    "gp_get_boundary_geometry",
     "gp_set_boundary_values", "gp_set_alpha", "gp_set_rhs", "gp_set_x", "gp_get_x", "gp_mg_vcycle", "gp_solve",
     "gp_residual", "gp_set_state", "gp_cn_step", "gp_get_classes", "gp_get_ghost_rows", "gp_get_ext_rows",
     "gp_relax", "gp_time_kernel", "gp_probe_start", "gp_probe_stop", "gp_apply_mt", "gp_adjoint_solve", "gp_apply_cycle", "gp_apply_cycle_t",
@@ -87,6 +88,7 @@ def lib():
         "gp_last_hip_error": (ctypes.c_char_p, [vp]),
         "gp_set_levelset": (i, [vp, vp, i, d, ctypes.POINTER(GpRigid)]),
         "gp_set_levelset_analytic": (i, [vp, ctypes.POINTER(GpShape), d, ctypes.POINTER(GpRigid)]),
+        "gp_prepare_levelset_analytic": (i, [vp, ctypes.POINTER(GpShape), d, ctypes.POINTER(GpRigid)]),
         "gp_set_walls": (i, [vp, vp]),
         "gp_get_boundary_geometry": (i, [vp, vp, vp]),
         "gp_set_boundary_values": (i, [vp, vp, vp, vp, i]),
@@ -189,6 +191,14 @@ class Solver:
         m = None if motion is None else GpRigid(*[float(v) for v in list(motion)[:5]])
         st = lib().gp_set_levelset_analytic(self._h, ctypes.byref(sh), t, ctypes.byref(m) if m else None)
         return self._check(st, "gp_set_levelset_analytic") if check else st
+
+    def prepare_levelset_analytic(self, kind, params, t=0.0, motion=None):
+        """start building in the background the geometry that set_levelset_analytic with the same arguments
+        will then take"""
+        sh = GpShape(kind, (ctypes.c_double * 4)(*(list(params) + [0.0] * (4 - len(params)))))
+        m = None if motion is None else GpRigid(*[float(v) for v in list(motion)[:5]])
+        st = lib().gp_prepare_levelset_analytic(self._h, ctypes.byref(sh), t, ctypes.byref(m) if m else None)
+        self._check(st, "gp_prepare_levelset_analytic")
 
     def set_walls(self, walls):
         self._check(lib().gp_set_walls(self._h, _ptr(_host(walls))), "gp_set_walls")

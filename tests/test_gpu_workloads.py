@@ -187,3 +187,41 @@ def test_translating_ellipse_second_order_on_gpu():
     r1, r2 = errs[0] / errs[1], errs[1] / errs[2]
     say(f"  ratios {r1:.2f} {r2:.2f}")
     assert r1 > 3.0 and r2 > 3.0
+
+
+def test_prepared_geometry_matches_geometry_built_in_place():
+    """A moving body's next geometry built in the background during the current step (prepare) and taken by the
+    next set gives the same CN steps as building it in place: rotating flower, N = 128, four steps of dt = h;
+    one preparation for a different time is discarded and the geometry built as usual."""
+    from paper_1911_00994_amd import gpmg
+    N, Re = 128, 400.0
+    h = 2.0 / N
+    dt = h
+    shape = wl.Shape(wl.PETALS, (0.35, 0.07, 0.0, 5.0))
+    mo = [0.0, 0.0, 0.0, 0.0, 1.0]
+    say(f"[prepared geometry] N={N}")
+    fu, fv = wl.fourier_forcing(N, seed=3)
+    z = np.zeros((N + 2, N + 2))
+    runs = []
+    for prepared in (False, True):
+        s = gpmg.Solver(N, Re=Re)
+        s.set_levelset_analytic(shape.kind, shape.params, 0.0, mo)
+        s.set_state(z, z, z, 0.0)
+        out = []
+        t = 0.0
+        for k in range(4):
+            t1 = t + dt
+            s.set_levelset_analytic(shape.kind, shape.params, t1, mo)
+            if prepared:  # the next step's geometry, except once a wrong time (to be discarded)
+                s.prepare_levelset_analytic(shape.kind, shape.params, t1 + (3.0 if k == 1 else 1.0) * dt, mo)
+            st, info = s.cn_step(dt, fu, fv, None, tol=1e-10, max_cycles=200)
+            assert st == 0, info
+            out.append((flat(s.get_x()), s.classes().copy(), info["cycles"]))
+            t = t1
+        runs.append(out)
+        del s
+    for (xa, ca, na), (xb, cb, nb) in zip(*runs):
+        assert np.array_equal(ca, cb)
+        assert na == nb
+        scale = max(1.0, np.abs(xa).max())
+        assert np.abs(xa - xb).max() / scale < 1e-12
