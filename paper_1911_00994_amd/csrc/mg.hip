@@ -941,22 +941,32 @@ __global__ void k_pshift(int W, const uint8_t *__restrict__ cls, T *__restrict__
 // ---------------------------------------------------------------------------------------------------------
 // residual of the point rows (internal momentum and continuity rows, wall identity rows; 0 for every other
 // point, whose row, if any, is a ghost row handled by k_resid_ghost)
+template <typename T, int G>
+__device__ __forceinline__ double resid_int(int W, double h, double a, double d, const T *__restrict__ x,
+                                            const T *__restrict__ b, int t) {
+  // the residual of the internal row t of component G (any padded position at least one cell inside the ring
+  // reads only entries of x)
+  const int WW = W * W, q = t - G * WW;
+  const T *u = x, *v = x + WW, *p = x + 2 * WW;
+  double ih = 1.0 / h;
+  if (G == 0)
+    return (double)b[t] - (d * (double)u[q] - a * ((double)u[q - 1] + (double)u[q + 1] + (double)u[q - W] + (double)u[q + W]) +
+                           ((double)p[q] - (double)p[q - 1]) * ih);
+  if (G == 1)
+    return (double)b[t] - (d * (double)v[q] - a * ((double)v[q - 1] + (double)v[q + 1] + (double)v[q - W] + (double)v[q + W]) +
+                           ((double)p[q] - (double)p[q - W]) * ih);
+  return (double)b[t] - (((double)u[q + 1] - (double)u[q] + (double)v[q + W] - (double)v[q]) * ih - (double)x[3 * WW]);
+}
 template <typename T>
 __device__ __forceinline__ double resid_point(int W, double h, double a, double d, const uint8_t *__restrict__ cls,
                                               const T *__restrict__ x, const T *__restrict__ b, int t) {
   const int WW = W * W;
   uint8_t c = cls[t];
   if (c == K_INT) {
-    int g = t / WW, q = t - g * WW;
-    const T *u = x, *v = x + WW, *p = x + 2 * WW;
-    double ih = 1.0 / h;
-    if (g == 0)
-      return (double)b[t] - (d * (double)u[q] - a * ((double)u[q - 1] + (double)u[q + 1] + (double)u[q - W] + (double)u[q + W]) +
-                             ((double)p[q] - (double)p[q - 1]) * ih);
-    if (g == 1)
-      return (double)b[t] - (d * (double)v[q] - a * ((double)v[q - 1] + (double)v[q + 1] + (double)v[q - W] + (double)v[q + W]) +
-                             ((double)p[q] - (double)p[q - W]) * ih);
-    return (double)b[t] - (((double)u[q + 1] - (double)u[q] + (double)v[q + W] - (double)v[q]) * ih - (double)x[3 * WW]);
+    const int g = t / WW;
+    if (g == 0) return resid_int<T, 0>(W, h, a, d, x, b, t);
+    if (g == 1) return resid_int<T, 1>(W, h, a, d, x, b, t);
+    return resid_int<T, 2>(W, h, a, d, x, b, t);
   }
   if (c == K_WALLD) return (double)b[t] - (double)x[t];
   return 0.0;
@@ -1192,6 +1202,81 @@ __device__ __forceinline__ double restrict_value(int Nf, int Wf, const uint8_t *
 // gp_start) as block partials: gpart[block - b0] = the sum of the restricted continuity right-hand sides of the
 // block's internal cells, for the blocks b0 = 2 Wc^2 / TPB and on (those holding pressure entries; with x = 0
 // the wall Dirichlet faces add nothing).
+// the restricted residual of coarse entry t (restrict_core with the residual formed inline): the classes of the
+// entry's fine points are loaded together, then the values of all its internal ones together (a fine point that is
+// not taken reads a fixed internal position instead), so an entry costs three dependent loads whatever its mix of
+// classes; the sums are formed in restrict_core's order.
+template <typename T>
+__device__ __forceinline__ double resid_restrict_entry(int Nf, int Wf, double h, double a, double d,
+                                                       const uint8_t *__restrict__ clsf, const T *__restrict__ xf,
+                                                       const T *__restrict__ bf, const int *__restrict__ growof,
+                                                       const int *__restrict__ gcol, const double *__restrict__ gw,
+                                                       int Wc, const uint8_t *__restrict__ clsc, int t) {
+  const int WWc = Wc * Wc, WWf = Wf * Wf;
+  const bool xi_entry = t == 3 * WWc;  // the entry of xi restricts to 0
+  const int tt = xi_entry ? 0 : t;
+  const int g = tt / WWc, q = tt - g * WWc, jc = q / Wc - 1, ic = q % Wc - 1;
+  const uint8_t cc = clsc[tt];  // loaded together with the fine classes below (no branch between)
+  const bool taken = !xi_entry && (cc == K_INT || cc == K_GHOST || cc == K_WALLG);
+  const int m = g < 2 ? 6 : 4, safe = g * WWf + pidx(Wf, 0, 0);
+  int kf[6];
+  bool ok[6];
+  double fw[6], rv[6];
+#pragma unroll
+  for (int z = 0; z < 6; z++) {  // u: 2 rows of 3, v: 3 rows of 2, p: 2 x 2
+    const int dx = g == 0 ? z % 3 - 1 : z % 2, dy = g == 0 ? z / 3 : (g == 1 ? z / 2 - 1 : z / 2);
+    const int fi = 2 * ic + dx, fj = 2 * jc + dy;
+    fw[z] = g == 2 ? 0.25 : ((g == 0 ? dx : dy) == 0 ? 0.25 : 0.125);
+    const bool in = z < m && fi >= -1 && fi <= Nf && fj >= -1 && fj <= Nf;
+    kf[z] = in ? g * WWf + pidx(Wf, fi, fj) : safe;
+    ok[z] = in;
+  }
+#pragma unroll
+  for (int z = 0; z < 6; z++) {
+    const uint8_t cz = clsf[kf[z]];  // loaded for every slot (no short circuit)
+    ok[z] = ok[z] & taken & (cz == cc);
+  }
+  if (cc == K_INT) {  // one branch per component, each slot's loads straight-line
+    if (g == 0) {
+#pragma unroll
+      for (int z = 0; z < 6; z++) rv[z] = (double)(T)resid_int<T, 0>(Wf, h, a, d, xf, bf, ok[z] ? kf[z] : safe);
+    } else if (g == 1) {
+#pragma unroll
+      for (int z = 0; z < 6; z++) rv[z] = (double)(T)resid_int<T, 1>(Wf, h, a, d, xf, bf, ok[z] ? kf[z] : safe);
+    } else {
+#pragma unroll
+      for (int z = 0; z < 4; z++) rv[z] = (double)(T)resid_int<T, 2>(Wf, h, a, d, xf, bf, ok[z] ? kf[z] : safe);
+      rv[4] = rv[5] = 0.0;
+    }
+  } else {
+#pragma unroll
+    for (int z = 0; z < 6; z++) {
+      rv[z] = 0.0;
+      if (ok[z]) {
+        const int r = growof[kf[z]];
+        double sw = 0;
+#pragma unroll
+        for (int e = 0; e < 9; e++) sw += gw[9 * r + e] * (double)xf[gcol[9 * r + e]];
+        rv[z] = (double)(T)((double)bf[kf[z]] - sw);
+      }
+    }
+  }
+  if (!taken) return 0.0;
+  bool all = true;
+  int cnt = 0;
+  double sw = 0, sa = 0;
+#pragma unroll
+  for (int z = 0; z < 6; z++) {
+    if (z >= m) break;
+    if (ok[z]) {
+      cnt++;
+      sw += fw[z] * rv[z];
+      sa += rv[z];
+    } else
+      all = false;
+  }
+  return all ? sw : (cnt ? sa / cnt : 0.0);
+}
 template <typename T>
 __global__ void __launch_bounds__(TPB) k_resid_restrict(int Nf, int Wf, double h, double a, double d,
                                                         const uint8_t *__restrict__ clsf, const T *__restrict__ xf,
@@ -1202,14 +1287,7 @@ __global__ void __launch_bounds__(TPB) k_resid_restrict(int Nf, int Wf, double h
   const int t = blockIdx.x * blockDim.x + threadIdx.x, WWc = Wc * Wc;
   double gs = 0;
   if (t <= 3 * WWc) {
-    const T v = (T)restrict_core(Nf, Wf, clsf, Nc, Wc, clsc, t, [&](int kf, uint8_t cc) -> double {
-      if (cc == K_INT) return (double)(T)resid_point<T>(Wf, h, a, d, clsf, xf, bf, kf);
-      const int r = growof[kf];
-      double sw = 0;
-#pragma unroll
-      for (int z = 0; z < 9; z++) sw += gw[9 * r + z] * (double)xf[gcol[9 * r + z]];
-      return (double)(T)((double)bf[kf] - sw);
-    });
+    const T v = (T)resid_restrict_entry<T>(Nf, Wf, h, a, d, clsf, xf, bf, growof, gcol, gw, Wc, clsc, t);
     bc[t] = v;
     xc[t] = (T)0;
     if (t >= 2 * WWc && t < 3 * WWc && clsc[t] == K_INT) gs = (double)v;
@@ -1245,21 +1323,24 @@ __global__ void k_ext_fill(const int *__restrict__ e_pt, const int *__restrict__
 
 // bilinear prolongation of the coarse correction to fine entry t (internal, ghost, extrapolated and wall-ghost
 // points and xi; 0 elsewhere), coarse pressure mirrored outside the box (Sect. 4.3); xcv(kc) is the coarse value
-template <typename XV>
-__device__ __forceinline__ double prolong_value(int Nf, int Wf, const uint8_t *__restrict__ clsf, int Nc, int Wc,
-                                                XV xcv, int t) {
+// the coarse points of fine entry t (an entry of component g below 3 Wf^2) and their bilinear weights, in the
+// order the sum takes them: slot 2 aa + bb for the y offset aa and x offset bb; ok: the slot is used
+struct ProlongSlots {
+  int kc[4];
+  double w[4];
+  bool ok[4];
+};
+__device__ __forceinline__ ProlongSlots prolong_slots(int Nf, int Wf, int Nc, int Wc, int t) {
   const int WWf = Wf * Wf, WWc = Wc * Wc;
-  if (t == 3 * WWf) return xcv(3 * WWc);
-  uint8_t c = clsf[t];
-  if (!(c == K_INT || c == K_GHOST || c == K_GHOSTX || c == K_WALLG)) return 0.0;
   int g = t / WWf, q = t - g * WWf, j = q / Wf - 1, i = q % Wf - 1;
   int xi_[2], yi_[2];
   double xw[2], yw[2];
   int nx, ny;
   if (g == 0) {  // faces along x
     if ((i & 1) == 0) {
-      xi_[0] = i / 2;
+      xi_[0] = xi_[1] = i / 2;
       xw[0] = 1;
+      xw[1] = 0;
       nx = 1;
     } else {
       xi_[0] = (i - 1) / 2;
@@ -1281,8 +1362,9 @@ __device__ __forceinline__ double prolong_value(int Nf, int Wf, const uint8_t *_
   }
   if (g == 1) {  // faces along y
     if ((j & 1) == 0) {
-      yi_[0] = j / 2;
+      yi_[0] = yi_[1] = j / 2;
       yw[0] = 1;
+      yw[1] = 0;
       ny = 1;
     } else {
       yi_[0] = (j - 1) / 2;
@@ -1302,17 +1384,35 @@ __device__ __forceinline__ double prolong_value(int Nf, int Wf, const uint8_t *_
     yw[1] = 0.25;
     ny = 2;
   }
-  double e = 0;
-  for (int aa = 0; aa < ny; aa++)
-    for (int bb = 0; bb < nx; bb++) {
+  ProlongSlots S;
+#pragma unroll
+  for (int aa = 0; aa < 2; aa++)
+#pragma unroll
+    for (int bb = 0; bb < 2; bb++) {
+      const int z = 2 * aa + bb;
       int ic = xi_[bb], jc = yi_[aa];
       if (g == 2) {  // pressure outside the box mirrored
         ic = ic < 0 ? 0 : (ic > Nc - 1 ? Nc - 1 : ic);
         jc = jc < 0 ? 0 : (jc > Nc - 1 ? Nc - 1 : jc);
       }
-      if (ic < -1 || ic > Nc || jc < -1 || jc > Nc) continue;
-      e += xw[bb] * yw[aa] * xcv(g * WWc + pidx(Wc, ic, jc));
+      S.ok[z] = aa < ny && bb < nx && ic >= -1 && ic <= Nc && jc >= -1 && jc <= Nc;
+      S.kc[z] = g * WWc + (S.ok[z] ? pidx(Wc, ic, jc) : pidx(Wc, 0, 0));
+      S.w[z] = xw[bb] * yw[aa];
     }
+  return S;
+}
+template <typename XV>
+__device__ __forceinline__ double prolong_value(int Nf, int Wf, const uint8_t *__restrict__ clsf, int Nc, int Wc,
+                                                XV xcv, int t) {
+  const int WWf = Wf * Wf, WWc = Wc * Wc;
+  if (t == 3 * WWf) return xcv(3 * WWc);
+  uint8_t c = clsf[t];
+  if (!(c == K_INT || c == K_GHOST || c == K_GHOSTX || c == K_WALLG)) return 0.0;
+  const ProlongSlots S = prolong_slots(Nf, Wf, Nc, Wc, t);
+  double e = 0;
+#pragma unroll
+  for (int z = 0; z < 4; z++)
+    if (S.ok[z]) e += S.w[z] * xcv(S.kc[z]);
   return e;
 }
 // With erow, the coarse extension points take their extrapolation from the sources here, rounded to TC as
@@ -1325,16 +1425,37 @@ __global__ void __launch_bounds__(TPB) k_prolong(int Nf, int Wf, const uint8_t *
                                                  const int *__restrict__ erow, const int *__restrict__ esrc,
                                                  const double *__restrict__ ew) {
   int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t > 3 * Wf * Wf) return;
-  const double e = prolong_value(Nf, Wf, clsf, Nc, Wc, [&](int kc) -> double {
-    if (erow && clsc[kc] == K_EXT) {
-      const int r = erow[kc];
-      return (double)(TC)(ew[3 * r] * (double)xc[esrc[3 * r]] + ew[3 * r + 1] * (double)xc[esrc[3 * r + 1]] +
-                          ew[3 * r + 2] * (double)xc[esrc[3 * r + 2]]);
+  const int WWf = Wf * Wf;
+  if (t > 3 * WWf) return;
+  if (t == 3 * WWf) {  // xi
+    xf[t] = (TF)((double)xf[t] + (double)xc[3 * Wc * Wc]);
+    return;
+  }
+  // every load of the entry is issued before any test (a slot that is not used reads a fixed coarse point)
+  const ProlongSlots S = prolong_slots(Nf, Wf, Nc, Wc, t);
+  const uint8_t c = clsf[t];
+  const double xft = (double)xf[t];
+  double xv[4];
+  bool ext[4];
+#pragma unroll
+  for (int z = 0; z < 4; z++) {
+    xv[z] = (double)xc[S.kc[z]];
+    ext[z] = erow != nullptr && clsc[S.kc[z]] == K_EXT;
+  }
+  if (!(c == K_INT || c == K_GHOST || c == K_GHOSTX || c == K_WALLG)) return;
+  double e = 0;
+#pragma unroll
+  for (int z = 0; z < 4; z++) {
+    if (!S.ok[z]) continue;
+    double v = xv[z];
+    if (ext[z]) {
+      const int r = erow[S.kc[z]];
+      v = (double)(TC)(ew[3 * r] * (double)xc[esrc[3 * r]] + ew[3 * r + 1] * (double)xc[esrc[3 * r + 1]] +
+                       ew[3 * r + 2] * (double)xc[esrc[3 * r + 2]]);
     }
-    return (double)xc[kc];
-  }, t);
-  if (e != 0.0 || t == 3 * Wf * Wf) xf[t] = (TF)((double)xf[t] + e);
+    e += S.w[z] * v;
+  }
+  if (e != 0.0) xf[t] = (TF)(xft + e);
 }
 
 // exact coarsest solve with the stored inverse: x[map[q]] = sum_r Ainv[q][r] b[map[r]] (one wavefront per row)
