@@ -915,10 +915,11 @@ __global__ void __launch_bounds__(RD_T) k_pmean(int W, const uint8_t *__restrict
     uint8_t c[RD_U];
     double v[RD_U];
 #pragma unroll
-    for (int u = 0; u < RD_U; u++) {
-      const int t = t0 + u * stride;
-      c[u] = t < WW ? cls[2 * WW + t] : (uint8_t)K_INACTIVE;
-      v[u] = t < WW ? (double)x[2 * WW + t] : 0.0;
+    for (int u = 0; u < RD_U; u++) {  // loads at a clamped position: none waits for a test
+      const int t = t0 + u * stride, tc = min(t, WW - 1);
+      const uint8_t cv = cls[2 * WW + tc];
+      v[u] = (double)x[2 * WW + tc];
+      c[u] = t < WW ? cv : (uint8_t)K_INACTIVE;
     }
 #pragma unroll
     for (int u = 0; u < RD_U; u++)
@@ -932,8 +933,9 @@ __global__ void k_pshift(int W, const uint8_t *__restrict__ cls, T *__restrict__
   const int WW = W * W;
   int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= WW) return;
-  uint8_t c = cls[2 * WW + t];
-  if (c == K_INT || c == K_GHOST || c == K_GHOSTX) x[2 * WW + t] = (T)((double)x[2 * WW + t] - *mean);
+  const uint8_t c = cls[2 * WW + t];
+  const double v = (double)x[2 * WW + t], m = *mean;  // loaded with the class
+  if (c == K_INT || c == K_GHOST || c == K_GHOSTX) x[2 * WW + t] = (T)(v - m);
 }
 
 // ---------------------------------------------------------------------------------------------------------
@@ -998,11 +1000,18 @@ __global__ void __launch_bounds__(TPB) k_resid_pts_norm(int W, double h, double 
   if ((int)blockIdx.x < nbp) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t < 3 * WW) {
+      // the loads of the internal row go out with the class (at a fixed internal position where this point's
+      // row would read outside its component), then the class picks the row
+      const int g = t / WW, q = t - g * WW;
+      const int k = q > W && q < WW - W - 1 ? t : g * WW + W + 1;
       const uint8_t c = cls[t];
+      const double bt = (double)b[t], xt = (double)x[t];
+      const double ri = g == 0 ? resid_int<T, 0>(W, h, a, d, x, b, k)
+                                : (g == 1 ? resid_int<T, 1>(W, h, a, d, x, b, k) : resid_int<T, 2>(W, h, a, d, x, b, k));
       if (c != K_GHOST && c != K_GHOSTX && c != K_WALLG) {
-        res = resid_point<T>(W, h, a, d, cls, x, b, t);
+        res = c == K_INT ? ri : (c == K_WALLD ? bt - xt : 0.0);
         if (store) r[t] = (T)res;
-        if (t >= 2 * WW && c == K_INT) ps += (double)x[t];
+        if (t >= 2 * WW && c == K_INT) ps += xt;
       }
     }
   } else {
