@@ -718,7 +718,8 @@ __global__ void __launch_bounds__(BAND_T) k_xi_faces(int WW, double h, T *x, con
 struct SecTabs {
   int poff[SEC_MAX + 1], boff[5 * SEC_MAX + 1], goff[SEC_MAX + 1], ooff[SEC_MAX + 1];
 };
-template <typename T>
+// GST: the sector's ghost-row tables are staged in LDS with the region (the sweeps then read no global memory)
+template <typename T, bool GST>
 __global__ void __launch_bounds__(BAND_T) k_band_sec(int N, int W, BoxK K, const T *x, T *xw,
                                                      const T *__restrict__ b, int S, SecTabs tb,
                                                      const int *__restrict__ spt, const uint16_t *__restrict__ bsl,
@@ -743,6 +744,8 @@ __global__ void __launch_bounds__(BAND_T) k_band_sec(int N, int W, BoxK K, const
   T *xs = reinterpret_cast<T *>(lds_raw);
   double *nv = reinterpret_cast<double *>(lds_raw + ((np * sizeof(T) + 7) & ~(size_t)7));
   double *gb = nv + ng;
+  double *gws = gb + ng, *gdts = gws + 9 * ng;              // GST: 9 weights field-major, dtau
+  uint16_t *gls = reinterpret_cast<uint16_t *>(gdts + ng);  // GST: own + 9 column slots, field-major
   for (int q0 = tid; q0 < np; q0 += BATCH * BAND_T) {
     int gi[BATCH];
     T vv[BATCH];
@@ -754,20 +757,35 @@ __global__ void __launch_bounds__(BAND_T) k_band_sec(int N, int W, BoxK K, const
     for (int u = 0; u < BATCH; u++)
       if (q0 + u * BAND_T < np) xs[q0 + u * BAND_T] = vv[u];
   }
-  for (int k = tid; k < ng; k += BAND_T) gb[k] = (double)b[gk[g0 + k]];
+  for (int k = tid; k < ng; k += BAND_T) {
+    gb[k] = (double)b[gk[g0 + k]];
+    if (GST) {
+#pragma unroll
+      for (int z = 0; z < 9; z++) gws[z * ng + k] = gw[z * gstride + g0 + k];
+#pragma unroll
+      for (int z = 0; z < 10; z++) gls[z * ng + k] = gl[z * gstride + g0 + k];
+      gdts[k] = gdt[g0 + k];
+    }
+  }
   const double xi = (double)x[3 * WW];
   __syncthreads();
   auto ghost_block = [&]() {
     for (int it = 0; it < lambda; it++) {
       for (int k = tid; k < ng; k += BAND_T) {
-        const int idx = g0 + k;
         double sum = 0;
+        if (GST) {
 #pragma unroll
-        for (int z = 0; z < 9; z++) sum += gw[z * gstride + idx] * (double)xs[gl[(1 + z) * gstride + idx]];
-        nv[k] = (double)xs[gl[idx]] + gdt[idx] * (gb[k] - sum);
+          for (int z = 0; z < 9; z++) sum += gws[z * ng + k] * (double)xs[gls[(1 + z) * ng + k]];
+          nv[k] = (double)xs[gls[k]] + gdts[k] * (gb[k] - sum);
+        } else {
+          const int idx = g0 + k;
+#pragma unroll
+          for (int z = 0; z < 9; z++) sum += gw[z * gstride + idx] * (double)xs[gl[(1 + z) * gstride + idx]];
+          nv[k] = (double)xs[gl[idx]] + gdt[idx] * (gb[k] - sum);
+        }
       }
       __syncthreads();
-      for (int k = tid; k < ng; k += BAND_T) xs[gl[g0 + k]] = (T)nv[k];
+      for (int k = tid; k < ng; k += BAND_T) xs[GST ? gls[k] : gl[g0 + k]] = (T)nv[k];
       __syncthreads();
     }
   };
@@ -1792,8 +1810,8 @@ static void relax(Ctx *ctx, int l) {
   }
   const bool band = ctx->prm.bnd_sweeps > 0 && G.nband > 0;
   const size_t lds_bytes = (size_t)G.nreg * sizeof(T);
-  if (band && G.sec_S > 0 &&
-      (size_t)G.sec_maxreg * sizeof(T) + 2 * (size_t)G.sec_maxrow * sizeof(double) + 1024 <= ctx->max_lds) {
+  const size_t sec_base = ((G.sec_maxreg * sizeof(T) + 7) & ~(size_t)7) + 2 * (size_t)G.sec_maxrow * sizeof(double);
+  if (band && G.sec_S > 0 && sec_base + 1024 <= ctx->max_lds) {
     // a large band over angular sectors, one workgroup each, plus the wall rows; then write-back and xi
     SecTabs tb;
     for (int q = 0; q <= G.sec_S; q++) {
@@ -1802,9 +1820,13 @@ static void relax(Ctx *ctx, int l) {
       tb.ooff[q] = G.sec_ooff[q];
     }
     for (int q = 0; q <= 5 * G.sec_S; q++) tb.boff[q] = G.sec_boff[q];
-    const size_t lds = ((G.sec_maxreg * sizeof(T) + 7) & ~(size_t)7) + 2 * (size_t)G.sec_maxrow * sizeof(double);
+    // the ghost-row tables join the region in LDS where they fit (9 weights and dtau, 10 slots per row)
+    const size_t lds_g = sec_base + (size_t)G.sec_maxrow * (10 * sizeof(double) + 10 * sizeof(uint16_t));
+    const bool gst = lds_g + 1024 <= ctx->max_lds;
+    const size_t lds = gst ? lds_g : sec_base;
     const int nwb = (G.nwg + BAND_T - 1) / BAND_T;
-    k_band_sec<T><<<G.sec_S + nwb, BAND_T, lds, s>>>(
+    auto kern = gst ? k_band_sec<T, true> : k_band_sec<T, false>;
+    kern<<<G.sec_S + nwb, BAND_T, lds, s>>>(
         G.N, G.W, BK, V.x, V.x, V.b, G.sec_S, tb, G.sec_pt, G.sec_bsl, G.sec_bfl, G.sec_bcell, G.sec_bcap, G.sec_gl,
         G.sec_gw, G.sec_gdt, G.sec_gk, G.sec_gcap, G.sec_own_loc, G.sec_own_g, G.sec_out, G.g_pt, G.g_col, G.g_w,
         G.g_dtau, G.wg_rows, G.nwg, ctx->prm.bnd_sweeps, ctx->prm.lambda_ghost);
