@@ -767,6 +767,13 @@ __global__ void __launch_bounds__(BAND_T) k_band_sec(int N, int W, BoxK K, const
       gdts[k] = gdt[g0 + k];
     }
   }
+  // the cell of this thread's first box of the next colour is loaded one colour ahead, so that the right-hand
+  // sides of the box go out together with its table
+  auto first_cell_of = [&](int c) {
+    const int q = tb.boff[5 * sec + c] + tid;
+    return q < tb.boff[5 * sec + c + 1] ? bcell[q] : 0;
+  };
+  int next_cell = first_cell_of(0);
   const double xi = (double)x[3 * WW];
   __syncthreads();
   auto ghost_block = [&]() {
@@ -792,9 +799,12 @@ __global__ void __launch_bounds__(BAND_T) k_band_sec(int N, int W, BoxK K, const
   ghost_block();
   for (int sw = 0; sw < sweeps; sw++) {
     for (int c = 0; c < 5; c++) {
+      const int first_cell = next_cell;
+      next_cell = first_cell_of(c == 4 ? 0 : c + 1);
       for (int q = tb.boff[5 * sec + c] + tid; q < tb.boff[5 * sec + c + 1]; q += BAND_T) {
         auto TB = [&](int fld) { return (int)bsl[fld * bstride + q]; };
-        const int cell = bcell[q], i = cell % N, j = cell / N, cg = (j + 1) * W + (i + 1);
+        const int cell = q == tb.boff[5 * sec + c] + tid ? first_cell : bcell[q];
+        const int i = cell % N, j = cell / N, cg = (j + 1) * W + (i + 1);
         const int f = bfl[q];
         const bool fW = f & 1, fE = f & 2, fS = f & 4, fN = f & 8, fP = f & 16;
         const double bW_ = b[cg], bE_ = b[cg + 1], bS_ = b[WW + cg], bN_ = b[WW + cg + W], bP_ = b[2 * WW + cg];
