@@ -1257,8 +1257,14 @@ gp_status sector_build(Ctx *ctx, int l) {
   const double R = (lam * (reach + 1) + nsw * (5 * 3 + lam * (reach + 1)) + 2) * std::sqrt(2.0) * G.h;
   if (!(rmin > 0) || R >= 2.0 * rmin) return GP_OK;
   sg.delta = 2.0 * std::asin(R / (2.0 * rmin));
-  sg.S = 8;
+  // SEC_MAX sectors where no point falls in more than four of them (smaller regions to stage per workgroup),
+  // else 8
+  sg.S = SEC_MAX;
   sg.w = 2.0 * M_PI / sg.S;
+  if (2.0 * sg.delta > 2.5 * sg.w) {
+    sg.S = 8;
+    sg.w = 2.0 * M_PI / sg.S;
+  }
   if (2.0 * sg.delta > 2.5 * sg.w) return GP_OK;  // more than four sectors per point
   const int S = sg.S;
   int *cnt_b = ic, *cnt_g = ic + 5 * S, *cnt_p = ic + 6 * S, *cnt_o = ic + 7 * S, *bad = ic + 8 * S;
