@@ -182,6 +182,11 @@ gp_status gp_get_classes(gp_ctx *ctx, int level, unsigned char *cls);
 gp_status gp_get_ghost_rows(gp_ctx *ctx, int level, double *B, double *nB, double *theta, double *w9, int *col9,
                             double *dtau, int *kind);
 gp_status gp_get_ext_rows(gp_ctx *ctx, int level, int *src3, double *w3);
+/* inspection (tests): the boundary band of one level as the current geometry laid it out (Sect. 4.1, the extra
+ * band relaxation): out[0] band cells, out[1] body ghost rows, out[2] angular sectors the band is relaxed over
+ * (0: not in sectors), out[3] 1 when the band fits the one-workgroup LDS kernel.  out is a host array of 4 ints.
+ * GP_EINVAL for a NULL argument, a level out of range or no geometry yet. */
+gp_status gp_get_band_layout(gp_ctx *ctx, int level, int *out);
 /* relaxation steps (Alg. relax with nu = steps) on one level in FP64, on that level's current x and b */
 gp_status gp_relax(gp_ctx *ctx, int level, int steps);
 

@@ -140,6 +140,16 @@ const char *gp_last_hip_error(const gp_ctx *ctx) { return ctx ? ctx->hip_err.c_s
 
 int gp_num_levels(const gp_ctx *ctx) { return ctx ? ctx->L : 0; }
 
+gp_status gp_get_band_layout(gp_ctx *ctx, int level, int *out) {
+  if (!ctx || !out || level < 0 || level >= ctx->L || !ctx->have_geom) return GP_EINVAL;
+  const Geo &G = ctx->geo[level];
+  out[0] = G.nband;
+  out[1] = G.nbg;
+  out[2] = G.sec_S;
+  out[3] = G.lds_ok;
+  return GP_OK;
+}
+
 void gp_destroy(gp_ctx *ctx) {
   if (!ctx) return;
   prep_discard(ctx);

@@ -24,6 +24,7 @@ EXPORTS = [
     "gp_get_boundary_geometry",
     "gp_set_boundary_values", "gp_set_alpha", "gp_set_rhs", "gp_set_x", "gp_get_x", "gp_mg_vcycle", "gp_solve",
     "gp_residual", "gp_set_state", "gp_cn_step", "gp_get_classes", "gp_get_ghost_rows", "gp_get_ext_rows",
+    "gp_get_band_layout",
     "gp_relax", "gp_time_kernel", "gp_probe_start", "gp_probe_stop", "gp_apply_mt", "gp_adjoint_solve", "gp_apply_cycle", "gp_apply_cycle_t",
     "gp_tape_forward", "gp_tape_backward",
 ]
@@ -102,6 +103,7 @@ def lib():
         "gp_set_state": (i, [vp, vp, vp, vp, d, i]),
         "gp_cn_step": (i, [vp, d, vp, vp, vp, i, i, d, i, d, i, ctypes.POINTER(GpStats)]),
         "gp_get_classes": (i, [vp, i, vp]),
+        "gp_get_band_layout": (i, [vp, i, vp]),
         "gp_get_ghost_rows": (i, [vp, i, vp, vp, vp, vp, vp, vp, vp]),
         "gp_get_ext_rows": (i, [vp, i, vp, vp]),
         "gp_relax": (i, [vp, i, i]),
@@ -302,6 +304,12 @@ class Solver:
         out = np.zeros(3 * W * W, dtype=np.uint8)
         self._check(lib().gp_get_classes(self._h, level, _ptr(out)), "gp_get_classes")
         return out.reshape(3, W, W)
+
+    def band_layout(self, level=0):
+        """Band cells, body ghost rows, angular sectors (0: none) and whether the one-workgroup kernel fits."""
+        out = np.zeros(4, dtype=np.int32)
+        self._check(lib().gp_get_band_layout(self._h, level, _ptr(out)), "gp_get_band_layout")
+        return {"nband": int(out[0]), "nbg": int(out[1]), "sectors": int(out[2]), "lds_ok": bool(out[3])}
 
     def ghost_rows(self, level=0):
         W = self.level_n(level) + 2

@@ -176,6 +176,9 @@ def test_band_sectors_against_single_band_layouts(N):
         s.set_levelset_analytic(FLOWER.kind, FLOWER.params, 0.0, mo[:5])
         s.set_alpha(h / 800.0)
         s.set_rhs(fu, fv, None)
+        lay = s.band_layout(0)
+        # sixteen sectors where the margin allows it (N = 1024), eight otherwise; none when sectors are off
+        assert lay["sectors"] == ((16 if N >= 1024 else 8) if smin == 1500 else 0), lay
         res = [s.cycle() for _ in range(3)]
         out.append((flat(s.get_x()), res))
         cls = s.classes().ravel()
