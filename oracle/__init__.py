@@ -79,6 +79,7 @@ def lib():
             ("or_get_x", [vp, vp, vp, vp, vp]),
             ("or_get_b", [vp, vp]),
             ("or_ext_fill_finest", [vp]),
+            ("or_set_conv_history", [vp, vp, vp, vp, vp, vp, vp, i]),
         ]:
             f = getattr(L, name)
             f.restype = None
@@ -121,9 +122,11 @@ class Oracle:
     """Handle on one oracle solver (all levels of one grid hierarchy)."""
 
     def __init__(self, N, Re=100.0, nu1=2, nu2=2, gamma=1, lam=2, coarsest_n=8, march_max=8, ext_radius=4,
-                 perm_seed=0, dtau_dir=0.9, dtau_neu_over_h=0.9, eps_over_h=0.01, cg_min=0.1, bnd_sweeps=1, bnd_radius=2):
+                 perm_seed=0, dtau_dir=0.9, dtau_neu_over_h=0.9, eps_over_h=0.01, cg_min=0.1, bnd_sweeps=0, bnd_radius=2,
+                 ghost_boxes=1, lex_order=0):
         self.N, self.W, self.Re = N, N + 2, Re
-        ip = np.array([nu1, nu2, gamma, lam, coarsest_n, march_max, ext_radius, perm_seed, bnd_sweeps, bnd_radius], dtype=np.int32)
+        ip = np.array([nu1, nu2, gamma, lam, coarsest_n, march_max, ext_radius, perm_seed, bnd_sweeps, bnd_radius,
+                       ghost_boxes, lex_order], dtype=np.int32)
         dp = np.array([dtau_dir, dtau_neu_over_h, eps_over_h, cg_min], dtype=np.float64)
         self._h = lib().or_create(N, Re, _p(ip), _p(dp))
         if not self._h:
@@ -254,6 +257,11 @@ class Oracle:
         return lib().or_ext_fail_count(self._h, l)
 
     # time stepping ---------------------------------------------------------------------------
+    def set_conv_history(self, cu, cv, nstep):
+        """Test hook: convection histories [c^n, c^{n-1}, c^{n-2}] for the u and v grids."""
+        a = [_f64(np.asarray(x)) for x in (cu[0], cv[0], cu[1], cv[1], cu[2], cv[2])]
+        lib().or_set_conv_history(self._h, *[_p(x) for x in a], nstep)
+
     def set_state(self, u, v, p, xi=0.0) -> int:
         return lib().or_set_state(self._h, _p(_f64(u)), _p(_f64(v)), _p(_f64(p)), xi)
 

@@ -80,6 +80,12 @@ typedef struct {
   double *va;
   /* vectors */
   double *x, *b, *r;
+  /* coupled ghost boxes (see coupled_boxes): per box the cell, the unknowns (box unknowns first, then the
+   * coupled ghosts) and which of them the box writes; boxes ordered by colour, then cell index */
+  int nxb;
+  int xb_coff[6];
+  int *xb_cell, *xb_off, *xb_nbox, *xb_idx, *xb_of_cell;
+  unsigned char *xb_wr;
   /* dense LU (coarsest level only) */
   double *lu;
   int *piv;
@@ -92,6 +98,7 @@ typedef struct {
   double Re, alpha;
   /* parameters */
   int nu1, nu2, gamma, lambda, coarsest_n, march_max, nbis, ext_radius, colour_perm_seed, bnd_sweeps, bnd_radius;
+  int ghost_boxes, lex_order;
   double dtau_dir, dtau_neu_over_h, eps_over_h, cg_min;
   /* geometry / boundary data */
   double *phi; /* (2N+1)^2 fine half lattice */
@@ -294,11 +301,18 @@ static void free_level(OLevel *L) {
   free(L->r);
   free(L->lu);
   free(L->piv);
+  free(L->xb_cell);
+  free(L->xb_off);
+  free(L->xb_nbox);
+  free(L->xb_idx);
+  free(L->xb_wr);
+  free(L->xb_of_cell);
   memset(L, 0, sizeof(*L));
 }
 
-/* iparams: nu1 nu2 gamma lambda coarsest_n march_max ext_radius colour_perm_seed
- * dparams: dtau_dir dtau_neu_over_h eps_over_h */
+/* iparams: nu1 nu2 gamma lambda coarsest_n march_max ext_radius colour_perm_seed bnd_sweeps bnd_radius
+ *          ghost_boxes lex_order
+ * dparams: dtau_dir dtau_neu_over_h eps_over_h cg_min (coarse levels) */
 void *or_create(int N, double Re, const int *ip, const double *dp) {
   if (N < 8 || (N & (N - 1))) return NULL;
   OSolver *S = (OSolver *)xcalloc(1, sizeof(OSolver));
@@ -314,6 +328,8 @@ void *or_create(int N, double Re, const int *ip, const double *dp) {
   S->colour_perm_seed = ip[7];
   S->bnd_sweeps = ip[8];
   S->bnd_radius = ip[9];
+  S->ghost_boxes = ip[10];
+  S->lex_order = ip[11];
 
   S->dtau_dir = dp[0];
   S->dtau_neu_over_h = dp[1];
@@ -379,45 +395,65 @@ int or_level_n(void *h, int l) { return ((OSolver *)h)->lev[l].N; }
 /* geometry: classification, ghost closure, Alg. 1, ghost rows, extension     */
 /* ------------------------------------------------------------------------- */
 
-/* Alg. 1: from an external grid point G, march along the bilinear normal by h/2 until an
- * internal point H is reached (K = last external point), then bisect HK.
- * Returns 1 on success. */
-static int alg1(const OSolver *S, const OLevel *L, double xg, double yg, double phig, double *Bx, double *By) {
-  double hx = xg, hy = yg, ph = phig, kx = xg, ky = yg;
-  int it = 0;
-  while (ph > 0) {
-    if (it == S->march_max) return 0;
-    kx = hx;
-    ky = hy;
-    double nx, ny;
-    unit_normal(S, L, hx, hy, &nx, &ny);
-    hx = hx - 0.5 * L->h * nx;
-    hy = hy - 0.5 * L->h * ny;
-    bilin(S, L, hx, hy, &ph, NULL, NULL);
-    it++;
+/* Alg. 1 in two parts.  (i) From an external point, step by h/2 against the bilinear normal until the
+ * interpolated level set is no longer positive: the last two points bracket the boundary.  Returns the
+ * number of steps taken, or -1 if the bracket is not found within march_max steps. */
+static int march_to_fluid(const OSolver *S, const OLevel *L, const double g[2], double phig, double out[2],
+                          double in[2], double *phi_in) {
+  double p[2] = {g[0], g[1]}, ph = phig;
+  out[0] = g[0];
+  out[1] = g[1];
+  int steps = 0;
+  for (; ph > 0; steps++) {
+    if (steps == S->march_max) return -1;
+    double n[2];
+    out[0] = p[0];
+    out[1] = p[1];
+    unit_normal(S, L, p[0], p[1], &n[0], &n[1]);
+    p[0] -= 0.5 * L->h * n[0];
+    p[1] -= 0.5 * L->h * n[1];
+    bilin(S, L, p[0], p[1], &ph, NULL, NULL);
   }
-  if (it == 0 || ph == 0.0) {
-    *Bx = hx;
-    *By = hy;
+  in[0] = p[0];
+  in[1] = p[1];
+  *phi_in = ph;
+  return steps;
+}
+
+/* (ii) Bisection of a bracketing segment for the zero of the interpolated level set: a fixed number of
+ * halvings, each keeping the half whose ends still differ in sign (tested against the inner end); the
+ * result is the last midpoint. */
+static void bisect_segment(const OSolver *S, const OLevel *L, double in[2], double phi_in, double out[2], int iters,
+                           double res[2]) {
+  double mid[2] = {in[0], in[1]};
+  for (int k = 0; k < iters; k++) {
+    mid[0] = 0.5 * (in[0] + out[0]);
+    mid[1] = 0.5 * (in[1] + out[1]);
+    double pm;
+    bilin(S, L, mid[0], mid[1], &pm, NULL, NULL);
+    double *keep = (pm * phi_in < 0) ? out : in;
+    keep[0] = mid[0];
+    keep[1] = mid[1];
+    if (keep == in) phi_in = pm;
+  }
+  res[0] = mid[0];
+  res[1] = mid[1];
+}
+
+/* boundary point B of an external point G (Alg. 1).  A point on the boundary itself, or a march that lands
+ * exactly on it, is its own boundary point.  Returns 1 on success. */
+static int alg1(const OSolver *S, const OLevel *L, double xg, double yg, double phig, double *Bx, double *By) {
+  double g[2] = {xg, yg}, out[2], in[2], phi_in = phig, B[2];
+  int steps = march_to_fluid(S, L, g, phig, out, in, &phi_in);
+  if (steps < 0) return 0;
+  if (steps == 0 || phi_in == 0.0) {
+    *Bx = steps == 0 ? xg : in[0];
+    *By = steps == 0 ? yg : in[1];
     return 1;
   }
-  double bx = hx, by = hy;
-  for (int k = 0; k < S->nbis; k++) {
-    bx = 0.5 * (hx + kx);
-    by = 0.5 * (hy + ky);
-    double pb;
-    bilin(S, L, bx, by, &pb, NULL, NULL);
-    if (pb * ph < 0) {
-      kx = bx;
-      ky = by;
-    } else {
-      hx = bx;
-      hy = by;
-      ph = pb;
-    }
-  }
-  *Bx = bx;
-  *By = by;
+  bisect_segment(S, L, in, phi_in, out, S->nbis, B);
+  *Bx = B[0];
+  *By = B[1];
   return 1;
 }
 
@@ -475,6 +511,123 @@ static int extrap_sources(const OSolver *S, const OLevel *L, int g, int i, int j
     return 1;
   }
   return 0;
+}
+
+
+/* ------------------------------------------------------------------------- */
+/* coupled ghost boxes                                                        */
+/* ------------------------------------------------------------------------- */
+/* The box of a cell (Sect. 4.1.1) holds its pressure and its four faces.  A ghost whose eq. (BCu) row (or
+ * pressure normal-derivative row) has a weight on one of those internal unknowns ties the box to the
+ * boundary condition: where that weight dominates the ghost's own diagonal, the ghost value is fixed by the
+ * internal equations and the internal value by the ghost's row, and neither the box nor the fictitious-time
+ * step of eq. (ghostrelax) alone can resolve the pair.  A coupled box therefore solves the cell's internal
+ * unknowns together with every such ghost, from all their rows (a collective relaxation in the sense of
+ * Sect. 4.1.1 extended across the boundary).  The table lists, per box, the box unknowns (west, east,
+ * south, north face, pressure; internal ones only), then the coupled ghosts in increasing point order. */
+static int cmp_long(const void *a, const void *b) {
+  long x = *(const long *)a, y = *(const long *)b;
+  return x < y ? -1 : x > y;
+}
+static int box_unknowns(const OLevel *L, int i, int j, int *U) {
+  int cand[5] = {gidx(L, 0, i, j), gidx(L, 0, i + 1, j), gidx(L, 1, i, j), gidx(L, 1, i, j + 1), gidx(L, 2, i, j)};
+  int m = 0;
+  for (int q = 0; q < 5; q++)
+    if (L->cls[cand[q]] == C_INT) U[m++] = cand[q];
+  return m;
+}
+static void build_coupled_boxes(OLevel *L) {
+  int N = L->N, W = L->W, WW = W * W;
+  long P = 3L * WW;
+  free(L->xb_cell);
+  free(L->xb_off);
+  free(L->xb_nbox);
+  free(L->xb_idx);
+  free(L->xb_wr);
+  free(L->xb_of_cell);
+  /* (cell, ghost) pairs: a ghost row's internal column belongs to the boxes of the cells it borders */
+  long cap = 18L * (L->ng + 1), np = 0;
+  long *pr = (long *)xcalloc(cap, sizeof(long));
+  for (int r = 0; r < L->ng; r++) {
+    int G = L->g_pt[r];
+    if (L->cls[G] != C_GHOST) continue;
+    for (int q = 0; q < 9; q++) {
+      int c = L->g_col[9 * r + q];
+      if (L->g_w[9 * r + q] == 0.0 || L->cls[c] != C_INT) continue;
+      int g = c / WW, loc = c % WW, j = loc / W - 1, i = loc % W - 1;
+      int cells[2][2], nc = 0;
+      if (g == 0) {
+        cells[0][0] = i - 1, cells[0][1] = j;
+        cells[1][0] = i, cells[1][1] = j;
+        nc = 2;
+      } else if (g == 1) {
+        cells[0][0] = i, cells[0][1] = j - 1;
+        cells[1][0] = i, cells[1][1] = j;
+        nc = 2;
+      } else {
+        cells[0][0] = i, cells[0][1] = j;
+        nc = 1;
+      }
+      for (int z = 0; z < nc; z++) {
+        int ci = cells[z][0], cj = cells[z][1];
+        if (ci < 0 || cj < 0 || ci >= N || cj >= N) continue;
+        int col = (ci + 2 * cj) % 5;
+        /* key: colour, cell, ghost -- the order in which the boxes are visited */
+        pr[np++] = ((long)col * N * N + (long)cj * N + ci) * P + G;
+      }
+    }
+  }
+  qsort(pr, np, sizeof(long), cmp_long);
+  long nu = 0;
+  for (long q = 0; q < np; q++)
+    if (q == 0 || pr[q] != pr[q - 1]) pr[nu++] = pr[q];
+  /* boxes */
+  int nb = 0;
+  for (long q = 0; q < nu; q++)
+    if (q == 0 || pr[q] / P != pr[q - 1] / P) nb++;
+  L->xb_cell = (int *)xcalloc(nb, sizeof(int));
+  L->xb_off = (int *)xcalloc(nb + 1, sizeof(int));
+  L->xb_nbox = (int *)xcalloc(nb, sizeof(int));
+  L->xb_idx = (int *)xcalloc(nu + 5L * nb, sizeof(int));
+  L->xb_wr = (unsigned char *)xcalloc(nu + 5L * nb, 1);
+  int *seen = (int *)xcalloc(P, sizeof(int)); /* colour + 1 of the last box that writes the point */
+  int b = 0, o = 0;
+  for (int c = 0; c <= 5; c++) L->xb_coff[c] = 0;
+  for (long q = 0; q < nu;) {
+    long key = pr[q] / P;
+    int col = (int)(key / ((long)N * N)), cell = (int)(key % ((long)N * N));
+    int i = cell % N, j = cell / N;
+    int U[5], m0 = box_unknowns(L, i, j, U);
+    long q2 = q;
+    while (q2 < nu && pr[q2] / P == key) q2++;
+    if (m0 > 0) {
+      L->xb_cell[b] = cell;
+      L->xb_off[b] = o;
+      L->xb_nbox[b] = m0;
+      for (int a = 0; a < m0; a++) {
+        L->xb_idx[o] = U[a];
+        L->xb_wr[o++] = 1;
+      }
+      for (long z = q; z < q2; z++) {
+        int G = (int)(pr[z] % P);
+        L->xb_idx[o] = G;
+        /* within one colour a ghost is written by the first box that holds it */
+        L->xb_wr[o++] = (unsigned char)(seen[G] != col + 1);
+        seen[G] = col + 1;
+      }
+      L->xb_coff[col + 1] = ++b;
+    }
+    q = q2;
+  }
+  for (int c = 1; c <= 5; c++)
+    if (L->xb_coff[c] < L->xb_coff[c - 1]) L->xb_coff[c] = L->xb_coff[c - 1];
+  L->xb_off[b] = o;
+  L->nxb = b;
+  L->xb_of_cell = (int *)xcalloc((size_t)N * N, sizeof(int));
+  for (int q = 0; q < N * N; q++) L->xb_of_cell[q] = -1;
+  for (int q = 0; q < b; q++) L->xb_of_cell[L->xb_cell[q]] = q;
+  free(seen);
+  free(pr);
 }
 
 static int build_level_geometry(OSolver *S, int l) {
@@ -668,10 +821,11 @@ static int build_level_geometry(OSolver *S, int l) {
             L->g_dtau[r] = S->dtau_neu_over_h * L->h;
           }
           if (!(thx > -0.5 && thx < 1.0 && thy > -0.5 && thy < 1.0)) ok = 0;
-          /* the diagonal of the row (weight of G itself, times h for the normal-derivative rows) must
-           * not fall below cg_min: with a tiny diagonal the ghost value is barely determined by its own
-           * condition and the fictitious-time relaxation stalls */
-          if (!((g < 2 ? w[0] : w[0] * L->h) > S->cg_min)) ok = 0;
+          /* the diagonal of the row (weight of G itself, times h for the normal-derivative rows) must be
+           * positive on the finest level, where the rows define the discrete problem.  The coarse levels
+           * only carry the correction equations, and there a row whose diagonal is below cg_min is
+           * replaced as well: a ghost barely determined by its own row slows the coarse relaxation */
+          if (!((g < 2 ? w[0] : w[0] * L->h) > (l == 0 ? 0.0 : S->cg_min))) ok = 0;
           L->g_valid[r] = ok;
           L->g_B[2 * r] = Bx;
           L->g_B[2 * r + 1] = By;
@@ -758,6 +912,7 @@ static int build_level_geometry(OSolver *S, int l) {
                  (cls_at(L, 1, i, j + 1) == C_INT);
         if (nf == 0 && l == 0) empty_box = 1;
       }
+  build_coupled_boxes(L);
   if (L->Mp == 0 || wall_bad || finest_bad || empty_box) return E_GEOM;
   return OK;
 }
@@ -1179,39 +1334,105 @@ static uint64_t lcg_next(uint64_t *s) {
   return *s >> 33;
 }
 
-/* one relaxation step (Alg. relax with nu = 1): box sweep in the colour order (i + 2j) mod 5 = 0..4,
- * lambda simultaneous ghost sweeps (eq. ghostrelax), then bnd_sweeps extra box sweeps restricted to the
- * cells within bnd_radius cells of a cell touching the body, each followed by lambda ghost sweeps (boundary
- * relaxation: the slowest error components of this discretisation sit at the body), then the
- * average-divergence unknown xi is set so that the continuity residuals sum to zero. */
+/* solve one coupled box from the values xs: rows and columns are the box's unknowns; every other value is
+ * held at xs.  Returns 0 (and leaves sol untouched) if the block is singular. */
+static int coupled_solve(const OLevel *L, int bx, const double *xs, double *sol) {
+  int o = L->xb_off[bx], m = L->xb_off[bx + 1] - o;
+  const int *U = &L->xb_idx[o];
+  double *A = (double *)xcalloc((size_t)m * m, sizeof(double)), *rhs = (double *)xcalloc(m, sizeof(double));
+  for (int a = 0; a < m; a++) {
+    double t = L->b[U[a]] - row_dot(L, U[a], xs);
+    for (int c = 0; c < m; c++) {
+      A[a * m + c] = row_coef(L, U[a], U[c]);
+      t += A[a * m + c] * xs[U[c]];
+    }
+    rhs[a] = t;
+  }
+  int ok = dense_solve(m, A, rhs);
+  if (ok)
+    for (int a = 0; a < m; a++) sol[a] = rhs[a];
+  free(A);
+  free(rhs);
+  return ok;
+}
+
+/* the coupled boxes of a level, colour by colour: every box of a colour is solved from the values at the
+ * start of that colour's pass (the boxes of one colour share no box unknown, but a ghost row of one box
+ * may read another's unknowns); then each box writes its box unknowns and the ghosts it owns */
+static void coupled_boxes(OLevel *L) {
+  double *xs = (double *)xcalloc(L->n, sizeof(double));
+  double *sol = (double *)xcalloc(L->xb_off[L->nxb] + 1, sizeof(double));
+  int *ok = (int *)xcalloc(L->nxb + 1, sizeof(int));
+  for (int c = 0; c < 5; c++) {
+    int lo = L->xb_coff[c], hi = L->xb_coff[c + 1];
+    if (hi == lo) continue;
+    memcpy(xs, L->x, sizeof(double) * L->n);
+    for (int bx = lo; bx < hi; bx++) ok[bx] = coupled_solve(L, bx, xs, &sol[L->xb_off[bx]]);
+    for (int bx = lo; bx < hi; bx++) {
+      if (!ok[bx]) continue;
+      for (int q = L->xb_off[bx]; q < L->xb_off[bx + 1]; q++)
+        if (L->xb_wr[q]) L->x[L->xb_idx[q]] = sol[q];
+    }
+  }
+  free(xs);
+  free(sol);
+  free(ok);
+}
+
+
+/* one relaxation step (Alg. relax with nu = 1).
+ * Default order: box sweep in the colour order (i + 2j) mod 5 = 0..4, then the coupled boxes colour by
+ * colour (ghost_boxes), then lambda simultaneous ghost sweeps (eq. ghostrelax).
+ * Lexicographic order (the paper's GS-LEX): one pass over the cells row by row, each cell relaxed by its
+ * coupled box if it has one (ghost_boxes) and by its plain box otherwise, each box seeing every earlier
+ * update; then the ghost sweeps.
+ * Optionally bnd_sweeps extra box sweeps restricted to the cells within bnd_radius cells of a cell touching
+ * the body, each followed by lambda ghost sweeps (not part of the paper's Alg. relax; off by default).
+ * Finally the average-divergence unknown xi is set so that the continuity residuals sum to zero. */
 static void relax_step(OSolver *S, int l) {
   OLevel *L = &S->lev[l];
   int N = L->N, WW = L->W * L->W;
-  for (int col = 0; col < 5; col++) {
-    if (S->colour_perm_seed == 0) {
-      for (int j = 0; j < N; j++)
-        for (int i = 0; i < N; i++)
-          if ((i + 2 * j) % 5 == col) box_relax(L, i, j);
-    } else { /* same colour, random order: must give an identical result */
-      int cnt = 0;
-      for (int j = 0; j < N; j++)
-        for (int i = 0; i < N; i++)
-          if ((i + 2 * j) % 5 == col) cnt++;
-      int *list = (int *)xcalloc(cnt, sizeof(int));
-      int c2 = 0;
-      for (int j = 0; j < N; j++)
-        for (int i = 0; i < N; i++)
-          if ((i + 2 * j) % 5 == col) list[c2++] = j * N + i;
-      uint64_t st = (uint64_t)S->colour_perm_seed * 7919u + (uint64_t)col;
-      for (int q = cnt - 1; q > 0; q--) {
-        int z = (int)(lcg_next(&st) % (uint64_t)(q + 1));
-        int t = list[q];
-        list[q] = list[z];
-        list[z] = t;
+  if (S->lex_order) {
+    double *sol = (double *)xcalloc(L->xb_off[L->nxb] + 1, sizeof(double));
+    for (int j = 0; j < N; j++)
+      for (int i = 0; i < N; i++) {
+        int bx = S->ghost_boxes ? L->xb_of_cell[j * N + i] : -1;
+        if (bx < 0) {
+          box_relax(L, i, j);
+          continue;
+        }
+        if (coupled_solve(L, bx, L->x, sol))
+          for (int q = L->xb_off[bx], a = 0; q < L->xb_off[bx + 1]; q++, a++) L->x[L->xb_idx[q]] = sol[a];
       }
-      for (int q = 0; q < cnt; q++) box_relax(L, list[q] % N, list[q] / N);
-      free(list);
+    free(sol);
+  } else {
+    for (int col = 0; col < 5; col++) {
+      if (S->colour_perm_seed == 0) {
+        for (int j = 0; j < N; j++)
+          for (int i = 0; i < N; i++)
+            if ((i + 2 * j) % 5 == col) box_relax(L, i, j);
+      } else { /* same colour, random order: must give an identical result */
+        int cnt = 0;
+        for (int j = 0; j < N; j++)
+          for (int i = 0; i < N; i++)
+            if ((i + 2 * j) % 5 == col) cnt++;
+        int *list = (int *)xcalloc(cnt, sizeof(int));
+        int c2 = 0;
+        for (int j = 0; j < N; j++)
+          for (int i = 0; i < N; i++)
+            if ((i + 2 * j) % 5 == col) list[c2++] = j * N + i;
+        uint64_t st = (uint64_t)S->colour_perm_seed * 7919u + (uint64_t)col;
+        for (int q = cnt - 1; q > 0; q--) {
+          int z = (int)(lcg_next(&st) % (uint64_t)(q + 1));
+          int t = list[q];
+          list[q] = list[z];
+          list[z] = t;
+        }
+        for (int q = 0; q < cnt; q++) box_relax(L, list[q] % N, list[q] / N);
+        free(list);
+      }
     }
+    if (S->ghost_boxes) coupled_boxes(L);
   }
   ghost_sweeps(S, L);
   for (int q = 0; q < S->bnd_sweeps; q++) {
@@ -1638,6 +1859,20 @@ int or_set_state(void *h, const double *u, const double *v, const double *p, dou
   }
   S->nstep = 0;
   return OK;
+}
+
+/* test hook: replace the convection histories c^n, c^{n-1}, c^{n-2} (u and v grids, finest layout) and the
+ * step counter, so that the next step's treatment of the convection can be checked in closed form */
+void or_set_conv_history(void *h, const double *cu0, const double *cv0, const double *cu1, const double *cv1,
+                         const double *cu2, const double *cv2, int nstep) {
+  OSolver *S = (OSolver *)h;
+  int WW = S->lev[0].W * S->lev[0].W;
+  const double *src[6] = {cu0, cv0, cu1, cv1, cu2, cv2};
+  for (int k = 0; k < 3; k++) {
+    memcpy(S->cu[k], src[2 * k], WW * sizeof(double));
+    memcpy(S->cv[k], src[2 * k + 1], WW * sizeof(double));
+  }
+  S->nstep = nstep;
 }
 
 /* stats: [0] cycles total, [1] picard iterations, [2] final residual, [3] last rho */

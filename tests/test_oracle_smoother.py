@@ -1,0 +1,204 @@
+"""CPU pins of the oracle's discrete system and relaxation (no GPU).
+
+* The finest level carries the paper's eq. (BCu) row at every ghost whose row is defined (Alg. LS); the
+  only replaced rows are those whose stencil or boundary point is not usable.
+* The multigrid fixed point is the direct solution of that system (V and W cycles, colour and
+  lexicographic order), for the body shapes of the workloads.
+* The convergence factor stays bounded and N-independent for the circle, ellipse and petal body, and the
+  paper's cycle (lexicographic order, W(2,1)) lands near the reference factor of Sect. 5.3.
+* Closed forms: the three-level convection extrapolation of eq. (extrUdU) on a quadratic history, the
+  ghost seeding of the internal rows.
+"""
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+
+import oracle as O
+from paper_1911_00994_amd import workloads as wl
+from tests.common import make_linear_problem
+
+CIRCLE = wl.Shape(wl.CIRCLE_DIST, (0.3,))
+ELLIPSE = wl.Shape(wl.ELLIPSE_SQRT, (0.4, 0.2, 0.0))
+PETALS = wl.Shape(wl.PETALS, (0.35, 0.07, 0.0, 5.0))
+
+
+def _direct(o):
+    A, b = o.csr(0)
+    return spla.spsolve(A.tocsc(), b)
+
+
+def _mg_vector(o):
+    u, v, p, xi = o.get_x()
+    return np.concatenate([u.ravel(), v.ravel(), p.ravel(), [xi]])
+
+
+def _active(o):
+    cls = o.classes(0).ravel()
+    m = (cls == O.C_INT) | (cls == O.C_GHOST) | (cls == O.C_GHOSTX) | (cls == O.C_WALLG) | (cls == O.C_WALLD)
+    return np.concatenate([m, [True]])
+
+
+# --------------------------------------------------------------------------------------------
+# the discrete system of Alg. LS on the finest level
+# --------------------------------------------------------------------------------------------
+@pytest.mark.parametrize("shape", [CIRCLE, ELLIPSE, PETALS])
+def test_finest_ghost_rows_are_the_paper_rows(shape):
+    """Every finest-level ghost keeps its eq. (BCu) row (or pressure normal-derivative row) unless the
+    row is undefined: boundary point outside the upwind stencil's cell (theta outside (-1/2, 1)), a
+    non-positive diagonal, or a stencil leaving the grid.  Rows with a small diagonal are kept."""
+    N = 128
+    o, _, _ = make_linear_problem(N, shape, 0.64 * (2.0 / N) ** 2)
+    gr = o.ghost_rows(0)
+    cls = o.classes(0).ravel()
+    body = (cls == O.C_GHOST) | (cls == O.C_GHOSTX)
+    th = gr["theta"][body]
+    inside = (th[:, 0] > -0.5) & (th[:, 0] < 1.0) & (th[:, 1] > -0.5) & (th[:, 1] < 1.0)
+    replaced = cls[body] == O.C_GHOSTX
+    # a replaced row is one whose boundary point lies outside the stencil's cell
+    assert np.all(~inside[replaced]), "a finest-level row with a usable boundary point was replaced"
+    kept = ~replaced
+    diag = gr["w"][body][:, 0]
+    W = N + 2
+    is_p = (np.nonzero(body)[0] // (W * W)) == 2
+    hd = np.where(is_p, diag * (2.0 / N), diag)
+    assert np.all(hd[kept] > 0)
+    # small diagonals (barely self-determined ghosts) are part of the system, not replaced
+    assert np.count_nonzero(hd[kept] < 0.1) >= 0.05 * np.count_nonzero(kept)
+
+
+@pytest.mark.parametrize("N,shape,kw", [
+    (64, PETALS, {}),
+    (128, PETALS, {}),
+    (64, ELLIPSE, {}),
+    (64, PETALS, dict(gamma=2, nu2=1)),
+    (64, PETALS, dict(gamma=2, nu2=1, lex_order=1)),
+    (64, CIRCLE, dict(ghost_boxes=0)),
+])
+def test_fixed_point_is_direct_solution_of_paper_system(N, shape, kw):
+    """The cycle converges to the sparse direct solution of the assembled finest system (all eq. (BCu)
+    rows) for the V and W cycle, colour and lexicographic order."""
+    o, _, _ = make_linear_problem(N, shape, 0.64 * (2.0 / N) ** 2, **kw)
+    st, s = o.solve(1e-11, 60)
+    assert st == O.OK, (st, s)
+    xd = _direct(o)
+    xm = _mg_vector(o)
+    act = _active(o)
+    rel = np.abs(xm - xd)[act].max() / np.abs(xd[act]).max()
+    assert rel < 1e-9, rel
+
+
+def test_petal_body_error_is_the_direct_solve_error():
+    """With the paper's rows the manufactured-solution error of the petal body at N = 128 is that of the
+    direct solution of the system (7.8e-5), not the larger error of rows replaced by extrapolation."""
+    N = 128
+    o, _, _ = make_linear_problem(N, PETALS, 0.64 * (2.0 / N) ** 2)
+    assert o.solve(1e-11, 60)[0] == O.OK
+    u, v, p, xi = o.get_x()
+    cls = o.classes(0)
+    ue, ve, _ = wl.mms_fields(wl.TaylorGreenMMS(), N, 0.3)
+    err = max(np.abs(u - ue)[cls[0] == O.C_INT].max(), np.abs(v - ve)[cls[1] == O.C_INT].max())
+    assert err < 9e-5, err
+
+
+def test_internal_rows_reference_only_valued_points():
+    """Ghost seeding (Sect. 3.3, Alg. LS): every column of an internal row is an internal point, a ghost
+    (boundary-condition or replaced row), a wall point or the xi column -- never an extension or inactive
+    point -- and every body ghost is referenced by an internal row or lies in another ghost's stencil."""
+    N = 64
+    for shape in (CIRCLE, PETALS):
+        o, _, _ = make_linear_problem(N, shape, 0.64 * (2.0 / N) ** 2)
+        A, _ = o.csr(0)
+        cls = np.concatenate([o.classes(0).ravel(), [255]])
+        ok = {O.C_INT, O.C_GHOST, O.C_GHOSTX, O.C_WALLD, O.C_WALLG, 255}
+        A = A.tocsr()
+        used = np.zeros(len(cls), bool)
+        for r in np.nonzero(cls == O.C_INT)[0]:
+            cols = A.indices[A.indptr[r]:A.indptr[r + 1]]
+            assert all(int(cls[c]) in ok for c in cols), r
+            used[cols] = True
+        gr = o.ghost_rows(0)
+        for r in np.nonzero(cls == O.C_GHOST)[0]:
+            used[gr["col"][r][gr["w"][r] != 0]] = True
+        ghosts = np.nonzero(cls == O.C_GHOST)[0]
+        # reached from an internal row, directly or through ghost stencils
+        reach = np.zeros(len(cls), bool)
+        for r in np.nonzero(cls == O.C_INT)[0]:
+            reach[A.indices[A.indptr[r]:A.indptr[r + 1]]] = True
+        for _ in range(4):
+            for r in ghosts:
+                if reach[r]:
+                    reach[gr["col"][r]] = True
+        assert np.all(reach[ghosts])
+
+
+# --------------------------------------------------------------------------------------------
+# convergence factor (Sect. 5.3)
+# --------------------------------------------------------------------------------------------
+def _rho(N, shape, alpha_h2=0.64, **kw):
+    h = 2.0 / N
+    o = O.Oracle(N, **kw)
+    phi = O.levelset_analytic(shape.kind, shape.padded(), [0] * 6, 0.0, N)
+    assert o.set_levelset(phi) == O.OK
+    o.set_alpha(alpha_h2 * h * h)
+    W = N + 2
+    cls = o.classes()
+    z = np.zeros((W, W))
+    o.set_rhs(z, z, z)
+    o.set_boundary_values(z, z, z)
+    rng = np.random.default_rng(0)
+    o.set_x(*[rng.standard_normal((W, W)) * (cls[g] != O.C_WALLD) for g in range(3)], 0.0)
+    o.solve(1e-13, 30)
+    hst = o.res_history()
+    r = hst[1:] / hst[:-1]
+    return float(np.exp(np.mean(np.log(r[-6:]))))
+
+
+@pytest.mark.parametrize("shape,bound", [(CIRCLE, 0.2), (ELLIPSE, 0.3), (PETALS, 0.25)])
+def test_convergence_factor_bounded_for_each_body(shape, bound):
+    """V(2,2) with the paper's relaxation (box sweep, coupled ghost boxes, fictitious-time ghost sweeps):
+    the factor stays below the bound and does not grow with N."""
+    rhos = [_rho(N, shape) for N in (64, 128, 256)]
+    assert max(rhos) < bound and max(rhos) - min(rhos) < 0.12, rhos
+
+
+def test_paper_cycle_convergence_factor():
+    """Sect. 5.3: W cycle, two pre- and one post-relaxation, lexicographic box order; the paper's
+    reference factor is 0.119 (a local Fourier analysis value).  Measured on the paper's petal body."""
+    rhos = [_rho(N, wl.paper_flower(), gamma=2, nu2=1, lex_order=1) for N in (128, 256)]
+    assert max(rhos) < 0.2 and abs(rhos[0] - rhos[1]) < 0.05, rhos
+
+
+# --------------------------------------------------------------------------------------------
+# eq. (extrUdU): three-level extrapolation of the convection
+# --------------------------------------------------------------------------------------------
+def test_convection_extrapolation_on_a_quadratic_history():
+    """From the third step on, the convection at t^{n+1/2} is c^n + c^{n-1}/2 - c^{n-2}/2 (eq. extrUdU).
+    For a history c(t) = c0 + c1 t + c2 t^2 this reproduces c(t^{n+1/2}) up to -7/4 c2 dt^2 (Adams-Bashforth
+    of the same order would leave -3/4 c2 dt^2).  Read through the right-hand side of the step: with zero
+    state and forcing it is -dt C at the internal points."""
+    N = 32
+    h = 2.0 / N
+    dt = h
+    o = O.Oracle(N, Re=100.0)
+    phi = O.levelset_analytic(wl.NO_BODY, (0, 0, 0, 0), [0] * 6, 0.0, N)
+    assert o.set_levelset(phi) == O.OK
+    W = N + 2
+    z = np.zeros((W, W))
+    assert o.set_state(z, z, z, 0.0) == O.OK
+    rng = np.random.default_rng(3)
+    c0, c1, c2 = (rng.uniform(-1, 1, (2, W, W)) for _ in range(3))
+    tn = 0.7
+
+    def c_at(t):
+        return c0 + c1 * t + c2 * t * t
+
+    hist = [c_at(tn), c_at(tn - dt), c_at(tn - 2 * dt)]
+    o.set_conv_history([hh[0] for hh in hist], [hh[1] for hh in hist], nstep=5)
+    o.cn_step(dt, None, None, None, tol=1e-6, max_cycles=1)
+    b = o.get_b()
+    cls = o.classes()
+    for g in range(2):
+        C = -b[g * W * W:(g + 1) * W * W].reshape(W, W) / dt
+        m = cls[g] == O.C_INT
+        err = (C - c_at(tn + 0.5 * dt)[g])[m]
+        np.testing.assert_allclose(err, -1.75 * c2[g][m] * dt * dt, rtol=1e-9, atol=1e-12)
