@@ -69,7 +69,8 @@ enum { GP_INACTIVE = 0, GP_INTERNAL = 1, GP_GHOST = 2, GP_WALL_DIRICHLET = 3, GP
  * sweeps) over the cells within bnd_radius = 2 cells of a cell touching the body.  The last five fields
  * choose how the same computation is laid out on the device (results agree to rounding): fuse_small_levels = 1
  * runs the cycle of the levels with N <= 32 in one workgroup with their data in LDS, band_split_min = 3000: a
- * boundary band with at least that many cells is relaxed with device-wide launches instead of one workgroup,
+ * boundary band with at least that many cells, and the coupled boxes of a level with a colour of at least that many
+ * slots, are relaxed with device-wide launches instead of one workgroup,
  * band_sector_min = 1500: a band with at least that many cells is relaxed by angular sectors, one workgroup each
  * (where the band lies far enough from its centre; otherwise as above),
  * graph_iterations = 0; 1 captures the launches of one solver iteration (cycle, mean projection, residual
@@ -84,6 +85,7 @@ typedef struct {
   int mixed_inner_cycles; /* FP32 cycles per FP64 refinement step in GP_MIXED solves */
   int bnd_sweeps, bnd_radius;
   int fuse_small_levels, band_split_min, graph_iterations, band_sector_min, queue_ahead;
+  int ghost_boxes; /* 1: coupled ghost boxes in every relaxation step (see above); 0: plain boxes only */
 } gp_params;
 
 /* rigid motion: the body frame point of x at time t is R(-omega t) (x - X0 - U t); the boundary velocity at a
@@ -187,6 +189,15 @@ gp_status gp_get_ext_rows(gp_ctx *ctx, int level, int *src3, double *w3);
  * (0: not in sectors), out[3] 1 when the band fits the one-workgroup LDS kernel.  out is a host array of 4 ints.
  * GP_EINVAL for a NULL argument, a level out of range or no geometry yet. */
 gp_status gp_get_band_layout(gp_ctx *ctx, int level, int *out);
+/* inspection (tests): the coupled ghost boxes of one level (see gp_params.ghost_boxes) in the order a relaxation
+ * step visits them (colour (i + 2j) mod 5, then cell index).  counts (host int[2]) receives the number of boxes and
+ * of slots (box unknowns, summed over the boxes); each other argument may be NULL: cell[boxes] the cell j*N + i,
+ * off[boxes + 1] each box's first slot, idx[slots] the unknown of each slot (global index g*W*W + point: the
+ * internal W, E, S, N face and pressure of the cell, then the box's ghosts in increasing order), wr[slots] 1 where
+ * the box writes that value (a ghost held by several boxes of one colour is written by the first), colour_off[6]
+ * the first box of each colour.  GP_EINVAL for a NULL counts, a level out of range or no geometry yet. */
+gp_status gp_get_coupled_boxes(gp_ctx *ctx, int level, int *counts, int *cell, int *off, int *idx, unsigned char *wr,
+                               int *colour_off);
 /* relaxation steps (Alg. relax with nu = steps) on one level in FP64, on that level's current x and b */
 gp_status gp_relax(gp_ctx *ctx, int level, int steps);
 

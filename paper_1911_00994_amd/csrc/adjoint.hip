@@ -271,6 +271,57 @@ __global__ void k_gadj_b(const int *__restrict__ col, const double *__restrict__
   for (int z = 0; z < 9; z++) atomicAdd(&xb[col[9 * r + z]], -w[9 * r + z] * t);
 }
 
+// transposed coupled boxes of one colour.  Forward: x_k <- x_k + sum_c Ainv[a_k][c] r_c over the written slots k of
+// each box, r = b - M x on the box's rows, all boxes of the colour from the same x.  Transposed: t_c = sum over the
+// written slots k of Ainv[a_k][c] xbar_k (all boxes first), then bbar on row c += t_c and xbar -= t_c (row c of M).
+__global__ void k_xbt_t(int lo, int hi, const int *__restrict__ idx, const int *__restrict__ box, const int *__restrict__ off,
+                        const int *__restrict__ ioff, const uint8_t *__restrict__ wr, const uint8_t *__restrict__ ok,
+                        const double *__restrict__ inv, const double *__restrict__ xb, double *t) {
+  const int s = lo + blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= hi) return;
+  const int bx = box[s], o = off[bx], m = off[bx + 1] - o, c = s - o;
+  double v = 0;
+  if (ok[bx]) {
+    const double *iv = inv + ioff[bx];
+    for (int q = 0; q < m; q++)
+      if (wr[o + q]) v += iv[(size_t)q * m + c] * xb[idx[o + q]];
+  }
+  t[s] = v;
+}
+__global__ void k_xbt_scatter(int lo, int hi, int W, double h, double a, double d, const uint8_t *__restrict__ cls,
+                              const int *__restrict__ idx, const int *__restrict__ g_rowof, const int *__restrict__ g_col,
+                              const double *__restrict__ g_w, const double *__restrict__ t, double *xb, double *bb) {
+  const int s = lo + blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= hi) return;
+  const double v = t[s];
+  if (v == 0.0) return;
+  const int k = idx[s], WW = W * W;
+  atomicAdd(&bb[k], v);
+  if (cls[k] == K_INT) {
+    const int g = k / WW, q = k - g * WW;
+    const double ih = 1.0 / h;
+    if (g < 2) {
+      atomicAdd(&xb[k], -v * d);
+      atomicAdd(&xb[k - 1], v * a);
+      atomicAdd(&xb[k + 1], v * a);
+      atomicAdd(&xb[k - W], v * a);
+      atomicAdd(&xb[k + W], v * a);
+      atomicAdd(&xb[2 * WW + q], -v * ih);
+      atomicAdd(&xb[2 * WW + q - (g == 0 ? 1 : W)], v * ih);
+    } else {
+      atomicAdd(&xb[q + 1], -v * ih);
+      atomicAdd(&xb[q], v * ih);
+      atomicAdd(&xb[WW + q + W], -v * ih);
+      atomicAdd(&xb[WW + q], v * ih);
+      atomicAdd(&xb[3 * WW], v);  // the -xi column
+    }
+    return;
+  }
+  const int r = g_rowof[k];
+#pragma unroll
+  for (int z = 0; z < 9; z++) atomicAdd(&xb[g_col[9 * r + z]], -v * g_w[9 * r + z]);
+}
+
 // transposed xi update: xi = (sum over internal cells of (div u - g)) / mp
 __global__ void k_take(double *src, double *dst) {
   *dst = *src;
@@ -605,7 +656,25 @@ static void ghost_sweep_t(Ctx *ctx, int l) {
   k_gadj_b<<<nblk(G.ng), TPB, 0, ctx->stream>>>(G.g_col, G.g_w, G.ng, ctx->gtmp, A.x);
 }
 
-// reverse of: box colours 0..4, lambda ghost sweeps, [band colours 0..4, lambda ghost sweeps] x bnd_sweeps, xi
+// reverse of the coupled boxes of level l (colours 4..0)
+static void xb_relax_t(Ctx *ctx, int l) {
+  Geo &G = ctx->geo[l];
+  if (!ctx->prm.ghost_boxes || !G.nxb) return;
+  Vec<double> &A = ctx->adj[l];
+  hipStream_t s = ctx->stream;
+  const double a = coef_a_l(ctx, l), d = 1.0 + 4.0 * a;
+  for (int c = 4; c >= 0; c--) {
+    const int lo = G.xb_soff[c], hi = G.xb_soff[c + 1];
+    if (hi == lo) continue;
+    k_xbt_t<<<nblk(hi - lo), TPB, 0, s>>>(lo, hi, G.xb_idx, G.xb_box, G.xb_off, G.xb_ioff, G.xb_wr, G.xb_ok, G.xb_inv, A.x,
+                                        G.xb_r);
+    k_xbt_scatter<<<nblk(hi - lo), TPB, 0, s>>>(lo, hi, G.W, G.h, a, d, G.cls, G.xb_idx, G.g_rowof, G.g_col, G.g_w, G.xb_r,
+                                              A.x, A.b);
+  }
+}
+
+// reverse of: box colours 0..4, coupled boxes, lambda ghost sweeps, [band colours 0..4, lambda ghost sweeps] x
+// bnd_sweeps, xi
 static void relax_t(Ctx *ctx, int l) {
   Geo &G = ctx->geo[l];
   Vec<double> &A = ctx->adj[l];
@@ -621,6 +690,7 @@ static void relax_t(Ctx *ctx, int l) {
     }
   }
   for (int it = 0; it < lam; it++) ghost_sweep_t(ctx, l);
+  xb_relax_t(ctx, l);
   for (int c = 4; c >= 0; c--) box_colour_t(ctx, l, c, false);
 }
 
@@ -665,6 +735,8 @@ static gp_status ready(Ctx *ctx) {
     gp_status st = coarse_factor(ctx);
     if (st) return st;
   }
+  gp_status st = ensure_xb(ctx);
+  if (st) return st;
   return adjoint_alloc(ctx);
 }
 

@@ -114,13 +114,14 @@ void gp_default_params(gp_params *p) {
   p->bisect_eps_over_h = 0.01;
   p->cg_min = 0.1;
   p->mixed_inner_cycles = 2;
-  p->bnd_sweeps = 1;
+  p->bnd_sweeps = 0;
   p->bnd_radius = 2;
   p->fuse_small_levels = 1;
   p->band_split_min = 3000;
   p->graph_iterations = 0;
   p->band_sector_min = 1500;
   p->queue_ahead = 1;
+  p->ghost_boxes = 1;
 }
 
 const char *gp_strerror(gp_status st) {
@@ -150,6 +151,23 @@ gp_status gp_get_band_layout(gp_ctx *ctx, int level, int *out) {
   return GP_OK;
 }
 
+gp_status gp_get_coupled_boxes(gp_ctx *ctx, int level, int *counts, int *cell, int *off, int *idx, unsigned char *wr,
+                               int *colour_off) {
+  if (!ctx || !counts || level < 0 || level >= ctx->L || !ctx->have_geom) return GP_EINVAL;
+  const Geo &G = ctx->geo[level];
+  counts[0] = G.nxb;
+  counts[1] = G.nxs;
+  if (colour_off)
+    for (int c = 0; c < 6; c++) colour_off[c] = G.xb_coff[c];
+  if (G.nxb == 0) return GP_OK;
+  if (cell) GP_HIP(hipMemcpyAsync(cell, G.xb_cell, (size_t)G.nxb * sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+  if (off) GP_HIP(hipMemcpyAsync(off, G.xb_off, (size_t)(G.nxb + 1) * sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+  if (idx) GP_HIP(hipMemcpyAsync(idx, G.xb_idx, (size_t)G.nxs * sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+  if (wr) GP_HIP(hipMemcpyAsync(wr, G.xb_wr, (size_t)G.nxs, hipMemcpyDeviceToHost, ctx->stream));
+  GP_HIP(hipStreamSynchronize(ctx->stream));
+  return GP_OK;
+}
+
 void gp_destroy(gp_ctx *ctx) {
   if (!ctx) return;
   prep_discard(ctx);
@@ -160,6 +178,19 @@ void gp_destroy(gp_ctx *ctx) {
   for (int l = 0; l < ctx->L; l++) {
     Geo &G = ctx->geo[l];
     dfree(G.cls);
+    dfree(G.xb_cell);
+    dfree(G.xb_off);
+    dfree(G.xb_ioff);
+    dfree(G.xb_gcnt);
+    dfree(G.xb_gtmp);
+    dfree(G.xb_ok);
+    dfree(G.xb_idx);
+    dfree(G.xb_box);
+    dfree(G.xb_wr);
+    dfree(G.xb_r);
+    dfree(G.xb_inv);
+    dfree(G.xb_own);
+    dfree(G.d_xb_co);
     dfree(G.sec_pt);
     dfree(G.sec_bfl);
     dfree(G.sec_bcell);
@@ -272,7 +303,8 @@ gp_status gp_setup_grid(gp_ctx **out, int N, double Re, const gp_params *prm, vo
     gp_default_params(&P);
   if (!pow2(N) || N < 16 || !pow2(P.coarsest_n) || P.coarsest_n < 4 || P.coarsest_n > N / 2 || P.nu1 < 0 || P.nu2 < 0 ||
       P.gamma < 1 || P.lambda_ghost < 0 || P.march_max < 1 || P.ext_radius < 1 || !(Re > 0) || P.mixed_inner_cycles < 1 ||
-      P.bnd_sweeps < 0 || P.bnd_radius < 0 || P.band_split_min < 1 || P.band_sector_min < 1)
+      P.bnd_sweeps < 0 || P.bnd_radius < 0 || P.band_split_min < 1 || P.band_sector_min < 1 ||
+      (P.ghost_boxes != 0 && P.ghost_boxes != 1))
     return GP_EINVAL;
   gp_ctx *ctx = new gp_ctx();
   ctx->N = N;
@@ -362,6 +394,24 @@ gp_status gp_setup_grid(gp_ctx **out, int N, double Re, const gp_params *prm, vo
       ALLOC(G.sec_gk, (size_t)G.sec_gcap);
     }
     ALLOC(G.f_loc, (size_t)G.fcap);
+    if (P.ghost_boxes) {  // coupled ghost boxes
+      G.xb_bcap = G.gcap;
+      G.xb_scap = 8 * G.gcap;
+      G.xb_icap = 24L * G.gcap;
+      ALLOC(G.xb_cell, (size_t)G.xb_bcap);
+      ALLOC(G.xb_off, (size_t)G.xb_bcap + 1);
+      ALLOC(G.xb_ioff, (size_t)G.xb_bcap + 1);
+      ALLOC(G.xb_gcnt, (size_t)G.xb_bcap);
+      ALLOC(G.xb_gtmp, (size_t)48 * G.xb_bcap);
+      ALLOC(G.xb_ok, (size_t)G.xb_bcap);
+      ALLOC(G.xb_idx, (size_t)G.xb_scap);
+      ALLOC(G.xb_box, (size_t)G.xb_scap);
+      ALLOC(G.xb_wr, (size_t)G.xb_scap);
+      ALLOC(G.xb_r, (size_t)G.xb_scap);
+      ALLOC(G.xb_inv, (size_t)G.xb_icap);
+      ALLOC(G.xb_own, (size_t)5 * G.gcap);
+      ALLOC(G.d_xb_co, 16);
+    }
     ALLOC(G.g_rowof, (size_t)G.n);
     ALLOC(G.e_rowof, (size_t)G.n);
     ALLOC(ctx->v64[l].x, (size_t)G.n);

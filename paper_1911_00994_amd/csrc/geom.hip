@@ -904,6 +904,266 @@ __global__ void k_bvals_points(const uint8_t *cls, int N, int W, double *b, doub
 // ---------------------------------------------------------------------------------------------------------
 // host drivers
 // ---------------------------------------------------------------------------------------------------------
+// ---------------------------------------------------------------------------------------------------------
+// coupled ghost boxes: a cell's box (Sect. 4.1.1: its pressure and its four faces) relaxed together with the body
+// ghosts whose boundary rows weigh one of its internal unknowns.  Where such a weight dominates the ghost's own
+// diagonal, the ghost row fixes the internal value and the internal equations fix the ghost value, and neither
+// the box alone nor the fictitious-time step of eq. (ghostrelax) can resolve the pair.
+// ---------------------------------------------------------------------------------------------------------
+constexpr int XB_MAXM = 32;  // unknowns of one coupled box, at most
+constexpr int XB_GCAP = 48;  // ghost entries gathered per box before duplicates are removed
+
+// the cells whose box holds the internal point k: a u face separates cells (i-1, j) and (i, j), a v face (i, j-1)
+// and (i, j); a pressure point belongs to its own cell
+__device__ __forceinline__ int box_cells(int N, int W, int k, int cells[2]) {
+  const int WW = W * W, g = k / WW, loc = k - g * WW, j = loc / W - 1, i = loc % W - 1;
+  int n = 0;
+  const int ci[2] = {g == 0 ? i - 1 : i, i}, cj[2] = {g == 1 ? j - 1 : j, j};
+  for (int z = (g == 2 ? 1 : 0); z < 2; z++)
+    if (ci[z] >= 0 && cj[z] >= 0 && ci[z] < N && cj[z] < N) cells[n++] = cj[z] * N + ci[z];
+  return n;
+}
+__device__ __forceinline__ int cell_colour(int N, int cell) { return (cell % N + 2 * (cell / N)) % 5; }
+
+// cells holding an internal column of a body ghost row
+__global__ void k_xb_mark(const uint8_t *cls, int N, int W, const int *g_pt, const int *g_col, const double *g_w, int ng,
+                          uint8_t *flag) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= ng || cls[g_pt[r]] != K_GHOST) return;
+  for (int z = 0; z < 9; z++) {
+    const int c = g_col[9 * r + z];
+    if (g_w[9 * r + z] == 0.0 || cls[c] != K_INT) continue;
+    int cells[2];
+    const int n = box_cells(N, W, c, cells);
+    for (int q = 0; q < n; q++) flag[cells[q]] = 1;
+  }
+}
+// per-block counts of the marked cells per colour (then k_scan_blocks over the 5 nb counts, colour-major)
+__global__ void __launch_bounds__(TPB) k_xb_count(const uint8_t *flag, int N, int nb, int *bcnt) {
+  const int t = blockIdx.x * TPB + threadIdx.x;
+  const int col = t < N * N && flag[t] ? cell_colour(N, t) : -1;
+  int tot[5];
+  (void)colour_rank(col, tot);
+  if (threadIdx.x == 0)
+    for (int c = 0; c < 5; c++) bcnt[c * nb + blockIdx.x] = tot[c];
+}
+// boxes in colour order, ascending cell within a colour; cellbox[cell] = its box or -1
+__global__ void __launch_bounds__(TPB) k_xb_fill(const uint8_t *flag, int N, int nb, const int *boff, int *xb_cell,
+                                                 int *cellbox, int cap, int *over) {
+  const int t = blockIdx.x * TPB + threadIdx.x;
+  const int col = t < N * N && flag[t] ? cell_colour(N, t) : -1;
+  int tot[5];
+  const int r = colour_rank(col, tot);
+  if (t >= N * N) return;
+  int b = -1;
+  if (col >= 0) {
+    b = boff[col * nb + blockIdx.x] + r;
+    if (b < cap)
+      xb_cell[b] = t;
+    else {
+      atomicOr(over, 1);
+      b = -1;
+    }
+  }
+  cellbox[t] = b;
+}
+// each body ghost row appended to the boxes of the cells its internal columns border (duplicates removed later)
+__global__ void k_xb_gather(const uint8_t *cls, int N, int W, const int *g_pt, const int *g_col, const double *g_w,
+                            int ng, const int *cellbox, int *gcnt, int *gtmp, int *over) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= ng) return;
+  const int G = g_pt[r];
+  if (cls[G] != K_GHOST) return;
+  for (int z = 0; z < 9; z++) {
+    const int c = g_col[9 * r + z];
+    if (g_w[9 * r + z] == 0.0 || cls[c] != K_INT) continue;
+    int cells[2];
+    const int n = box_cells(N, W, c, cells);
+    for (int q = 0; q < n; q++) {
+      const int b = cellbox[cells[q]];
+      if (b < 0) continue;
+      const int slot = atomicAdd(&gcnt[b], 1);
+      if (slot < XB_GCAP)
+        gtmp[b * XB_GCAP + slot] = G;
+      else
+        atomicOr(over, 1);
+    }
+  }
+}
+__device__ __forceinline__ int box_unknowns(const uint8_t *cls, int N, int W, int cell, int U[5]) {
+  const int WW = W * W, i = cell % N, j = cell / N, c = (j + 1) * W + (i + 1);
+  const int cand[5] = {c, c + 1, WW + c, WW + c + W, 2 * WW + c};
+  int m = 0;
+  for (int q = 0; q < 5; q++)
+    if (cls[cand[q]] == K_INT) U[m++] = cand[q];
+  return m;
+}
+// per box: its ghosts sorted and distinct (count back into gcnt), its unknown count m and m^2 (scanned next)
+__global__ void k_xb_size(const uint8_t *cls, int N, int W, const int *xb_cell, int nxb, int *gcnt, int *gtmp, int *mcnt,
+                          int *sqcnt, int *over) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= nxb) return;
+  int *lst = gtmp + (size_t)b * XB_GCAP;
+  const int n = min(gcnt[b], XB_GCAP);
+  for (int q = 1; q < n; q++) {  // insertion sort (a few dozen entries)
+    const int v = lst[q];
+    int z = q - 1;
+    while (z >= 0 && lst[z] > v) {
+      lst[z + 1] = lst[z];
+      z--;
+    }
+    lst[z + 1] = v;
+  }
+  int u = 0;
+  for (int q = 0; q < n; q++)
+    if (q == 0 || lst[q] != lst[q - 1]) lst[u++] = lst[q];
+  gcnt[b] = u;
+  int U[5];
+  int m = box_unknowns(cls, N, W, xb_cell[b], U) + u;
+  if (m > XB_MAXM) {
+    atomicOr(over, 2);
+    m = 0;
+  }
+  mcnt[b] = m;
+  sqcnt[b] = m * m;
+}
+__global__ void k_xb_slots(const uint8_t *cls, int N, int W, const int *xb_cell, int nxb, const int *gcnt,
+                           const int *gtmp, const int *xb_off, int *xb_idx, int *xb_box) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= nxb) return;
+  const int o = xb_off[b];
+  if (xb_off[b + 1] == o) return;
+  int U[5];
+  const int m0 = box_unknowns(cls, N, W, xb_cell[b], U);
+  for (int a = 0; a < m0; a++) {
+    xb_idx[o + a] = U[a];
+    xb_box[o + a] = b;
+  }
+  for (int a = 0; a < gcnt[b]; a++) {
+    xb_idx[o + m0 + a] = gtmp[(size_t)b * XB_GCAP + a];
+    xb_box[o + m0 + a] = b;
+  }
+}
+__global__ void k_xb_own_clear(int *own, int n) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n) own[t] = 0x7fffffff;
+}
+// the first box of a colour that holds a ghost (the boxes are in colour order, so the smallest index)
+__global__ void k_xb_own(const uint8_t *cls, int N, const int *xb_idx, const int *xb_box, const int *xb_cell, int nxs,
+                         const int *g_rowof, int ng, int *own) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nxs) return;
+  const int k = xb_idx[t];
+  if (cls[k] != K_GHOST) return;
+  const int b = xb_box[t];
+  atomicMin(&own[cell_colour(N, xb_cell[b]) * ng + g_rowof[k]], b);
+}
+__global__ void k_xb_wr(const uint8_t *cls, int N, const int *xb_idx, const int *xb_box, const int *xb_cell, int nxs,
+                        const int *g_rowof, int ng, const int *own, uint8_t *wr) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nxs) return;
+  const int k = xb_idx[t], b = xb_box[t];
+  wr[t] = cls[k] == K_INT ? 1 : (uint8_t)(own[cell_colour(N, xb_cell[b]) * ng + g_rowof[k]] == b);
+}
+__global__ void k_xb_soff(const int *xb_off, const int *co, int *out) {
+  const int c = threadIdx.x;
+  if (c < 6) out[c] = xb_off[co[c]];
+}
+
+// coefficient of unknown c in the row of point k (internal momentum or continuity row of Sect. 3.2, or the ghost
+// row of k); the xi column of the continuity rows is not a box unknown
+__device__ double xb_coef(const uint8_t *cls, int W, double h, double a, double d, const int *g_rowof, const int *g_col,
+                          const double *g_w, int k, int c) {
+  const int WW = W * W;
+  if (cls[k] == K_INT) {
+    const int g = k / WW, q = k - g * WW;
+    const double ih = 1.0 / h;
+    if (g < 2) {
+      if (c == k) return d;
+      if (c == k - 1 || c == k + 1 || c == k - W || c == k + W) return -a;
+      if (c == 2 * WW + q) return ih;
+      if (c == 2 * WW + q - (g == 0 ? 1 : W)) return -ih;
+      return 0.0;
+    }
+    if (c == q + 1 || c == WW + q + W) return ih;
+    if (c == q || c == WW + q) return -ih;
+    return 0.0;
+  }
+  const int r = g_rowof[k];
+  double s = 0;
+  for (int z = 0; z < 9; z++)
+    if (g_col[9 * r + z] == c) s += g_w[9 * r + z];
+  return s;
+}
+// inverse of each box's block by Gauss-Jordan elimination with partial pivoting, one wavefront per box, the
+// augmented block [A | I] in LDS
+constexpr int XF_T = 64;
+__global__ void __launch_bounds__(XF_T) k_xb_factor(const uint8_t *cls, int W, double h, double a, double d,
+                                                    const int *xb_off, const int *xb_ioff, const int *xb_idx,
+                                                    const int *g_rowof, const int *g_col, const double *g_w,
+                                                    double *xb_inv, uint8_t *xb_ok) {
+  __shared__ double A[XB_MAXM][2 * XB_MAXM + 1];
+  __shared__ double colk[XB_MAXM];
+  __shared__ int U[XB_MAXM];
+  const int b = blockIdx.x, tid = threadIdx.x;
+  const int o = xb_off[b], m = xb_off[b + 1] - o, m2 = 2 * m;
+  if (m == 0) {
+    if (tid == 0) xb_ok[b] = 0;
+    return;
+  }
+  if (tid < m) U[tid] = xb_idx[o + tid];
+  __syncthreads();
+  for (int e = tid; e < m * m; e += XF_T) {
+    const int r = e / m, c = e - r * m;
+    A[r][c] = xb_coef(cls, W, h, a, d, g_rowof, g_col, g_w, U[r], U[c]);
+    A[r][m + c] = r == c ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  bool ok = true;
+  for (int k = 0; k < m; k++) {
+    // pivot: the largest |A[r][k]|, r >= k (the smaller row on ties)
+    double v = (tid >= k && tid < m) ? fabs(A[tid][k]) : -1.0;
+    int ir = tid;
+    for (int off = 32; off > 0; off >>= 1) {
+      const double v2 = __shfl_xor(v, off, 64);
+      const int i2 = __shfl_xor(ir, off, 64);
+      if (v2 > v || (v2 == v && i2 < ir)) {
+        v = v2;
+        ir = i2;
+      }
+    }
+    if (!(v > 0.0)) {
+      ok = false;
+      break;
+    }
+    if (ir != k)
+      for (int c = tid; c < m2; c += XF_T) {
+        const double t = A[k][c];
+        A[k][c] = A[ir][c];
+        A[ir][c] = t;
+      }
+    __syncthreads();
+    const double piv = A[k][k];
+    __syncthreads();
+    for (int c = tid; c < m2; c += XF_T) A[k][c] /= piv;
+    __syncthreads();
+    if (tid < m) colk[tid] = A[tid][k];
+    __syncthreads();
+    for (int e = tid; e < m * m2; e += XF_T) {
+      const int r = e / m2, c = e - r * m2;
+      if (r != k) A[r][c] -= colk[r] * A[k][c];
+    }
+    __syncthreads();
+  }
+  double *out = xb_inv + xb_ioff[b];
+  if (ok)
+    for (int e = tid; e < m * m; e += XF_T) {
+      const int r = e / m, c = e - r * m;
+      out[e] = A[r][m + c];
+    }
+  if (tid == 0) xb_ok[b] = ok ? 1 : 0;
+}
+
 static Lat make_lat(Ctx *ctx, int l) {
   Lat L;
   L.phi = ctx->phi;
@@ -1313,6 +1573,85 @@ gp_status sector_build(Ctx *ctx, int l) {
   return GP_OK;
 }
 
+// coupled-box tables of level l (after its ghost rows, their row map and the classes are final)
+static gp_status xb_build(Ctx *ctx, int l, BuildRes &B) {
+  Geo &G = ctx->geo[l];
+  const int N = G.N, W = G.W;
+  hipStream_t s = B.s;
+  G.nxb = G.nxs = G.xb_maxs = 0;
+  for (int c = 0; c < 6; c++) G.xb_coff[c] = G.xb_soff[c] = 0;
+  G.xb_alpha = -1;
+  if (!G.ng || !G.xb_cell) return GP_OK;
+  int *cellbox = B.iscr;                                               // N^2 ints
+  uint8_t *flag = reinterpret_cast<uint8_t *>(B.iscr + (size_t)N * N);  // N^2 bytes after them
+  int *over = B.flags + 13;
+  GP_HIP(hipMemsetAsync(flag, 0, (size_t)N * N, s));
+  GP_HIP(hipMemsetAsync(over, 0, sizeof(int), s));
+  k_xb_mark<<<nblk(G.ng), TPB, 0, s>>>(G.cls, N, W, G.g_pt, G.g_col, G.g_w, G.ng, flag);
+  const int nb = nblk((long)N * N);
+  k_xb_count<<<nb, TPB, 0, s>>>(flag, N, nb, B.bcnt);
+  k_scan_blocks<<<1, SCAN_T, 0, s>>>(B.bcnt, 5 * nb);
+  k_band_offsets<<<1, 64, 0, s>>>(B.bcnt, nb, G.d_xb_co);
+  k_xb_fill<<<nb, TPB, 0, s>>>(flag, N, nb, B.bcnt, G.xb_cell, cellbox, G.xb_bcap, over);
+  GP_HIP(hipGetLastError());
+  int hco[6];
+  gp_status fs = fetch(ctx, B, {{G.d_xb_co, 6}}, hco);
+  if (fs) return fs;
+  const int nxb = hco[5];
+  if (nxb > G.xb_bcap) return GP_ENOMEM;
+  if (nxb == 0) return GP_OK;
+  GP_HIP(hipMemsetAsync(G.xb_gcnt, 0, (size_t)nxb * sizeof(int), s));
+  k_xb_gather<<<nblk(G.ng), TPB, 0, s>>>(G.cls, N, W, G.g_pt, G.g_col, G.g_w, G.ng, cellbox, G.xb_gcnt, G.xb_gtmp, over);
+  k_xb_size<<<nblk(nxb), TPB, 0, s>>>(G.cls, N, W, G.xb_cell, nxb, G.xb_gcnt, G.xb_gtmp, G.xb_off, G.xb_ioff, over);
+  k_scan_blocks<<<1, SCAN_T, 0, s>>>(G.xb_off, nxb);
+  k_scan_blocks<<<1, SCAN_T, 0, s>>>(G.xb_ioff, nxb);
+  k_xb_soff<<<1, 64, 0, s>>>(G.xb_off, G.d_xb_co, G.d_xb_co + 8);
+  GP_HIP(hipGetLastError());
+  int w[9];
+  fs = fetch(ctx, B, {{G.d_xb_co + 8, 6}, {G.xb_ioff + nxb, 1}, {over, 1}}, w);
+  if (fs) return fs;
+  if (w[7]) return GP_ENOMEM;  // a box with more ghosts or unknowns than the tables hold
+  const int nxs = w[5];
+  if (nxs > G.xb_scap || (long)w[6] > G.xb_icap) return GP_ENOMEM;
+  k_xb_slots<<<nblk(nxb), TPB, 0, s>>>(G.cls, N, W, G.xb_cell, nxb, G.xb_gcnt, G.xb_gtmp, G.xb_off, G.xb_idx, G.xb_box);
+  k_xb_own_clear<<<nblk(5L * G.ng), TPB, 0, s>>>(G.xb_own, 5 * G.ng);
+  if (nxs) {
+    k_xb_own<<<nblk(nxs), TPB, 0, s>>>(G.cls, N, G.xb_idx, G.xb_box, G.xb_cell, nxs, G.g_rowof, G.ng, G.xb_own);
+    k_xb_wr<<<nblk(nxs), TPB, 0, s>>>(G.cls, N, G.xb_idx, G.xb_box, G.xb_cell, nxs, G.g_rowof, G.ng, G.xb_own, G.xb_wr);
+  }
+  GP_HIP(hipGetLastError());
+  G.nxb = nxb;
+  G.nxs = nxs;
+  for (int c = 0; c < 6; c++) {
+    G.xb_coff[c] = hco[c];
+    G.xb_soff[c] = w[c];
+  }
+  for (int c = 0; c < 5; c++) G.xb_maxs = std::max(G.xb_maxs, G.xb_soff[c + 1] - G.xb_soff[c]);
+  return GP_OK;
+}
+
+// the inverses of level l's coupled boxes for the current alpha, on stream s
+gp_status xb_factor(Ctx *ctx, int l, hipStream_t s) {
+  Geo &G = ctx->geo[l];
+  if (G.nxb) {
+    const double a = ctx->alpha / (G.h * G.h), d = 1.0 + 4.0 * a;
+    k_xb_factor<<<G.nxb, XF_T, 0, s>>>(G.cls, G.W, G.h, a, d, G.xb_off, G.xb_ioff, G.xb_idx, G.g_rowof, G.g_col, G.g_w,
+                                       G.xb_inv, G.xb_ok);
+    GP_HIP(hipGetLastError());
+  }
+  G.xb_alpha = ctx->alpha;
+  return GP_OK;
+}
+gp_status ensure_xb(Ctx *ctx) {
+  if (!ctx->have_geom || !ctx->prm.ghost_boxes) return GP_OK;
+  for (int l = 0; l < ctx->L; l++)
+    if (ctx->geo[l].nxb && ctx->geo[l].xb_alpha != ctx->alpha) {
+      gp_status st = xb_factor(ctx, l, ctx->stream);
+      if (st) return st;
+    }
+  return GP_OK;
+}
+
 static gp_status build_level(Ctx *ctx, int l) {
   Geo &G = ctx->geo[l];
   BuildRes &B = ctx->bres[l];
@@ -1351,7 +1690,8 @@ static gp_status build_level(Ctx *ctx, int l) {
   RowArgs R = row_args(G);
   double nbis_d = ceil(log2(0.5 / ctx->prm.bisect_eps_over_h) - 1e-12);
   if (G.ng) {
-    k_ghost_rows<<<nblk(G.ng), TPB, 0, s>>>(L, G.cls, W, R, ctx->prm.march_max, (int)nbis_d, ctx->prm.cg_min,
+    // the finest level keeps every row with a positive diagonal; coarse levels replace small ones (cg_min)
+    k_ghost_rows<<<nblk(G.ng), TPB, 0, s>>>(L, G.cls, W, R, ctx->prm.march_max, (int)nbis_d, l == 0 ? 0.0 : ctx->prm.cg_min,
                                             ctx->prm.dtau_dir, ctx->prm.dtau_neu_over_h * G.h);
     k_ghostx_rows<<<nblk(G.ng), TPB, 0, s>>>(L, G.cls, W, R, l == 0, B.flags);
   }
@@ -1361,6 +1701,12 @@ static gp_status build_level(Ctx *ctx, int l) {
     k_row_of<<<nblk(G.ne), TPB, 0, s>>>(G.e_pt, G.ne, G.e_rowof);
   }
   if (G.ng) k_row_of<<<nblk(G.ng), TPB, 0, s>>>(G.g_pt, G.ng, G.g_rowof);
+  if (ctx->prm.ghost_boxes) {
+    gp_status xs = xb_build(ctx, l, B);
+    if (xs) return xs;
+  } else {
+    G.nxb = G.nxs = G.xb_maxs = 0;
+  }
   GP_HIP(hipMemsetAsync(G.d_mp, 0, sizeof(int), s));
   k_count_mp<<<std::min(256, nblk(W * W)), TPB, 0, s>>>(G.cls, W, G.d_mp);
   // boundary band: cells grouped by colour, ascending cell index within a colour
@@ -1506,11 +1852,14 @@ gp_status geometry_build(Ctx *ctx) {
         return;
       }
       st[l] = build_level(ctx, l);
+      // the coupled-box inverses for the current alpha (a stale alpha is caught by ensure_xb)
+      if (st[l] == GP_OK && ctx->alpha > 0 && ctx->prm.ghost_boxes) st[l] = xb_factor(ctx, l, ctx->bres[l].s);
       // the coarsest level: its exact inverse for the current alpha too, while the finer levels still build (a
       // failure leaves c_ok = 0, and the solver factors again and reports it)
       if (l == L - 1 && st[l] == GP_OK && ctx->alpha > 0) (void)coarse_factor(ctx, ctx->bres[l]);
     });
   st[0] = build_level(ctx, 0);
+  if (st[0] == GP_OK && ctx->alpha > 0 && ctx->prm.ghost_boxes) st[0] = xb_factor(ctx, 0, ctx->stream);
   for (auto &t : th) t.join();
   for (int l = 0; l < L; l++)
     if (st[l]) return st[l];

@@ -86,6 +86,21 @@ struct Geo {
   // face enters the cell's divergence with a minus sign); f_loc = the same face as an LDS band-region entry
   int *f_code = nullptr, *f_loc = nullptr;
   int nf = 0, fcap = 0;
+  // coupled ghost boxes: the cells whose internal unknowns appear in a body ghost row, each relaxed together with
+  // those ghosts.  Boxes ordered by colour, then cell; per box its unknowns (slots xb_off[b] .. xb_off[b+1]: the
+  // internal box unknowns W, E, S, N face, pressure, then its ghosts in point order), per slot the box and whether
+  // the box writes the value (a ghost is written by the first box of a colour that holds it), per box the inverse
+  // of its block (row-major, at xb_ioff[b]) for the alpha xb_alpha and a flag (0: singular block, not relaxed)
+  int nxb = 0, nxs = 0;
+  int xb_coff[6] = {0, 0, 0, 0, 0, 0}, xb_soff[6] = {0, 0, 0, 0, 0, 0};  // host: box and slot offsets per colour
+  int xb_maxs = 0;                  // most slots of one colour
+  int xb_bcap = 0, xb_scap = 0;
+  long xb_icap = 0;
+  int *xb_cell = nullptr, *xb_off = nullptr, *xb_ioff = nullptr, *xb_idx = nullptr, *xb_box = nullptr;
+  int *xb_gcnt = nullptr, *xb_gtmp = nullptr, *xb_own = nullptr, *d_xb_co = nullptr;
+  uint8_t *xb_wr = nullptr, *xb_ok = nullptr;
+  double *xb_inv = nullptr, *xb_r = nullptr;
+  double xb_alpha = -1;
 };
 
 // one precision's vectors on one level
@@ -232,6 +247,8 @@ gp_status default_boundary_values(Ctx *ctx);
 gp_status coarse_factor(Ctx *ctx);
 gp_status coarse_factor(Ctx *ctx, BuildRes &B);
 gp_status sector_build(Ctx *ctx, int l);
+gp_status xb_factor(Ctx *ctx, int l, hipStream_t s);
+gp_status ensure_xb(Ctx *ctx);
 
 // multigrid (mg.hip)
 gp_status mg_cycle64(Ctx *ctx, double *res_inf);

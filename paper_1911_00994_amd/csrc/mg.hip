@@ -1001,6 +1001,76 @@ __device__ __forceinline__ double resid_point(int W, double h, double a, double 
   if (c == K_WALLD) return (double)b[t] - (double)x[t];
   return 0.0;
 }
+// ---------------------------------------------------------------------------------------------------------
+// coupled ghost boxes (tables and block inverses from the geometry build): after the box sweep, colour by colour,
+// every coupled box of the colour forms the residuals of its rows from the values at the start of the colour,
+// then adds its inverse times them to the unknowns it writes.  Phase one reads, phase two writes, so the boxes of
+// one colour never see each other's updates.
+// ---------------------------------------------------------------------------------------------------------
+struct XbTab {
+  const int *idx, *box, *off, *ioff;
+  const uint8_t *wr, *ok;
+  const double *inv;
+  const int *g_rowof, *g_col;
+  const double *g_w;
+};
+static inline XbTab xb_tab(const Geo &G) {
+  return XbTab{G.xb_idx, G.xb_box, G.xb_off, G.xb_ioff, G.xb_wr, G.xb_ok, G.xb_inv, G.g_rowof, G.g_col, G.g_w};
+}
+// residual of the row of point k (internal row, or the ghost row of k)
+template <typename T>
+__device__ __forceinline__ double xb_row_res(int W, double h, double a, double d, const uint8_t *__restrict__ cls,
+                                             const T *x, const T *b, const XbTab &X, int k) {
+  if (cls[k] == K_INT) return resid_point<T>(W, h, a, d, cls, x, b, k);
+  const int r = X.g_rowof[k];
+  double sw = 0;
+#pragma unroll
+  for (int z = 0; z < 9; z++) sw += X.g_w[9 * r + z] * (double)x[X.g_col[9 * r + z]];
+  return (double)b[k] - sw;
+}
+// the new value of slot s (when its box writes it): x + (row s of the inverse) . (the box's residuals), the
+// residual of slot q of the box at rs[q - rbase]
+template <typename T>
+__device__ __forceinline__ void xb_write(const XbTab &X, T *x, const double *rs, int rbase, int s) {
+  if (!X.wr[s]) return;
+  const int bx = X.box[s];
+  if (!X.ok[bx]) return;
+  const int o = X.off[bx], m = X.off[bx + 1] - o;
+  const double *iv = X.inv + X.ioff[bx] + (size_t)(s - o) * m;
+  const double *r = rs + (o - rbase);
+  double v = 0;
+  for (int c = 0; c < m; c++) v += iv[c] * r[c];
+  const int k = X.idx[s];
+  x[k] = (T)((double)x[k] + v);
+}
+template <typename T>
+__global__ void __launch_bounds__(TPB) k_xb_res(int lo, int hi, int W, double h, double a, double d,
+                                                const uint8_t *__restrict__ cls, const T *x, const T *b, XbTab X,
+                                                double *rs) {
+  const int s = lo + blockIdx.x * blockDim.x + threadIdx.x;
+  if (s < hi) rs[s] = xb_row_res<T>(W, h, a, d, cls, x, b, X, X.idx[s]);
+}
+template <typename T>
+__global__ void __launch_bounds__(TPB) k_xb_upd(int lo, int hi, T *x, XbTab X, const double *rs) {
+  const int s = lo + blockIdx.x * blockDim.x + threadIdx.x;
+  if (s < hi) xb_write<T>(X, x, rs, 0, s);
+}
+struct XbOff {
+  int o[6];
+};
+// all five colours in one workgroup (levels whose colours have few slots)
+constexpr int XW_T = 1024;
+template <typename T>
+__global__ void __launch_bounds__(XW_T) k_xb_wg(XbOff so, int W, double h, double a, double d,
+                                                const uint8_t *__restrict__ cls, T *x, const T *b, XbTab X, double *rs) {
+  for (int c = 0; c < 5; c++) {
+    for (int s = so.o[c] + threadIdx.x; s < so.o[c + 1]; s += XW_T) rs[s] = xb_row_res<T>(W, h, a, d, cls, x, b, X, X.idx[s]);
+    __syncthreads();
+    for (int s = so.o[c] + threadIdx.x; s < so.o[c + 1]; s += XW_T) xb_write<T>(X, x, rs, 0, s);
+    __syncthreads();
+  }
+}
+
 template <typename T>
 __global__ void __launch_bounds__(TPB) k_resid_pts(int N, int W, double h, double a, double d,
                                                    const uint8_t *__restrict__ cls, const T *__restrict__ x,
@@ -1527,6 +1597,9 @@ struct SmallLevel {
   int ox, ob, orr, oc;  // LDS offsets (bytes) of x, b, r and the classes
   int ogw, ogc, ogp, ogd;  // LDS offsets of the ghost rows, field-major: 9 weights, 9 columns, point, dtau
   int obl;                 // LDS offset of the band cells
+  int nxb;                 // coupled boxes (tables in global memory), slot offsets per colour
+  int xso[6];
+  XbTab xb;
 };
 struct SmallCycle {
   int nl;  // fused levels; the last one is the coarsest
@@ -1534,6 +1607,7 @@ struct SmallCycle {
   const double *Ainv;
   const int *map, *bmap;
   int nc, nu1, nu2, lambda, bnd, onv;
+  int oxr;  // LDS offset of the coupled boxes' residuals (one colour)
 };
 
 __device__ double sc_block_sum(double v) {
@@ -1572,7 +1646,7 @@ __device__ void sc_ghosts(const SmallLevel &L, const ScRows &G, T *x, const T *b
 
 template <typename T>
 __device__ void sc_relax(const SmallCycle &P, const SmallLevel &L, const ScRows &G, T *x, const T *b, const uint8_t *cls,
-                         double *nv, const int *band) {
+                         double *nv, const int *band, double *xr) {
   const int K = L.N / 5 + 1;
   for (int c = 0; c < 5; c++) {
     for (int t = threadIdx.x; t < K * L.N; t += SC_T) {
@@ -1582,6 +1656,14 @@ __device__ void sc_relax(const SmallCycle &P, const SmallLevel &L, const ScRows 
     }
     __syncthreads();
   }
+  if (L.nxb)
+    for (int c = 0; c < 5; c++) {
+      for (int s = L.xso[c] + threadIdx.x; s < L.xso[c + 1]; s += SC_T)
+        xr[s - L.xso[c]] = xb_row_res<T>(L.W, L.h, L.a, L.d, cls, x, b, L.xb, L.xb.idx[s]);
+      __syncthreads();
+      for (int s = L.xso[c] + threadIdx.x; s < L.xso[c + 1]; s += SC_T) xb_write<T>(L.xb, x, xr, L.xso[c], s);
+      __syncthreads();
+    }
   sc_ghosts<T>(L, G, x, b, nv, P.lambda);
   if (P.bnd > 0 && L.nband > 0) {
     for (int q = 0; q < P.bnd; q++) {
@@ -1616,6 +1698,7 @@ __global__ void __launch_bounds__(SC_T) k_small_cycle(SmallCycle P, T *xg, const
   auto R = [&](int m) { return reinterpret_cast<T *>(lds_raw + P.lv[m].orr); };
   auto C = [&](int m) { return reinterpret_cast<uint8_t *>(lds_raw + P.lv[m].oc); };
   double *nv = reinterpret_cast<double *>(lds_raw + P.onv);
+  double *xr = reinterpret_cast<double *>(lds_raw + P.oxr);
   auto GR = [&](int m) {
     const SmallLevel &L = P.lv[m];
     return ScRows{reinterpret_cast<const double *>(lds_raw + L.ogw), reinterpret_cast<const double *>(lds_raw + L.ogd),
@@ -1651,7 +1734,7 @@ __global__ void __launch_bounds__(SC_T) k_small_cycle(SmallCycle P, T *xg, const
     const SmallLevel &L = P.lv[m], &Cl = P.lv[m + 1];
     const ScRows G = GR(m);
     const int *bl = reinterpret_cast<const int *>(lds_raw + L.obl);
-    for (int q = 0; q < P.nu1; q++) sc_relax<T>(P, L, G, X(m), B(m), C(m), nv, bl);
+    for (int q = 0; q < P.nu1; q++) sc_relax<T>(P, L, G, X(m), B(m), C(m), nv, bl, xr);
     for (int t = tid; t < 3 * L.W * L.W; t += SC_T) R(m)[t] = (T)resid_point<T>(L.W, L.h, L.a, L.d, C(m), X(m), B(m), t);
     __syncthreads();
     for (int r = tid; r < L.ng; r += SC_T) {
@@ -1722,7 +1805,7 @@ __global__ void __launch_bounds__(SC_T) k_small_cycle(SmallCycle P, T *xg, const
     }
     __syncthreads();
     for (int q = 0; q < P.nu2; q++)
-      sc_relax<T>(P, L, GR(m), X(m), B(m), C(m), nv, reinterpret_cast<const int *>(lds_raw + L.obl));
+      sc_relax<T>(P, L, GR(m), X(m), B(m), C(m), nv, reinterpret_cast<const int *>(lds_raw + L.obl), xr);
   }
   for (int t = tid; t < P.lv[0].n; t += SC_T) xg[t] = X(0)[t];
 }
@@ -1797,6 +1880,30 @@ static void box5_finest(Ctx *ctx, const BoxK &BK, const unsigned long long *go, 
   if (probed) *probed = probe;
 }
 
+// the coupled boxes of level l after its box sweep: one workgroup for all five colours where every colour has
+// fewer than band_split_min slots, else two launches per colour (residuals, then writes)
+template <typename T>
+static void xb_relax(Ctx *ctx, int l) {
+  Geo &G = ctx->geo[l];
+  if (!ctx->prm.ghost_boxes || !G.nxb) return;
+  Vec<T> &V = vec<T>(ctx, l);
+  hipStream_t s = ctx->stream;
+  const double a = coef_a(ctx, l), d = 1.0 + 4.0 * a;
+  const XbTab X = xb_tab(G);
+  if (G.xb_maxs < ctx->band_split_min) {
+    XbOff so;
+    for (int c = 0; c < 6; c++) so.o[c] = G.xb_soff[c];
+    k_xb_wg<T><<<1, XW_T, 0, s>>>(so, G.W, G.h, a, d, G.cls, V.x, V.b, X, G.xb_r);
+    return;
+  }
+  for (int c = 0; c < 5; c++) {
+    const int lo = G.xb_soff[c], hi = G.xb_soff[c + 1];
+    if (hi == lo) continue;
+    k_xb_res<T><<<nblk(hi - lo), TPB, 0, s>>>(lo, hi, G.W, G.h, a, d, G.cls, V.x, V.b, X, G.xb_r);
+    k_xb_upd<T><<<nblk(hi - lo), TPB, 0, s>>>(lo, hi, V.x, X, G.xb_r);
+  }
+}
+
 template <typename T>
 static void relax(Ctx *ctx, int l) {
   Geo &G = ctx->geo[l];
@@ -1818,6 +1925,7 @@ static void relax(Ctx *ctx, int l) {
   } else {
     for (int col = 0; col < 5; col++) k_box<T><<<box_grid(K, G.N), TPB, 0, s>>>(G.N, G.W, BK, G.cls, V.x, V.b, col);
   }
+  xb_relax<T>(ctx, l);
   const bool band = ctx->prm.bnd_sweeps > 0 && G.nband > 0;
   const size_t lds_bytes = (size_t)G.nreg * sizeof(T);
   const size_t sec_base = ((G.sec_maxreg * sizeof(T) + 7) & ~(size_t)7) + 2 * (size_t)G.sec_maxrow * sizeof(double);
@@ -1952,7 +2060,7 @@ static size_t small_cycle_setup(Ctx *ctx, int l, SmallCycle &P) {
   P.nl = ctx->L - l;
   if (P.nl < 2 || P.nl > SC_MAXL) return 0;
   size_t off = 0;
-  int maxng = 0;
+  int maxng = 0, maxxs = 0;
   auto take = [&](size_t bytes) {
     size_t o = off;
     off += (bytes + 15) & ~(size_t)15;
@@ -1992,9 +2100,14 @@ static size_t small_cycle_setup(Ctx *ctx, int l, SmallCycle &P) {
     S.ogc = bottom ? 0 : take((size_t)9 * G.ng * sizeof(int));
     S.ogp = bottom ? 0 : take((size_t)G.ng * sizeof(int));
     S.obl = bottom ? 0 : take((size_t)S.nband * sizeof(int));
+    S.nxb = (!bottom && ctx->prm.ghost_boxes) ? G.nxb : 0;
+    for (int c = 0; c < 6; c++) S.xso[c] = G.xb_soff[c];
+    S.xb = xb_tab(G);
     if (!bottom) maxng = std::max(maxng, G.ng);
+    if (S.nxb) maxxs = std::max(maxxs, G.xb_maxs);
   }
   P.onv = take((size_t)maxng * sizeof(double));
+  P.oxr = take((size_t)std::max(1, maxxs) * sizeof(double));
   if (off + 2048 > ctx->max_lds) return 0;
   P.Ainv = ctx->c_inv;
   P.map = ctx->c_map;
@@ -2106,6 +2219,8 @@ gp_status set_wall_dirichlet(Ctx *ctx) {
 }
 
 gp_status relax64(Ctx *ctx, int level, int steps) {
+  gp_status st = ensure_xb(ctx);
+  if (st) return st;
   gsum<double>(ctx, level);
   for (int q = 0; q < steps; q++) relax<double>(ctx, level);
   GP_HIP(hipGetLastError());
@@ -2203,6 +2318,7 @@ gp_status residual64(Ctx *ctx, int level, double *res_inf) {
 gp_status mg_cycle64(Ctx *ctx, double *res_inf) {
   gp_status st = set_wall_dirichlet(ctx);
   if (st) return st;
+  if ((st = ensure_xb(ctx))) return st;
   gsum<double>(ctx, 0);
   cycle<double>(ctx, 0);
   mean_project<double>(ctx);
@@ -2332,6 +2448,7 @@ gp_status mg_solve(Ctx *ctx, int precision, double tol, int max_cycles, gp_stats
   auto t0 = std::chrono::steady_clock::now();
   gp_status st = set_wall_dirichlet(ctx);
   if (st) return st;
+  if ((st = ensure_xb(ctx))) return st;
   double r0, bn;
   if ((st = resnorm64(ctx, &r0))) return st;
   if ((st = bnorm64(ctx, &bn))) return st;

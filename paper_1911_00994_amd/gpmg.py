@@ -24,7 +24,7 @@ EXPORTS = [
     "gp_get_boundary_geometry",
     "gp_set_boundary_values", "gp_set_alpha", "gp_set_rhs", "gp_set_x", "gp_get_x", "gp_mg_vcycle", "gp_solve",
     "gp_residual", "gp_set_state", "gp_cn_step", "gp_get_classes", "gp_get_ghost_rows", "gp_get_ext_rows",
-    "gp_get_band_layout",
+    "gp_get_band_layout", "gp_get_coupled_boxes",
     "gp_relax", "gp_time_kernel", "gp_probe_start", "gp_probe_stop", "gp_apply_mt", "gp_adjoint_solve", "gp_apply_cycle", "gp_apply_cycle_t",
     "gp_tape_forward", "gp_tape_backward",
 ]
@@ -38,7 +38,7 @@ class GpParams(ctypes.Structure):
                 ("mixed_inner_cycles", ctypes.c_int), ("bnd_sweeps", ctypes.c_int), ("bnd_radius", ctypes.c_int),
                 ("fuse_small_levels", ctypes.c_int), ("band_split_min", ctypes.c_int),
                 ("graph_iterations", ctypes.c_int), ("band_sector_min", ctypes.c_int),
-                ("queue_ahead", ctypes.c_int)]
+                ("queue_ahead", ctypes.c_int), ("ghost_boxes", ctypes.c_int)]
 
 
 class GpRigid(ctypes.Structure):
@@ -104,6 +104,7 @@ def lib():
         "gp_cn_step": (i, [vp, d, vp, vp, vp, i, i, d, i, d, i, ctypes.POINTER(GpStats)]),
         "gp_get_classes": (i, [vp, i, vp]),
         "gp_get_band_layout": (i, [vp, i, vp]),
+        "gp_get_coupled_boxes": (i, [vp, i, vp, vp, vp, vp, vp, vp]),
         "gp_get_ghost_rows": (i, [vp, i, vp, vp, vp, vp, vp, vp, vp]),
         "gp_get_ext_rows": (i, [vp, i, vp, vp]),
         "gp_relax": (i, [vp, i, i]),
@@ -310,6 +311,21 @@ class Solver:
         out = np.zeros(4, dtype=np.int32)
         self._check(lib().gp_get_band_layout(self._h, level, _ptr(out)), "gp_get_band_layout")
         return {"nband": int(out[0]), "nbg": int(out[1]), "sectors": int(out[2]), "lds_ok": bool(out[3])}
+
+    def coupled_boxes(self, level=0):
+        """The coupled-box table of one level (boxes in visiting order: colour, then cell)."""
+        cnt = np.zeros(2, dtype=np.int32)
+        self._check(lib().gp_get_coupled_boxes(self._h, level, _ptr(cnt), None, None, None, None, None),
+                    "gp_get_coupled_boxes")
+        nb, ns = int(cnt[0]), int(cnt[1])
+        cell = np.zeros(max(nb, 1), dtype=np.int32)
+        off = np.zeros(nb + 1, dtype=np.int32)
+        idx = np.zeros(max(ns, 1), dtype=np.int32)
+        wr = np.zeros(max(ns, 1), dtype=np.uint8)
+        coff = np.zeros(6, dtype=np.int32)
+        self._check(lib().gp_get_coupled_boxes(self._h, level, _ptr(cnt), _ptr(cell), _ptr(off), _ptr(idx), _ptr(wr),
+                                               _ptr(coff)), "gp_get_coupled_boxes")
+        return dict(cell=cell[:nb], off=off, idx=idx[:ns], wr=wr[:ns], coff=coff)
 
     def ghost_rows(self, level=0):
         W = self.level_n(level) + 2
