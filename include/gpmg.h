@@ -86,6 +86,8 @@ typedef struct {
   int bnd_sweeps, bnd_radius;
   int fuse_small_levels, band_split_min, graph_iterations, band_sector_min, queue_ahead;
   int ghost_boxes; /* 1: coupled ghost boxes in every relaxation step (see above); 0: plain boxes only */
+  int krylov;      /* m > 0: gp_solve and gp_adjoint_solve accelerate the cycle by GCR restarted after m directions
+                      (see gp_solve); 0: the cycle on its own */
 } gp_params;
 
 /* rigid motion: the body frame point of x at time t is R(-omega t) (x - X0 - U t); the boundary velocity at a

@@ -65,6 +65,8 @@ def lib():
             ("or_ext_fail_count", [vp, i]),
             ("or_test_restrict", [vp, i, vp, vp]),
             ("or_test_prolong", [vp, i, vp, vp]),
+            ("or_coupled_box_count", [vp, i, vp, vp]),
+            ("or_get_coupled_boxes", [vp, i, vp, vp, vp, vp, vp, vp]),
         ]:
             f = getattr(L, name)
             f.restype = i
@@ -123,10 +125,10 @@ class Oracle:
 
     def __init__(self, N, Re=100.0, nu1=2, nu2=2, gamma=1, lam=2, coarsest_n=8, march_max=8, ext_radius=4,
                  perm_seed=0, dtau_dir=0.9, dtau_neu_over_h=0.9, eps_over_h=0.01, cg_min=0.1, bnd_sweeps=0, bnd_radius=2,
-                 ghost_boxes=1, lex_order=0):
+                 ghost_boxes=1, lex_order=0, krylov=16):
         self.N, self.W, self.Re = N, N + 2, Re
         ip = np.array([nu1, nu2, gamma, lam, coarsest_n, march_max, ext_radius, perm_seed, bnd_sweeps, bnd_radius,
-                       ghost_boxes, lex_order], dtype=np.int32)
+                       ghost_boxes, lex_order, krylov], dtype=np.int32)
         dp = np.array([dtau_dir, dtau_neu_over_h, eps_over_h, cg_min], dtype=np.float64)
         self._h = lib().or_create(N, Re, _p(ip), _p(dp))
         if not self._h:
@@ -171,6 +173,20 @@ class Oracle:
         assert lib().or_get_ghost_rows(self._h, l, _p(B), _p(nB), _p(th), _p(w9), _p(c9), _p(dt), _p(va)) == OK
         return dict(B=B.reshape(P, 2), nB=nB.reshape(P, 2), theta=th.reshape(P, 2), w=w9.reshape(P, 9),
                     col=c9.reshape(P, 9), dtau=dt, valid=va)
+
+    def coupled_boxes(self, l=0) -> dict:
+        """The coupled-box table of level l (boxes in visiting order: colour, then cell index)."""
+        nb, ns = ctypes.c_int(0), ctypes.c_int(0)
+        assert lib().or_coupled_box_count(self._h, l, ctypes.byref(nb), ctypes.byref(ns)) == OK
+        cell = np.zeros(max(nb.value, 1), dtype=np.int32)
+        off = np.zeros(nb.value + 1, dtype=np.int32)
+        nbx = np.zeros(max(nb.value, 1), dtype=np.int32)
+        idx = np.zeros(max(ns.value, 1), dtype=np.int32)
+        wr = np.zeros(max(ns.value, 1), dtype=np.uint8)
+        coff = np.zeros(6, dtype=np.int32)
+        assert lib().or_get_coupled_boxes(self._h, l, _p(cell), _p(off), _p(nbx), _p(idx), _p(wr), _p(coff)) == OK
+        return dict(cell=cell[:nb.value], off=off, nbox=nbx[:nb.value], idx=idx[:ns.value], wr=wr[:ns.value],
+                    coff=coff)
 
     def ext_rows(self, l=0):
         W = self.level_n(l) + 2

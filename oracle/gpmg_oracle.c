@@ -98,7 +98,7 @@ typedef struct {
   double Re, alpha;
   /* parameters */
   int nu1, nu2, gamma, lambda, coarsest_n, march_max, nbis, ext_radius, colour_perm_seed, bnd_sweeps, bnd_radius;
-  int ghost_boxes, lex_order;
+  int ghost_boxes, lex_order, krylov;
   double dtau_dir, dtau_neu_over_h, eps_over_h, cg_min;
   /* geometry / boundary data */
   double *phi; /* (2N+1)^2 fine half lattice */
@@ -311,7 +311,7 @@ static void free_level(OLevel *L) {
 }
 
 /* iparams: nu1 nu2 gamma lambda coarsest_n march_max ext_radius colour_perm_seed bnd_sweeps bnd_radius
- *          ghost_boxes lex_order
+ *          ghost_boxes lex_order krylov
  * dparams: dtau_dir dtau_neu_over_h eps_over_h cg_min (coarse levels) */
 void *or_create(int N, double Re, const int *ip, const double *dp) {
   if (N < 8 || (N & (N - 1))) return NULL;
@@ -330,6 +330,7 @@ void *or_create(int N, double Re, const int *ip, const double *dp) {
   S->bnd_radius = ip[9];
   S->ghost_boxes = ip[10];
   S->lex_order = ip[11];
+  S->krylov = ip[12];
 
   S->dtau_dir = dp[0];
   S->dtau_neu_over_h = dp[1];
@@ -389,6 +390,29 @@ void or_destroy(void *h) {
 }
 
 int or_num_levels(void *h) { return ((OSolver *)h)->L; }
+
+/* the coupled-box table of a level: counts, then (cell, slot offsets, number of box unknowns, unknown
+ * indices, write flags, colour offsets) in the order the relaxation visits the boxes */
+int or_coupled_box_count(void *h, int l, int *nbox, int *nslot) {
+  OSolver *S = (OSolver *)h;
+  if (l < 0 || l >= S->L) return E_INVAL;
+  *nbox = S->lev[l].nxb;
+  *nslot = S->lev[l].nxb ? S->lev[l].xb_off[S->lev[l].nxb] : 0;
+  return OK;
+}
+int or_get_coupled_boxes(void *h, int l, int *cell, int *off, int *nbox, int *idx, unsigned char *wr, int *coff) {
+  OSolver *S = (OSolver *)h;
+  if (l < 0 || l >= S->L) return E_INVAL;
+  OLevel *L = &S->lev[l];
+  int ns = L->nxb ? L->xb_off[L->nxb] : 0;
+  memcpy(cell, L->xb_cell, sizeof(int) * L->nxb);
+  memcpy(off, L->xb_off, sizeof(int) * (L->nxb + 1));
+  memcpy(nbox, L->xb_nbox, sizeof(int) * L->nxb);
+  memcpy(idx, L->xb_idx, sizeof(int) * ns);
+  memcpy(wr, L->xb_wr, ns);
+  memcpy(coff, L->xb_coff, sizeof(int) * 6);
+  return OK;
+}
 int or_level_n(void *h, int l) { return ((OSolver *)h)->lev[l].N; }
 
 /* ------------------------------------------------------------------------- */
@@ -1690,7 +1714,49 @@ int or_cycle(void *h, double *res_inf) {
   return (r != r) ? E_DIVERGED : OK;
 }
 
-/* stats: cycles, res0, res, rho (geometric mean of the last ratios) */
+/* y = M x over the rows that carry an equation (internal, ghost, wall and mean rows); 0 elsewhere */
+static void matvec(OLevel *L, const double *x, double *y) {
+  for (int k = 0; k < L->n; k++) {
+    unsigned char c = (k < 3 * L->W * L->W) ? L->cls[k] : C_INT;
+    y[k] = (c == C_INT || ghost_row_class(c) || c == C_WALLD) ? row_dot(L, k, x) : 0.0;
+  }
+}
+static double dot(const double *a, const double *b, int n) {
+  double s = 0;
+  for (int k = 0; k < n; k++) s += a[k] * b[k];
+  return s;
+}
+
+/* the cycle as a linear operator on a residual vector: one cycle from zero with right-hand side r, the mean
+ * projection, then the pressure unknowns shifted by the mean-row entry of r (the cycle itself solves the other
+ * rows and leaves the mean at zero; a constant pressure shift changes no other row).  z = 0 where no equation. */
+static void precondition(OSolver *S, const double *r, double *z) {
+  OLevel *L = &S->lev[0];
+  int WW = L->W * L->W;
+  double *sb = L->b, *sx = L->x;
+  L->b = (double *)r;
+  L->x = z;
+  for (int k = 0; k < L->n; k++) z[k] = 0.0;
+  set_wall_dirichlet(S);
+  mg_cycle(S, 0);
+  mean_project(S);
+  for (int k = 2 * WW; k < 3 * WW; k++)
+    if (L->cls[k] == C_INT || L->cls[k] == C_GHOST || L->cls[k] == C_GHOSTX) z[k] += r[3 * WW];
+  for (int k = 0; k < 3 * WW; k++) {
+    unsigned char c = L->cls[k];
+    if (!(c == C_INT || ghost_row_class(c) || c == C_WALLD)) z[k] = 0.0;
+  }
+  L->b = sb;
+  L->x = sx;
+}
+
+/* Solve M x = b to ||r||_inf <= tol max(1, ||b||_inf).
+ * krylov = 0: repeated cycles x <- x + B'(b - M x) (the multigrid iteration of Sect. 4 on its own).
+ * krylov = m > 0: the same cycle B' as the preconditioner of a generalized conjugate residual iteration (GCR,
+ * restarted after m directions): z = B' r, q = M z, q and z orthogonalised against the stored q's (classical
+ * Gram-Schmidt, one pass), normalised, x += (r.q) z, r -= (r.q) q.  The residual is updated recursively; when
+ * it meets the tolerance the true residual is formed and the iteration restarts from it if it does not.
+ * stats: cycles, res0, res, rho (last residual ratio). */
 int or_solve(void *h, double tol, int max_cycles, double *stats) {
   OSolver *S = (OSolver *)h;
   if (!S->have_geom) return E_INVAL;
@@ -1703,24 +1769,77 @@ int or_solve(void *h, double tol, int max_cycles, double *stats) {
   double r = r0, rprev = r0;
   int c = 0;
   double rho = 0;
+  int status = OK;
   S->res_hist[0] = r0;
-  while (r > thr && c < max_cycles) {
-    mg_cycle(S, 0);
-    mean_project(S);
-    rprev = r;
-    r = res_norm_finest(S);
-    c++;
-    if (c < 1024) S->res_hist[c] = r;
-    rho = r / rprev;
-    if (r != r || r > 1e6 * (r0 > 1 ? r0 : 1)) {
-      if (stats) {
-        stats[0] = c;
-        stats[1] = r0;
-        stats[2] = r;
-        stats[3] = rho;
+  if (S->krylov <= 0) {
+    while (r > thr && c < max_cycles) {
+      mg_cycle(S, 0);
+      mean_project(S);
+      rprev = r;
+      r = res_norm_finest(S);
+      c++;
+      if (c < 1024) S->res_hist[c] = r;
+      rho = r / rprev;
+      if (r != r || r > 1e6 * (r0 > 1 ? r0 : 1)) {
+        status = E_DIVERGED;
+        break;
       }
-      return E_DIVERGED;
     }
+  } else {
+    int n = L->n, m = S->krylov;
+    double *rv = (double *)xcalloc(n, sizeof(double)), *zv = (double *)xcalloc(n, sizeof(double));
+    double *qv = (double *)xcalloc(n, sizeof(double));
+    double *Q = (double *)xcalloc((size_t)m * n, sizeof(double)), *Z = (double *)xcalloc((size_t)m * n, sizeof(double));
+    double *beta = (double *)xcalloc(m, sizeof(double));
+    memcpy(rv, L->r, sizeof(double) * n); /* true residual from res_norm_finest */
+    int k = 0;
+    while (r > thr && c < max_cycles) {
+      precondition(S, rv, zv);
+      matvec(L, zv, qv);
+      for (int i = 0; i < k; i++) beta[i] = dot(&Q[(size_t)i * n], qv, n);
+      for (int i = 0; i < k; i++)
+        for (int e = 0; e < n; e++) {
+          qv[e] -= beta[i] * Q[(size_t)i * n + e];
+          zv[e] -= beta[i] * Z[(size_t)i * n + e];
+        }
+      double nu = sqrt(dot(qv, qv, n));
+      c++;
+      if (!(nu > 0)) { /* no new direction: the residual is already in the span (or the cycle broke down) */
+        status = (nu == nu) ? E_NOCONV : E_DIVERGED;
+        break;
+      }
+      for (int e = 0; e < n; e++) {
+        qv[e] /= nu;
+        zv[e] /= nu;
+      }
+      double a = dot(rv, qv, n);
+      for (int e = 0; e < n; e++) {
+        L->x[e] += a * zv[e];
+        rv[e] -= a * qv[e];
+      }
+      memcpy(&Q[(size_t)k * n], qv, sizeof(double) * n);
+      memcpy(&Z[(size_t)k * n], zv, sizeof(double) * n);
+      k++;
+      rprev = r;
+      r = norm_inf(rv, n);
+      if (r <= thr || k == m) { /* confirm with the true residual, or restart from it */
+        r = res_norm_finest(S);
+        memcpy(rv, L->r, sizeof(double) * n);
+        k = 0;
+      }
+      if (c < 1024) S->res_hist[c] = r;
+      rho = r / rprev;
+      if (r != r || r > 1e6 * (r0 > 1 ? r0 : 1)) {
+        status = E_DIVERGED;
+        break;
+      }
+    }
+    free(rv);
+    free(zv);
+    free(qv);
+    free(Q);
+    free(Z);
+    free(beta);
   }
   S->last_cycles = c;
   if (stats) {
@@ -1729,6 +1848,7 @@ int or_solve(void *h, double tol, int max_cycles, double *stats) {
     stats[2] = r;
     stats[3] = rho;
   }
+  if (status != OK) return status;
   return r <= thr ? OK : E_NOCONV;
 }
 

@@ -765,7 +765,33 @@ gp_status adjoint_solve_dev(Ctx *ctx, double tol, int max_cycles, gp_stats *stt)
   const double thr = tol * (gn > 1 ? gn : 1);
   int c = 0;
   gp_status out = GP_OK;
-  for (;;) {
+  if (ctx->prm.krylov > 0) {
+    // GCR with the transposed cycle as the preconditioner (the transpose of the forward solve's iteration)
+    if ((st = gcr_alloc(ctx))) return st;
+    const long n = G.n;
+    mt_apply(ctx, 0, ctx->a_lam, ctx->a_g, -1.0, ctx->kr_r);
+    if ((st = absmax_dev(ctx, ctx->kr_r, n, &r0))) return st;
+    GcrOps ops;
+    ops.precond = [&](const double *r, double *z) {
+      k_copy<<<nblk(n), TPB, 0, s>>>(A.x, r, n);
+      apply_cycle_t(ctx);
+      k_copy<<<nblk(n), TPB, 0, s>>>(z, A.b, n);
+      k_mask_unknowns<<<nblk(3L * G.WW), TPB, 0, s>>>(3 * G.WW, G.cls, z);
+    };
+    ops.apply_neg = [&](const double *z, double *q) {
+      mt_apply(ctx, 0, z, ctx->kr_zero, -1.0, q);
+      k_mask_unknowns<<<nblk(3L * G.WW), TPB, 0, s>>>(3 * G.WW, G.cls, q);
+    };
+    ops.residual = [&](double *rinf) -> gp_status {
+      mt_apply(ctx, 0, ctx->a_lam, ctx->a_g, -1.0, ctx->kr_r);
+      return absmax_dev(ctx, ctx->kr_r, n, rinf);
+    };
+    int status = GP_OK;
+    const double lim = 1e6 * (r0 > 1 ? r0 : 1);
+    if ((st = gcr_solve(ctx, ops, ctx->a_lam, ctx->kr_r, r0, thr, lim, max_cycles, &c, &r, &rho, &status))) return st;
+    out = status;
+  }
+  for (; ctx->prm.krylov == 0;) {
     mt_apply(ctx, 0, ctx->a_lam, ctx->a_g, -1.0, A.x);  // A.x = g - M^T lam
     double rp = r;
     if ((st = absmax_dev(ctx, A.x, G.n, &r))) return st;

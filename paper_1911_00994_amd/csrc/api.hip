@@ -122,6 +122,7 @@ void gp_default_params(gp_params *p) {
   p->band_sector_min = 1500;
   p->queue_ahead = 1;
   p->ghost_boxes = 1;
+  p->krylov = 16;
 }
 
 const char *gp_strerror(gp_status st) {
@@ -289,6 +290,13 @@ void gp_destroy(gp_ctx *ctx) {
   dfree(ctx->cku);
   dfree(ctx->ckv);
   dfree(ctx->fwork);
+  dfree(ctx->kr_r);
+  dfree(ctx->kr_z);
+  dfree(ctx->kr_Q);
+  dfree(ctx->kr_Z);
+  dfree(ctx->kr_zero);
+  dfree(ctx->kr_s);
+  dfree(ctx->kr_part);
   if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
   delete ctx;
 }
@@ -304,7 +312,7 @@ gp_status gp_setup_grid(gp_ctx **out, int N, double Re, const gp_params *prm, vo
   if (!pow2(N) || N < 16 || !pow2(P.coarsest_n) || P.coarsest_n < 4 || P.coarsest_n > N / 2 || P.nu1 < 0 || P.nu2 < 0 ||
       P.gamma < 1 || P.lambda_ghost < 0 || P.march_max < 1 || P.ext_radius < 1 || !(Re > 0) || P.mixed_inner_cycles < 1 ||
       P.bnd_sweeps < 0 || P.bnd_radius < 0 || P.band_split_min < 1 || P.band_sector_min < 1 ||
-      (P.ghost_boxes != 0 && P.ghost_boxes != 1))
+      (P.ghost_boxes != 0 && P.ghost_boxes != 1) || P.krylov < 0 || P.krylov > 64)
     return GP_EINVAL;
   gp_ctx *ctx = new gp_ctx();
   ctx->N = N;

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <functional>
 #include <mutex>
 #include <thread>
 #include <string>
@@ -216,6 +217,12 @@ struct Ctx {
   const double *gs_ptr[MAXLEV] = {nullptr};
   int gs_n[MAXLEV] = {0};
   bool head_queued = false, head_probe = false;
+  // generalized conjugate residual iteration around the cycle (finest-level vectors of n = 3 W^2 + 1 doubles):
+  // residual, direction, the stored normalised directions Z and their images Q (kr_m of each), a zero vector,
+  // device scalars (the Gram-Schmidt coefficients, then |q|^2, (r, q) and the step)
+  int kr_m = 0;
+  double *kr_r = nullptr, *kr_z = nullptr, *kr_Q = nullptr, *kr_Z = nullptr, *kr_zero = nullptr, *kr_s = nullptr;
+  double *kr_part = nullptr;        // block partials of the GCR reductions
   // the geometry of a later time built in the background (gp_prepare_levelset_analytic) in a second context
   Ctx *shadow = nullptr;
   std::thread prep;
@@ -259,6 +266,18 @@ gp_status set_wall_dirichlet(Ctx *ctx);
 gp_status time_kernel(Ctx *ctx, int which, int level, int reps, double *avg_us);
 gp_status probe_start(Ctx *ctx, int max_launches, int every);
 gp_status probe_stop(Ctx *ctx, double *avg_us, int *launches);
+
+// GCR (mg.hip): M x = b to ||r||_inf <= thr.  precond(r, z): z = B' r (the cycle as an operator, 0 where no
+// equation); apply_neg(z, q): q = -M z; residual(x, r): r = b - M x (true residual) and its max norm.  x and r
+// are the caller's device vectors (n doubles); r must hold b - M x on entry.
+struct GcrOps {
+  std::function<void(const double *r, double *z)> precond;
+  std::function<void(const double *z, double *q)> apply_neg;
+  std::function<gp_status(double *rinf)> residual;
+};
+gp_status gcr_solve(Ctx *ctx, GcrOps &ops, double *x, double *r, double r0, double thr, double lim, int max_it,
+                    int *iters, double *res, double *rho, int *status);
+gp_status gcr_alloc(Ctx *ctx);
 
 // adjoint (adjoint.hip)
 gp_status adjoint_alloc(Ctx *ctx);

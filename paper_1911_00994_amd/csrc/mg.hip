@@ -2444,7 +2444,314 @@ static void drop_head(Ctx *ctx) {
   if (ctx->head_probe) ctx->probe_n--;
 }
 
+// ---------------------------------------------------------------------------------------------------------
+// generalized conjugate residual iteration (GCR) around the cycle.  Per iteration: z = B' r (the preconditioner),
+// q = M z, q and z orthogonalised against the stored images Q_i and directions Z_i (classical Gram-Schmidt, one
+// pass), Q_k = q / |q|, Z_k = z / |q|, x += (r . Q_k) Z_k, r -= (r . Q_k) Q_k.  The vectors are the finest level's
+// full unknown vectors (3 W^2 + 1 doubles, zero where no equation); every reduction runs over GR_B fixed blocks and
+// is summed in block order, so the iteration is deterministic.  The image is formed as -M z (the residual kernel
+// with a zero right-hand side), so the kernels below carry qn = -q.
+// ---------------------------------------------------------------------------------------------------------
+constexpr int GR_B = 256, GR_T = 256, KR_MAX = 64;
+
+// partials of the k dot products (Q_i . qn), i < k: part[i * GR_B + block]
+__global__ void __launch_bounds__(GR_T) k_gcr_dots(const double *__restrict__ Q, long n, int k, const double *__restrict__ qn,
+                                                   double *part) {
+  __shared__ double sm[GR_T];
+  double acc[KR_MAX / 4];
+  for (int i0 = 0; i0 < k; i0 += KR_MAX / 4) {
+    const int kk = min(KR_MAX / 4, k - i0);
+    for (int i = 0; i < KR_MAX / 4; i++) acc[i] = 0;
+    for (long e = blockIdx.x * (long)GR_T + threadIdx.x; e < n; e += (long)GR_B * GR_T) {
+      const double q = qn[e];
+#pragma unroll
+      for (int i = 0; i < KR_MAX / 4; i++)
+        if (i < kk) acc[i] += Q[(size_t)(i0 + i) * n + e] * q;
+    }
+    for (int i = 0; i < kk; i++) {
+      sm[threadIdx.x] = acc[i];
+      __syncthreads();
+      for (int o = GR_T / 2; o > 0; o >>= 1) {
+        if (threadIdx.x < o) sm[threadIdx.x] += sm[threadIdx.x + o];
+        __syncthreads();
+      }
+      if (threadIdx.x == 0) part[(size_t)(i0 + i) * GR_B + blockIdx.x] = sm[0];
+      __syncthreads();
+    }
+  }
+}
+// sum the partials of cnt reductions in block order: out[i] = sum_b part[i * GR_B + b]
+__global__ void __launch_bounds__(GR_B) k_gcr_sum(const double *__restrict__ part, int cnt, double *out) {
+  __shared__ double sm[GR_B];
+  for (int i = 0; i < cnt; i++) {
+    sm[threadIdx.x] = part[(size_t)i * GR_B + threadIdx.x];
+    __syncthreads();
+    for (int o = GR_B / 2; o > 0; o >>= 1) {
+      if (threadIdx.x < o) sm[threadIdx.x] += sm[threadIdx.x + o];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) out[i] = sm[0];
+    __syncthreads();
+  }
+}
+// Gram-Schmidt step: qn' = qn - sum_i b_i Q_i, z' = z - sum_i b_i Z_i with b_i = Q_i . qn (beta), then the
+// partials of |qn'|^2 and r . qn' into part[0 * GR_B + block], part[1 * GR_B + block]
+__global__ void __launch_bounds__(GR_T) k_gcr_orth(const double *__restrict__ Q, const double *__restrict__ Z, long n,
+                                                   int k, const double *__restrict__ beta, double *qn, double *z,
+                                                   const double *__restrict__ r, double *part) {
+  __shared__ double sm[GR_T];
+  double s2 = 0, sr = 0;
+  for (long e = blockIdx.x * (long)GR_T + threadIdx.x; e < n; e += (long)GR_B * GR_T) {
+    double q = qn[e], zz = z[e];
+    for (int i = 0; i < k; i++) {
+      const double b = beta[i];
+      q -= b * Q[(size_t)i * n + e];
+      zz -= b * Z[(size_t)i * n + e];
+    }
+    if (k) {
+      qn[e] = q;
+      z[e] = zz;
+    }
+    s2 += q * q;
+    sr += r[e] * q;
+  }
+  for (int w = 0; w < 2; w++) {
+    sm[threadIdx.x] = w == 0 ? s2 : sr;
+    __syncthreads();
+    for (int o = GR_T / 2; o > 0; o >>= 1) {
+      if (threadIdx.x < o) sm[threadIdx.x] += sm[threadIdx.x + o];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) part[(size_t)w * GR_B + blockIdx.x] = sm[0];
+    __syncthreads();
+  }
+}
+// the step, with nu^2 = |qn|^2 and s = r . qn (sc[0], sc[1]) and g = s / nu^2: the direction's image is
+// M (z / nu) = -qn / nu, and its coefficient r . (-qn / nu) = -s / nu, so x -= g z and r -= g qn; the stored pair is
+// Q_k = qn / nu, Z_k = z / nu (so that M Z_k = -Q_k for every stored pair); block maxima of |r| into part[block]
+__global__ void __launch_bounds__(GR_T) k_gcr_step(long n, const double *__restrict__ sc, double *qn, double *z, double *x,
+                                                   double *r, double *Qk, double *Zk, double *part) {
+  __shared__ double sm[GR_T];
+  const double nu2 = sc[0], s = sc[1];
+  const double inv = nu2 > 0 ? 1.0 / sqrt(nu2) : 0.0, g = nu2 > 0 ? s / nu2 : 0.0;
+  double m = 0;
+  for (long e = blockIdx.x * (long)GR_T + threadIdx.x; e < n; e += (long)GR_B * GR_T) {
+    const double q = qn[e], zz = z[e];
+    x[e] -= g * zz;
+    const double rr = r[e] - g * q;
+    r[e] = rr;
+    Qk[e] = q * inv;
+    Zk[e] = zz * inv;
+    const double a = fabs(rr);
+    m = (a > m || a != a) ? a : m;
+  }
+  sm[threadIdx.x] = m;
+  __syncthreads();
+  for (int o = GR_T / 2; o > 0; o >>= 1) {
+    if (threadIdx.x < o) {
+      const double v = sm[threadIdx.x + o];
+      if (v > sm[threadIdx.x] || v != v) sm[threadIdx.x] = v;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = sm[0];
+}
+// max of the block maxima into *dmax (as bits) and *hmax (pinned host memory)
+__global__ void __launch_bounds__(GR_B) k_gcr_max(const double *__restrict__ part, unsigned long long *dmax,
+                                                  unsigned long long *hmax) {
+  __shared__ double sm[GR_B];
+  sm[threadIdx.x] = part[threadIdx.x];
+  __syncthreads();
+  for (int o = GR_B / 2; o > 0; o >>= 1) {
+    if (threadIdx.x < o) {
+      const double v = sm[threadIdx.x + o];
+      if (v > sm[threadIdx.x] || v != v) sm[threadIdx.x] = v;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const unsigned long long b = (unsigned long long)__double_as_longlong(sm[0]);
+    *dmax = b;
+    if (hmax) __hip_atomic_store(hmax, b, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+  }
+}
+
+gp_status gcr_alloc(Ctx *ctx) {
+  const int m = std::max(1, ctx->prm.krylov);
+  if (ctx->kr_r && ctx->kr_m == m) return GP_OK;
+  const size_t n = ctx->geo[0].n;
+  auto fr = [](double *&p) {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+  };
+  fr(ctx->kr_r);
+  fr(ctx->kr_z);
+  fr(ctx->kr_Q);
+  fr(ctx->kr_Z);
+  fr(ctx->kr_zero);
+  fr(ctx->kr_s);
+  fr(ctx->kr_part);
+  GP_HIP(hipMalloc((void **)&ctx->kr_r, n * sizeof(double)));
+  GP_HIP(hipMalloc((void **)&ctx->kr_z, n * sizeof(double)));
+  GP_HIP(hipMalloc((void **)&ctx->kr_Q, (size_t)m * n * sizeof(double)));
+  GP_HIP(hipMalloc((void **)&ctx->kr_Z, (size_t)m * n * sizeof(double)));
+  GP_HIP(hipMalloc((void **)&ctx->kr_zero, n * sizeof(double)));
+  GP_HIP(hipMalloc((void **)&ctx->kr_s, (KR_MAX + 8) * sizeof(double)));
+  GP_HIP(hipMalloc((void **)&ctx->kr_part, (size_t)(KR_MAX + 2) * GR_B * sizeof(double)));
+  GP_HIP(hipMemsetAsync(ctx->kr_zero, 0, n * sizeof(double), ctx->stream));
+  ctx->kr_m = m;
+  return GP_OK;
+}
+
+gp_status gcr_solve(Ctx *ctx, GcrOps &ops, double *x, double *r, double r0, double thr, double lim, int max_it,
+                    int *iters, double *res, double *rho, int *status) {
+  gp_status st = gcr_alloc(ctx);
+  if (st) return st;
+  hipStream_t s = ctx->stream;
+  const long n = ctx->geo[0].n;
+  const int m = ctx->kr_m;
+  double *beta = ctx->kr_s, *sc = ctx->kr_s + KR_MAX;
+  double rn = r0, rp = r0;
+  int c = 0, k = 0;
+  *status = GP_OK;
+  *rho = 0;
+  while (rn > thr && c < max_it) {
+    double *z = ctx->kr_z, *qn = ctx->v64[0].r;
+    ops.precond(r, z);
+    ops.apply_neg(z, qn);  // qn = -M z
+    // Gram-Schmidt against the stored images: with M Z_i = -Q_i and qn = -M z, q' = q - (q . M Z_i) M Z_i reads
+    // qn' = qn - (Q_i . qn) Q_i, and z' = z - (Q_i . qn) Z_i
+    if (k) {
+      k_gcr_dots<<<GR_B, GR_T, 0, s>>>(ctx->kr_Q, n, k, qn, ctx->kr_part);
+      k_gcr_sum<<<1, GR_B, 0, s>>>(ctx->kr_part, k, beta);
+    }
+    k_gcr_orth<<<GR_B, GR_T, 0, s>>>(ctx->kr_Q, ctx->kr_Z, n, k, beta, qn, z, r, ctx->kr_part);
+    k_gcr_sum<<<1, GR_B, 0, s>>>(ctx->kr_part, 2, sc);
+    k_gcr_step<<<GR_B, GR_T, 0, s>>>(n, sc, qn, z, x, r, ctx->kr_Q + (size_t)k * n, ctx->kr_Z + (size_t)k * n, ctx->kr_part);
+    __atomic_store_n(ctx->h_rmax, NORM_PENDING, __ATOMIC_RELEASE);
+    k_gcr_max<<<1, GR_B, 0, s>>>(ctx->kr_part, (unsigned long long *)(ctx->d_scal + 1), ctx->h_rmax);
+    GP_HIP(hipGetLastError());
+    if ((st = wait_norm(ctx, &rn))) return st;
+    c++;
+    k++;
+    if (!(rn == rn) || rn > lim) {
+      *status = GP_EDIVERGED;
+      break;
+    }
+    if (rn <= thr || k == m) {  // confirm with the true residual, or restart from it
+      if ((st = ops.residual(&rn))) return st;
+      k = 0;
+    }
+    *rho = rn / rp;
+    rp = rn;
+  }
+  *iters = c;
+  *res = rn;
+  return GP_OK;
+}
+
+// the cycle's result as a preconditioner output: pressure unknowns shifted by the mean-row entry of r (the cycle
+// itself leaves the mean at zero; a constant pressure changes no other row), zero where no equation
+template <typename T>
+__global__ void k_pc_out(const uint8_t *__restrict__ cls, int WW, const T *xin, const double *__restrict__ r, double *z) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t > 3 * WW) return;
+  if (t == 3 * WW) {
+    z[t] = (double)xin[t];
+    return;
+  }
+  const uint8_t c = cls[t];
+  const bool eq = c == K_INT || c == K_GHOST || c == K_GHOSTX || c == K_WALLG || c == K_WALLD;
+  const bool pu = t >= 2 * WW && (c == K_INT || c == K_GHOST || c == K_GHOSTX);
+  z[t] = eq ? (double)xin[t] + (pu ? r[3 * WW] : 0.0) : 0.0;
+}
+
+// GCR around the FP64 cycle (precision GP_FP64) or the FP32 cycle (GP_MIXED: the preconditioner runs in FP32
+// storage, everything else in FP64)
+static gp_status gcr_mg_solve(Ctx *ctx, int precision, double tol, int max_cycles, gp_stats *stt) {
+  auto t0 = std::chrono::steady_clock::now();
+  gp_status st = set_wall_dirichlet(ctx);
+  if (st) return st;
+  if ((st = ensure_xb(ctx))) return st;
+  if (precision != GP_FP64 && (st = ensure_fp32(ctx))) return st;
+  if ((st = gcr_alloc(ctx))) return st;
+  Geo &G = ctx->geo[0];
+  Vec<double> &V = ctx->v64[0];
+  hipStream_t s = ctx->stream;
+  const long n = G.n;
+  double *X0 = V.x, *B0 = V.b;
+  double r0, bn;
+  if ((st = resnorm64(ctx, &r0))) return st;  // V.r = b - M x
+  GP_HIP(hipMemcpyAsync(ctx->kr_r, V.r, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+  if ((st = bnorm64(ctx, &bn))) return st;
+  const double thr = tol * (bn > 1 ? bn : 1), lim = 1e6 * (r0 > 1 ? r0 : 1);
+  GcrOps ops;
+  ops.precond = [&](const double *r, double *z) {
+    if (precision == GP_FP64) {
+      double *Y0 = V.y;
+      V.x = z;
+      V.b = const_cast<double *>(r);
+      k_fill<double><<<nblk(n), TPB, 0, s>>>(z, n, 0.0);
+      k_set_walld<double><<<nblk(3L * G.WW), TPB, 0, s>>>(3 * G.WW, G.cls, z, r);
+      gsum<double>(ctx, 0);
+      cycle<double>(ctx, 0);
+      mean_project<double>(ctx);
+      if (V.x != z) {  // an odd number of finest sweeps leaves the result in the second buffer
+        (void)hipMemcpyAsync(z, V.x, n * sizeof(double), hipMemcpyDeviceToDevice, s);
+      }
+      V.x = X0;
+      V.b = B0;
+      V.y = Y0;
+      k_pc_out<double><<<nblk(n), TPB, 0, s>>>(G.cls, G.WW, z, r, z);
+    } else {
+      Vec<float> &E = ctx->v32[0];
+      k_cast_rhs<<<nblk(n), TPB, 0, s>>>(r, E.b, n);
+      k_fill<float><<<nblk(n), TPB, 0, s>>>(E.x, n, 0.0f);
+      k_set_walld<float><<<nblk(3L * G.WW), TPB, 0, s>>>(3 * G.WW, G.cls, E.x, E.b);
+      gsum<float>(ctx, 0);
+      cycle<float>(ctx, 0);
+      mean_project<float>(ctx);
+      k_pc_out<float><<<nblk(n), TPB, 0, s>>>(G.cls, G.WW, E.x, r, z);
+    }
+  };
+  ops.apply_neg = [&](const double *z, double *q) {
+    V.x = const_cast<double *>(z);
+    V.b = ctx->kr_zero;
+    double *R0 = V.r;
+    V.r = q;
+    residual<double>(ctx, 0, (unsigned long long *)(ctx->d_scal + 2), nullptr, true);
+    V.x = X0;
+    V.b = B0;
+    V.r = R0;
+  };
+  ops.residual = [&](double *rinf) -> gp_status {
+    gp_status e = resnorm64(ctx, rinf);
+    if (e) return e;
+    GP_HIP(hipMemcpyAsync(ctx->kr_r, V.r, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    return GP_OK;
+  };
+  int iters = 0, status = GP_OK;
+  double res = r0, rho = 0;
+  st = gcr_solve(ctx, ops, X0, ctx->kr_r, r0, thr, lim, max_cycles, &iters, &res, &rho, &status);
+  V.x = X0;
+  V.b = B0;
+  if (st) return st;
+  gp_status out = status;
+  if (out == GP_OK && res > thr) out = GP_ENOCONV;
+  ctx->last_cycles = iters;
+  if (stt) {
+    stt->cycles = iters;
+    stt->outer = 0;
+    stt->res0 = r0;
+    stt->res = res;
+    stt->rho = rho;
+    stt->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  }
+  return out;
+}
+
 gp_status mg_solve(Ctx *ctx, int precision, double tol, int max_cycles, gp_stats *stt) {
+  if (ctx->prm.krylov > 0) return gcr_mg_solve(ctx, precision, tol, max_cycles, stt);
   auto t0 = std::chrono::steady_clock::now();
   gp_status st = set_wall_dirichlet(ctx);
   if (st) return st;

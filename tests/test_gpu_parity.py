@@ -162,9 +162,10 @@ def check_cycles(o, s):
 
 @pytest.mark.parametrize("N", [512, 1024])
 def test_band_sectors_against_single_band_layouts(N):
-    """The boundary band relaxed over angular sectors (one workgroup each, redundant near the sector edges) against
-    the one-workgroup and device-wide layouts: three cycles of the rotating flower, same iterates to rounding (the
-    wall ghost rows sum their terms in another order in the device-wide layout)."""
+    """The optional extra band relaxation (bnd_sweeps = 1) relaxed over angular sectors (one workgroup each,
+    redundant near the sector edges) against the one-workgroup and device-wide layouts: three cycles of the
+    rotating flower, same iterates to rounding (the wall ghost rows sum their terms in another order in the
+    device-wide layout)."""
     from paper_1911_00994_amd import gpmg
     say(f"[band sectors] N={N}")
     h = 2.0 / N
@@ -172,7 +173,7 @@ def test_band_sectors_against_single_band_layouts(N):
     fu, fv = wl.fourier_forcing(N, 0)
     out = []
     for smin in (1500, 1 << 30):
-        s = gpu_solver(N, Re=400.0, band_sector_min=smin)
+        s = gpu_solver(N, Re=400.0, band_sector_min=smin, bnd_sweeps=1)
         s.set_levelset_analytic(FLOWER.kind, FLOWER.params, 0.0, mo[:5])
         s.set_alpha(h / 800.0)
         s.set_rhs(fu, fv, None)

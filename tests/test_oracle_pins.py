@@ -421,7 +421,9 @@ def test_manufactured_solution_second_order():
 
 
 def _rho(N, shape, **kw):
+    """convergence factor of the multigrid iteration on its own (eq. convfact), no Krylov acceleration"""
     h = 2.0 / N
+    kw.setdefault("krylov", 0)
     o = O.Oracle(N, **kw)
     phi = O.levelset_analytic(shape.kind, shape.padded(), [0] * 6, 0.0, N)
     assert o.set_levelset(phi) == O.OK

@@ -135,7 +135,9 @@ def test_internal_rows_reference_only_valued_points():
 # convergence factor (Sect. 5.3)
 # --------------------------------------------------------------------------------------------
 def _rho(N, shape, alpha_h2=0.64, **kw):
+    """convergence factor of the multigrid iteration on its own (eq. convfact), no Krylov acceleration"""
     h = 2.0 / N
+    kw.setdefault("krylov", 0)
     o = O.Oracle(N, **kw)
     phi = O.levelset_analytic(shape.kind, shape.padded(), [0] * 6, 0.0, N)
     assert o.set_levelset(phi) == O.OK
