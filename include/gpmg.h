@@ -88,6 +88,7 @@ typedef struct {
   int ghost_boxes; /* 1: coupled ghost boxes in every relaxation step (see above); 0: plain boxes only */
   int krylov;      /* m > 0: gp_solve and gp_adjoint_solve accelerate the cycle by GCR restarted after m directions
                       (see gp_solve); 0: the cycle on its own */
+  int ghost_box_levels; /* the coupled ghost boxes run on this many finest levels (default 1) */
 } gp_params;
 
 /* rigid motion: the body frame point of x at time t is R(-omega t) (x - X0 - U t); the boundary velocity at a

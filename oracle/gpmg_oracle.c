@@ -98,7 +98,7 @@ typedef struct {
   double Re, alpha;
   /* parameters */
   int nu1, nu2, gamma, lambda, coarsest_n, march_max, nbis, ext_radius, colour_perm_seed, bnd_sweeps, bnd_radius;
-  int ghost_boxes, lex_order, krylov;
+  int ghost_boxes, lex_order, krylov, ghost_box_levels;
   double dtau_dir, dtau_neu_over_h, eps_over_h, cg_min;
   /* geometry / boundary data */
   double *phi; /* (2N+1)^2 fine half lattice */
@@ -311,7 +311,7 @@ static void free_level(OLevel *L) {
 }
 
 /* iparams: nu1 nu2 gamma lambda coarsest_n march_max ext_radius colour_perm_seed bnd_sweeps bnd_radius
- *          ghost_boxes lex_order krylov
+ *          ghost_boxes lex_order krylov ghost_box_levels
  * dparams: dtau_dir dtau_neu_over_h eps_over_h cg_min (coarse levels) */
 void *or_create(int N, double Re, const int *ip, const double *dp) {
   if (N < 8 || (N & (N - 1))) return NULL;
@@ -331,6 +331,7 @@ void *or_create(int N, double Re, const int *ip, const double *dp) {
   S->ghost_boxes = ip[10];
   S->lex_order = ip[11];
   S->krylov = ip[12];
+  S->ghost_box_levels = ip[13];
 
   S->dtau_dir = dp[0];
   S->dtau_neu_over_h = dp[1];
@@ -1406,7 +1407,8 @@ static void coupled_boxes(OLevel *L) {
 
 /* one relaxation step (Alg. relax with nu = 1).
  * Default order: box sweep in the colour order (i + 2j) mod 5 = 0..4, then the coupled boxes colour by
- * colour (ghost_boxes), then lambda simultaneous ghost sweeps (eq. ghostrelax).
+ * colour (ghost_boxes, on the ghost_box_levels finest levels), then lambda simultaneous ghost sweeps
+ * (eq. ghostrelax).
  * Lexicographic order (the paper's GS-LEX): one pass over the cells row by row, each cell relaxed by its
  * coupled box if it has one (ghost_boxes) and by its plain box otherwise, each box seeing every earlier
  * update; then the ghost sweeps.
@@ -1420,7 +1422,7 @@ static void relax_step(OSolver *S, int l) {
     double *sol = (double *)xcalloc(L->xb_off[L->nxb] + 1, sizeof(double));
     for (int j = 0; j < N; j++)
       for (int i = 0; i < N; i++) {
-        int bx = S->ghost_boxes ? L->xb_of_cell[j * N + i] : -1;
+        int bx = (S->ghost_boxes && l < S->ghost_box_levels) ? L->xb_of_cell[j * N + i] : -1;
         if (bx < 0) {
           box_relax(L, i, j);
           continue;
@@ -1456,7 +1458,7 @@ static void relax_step(OSolver *S, int l) {
         free(list);
       }
     }
-    if (S->ghost_boxes) coupled_boxes(L);
+    if (S->ghost_boxes && l < S->ghost_box_levels) coupled_boxes(L);
   }
   ghost_sweeps(S, L);
   for (int q = 0; q < S->bnd_sweeps; q++) {

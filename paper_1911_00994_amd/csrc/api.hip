@@ -123,6 +123,7 @@ void gp_default_params(gp_params *p) {
   p->queue_ahead = 1;
   p->ghost_boxes = 1;
   p->krylov = 16;
+  p->ghost_box_levels = 1;
 }
 
 const char *gp_strerror(gp_status st) {
@@ -312,7 +313,8 @@ gp_status gp_setup_grid(gp_ctx **out, int N, double Re, const gp_params *prm, vo
   if (!pow2(N) || N < 16 || !pow2(P.coarsest_n) || P.coarsest_n < 4 || P.coarsest_n > N / 2 || P.nu1 < 0 || P.nu2 < 0 ||
       P.gamma < 1 || P.lambda_ghost < 0 || P.march_max < 1 || P.ext_radius < 1 || !(Re > 0) || P.mixed_inner_cycles < 1 ||
       P.bnd_sweeps < 0 || P.bnd_radius < 0 || P.band_split_min < 1 || P.band_sector_min < 1 ||
-      (P.ghost_boxes != 0 && P.ghost_boxes != 1) || P.krylov < 0 || P.krylov > 64)
+      (P.ghost_boxes != 0 && P.ghost_boxes != 1) || P.krylov < 0 || P.krylov > 64 ||
+      P.ghost_box_levels < 0)
     return GP_EINVAL;
   gp_ctx *ctx = new gp_ctx();
   ctx->N = N;
@@ -402,7 +404,7 @@ gp_status gp_setup_grid(gp_ctx **out, int N, double Re, const gp_params *prm, vo
       ALLOC(G.sec_gk, (size_t)G.sec_gcap);
     }
     ALLOC(G.f_loc, (size_t)G.fcap);
-    if (P.ghost_boxes) {  // coupled ghost boxes
+    if (P.ghost_boxes && l < P.ghost_box_levels) {  // coupled ghost boxes
       G.xb_bcap = G.gcap;
       G.xb_scap = 8 * G.gcap;
       G.xb_icap = 24L * G.gcap;

@@ -1701,7 +1701,7 @@ static gp_status build_level(Ctx *ctx, int l) {
     k_row_of<<<nblk(G.ne), TPB, 0, s>>>(G.e_pt, G.ne, G.e_rowof);
   }
   if (G.ng) k_row_of<<<nblk(G.ng), TPB, 0, s>>>(G.g_pt, G.ng, G.g_rowof);
-  if (ctx->prm.ghost_boxes) {
+  if (ctx->prm.ghost_boxes && l < ctx->prm.ghost_box_levels) {
     gp_status xs = xb_build(ctx, l, B);
     if (xs) return xs;
   } else {

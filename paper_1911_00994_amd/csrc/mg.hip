@@ -715,6 +715,37 @@ __global__ void __launch_bounds__(BAND_T) k_xi_faces(int WW, double h, T *x, con
 // also computed by the neighbouring sectors) are relaxed as in k_band_lds, and the values of the written points
 // it owns go to out (by region index); workgroups S and on take the wall ghost rows.  k_band_sec_fin then moves
 // out into x and updates xi.  Nothing reads x while this kernel writes it: the sectors write out only.
+// lambda Jacobi sweeps of all ghost rows (eq. (ghostrelax)) and then xi from the boundary faces of the internal
+// cells, in one workgroup (levels without the extra band relaxation)
+template <typename T>
+__global__ void __launch_bounds__(BAND_T) k_ghost_xi(const int *__restrict__ pt, const int *__restrict__ col,
+                                                     const double *__restrict__ w, const double *__restrict__ dtau, int ng,
+                                                     T *x, const T *__restrict__ b, double *tmp, int sweeps, int WW,
+                                                     double h, const int *__restrict__ f_code, int nf,
+                                                     const double *__restrict__ gp, int ngp, const int *__restrict__ mp) {
+  for (int it = 0; it < sweeps; it++) {
+    for (int r = threadIdx.x; r < ng; r += BAND_T) {
+      const int k = pt[r];
+      double s = 0;
+#pragma unroll
+      for (int q = 0; q < 9; q++) s += w[9 * r + q] * (double)x[col[9 * r + q]];
+      tmp[r] = (double)x[k] + dtau[r] * ((double)b[k] - s);
+    }
+    __syncthreads();
+    for (int r = threadIdx.x; r < ng; r += BAND_T) x[pt[r]] = (T)tmp[r];
+    __syncthreads();
+  }
+  const GpPre gpre = gp_start(gp, ngp);
+  double fs = 0;
+  for (int q = threadIdx.x; q < nf; q += BAND_T) {
+    const double v = (double)x[f_code[q] >> 1];
+    fs += (f_code[q] & 1) ? -v : v;
+  }
+  fs = band_block_sum(fs);
+  const double gsum = gp_total(gpre, gp, ngp);
+  if (threadIdx.x == 0) x[3 * WW] = (T)((fs / h - gsum) / *mp);
+}
+
 struct SecTabs {
   int poff[SEC_MAX + 1], boff[5 * SEC_MAX + 1], goff[SEC_MAX + 1], ooff[SEC_MAX + 1];
 };
@@ -1039,6 +1070,7 @@ __device__ __forceinline__ void xb_write(const XbTab &X, T *x, const double *rs,
   const double *iv = X.inv + X.ioff[bx] + (size_t)(s - o) * m;
   const double *r = rs + (o - rbase);
   double v = 0;
+#pragma unroll 8
   for (int c = 0; c < m; c++) v += iv[c] * r[c];
   const int k = X.idx[s];
   x[k] = (T)((double)x[k] + v);
@@ -2004,6 +2036,30 @@ static void relax(Ctx *ctx, int l) {
                                           G.nf, ctx->gs_ptr[l], ctx->gs_n[l], G.d_mp);
     return;
   }
+  if (!band && G.ng <= 2 * BAND_T) {
+    // the ghost sweeps and xi in one workgroup (a few rows per thread)
+    k_ghost_xi<T><<<1, BAND_T, 0, s>>>(G.g_pt, G.g_col, G.g_w, G.g_dtau, G.ng, V.x, V.b, ctx->gtmp,
+                                      ctx->prm.lambda_ghost, G.WW, G.h, G.f_code, G.nf, ctx->gs_ptr[l], ctx->gs_n[l],
+                                      G.d_mp);
+    return;
+  }
+  if (!band && G.ng) {
+    // many ghost rows: one device-wide launch per sweep (the sweeps between go through two row buffers), then xi
+    const int lam = ctx->prm.lambda_ghost;
+    if (G.colr_ok) {
+      double *buf[2] = {ctx->gtmp, ctx->gtmp2};
+      for (int it = 0; it < lam; it++) {
+        const double *prev = it == 0 ? nullptr : buf[(it - 1) & 1];
+        double *next = it == lam - 1 ? nullptr : buf[it & 1];
+        k_ghost_sweep2<T><<<nblk(G.ng), TPB, 0, s>>>(G.g_pt, G.g_col, G.g_colr, G.g_w, G.g_dtau, G.ng, V.x, V.b, prev,
+                                                   next);
+      }
+    } else {
+      relax_ghosts<T>(ctx, l);
+    }
+    k_xi_faces<T><<<1, BAND_T, 0, s>>>(G.WW, G.h, V.x, G.f_code, G.nf, ctx->gs_ptr[l], ctx->gs_n[l], G.d_mp);
+    return;
+  }
   if (band && G.ng <= 4 * GH_T) {
     // ghost sweeps and the band sweeps in one workgroup
     k_band_sweeps<T><<<1, BAND_T, 0, s>>>(G.N, G.W, BK, G.cls, V.x, V.b, G.band, G.d_band_off, G.g_pt, G.g_col,
@@ -2446,13 +2502,14 @@ static void drop_head(Ctx *ctx) {
 
 // ---------------------------------------------------------------------------------------------------------
 // generalized conjugate residual iteration (GCR) around the cycle.  Per iteration: z = B' r (the preconditioner),
-// q = M z, q and z orthogonalised against the stored images Q_i and directions Z_i (classical Gram-Schmidt, one
-// pass), Q_k = q / |q|, Z_k = z / |q|, x += (r . Q_k) Z_k, r -= (r . Q_k) Q_k.  The vectors are the finest level's
-// full unknown vectors (3 W^2 + 1 doubles, zero where no equation); every reduction runs over GR_B fixed blocks and
-// is summed in block order, so the iteration is deterministic.  The image is formed as -M z (the residual kernel
-// with a zero right-hand side), so the kernels below carry qn = -q.
+// q = M z, q and z orthogonalised against the stored images Q_i = M Z_i and directions Z_i (classical Gram-Schmidt,
+// one pass: q -= sum (Q_i . q / |Q_i|^2) Q_i, z likewise with Z_i), stored as Q_k, Z_k, then x += (r . Q_k / |Q_k|^2)
+// Z_k, r -= (r . Q_k / |Q_k|^2) Q_k.  The vectors are the finest level's full unknown vectors (3 W^2 + 1 doubles,
+// zero where no equation); every reduction runs over GR_B fixed blocks summed in block order, so the iteration is
+// deterministic.  The image is formed as -M z (the residual kernel with a zero right-hand side), so the stored
+// images are -M Z_i; the signs cancel in every coefficient.
 // ---------------------------------------------------------------------------------------------------------
-constexpr int GR_B = 256, GR_T = 256, KR_MAX = 64;
+constexpr int GR_B = 1024, GR_T = 256, KR_MAX = 64;
 
 // partials of the k dot products (Q_i . qn), i < k: part[i * GR_B + block]
 __global__ void __launch_bounds__(GR_T) k_gcr_dots(const double *__restrict__ Q, long n, int k, const double *__restrict__ qn,
@@ -2480,8 +2537,10 @@ __global__ void __launch_bounds__(GR_T) k_gcr_dots(const double *__restrict__ Q,
     }
   }
 }
-// sum the partials of cnt reductions in block order: out[i] = sum_b part[i * GR_B + b]
-__global__ void __launch_bounds__(GR_B) k_gcr_sum(const double *__restrict__ part, int cnt, double *out) {
+// out[i] = (sum_b part[i * GR_B + b]) / div[i] for i < cnt (div may be null: no division); with nu2 set, also
+// nu2[0] = out[0] (the squared norm of the new image, kept for the later projections)
+__global__ void __launch_bounds__(GR_B) k_gcr_sum(const double *__restrict__ part, int cnt, const double *__restrict__ div,
+                                                  double *out, double *nu2) {
   __shared__ double sm[GR_B];
   for (int i = 0; i < cnt; i++) {
     sm[threadIdx.x] = part[(size_t)i * GR_B + threadIdx.x];
@@ -2490,15 +2549,20 @@ __global__ void __launch_bounds__(GR_B) k_gcr_sum(const double *__restrict__ par
       if (threadIdx.x < o) sm[threadIdx.x] += sm[threadIdx.x + o];
       __syncthreads();
     }
-    if (threadIdx.x == 0) out[i] = sm[0];
+    if (threadIdx.x == 0) {
+      const double v = div ? sm[0] / div[i] : sm[0];
+      out[i] = v;
+      if (nu2 && i == 0) *nu2 = v;
+    }
     __syncthreads();
   }
 }
-// Gram-Schmidt step: qn' = qn - sum_i b_i Q_i, z' = z - sum_i b_i Z_i with b_i = Q_i . qn (beta), then the
-// partials of |qn'|^2 and r . qn' into part[0 * GR_B + block], part[1 * GR_B + block]
+// Gram-Schmidt step into the k-th slots: Qk = qn - sum_i b_i Q_i, Zk = z - sum_i b_i Z_i (b_i = Q_i . qn / |Q_i|^2),
+// and the partials of |Qk|^2 and r . Qk into part[block], part[GR_B + block]
 __global__ void __launch_bounds__(GR_T) k_gcr_orth(const double *__restrict__ Q, const double *__restrict__ Z, long n,
-                                                   int k, const double *__restrict__ beta, double *qn, double *z,
-                                                   const double *__restrict__ r, double *part) {
+                                                   int k, const double *__restrict__ beta, const double *__restrict__ qn,
+                                                   const double *__restrict__ z, const double *__restrict__ r, double *Qk,
+                                                   double *Zk, double *part) {
   __shared__ double sm[GR_T];
   double s2 = 0, sr = 0;
   for (long e = blockIdx.x * (long)GR_T + threadIdx.x; e < n; e += (long)GR_B * GR_T) {
@@ -2508,10 +2572,8 @@ __global__ void __launch_bounds__(GR_T) k_gcr_orth(const double *__restrict__ Q,
       q -= b * Q[(size_t)i * n + e];
       zz -= b * Z[(size_t)i * n + e];
     }
-    if (k) {
-      qn[e] = q;
-      z[e] = zz;
-    }
+    Qk[e] = q;
+    Zk[e] = zz;
     s2 += q * q;
     sr += r[e] * q;
   }
@@ -2526,22 +2588,17 @@ __global__ void __launch_bounds__(GR_T) k_gcr_orth(const double *__restrict__ Q,
     __syncthreads();
   }
 }
-// the step, with nu^2 = |qn|^2 and s = r . qn (sc[0], sc[1]) and g = s / nu^2: the direction's image is
-// M (z / nu) = -qn / nu, and its coefficient r . (-qn / nu) = -s / nu, so x -= g z and r -= g qn; the stored pair is
-// Q_k = qn / nu, Z_k = z / nu (so that M Z_k = -Q_k for every stored pair); block maxima of |r| into part[block]
-__global__ void __launch_bounds__(GR_T) k_gcr_step(long n, const double *__restrict__ sc, double *qn, double *z, double *x,
-                                                   double *r, double *Qk, double *Zk, double *part) {
+// the step with g = (r . Qk) / |Qk|^2 (sc[0] = |Qk|^2, sc[1] = r . Qk): the image of Zk is -Qk, so the coefficient
+// of the direction is -g: x -= g Zk, r -= g Qk; block maxima of |r| into part[block]
+__global__ void __launch_bounds__(GR_T) k_gcr_step(long n, const double *__restrict__ sc, const double *__restrict__ Qk,
+                                                   const double *__restrict__ Zk, double *x, double *r, double *part) {
   __shared__ double sm[GR_T];
-  const double nu2 = sc[0], s = sc[1];
-  const double inv = nu2 > 0 ? 1.0 / sqrt(nu2) : 0.0, g = nu2 > 0 ? s / nu2 : 0.0;
+  const double nu2 = sc[0], g = nu2 > 0 ? sc[1] / nu2 : 0.0;
   double m = 0;
   for (long e = blockIdx.x * (long)GR_T + threadIdx.x; e < n; e += (long)GR_B * GR_T) {
-    const double q = qn[e], zz = z[e];
-    x[e] -= g * zz;
-    const double rr = r[e] - g * q;
+    x[e] -= g * Zk[e];
+    const double rr = r[e] - g * Qk[e];
     r[e] = rr;
-    Qk[e] = q * inv;
-    Zk[e] = zz * inv;
     const double a = fabs(rr);
     m = (a > m || a != a) ? a : m;
   }
@@ -2575,6 +2632,21 @@ __global__ void __launch_bounds__(GR_B) k_gcr_max(const double *__restrict__ par
     if (hmax) __hip_atomic_store(hmax, b, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
   }
 }
+// preconditioner input: z = 0 except at the wall Dirichlet rows, where the cycle's x equals its right-hand side
+__global__ void k_pc_in(const uint8_t *__restrict__ cls, long n, const double *__restrict__ r, double *z) {
+  const long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  z[t] = (t < n - 1 && cls[t] == K_WALLD) ? r[t] : 0.0;
+}
+// preconditioner output (FP64, in place): the pressure unknowns shifted by -mean + (mean-row entry of r), which is
+// the cycle's mean projection followed by the mean-row column of B' (a constant pressure changes no other row)
+__global__ void k_pc_shift(const uint8_t *__restrict__ cls, int WW, const double *__restrict__ mean,
+                           const double *__restrict__ r, double *z) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= WW) return;
+  const uint8_t c = cls[2 * WW + t];
+  if (c == K_INT || c == K_GHOST || c == K_GHOSTX) z[2 * WW + t] += r[3 * WW] - *mean;
+}
 
 gp_status gcr_alloc(Ctx *ctx) {
   const int m = std::max(1, ctx->prm.krylov);
@@ -2596,7 +2668,7 @@ gp_status gcr_alloc(Ctx *ctx) {
   GP_HIP(hipMalloc((void **)&ctx->kr_Q, (size_t)m * n * sizeof(double)));
   GP_HIP(hipMalloc((void **)&ctx->kr_Z, (size_t)m * n * sizeof(double)));
   GP_HIP(hipMalloc((void **)&ctx->kr_zero, n * sizeof(double)));
-  GP_HIP(hipMalloc((void **)&ctx->kr_s, (KR_MAX + 8) * sizeof(double)));
+  GP_HIP(hipMalloc((void **)&ctx->kr_s, (2 * KR_MAX + 8) * sizeof(double)));
   GP_HIP(hipMalloc((void **)&ctx->kr_part, (size_t)(KR_MAX + 2) * GR_B * sizeof(double)));
   GP_HIP(hipMemsetAsync(ctx->kr_zero, 0, n * sizeof(double), ctx->stream));
   ctx->kr_m = m;
@@ -2610,24 +2682,23 @@ gp_status gcr_solve(Ctx *ctx, GcrOps &ops, double *x, double *r, double r0, doub
   hipStream_t s = ctx->stream;
   const long n = ctx->geo[0].n;
   const int m = ctx->kr_m;
-  double *beta = ctx->kr_s, *sc = ctx->kr_s + KR_MAX;
+  double *beta = ctx->kr_s, *sc = ctx->kr_s + KR_MAX, *nu2 = ctx->kr_s + KR_MAX + 8;
   double rn = r0, rp = r0;
   int c = 0, k = 0;
   *status = GP_OK;
   *rho = 0;
   while (rn > thr && c < max_it) {
     double *z = ctx->kr_z, *qn = ctx->v64[0].r;
+    double *Qk = ctx->kr_Q + (size_t)k * n, *Zk = ctx->kr_Z + (size_t)k * n;
     ops.precond(r, z);
     ops.apply_neg(z, qn);  // qn = -M z
-    // Gram-Schmidt against the stored images: with M Z_i = -Q_i and qn = -M z, q' = q - (q . M Z_i) M Z_i reads
-    // qn' = qn - (Q_i . qn) Q_i, and z' = z - (Q_i . qn) Z_i
     if (k) {
       k_gcr_dots<<<GR_B, GR_T, 0, s>>>(ctx->kr_Q, n, k, qn, ctx->kr_part);
-      k_gcr_sum<<<1, GR_B, 0, s>>>(ctx->kr_part, k, beta);
+      k_gcr_sum<<<1, GR_B, 0, s>>>(ctx->kr_part, k, nu2, beta, nullptr);
     }
-    k_gcr_orth<<<GR_B, GR_T, 0, s>>>(ctx->kr_Q, ctx->kr_Z, n, k, beta, qn, z, r, ctx->kr_part);
-    k_gcr_sum<<<1, GR_B, 0, s>>>(ctx->kr_part, 2, sc);
-    k_gcr_step<<<GR_B, GR_T, 0, s>>>(n, sc, qn, z, x, r, ctx->kr_Q + (size_t)k * n, ctx->kr_Z + (size_t)k * n, ctx->kr_part);
+    k_gcr_orth<<<GR_B, GR_T, 0, s>>>(ctx->kr_Q, ctx->kr_Z, n, k, beta, qn, z, r, Qk, Zk, ctx->kr_part);
+    k_gcr_sum<<<1, GR_B, 0, s>>>(ctx->kr_part, 2, nullptr, sc, nu2 + k);
+    k_gcr_step<<<GR_B, GR_T, 0, s>>>(n, sc, Qk, Zk, x, r, ctx->kr_part);
     __atomic_store_n(ctx->h_rmax, NORM_PENDING, __ATOMIC_RELEASE);
     k_gcr_max<<<1, GR_B, 0, s>>>(ctx->kr_part, (unsigned long long *)(ctx->d_scal + 1), ctx->h_rmax);
     GP_HIP(hipGetLastError());
@@ -2691,18 +2762,18 @@ static gp_status gcr_mg_solve(Ctx *ctx, int precision, double tol, int max_cycle
       double *Y0 = V.y;
       V.x = z;
       V.b = const_cast<double *>(r);
-      k_fill<double><<<nblk(n), TPB, 0, s>>>(z, n, 0.0);
-      k_set_walld<double><<<nblk(3L * G.WW), TPB, 0, s>>>(3 * G.WW, G.cls, z, r);
+      k_pc_in<<<nblk(n), TPB, 0, s>>>(G.cls, n, r, z);
       gsum<double>(ctx, 0);
       cycle<double>(ctx, 0);
-      mean_project<double>(ctx);
       if (V.x != z) {  // an odd number of finest sweeps leaves the result in the second buffer
         (void)hipMemcpyAsync(z, V.x, n * sizeof(double), hipMemcpyDeviceToDevice, s);
       }
       V.x = X0;
       V.b = B0;
       V.y = Y0;
-      k_pc_out<double><<<nblk(n), TPB, 0, s>>>(G.cls, G.WW, z, r, z);
+      // the mean projection and the mean-row column in one pass
+      k_pmean<double><<<rd_blocks(G.WW), RD_T, 0, s>>>(G.W, G.cls, z, ctx->d_red, ctx->d_ticket, G.d_mp, ctx->d_scal);
+      k_pc_shift<<<nblk(G.WW), TPB, 0, s>>>(G.cls, G.WW, ctx->d_scal, r, z);
     } else {
       Vec<float> &E = ctx->v32[0];
       k_cast_rhs<<<nblk(n), TPB, 0, s>>>(r, E.b, n);

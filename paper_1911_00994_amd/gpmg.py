@@ -38,7 +38,8 @@ class GpParams(ctypes.Structure):
                 ("mixed_inner_cycles", ctypes.c_int), ("bnd_sweeps", ctypes.c_int), ("bnd_radius", ctypes.c_int),
                 ("fuse_small_levels", ctypes.c_int), ("band_split_min", ctypes.c_int),
                 ("graph_iterations", ctypes.c_int), ("band_sector_min", ctypes.c_int),
-                ("queue_ahead", ctypes.c_int), ("ghost_boxes", ctypes.c_int), ("krylov", ctypes.c_int)]
+                ("queue_ahead", ctypes.c_int), ("ghost_boxes", ctypes.c_int), ("krylov", ctypes.c_int),
+                ("ghost_box_levels", ctypes.c_int)]
 
 
 class GpRigid(ctypes.Structure):

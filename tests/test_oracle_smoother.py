@@ -157,16 +157,26 @@ def _rho(N, shape, alpha_h2=0.64, **kw):
 
 @pytest.mark.parametrize("shape,bound", [(CIRCLE, 0.2), (ELLIPSE, 0.3), (PETALS, 0.25)])
 def test_convergence_factor_bounded_for_each_body(shape, bound):
-    """V(2,2) with the paper's relaxation (box sweep, coupled ghost boxes, fictitious-time ghost sweeps):
-    the factor stays below the bound and does not grow with N."""
-    rhos = [_rho(N, shape) for N in (64, 128, 256)]
+    """The cycle on its own, V(2,2) with the paper's relaxation (box sweep, fictitious-time ghost sweeps) and
+    coupled ghost boxes on every level: the factor stays below the bound and does not grow with N."""
+    rhos = [_rho(N, shape, ghost_box_levels=99) for N in (64, 128, 256)]
     assert max(rhos) < bound and max(rhos) - min(rhos) < 0.12, rhos
+
+
+@pytest.mark.parametrize("shape", [CIRCLE, ELLIPSE, PETALS, wl.paper_flower()])
+def test_krylov_iteration_counts(shape):
+    """The default solver (GCR around V(2,2) with coupled ghost boxes on the finest level) reaches a max-norm
+    residual of 1e-10 max(1, |b|) on the manufactured problem within 20 cycles at N = 128 and 256."""
+    for N in (128, 256):
+        o, _, _ = make_linear_problem(N, shape, 0.64 * (2.0 / N) ** 2)
+        st, s = o.solve(1e-10, 40)
+        assert st == O.OK and s["cycles"] <= 20, (N, st, s)
 
 
 def test_paper_cycle_convergence_factor():
     """Sect. 5.3: W cycle, two pre- and one post-relaxation, lexicographic box order; the paper's
     reference factor is 0.119 (a local Fourier analysis value).  Measured on the paper's petal body."""
-    rhos = [_rho(N, wl.paper_flower(), gamma=2, nu2=1, lex_order=1) for N in (128, 256)]
+    rhos = [_rho(N, wl.paper_flower(), gamma=2, nu2=1, lex_order=1, ghost_box_levels=99) for N in (128, 256)]
     assert max(rhos) < 0.2 and abs(rhos[0] - rhos[1]) < 0.05, rhos
 
 
