@@ -24,7 +24,7 @@ OK, E_INVAL, E_NOMEM, E_HIP, E_GEOM, E_NOCONV, E_DIVERGED = 0, -1, -2, -3, -4, -
 
 
 def build_oracle(force: bool = False) -> str:
-    """Compile the oracle with plain gcc (no GPU code involved)."""
+    """Compile the oracle with plain gcc (no GPU code involved), portable flags, one thread."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + ".tmp"
         subprocess.check_call(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"])
@@ -32,13 +32,29 @@ def build_oracle(force: bool = False) -> str:
     return _LIB
 
 
+def build_native(path: str, openmp: bool) -> str:
+    """Compile the oracle for the CPU it runs on (-O3 -march=native, with or without OpenMP over the boxes of a
+    colour, the ghost rows and the rows of the residual and transfers) into path: the CPU-baseline timing builds
+    it on the host it times, so the machine code matches that host.  Results equal the portable build's to
+    rounding (FMA contraction may differ)."""
+    tmp = path + ".tmp"
+    flags = ["-O3", "-march=native", "-std=c99", "-fPIC", "-shared"] + (["-fopenmp"] if openmp else [])
+    subprocess.check_call(["gcc"] + flags + ["-o", tmp, _SRC, "-lm"])
+    os.replace(tmp, path)
+    return path
+
+
 _lib = None
 
 
-def lib():
+def lib(path: str = None):
+    """the portable library (default) or, with path, a library built by build_native (loaded as the module's
+    library from then on)"""
     global _lib
+    if path is not None:
+        _lib = None
     if _lib is None:
-        _lib = ctypes.CDLL(build_oracle())
+        _lib = ctypes.CDLL(path or build_oracle())
         L = _lib
         d, i, vp = ctypes.c_double, ctypes.c_int, ctypes.c_void_p
         L.or_create.restype = vp
@@ -65,6 +81,7 @@ def lib():
             ("or_ext_fail_count", [vp, i]),
             ("or_test_restrict", [vp, i, vp, vp]),
             ("or_test_prolong", [vp, i, vp, vp]),
+            ("or_threads", []),
             ("or_coupled_box_count", [vp, i, vp, vp]),
             ("or_get_coupled_boxes", [vp, i, vp, vp, vp, vp, vp, vp]),
         ]:

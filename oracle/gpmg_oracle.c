@@ -392,6 +392,14 @@ void or_destroy(void *h) {
 
 int or_num_levels(void *h) { return ((OSolver *)h)->L; }
 
+/* threads the library runs its parallel loops on (1 unless built with OpenMP) */
+#ifdef _OPENMP
+#include <omp.h>
+int or_threads(void) { return omp_get_max_threads(); }
+#else
+int or_threads(void) { return 1; }
+#endif
+
 /* the coupled-box table of a level: counts, then (cell, slot offsets, number of box unknowns, unknown
  * indices, write flags, colour offsets) in the order the relaxation visits the boxes */
 int or_coupled_box_count(void *h, int l, int *nbox, int *nslot) {
@@ -1345,6 +1353,7 @@ static int in_band(const OLevel *L, int i, int j, int R) {
 static void ghost_sweeps(OSolver *S, OLevel *L) {
   double *nv = (double *)calloc(L->ng ? L->ng : 1, sizeof(double));
   for (int it = 0; it < S->lambda; it++) {
+#pragma omp parallel for schedule(static)
     for (int r = 0; r < L->ng; r++) {
       int k = L->g_pt[r];
       nv[r] = L->x[k] + L->g_dtau[r] * (L->b[k] - row_dot(L, k, L->x));
@@ -1392,6 +1401,7 @@ static void coupled_boxes(OLevel *L) {
     int lo = L->xb_coff[c], hi = L->xb_coff[c + 1];
     if (hi == lo) continue;
     memcpy(xs, L->x, sizeof(double) * L->n);
+#pragma omp parallel for schedule(dynamic, 16)
     for (int bx = lo; bx < hi; bx++) ok[bx] = coupled_solve(L, bx, xs, &sol[L->xb_off[bx]]);
     for (int bx = lo; bx < hi; bx++) {
       if (!ok[bx]) continue;
@@ -1434,6 +1444,9 @@ static void relax_step(OSolver *S, int l) {
   } else {
     for (int col = 0; col < 5; col++) {
       if (S->colour_perm_seed == 0) {
+        /* the boxes of one colour are independent (none reads what another writes), so the rows of cells may
+         * run on several threads (built with OpenMP only for the CPU timing) with identical results */
+#pragma omp parallel for schedule(static)
         for (int j = 0; j < N; j++)
           for (int i = 0; i < N; i++)
             if ((i + 2 * j) % 5 == col) box_relax(L, i, j);
@@ -1484,6 +1497,7 @@ int or_relax(void *h, int l, int steps) {
 
 /* residual r = b - M x; rows without an equation get 0 */
 static void residual(OLevel *L) {
+#pragma omp parallel for schedule(static)
   for (int k = 0; k < L->n; k++) {
     unsigned char c = (k < 3 * L->W * L->W) ? L->cls[k] : C_INT;
     if (c == C_INT || ghost_row_class(c) || c == C_WALLD)
@@ -1509,6 +1523,7 @@ static void restrict_res(OSolver *S, int l) {
   int WWc = C->W * C->W;
   for (int k = 0; k < C->n; k++) C->b[k] = 0;
   for (int g = 0; g < 3; g++)
+#pragma omp parallel for schedule(static)
     for (int jc = -1; jc <= C->N; jc++)
       for (int ic = -1; ic <= C->N; ic++) {
         int kc = gidx(C, g, ic, jc);
@@ -1578,6 +1593,7 @@ static void prolong_correct(OSolver *S, int l) {
   OLevel *F = &S->lev[l], *C = &S->lev[l + 1];
   int Nc = C->N;
   for (int g = 0; g < 3; g++)
+#pragma omp parallel for schedule(static)
     for (int j = -1; j <= F->N; j++)
       for (int i = -1; i <= F->N; i++) {
         int kf = gidx(F, g, i, j);
@@ -1718,6 +1734,7 @@ int or_cycle(void *h, double *res_inf) {
 
 /* y = M x over the rows that carry an equation (internal, ghost, wall and mean rows); 0 elsewhere */
 static void matvec(OLevel *L, const double *x, double *y) {
+#pragma omp parallel for schedule(static)
   for (int k = 0; k < L->n; k++) {
     unsigned char c = (k < 3 * L->W * L->W) ? L->cls[k] : C_INT;
     y[k] = (c == C_INT || ghost_row_class(c) || c == C_WALLD) ? row_dot(L, k, x) : 0.0;
@@ -1771,7 +1788,8 @@ int or_solve(void *h, double tol, int max_cycles, double *stats) {
   double r = r0, rprev = r0;
   int c = 0;
   double rho = 0;
-  int status = OK;
+  int status = r0 == r0 ? OK : E_DIVERGED; /* NaN in the data */
+  if (status != OK) max_cycles = 0;
   S->res_hist[0] = r0;
   if (S->krylov <= 0) {
     while (r > thr && c < max_cycles) {

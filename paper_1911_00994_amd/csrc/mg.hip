@@ -2753,6 +2753,7 @@ static gp_status gcr_mg_solve(Ctx *ctx, int precision, double tol, int max_cycle
   double *X0 = V.x, *B0 = V.b;
   double r0, bn;
   if ((st = resnorm64(ctx, &r0))) return st;  // V.r = b - M x
+  if (!(r0 == r0)) return GP_EDIVERGED;        // NaN or Inf in the data
   GP_HIP(hipMemcpyAsync(ctx->kr_r, V.r, n * sizeof(double), hipMemcpyDeviceToDevice, s));
   if ((st = bnorm64(ctx, &bn))) return st;
   const double thr = tol * (bn > 1 ? bn : 1), lim = 1e6 * (r0 > 1 ? r0 : 1);
@@ -2829,6 +2830,7 @@ gp_status mg_solve(Ctx *ctx, int precision, double tol, int max_cycles, gp_stats
   if ((st = ensure_xb(ctx))) return st;
   double r0, bn;
   if ((st = resnorm64(ctx, &r0))) return st;
+  if (!(r0 == r0)) return GP_EDIVERGED;  // NaN or Inf in the data
   if ((st = bnorm64(ctx, &bn))) return st;
   double thr = tol * (bn > 1 ? bn : 1);
   double r = r0, rho = 0;

@@ -43,3 +43,23 @@ def make_linear_problem(N, shape, alpha, m=None, t=0.3, motion=None, **kw):
 def active_mask(cls):
     """Points carrying an equation of the system (internal, ghost, wall)."""
     return (cls == O.C_INT) | (cls == O.C_GHOST) | (cls == O.C_GHOSTX) | (cls == O.C_WALLD) | (cls == O.C_WALLG)
+
+
+_NATIVE = {}
+
+
+class native_oracle:
+    """Context manager: the oracle library built for this host with OpenMP (oracle.build_native) in place of the
+    portable single-thread build, for the parity runs at full size (same arithmetic, several threads)."""
+
+    def __enter__(self):
+        import tempfile
+        if "path" not in _NATIVE:
+            d = tempfile.mkdtemp(prefix="oracle_omp_")
+            _NATIVE["path"] = O.build_native(d + "/liboracle_omp.so", openmp=True)
+        O.lib(_NATIVE["path"])
+        return O
+
+    def __exit__(self, *exc):
+        O.lib(O.build_oracle())
+        return False

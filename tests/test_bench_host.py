@@ -55,3 +55,24 @@ def test_multi_gpu_request_is_refused():
                        text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stderr
+
+
+def test_native_oracle_builds_with_openmp_and_matches_portable_build(tmp_path):
+    """the CPU-baseline library (-O3 -march=native -fopenmp) runs the same iteration: a cycle of the petal body
+    at N = 64 agrees with the portable single-thread build to rounding"""
+    import oracle as O
+    from paper_1911_00994_amd import workloads as wl
+    from tests.common import make_linear_problem
+    shape = wl.Shape(wl.PETALS, (0.35, 0.07, 0.0, 5.0))
+    N = 64
+    out = []
+    for path in (None, O.build_native(str(tmp_path / "libnative.so"), openmp=True)):
+        O.lib(path or O.build_oracle())
+        o, _, _ = make_linear_problem(N, shape, 0.64 * (2.0 / N) ** 2)
+        o.cycle()
+        out.append(np.concatenate([a.ravel() for a in o.get_x()[:3]]))
+        threads = O.lib().or_threads()
+        del o
+    O.lib(O.build_oracle())
+    assert threads >= 1
+    assert np.abs(out[0] - out[1]).max() < 1e-9 * max(1.0, np.abs(out[0]).max())

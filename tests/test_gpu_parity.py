@@ -1,7 +1,8 @@
 """Parity of the HIP path with the CPU oracle (element by element, same seeded inputs).
 
-FP64 bar: geometry tables within 1e-12 (classes bit-exact), one relaxation step / one cycle within 1e-11
-relative, converged solves within 1e-10 relative.  Every case prints its name before touching the GPU.
+FP64 bar: geometry tables within 1e-12 (classes and coupled-box tables bit-exact), one relaxation step / one
+cycle within 1e-11 relative, converged solves and Crank-Nicolson steps within 1e-10 relative (the measured
+difference is printed).  Every case prints its name before touching the GPU.
 """
 import sys
 
@@ -29,9 +30,14 @@ def gpu_solver(N, Re=100.0, **kw):
     return gpmg.Solver(N, Re=Re, **kw)
 
 
+# solver parameters that exist on both sides under the same name (the oracle's lambda is lam)
+SHARED = ("nu1", "nu2", "gamma", "ghost_boxes", "krylov", "ghost_box_levels", "bnd_sweeps")
+
+
 def pair(N, shape, alpha, motion=None, t=0.0, m=None, Re=100.0, zero_x=True, **gpu_params):
-    """oracle and GPU solver on the same level set, alpha, rhs and boundary data"""
-    o = O.Oracle(N, Re=Re)
+    """oracle and GPU solver on the same level set, alpha, rhs and boundary data (shared solver parameters go
+    to both sides)"""
+    o = O.Oracle(N, Re=Re, **{k: v for k, v in gpu_params.items() if k in SHARED})
     mo = motion.as_array() if motion is not None else np.zeros(6)
     phi = O.levelset_analytic(shape.kind, shape.padded(), mo, t, N)
     assert o.set_levelset(phi, t, mo) == O.OK
@@ -149,15 +155,18 @@ def test_cycle_parity_layouts(fuse, split):
     check_cycles(o, s)
 
 
-def check_cycles(o, s):
+def check_cycles(o, s, cycles=3):
     cls = o.classes().ravel()
     act = np.concatenate([active_mask(cls), [True]])
-    for c in range(3):
+    for c in range(cycles):
         _, ro = o.cycle()
         rg = s.cycle()
         a, b = flat(o.get_x()), flat(s.get_x())
-        assert rel_diff(a, b, act) < 1e-11, (c, rel_diff(a, b, act))
-        assert abs(ro - rg) <= 1e-9 * max(1.0, ro), (c, ro, rg)
+        d = rel_diff(a, b, act)
+        say(f"  cycle {c}: residual oracle {ro:.6e} gpu {rg:.6e}, iterate rel diff {d:.2e}")
+        assert d < 1e-11, (c, d)
+        # the residual norms relative to each other (they are summed in another order on each side)
+        assert abs(ro - rg) <= 1e-8 * ro, (c, ro, rg)
 
 
 @pytest.mark.parametrize("N", [512, 1024])
@@ -191,17 +200,41 @@ def test_band_sectors_against_single_band_layouts(N):
     assert np.all(np.isfinite(out[0][0]))
 
 
+@pytest.mark.parametrize("N,gamma,nu2", [(128, 2, 1), (256, 2, 1)])
+def test_w_cycle_parity(N, gamma, nu2):
+    """The paper's cycle shape, W(2,1) (Sect. 4.3, Sect. 5.3), colour order, against the oracle"""
+    say(f"[W cycle] N={N} gamma={gamma} nu2={nu2}")
+    o, s = pair(N, wl.paper_flower(), 0.64 * (2.0 / N) ** 2, gamma=gamma, nu2=nu2)
+    check_cycles(o, s)
+
+
+@pytest.mark.parametrize("N,shape,motion", [(256, FLOWER, wl.Motion(omega=1.0)), (1024, FLOWER, wl.Motion(omega=1.0)),
+                                            (128, wl.paper_ellipse(), None)])
+def test_coupled_box_table_parity(N, shape, motion):
+    """The coupled-box table (cells in visiting order, unknowns, write flags, colour offsets): bit-exact"""
+    say(f"[coupled boxes] N={N} shape={shape}")
+    # every level builds its table (the default relaxes the coupled boxes on the finest level only)
+    o, s = pair(N, shape, 0.64 * (2.0 / N) ** 2, motion=motion, t=0.3, ghost_box_levels=99)
+    for lv in range(o.nlev):
+        a, b = o.coupled_boxes(lv), s.coupled_boxes(lv)
+        for key in ("cell", "off", "idx", "wr", "coff"):
+            assert np.array_equal(a[key], b[key]), (lv, key)
+    say(f"  level 0: {len(a['cell'])} boxes, {len(a['idx'])} slots")
+
+
 @pytest.mark.parametrize("N,shape", [(64, CIRCLE), (128, FLOWER)])
 def test_converged_solve_parity(N, shape):
     say(f"[solve] N={N} shape={shape}")
     o, s = pair(N, shape, 0.64 * (2.0 / N) ** 2, m=wl.PaperMMS(), t=0.4)
-    st_o, so = o.solve(1e-12, 200)
-    st_g, sg = s.solve(1e-12, 200)
+    st_o, so = o.solve(1e-11, 200)
+    st_g, sg = s.solve(1e-11, 200)
     assert st_o == O.OK and st_g == 0
-    assert abs(so["cycles"] - sg["cycles"]) <= 1
     cls = o.classes().ravel()
     act = np.concatenate([active_mask(cls), [True]])
-    assert rel_diff(flat(o.get_x()), flat(s.get_x()), act) < 1e-10
+    d = rel_diff(flat(o.get_x()), flat(s.get_x()), act)
+    say(f"  cycles oracle {so['cycles']} gpu {sg['cycles']}, rel diff {d:.2e}")
+    assert abs(so["cycles"] - sg["cycles"]) <= 1
+    assert d < 1e-10
 
 
 @pytest.mark.parametrize("mixed,split", [(0, 3000), (0, 1), (1, 3000)])
@@ -306,7 +339,9 @@ def test_cn_step_parity(N, shape, motion, m, steps):
     cls = o.classes().ravel()
     act = np.concatenate([active_mask(cls), [True]])
     for k, (a, b) in enumerate(out):
-        assert rel_diff(a, b, act) < 1e-9, (k, rel_diff(a, b, act))
+        d = rel_diff(a, b, act)
+        say(f"  step {k}: rel diff {d:.2e}")
+        assert d < 1e-10, (k, d)
 
 
 def test_full_size_cycle_parity():
@@ -360,7 +395,29 @@ def test_mixed_precision_solve_against_oracle(N, shape):
     s.set_x(z, z, z, 0.0)
     stm, im = s.solve(1e-8, 200, precision=gpmg.GP_MIXED)
     em = rel_diff(xo, flat(s.get_x()), act)
-    say(f"  fp64: {i64['cycles']} cycles err {e64:.2e}; mixed: {im['cycles']} cycles ({im['outer']} outer) err {em:.2e}")
+    say(f"  fp64: {i64['cycles']} cycles err {e64:.2e}; mixed: {im['cycles']} cycles err {em:.2e}")
     assert st64 == 0 and stm == 0
-    assert im["res"] <= 1e-8 * max(1.0, 1.0) * 1e3  # residual is relative to max(1, ||b||)
+    bn = np.abs(o.get_b()).max()
+    assert im["res"] <= 1e-8 * max(1.0, bn), im  # the FP64 residual meets the tolerance
     assert em <= 10 * e64 + 1e-10
+
+
+def test_error_paths_on_the_device():
+    """GP_EINVAL for N not a power of two, GP_EGEOM for a body that covers the box walls, GP_EDIVERGED for a NaN
+    in the right-hand side (forced from the host; every kernel still runs to completion)"""
+    from paper_1911_00994_amd import gpmg
+    say("[error paths] N=48, wall body, NaN forcing")
+    with pytest.raises(gpmg.GpmgError) as ei:
+        gpmg.Solver(48)
+    assert ei.value.status == gpmg.GP_EINVAL
+    s = gpmg.Solver(32)
+    st = s.set_levelset_analytic(wl.CIRCLE_DIST, (1.5,), 0.0, None, check=False)
+    assert st == gpmg.GP_EGEOM
+    assert s.set_levelset_analytic(wl.CIRCLE_DIST, (0.3,), 0.0, None) == 0
+    s.set_alpha(0.64 * (2.0 / 32) ** 2)
+    W = 34
+    fu = np.zeros((W, W))
+    fu[10, 10] = np.nan
+    s.set_rhs(fu, np.zeros((W, W)), None)
+    st, _ = s.solve(1e-10, 20, check=False)
+    assert st == gpmg.GP_EDIVERGED
