@@ -51,7 +51,8 @@ enum {
   GP_EGEOM = -4,     /* geometry rejected: body touches the box walls, a finest-level ghost has no usable
                         row, or an internal cell has no internal face */
   GP_ENOCONV = -5,   /* max_cycles reached before the tolerance; the iterate is kept, stats are filled */
-  GP_EDIVERGED = -6  /* NaN/Inf or residual growth beyond 1e6 times the initial one */
+  GP_EDIVERGED = -6, /* NaN/Inf or residual growth beyond 1e6 times the initial one */
+  GP_ESCRATCH = -7   /* gp_solve_noalloc: the problem's workspace exceeds the library's static scratch array */
 };
 
 enum { GP_FP64 = 0, GP_MIXED = 1 };
@@ -166,6 +167,17 @@ gp_status gp_get_x(gp_ctx *ctx, double *u, double *v, double *p, double *xi, int
 gp_status gp_mg_vcycle(gp_ctx *ctx, int precision, double *res_inf);
 /* cycles until ||r||_inf <= tol * max(1, ||b||_inf) or max_cycles */
 gp_status gp_solve(gp_ctx *ctx, int precision, double tol, int max_cycles, gp_stats *st);
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc): gp_solve in FP64 (same iteration, same results) without any device allocation.  gp_solve
+ * allocates the GCR workspace ((3 + 2 krylov) vectors of 3 W^2 + 1 doubles) at its first call; this entry point
+ * takes it from a static device array of 64 MiB that every GPU the library runs on holds until the process ends
+ * (its address is looked up once per device at gp_setup_grid).  Limit: the workspace must fit 64 MiB, which holds
+ * N <= 256 with the default krylov = 16 (N = 512 with krylov <= 3); larger problems return GP_ESCRATCH (the text
+ * via gp_last_hip_error) without touching the context.  krylov = 0 needs no workspace (any N).  The context itself
+ * (geometry, hierarchy) is allocated by gp_setup_grid and the geometry calls, so call this after them.  Calls on
+ * one GPU share the array: calls that overlap in time on the same GPU (from several threads or streams) race and
+ * must be serialised by the caller.  Graph replay (graph_iterations) is not used by this call. */
+gp_status gp_solve_noalloc(gp_ctx *ctx, double tol, int max_cycles, gp_stats *st);
 /* residual of every row (host array of 3*W*W + 1 doubles, the last entry is the mean-pressure row; may be
  * NULL) and its max norm */
 gp_status gp_residual(gp_ctx *ctx, double *r, double *res_inf);

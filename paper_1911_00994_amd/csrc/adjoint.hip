@@ -769,8 +769,8 @@ gp_status adjoint_solve_dev(Ctx *ctx, double tol, int max_cycles, gp_stats *stt)
     // GCR with the transposed cycle as the preconditioner (the transpose of the forward solve's iteration)
     if ((st = gcr_alloc(ctx))) return st;
     const long n = G.n;
-    mt_apply(ctx, 0, ctx->a_lam, ctx->a_g, -1.0, ctx->kr_r);
-    if ((st = absmax_dev(ctx, ctx->kr_r, n, &r0))) return st;
+    mt_apply(ctx, 0, ctx->a_lam, ctx->a_g, -1.0, ctx->kr.r);
+    if ((st = absmax_dev(ctx, ctx->kr.r, n, &r0))) return st;
     GcrOps ops;
     ops.precond = [&](const double *r, double *z) {
       k_copy<<<nblk(n), TPB, 0, s>>>(A.x, r, n);
@@ -779,16 +779,16 @@ gp_status adjoint_solve_dev(Ctx *ctx, double tol, int max_cycles, gp_stats *stt)
       k_mask_unknowns<<<nblk(3L * G.WW), TPB, 0, s>>>(3 * G.WW, G.cls, z);
     };
     ops.apply_neg = [&](const double *z, double *q) {
-      mt_apply(ctx, 0, z, ctx->kr_zero, -1.0, q);
+      mt_apply(ctx, 0, z, ctx->kr.zero, -1.0, q);
       k_mask_unknowns<<<nblk(3L * G.WW), TPB, 0, s>>>(3 * G.WW, G.cls, q);
     };
     ops.residual = [&](double *rinf) -> gp_status {
-      mt_apply(ctx, 0, ctx->a_lam, ctx->a_g, -1.0, ctx->kr_r);
-      return absmax_dev(ctx, ctx->kr_r, n, rinf);
+      mt_apply(ctx, 0, ctx->a_lam, ctx->a_g, -1.0, ctx->kr.r);
+      return absmax_dev(ctx, ctx->kr.r, n, rinf);
     };
     int status = GP_OK;
     const double lim = 1e6 * (r0 > 1 ? r0 : 1);
-    if ((st = gcr_solve(ctx, ops, ctx->a_lam, ctx->kr_r, r0, thr, lim, max_cycles, &c, &r, &rho, &status))) return st;
+    if ((st = gcr_solve(ctx, ctx->kr, ops, ctx->a_lam, ctx->kr.r, r0, thr, lim, max_cycles, &c, &r, &rho, &status))) return st;
     out = status;
   }
   for (; ctx->prm.krylov == 0;) {

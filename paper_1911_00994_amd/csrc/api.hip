@@ -135,6 +135,7 @@ const char *gp_strerror(gp_status st) {
     case GP_EGEOM: return "geometry rejected";
     case GP_ENOCONV: return "no convergence within max_cycles";
     case GP_EDIVERGED: return "iteration diverged";
+    case GP_ESCRATCH: return "problem too large for the static scratch of gp_solve_noalloc";
     default: return "unknown status";
   }
 }
@@ -291,13 +292,7 @@ void gp_destroy(gp_ctx *ctx) {
   dfree(ctx->cku);
   dfree(ctx->ckv);
   dfree(ctx->fwork);
-  dfree(ctx->kr_r);
-  dfree(ctx->kr_z);
-  dfree(ctx->kr_Q);
-  dfree(ctx->kr_Z);
-  dfree(ctx->kr_zero);
-  dfree(ctx->kr_s);
-  dfree(ctx->kr_part);
+  for (double *p : {ctx->kr.r, ctx->kr.z, ctx->kr.Q, ctx->kr.Z, ctx->kr.zero, ctx->kr.s, ctx->kr.part}) dfree(p);
   if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
   delete ctx;
 }
@@ -465,6 +460,7 @@ gp_status gp_setup_grid(gp_ctx **out, int N, double Re, const gp_params *prm, vo
   ALLOC(ctx->d_flags, 16);
   // geometry build resources: level 0 the context's own, the others a stream, event and scratch each
   GP_HIP(hipGetDevice(&ctx->device));
+  (void)scratch_init(ctx);  // address of the static scratch on this device (gp_solve_noalloc reports a failure)
   for (int l = 0; l < L; l++) {
     BuildRes &B = ctx->bres[l];
     GP_HIP(hipEventCreateWithFlags(&B.ev, hipEventDisableTiming));
@@ -707,6 +703,13 @@ gp_status gp_solve(gp_ctx *ctx, int precision, double tol, int max_cycles, gp_st
   gp_status st = ensure_coarse(ctx);
   if (st) return st;
   return mg_solve(ctx, precision, tol, max_cycles, s);
+}
+
+gp_status gp_solve_noalloc(gp_ctx *ctx, double tol, int max_cycles, gp_stats *s) {
+  if (!ctx || !(tol > 0) || max_cycles < 0) return GP_EINVAL;
+  gp_status st = ensure_coarse(ctx);
+  if (st) return st;
+  return mg_solve_noalloc(ctx, tol, max_cycles, s);
 }
 
 gp_status gp_residual(gp_ctx *ctx, double *r, double *res_inf) {

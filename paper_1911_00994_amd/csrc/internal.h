@@ -148,6 +148,15 @@ struct BuildRes {
   unsigned seq = 0;           // the last one issued
 };
 
+// GCR workspace (gcr_solve): the residual, the preconditioned direction, m stored directions Z and their images
+// Q, a zero vector (n doubles each), device scalars (the Gram-Schmidt coefficients, then |q|^2, (r, q) and the
+// step) and the block partials of the reductions.  Either the context's own buffers (gcr_alloc) or slices of the
+// library's static scratch array (gp_solve_noalloc).
+struct GcrWs {
+  int m = 0;
+  double *r = nullptr, *z = nullptr, *Q = nullptr, *Z = nullptr, *zero = nullptr, *s = nullptr, *part = nullptr;
+};
+
 struct Ctx {
   int N = 0, L = 0;
   double Re = 100, alpha = 0;
@@ -218,11 +227,8 @@ struct Ctx {
   int gs_n[MAXLEV] = {0};
   bool head_queued = false, head_probe = false;
   // generalized conjugate residual iteration around the cycle (finest-level vectors of n = 3 W^2 + 1 doubles):
-  // residual, direction, the stored normalised directions Z and their images Q (kr_m of each), a zero vector,
-  // device scalars (the Gram-Schmidt coefficients, then |q|^2, (r, q) and the step)
-  int kr_m = 0;
-  double *kr_r = nullptr, *kr_z = nullptr, *kr_Q = nullptr, *kr_Z = nullptr, *kr_zero = nullptr, *kr_s = nullptr;
-  double *kr_part = nullptr;        // block partials of the GCR reductions
+  // the GCR workspace of gp_solve / gp_adjoint_solve (allocated at the first solve, gcr_alloc)
+  GcrWs kr{};
   // the geometry of a later time built in the background (gp_prepare_levelset_analytic) in a second context
   Ctx *shadow = nullptr;
   std::thread prep;
@@ -275,9 +281,13 @@ struct GcrOps {
   std::function<void(const double *z, double *q)> apply_neg;
   std::function<gp_status(double *rinf)> residual;
 };
-gp_status gcr_solve(Ctx *ctx, GcrOps &ops, double *x, double *r, double r0, double thr, double lim, int max_it,
-                    int *iters, double *res, double *rho, int *status);
+gp_status gcr_solve(Ctx *ctx, const GcrWs &ws, GcrOps &ops, double *x, double *r, double r0, double thr, double lim,
+                    int max_it, int *iters, double *res, double *rho, int *status);
 gp_status gcr_alloc(Ctx *ctx);
+// the static scratch array of gp_solve_noalloc: its device address on the current device, taken once per device
+// (scratch_init, at context set-up), and the FP64 solve with the GCR workspace carved from it
+gp_status scratch_init(Ctx *ctx);
+gp_status mg_solve_noalloc(Ctx *ctx, double tol, int max_cycles, gp_stats *st);
 
 // adjoint (adjoint.hip)
 gp_status adjoint_alloc(Ctx *ctx);

@@ -6,6 +6,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 
 #include <hip/hip_ext.h>
 
@@ -2650,57 +2651,52 @@ __global__ void k_pc_shift(const uint8_t *__restrict__ cls, int WW, const double
 
 gp_status gcr_alloc(Ctx *ctx) {
   const int m = std::max(1, ctx->prm.krylov);
-  if (ctx->kr_r && ctx->kr_m == m) return GP_OK;
+  GcrWs &w = ctx->kr;
+  if (w.r && w.m == m) return GP_OK;
   const size_t n = ctx->geo[0].n;
-  auto fr = [](double *&p) {
-    if (p) (void)hipFree(p);
-    p = nullptr;
-  };
-  fr(ctx->kr_r);
-  fr(ctx->kr_z);
-  fr(ctx->kr_Q);
-  fr(ctx->kr_Z);
-  fr(ctx->kr_zero);
-  fr(ctx->kr_s);
-  fr(ctx->kr_part);
-  GP_HIP(hipMalloc((void **)&ctx->kr_r, n * sizeof(double)));
-  GP_HIP(hipMalloc((void **)&ctx->kr_z, n * sizeof(double)));
-  GP_HIP(hipMalloc((void **)&ctx->kr_Q, (size_t)m * n * sizeof(double)));
-  GP_HIP(hipMalloc((void **)&ctx->kr_Z, (size_t)m * n * sizeof(double)));
-  GP_HIP(hipMalloc((void **)&ctx->kr_zero, n * sizeof(double)));
-  GP_HIP(hipMalloc((void **)&ctx->kr_s, (2 * KR_MAX + 8) * sizeof(double)));
-  GP_HIP(hipMalloc((void **)&ctx->kr_part, (size_t)(KR_MAX + 2) * GR_B * sizeof(double)));
-  GP_HIP(hipMemsetAsync(ctx->kr_zero, 0, n * sizeof(double), ctx->stream));
-  ctx->kr_m = m;
+  for (double **p : {&w.r, &w.z, &w.Q, &w.Z, &w.zero, &w.s, &w.part}) {
+    if (*p) (void)hipFree(*p);
+    *p = nullptr;
+  }
+  w.m = 0;
+  GP_HIP(hipMalloc((void **)&w.r, n * sizeof(double)));
+  GP_HIP(hipMalloc((void **)&w.z, n * sizeof(double)));
+  GP_HIP(hipMalloc((void **)&w.Q, (size_t)m * n * sizeof(double)));
+  GP_HIP(hipMalloc((void **)&w.Z, (size_t)m * n * sizeof(double)));
+  GP_HIP(hipMalloc((void **)&w.zero, n * sizeof(double)));
+  GP_HIP(hipMalloc((void **)&w.s, (2 * KR_MAX + 8) * sizeof(double)));
+  GP_HIP(hipMalloc((void **)&w.part, (size_t)(KR_MAX + 2) * GR_B * sizeof(double)));
+  k_fill<double><<<nblk((long)n), TPB, 0, ctx->stream>>>(w.zero, (long)n, 0.0);
+  GP_HIP(hipGetLastError());
+  w.m = m;
   return GP_OK;
 }
 
-gp_status gcr_solve(Ctx *ctx, GcrOps &ops, double *x, double *r, double r0, double thr, double lim, int max_it,
-                    int *iters, double *res, double *rho, int *status) {
-  gp_status st = gcr_alloc(ctx);
-  if (st) return st;
+gp_status gcr_solve(Ctx *ctx, const GcrWs &ws, GcrOps &ops, double *x, double *r, double r0, double thr, double lim,
+                    int max_it, int *iters, double *res, double *rho, int *status) {
   hipStream_t s = ctx->stream;
   const long n = ctx->geo[0].n;
-  const int m = ctx->kr_m;
-  double *beta = ctx->kr_s, *sc = ctx->kr_s + KR_MAX, *nu2 = ctx->kr_s + KR_MAX + 8;
+  const int m = ws.m;
+  double *beta = ws.s, *sc = ws.s + KR_MAX, *nu2 = ws.s + KR_MAX + 8;
   double rn = r0, rp = r0;
   int c = 0, k = 0;
+  gp_status st = GP_OK;
   *status = GP_OK;
   *rho = 0;
   while (rn > thr && c < max_it) {
-    double *z = ctx->kr_z, *qn = ctx->v64[0].r;
-    double *Qk = ctx->kr_Q + (size_t)k * n, *Zk = ctx->kr_Z + (size_t)k * n;
+    double *z = ws.z, *qn = ctx->v64[0].r;
+    double *Qk = ws.Q + (size_t)k * n, *Zk = ws.Z + (size_t)k * n;
     ops.precond(r, z);
     ops.apply_neg(z, qn);  // qn = -M z
     if (k) {
-      k_gcr_dots<<<GR_B, GR_T, 0, s>>>(ctx->kr_Q, n, k, qn, ctx->kr_part);
-      k_gcr_sum<<<1, GR_B, 0, s>>>(ctx->kr_part, k, nu2, beta, nullptr);
+      k_gcr_dots<<<GR_B, GR_T, 0, s>>>(ws.Q, n, k, qn, ws.part);
+      k_gcr_sum<<<1, GR_B, 0, s>>>(ws.part, k, nu2, beta, nullptr);
     }
-    k_gcr_orth<<<GR_B, GR_T, 0, s>>>(ctx->kr_Q, ctx->kr_Z, n, k, beta, qn, z, r, Qk, Zk, ctx->kr_part);
-    k_gcr_sum<<<1, GR_B, 0, s>>>(ctx->kr_part, 2, nullptr, sc, nu2 + k);
-    k_gcr_step<<<GR_B, GR_T, 0, s>>>(n, sc, Qk, Zk, x, r, ctx->kr_part);
+    k_gcr_orth<<<GR_B, GR_T, 0, s>>>(ws.Q, ws.Z, n, k, beta, qn, z, r, Qk, Zk, ws.part);
+    k_gcr_sum<<<1, GR_B, 0, s>>>(ws.part, 2, nullptr, sc, nu2 + k);
+    k_gcr_step<<<GR_B, GR_T, 0, s>>>(n, sc, Qk, Zk, x, r, ws.part);
     __atomic_store_n(ctx->h_rmax, NORM_PENDING, __ATOMIC_RELEASE);
-    k_gcr_max<<<1, GR_B, 0, s>>>(ctx->kr_part, (unsigned long long *)(ctx->d_scal + 1), ctx->h_rmax);
+    k_gcr_max<<<1, GR_B, 0, s>>>(ws.part, (unsigned long long *)(ctx->d_scal + 1), ctx->h_rmax);
     GP_HIP(hipGetLastError());
     if ((st = wait_norm(ctx, &rn))) return st;
     c++;
@@ -2739,13 +2735,12 @@ __global__ void k_pc_out(const uint8_t *__restrict__ cls, int WW, const T *xin, 
 
 // GCR around the FP64 cycle (precision GP_FP64) or the FP32 cycle (GP_MIXED: the preconditioner runs in FP32
 // storage, everything else in FP64)
-static gp_status gcr_mg_solve(Ctx *ctx, int precision, double tol, int max_cycles, gp_stats *stt) {
+static gp_status gcr_mg_solve(Ctx *ctx, const GcrWs &ws, int precision, double tol, int max_cycles, gp_stats *stt) {
   auto t0 = std::chrono::steady_clock::now();
   gp_status st = set_wall_dirichlet(ctx);
   if (st) return st;
   if ((st = ensure_xb(ctx))) return st;
   if (precision != GP_FP64 && (st = ensure_fp32(ctx))) return st;
-  if ((st = gcr_alloc(ctx))) return st;
   Geo &G = ctx->geo[0];
   Vec<double> &V = ctx->v64[0];
   hipStream_t s = ctx->stream;
@@ -2754,7 +2749,7 @@ static gp_status gcr_mg_solve(Ctx *ctx, int precision, double tol, int max_cycle
   double r0, bn;
   if ((st = resnorm64(ctx, &r0))) return st;  // V.r = b - M x
   if (!(r0 == r0)) return GP_EDIVERGED;        // NaN or Inf in the data
-  GP_HIP(hipMemcpyAsync(ctx->kr_r, V.r, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+  GP_HIP(hipMemcpyAsync(ws.r, V.r, n * sizeof(double), hipMemcpyDeviceToDevice, s));
   if ((st = bnorm64(ctx, &bn))) return st;
   const double thr = tol * (bn > 1 ? bn : 1), lim = 1e6 * (r0 > 1 ? r0 : 1);
   GcrOps ops;
@@ -2788,7 +2783,7 @@ static gp_status gcr_mg_solve(Ctx *ctx, int precision, double tol, int max_cycle
   };
   ops.apply_neg = [&](const double *z, double *q) {
     V.x = const_cast<double *>(z);
-    V.b = ctx->kr_zero;
+    V.b = ws.zero;
     double *R0 = V.r;
     V.r = q;
     residual<double>(ctx, 0, (unsigned long long *)(ctx->d_scal + 2), nullptr, true);
@@ -2799,12 +2794,12 @@ static gp_status gcr_mg_solve(Ctx *ctx, int precision, double tol, int max_cycle
   ops.residual = [&](double *rinf) -> gp_status {
     gp_status e = resnorm64(ctx, rinf);
     if (e) return e;
-    GP_HIP(hipMemcpyAsync(ctx->kr_r, V.r, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    GP_HIP(hipMemcpyAsync(ws.r, V.r, n * sizeof(double), hipMemcpyDeviceToDevice, s));
     return GP_OK;
   };
   int iters = 0, status = GP_OK;
   double res = r0, rho = 0;
-  st = gcr_solve(ctx, ops, X0, ctx->kr_r, r0, thr, lim, max_cycles, &iters, &res, &rho, &status);
+  st = gcr_solve(ctx, ws, ops, X0, ws.r, r0, thr, lim, max_cycles, &iters, &res, &rho, &status);
   V.x = X0;
   V.b = B0;
   if (st) return st;
@@ -2822,8 +2817,16 @@ static gp_status gcr_mg_solve(Ctx *ctx, int precision, double tol, int max_cycle
   return out;
 }
 
+static gp_status plain_mg_solve(Ctx *ctx, int precision, double tol, int max_cycles, gp_stats *stt);
+
 gp_status mg_solve(Ctx *ctx, int precision, double tol, int max_cycles, gp_stats *stt) {
-  if (ctx->prm.krylov > 0) return gcr_mg_solve(ctx, precision, tol, max_cycles, stt);
+  if (ctx->prm.krylov <= 0) return plain_mg_solve(ctx, precision, tol, max_cycles, stt);
+  gp_status st = gcr_alloc(ctx);
+  if (st) return st;
+  return gcr_mg_solve(ctx, ctx->kr, precision, tol, max_cycles, stt);
+}
+
+static gp_status plain_mg_solve(Ctx *ctx, int precision, double tol, int max_cycles, gp_stats *stt) {
   auto t0 = std::chrono::steady_clock::now();
   gp_status st = set_wall_dirichlet(ctx);
   if (st) return st;
@@ -2907,6 +2910,90 @@ gp_status mg_solve(Ctx *ctx, int precision, double tol, int max_cycles, gp_stats
     stt->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   }
   return out;
+}
+
+
+// ---------------------------------------------------------------------------------------------------------
+// gp_solve_noalloc: the FP64 solve of gp_solve with its GCR workspace taken from a static device array instead of
+// device memory the context allocates at its first solve.  Every device the library runs on holds one copy of the
+// array (SCRATCH_BYTES) until the process ends; its address on a device is taken once, by scratch_init with that
+// device current (context set-up), and kept per device.  Host code never uses the array's name as an address: on
+// the host the name stands for a host-side shadow, which a kernel cannot dereference.
+// ---------------------------------------------------------------------------------------------------------
+constexpr size_t SCRATCH_BYTES = size_t(64) << 20;
+constexpr size_t SCRATCH_DOUBLES = SCRATCH_BYTES / sizeof(double);
+static __device__ __align__(256) double scratch[SCRATCH_DOUBLES];
+constexpr int SCRATCH_MAX_DEV = 64;
+static std::mutex scratch_mu;
+static double *scratch_dev[SCRATCH_MAX_DEV];
+static bool scratch_done[SCRATCH_MAX_DEV];
+
+gp_status scratch_init(Ctx *ctx) {
+  const int dev = ctx->device;
+  if (dev < 0 || dev >= SCRATCH_MAX_DEV) return GP_EINVAL;
+  std::lock_guard<std::mutex> lk(scratch_mu);
+  if (scratch_done[dev]) return scratch_dev[dev] ? GP_OK : GP_EHIP;
+  void *p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  scratch_done[dev] = true;
+  if (e != hipSuccess || !p) {
+    ctx->hip_err = std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e);
+    return GP_EHIP;
+  }
+  scratch_dev[dev] = (double *)p;
+  return GP_OK;
+}
+
+// doubles of a GCR workspace with m directions over vectors of n doubles, each piece starting on a 256-byte boundary
+static size_t gcr_ws_doubles(long n, int m) {
+  auto up = [](size_t v) { return (v + 31) & ~(size_t)31; };
+  return 3 * up((size_t)n) + 2 * up((size_t)m * n) + up(2 * KR_MAX + 8) + up((size_t)(KR_MAX + 2) * GR_B);
+}
+
+gp_status mg_solve_noalloc(Ctx *ctx, double tol, int max_cycles, gp_stats *stt) {
+  const bool graphs = ctx->graphs;
+  ctx->graphs = 0;  // instantiating a graph allocates
+  gp_status st = GP_OK;
+  if (ctx->prm.krylov <= 0) {  // the plain cycle iteration uses no workspace
+    st = plain_mg_solve(ctx, GP_FP64, tol, max_cycles, stt);
+    ctx->graphs = graphs;
+    return st;
+  }
+  ctx->graphs = graphs;
+  double *base = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(scratch_mu);
+    if (ctx->device >= 0 && ctx->device < SCRATCH_MAX_DEV) base = scratch_dev[ctx->device];
+  }
+  if (!base) {
+    if (ctx->hip_err.empty()) ctx->hip_err = "gp_solve_noalloc: the static scratch array has no address on this device";
+    return GP_EHIP;
+  }
+  const long n = ctx->geo[0].n;
+  const int m = ctx->prm.krylov;
+  const size_t need = gcr_ws_doubles(n, m);
+  if (need > SCRATCH_DOUBLES) {
+    ctx->hip_err = "gp_solve_noalloc: GCR workspace of " + std::to_string(need * sizeof(double)) + " bytes (N = " +
+                   std::to_string(ctx->N) + ", krylov = " + std::to_string(m) + ") exceeds the static scratch of " +
+                   std::to_string(SCRATCH_BYTES) + " bytes";
+    return GP_ESCRATCH;
+  }
+  auto up = [](size_t v) { return (v + 31) & ~(size_t)31; };
+  GcrWs w;
+  w.m = m;
+  double *p = base;
+  w.r = p, p += up((size_t)n);
+  w.z = p, p += up((size_t)n);
+  w.zero = p, p += up((size_t)n);
+  w.Q = p, p += up((size_t)m * n);
+  w.Z = p, p += up((size_t)m * n);
+  w.s = p, p += up(2 * KR_MAX + 8);
+  w.part = p;
+  // the array keeps whatever the last call on this device left in it: the zero vector is cleared by a fill kernel
+  // (every other piece is written before it is read)
+  k_fill<double><<<nblk(n), TPB, 0, ctx->stream>>>(w.zero, n, 0.0);
+  GP_HIP(hipGetLastError());
+  return gcr_mg_solve(ctx, w, GP_FP64, tol, max_cycles, stt);
 }
 
 }  // namespace gpmg

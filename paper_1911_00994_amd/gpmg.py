@@ -15,14 +15,14 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIBPATH = os.path.join(HERE, "libgpmg.so")
 
-GP_OK, GP_EINVAL, GP_ENOMEM, GP_EHIP, GP_EGEOM, GP_ENOCONV, GP_EDIVERGED = 0, -1, -2, -3, -4, -5, -6
+GP_OK, GP_EINVAL, GP_ENOMEM, GP_EHIP, GP_EGEOM, GP_ENOCONV, GP_EDIVERGED, GP_ESCRATCH = 0, -1, -2, -3, -4, -5, -6, -7
 GP_FP64, GP_MIXED = 0, 1
 
 EXPORTS = [
     "gp_default_params", "gp_setup_grid", "gp_destroy", "gp_num_levels", "gp_strerror", "gp_last_hip_error",
     "gp_set_levelset", "gp_set_levelset_analytic", "gp_prepare_levelset_analytic", "gp_set_walls",
     "gp_get_boundary_geometry",
-    "gp_set_boundary_values", "gp_set_alpha", "gp_set_rhs", "gp_set_x", "gp_get_x", "gp_mg_vcycle", "gp_solve",
+    "gp_set_boundary_values", "gp_set_alpha", "gp_set_rhs", "gp_set_x", "gp_get_x", "gp_mg_vcycle", "gp_solve", "gp_solve_noalloc",
     "gp_residual", "gp_set_state", "gp_cn_step", "gp_get_classes", "gp_get_ghost_rows", "gp_get_ext_rows",
     "gp_get_band_layout", "gp_get_coupled_boxes",
     "gp_relax", "gp_time_kernel", "gp_probe_start", "gp_probe_stop", "gp_apply_mt", "gp_adjoint_solve", "gp_apply_cycle", "gp_apply_cycle_t",
@@ -100,6 +100,7 @@ def lib():
         "gp_get_x": (i, [vp, vp, vp, vp, vp, i]),
         "gp_mg_vcycle": (i, [vp, i, vp]),
         "gp_solve": (i, [vp, i, d, i, ctypes.POINTER(GpStats)]),
+        "gp_solve_noalloc": (i, [vp, d, i, ctypes.POINTER(GpStats)]),
         "gp_residual": (i, [vp, vp, vp]),
         "gp_set_state": (i, [vp, vp, vp, vp, d, i]),
         "gp_cn_step": (i, [vp, d, vp, vp, vp, i, i, d, i, d, i, ctypes.POINTER(GpStats)]),
@@ -256,6 +257,14 @@ class Solver:
         st = lib().gp_solve(self._h, precision, tol, max_cycles, ctypes.byref(s))
         if check and st not in (GP_OK,):
             self._check(st, "gp_solve")
+        return st, s.as_dict()
+
+    def solve_noalloc(self, tol=1e-10, max_cycles=100, check=True):
+        """gp_solve_noalloc: the FP64 solve without device allocation (workspace in the library's static array)"""
+        s = GpStats()
+        st = lib().gp_solve_noalloc(self._h, tol, max_cycles, ctypes.byref(s))
+        if check and st not in (GP_OK,):
+            self._check(st, "gp_solve_noalloc")
         return st, s.as_dict()
 
     def residual(self):
