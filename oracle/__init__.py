@@ -84,6 +84,7 @@ def lib(path: str = None):
             ("or_threads", []),
             ("or_coupled_box_count", [vp, i, vp, vp]),
             ("or_get_coupled_boxes", [vp, i, vp, vp, vp, vp, vp, vp]),
+            ("or_reinit", [vp, i, d, i, d, vp]),
         ]:
             f = getattr(L, name)
             f.restype = i
@@ -135,6 +136,18 @@ def levelset_analytic(kind: int, sp, motion, t: float, N: int) -> np.ndarray:
     st = lib().or_levelset_analytic(kind, _p(sp), _p(mo), t, N, _p(phi))
     assert st == OK
     return phi
+
+
+def reinit(phi0, dx: float, iters: int, cfl: float = 0.3) -> np.ndarray:
+    """Reinitialisation of a level set sampled on a square lattice of spacing dx towards the signed distance
+    (Sect. 3.1, eq. (sdf)); the discretisation is described at or_reinit."""
+    a = _f64(np.asarray(phi0))
+    n = a.shape[0]
+    assert a.shape == (n, n)
+    out = np.zeros_like(a)
+    st = lib().or_reinit(_p(a), n, dx, iters, cfl, _p(out))
+    assert st == OK, st
+    return out
 
 
 class Oracle:

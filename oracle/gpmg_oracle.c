@@ -18,6 +18,7 @@
  *     relaxation eqs. (fictBC),(ghostrelax), Alg. relax, restriction eqs.
  *     (restop),(restop5), bilinear interpolation (Sect. 4.3), cycles (Sect. 4.3)
  *   - moving domains: Sect. 3.4
+ *   - level-set reinitialisation: Sect. 3.1, eq. (sdf) (or_reinit)
  * Readings of points the paper leaves open are listed in the design notes and
  * repeated at the place they are used.
  *
@@ -2166,5 +2167,95 @@ int or_test_prolong(void *h, int l, const double *e_coarse, double *x_fine) {
   memcpy(C->x, sc, C->n * sizeof(double));
   free(sx);
   free(sc);
+  return OK;
+}
+
+/* ------------------------------------------------------------------------- */
+/* level-set reinitialisation, Sect. 3.1 eq. (sdf)                            */
+/* ------------------------------------------------------------------------- */
+/* Steady state of d(phi_d)/d(mu) = sgn(phi) (1 - |grad phi_d|), phi_d = phi at mu = 0, on an n x n lattice of
+ * spacing dx (entry [ky * n + kx]).  The paper fixes the equation, not its discretisation; this reading:
+ *   - explicit Euler steps in the fictitious time mu with dmu = cfl * dx, iters steps;
+ *   - |grad phi_d| by the Godunov upwind approximation of first order: with the one-sided differences
+ *     a = (phi_i - phi_{i-1})/dx, b = (phi_{i+1} - phi_i)/dx (c, d likewise in y), where sgn(phi) > 0 the
+ *     x part is max(max(a, 0)^2, min(b, 0)^2), where sgn(phi) < 0 it is max(min(a, 0)^2, max(b, 0)^2);
+ *     outside the lattice the nearest lattice value is repeated (zero one-sided difference);
+ *   - at the points next to the interface (phi changes sign towards a lattice neighbour, or phi = 0) the
+ *     distance estimate D = dx phi / |Delta phi| of the initial data replaces the upwind step, so that the
+ *     interface stays where phi puts it: phi_d <- phi_d - (dmu / dx) (sgn(phi) |phi_d| - D), with |Delta phi|
+ *     the length of the vector of the largest of the central and the two one-sided differences per axis
+ *     (bounded below by 1e-300);
+ *   - sgn(0) = 0 (a point on the interface does not move).
+ * Pins: a linear level set of any slope becomes the exact signed distance; on a circle the result approaches
+ * R - r at first order and the zero set does not move. */
+static double rs_max3(double a, double b, double c) {
+  double m = a > b ? a : b;
+  return m > c ? m : c;
+}
+int or_reinit(const double *phi0, int n, double dx, int iters, double cfl, double *out) {
+  if (n < 2 || !(dx > 0) || iters < 0 || !(cfl > 0)) return E_INVAL;
+  size_t nn = (size_t)n * n;
+  double *cur = (double *)xcalloc(nn, sizeof(double)), *nxt = (double *)xcalloc(nn, sizeof(double));
+  double *Dest = (double *)xcalloc(nn, sizeof(double));
+  signed char *sg = (signed char *)xcalloc(nn, 1);
+  unsigned char *near = (unsigned char *)xcalloc(nn, 1);
+#define P0(i, j) phi0[(size_t)(j) * n + (i)]
+  for (int j = 0; j < n; j++)
+    for (int i = 0; i < n; i++) {
+      size_t k = (size_t)j * n + i;
+      double p = P0(i, j);
+      sg[k] = p > 0 ? 1 : (p < 0 ? -1 : 0);
+      int im = i > 0 ? i - 1 : i, ip = i < n - 1 ? i + 1 : i, jm = j > 0 ? j - 1 : j, jp = j < n - 1 ? j + 1 : j;
+      int cross = p == 0.0 || p * P0(im, j) < 0 || p * P0(ip, j) < 0 || p * P0(i, jm) < 0 || p * P0(i, jp) < 0;
+      near[k] = (unsigned char)cross;
+      if (cross) {
+        double ex = rs_max3(fabs(P0(ip, j) - P0(im, j)) / 2, fabs(P0(ip, j) - p), fabs(p - P0(im, j)));
+        double ey = rs_max3(fabs(P0(i, jp) - P0(i, jm)) / 2, fabs(P0(i, jp) - p), fabs(p - P0(i, jm)));
+        double len = sqrt(ex * ex + ey * ey);
+        if (len < 1e-300) len = 1e-300;
+        Dest[k] = dx * p / len;
+      }
+      cur[k] = p;
+    }
+#undef P0
+  const double dmu = cfl * dx;
+  for (int it = 0; it < iters; it++) {
+    for (int j = 0; j < n; j++)
+      for (int i = 0; i < n; i++) {
+        size_t k = (size_t)j * n + i;
+        double p = cur[k];
+        if (sg[k] == 0) {
+          nxt[k] = p;
+          continue;
+        }
+        if (near[k]) {
+          nxt[k] = p - (dmu / dx) * (sg[k] * fabs(p) - Dest[k]);
+          continue;
+        }
+        int im = i > 0 ? i - 1 : i, ip = i < n - 1 ? i + 1 : i, jm = j > 0 ? j - 1 : j, jp = j < n - 1 ? j + 1 : j;
+        double a = (p - cur[(size_t)j * n + im]) / dx, b = (cur[(size_t)j * n + ip] - p) / dx;
+        double c = (p - cur[(size_t)jm * n + i]) / dx, d = (cur[(size_t)jp * n + i] - p) / dx;
+        double gx, gy;
+        if (sg[k] > 0) {
+          double a1 = a > 0 ? a : 0, b1 = b < 0 ? b : 0, c1 = c > 0 ? c : 0, d1 = d < 0 ? d : 0;
+          gx = a1 * a1 > b1 * b1 ? a1 * a1 : b1 * b1;
+          gy = c1 * c1 > d1 * d1 ? c1 * c1 : d1 * d1;
+        } else {
+          double a1 = a < 0 ? a : 0, b1 = b > 0 ? b : 0, c1 = c < 0 ? c : 0, d1 = d > 0 ? d : 0;
+          gx = a1 * a1 > b1 * b1 ? a1 * a1 : b1 * b1;
+          gy = c1 * c1 > d1 * d1 ? c1 * c1 : d1 * d1;
+        }
+        nxt[k] = p - dmu * sg[k] * (sqrt(gx + gy) - 1.0);
+      }
+    double *t = cur;
+    cur = nxt;
+    nxt = t;
+  }
+  memcpy(out, cur, nn * sizeof(double));
+  free(cur);
+  free(nxt);
+  free(Dest);
+  free(sg);
+  free(near);
   return OK;
 }
