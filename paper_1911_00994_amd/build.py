@@ -1,7 +1,8 @@
 """Build of the HIP library (gfx950) in-tree: paper_1911_00994_amd/libgpmg.so.
 
 Every .hip source under csrc/ is compiled to an object with hipcc and linked into one shared library.  The
-geometry file is compiled with FMA contraction off (branch decisions of the boundary-point bisection).
+geometry file is compiled with FMA contraction off (branch decisions of the boundary-point bisection), and so is the
+level-set file (its arithmetic then matches the plain C oracle's operation for operation).
 """
 from __future__ import annotations
 
@@ -17,8 +18,8 @@ ARCH = os.environ.get("GPMG_ARCH", "gfx950")
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang",
           "-packed-fp32-ops", "-Wall", "-Wno-unused-function"]
-PER_FILE = {"geom.hip": ["-ffp-contract=off"]}
-SOURCES = ["geom.hip", "mg.hip", "cn.hip", "adjoint.hip", "api.hip"]
+PER_FILE = {"geom.hip": ["-ffp-contract=off"], "levelset.hip": ["-ffp-contract=off"]}
+SOURCES = ["geom.hip", "mg.hip", "cn.hip", "adjoint.hip", "levelset.hip", "api.hip"]
 
 
 def hipcc() -> str:
