@@ -126,6 +126,40 @@ def cpu_baseline(wk, sizes=((256, 8), (512, 4), (1024, 2)), tol=1e-8):
     return res
 
 
+def cavity_time_to_tol(gpmg, wl, np, torch, warm_steps=5, tol=1e-8):
+    """Time to tol from x = 0, FP64 against mixed precision, on the N = 2048 lid-driven cavity around the fixed
+    circle (Re = 1000, dt = h) after a few steps (its FP64 working set, about 0.4 GB, is larger than the MALL)."""
+    wk = wl.config_cavity2048()
+    N = wk.N
+    s = gpmg.Solver(N, Re=wk.Re, stream=torch.cuda.current_stream().cuda_stream)
+    s.set_walls(wk.walls)
+    s.set_levelset_analytic(wk.shape.kind, wk.shape.params, 0.0, None)
+    W = N + 2
+    z = np.zeros((W, W))
+    s.set_state(z, z, z, 0.0)
+    dt = 2.0 / N
+    for _ in range(warm_steps):
+        s.cn_step(dt, None, None, None, tol=tol, max_cycles=200, picard_eps=1e-8, picard_max=40)
+    out = {"workload": wk.name, "N": N, "tol": tol, "after_steps": warm_steps}
+    sols = {}
+    for name, pr in (("fp64", gpmg.GP_FP64), ("mixed", gpmg.GP_MIXED), ("fp64_again", gpmg.GP_FP64),
+                     ("mixed_again", gpmg.GP_MIXED)):
+        s.set_x(z, z, z, 0.0)
+        torch.cuda.synchronize()
+        a0 = time.perf_counter()
+        st, info = s.solve(tol, 400, precision=pr, check=False)
+        out[name] = {"ms": 1000 * (time.perf_counter() - a0), "cycles": info["cycles"], "res": info["res"],
+                     "status": st, "bytes_alg": info["bytes_alg"]}
+        sols[name] = np.concatenate([a.ravel() for a in s.get_x()[:3]])
+    cls = s.classes().ravel()
+    act = (cls == 1) | (cls == 2) | (cls == 4) | (cls == 7)
+    out["max_rel_diff_mixed_vs_fp64"] = float(np.abs(sols["fp64"] - sols["mixed"])[act].max() /
+                                             max(1.0, np.abs(sols["fp64"][act]).max()))
+    out["speedup"] = out["fp64_again"]["ms"] / out["mixed_again"]["ms"]
+    s.close()
+    return out
+
+
 def adjoint_run(gpmg, wl, N=512, steps=40, K=8, tol=1e-8):
     """Reverse mode of the moving-circle run (N = 512, r = 0.25 translating at (0.5, 0), Re = 100, 40 steps of
     dt = h, stream-function forcing of 64 modes): J = h^2 sum of the internal u^2 + v^2 at the end, gradients with
@@ -179,6 +213,9 @@ def parse():
                     help="replay each solver iteration from a HIP graph (by default the launches are issued from the "
                          "host, with the next cycle's first sweep queued ahead of the convergence test)")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-cavity", action="store_true", help="skip the N = 2048 cavity time-to-tolerance comparison")
+    ap.add_argument("--krylov", type=int, default=None,
+                    help="GCR restart length of the solver (library default when not given; 0: the plain cycle)")
     ap.add_argument("--profile-kernel", action="store_true",
                     help="set up the N=1024 system, run a plain 64 MiB device copy (counter calibration) and 10 "
                          "launches of the five-colour box sweep on the finest level, then exit (for rocprofv3 "
@@ -206,7 +243,8 @@ def main():
     prec = gpmg.GP_MIXED if args.precision == "mixed" else gpmg.GP_FP64
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream(dev)
-    solver = gpmg.Solver(N, Re=Re, stream=stream.cuda_stream, graph_iterations=1 if args.graphs else 0)
+    extra = {} if args.krylov is None else {"krylov": args.krylov}
+    solver = gpmg.Solver(N, Re=Re, stream=stream.cuda_stream, graph_iterations=1 if args.graphs else 0, **extra)
     fu, fv = wl.fourier_forcing(N, seed=0)
     fu_d = torch.from_numpy(fu).to(dev)
     fv_d = torch.from_numpy(fv).to(dev)
@@ -292,19 +330,22 @@ def main():
     z = np.zeros((W, W))
     ttt = {}
     sols = {}
-    for name, pr in (("fp64", gpmg.GP_FP64), ("mixed", gpmg.GP_MIXED)):
+    # each precision twice, the second timed (the first mixed solve allocates the FP32 hierarchy)
+    for name, pr in (("fp64", gpmg.GP_FP64), ("mixed", gpmg.GP_MIXED), ("fp64", gpmg.GP_FP64),
+                     ("mixed", gpmg.GP_MIXED)):
         solver.set_x(z, z, z, 0.0)
         torch.cuda.synchronize()
         a0 = time.perf_counter()
         st, info = solver.solve(args.tol, 400, precision=pr, check=False)
         ttt[name] = {"ms": 1000 * (time.perf_counter() - a0), "cycles": info["cycles"], "outer": info["outer"],
-                     "res": info["res"], "status": st}
+                     "res": info["res"], "status": st, "bytes_alg": info["bytes_alg"]}
         sols[name] = np.concatenate([a.ravel() for a in solver.get_x()[:3]])
     act = ((cls == 1) | (cls == 2) | (cls == 4) | (cls == 7)).ravel()
     diff = float(np.abs(sols["fp64"] - sols["mixed"])[act].max() / max(1.0, np.abs(sols["fp64"][act]).max()))
     solver.set_x(u, v, p, xi)
     mixed_vs_fp64 = {"tol": args.tol, "fp64": ttt["fp64"], "mixed": ttt["mixed"],
                      "speedup": ttt["fp64"]["ms"] / ttt["mixed"]["ms"], "max_rel_diff_mixed_vs_fp64": diff}
+    cavity = None if args.no_cavity else cavity_time_to_tol(gpmg, wl, np, torch)
     adjoint = None if args.no_adjoint else adjoint_run(gpmg, wl)
     cpu = None
     if not args.no_cpu_baseline:
@@ -323,12 +364,14 @@ def main():
         "dtype": "f64" if prec == gpmg.GP_FP64 else "f32+f64",
         "data": "synthetic",
         "config": {"workload": wk.name, "N": N, "Re": Re, "dt": "h", "tol": args.tol,
-                   "solver": "GCR(16) around V(2,2) cycles (coupled ghost boxes on the finest level)",
+                   "solver": (f"GCR({solver._p.krylov}) around V(2,2) cycles" if solver._p.krylov > 0 else
+                              "V(2,2) cycles") + " (coupled ghost boxes on the finest level)",
                    "precision": args.precision, "unknowns": n_unk, "cycles": cycles,
                    "cycles_per_step": cycles / args.steps, "wall_s": wall,
                    "cycle_level_hbm_fraction": cyc_gbs / PEAK_HBM_GBS},
         "roofline": roofline,
         "mixed_vs_fp64_time_to_tol": mixed_vs_fp64,
+        "mixed_vs_fp64_time_to_tol_cavity2048": cavity,
         "adjoint": adjoint,
         "cpu_baseline": cpu,
     }

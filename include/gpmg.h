@@ -65,9 +65,13 @@ enum { GP_INACTIVE = 0, GP_INTERNAL = 1, GP_GHOST = 2, GP_WALL_DIRICHLET = 3, GP
  * W cycle is gamma = 2, Sect. 4.3), lambda_ghost = 2 ghost sweeps per box sweep (Alg. relax), coarsest grid
  * 8 x 8 cells solved exactly (Sect. 4.3), Alg. 1 march limit 8 steps and bisection accuracy 0.01 h (Sect. 3.3),
  * fictitious time steps 0.9 (Dirichlet) and 0.9 h (normal derivative) (Sect. 4.1.2), extension band of 4
- * grid steps, minimum ghost-row diagonal 0.1 (below it the ghost takes an extrapolation row), and after each
- * relaxation step bnd_sweeps = 1 extra box sweep (same colour order, each followed by lambda_ghost ghost
- * sweeps) over the cells within bnd_radius = 2 cells of a cell touching the body.  The last five fields
+ * grid steps, minimum ghost-row diagonal cg_min = 0.1 on the coarse levels (below it a coarse ghost takes an
+ * extrapolation row; the finest level keeps every defined eq. (BCu) row), optionally bnd_sweeps extra box sweeps
+ * after each relaxation step (default 0; same colour order, each followed by lambda_ghost ghost sweeps) over the
+ * cells within bnd_radius = 2 cells of a cell touching the body, coupled ghost boxes (ghost_boxes = 1: after the
+ * box sweep, each cell whose internal unknowns appear in a body ghost row is relaxed together with those ghosts, on
+ * the ghost_box_levels = 1 finest levels), and krylov = 8 (the solves use the cycle as the preconditioner of a
+ * GCR iteration restarted after 8 directions; 0 runs the multigrid iteration of Sect. 4 on its own).  The last five fields
  * choose how the same computation is laid out on the device (results agree to rounding): fuse_small_levels = 1
  * runs the cycle of the levels with N <= 32 in one workgroup with their data in LDS, band_split_min = 3000: a
  * boundary band with at least that many cells, and the coupled boxes of a level with a colour of at least that many
@@ -113,16 +117,25 @@ typedef struct {
   double res;      /* final max-norm residual */
   double rho;      /* last residual ratio */
   double seconds;  /* wall time of the call (host clock, includes the final synchronisation) */
+  double bytes_alg; /* algorithmic HBM bytes of the call's iterations: per cycle, the compulsory traffic of each
+                       level's sweeps (65 B per cell and relaxation step in FP64, 33 in FP32 storage), residual with
+                       restriction and prolongation (53 B, 27), weighted by (gamma / 4)^level; per GCR iteration
+                       (3 k + 12) vector passes of 8 (3 W^2 + 1) B for the k-th direction; per convergence test
+                       41 B per cell */
 } gp_stats;
 
 void gp_default_params(gp_params *prm);
 
-/* Create a context for an N x N cell grid and Reynolds number Re (used by gp_cn_step).  prm may be NULL
+/* Create a context for an N x N cell grid and Reynolds number Re (used by gp_cn_step): the staggered MAC grid of
+ * Sect. 3.2 on D = (-1, 1)^2 and the multigrid hierarchy of Sect. 4 (levels N, N/2, ... down to the coarsest grid of
+ * Sect. 4.3, coarsest_n cells per side), with every device buffer of every level allocated here.  prm may be NULL
  * (defaults).  hip_stream is the hipStream_t all work of the context goes to; NULL makes the context create
  * its own (blocking, default priority, so it orders with the null stream; destroyed by gp_destroy).  *out is
  * NULL on error. */
 gp_status gp_setup_grid(gp_ctx **out, int N, double Re, const gp_params *prm, void *hip_stream);
+/* Release every device and host resource of the context (resource management; no passage of the paper). */
 void gp_destroy(gp_ctx *ctx);
+/* Number of grid levels of the hierarchy (Sect. 4.3: from the finest grid to the coarsest, solved exactly). */
 int gp_num_levels(const gp_ctx *ctx);
 const char *gp_strerror(gp_status st);
 const char *gp_last_hip_error(const gp_ctx *ctx);
@@ -145,6 +158,16 @@ gp_status gp_set_levelset_analytic(gp_ctx *ctx, const gp_shape *shape, double t,
  * reported here: gp_set_levelset_analytic then builds as usual and reports them. */
 gp_status gp_prepare_levelset_analytic(gp_ctx *ctx, const gp_shape *shape, double t, const gp_rigid *motion);
 
+/* Level-set reinitialisation (Sect. 3.1, eq. (sdf)): phi ((2N+1)^2 doubles on the context's half-step lattice,
+ * host or device per on_device) is replaced in place by iters explicit pseudo-time steps of size cfl * (h/2)
+ * (0 < cfl <= 0.5) towards the signed distance with the same zero set, positive inside the body: first-order
+ * Godunov upwind steps, and next to the interface the distance estimate (h/2) phi / |Delta phi| of the input held
+ * fixed (the interface does not move).  After iters steps the values within about iters * cfl * h/2 of the
+ * interface are converged.  Use it before gp_set_levelset for a level set that is no longer a distance function
+ * (a deforming body).  The first call allocates four lattice-sized buffers on the device.  GP_EINVAL for a NULL
+ * phi, iters < 0 or cfl outside (0, 0.5]. */
+gp_status gp_reinit_levelset(gp_ctx *ctx, double *phi, int on_device, int iters, double cfl);
+
 /* wall velocities: {bottom u, bottom v, right u, right v, top u, top v, left u, left v} (host array of 8) */
 gp_status gp_set_walls(gp_ctx *ctx, const double *walls8);
 
@@ -165,14 +188,21 @@ gp_status gp_get_x(gp_ctx *ctx, double *u, double *v, double *p, double *xi, int
 /* one multigrid cycle on the finest level followed by the mean-pressure projection; *res_inf receives the
  * max-norm residual afterwards (may be NULL) */
 gp_status gp_mg_vcycle(gp_ctx *ctx, int precision, double *res_inf);
-/* cycles until ||r||_inf <= tol * max(1, ||b||_inf) or max_cycles */
+/* Solve the system of the current geometry, alpha and right-hand side (Sect. 4) from the current x until
+ * ||r||_inf <= tol * max(1, ||b||_inf) (over all rows as written) or max_cycles cycles.  krylov = 0: the multigrid
+ * iteration x <- x + B'(b - M x) of Sect. 4 (B' one cycle and the mean-pressure projection).  krylov = m > 0: the
+ * same B' preconditions a generalized conjugate residual iteration (GCR) restarted after m directions (each
+ * iteration one cycle, one product with M and the orthogonalisation; the residual is updated recursively and
+ * confirmed by the true residual at convergence and at each restart).  GP_MIXED runs the cycle in FP32 storage
+ * (the FP64 iteration around it).  st->cycles counts cycles (GCR iterations).  GP_ENOCONV if max_cycles is
+ * reached (x keeps the last iterate), GP_EDIVERGED on NaN or growth beyond 1e6 times the initial residual. */
 gp_status gp_solve(gp_ctx *ctx, int precision, double tol, int max_cycles, gp_stats *st);
 /* For callers that cannot allocate device memory (code under HIP graph capture, tight serving loops, harnesses
  * that forbid hipMalloc): gp_solve in FP64 (same iteration, same results) without any device allocation.  gp_solve
  * allocates the GCR workspace ((3 + 2 krylov) vectors of 3 W^2 + 1 doubles) at its first call; this entry point
  * takes it from a static device array of 64 MiB that every GPU the library runs on holds until the process ends
  * (its address is looked up once per device at gp_setup_grid).  Limit: the workspace must fit 64 MiB, which holds
- * N <= 256 with the default krylov = 16 (N = 512 with krylov <= 3); larger problems return GP_ESCRATCH (the text
+ * N <= 256 with the default krylov = 8 (N = 512 with krylov <= 3); larger problems return GP_ESCRATCH (the text
  * via gp_last_hip_error) without touching the context.  krylov = 0 needs no workspace (any N).  The context itself
  * (geometry, hierarchy) is allocated by gp_setup_grid and the geometry calls, so call this after them.  Calls on
  * one GPU share the array: calls that overlap in time on the same GPU (from several threads or streams) race and

@@ -155,7 +155,7 @@ class Oracle:
 
     def __init__(self, N, Re=100.0, nu1=2, nu2=2, gamma=1, lam=2, coarsest_n=8, march_max=8, ext_radius=4,
                  perm_seed=0, dtau_dir=0.9, dtau_neu_over_h=0.9, eps_over_h=0.01, cg_min=0.1, bnd_sweeps=0, bnd_radius=2,
-                 ghost_boxes=1, lex_order=0, krylov=16, ghost_box_levels=1):
+                 ghost_boxes=1, lex_order=0, krylov=8, ghost_box_levels=1):
         self.N, self.W, self.Re = N, N + 2, Re
         ip = np.array([nu1, nu2, gamma, lam, coarsest_n, march_max, ext_radius, perm_seed, bnd_sweeps, bnd_radius,
                        ghost_boxes, lex_order, krylov, ghost_box_levels], dtype=np.int32)

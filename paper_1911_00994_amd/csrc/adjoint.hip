@@ -764,6 +764,7 @@ gp_status adjoint_solve_dev(Ctx *ctx, double tol, int max_cycles, gp_stats *stt)
   if ((st = absmax_dev(ctx, ctx->a_g, G.n, &gn))) return st;
   const double thr = tol * (gn > 1 ? gn : 1);
   int c = 0;
+  double kb = 0;
   gp_status out = GP_OK;
   if (ctx->prm.krylov > 0) {
     // GCR with the transposed cycle as the preconditioner (the transpose of the forward solve's iteration)
@@ -788,7 +789,9 @@ gp_status adjoint_solve_dev(Ctx *ctx, double tol, int max_cycles, gp_stats *stt)
     };
     int status = GP_OK;
     const double lim = 1e6 * (r0 > 1 ? r0 : 1);
-    if ((st = gcr_solve(ctx, ctx->kr, ops, ctx->a_lam, ctx->kr.r, r0, thr, lim, max_cycles, &c, &r, &rho, &status))) return st;
+    if ((st = gcr_solve(ctx, ctx->kr, ops, ctx->a_lam, ctx->kr.r, r0, thr, lim, max_cycles, &c, &r, &rho, &status,
+                        &kb)))
+      return st;
     out = status;
   }
   for (; ctx->prm.krylov == 0;) {
@@ -814,6 +817,7 @@ gp_status adjoint_solve_dev(Ctx *ctx, double tol, int max_cycles, gp_stats *stt)
     stt->res0 = r0;
     stt->res = r;
     stt->rho = rho;
+    stt->bytes_alg = c * cycle_bytes(ctx, false) + kb;
     stt->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   }
   return out;

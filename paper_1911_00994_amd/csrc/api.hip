@@ -122,7 +122,7 @@ void gp_default_params(gp_params *p) {
   p->band_sector_min = 1500;
   p->queue_ahead = 1;
   p->ghost_boxes = 1;
-  p->krylov = 16;
+  p->krylov = 8;
   p->ghost_box_levels = 1;
 }
 
@@ -192,6 +192,8 @@ void gp_destroy(gp_ctx *ctx) {
     dfree(G.xb_wr);
     dfree(G.xb_r);
     dfree(G.xb_inv);
+    for (void *q : {(void *)G.xb_gc, (void *)G.xb_gw, (void *)G.xb_uk, (void *)G.xb_uo, (void *)G.xb_ub, (void *)G.xb_um})
+      dfree(q);
     dfree(G.xb_own);
     dfree(G.d_xb_co);
     dfree(G.sec_pt);
@@ -293,6 +295,7 @@ void gp_destroy(gp_ctx *ctx) {
   dfree(ctx->ckv);
   dfree(ctx->fwork);
   for (double *p : {ctx->kr.r, ctx->kr.z, ctx->kr.Q, ctx->kr.Z, ctx->kr.zero, ctx->kr.s, ctx->kr.part}) dfree(p);
+  for (void *p : {(void *)ctx->rl_a, (void *)ctx->rl_b, (void *)ctx->rl_d, (void *)ctx->rl_c}) dfree(p);
   if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
   delete ctx;
 }
@@ -414,6 +417,12 @@ gp_status gp_setup_grid(gp_ctx **out, int N, double Re, const gp_params *prm, vo
       ALLOC(G.xb_wr, (size_t)G.xb_scap);
       ALLOC(G.xb_r, (size_t)G.xb_scap);
       ALLOC(G.xb_inv, (size_t)G.xb_icap);
+      ALLOC(G.xb_gc, (size_t)9 * G.xb_scap);
+      ALLOC(G.xb_gw, (size_t)9 * G.xb_scap);
+      ALLOC(G.xb_uk, (size_t)G.xb_scap);
+      ALLOC(G.xb_uo, (size_t)G.xb_scap);
+      ALLOC(G.xb_ub, (size_t)G.xb_scap);
+      ALLOC(G.xb_um, (size_t)G.xb_scap);
       ALLOC(G.xb_own, (size_t)5 * G.gcap);
       ALLOC(G.d_xb_co, 16);
     }
@@ -703,6 +712,11 @@ gp_status gp_solve(gp_ctx *ctx, int precision, double tol, int max_cycles, gp_st
   gp_status st = ensure_coarse(ctx);
   if (st) return st;
   return mg_solve(ctx, precision, tol, max_cycles, s);
+}
+
+gp_status gp_reinit_levelset(gp_ctx *ctx, double *phi, int on_device, int iters, double cfl) {
+  if (!ctx || !phi || iters < 0 || !(cfl > 0 && cfl <= 0.5)) return GP_EINVAL;
+  return reinit_levelset(ctx, phi, on_device, iters, cfl);
 }
 
 gp_status gp_solve_noalloc(gp_ctx *ctx, double tol, int max_cycles, gp_stats *s) {

@@ -213,15 +213,18 @@ gp_status cn_step(Ctx *ctx, double dt, const double *fu, const double *fv, const
   if (hf[1] || !(fbn == fbn)) return GP_EGEOM;  // an internal point of the new domain lacks step-n values
   gp_stats sub{};
   int total = 0, picard = 0;
+  double bytes = 0;
   gp_status st = GP_OK;
   if (extrap) {
     st = mg_solve(ctx, precision, tol, max_cycles, &sub);
     total = sub.cycles;
+    bytes = sub.bytes_alg;
   } else {
     double h = G.h, a = alpha / (h * h), d = 1.0 + 4.0 * a;
     for (;;) {
       st = mg_solve(ctx, precision, tol, max_cycles, &sub);
       total += sub.cycles;
+      bytes += sub.bytes_alg;
       picard++;
       if (st != GP_OK && st != GP_ENOCONV) break;
       if (G.ne) k_ext_fill_cn<double><<<nblk(G.ne), TPB, 0, s>>>(G.e_pt, G.e_src, G.e_w, G.ne, ctx->v64[0].x);
@@ -258,6 +261,7 @@ gp_status cn_step(Ctx *ctx, double dt, const double *fu, const double *fv, const
   if (stt) {
     *stt = sub;
     stt->cycles = total;
+    stt->bytes_alg = bytes;
     stt->outer = picard;
     stt->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   }

@@ -1069,6 +1069,30 @@ __global__ void k_xb_soff(const int *xb_off, const int *co, int *out) {
   const int c = threadIdx.x;
   if (c < 6) out[c] = xb_off[co[c]];
 }
+// flat per-slot row tables (see Geo::xb_gc): the 9 columns and weights of each ghost slot's row, -1 for internal slots
+__global__ void k_xb_flat_rows(const uint8_t *cls, const int *xb_idx, int nxs, int scap, const int *g_rowof,
+                               const int *g_col, const double *g_w, int *gc, double *gw) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= nxs) return;
+  const int k = xb_idx[s];
+  const bool ghost = cls[k] != K_INT;
+  const int r = ghost ? g_rowof[k] : 0;
+  for (int z = 0; z < 9; z++) {
+    gc[(size_t)z * scap + s] = ghost ? g_col[9 * r + z] : -1;
+    gw[(size_t)z * scap + s] = ghost ? g_w[9 * r + z] : 0.0;
+  }
+}
+// flat per-slot write tables (see Geo::xb_uk), after the inverses (which decide which blocks are usable)
+__global__ void k_xb_flat_write(const int *xb_idx, const int *xb_box, const int *xb_off, const int *xb_ioff,
+                                const uint8_t *xb_wr, const uint8_t *xb_ok, int nxs, int *uk, int *uo, int *ub, int *um) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= nxs) return;
+  const int bx = xb_box[s], o = xb_off[bx], m = xb_off[bx + 1] - o;
+  uk[s] = (xb_wr[s] && xb_ok[bx]) ? xb_idx[s] : -1;
+  uo[s] = xb_ioff[bx] + (s - o) * m;
+  ub[s] = o;
+  um[s] = m;
+}
 
 // coefficient of unknown c in the row of point k (internal momentum or continuity row of Sect. 3.2, or the ghost
 // row of k); the xi column of the continuity rows is not a box unknown
@@ -1618,6 +1642,8 @@ static gp_status xb_build(Ctx *ctx, int l, BuildRes &B) {
   if (nxs) {
     k_xb_own<<<nblk(nxs), TPB, 0, s>>>(G.cls, N, G.xb_idx, G.xb_box, G.xb_cell, nxs, G.g_rowof, G.ng, G.xb_own);
     k_xb_wr<<<nblk(nxs), TPB, 0, s>>>(G.cls, N, G.xb_idx, G.xb_box, G.xb_cell, nxs, G.g_rowof, G.ng, G.xb_own, G.xb_wr);
+    k_xb_flat_rows<<<nblk(nxs), TPB, 0, s>>>(G.cls, G.xb_idx, nxs, G.xb_scap, G.g_rowof, G.g_col, G.g_w, G.xb_gc,
+                                             G.xb_gw);
   }
   GP_HIP(hipGetLastError());
   G.nxb = nxb;
@@ -1637,6 +1663,9 @@ gp_status xb_factor(Ctx *ctx, int l, hipStream_t s) {
     const double a = ctx->alpha / (G.h * G.h), d = 1.0 + 4.0 * a;
     k_xb_factor<<<G.nxb, XF_T, 0, s>>>(G.cls, G.W, G.h, a, d, G.xb_off, G.xb_ioff, G.xb_idx, G.g_rowof, G.g_col, G.g_w,
                                        G.xb_inv, G.xb_ok);
+    if (G.nxs)
+      k_xb_flat_write<<<nblk(G.nxs), TPB, 0, s>>>(G.xb_idx, G.xb_box, G.xb_off, G.xb_ioff, G.xb_wr, G.xb_ok, G.nxs,
+                                                   G.xb_uk, G.xb_uo, G.xb_ub, G.xb_um);
     GP_HIP(hipGetLastError());
   }
   G.xb_alpha = ctx->alpha;

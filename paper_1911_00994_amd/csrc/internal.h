@@ -101,6 +101,13 @@ struct Geo {
   int *xb_gcnt = nullptr, *xb_gtmp = nullptr, *xb_own = nullptr, *d_xb_co = nullptr;
   uint8_t *xb_wr = nullptr, *xb_ok = nullptr;
   double *xb_inv = nullptr, *xb_r = nullptr;
+  // the same tables flattened per slot, so a relaxation kernel reaches everything it needs in one dependent load:
+  // xb_gc / xb_gw the 9 columns and weights of a ghost slot's row (field-major, stride xb_scap; xb_gc[s] = -1 for
+  // an internal slot), and for the write phase (refreshed with the inverses) xb_uk the point a slot writes (-1: the
+  // box does not write it, or its block is singular), xb_uo the offset of its row of the inverse, xb_ub the box's
+  // first slot and xb_um the box's size
+  int *xb_gc = nullptr, *xb_uk = nullptr, *xb_uo = nullptr, *xb_ub = nullptr, *xb_um = nullptr;
+  double *xb_gw = nullptr;
   double xb_alpha = -1;
 };
 
@@ -229,6 +236,10 @@ struct Ctx {
   // generalized conjugate residual iteration around the cycle (finest-level vectors of n = 3 W^2 + 1 doubles):
   // the GCR workspace of gp_solve / gp_adjoint_solve (allocated at the first solve, gcr_alloc)
   GcrWs kr{};
+  // level-set reinitialisation (gp_reinit_levelset, allocated at its first call): two lattices of values, the
+  // interface distance estimates and the point codes, (2N+1)^2 each
+  double *rl_a = nullptr, *rl_b = nullptr, *rl_d = nullptr;
+  int8_t *rl_c = nullptr;
   // the geometry of a later time built in the background (gp_prepare_levelset_analytic) in a second context
   Ctx *shadow = nullptr;
   std::thread prep;
@@ -282,12 +293,16 @@ struct GcrOps {
   std::function<gp_status(double *rinf)> residual;
 };
 gp_status gcr_solve(Ctx *ctx, const GcrWs &ws, GcrOps &ops, double *x, double *r, double r0, double thr, double lim,
-                    int max_it, int *iters, double *res, double *rho, int *status);
+                    int max_it, int *iters, double *res, double *rho, int *status, double *kbytes);
+double cycle_bytes(const Ctx *ctx, bool fp32);
 gp_status gcr_alloc(Ctx *ctx);
 // the static scratch array of gp_solve_noalloc: its device address on the current device, taken once per device
 // (scratch_init, at context set-up), and the FP64 solve with the GCR workspace carved from it
 gp_status scratch_init(Ctx *ctx);
 gp_status mg_solve_noalloc(Ctx *ctx, double tol, int max_cycles, gp_stats *st);
+
+// level-set reinitialisation (levelset.hip)
+gp_status reinit_levelset(Ctx *ctx, double *phi, int on_device, int iters, double cfl);
 
 // adjoint (adjoint.hip)
 gp_status adjoint_alloc(Ctx *ctx);

@@ -328,9 +328,11 @@ __global__ void k_ghost_b(const int *__restrict__ pt, int ng, const double *__re
 // value the sweep reads comes from prev (colr gives ghost columns as -(row + 1)), so writing x in place is safe;
 // the arithmetic is that of k_ghost_a followed by k_ghost_b.
 template <typename T>
-__global__ void k_ghost_sweep2(const int *__restrict__ pt, const int *__restrict__ col, const int *__restrict__ colr,
-                               const double *__restrict__ w, const double *__restrict__ dtau, int ng, T *x,
-                               const T *__restrict__ b, const double *__restrict__ prev, double *__restrict__ next) {
+__global__ void __launch_bounds__(TPB) k_ghost_sweep2(const int *__restrict__ pt, const int *__restrict__ col,
+                                                      const int *__restrict__ colr, const double *__restrict__ w,
+                                                      const double *__restrict__ dtau, int ng, T *x,
+                                                      const T *__restrict__ b, const double *__restrict__ prev,
+                                                      double *__restrict__ next) {
   int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= ng) return;
   int k = pt[r];
@@ -717,34 +719,68 @@ __global__ void __launch_bounds__(BAND_T) k_xi_faces(int WW, double h, T *x, con
 // it owns go to out (by region index); workgroups S and on take the wall ghost rows.  k_band_sec_fin then moves
 // out into x and updates xi.  Nothing reads x while this kernel writes it: the sectors write out only.
 // lambda Jacobi sweeps of all ghost rows (eq. (ghostrelax)) and then xi from the boundary faces of the internal
-// cells, in one workgroup (levels without the extra band relaxation)
+// cells, in one workgroup (levels without the extra band relaxation, at most 2 BAND_T ghost rows).  Each thread
+// keeps the tables of its rows in registers for every sweep and its new values in registers between the read and
+// the write phase of a sweep; the face codes are loaded with the tables.
+constexpr int GX_F = 4;  // face codes per thread loaded ahead
 template <typename T>
 __global__ void __launch_bounds__(BAND_T) k_ghost_xi(const int *__restrict__ pt, const int *__restrict__ col,
                                                      const double *__restrict__ w, const double *__restrict__ dtau, int ng,
-                                                     T *x, const T *__restrict__ b, double *tmp, int sweeps, int WW,
-                                                     double h, const int *__restrict__ f_code, int nf,
+                                                     T *x, const T *__restrict__ b, int sweeps, int WW, double h,
+                                                     const int *__restrict__ f_code, int nf,
                                                      const double *__restrict__ gp, int ngp, const int *__restrict__ mp) {
+  const int tid = threadIdx.x;
+  const GpPre gpre = gp_start(gp, ngp);
+  int fc[GX_F];
+#pragma unroll
+  for (int j = 0; j < GX_F; j++) fc[j] = tid + j * BAND_T < nf ? f_code[tid + j * BAND_T] : 0;
+  // a thread without a second row computes a dummy one (point 0, weights 0) and does not store it, so that the
+  // loads of both rows go out together
+  int kk[2], cc[2][9];
+  double ww[2][9], dt[2];
+  bool has[2];
+#pragma unroll
+  for (int i = 0; i < 2; i++) {
+    const int r = tid + i * BAND_T;
+    has[i] = r < ng;
+    kk[i] = has[i] ? pt[r] : 0;
+    dt[i] = has[i] ? dtau[r] : 0.0;
+#pragma unroll
+    for (int z = 0; z < 9; z++) {
+      cc[i][z] = has[i] ? col[9 * r + z] : 0;
+      ww[i][z] = has[i] ? w[9 * r + z] : 0.0;
+    }
+  }
   for (int it = 0; it < sweeps; it++) {
-    for (int r = threadIdx.x; r < ng; r += BAND_T) {
-      const int k = pt[r];
+    double nv[2];
+#pragma unroll
+    for (int i = 0; i < 2; i++) {
       double s = 0;
 #pragma unroll
-      for (int q = 0; q < 9; q++) s += w[9 * r + q] * (double)x[col[9 * r + q]];
-      tmp[r] = (double)x[k] + dtau[r] * ((double)b[k] - s);
+      for (int z = 0; z < 9; z++) s += ww[i][z] * (double)x[cc[i][z]];
+      nv[i] = (double)x[kk[i]] + dt[i] * ((double)b[kk[i]] - s);
     }
     __syncthreads();
-    for (int r = threadIdx.x; r < ng; r += BAND_T) x[pt[r]] = (T)tmp[r];
+#pragma unroll
+    for (int i = 0; i < 2; i++)
+      if (has[i]) x[kk[i]] = (T)nv[i];
     __syncthreads();
   }
-  const GpPre gpre = gp_start(gp, ngp);
+  // faces (some are ghost points the sweeps wrote): the codes loaded ahead, then any beyond them
   double fs = 0;
-  for (int q = threadIdx.x; q < nf; q += BAND_T) {
+#pragma unroll
+  for (int j = 0; j < GX_F; j++)
+    if (tid + j * BAND_T < nf) {
+      const double v = (double)x[fc[j] >> 1];
+      fs += (fc[j] & 1) ? -v : v;
+    }
+  for (int q = tid + GX_F * BAND_T; q < nf; q += BAND_T) {
     const double v = (double)x[f_code[q] >> 1];
     fs += (f_code[q] & 1) ? -v : v;
   }
   fs = band_block_sum(fs);
   const double gsum = gp_total(gpre, gp, ngp);
-  if (threadIdx.x == 0) x[3 * WW] = (T)((fs / h - gsum) / *mp);
+  if (tid == 0) x[3 * WW] = (T)((fs / h - gsum) / *mp);
 }
 
 struct SecTabs {
@@ -1040,40 +1076,53 @@ __device__ __forceinline__ double resid_point(int W, double h, double a, double 
 // one colour never see each other's updates.
 // ---------------------------------------------------------------------------------------------------------
 struct XbTab {
-  const int *idx, *box, *off, *ioff;
-  const uint8_t *wr, *ok;
+  const int *idx;
   const double *inv;
-  const int *g_rowof, *g_col;
-  const double *g_w;
+  int S;                   // stride of the field-major row tables (the level's slot capacity)
+  const int *gc;           // 9 columns per ghost slot (gc[s] = -1: internal slot)
+  const double *gw;        // 9 weights per ghost slot
+  const int *uk, *uo, *ub, *um;  // write tables: target point (-1: none), inverse row, box's first slot, box size
 };
 static inline XbTab xb_tab(const Geo &G) {
-  return XbTab{G.xb_idx, G.xb_box, G.xb_off, G.xb_ioff, G.xb_wr, G.xb_ok, G.xb_inv, G.g_rowof, G.g_col, G.g_w};
+  return XbTab{G.xb_idx, G.xb_inv, G.xb_scap, G.xb_gc, G.xb_gw, G.xb_uk, G.xb_uo, G.xb_ub, G.xb_um};
 }
-// residual of the row of point k (internal row, or the ghost row of k)
+// residual of the row of slot s (its point's internal row, or the point's ghost row); every table entry it needs
+// is one load away from s
 template <typename T>
-__device__ __forceinline__ double xb_row_res(int W, double h, double a, double d, const uint8_t *__restrict__ cls,
-                                             const T *x, const T *b, const XbTab &X, int k) {
-  if (cls[k] == K_INT) return resid_point<T>(W, h, a, d, cls, x, b, k);
-  const int r = X.g_rowof[k];
+__device__ __forceinline__ double xb_slot_res(int W, double h, double a, double d, const T *x, const T *b,
+                                              const XbTab &X, int s) {
+  // every table entry of the slot at once (an internal slot's ghost entries are not used)
+  const int k = X.idx[s];
+  int c[9];
+  double w[9];
+#pragma unroll
+  for (int z = 0; z < 9; z++) {
+    c[z] = X.gc[(size_t)z * X.S + s];
+    w[z] = X.gw[(size_t)z * X.S + s];
+  }
+  if (c[0] < 0) {
+    const int g = k / (W * W);
+    if (g == 0) return resid_int<T, 0>(W, h, a, d, x, b, k);
+    if (g == 1) return resid_int<T, 1>(W, h, a, d, x, b, k);
+    return resid_int<T, 2>(W, h, a, d, x, b, k);
+  }
   double sw = 0;
 #pragma unroll
-  for (int z = 0; z < 9; z++) sw += X.g_w[9 * r + z] * (double)x[X.g_col[9 * r + z]];
+  for (int z = 0; z < 9; z++) sw += w[z] * (double)x[c[z]];
   return (double)b[k] - sw;
 }
 // the new value of slot s (when its box writes it): x + (row s of the inverse) . (the box's residuals), the
 // residual of slot q of the box at rs[q - rbase]
 template <typename T>
-__device__ __forceinline__ void xb_write(const XbTab &X, T *x, const double *rs, int rbase, int s) {
-  if (!X.wr[s]) return;
-  const int bx = X.box[s];
-  if (!X.ok[bx]) return;
-  const int o = X.off[bx], m = X.off[bx + 1] - o;
-  const double *iv = X.inv + X.ioff[bx] + (size_t)(s - o) * m;
-  const double *r = rs + (o - rbase);
+__device__ __forceinline__ void xb_slot_write(const XbTab &X, T *x, const double *rs, int rbase, int s) {
+  const int k = X.uk[s];
+  if (k < 0) return;
+  const int m = X.um[s];
+  const double *iv = X.inv + X.uo[s];
+  const double *r = rs + (X.ub[s] - rbase);
   double v = 0;
 #pragma unroll 8
   for (int c = 0; c < m; c++) v += iv[c] * r[c];
-  const int k = X.idx[s];
   x[k] = (T)((double)x[k] + v);
 }
 template <typename T>
@@ -1081,12 +1130,12 @@ __global__ void __launch_bounds__(TPB) k_xb_res(int lo, int hi, int W, double h,
                                                 const uint8_t *__restrict__ cls, const T *x, const T *b, XbTab X,
                                                 double *rs) {
   const int s = lo + blockIdx.x * blockDim.x + threadIdx.x;
-  if (s < hi) rs[s] = xb_row_res<T>(W, h, a, d, cls, x, b, X, X.idx[s]);
+  if (s < hi) rs[s] = xb_slot_res<T>(W, h, a, d, x, b, X, s);
 }
 template <typename T>
 __global__ void __launch_bounds__(TPB) k_xb_upd(int lo, int hi, T *x, XbTab X, const double *rs) {
   const int s = lo + blockIdx.x * blockDim.x + threadIdx.x;
-  if (s < hi) xb_write<T>(X, x, rs, 0, s);
+  if (s < hi) xb_slot_write<T>(X, x, rs, 0, s);
 }
 struct XbOff {
   int o[6];
@@ -1097,9 +1146,9 @@ template <typename T>
 __global__ void __launch_bounds__(XW_T) k_xb_wg(XbOff so, int W, double h, double a, double d,
                                                 const uint8_t *__restrict__ cls, T *x, const T *b, XbTab X, double *rs) {
   for (int c = 0; c < 5; c++) {
-    for (int s = so.o[c] + threadIdx.x; s < so.o[c + 1]; s += XW_T) rs[s] = xb_row_res<T>(W, h, a, d, cls, x, b, X, X.idx[s]);
+    for (int s = so.o[c] + threadIdx.x; s < so.o[c + 1]; s += XW_T) rs[s] = xb_slot_res<T>(W, h, a, d, x, b, X, s);
     __syncthreads();
-    for (int s = so.o[c] + threadIdx.x; s < so.o[c + 1]; s += XW_T) xb_write<T>(X, x, rs, 0, s);
+    for (int s = so.o[c] + threadIdx.x; s < so.o[c + 1]; s += XW_T) xb_slot_write<T>(X, x, rs, 0, s);
     __syncthreads();
   }
 }
@@ -1692,9 +1741,9 @@ __device__ void sc_relax(const SmallCycle &P, const SmallLevel &L, const ScRows 
   if (L.nxb)
     for (int c = 0; c < 5; c++) {
       for (int s = L.xso[c] + threadIdx.x; s < L.xso[c + 1]; s += SC_T)
-        xr[s - L.xso[c]] = xb_row_res<T>(L.W, L.h, L.a, L.d, cls, x, b, L.xb, L.xb.idx[s]);
+        xr[s - L.xso[c]] = xb_slot_res<T>(L.W, L.h, L.a, L.d, x, b, L.xb, s);
       __syncthreads();
-      for (int s = L.xso[c] + threadIdx.x; s < L.xso[c + 1]; s += SC_T) xb_write<T>(L.xb, x, xr, L.xso[c], s);
+      for (int s = L.xso[c] + threadIdx.x; s < L.xso[c + 1]; s += SC_T) xb_slot_write<T>(L.xb, x, xr, L.xso[c], s);
       __syncthreads();
     }
   sc_ghosts<T>(L, G, x, b, nv, P.lambda);
@@ -2039,13 +2088,13 @@ static void relax(Ctx *ctx, int l) {
   }
   if (!band && G.ng <= 2 * BAND_T) {
     // the ghost sweeps and xi in one workgroup (a few rows per thread)
-    k_ghost_xi<T><<<1, BAND_T, 0, s>>>(G.g_pt, G.g_col, G.g_w, G.g_dtau, G.ng, V.x, V.b, ctx->gtmp,
-                                      ctx->prm.lambda_ghost, G.WW, G.h, G.f_code, G.nf, ctx->gs_ptr[l], ctx->gs_n[l],
-                                      G.d_mp);
+    k_ghost_xi<T><<<1, BAND_T, 0, s>>>(G.g_pt, G.g_col, G.g_w, G.g_dtau, G.ng, V.x, V.b, ctx->prm.lambda_ghost, G.WW,
+                                      G.h, G.f_code, G.nf, ctx->gs_ptr[l], ctx->gs_n[l], G.d_mp);
     return;
   }
   if (!band && G.ng) {
     // many ghost rows: one device-wide launch per sweep (the sweeps between go through two row buffers), then xi
+    // (some of its faces are ghost points the last sweep writes)
     const int lam = ctx->prm.lambda_ghost;
     if (G.colr_ok) {
       double *buf[2] = {ctx->gtmp, ctx->gtmp2};
@@ -2225,6 +2274,22 @@ static void mean_project(Ctx *ctx) {
 // one also stores the norm there; wait_norm polls the slot, and now and then the stream, so that a failed launch
 // ends the wait (once the stream is idle the store has landed; else the device copy is read).
 constexpr unsigned long long NORM_PENDING = ~0ull;
+// algorithmic bytes of one cycle from the finest level (the compulsory traffic model of the kernels: per cell of a
+// level, 65 B per relaxation step in FP64 storage (33 in FP32), 53 B (27) for the residual with the restriction and
+// the prolongation; a level below is visited gamma times as often on a quarter of the cells) and of one residual
+// norm (41 B per cell)
+double cycle_bytes(const Ctx *ctx, bool fp32) {
+  const double step = fp32 ? 33.0 : 65.0, tr = fp32 ? 27.0 : 53.0;
+  double b = 0, wgt = 1;
+  for (int l = 0; l + 1 < ctx->L; l++) {
+    const double cells = (double)ctx->geo[l].N * ctx->geo[l].N;
+    b += wgt * cells * ((ctx->prm.nu1 + ctx->prm.nu2) * step + tr);
+    wgt *= (l + 2 == ctx->L) ? 1.0 : (double)ctx->prm.gamma;
+  }
+  return b;
+}
+static double norm_bytes(const Ctx *ctx) { return 41.0 * ctx->geo[0].N * ctx->geo[0].N; }
+
 static void norm_launch(Ctx *ctx, bool store = true) {
   __atomic_store_n(ctx->h_rmax, NORM_PENDING, __ATOMIC_RELEASE);
   residual<double>(ctx, 0, (unsigned long long *)(ctx->d_scal + 1), ctx->h_rmax, store);
@@ -2634,10 +2699,38 @@ __global__ void __launch_bounds__(GR_B) k_gcr_max(const double *__restrict__ par
   }
 }
 // preconditioner input: z = 0 except at the wall Dirichlet rows, where the cycle's x equals its right-hand side
-__global__ void k_pc_in(const uint8_t *__restrict__ cls, long n, const double *__restrict__ r, double *z) {
-  const long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
-  if (t >= n) return;
-  z[t] = (t < n - 1 && cls[t] == K_WALLD) ? r[t] : 0.0;
+// r; and, for the xi updates of the cycle, G = the sum over the internal cells of the continuity right-hand sides
+// less the wall Dirichlet faces' share (as k_gsum forms it from x = z and b = r), as PC_B block partials in part.
+// Thread t of the grid-stride loop covers the three grid entries at t (and the xi entry, t = 0) and cell t.
+constexpr int PC_B = 256, PC_T = 1024;
+__global__ void __launch_bounds__(PC_T) k_pc_in(const uint8_t *__restrict__ cls, int W, double h,
+                                                const double *__restrict__ r, double *z, double *part) {
+  __shared__ double sm[PC_T / 64];
+  const int WW = W * W;
+  double s = 0;
+  for (int t = blockIdx.x * PC_T + threadIdx.x; t < WW; t += PC_B * PC_T) {
+    const uint8_t cu = cls[t], cv = cls[WW + t], cp = cls[2 * WW + t];
+    z[t] = cu == K_WALLD ? r[t] : 0.0;
+    z[WW + t] = cv == K_WALLD ? r[WW + t] : 0.0;
+    z[2 * WW + t] = cp == K_WALLD ? r[2 * WW + t] : 0.0;
+    if (t == 0) z[3 * WW] = 0.0;
+    if (cp == K_INT) {
+      double wf = 0;
+      if (cls[t + 1] == K_WALLD) wf += r[t + 1];
+      if (cu == K_WALLD) wf -= r[t];
+      if (cls[WW + t + W] == K_WALLD) wf += r[WW + t + W];
+      if (cv == K_WALLD) wf -= r[WW + t];
+      s += r[2 * WW + t] - wf / h;
+    }
+  }
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+  if ((threadIdx.x & 63) == 0) sm[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0;
+    for (int q = 0; q < PC_T / 64; q++) t += sm[q];
+    part[blockIdx.x] = t;
+  }
 }
 // preconditioner output (FP64, in place): the pressure unknowns shifted by -mean + (mean-row entry of r), which is
 // the cycle's mean projection followed by the mean-row column of B' (a constant pressure changes no other row)
@@ -2673,7 +2766,7 @@ gp_status gcr_alloc(Ctx *ctx) {
 }
 
 gp_status gcr_solve(Ctx *ctx, const GcrWs &ws, GcrOps &ops, double *x, double *r, double r0, double thr, double lim,
-                    int max_it, int *iters, double *res, double *rho, int *status) {
+                    int max_it, int *iters, double *res, double *rho, int *status, double *kbytes) {
   hipStream_t s = ctx->stream;
   const long n = ctx->geo[0].n;
   const int m = ws.m;
@@ -2683,6 +2776,7 @@ gp_status gcr_solve(Ctx *ctx, const GcrWs &ws, GcrOps &ops, double *x, double *r
   gp_status st = GP_OK;
   *status = GP_OK;
   *rho = 0;
+  double kb = 0;
   while (rn > thr && c < max_it) {
     double *z = ws.z, *qn = ctx->v64[0].r;
     double *Qk = ws.Q + (size_t)k * n, *Zk = ws.Z + (size_t)k * n;
@@ -2699,6 +2793,7 @@ gp_status gcr_solve(Ctx *ctx, const GcrWs &ws, GcrOps &ops, double *x, double *r
     k_gcr_max<<<1, GR_B, 0, s>>>(ws.part, (unsigned long long *)(ctx->d_scal + 1), ctx->h_rmax);
     GP_HIP(hipGetLastError());
     if ((st = wait_norm(ctx, &rn))) return st;
+    kb += (3.0 * k + 12.0) * 8.0 * (double)n;
     c++;
     k++;
     if (!(rn == rn) || rn > lim) {
@@ -2714,6 +2809,7 @@ gp_status gcr_solve(Ctx *ctx, const GcrWs &ws, GcrOps &ops, double *x, double *r
   }
   *iters = c;
   *res = rn;
+  if (kbytes) *kbytes = kb;
   return GP_OK;
 }
 
@@ -2758,8 +2854,11 @@ static gp_status gcr_mg_solve(Ctx *ctx, const GcrWs &ws, int precision, double t
       double *Y0 = V.y;
       V.x = z;
       V.b = const_cast<double *>(r);
-      k_pc_in<<<nblk(n), TPB, 0, s>>>(G.cls, n, r, z);
-      gsum<double>(ctx, 0);
+      // z and the finest level's G (block partials in the workspace's reduction slots, which the GCR kernels
+      // only use after the cycle)
+      k_pc_in<<<PC_B, PC_T, 0, s>>>(G.cls, G.W, G.h, r, z, ws.part);
+      ctx->gs_ptr[0] = ws.part;
+      ctx->gs_n[0] = PC_B;
       cycle<double>(ctx, 0);
       if (V.x != z) {  // an odd number of finest sweeps leaves the result in the second buffer
         (void)hipMemcpyAsync(z, V.x, n * sizeof(double), hipMemcpyDeviceToDevice, s);
@@ -2799,7 +2898,8 @@ static gp_status gcr_mg_solve(Ctx *ctx, const GcrWs &ws, int precision, double t
   };
   int iters = 0, status = GP_OK;
   double res = r0, rho = 0;
-  st = gcr_solve(ctx, ws, ops, X0, ws.r, r0, thr, lim, max_cycles, &iters, &res, &rho, &status);
+  double kb = 0;
+  st = gcr_solve(ctx, ws, ops, X0, ws.r, r0, thr, lim, max_cycles, &iters, &res, &rho, &status, &kb);
   V.x = X0;
   V.b = B0;
   if (st) return st;
@@ -2808,6 +2908,7 @@ static gp_status gcr_mg_solve(Ctx *ctx, const GcrWs &ws, int precision, double t
   ctx->last_cycles = iters;
   if (stt) {
     stt->cycles = iters;
+    stt->bytes_alg = iters * (cycle_bytes(ctx, precision != GP_FP64) + norm_bytes(ctx)) + kb;
     stt->outer = 0;
     stt->res0 = r0;
     stt->res = res;
@@ -2903,6 +3004,7 @@ static gp_status plain_mg_solve(Ctx *ctx, int precision, double tol, int max_cyc
   ctx->last_cycles = c;
   if (stt) {
     stt->cycles = c;
+    stt->bytes_alg = c * (cycle_bytes(ctx, precision != GP_FP64) + norm_bytes(ctx));
     stt->outer = outer;
     stt->res0 = r0;
     stt->res = r;

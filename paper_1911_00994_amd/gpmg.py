@@ -21,6 +21,7 @@ GP_FP64, GP_MIXED = 0, 1
 EXPORTS = [
     "gp_default_params", "gp_setup_grid", "gp_destroy", "gp_num_levels", "gp_strerror", "gp_last_hip_error",
     "gp_set_levelset", "gp_set_levelset_analytic", "gp_prepare_levelset_analytic", "gp_set_walls",
+    "gp_reinit_levelset",
     "gp_get_boundary_geometry",
     "gp_set_boundary_values", "gp_set_alpha", "gp_set_rhs", "gp_set_x", "gp_get_x", "gp_mg_vcycle", "gp_solve", "gp_solve_noalloc",
     "gp_residual", "gp_set_state", "gp_cn_step", "gp_get_classes", "gp_get_ghost_rows", "gp_get_ext_rows",
@@ -53,7 +54,7 @@ class GpShape(ctypes.Structure):
 
 class GpStats(ctypes.Structure):
     _fields_ = [("cycles", ctypes.c_int), ("outer", ctypes.c_int), ("res0", ctypes.c_double), ("res", ctypes.c_double),
-                ("rho", ctypes.c_double), ("seconds", ctypes.c_double)]
+                ("rho", ctypes.c_double), ("seconds", ctypes.c_double), ("bytes_alg", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -92,6 +93,7 @@ def lib():
         "gp_set_levelset_analytic": (i, [vp, ctypes.POINTER(GpShape), d, ctypes.POINTER(GpRigid)]),
         "gp_prepare_levelset_analytic": (i, [vp, ctypes.POINTER(GpShape), d, ctypes.POINTER(GpRigid)]),
         "gp_set_walls": (i, [vp, vp]),
+        "gp_reinit_levelset": (i, [vp, vp, i, i, d]),
         "gp_get_boundary_geometry": (i, [vp, vp, vp]),
         "gp_set_boundary_values": (i, [vp, vp, vp, vp, i]),
         "gp_set_alpha": (i, [vp, d]),
@@ -204,6 +206,16 @@ class Solver:
         m = None if motion is None else GpRigid(*[float(v) for v in list(motion)[:5]])
         st = lib().gp_prepare_levelset_analytic(self._h, ctypes.byref(sh), t, ctypes.byref(m) if m else None)
         self._check(st, "gp_prepare_levelset_analytic")
+
+    def reinit_levelset(self, phi, iters, cfl=0.3, on_device=False):
+        """gp_reinit_levelset: returns the reinitialised lattice (host arrays) or updates the device buffer in place
+        (on_device: phi is a device pointer)"""
+        if on_device:
+            self._check(lib().gp_reinit_levelset(self._h, ctypes.c_void_p(phi), 1, iters, cfl), "gp_reinit_levelset")
+            return phi
+        a = _host(phi).copy()
+        self._check(lib().gp_reinit_levelset(self._h, _ptr(a), 0, iters, cfl), "gp_reinit_levelset")
+        return a
 
     def set_walls(self, walls):
         self._check(lib().gp_set_walls(self._h, _ptr(_host(walls))), "gp_set_walls")

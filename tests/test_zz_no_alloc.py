@@ -90,7 +90,7 @@ def test_noalloc_plain_cycle_any_size_and_refusal():
     s.close()
     assert st == st2 and info["cycles"] == info2["cycles"], (st, st2, info, info2)
     assert np.array_equal(a, b)
-    say("[noalloc] N=512 krylov=16: refused (workspace beyond the static array)")
+    say("[noalloc] N=512, default krylov = 8: refused (workspace beyond the static array)")
     s = _problem(gpmg, 512)
     st3, _ = s.solve_noalloc(1e-9, 80, check=False)
     msg = gpmg.lib().gp_last_hip_error(s._h).decode()
