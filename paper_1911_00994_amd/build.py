@@ -18,8 +18,8 @@ ARCH = os.environ.get("GPMG_ARCH", "gfx950")
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang",
           "-packed-fp32-ops", "-Wall", "-Wno-unused-function"]
-PER_FILE = {"geom.hip": ["-ffp-contract=off"], "levelset.hip": ["-ffp-contract=off"]}
-SOURCES = ["geom.hip", "mg.hip", "cn.hip", "adjoint.hip", "levelset.hip", "api.hip"]
+PER_FILE = {"geom.hip": ["-ffp-contract=off"], "levelset.hip": ["-ffp-contract=off"], "mg3d.hip": ["-ffp-contract=off"]}
+SOURCES = ["geom.hip", "mg.hip", "cn.hip", "adjoint.hip", "levelset.hip", "mg3d.hip", "api.hip"]
 
 
 def hipcc() -> str:

@@ -8,13 +8,14 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "gpmg.h")
+HEADER3 = os.path.join(ROOT, "include", "gpmg3.h")
 LIB = os.path.join(ROOT, "paper_1911_00994_amd", "libgpmg.so")
 
 
-def declared_functions():
-    src = open(HEADER).read()
+def declared_functions(header=HEADER):
+    src = open(header).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    names = re.findall(r"^\s*(?:const\s+)?[a-z_]+\s*\*?\s*(gp_[a-z_0-9]+)\s*\(", src, flags=re.M)
+    names = re.findall(r"^\s*(?:const\s+)?[a-z_]+\s*\*?\s*(gp3?_[a-z_0-9]+)\s*\(", src, flags=re.M)
     return sorted(set(names))
 
 
@@ -29,13 +30,14 @@ def test_library_exports_every_declared_symbol():
         from paper_1911_00994_amd import build
         build.build()
     lib = ctypes.CDLL(LIB)
-    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    missing = [n for h in (HEADER, HEADER3) for n in declared_functions(h) if not hasattr(lib, n)]
     assert not missing, missing
 
 
 def test_binding_covers_the_header():
-    from paper_1911_00994_amd import gpmg
+    from paper_1911_00994_amd import gpmg, gpmg3
     assert sorted(gpmg.EXPORTS) == declared_functions()
+    assert sorted(gpmg3.EXPORTS) == declared_functions(HEADER3)
 
 
 def test_binding_fails_loudly_without_library(tmp_path, monkeypatch):
