@@ -1,6 +1,7 @@
 """Accuracy runs of Sect. 5.1 on the HIP path: the manufactured solution of eq. (sol:exa) on the three bodies of
 eq. (domains) (circle, ellipse, five-petal flower), at rest or rotating about the origin with omega = 2 pi / 5,
-Re = 100, dt = h, from the exact fields at t = 0 to a final time T (the paper's tables use T = 10).
+Re = 100, from the exact fields at t = 0 to a final time T (the paper's tables use T = 10), with the paper's step
+bound dt <= min(h, h / max |u|): |u_exa| <= sqrt(2), so dt = T / ceil(sqrt(2) T / h).
 
 Reported per run: the max-norm and L1 errors (L1 = mean over the internal points, reading c19) of u and v at T
 against the exact fields, and the divergence error |div_h u - g| = |xi| (the continuity rows make div_h u - g the
@@ -44,12 +45,13 @@ def run(N: int, shape: wl.Shape, omega: float, T: float, Re: float = 100.0, tol:
     """One run; returns the errors at the final time and the step count."""
     m = wl.PaperMMS()
     h = 2.0 / N
-    dt = h
-    steps = int(round(T / dt))
+    steps = int(math.ceil(math.sqrt(2.0) * T / h - 1e-9))
+    dt = T / steps
     mo = np.array([0.0, 0.0, 0.0, 0.0, omega])
     moving = omega != 0.0
     s = gpmg.Solver(N, Re=Re)
     t0 = time.perf_counter()
+    n, t1 = 0, 0.0
     try:
         s.set_levelset_analytic(shape.kind, shape.params, 0.0, mo)
         u0, v0, p0 = wl.mms_fields(m, N, 0.0)
@@ -74,9 +76,9 @@ def run(N: int, shape: wl.Shape, omega: float, T: float, Re: float = 100.0, tol:
             fu, _ = m.forcing(xu, yu, th, Re)
             _, fv = m.forcing(xv, yv, th, Re)
             st, info = s.cn_step(dt, fu, fv, m.div(xp, yp, t1), tol=tol, max_cycles=200, picard_eps=1e-10,
-                                 picard_max=40)
+                                 picard_max=40, check=False)
             if st != gpmg.GP_OK:
-                raise RuntimeError(f"step {n} (t = {t1}): status {st}, {info}")
+                return {"N": N, "steps": steps, "failed_step": n, "T": t1, "status": st, "info": info}
             cycles += info["cycles"]
             t = t1
             if log and (n + 1) % max(1, steps // 4) == 0:
@@ -85,6 +87,8 @@ def run(N: int, shape: wl.Shape, omega: float, T: float, Re: float = 100.0, tol:
         cls = s.classes()
         eu = np.abs(u - m.u(xu, yu, t))[cls[0] == 1]
         ev = np.abs(v - m.v(xv, yv, t))[cls[1] == 1]
+    except gpmg.GpmgError as e:  # a geometry the library rejects (a body too thin for the grid)
+        return {"N": N, "steps": steps, "failed_step": n, "T": t1, "status": e.status, "info": str(e)}
     finally:
         s.close()
     return {"N": N, "steps": steps, "T": t, "cycles": cycles, "seconds": time.perf_counter() - t0,
@@ -94,6 +98,13 @@ def run(N: int, shape: wl.Shape, omega: float, T: float, Re: float = 100.0, tol:
 
 def bodies():
     return {"circle": wl.paper_circle(), "ellipse": wl.paper_ellipse(), "flower": wl.paper_flower()}
+
+
+def summary(q) -> str:
+    if "failed_step" in q:
+        return f"N={q['N']}: status {q['status']} at step {q['failed_step']} (t = {q['T']:.3f})"
+    return (f"N={q['N']}: L1 u {q['L1_u']:.3e} v {q['L1_v']:.3e}  Linf u {q['Linf_u']:.3e} v {q['Linf_v']:.3e}  "
+            f"div {q['div']:.3e}  {q['cycles'] / q['steps']:.1f} cycles/step, {q['seconds']:.1f} s")
 
 
 def table(Ns, T, body_names=("circle", "ellipse", "flower"), omegas=(0.0, 2.0 * math.pi / 5.0), log=None):
@@ -106,7 +117,11 @@ def table(Ns, T, body_names=("circle", "ellipse", "flower"), omegas=(0.0, 2.0 * 
                 if log:
                     log(f"[accuracy] {name} omega={om:.4f} N={N} T={T}")
                 runs.append(run(N, sh, om, T, log=log))
+                if log:
+                    log("  " + summary(runs[-1]))
             for a, b in zip(runs, runs[1:]):
+                if "failed_step" in a or "failed_step" in b:
+                    continue
                 for k in ("Linf_u", "Linf_v", "L1_u", "L1_v", "div"):
                     b["order_" + k] = math.log2(a[k] / b[k]) if b[k] > 0 and a[k] > 0 else None
             out.append({"body": name, "omega": om, "runs": runs})
@@ -118,6 +133,10 @@ def markdown(rows) -> str:
              "|---|---|---|---|---|---|---|---|---|---|---|"]
     for r in rows:
         for q in r["runs"]:
+            if "failed_step" in q:
+                lines.append(f"| {r['body']} | {r['omega']:.4f} | {q['N']} | status {q['status']} at step "
+                             f"{q['failed_step']} (t = {q['T']:.3f}) | | | | | | | |")
+                continue
             o1 = f"{q['order_L1_u']:.2f} / {q['order_L1_v']:.2f}" if "order_L1_u" in q else ""
             o2 = f"{q['order_Linf_u']:.2f} / {q['order_Linf_v']:.2f}" if "order_Linf_u" in q else ""
             lines.append(f"| {r['body']} | {r['omega']:.4f} | {q['N']} | {q['L1_u']:.2e} | {q['L1_v']:.2e} | "
@@ -131,13 +150,15 @@ def main():
     ap.add_argument("--T", type=float, default=10.0)
     ap.add_argument("--N", type=int, nargs="+", default=[64, 128, 256])
     ap.add_argument("--bodies", nargs="+", default=["circle", "ellipse", "flower"])
+    ap.add_argument("--motion", choices=["both", "steady", "moving"], default="both")
     ap.add_argument("--json", default=None)
     a = ap.parse_args()
+    om = {"both": (0.0, 2.0 * math.pi / 5.0), "steady": (0.0,), "moving": (2.0 * math.pi / 5.0,)}[a.motion]
 
     def log(msg):
         print(msg, flush=True)
 
-    rows = table(a.N, a.T, a.bodies, log=log)
+    rows = table(a.N, a.T, a.bodies, om, log=log)
     print(markdown(rows), flush=True)
     if a.json:
         with open(a.json, "w") as f:
