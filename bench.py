@@ -189,10 +189,13 @@ def adjoint_run(gpmg, wl, N=512, steps=40, K=8, tol=1e-8):
     t2 = time.perf_counter()
     out = s.tape_backward(seed_u, seed_v, tol=tol, max_cycles=300)
     t3 = time.perf_counter()
+    gpath, unmatched = s.tape_path_gradient()
     return {"workload": wk.name, "N": N, "steps": steps, "checkpoint_every": K, "tol": tol, "J": J,
             "forward_ms": 1000 * (t1 - t0), "forward_cycles": fwd["cycles"], "backward_ms": 1000 * (t3 - t2),
             "adjoint_cycles": out["stats"]["cycles"], "adjoint_solves": out["stats"]["outer"],
             "backward_over_forward": (t3 - t2) / (t1 - t0), "dJdU": [float(x) for x in out["dU"]],
+            "dJdU_path": [float(x) for x in gpath], "dJdU_total": [float(a + b) for a, b in zip(out["dU"], gpath)],
+            "path_rows_unmatched": unmatched,
             "grad_forcing_inf": float(max(np.abs(out["dfu"]).max(), np.abs(out["dfv"]).max()))}
 
 

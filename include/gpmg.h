@@ -305,6 +305,17 @@ gp_status gp_tape_backward(gp_ctx *ctx, const double *seed_u, const double *seed
                            int max_cycles, double *dJdfu, double *dJdfv, double *dJdU, double *dJdu0, double *dJdv0,
                            gp_stats *st);
 
+/* The part of dJ/dU that comes through the body path, for the last gp_tape_backward on this context.  The motion's
+ * U moves the body, X(t) = X0 + U t, and with it the boundary points, the eq. (BCu) rows (Sect. 3.3) and the
+ * boundary data u_b = U + omega x (B - X) of every step's geometry; with the discrete decisions of each geometry
+ * held fixed (classes, ghost points, upwind stencils, the number of Alg. 1 march steps and its bisection branches)
+ * these are smooth in X, and the reverse pass adds, per step n, t_{n+1} times the sum over the finest body ghost
+ * rows of lam_G d(b_G - M_G x^{n+1})/dX.  The total dJ/dU of the motion's velocity is dJdU (gp_tape_backward: the
+ * direct dependence of u_b on U, as for the offset) plus dJdU_path (host [2]).  *unmatched (may be NULL) counts
+ * rows whose recorded Alg. 1 path did not reproduce the stored boundary point (0 when the derivative is complete).
+ * Errors: GP_EINVAL without a taped run. */
+gp_status gp_tape_path_gradient(gp_ctx *ctx, double *dJdU_path, int *unmatched);
+
 #ifdef __cplusplus
 }
 #endif

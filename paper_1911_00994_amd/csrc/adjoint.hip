@@ -105,15 +105,18 @@ __global__ void k_mt_pts(int N, int W, double h, double a, double d, const uint8
   }
   y[t] = base[t] + sgn * s;
 }
-// ghost rows: y[col] += sgn * w * lam_G
-__global__ void k_mt_ghost(const int *__restrict__ pt, const int *__restrict__ col, const double *__restrict__ w, int ng,
-                           const double *__restrict__ lam, double sgn, double *y) {
-  int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= ng) return;
-  double lg = sgn * lam[pt[r]];
-  if (lg == 0.0) return;
-#pragma unroll
-  for (int z = 0; z < 9; z++) atomicAdd(&y[col[9 * r + z]], w[9 * r + z] * lg);
+// ghost rows: y[col] += sgn * w * lam_G, gathered per column from the ghost-row table
+__global__ void k_gt_mt(const int *__restrict__ tl, const int *__restrict__ off, const int *__restrict__ ent,
+                        const int *__restrict__ nt, const int *__restrict__ pt, const double *__restrict__ w,
+                        const double *__restrict__ lam, double sgn, double *y) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= *nt) return;
+  double acc = 0;
+  for (int q = off[s]; q < off[s + 1]; q++) {
+    const int e = ent[q];
+    acc += w[e] * (sgn * lam[pt[e / 9]]);
+  }
+  y[tl[s]] += acc;
 }
 // xi column: -1 in every internal continuity row
 __global__ void __launch_bounds__(TPB) k_mt_xi(int W, const uint8_t *__restrict__ cls, const double *__restrict__ lam,
@@ -128,16 +131,21 @@ __global__ void __launch_bounds__(TPB) k_mt_xi(int W, const uint8_t *__restrict_
 
 // ---------------------------------------------------------------------------------------------------------
 // transposed box colour.  Free unknowns F of the box (internal ones); s = A_F^{-T} y solved as S A_F^{-1} S y
-// with the closed form of the forward box solve (fixed unknowns enter with zero); then bbar_F += s, xbar_F = 0
-// and xbar_k -= M_{F,k} s over the columns outside F (atomics: same-colour boxes share read-only neighbours,
-// never unknowns).  The xi column collects sum of s_P (grid sum, added to xbar_xi by the last block).
+// with the closed form of the forward box solve (fixed unknowns enter with zero); then bbar_F += s, xbar_F = 0,
+// and the box's five values go to S (zero for fixed unknowns).  k_box_adj_g then forms xbar_k -= M_{F,k} s for the
+// columns outside F as a gather: every point adds, in a fixed order, the terms of the colour's boxes whose rows
+// reference it (same-colour boxes share read-only neighbours, never unknowns, so an unknown of F gathers nothing).
+// The xi column collects sum of s_P (grid sum, added to xbar_xi by the last block).
 // ---------------------------------------------------------------------------------------------------------
 __device__ __forceinline__ double box_adj(int N, int W, double h, double a, double d, const uint8_t *__restrict__ cls,
-                                          double *xb, double *bb, int i, int j) {
+                                          double *xb, double *bb, double *S, int i, int j) {
   const int WW = W * W, c = (j + 1) * W + (i + 1);
   const bool fW = cls[c] == K_INT, fE = cls[c + 1] == K_INT, fS = cls[WW + c] == K_INT, fN = cls[WW + c + W] == K_INT,
              fP = cls[2 * WW + c] == K_INT;
-  if (!(fW || fE || fS || fN || fP)) return 0.0;
+  if (!(fW || fE || fS || fN || fP)) {
+    for (int f = 0; f < 5; f++) S[f * WW + c] = 0.0;
+    return 0.0;
+  }
   const double ih = 1.0 / h, det = d * d - a * a;
   // right-hand side S y
   const double rW = fW ? xb[c] : 0.0, rE = fE ? xb[c + 1] : 0.0, rS = fS ? xb[WW + c] : 0.0, rN = fN ? xb[WW + c + W] : 0.0,
@@ -170,67 +178,46 @@ __device__ __forceinline__ double box_adj(int N, int W, double h, double a, doub
   double zP = 0;
   if (fP) {
     const double den = bE - bW + bN - bS;
-    if (den == 0.0) return 0.0;  // the forward sweep skips this box
+    if (den == 0.0) {  // the forward sweep skips this box
+      for (int f = 0; f < 5; f++) S[f * WW + c] = 0.0;
+      return 0.0;
+    }
     zP = (h * rP - (aE - aW + aN - aS)) / den;
   }
   const double sW = fW ? aW + bW * zP : 0.0, sE = fE ? aE + bE * zP : 0.0, sS = fS ? aS + bS * zP : 0.0,
                sN = fN ? aN + bN * zP : 0.0, sP = fP ? -zP : 0.0;
-  double *xu = xb, *xv = xb + WW, *xp = xb + 2 * WW;
   if (fW) {
     bb[c] += sW;
-    xu[c] = 0;
-    atomicAdd(&xu[c - 1], a * sW);
-    atomicAdd(&xu[c - W], a * sW);
-    atomicAdd(&xu[c + W], a * sW);
-    if (!fE) atomicAdd(&xu[c + 1], a * sW);
-    atomicAdd(&xp[c - 1], ih * sW);
-    if (!fP) atomicAdd(&xp[c], -ih * sW);
+    xb[c] = 0;
   }
   if (fE) {
     bb[c + 1] += sE;
-    xu[c + 1] = 0;
-    atomicAdd(&xu[c + 2], a * sE);
-    atomicAdd(&xu[c + 1 - W], a * sE);
-    atomicAdd(&xu[c + 1 + W], a * sE);
-    if (!fW) atomicAdd(&xu[c], a * sE);
-    atomicAdd(&xp[c + 1], -ih * sE);
-    if (!fP) atomicAdd(&xp[c], ih * sE);
+    xb[c + 1] = 0;
   }
   if (fS) {
     bb[WW + c] += sS;
-    xv[c] = 0;
-    atomicAdd(&xv[c - W], a * sS);
-    atomicAdd(&xv[c - 1], a * sS);
-    atomicAdd(&xv[c + 1], a * sS);
-    if (!fN) atomicAdd(&xv[c + W], a * sS);
-    atomicAdd(&xp[c - W], ih * sS);
-    if (!fP) atomicAdd(&xp[c], -ih * sS);
+    xb[WW + c] = 0;
   }
   if (fN) {
     bb[WW + c + W] += sN;
-    xv[c + W] = 0;
-    atomicAdd(&xv[c + 2 * W], a * sN);
-    atomicAdd(&xv[c + W - 1], a * sN);
-    atomicAdd(&xv[c + W + 1], a * sN);
-    if (!fS) atomicAdd(&xv[c], a * sN);
-    atomicAdd(&xp[c + W], -ih * sN);
-    if (!fP) atomicAdd(&xp[c], ih * sN);
+    xb[WW + c + W] = 0;
   }
   if (fP) {
     bb[2 * WW + c] += sP;
-    xp[c] = 0;
-    if (!fE) atomicAdd(&xu[c + 1], -ih * sP);
-    if (!fW) atomicAdd(&xu[c], ih * sP);
-    if (!fN) atomicAdd(&xv[c + W], -ih * sP);
-    if (!fS) atomicAdd(&xv[c], ih * sP);
+    xb[2 * WW + c] = 0;
   }
+  S[c] = sW;
+  S[WW + c] = sE;
+  S[2 * WW + c] = sS;
+  S[3 * WW + c] = sN;
+  S[4 * WW + c] = sP;
   (void)N;
   return sP;
 }
 // one colour over all cells (list == nullptr) or over the band cells list[lo, hi)
 __global__ void __launch_bounds__(TPB) k_box_adj(int N, int W, double h, double a, double d, const uint8_t *__restrict__ cls,
-                                                 double *xb, double *bb, int colour, const int *__restrict__ list, int lo,
-                                                 int hi, double *part, unsigned *ticket) {
+                                                 double *xb, double *bb, double *S, int colour, const int *__restrict__ list,
+                                                 int lo, int hi, double *part, unsigned *ticket) {
   const int K = N / 5 + 1;
   const long total = list ? (long)(hi - lo) : (long)K * N;
   double sp = 0;
@@ -246,10 +233,72 @@ __global__ void __launch_bounds__(TPB) k_box_adj(int N, int W, double h, double 
       i = ((colour - 2 * j) % 5 + 5) % 5 + 5 * kk;
       if (i >= N) continue;
     }
-    sp += box_adj(N, W, h, a, d, cls, xb, bb, i, j);
+    sp += box_adj(N, W, h, a, d, cls, xb, bb, S, i, j);
   }
   double tot;
   if (alast_total(sp, part, ticket, &tot) && threadIdx.x == 0) xb[3 * W * W] += tot;
+}
+
+// the scatter of the transposed box colour as a gather.  A box at cell c with values sW, sE, sS, sN, sP (its W, E,
+// S, N faces and pressure) adds to the points c + o of the terms below (coefficient, and a condition on the box's
+// own unknowns where a face or the pressure is a fixed unknown of the box); point q gathers them from the boxes
+// c = q - o of the colour.
+//   u:  sW a at -1, -W, +W and at +1 (E fixed);  sE a at +2, +1-W, +1+W and at 0 (W fixed);
+//       sP -1/h at +1 (E fixed), +1/h at 0 (W fixed)
+//   v:  sS a at -W, -1, +1 and at +W (N fixed);  sN a at +2W, +W-1, +W+1 and at 0 (S fixed);
+//       sP -1/h at +W (N fixed), +1/h at 0 (S fixed)
+//   p:  sW +1/h at -1, -1/h at 0 (P fixed);  sE -1/h at +1, +1/h at 0 (P fixed);  sS +1/h at -W, -1/h at 0 (P fixed);
+//       sN -1/h at +W, +1/h at 0 (P fixed)
+__global__ void __launch_bounds__(TPB) k_box_adj_g(int N, int W, double h, double a, const uint8_t *__restrict__ cls,
+                                                   const double *__restrict__ S, int colour, double *xb) {
+  const int WW = W * W;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= 3 * WW) return;
+  const int g = t / WW, q = t - g * WW;
+  const double ih = 1.0 / h;
+  const double *sW = S, *sE = S + WW, *sS = S + 2 * WW, *sN = S + 3 * WW, *sP = S + 4 * WW;
+  // the box at cell index c, if it is a cell of the grid and of this colour
+  auto box = [&](int c) {
+    if (c < 0 || c >= WW) return false;
+    const int i = c % W - 1, j = c / W - 1;
+    return i >= 0 && i < N && j >= 0 && j < N && (i + 2 * j) % 5 == colour;
+  };
+  auto fixed = [&](int k) { return cls[k] != K_INT; };
+  double acc = 0;
+  if (g == 0) {
+    if (box(q + 1)) acc += a * sW[q + 1];
+    if (box(q + W)) acc += a * sW[q + W];
+    if (box(q - W)) acc += a * sW[q - W];
+    if (box(q - 1) && fixed(q)) acc += a * sW[q - 1];  // E face of box q - 1 is q
+    if (box(q - 2)) acc += a * sE[q - 2];
+    if (box(q - 1 + W)) acc += a * sE[q - 1 + W];
+    if (box(q - 1 - W)) acc += a * sE[q - 1 - W];
+    if (box(q) && fixed(q)) acc += a * sE[q];  // W face of box q is q
+    if (box(q - 1) && fixed(q)) acc += -ih * sP[q - 1];
+    if (box(q) && fixed(q)) acc += ih * sP[q];
+  } else if (g == 1) {
+    if (box(q + W)) acc += a * sS[q + W];
+    if (box(q + 1)) acc += a * sS[q + 1];
+    if (box(q - 1)) acc += a * sS[q - 1];
+    if (box(q - W) && fixed(WW + q)) acc += a * sS[q - W];  // N face of box q - W is q
+    if (box(q - 2 * W)) acc += a * sN[q - 2 * W];
+    if (box(q - W + 1)) acc += a * sN[q - W + 1];
+    if (box(q - W - 1)) acc += a * sN[q - W - 1];
+    if (box(q) && fixed(WW + q)) acc += a * sN[q];  // S face of box q is q
+    if (box(q - W) && fixed(WW + q)) acc += -ih * sP[q - W];
+    if (box(q) && fixed(WW + q)) acc += ih * sP[q];
+  } else {
+    const bool pf = fixed(2 * WW + q);
+    if (box(q + 1)) acc += ih * sW[q + 1];
+    if (box(q) && pf) acc += -ih * sW[q];
+    if (box(q - 1)) acc += -ih * sE[q - 1];
+    if (box(q) && pf) acc += ih * sE[q];
+    if (box(q + W)) acc += ih * sS[q + W];
+    if (box(q) && pf) acc += -ih * sS[q];
+    if (box(q - W)) acc += -ih * sN[q - W];
+    if (box(q) && pf) acc += ih * sN[q];
+  }
+  if (acc != 0.0) xb[t] += acc;
 }
 
 // transposed Jacobi sweep of all ghost rows
@@ -261,14 +310,18 @@ __global__ void k_gadj_a(const int *__restrict__ pt, const double *__restrict__ 
   tmp[r] = t;
   bb[pt[r]] += t;
 }
-__global__ void k_gadj_b(const int *__restrict__ col, const double *__restrict__ w, int ng, const double *__restrict__ tmp,
-                         double *xb) {
-  int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= ng) return;
-  double t = tmp[r];
-  if (t == 0.0) return;
-#pragma unroll
-  for (int z = 0; z < 9; z++) atomicAdd(&xb[col[9 * r + z]], -w[9 * r + z] * t);
+// xbar[col] -= w * t, gathered per column from the ghost-row table
+__global__ void k_gt_sweep(const int *__restrict__ tl, const int *__restrict__ off, const int *__restrict__ ent,
+                           const int *__restrict__ nt, const double *__restrict__ w, const double *__restrict__ tmp,
+                           double *xb) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= *nt) return;
+  double acc = 0;
+  for (int q = off[s]; q < off[s + 1]; q++) {
+    const int e = ent[q];
+    acc += -w[e] * tmp[e / 9];
+  }
+  if (acc != 0.0) xb[tl[s]] += acc;
 }
 
 // transposed coupled boxes of one colour.  Forward: x_k <- x_k + sum_c Ainv[a_k][c] r_c over the written slots k of
@@ -288,38 +341,42 @@ __global__ void k_xbt_t(int lo, int hi, const int *__restrict__ idx, const int *
   }
   t[s] = v;
 }
-__global__ void k_xbt_scatter(int lo, int hi, int W, double h, double a, double d, const uint8_t *__restrict__ cls,
-                              const int *__restrict__ idx, const int *__restrict__ g_rowof, const int *__restrict__ g_col,
-                              const double *__restrict__ g_w, const double *__restrict__ t, double *xb, double *bb) {
-  const int s = lo + blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= hi) return;
-  const double v = t[s];
-  if (v == 0.0) return;
-  const int k = idx[s], WW = W * W;
-  atomicAdd(&bb[k], v);
-  if (cls[k] == K_INT) {
-    const int g = k / WW, q = k - g * WW;
-    const double ih = 1.0 / h;
-    if (g < 2) {
-      atomicAdd(&xb[k], -v * d);
-      atomicAdd(&xb[k - 1], v * a);
-      atomicAdd(&xb[k + 1], v * a);
-      atomicAdd(&xb[k - W], v * a);
-      atomicAdd(&xb[k + W], v * a);
-      atomicAdd(&xb[2 * WW + q], -v * ih);
-      atomicAdd(&xb[2 * WW + q - (g == 0 ? 1 : W)], v * ih);
-    } else {
-      atomicAdd(&xb[q + 1], -v * ih);
-      atomicAdd(&xb[q], v * ih);
-      atomicAdd(&xb[WW + q + W], -v * ih);
-      atomicAdd(&xb[WW + q], v * ih);
-      atomicAdd(&xb[3 * WW], v);  // the -xi column
-    }
-    return;
+// the scatter of the transposed coupled boxes as a gather over the slot table: entry z = 0 of slot s is bbar on its
+// point (+t_s); entries z = 1.. are the columns of its row (xbar -= t_s times the row's coefficient): the internal
+// momentum row (d on itself, -a on the four neighbours, the pressure difference / h), the internal continuity row
+// (the four face differences / h and -1 for xi), or a ghost row (its 9 weights)
+__device__ __forceinline__ double xt_coef(int k, int z, int W, double h, double a, double d,
+                                          const uint8_t *__restrict__ cls, const int *__restrict__ g_rowof,
+                                          const double *__restrict__ g_w) {
+  const int WW = W * W;
+  if (cls[k] != K_INT) return -g_w[9 * g_rowof[k] + z - 1];
+  const double ih = 1.0 / h;
+  if (k / WW < 2) return z == 1 ? -d : (z <= 5 ? a : (z == 6 ? -ih : ih));
+  return z == 5 ? 1.0 : ((z & 1) ? -ih : ih);
+}
+__global__ void k_xt_apply(int lo, int hi, const int *__restrict__ tl, const int *__restrict__ off,
+                           const int *__restrict__ ent, const int *__restrict__ nt, int W, double h, double a, double d,
+                           const uint8_t *__restrict__ cls, const int *__restrict__ idx, const int *__restrict__ g_rowof,
+                           const double *__restrict__ g_w, const double *__restrict__ t, double *xb, double *bb) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= *nt) return;
+  double accb = 0, accx = 0;
+  bool any = false;
+  for (int q = off[s]; q < off[s + 1]; q++) {
+    const int e = ent[q], sl = e / 10, z = e - 10 * sl;
+    if (sl < lo || sl >= hi) continue;
+    const double v = t[sl];
+    if (v == 0.0) continue;
+    any = true;
+    if (z == 0)
+      accb += v;
+    else
+      accx += xt_coef(idx[sl], z, W, h, a, d, cls, g_rowof, g_w) * v;
   }
-  const int r = g_rowof[k];
-#pragma unroll
-  for (int z = 0; z < 9; z++) atomicAdd(&xb[g_col[9 * r + z]], -v * g_w[9 * r + z]);
+  if (any) {
+    bb[tl[s]] += accb;
+    xb[tl[s]] += accx;
+  }
 }
 
 // transposed xi update: xi = (sum over internal cells of (div u - g)) / mp
@@ -495,15 +552,24 @@ __global__ void k_prolong_adj(int Nf, int Wf, const uint8_t *__restrict__ clsf, 
   xbc[t] = acc;
 }
 
-// transposed extension fill (sources are internal or ghost points, never extension points)
-__global__ void k_ext_adj(const int *__restrict__ e_pt, const int *__restrict__ e_src, const double *__restrict__ e_w, int ne,
-                          double *xb) {
-  int e = blockIdx.x * blockDim.x + threadIdx.x;
+// transposed extension fill (sources are internal or ghost points, never extension points): every source gathers
+// w * xbar of the extension points that read it (table entries 3 e + q), then the extension points' xbar are zeroed
+__global__ void k_et_apply(const int *__restrict__ tl, const int *__restrict__ off, const int *__restrict__ ent,
+                           const int *__restrict__ nt, const int *__restrict__ e_pt, const double *__restrict__ e_w,
+                           double *xb) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= *nt) return;
+  double acc = 0;
+  for (int q = off[s]; q < off[s + 1]; q++) {
+    const int e = ent[q];
+    acc += e_w[e] * xb[e_pt[e / 3]];
+  }
+  if (acc != 0.0) xb[tl[s]] += acc;
+}
+__global__ void k_et_zero(const int *__restrict__ e_pt, const int *__restrict__ e_src, int ne, double *xb) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= ne || e_src[3 * e] < 0) return;
-  double v = xb[e_pt[e]];
   xb[e_pt[e]] = 0.0;
-  if (v == 0.0) return;
-  for (int q = 0; q < 3; q++) atomicAdd(&xb[e_src[3 * e + q]], e_w[3 * e + q] * v);
 }
 
 // transposed coarsest solve: bbar[bmap[j]] += sum_q Ainv[q][j] xbar[map[q]] (one wavefront per column), then
@@ -594,6 +660,111 @@ __global__ void k_absmax_d(const double *__restrict__ v, long n, unsigned long l
 }  // namespace
 
 // ---------------------------------------------------------------------------------------------------------
+// transposed scatter tables (TTab): entry targets, then count, list, offsets, fill and per-target sort
+// ---------------------------------------------------------------------------------------------------------
+namespace {
+__global__ void k_izero(int *x, long n) {
+  long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (i < n) x[i] = 0;
+}
+__global__ void k_tt_tgt_ghost(const int *__restrict__ col, int n, int *tgt) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < n) tgt[e] = col[e];
+}
+__global__ void k_tt_tgt_ext(const int *__restrict__ src, int n, int *tgt) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < n) tgt[e] = src[3 * (e / 3)] < 0 ? -1 : src[e];
+}
+__global__ void k_tt_tgt_xb(int nxs, int W, const uint8_t *__restrict__ cls, const int *__restrict__ idx,
+                            const int *__restrict__ g_rowof, const int *__restrict__ g_col, int *tgt) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= 10 * nxs) return;
+  const int sl = e / 10, z = e - 10 * sl, k = idx[sl], WW = W * W;
+  int t = -1;
+  if (z == 0) {
+    t = k;
+  } else if (cls[k] != K_INT) {
+    t = g_col[9 * g_rowof[k] + z - 1];
+  } else {
+    const int g = k / WW, q = k - g * WW;
+    if (g < 2) {
+      const int tt[7] = {k, k - 1, k + 1, k - W, k + W, 2 * WW + q, 2 * WW + q - (g == 0 ? 1 : W)};
+      if (z <= 7) t = tt[z - 1];
+    } else {
+      const int tt[5] = {q + 1, q, WW + q + W, WW + q, 3 * WW};
+      if (z <= 5) t = tt[z - 1];
+    }
+  }
+  tgt[e] = t;
+}
+__global__ void k_tt_count(const int *__restrict__ tgt, int n, int *cnt) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < n && tgt[e] >= 0) atomicAdd(&cnt[tgt[e]], 1);
+}
+// the targets with entries, in any order (each target's sum does not depend on where it sits in the list)
+__global__ void k_tt_list(const int *__restrict__ cnt, int T, int *tl, int *tc, int *pos, int *nt) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= T || cnt[t] == 0) return;
+  const int sl = atomicAdd(nt, 1);
+  tl[sl] = t;
+  tc[sl] = cnt[t];
+  pos[t] = sl;
+}
+// exclusive scan of the counts tc[0 .. nt) into off (one workgroup); cur (the fill cursors) cleared
+__global__ void __launch_bounds__(1024) k_tt_scan(const int *__restrict__ nt_p, int *tc, int *off) {
+  __shared__ int part[1024];
+  const int nt = *nt_p, T = blockDim.x, tid = threadIdx.x;
+  const int per = (nt + T - 1) / T, lo = tid * per, hi = min(nt, lo + per);
+  int sum = 0;
+  for (int q = lo; q < hi; q++) sum += tc[q];
+  part[tid] = sum;
+  __syncthreads();
+  for (int o = 1; o < T; o <<= 1) {  // inclusive scan of the partials
+    int v = tid >= o ? part[tid - o] : 0;
+    __syncthreads();
+    part[tid] += v;
+    __syncthreads();
+  }
+  int run = part[tid] - sum;
+  for (int q = lo; q < hi; q++) {
+    const int c = tc[q];
+    off[q] = run;
+    run += c;
+    tc[q] = 0;
+  }
+  if (tid == T - 1) off[nt] = part[T - 1];
+}
+__global__ void k_tt_fill(const int *__restrict__ tgt, int n, const int *__restrict__ pos, const int *__restrict__ off,
+                          int *cur, int *ent) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n || tgt[e] < 0) return;
+  const int sl = pos[tgt[e]];
+  ent[off[sl] + atomicAdd(&cur[sl], 1)] = e;
+}
+// each target's entries in ascending order of their keys; the point counts cleared for the next table.  The key of
+// entry e is e, or with `pt` given pt[e / K] K + e % K: the entry's item named by its point, so that the order does
+// not depend on how a geometry build numbered the items (ghost rows and extension points are numbered in the order
+// a compaction met them)
+__global__ void k_tt_sort(const int *__restrict__ nt_p, const int *__restrict__ tl, const int *__restrict__ off,
+                          const int *__restrict__ pt, int K, int *ent, int *cnt) {
+  const int sl = blockIdx.x * blockDim.x + threadIdx.x;
+  if (sl >= *nt_p) return;
+  const int lo = off[sl], hi = off[sl + 1];
+  auto key = [&](int e) { return pt ? pt[e / K] * K + e % K : e; };
+  for (int q = lo + 1; q < hi; q++) {
+    const int v = ent[q], kv = key(v);
+    int r = q - 1;
+    while (r >= lo && key(ent[r]) > kv) {
+      ent[r + 1] = ent[r];
+      r--;
+    }
+    ent[r + 1] = v;
+  }
+  cnt[tl[sl]] = 0;
+}
+}  // namespace
+
+// ---------------------------------------------------------------------------------------------------------
 // host side: transposed cycle
 // ---------------------------------------------------------------------------------------------------------
 gp_status adjoint_alloc(Ctx *ctx) {
@@ -611,8 +782,115 @@ gp_status adjoint_alloc(Ctx *ctx) {
   size_t n0 = ctx->geo[0].n;
   GP_HIP(hipMalloc((void **)&ctx->a_g, n0 * sizeof(double)));
   GP_HIP(hipMalloc((void **)&ctx->a_lam, n0 * sizeof(double)));
+  GP_HIP(hipMalloc((void **)&ctx->a_S, 5 * (size_t)ctx->geo[0].WW * sizeof(double)));
   GP_HIP(hipGetLastError());
   return GP_OK;
+}
+
+static void ifree(int *&p) {
+  if (p) (void)hipFree(p);
+  p = nullptr;
+}
+
+// regroup the entries whose targets the launch `tgt_fn` writes into ctx->tt_tgt (n entries, targets below T)
+template <class F>
+static gp_status tt_build(Ctx *ctx, TTab &tab, int n, int T, const int *pt, int K, F tgt_fn) {
+  hipStream_t s = ctx->stream;
+  tab.ne = n;
+  if (n == 0) return GP_OK;
+  if (T > ctx->tt_ccap) {
+    ifree(ctx->tt_cnt);
+    ifree(ctx->tt_pos);
+    GP_HIP(hipMalloc((void **)&ctx->tt_cnt, (size_t)T * sizeof(int)));
+    GP_HIP(hipMalloc((void **)&ctx->tt_pos, (size_t)T * sizeof(int)));
+    k_izero<<<nblk(T), TPB, 0, s>>>(ctx->tt_cnt, T);
+    ctx->tt_ccap = T;
+  }
+  if (n > ctx->tt_tcap) {
+    ifree(ctx->tt_tgt);
+    GP_HIP(hipMalloc((void **)&ctx->tt_tgt, (size_t)n * sizeof(int)));
+    ctx->tt_tcap = n;
+  }
+  const int mt = std::min(n, T);
+  if (mt + 1 > tab.cap_t) {
+    ifree(tab.tl);
+    ifree(tab.off);
+    ifree(tab.cur);
+    GP_HIP(hipMalloc((void **)&tab.tl, (size_t)(mt + 1) * sizeof(int)));
+    GP_HIP(hipMalloc((void **)&tab.off, (size_t)(mt + 2) * sizeof(int)));
+    GP_HIP(hipMalloc((void **)&tab.cur, (size_t)(mt + 1) * sizeof(int)));
+    tab.cap_t = mt + 1;
+  }
+  if (n > tab.cap_e) {
+    ifree(tab.ent);
+    GP_HIP(hipMalloc((void **)&tab.ent, (size_t)n * sizeof(int)));
+    tab.cap_e = n;
+  }
+  if (!tab.d_nt) GP_HIP(hipMalloc((void **)&tab.d_nt, sizeof(int)));
+  tgt_fn(ctx->tt_tgt);
+  k_tt_count<<<nblk(n), TPB, 0, s>>>(ctx->tt_tgt, n, ctx->tt_cnt);
+  k_izero<<<1, 1, 0, s>>>(tab.d_nt, 1);
+  k_tt_list<<<nblk(T), TPB, 0, s>>>(ctx->tt_cnt, T, tab.tl, tab.cur, ctx->tt_pos, tab.d_nt);
+  k_tt_scan<<<1, 1024, 0, s>>>(tab.d_nt, tab.cur, tab.off);
+  k_tt_fill<<<nblk(n), TPB, 0, s>>>(ctx->tt_tgt, n, ctx->tt_pos, tab.off, tab.cur, tab.ent);
+  k_tt_sort<<<nblk(mt), TPB, 0, s>>>(tab.d_nt, tab.tl, tab.off, pt, K, tab.ent, ctx->tt_cnt);
+  GP_HIP(hipGetLastError());
+  return GP_OK;
+}
+
+// the transposed scatter tables of every level for its current geometry
+static gp_status ensure_tabs(Ctx *ctx) {
+  hipStream_t s = ctx->stream;
+  for (int l = 0; l < ctx->L; l++) {
+    Geo &G = ctx->geo[l];
+    AdjTabs &A = ctx->atab[l];
+    if (A.gen == G.gen) continue;
+    const int T = 3 * G.WW + 1;
+    gp_status st = tt_build(ctx, A.gt, 9 * G.ng, T, G.g_pt, 9, [&](int *tgt) {
+      k_tt_tgt_ghost<<<nblk(9 * G.ng), TPB, 0, s>>>(G.g_col, 9 * G.ng, tgt);
+    });
+    if (st) return st;
+    st = tt_build(ctx, A.et, 3 * G.ne, T, G.e_pt, 3, [&](int *tgt) {
+      k_tt_tgt_ext<<<nblk(3 * G.ne), TPB, 0, s>>>(G.e_src, 3 * G.ne, tgt);
+    });
+    if (st) return st;
+    const int nxs = (ctx->prm.ghost_boxes && G.nxb) ? G.nxs : 0;
+    st = tt_build(ctx, A.xt, 10 * nxs, T, nullptr, 10, [&](int *tgt) {
+      k_tt_tgt_xb<<<nblk(10 * nxs), TPB, 0, s>>>(nxs, G.W, G.cls, G.xb_idx, G.g_rowof, G.g_col, tgt);
+    });
+    if (st) return st;
+    A.gen = G.gen;
+  }
+  return GP_OK;
+}
+void adjoint_free_tabs(Ctx *ctx) {
+  for (int l = 0; l < MAXLEV; l++)
+    for (TTab *t : {&ctx->atab[l].gt, &ctx->atab[l].et, &ctx->atab[l].xt}) {
+      ifree(t->tl);
+      ifree(t->off);
+      ifree(t->ent);
+      ifree(t->cur);
+      ifree(t->d_nt);
+      *t = TTab();
+    }
+  ifree(ctx->tt_cnt);
+  ifree(ctx->tt_pos);
+  ifree(ctx->tt_tgt);
+  ctx->tt_ccap = ctx->tt_tcap = 0;
+  if (ctx->a_S) (void)hipFree(ctx->a_S);
+  ctx->a_S = nullptr;
+}
+// launch size covering every target of a table
+static inline int tt_blocks(const TTab &t, int T) { return nblk(std::min(t.ne, T)); }
+
+// transposed extension fill of level l on x
+static void ext_fill_t(Ctx *ctx, int l, double *x) {
+  Geo &G = ctx->geo[l];
+  const TTab &E = ctx->atab[l].et;
+  if (!G.ne || !E.ne) return;
+  hipStream_t s = ctx->stream;
+  k_et_apply<<<tt_blocks(E, 3 * G.WW + 1), TPB, 0, s>>>(E.tl, E.off, E.ent, E.d_nt, G.e_pt, G.e_w, x);
+  k_et_zero<<<nblk(G.ne), TPB, 0, s>>>(G.e_pt, G.e_src, G.ne, x);
 }
 
 static inline double coef_a_l(Ctx *ctx, int l) { return ctx->alpha / (ctx->geo[l].h * ctx->geo[l].h); }
@@ -625,7 +903,9 @@ static void mt_apply(Ctx *ctx, int l, const double *lam, const double *base, dou
   // every entry of y is written by one thread from the same entry of base, so y may alias base
   k_mt_xi<<<std::min(ARED, nblk(G.WW)), TPB, 0, s>>>(G.W, G.cls, lam, base, sgn, y, ctx->d_red, ctx->d_ticket);
   k_mt_pts<<<nblk(3L * G.WW), TPB, 0, s>>>(G.N, G.W, G.h, a, d, G.cls, lam, base, sgn, y, 1.0 / G.mp);
-  if (G.ng) k_mt_ghost<<<nblk(G.ng), TPB, 0, s>>>(G.g_pt, G.g_col, G.g_w, G.ng, lam, sgn, y);
+  const TTab &GT = ctx->atab[l].gt;
+  if (G.ng && GT.ne)
+    k_gt_mt<<<tt_blocks(GT, 3 * G.WW + 1), TPB, 0, s>>>(GT.tl, GT.off, GT.ent, GT.d_nt, G.g_pt, G.g_w, lam, sgn, y);
 }
 
 static void box_colour_t(Ctx *ctx, int l, int colour, bool band) {
@@ -645,7 +925,11 @@ static void box_colour_t(Ctx *ctx, int l, int colour, bool band) {
     total = (long)(G.N / 5 + 1) * G.N;
   }
   int nb = std::min(4096, nblk(total));
-  k_box_adj<<<nb, TPB, 0, ctx->stream>>>(G.N, G.W, G.h, a, d, G.cls, A.x, A.b, colour, list, lo, hi, ctx->d_red, ctx->d_ticket);
+  // a band colour writes the values of its listed boxes only: the others of the colour must read zero
+  if (band) k_fill0<<<nblk(5L * G.WW), TPB, 0, ctx->stream>>>(ctx->a_S, 5L * G.WW);
+  k_box_adj<<<nb, TPB, 0, ctx->stream>>>(G.N, G.W, G.h, a, d, G.cls, A.x, A.b, ctx->a_S, colour, list, lo, hi, ctx->d_red,
+                                         ctx->d_ticket);
+  k_box_adj_g<<<nblk(3L * G.WW), TPB, 0, ctx->stream>>>(G.N, G.W, G.h, a, G.cls, ctx->a_S, colour, A.x);
 }
 
 static void ghost_sweep_t(Ctx *ctx, int l) {
@@ -653,7 +937,8 @@ static void ghost_sweep_t(Ctx *ctx, int l) {
   if (!G.ng) return;
   Vec<double> &A = ctx->adj[l];
   k_gadj_a<<<nblk(G.ng), TPB, 0, ctx->stream>>>(G.g_pt, G.g_dtau, G.ng, A.x, A.b, ctx->gtmp);
-  k_gadj_b<<<nblk(G.ng), TPB, 0, ctx->stream>>>(G.g_col, G.g_w, G.ng, ctx->gtmp, A.x);
+  const TTab &GT = ctx->atab[l].gt;
+  k_gt_sweep<<<tt_blocks(GT, 3 * G.WW + 1), TPB, 0, ctx->stream>>>(GT.tl, GT.off, GT.ent, GT.d_nt, G.g_w, ctx->gtmp, A.x);
 }
 
 // reverse of the coupled boxes of level l (colours 4..0)
@@ -668,8 +953,10 @@ static void xb_relax_t(Ctx *ctx, int l) {
     if (hi == lo) continue;
     k_xbt_t<<<nblk(hi - lo), TPB, 0, s>>>(lo, hi, G.xb_idx, G.xb_box, G.xb_off, G.xb_ioff, G.xb_wr, G.xb_ok, G.xb_inv, A.x,
                                         G.xb_r);
-    k_xbt_scatter<<<nblk(hi - lo), TPB, 0, s>>>(lo, hi, G.W, G.h, a, d, G.cls, G.xb_idx, G.g_rowof, G.g_col, G.g_w, G.xb_r,
-                                              A.x, A.b);
+    const TTab &X = ctx->atab[l].xt;
+    if (X.ne)
+      k_xt_apply<<<tt_blocks(X, 3 * G.WW + 1), TPB, 0, s>>>(lo, hi, X.tl, X.off, X.ent, X.d_nt, G.W, G.h, a, d, G.cls,
+                                                           G.xb_idx, G.g_rowof, G.g_w, G.xb_r, A.x, A.b);
   }
 }
 
@@ -706,7 +993,7 @@ static void cycle_t(Ctx *ctx, int l) {
   Vec<double> &AF = ctx->adj[l], &AC = ctx->adj[l + 1];
   for (int q = 0; q < ctx->prm.nu2; q++) relax_t(ctx, l);
   k_prolong_adj<<<nblk(3L * C.WW + 1), TPB, 0, s>>>(F.N, F.W, F.cls, AF.x, C.N, C.W, AC.x);
-  if (C.ne) k_ext_adj<<<nblk(C.ne), TPB, 0, s>>>(C.e_pt, C.e_src, C.e_w, C.ne, AC.x);
+  ext_fill_t(ctx, l + 1, AC.x);
   k_fill0<<<nblk(C.n), TPB, 0, s>>>(AC.b, C.n);
   int reps = (l + 1 == ctx->L - 1) ? 1 : ctx->prm.gamma;
   for (int q = 0; q < reps; q++) cycle_t(ctx, l + 1);
@@ -737,7 +1024,8 @@ static gp_status ready(Ctx *ctx) {
   }
   gp_status st = ensure_xb(ctx);
   if (st) return st;
-  return adjoint_alloc(ctx);
+  if ((st = adjoint_alloc(ctx))) return st;
+  return ensure_tabs(ctx);
 }
 
 static gp_status absmax_dev(Ctx *ctx, const double *v, long n, double *out) {
@@ -977,7 +1265,9 @@ void tape_free(Ctx *ctx) {
   T.last.buf = nullptr;
   T.ckpt.clear();
   T.seg.clear();
-  for (double **p : {&T.fu, &T.fv, &T.xb, &T.yb, &T.xbn, &T.lamp, &T.ring, &T.fb, &T.tcb, &T.ub})
+  if (T.d_mism) (void)hipFree(T.d_mism);
+  T.d_mism = nullptr;
+  for (double **p : {&T.fu, &T.fv, &T.xb, &T.yb, &T.xbn, &T.lamp, &T.ring, &T.fb, &T.tcb, &T.ub, &T.upath, &T.pcx, &T.pcy})
     if (*p) {
       (void)hipFree(*p);
       *p = nullptr;
@@ -1021,7 +1311,7 @@ static gp_status adjoint_step(Ctx *ctx, const CnSnap &pre, const CnSnap &post, d
   k_conv_jt<<<nblk(2L * WW), TPB, 0, s>>>(G.N, G.W, G.h, y, R[0], R[0] + WW, T.xb);
   if (!extrap) k_copy<<<nblk(n), TPB, 0, s>>>(T.yb, T.xb, n);
   // adjoint of the extension fill, then of the solve
-  if (G.ne) k_ext_adj<<<nblk(G.ne), TPB, 0, s>>>(G.e_pt, G.e_src, G.e_w, G.ne, T.xb);
+  ext_fill_t(ctx, 0, T.xb);
   k_copy<<<nblk(n), TPB, 0, s>>>(ctx->a_g, T.xb, n);
   k_fill0<<<nblk(n), TPB, 0, s>>>(ctx->a_lam, n);
   gp_stats sub{};
@@ -1035,7 +1325,7 @@ static gp_status adjoint_step(Ctx *ctx, const CnSnap &pre, const CnSnap &post, d
       k_pscale<<<nblk(2L * WW), TPB, 0, s>>>(G.W, G.cls, ctx->a_lam, -0.5 * T.dt, T.tcb);
       k_copy<<<nblk(n), TPB, 0, s>>>(ctx->a_g, T.yb, n);
       k_conv_jt<<<nblk(2L * WW), TPB, 0, s>>>(G.N, G.W, G.h, y, T.tcb, T.tcb + WW, ctx->a_g);
-      if (G.ne) k_ext_adj<<<nblk(G.ne), TPB, 0, s>>>(G.e_pt, G.e_src, G.e_w, G.ne, ctx->a_g);
+      ext_fill_t(ctx, 0, ctx->a_g);
       k_copy<<<nblk(n), TPB, 0, s>>>(T.lamp, ctx->a_lam, n);
       st = adjoint_solve_dev(ctx, tol, max_cycles, &sub);  // warm start from the previous lam
       if (st != GP_OK && st != GP_ENOCONV) return st;
@@ -1059,6 +1349,8 @@ static gp_status adjoint_step(Ctx *ctx, const CnSnap &pre, const CnSnap &post, d
                                           R[3], extrap);
   for (int comp = 0; comp < 2; comp++)
     k_ub_sum<<<std::min(ARED, nblk(WW)), TPB, 0, s>>>(G.W, comp, G.cls, ctx->a_lam, ctx->d_red, ctx->d_ticket, T.ub);
+  // and of the body position along the path (the rows of this step's geometry at t = ctx->t_geom)
+  if ((st = path_terms(ctx, T.shape, T.motion, ctx->t_geom, y, ctx->a_lam, T.pcx, T.pcy, T.upath, T.d_mism))) return st;
   // rotate the ring: c^{n+1} is done (its slot becomes the zeroed c^{n-3}), c^n is the next step's first entry
   k_fill0<<<nblk(2L * WW), TPB, 0, s>>>(R[0], 2 * WW);
   T.ring_head = (T.ring_head + 1) & 3;
@@ -1134,8 +1426,11 @@ gp_status tape_backward(Ctx *ctx, const double *seed_u, const double *seed_v, in
   if ((st = adjoint_alloc(ctx))) return st;
   if ((st = dalloc0(ctx, &T.xb, n)) || (st = dalloc0(ctx, &T.yb, n)) || (st = dalloc0(ctx, &T.xbn, 2 * WW)) ||
       (st = dalloc0(ctx, &T.lamp, n)) || (st = dalloc0(ctx, &T.ring, 8 * WW)) || (st = dalloc0(ctx, &T.fb, 2 * WW)) ||
-      (st = dalloc0(ctx, &T.tcb, 2 * WW)) || (st = dalloc0(ctx, &T.ub, 2)))
+      (st = dalloc0(ctx, &T.tcb, 2 * WW)) || (st = dalloc0(ctx, &T.ub, 2)) || (st = dalloc0(ctx, &T.upath, 2)) ||
+      (st = dalloc0(ctx, &T.pcx, 3 * WW)) || (st = dalloc0(ctx, &T.pcy, 3 * WW)))
     return st;
+  if (!T.d_mism) GP_HIP(hipMalloc((void **)&T.d_mism, sizeof(int)));
+  k_izero<<<1, 1, 0, s>>>(T.d_mism, 1);
   T.ring_head = 0;
   hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
   if (seed_u) GP_HIP(hipMemcpyAsync(T.xb, seed_u, WW * sizeof(double), kind, s));
@@ -1171,6 +1466,8 @@ gp_status tape_backward(Ctx *ctx, const double *seed_u, const double *seed_v, in
   if (du0) GP_HIP(hipMemcpyAsync(du0, T.xb, WW * sizeof(double), ok, s));
   if (dv0) GP_HIP(hipMemcpyAsync(dv0, T.xb + WW, WW * sizeof(double), ok, s));
   if (dU) GP_HIP(hipMemcpyAsync(dU, T.ub, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+  GP_HIP(hipMemcpyAsync(T.h_upath, T.upath, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+  GP_HIP(hipMemcpyAsync(&T.h_mism, T.d_mism, sizeof(int), hipMemcpyDeviceToHost, s));
   GP_HIP(hipStreamSynchronize(s));
   acc.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0c).count();
   if (stt) *stt = acc;
@@ -1261,4 +1558,12 @@ extern "C" gp_status gp_tape_backward(gp_ctx *ctx, const double *seed_u, const d
                                       double *dJdv0, gp_stats *st) {
   if (!ctx || !(tol > 0) || max_cycles < 1) return GP_EINVAL;
   return tape_backward(ctx, seed_u, seed_v, on_device, tol, max_cycles, dJdfu, dJdfv, dJdU, dJdu0, dJdv0, st);
+}
+
+extern "C" gp_status gp_tape_path_gradient(gp_ctx *ctx, double *dJdU_path, int *unmatched) {
+  if (!ctx || !dJdU_path || !ctx->tape.valid) return GP_EINVAL;
+  dJdU_path[0] = ctx->tape.h_upath[0];
+  dJdU_path[1] = ctx->tape.h_upath[1];
+  if (unmatched) *unmatched = ctx->tape.h_mism;
+  return GP_OK;
 }

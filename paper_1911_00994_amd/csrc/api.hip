@@ -250,6 +250,7 @@ void gp_destroy(gp_ctx *ctx) {
   }
   dfree(ctx->a_g);
   dfree(ctx->a_lam);
+  adjoint_free_tabs(ctx);
   tape_free(ctx);
   for (auto &g : ctx->g_iter)
     if (g) (void)hipGraphExecDestroy(g);

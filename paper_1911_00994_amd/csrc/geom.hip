@@ -3,6 +3,7 @@
 // factorisation of the coarsest system.  Arithmetic is kept in FP64 everywhere (small cut cells make the
 // ghost coefficients ill-conditioned); this file is built with FMA contraction off so that the branch
 // decisions of the bisection see the same roundings as a plain IEEE evaluation.
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -263,9 +264,11 @@ __device__ __forceinline__ void dlagr3(double t, double D[3]) {
   D[2] = t - 0.5;
 }
 
-// Alg. 1 (march along the bilinear normal by h/2, then bisection on the last segment); returns success
+// Alg. 1 (march along the bilinear normal by h/2, then bisection on the last segment); returns success.  With rec
+// given, the discrete path is recorded: rec[0] = march steps (+ 65536 when the march ends exactly on the zero set),
+// rec[1] bit q set when bisection step q moved the inner end of the bracket
 __device__ bool boundary_point(const Lat &L, double xg, double yg, double phig, int march_max, int nbis, double *Bx,
-                               double *By) {
+                               double *By, unsigned *rec = nullptr) {
   double hx = xg, hy = yg, ph = phig, kx = xg, ky = yg;
   int it = 0;
   while (ph > 0) {
@@ -278,6 +281,10 @@ __device__ bool boundary_point(const Lat &L, double xg, double yg, double phig, 
     hy = hy - 0.5 * L.h * ny;
     bilin(L, hx, hy, &ph, nullptr, nullptr);
     it++;
+  }
+  if (rec) {
+    rec[0] = (unsigned)it + (ph == 0.0 ? 65536u : 0u);
+    rec[1] = 0;
   }
   if (it == 0 || ph == 0.0) {
     *Bx = hx;
@@ -293,6 +300,7 @@ __device__ bool boundary_point(const Lat &L, double xg, double yg, double phig, 
     if (pb * ph < 0) {
       kx = bx;
       ky = by;
+      if (rec) rec[1] |= 1u << q;
     } else {
       hx = bx;
       hy = by;
@@ -1307,14 +1315,16 @@ __device__ __forceinline__ unsigned sec_bits(double x, double y, const SecGeo &s
   for (int k = lo; k <= hi; k++) m |= 1u << (((k % sg.S) + sg.S) % sg.S);
   return m;
 }
-// sums of the band cells' centres (acc[0], acc[1]); reach of the body ghost rows in cells (reach)
+// sums of the band cells' column and row numbers (integers in acc[0], acc[1], so the sum does not depend on the
+// order of the additions); reach of the body ghost rows in cells (reach)
 __global__ void k_sec_centre(const int *band, int nband, int N, double h, const int *bg_k, const int *bg_loc, int nbg,
                              int gcap, const int *reg_pt, int W, double *acc, int *reach) {
+  (void)h;
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t < nband) {
     const int cell = band[t];
-    atomicAdd(&acc[0], -1.0 + (cell % N + 0.5) * h);
-    atomicAdd(&acc[1], -1.0 + (cell / N + 0.5) * h);
+    atomicAdd((unsigned long long *)&acc[0], (unsigned long long)(cell % N));
+    atomicAdd((unsigned long long *)&acc[1], (unsigned long long)(cell / N));
   } else if (t < nband + nbg) {
     const int s2 = t - nband, k = bg_k[s2];
     int m = 0;
@@ -1515,18 +1525,18 @@ gp_status sector_build(Ctx *ctx, int l) {
   GP_HIP(hipMemsetAsync(ic, 0, 4 * sizeof(int), s));
   k_sec_centre<<<nblk(nt), TPB, 0, s>>>(G.band, G.nband, G.N, G.h, G.bg_k, G.bg_loc, G.nbg, G.gcap, G.reg_pt, W, acc, ic);
   GP_HIP(hipGetLastError());
-  double hacc[2];
+  unsigned long long hacc[2];
   int reach = 0;
   {
     int w[5];
     gp_status fs = fetch(ctx, B, {{acc, 4}, {ic, 1}}, w);
     if (fs) return fs;
-    std::memcpy(hacc, w, 2 * sizeof(double));
+    std::memcpy(hacc, w, 2 * sizeof(unsigned long long));
     reach = w[4];
   }
-  SecGeo sg;
-  sg.cx = hacc[0] / G.nband;
-  sg.cy = hacc[1] / G.nband;
+  SecGeo sg;  // the mean of the band cells' centres
+  sg.cx = -1.0 + ((double)hacc[0] / G.nband + 0.5) * G.h;
+  sg.cy = -1.0 + ((double)hacc[1] / G.nband + 0.5) * G.h;
   GP_HIP(hipMemsetAsync(acc + 2, 0x7f, sizeof(double), s));  // 0x7f7f...: ~1.4e306, above any distance here
   k_sec_rmin<<<nblk(G.nreg), TPB, 0, s>>>(G.reg_pt, G.nreg, W, G.h, sg.cx, sg.cy, (unsigned long long *)(acc + 2));
   GP_HIP(hipGetLastError());
@@ -1681,8 +1691,11 @@ gp_status ensure_xb(Ctx *ctx) {
   return GP_OK;
 }
 
+static std::atomic<long> geo_gen_counter{0};
+
 static gp_status build_level(Ctx *ctx, int l) {
   Geo &G = ctx->geo[l];
+  G.gen = ++geo_gen_counter;  // tables derived from this level's (the reverse mode's) are rebuilt on a change
   BuildRes &B = ctx->bres[l];
   Lat L = make_lat(ctx, l);
   int W = G.W, P = 3 * W * W;
@@ -2193,6 +2206,259 @@ gp_status coarse_factor(Ctx *ctx, BuildRes &B) {
   if (st) return st;
   if (hf[6]) return GP_EGEOM;
   ctx->c_ok = 1;
+  return GP_OK;
+}
+
+
+// ---------------------------------------------------------------------------------------------------------
+// derivative of the finest boundary rows with respect to the body position (reverse mode, body velocity along
+// the path).  With the discrete decisions of the geometry frozen (classes, ghost points, the upwind stencils, the
+// number of march steps and the bisection branches of Alg. 1), the rows eq. (BCu) of the body ghosts and their
+// boundary data are smooth functions of the body position P = X(t).  The lattice samples move with it,
+// d phi_k / dP = -R(-omega t)^T grad phi0, and B, theta, n_B and the weights follow by forward-mode
+// differentiation (D2: a value and its two partials) along the recorded path.
+// ---------------------------------------------------------------------------------------------------------
+namespace {
+struct D2 {
+  double v, x, y;
+};
+__device__ __forceinline__ D2 dc(double v) { return {v, 0.0, 0.0}; }
+__device__ __forceinline__ D2 operator+(D2 a, D2 b) { return {a.v + b.v, a.x + b.x, a.y + b.y}; }
+__device__ __forceinline__ D2 operator-(D2 a, D2 b) { return {a.v - b.v, a.x - b.x, a.y - b.y}; }
+__device__ __forceinline__ D2 operator-(D2 a) { return {-a.v, -a.x, -a.y}; }
+__device__ __forceinline__ D2 operator*(D2 a, D2 b) { return {a.v * b.v, a.x * b.v + a.v * b.x, a.y * b.v + a.v * b.y}; }
+__device__ __forceinline__ D2 operator*(double c, D2 a) { return {c * a.v, c * a.x, c * a.y}; }
+__device__ __forceinline__ D2 operator/(D2 a, D2 b) {
+  const double q = a.v / b.v;
+  return {q, (a.x - q * b.x) / b.v, (a.y - q * b.y) / b.v};
+}
+__device__ __forceinline__ D2 operator/(D2 a, double c) { return {a.v / c, a.x / c, a.y / c}; }
+__device__ __forceinline__ D2 dsqrt(D2 a) {
+  const double r = sqrt(a.v);
+  return {r, r > 0 ? a.x / (2 * r) : 0.0, r > 0 ? a.y / (2 * r) : 0.0};
+}
+__device__ __forceinline__ D2 dcos(D2 a) { return {cos(a.v), -sin(a.v) * a.x, -sin(a.v) * a.y}; }
+__device__ __forceinline__ D2 datan2(D2 y, D2 x) {
+  const double d = x.v * x.v + y.v * y.v;
+  return {atan2(y.v, x.v), (x.v * y.x - y.v * x.x) / d, (x.v * y.y - y.v * x.y) / d};
+}
+
+struct ShapeArg {
+  int kind;
+  double a0, a1, a2, a3;
+  double X, Y, c, s;  // body position and the cosine and sine of its angle
+};
+// the shapes of shape_value on D2 arguments
+__device__ D2 shape_d2(const ShapeArg &S, D2 xb, D2 yb) {
+  const int kind = S.kind;
+  if (kind == 0) return dc(S.a0) - dsqrt(xb * xb + yb * yb);
+  if (kind == 1) return dc(S.a0 * S.a0) - (xb * xb + yb * yb);
+  if (kind == 2 || kind == 3) {
+    const double c = cos(S.a2), s = sin(S.a2);
+    const D2 xr = c * xb - s * yb, yr = s * xb + c * yb;
+    const D2 q = xr * xr / (S.a0 * S.a0) + yr * yr / (S.a1 * S.a1);
+    return kind == 2 ? dc(1.0) - q : dc(1.0) - dsqrt(q);
+  }
+  if (kind == 4) {
+    const D2 r = dsqrt(xb * xb + yb * yb);
+    if (r.v == 0.0) return dc(S.a0 + S.a1);
+    return dc(S.a0) + S.a1 * dcos(S.a3 * (datan2(yb, xb) - dc(S.a2))) - r;
+  }
+  return dc(-1.0);
+}
+// a finest lattice sample: the stored value and its partials along the body position
+__device__ D2 lat_d2(const Lat &L, const ShapeArg &S, int kx, int ky) {
+  const double hl = 0.5 * L.h;
+  const D2 x = {-1.0 + kx * hl - S.X, -1.0, 0.0}, y = {-1.0 + ky * hl - S.Y, 0.0, -1.0};
+  const D2 p = shape_d2(S, S.c * x + S.s * y, S.c * y - S.s * x);
+  return {lat_at(L, kx, ky), p.x, p.y};
+}
+// bilin on D2 positions (the cell of the interpolation is frozen)
+__device__ void bilin_d2(const Lat &L, const ShapeArg &S, D2 x, D2 y, D2 *val, D2 *gx, D2 *gy) {
+  const double hl = 0.5 * L.h;
+  const int nl = 2 * L.N + 1;
+  const D2 fx = (x + dc(1.0)) / hl, fy = (y + dc(1.0)) / hl;
+  int kx = (int)floor(fx.v), ky = (int)floor(fy.v);
+  kx = kx < 0 ? 0 : (kx > nl - 2 ? nl - 2 : kx);
+  ky = ky < 0 ? 0 : (ky > nl - 2 ? nl - 2 : ky);
+  const D2 tx = fx - dc(kx), ty = fy - dc(ky), ux = dc(1.0) - tx, uy = dc(1.0) - ty;
+  const D2 p00 = lat_d2(L, S, kx, ky), p10 = lat_d2(L, S, kx + 1, ky), p01 = lat_d2(L, S, kx, ky + 1),
+           p11 = lat_d2(L, S, kx + 1, ky + 1);
+  if (val) *val = ux * uy * p00 + tx * uy * p10 + ux * ty * p01 + tx * ty * p11;
+  if (gx) *gx = (uy * (p10 - p00) + ty * (p11 - p01)) / hl;
+  if (gy) *gy = (ux * (p01 - p00) + tx * (p11 - p10)) / hl;
+}
+__device__ void normal_d2(const Lat &L, const ShapeArg &S, D2 x, D2 y, D2 *nx, D2 *ny) {
+  D2 gx, gy;
+  bilin_d2(L, S, x, y, nullptr, &gx, &gy);
+  const D2 m = dsqrt(gx * gx + gy * gy);
+  if (m.v > 0) {
+    *nx = gx / m;
+    *ny = gy / m;
+  } else {
+    *nx = dc(0.0);
+    *ny = dc(0.0);
+  }
+}
+// Alg. 1 along a recorded path (boundary_point's rec)
+__device__ void boundary_point_d2(const Lat &L, const ShapeArg &S, double xg, double yg, int nbis, const unsigned rec[2],
+                                  D2 *Bx, D2 *By) {
+  D2 hx = dc(xg), hy = dc(yg), kx = hx, ky = hy;
+  const int nm = (int)(rec[0] & 65535u);
+  for (int it = 0; it < nm; it++) {
+    kx = hx;
+    ky = hy;
+    D2 nx, ny;
+    normal_d2(L, S, hx, hy, &nx, &ny);
+    hx = hx - (0.5 * L.h) * nx;
+    hy = hy - (0.5 * L.h) * ny;
+  }
+  if (nm == 0 || rec[0] >= 65536u) {
+    *Bx = hx;
+    *By = hy;
+    return;
+  }
+  D2 bx = hx, by = hy;
+  for (int q = 0; q < nbis; q++) {
+    bx = 0.5 * (hx + kx);
+    by = 0.5 * (hy + ky);
+    if (rec[1] >> q & 1u) {
+      kx = bx;
+      ky = by;
+    } else {
+      hx = bx;
+      hy = by;
+    }
+  }
+  *Bx = bx;
+  *By = by;
+}
+__device__ __forceinline__ void lagr3_d2(D2 t, D2 T[3]) {
+  T[0] = 0.5 * ((dc(1.0) - t) * (dc(2.0) - t));
+  T[1] = t * (dc(2.0) - t);
+  T[2] = 0.5 * (t * (t - dc(1.0)));
+}
+__device__ __forceinline__ void dlagr3_d2(D2 t, D2 D[3]) {
+  D[0] = t - dc(1.5);
+  D[1] = dc(2.0) - 2.0 * t;
+  D[2] = t - dc(0.5);
+}
+
+// per body ghost row (finest level, eq. (BCu) rows): lam_G times the partials of its residual b_G - sum w x along
+// the body position, into cx[k], cy[k] at the ghost's point k (other points untouched); mism counts rows whose
+// recomputed boundary point is not the stored one
+__global__ void k_path_rows(Lat L, ShapeArg S, double om, const uint8_t *__restrict__ cls, int W, RowArgs R,
+                            int march_max, int nbis, const double *__restrict__ x, const double *__restrict__ lam,
+                            double *cx, double *cy, int *mism) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= R.ng) return;
+  const int k = R.g_pt[r];
+  if (cls[k] != K_GHOST || R.g_kind[r] != 1) return;
+  const double h = L.h;
+  const int g = k / (W * W), loc = k % (W * W), j = loc / W - 1, i = loc % W - 1;
+  double xg, yg;
+  node_pos(g, i, j, h, &xg, &yg);
+  int kx, ky;
+  node_lat(g, i, j, &kx, &ky);
+  double ngx, ngy;
+  normal_at(L, xg, yg, &ngx, &ngy);
+  const double sx = sgn1(ngx), sy = sgn1(ngy);
+  double Bx, By;
+  unsigned rec[2];
+  if (!boundary_point(L, xg, yg, lat_at(L, kx, ky), march_max, nbis, &Bx, &By, rec) || Bx != R.g_B[2 * r] ||
+      By != R.g_B[2 * r + 1]) {
+    atomicAdd(mism, 1);
+    return;
+  }
+  D2 BX, BY;
+  boundary_point_d2(L, S, xg, yg, nbis, rec, &BX, &BY);
+  const D2 thx = (sx / h) * (dc(xg) - BX), thy = (sy / h) * (dc(yg) - BY);
+  D2 Tx[3], Ty[3], w[9];
+  lagr3_d2(thx, Tx);
+  lagr3_d2(thy, Ty);
+  if (g < 2) {
+    for (int b = 0; b < 3; b++)
+      for (int a = 0; a < 3; a++) w[b * 3 + a] = Tx[a] * Ty[b];
+  } else {
+    D2 nbx, nby, Dx[3], Dy[3];
+    normal_d2(L, S, BX, BY, &nbx, &nby);
+    dlagr3_d2(thx, Dx);
+    dlagr3_d2(thy, Dy);
+    for (int b = 0; b < 3; b++)
+      for (int a = 0; a < 3; a++) w[b * 3 + a] = -(1.0 / h) * (sx * (nbx * Dx[a] * Ty[b]) + sy * (nby * Tx[a] * Dy[b]));
+  }
+  double dx = 0, dy = 0;
+  for (int z = 0; z < 9; z++) {
+    const double xv = x[R.g_col[9 * r + z]];
+    dx -= w[z].x * xv;
+    dy -= w[z].y * xv;
+  }
+  // boundary data of the velocity rows, u_b = V + omega x (B - P)
+  if (g == 0) {
+    dx += -om * BY.x;
+    dy += -om * (BY.y - 1.0);
+  } else if (g == 1) {
+    dx += om * (BX.x - 1.0);
+    dy += om * BX.y;
+  }
+  const double l = lam[k];
+  cx[k] = l * dx;
+  cy[k] = l * dy;
+}
+__global__ void k_zero2(double *a, double *b, long n) {
+  const long q = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (q < n) a[q] = b[q] = 0.0;
+}
+// acc[0..1] += scale * (sum of cx, sum of cy) over the points, in a fixed order (one workgroup)
+__global__ void __launch_bounds__(1024) k_path_sum(const double *__restrict__ cx, const double *__restrict__ cy, long n,
+                                                   double scale, double *acc) {
+  __shared__ double sa[1024], sb[1024];
+  double a = 0, b = 0;
+  for (long q = threadIdx.x; q < n; q += 1024) {
+    a += cx[q];
+    b += cy[q];
+  }
+  sa[threadIdx.x] = a;
+  sb[threadIdx.x] = b;
+  __syncthreads();
+  for (int o = 512; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) {
+      sa[threadIdx.x] += sa[threadIdx.x + o];
+      sb[threadIdx.x] += sb[threadIdx.x + o];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    acc[0] += scale * sa[0];
+    acc[1] += scale * sb[0];
+  }
+}
+}  // namespace
+
+gp_status path_terms(Ctx *ctx, const gp_shape &sh, const gp_rigid &mo, double t, const double *x, const double *lam,
+                     double *cx, double *cy, double *acc, int *mism) {
+  Geo &G = ctx->geo[0];
+  if (!G.ng) return GP_OK;
+  hipStream_t s = ctx->stream;
+  Lat L = make_lat(ctx, 0);
+  ShapeArg S;
+  S.kind = sh.kind;
+  S.a0 = sh.p[0];
+  S.a1 = sh.p[1];
+  S.a2 = sh.p[2];
+  S.a3 = sh.p[3];
+  S.X = mo.X0x + mo.Ux * t;
+  S.Y = mo.X0y + mo.Uy * t;
+  S.c = cos(mo.omega * t);
+  S.s = sin(mo.omega * t);
+  const long n = 3L * G.WW;
+  k_zero2<<<nblk(n), TPB, 0, s>>>(cx, cy, n);
+  const double nbis_d = ceil(log2(0.5 / ctx->prm.bisect_eps_over_h) - 1e-12);
+  k_path_rows<<<nblk(G.ng), TPB, 0, s>>>(L, S, mo.omega, G.cls, G.W, row_args(G), ctx->prm.march_max, (int)nbis_d, x,
+                                          lam, cx, cy, mism);
+  // X(t) = X0 + U t: the partials along the position times t are those along U
+  k_path_sum<<<1, 1024, 0, s>>>(cx, cy, n, t, acc);
+  GP_HIP(hipGetLastError());
   return GP_OK;
 }
 

@@ -109,6 +109,21 @@ struct Geo {
   int *xb_gc = nullptr, *xb_uk = nullptr, *xb_uo = nullptr, *xb_ub = nullptr, *xb_um = nullptr;
   double *xb_gw = nullptr;
   double xb_alpha = -1;
+  long gen = 0;                     // identity of this build of the level's tables (fresh on every build)
+};
+
+// transposed scatter table of the reverse mode.  A table of items with K entries each (entry e = item * K + z) and a
+// target point per entry is regrouped by target: tl[0 .. nt) the targets that receive entries, ent[off[s] ..
+// off[s + 1]) the entries of target tl[s] in ascending order, so that a gather over one target adds its entries in
+// a fixed order (the scatter it replaces added them with atomics, in arrival order).  nt lives on the device.
+struct TTab {
+  int *tl = nullptr, *off = nullptr, *ent = nullptr, *cur = nullptr, *d_nt = nullptr;
+  int cap_t = 0, cap_e = 0;
+  int ne = 0;                       // entries of the table (host)
+};
+struct AdjTabs {
+  long gen = -1;                    // Geo::gen of the tables below
+  TTab gt, et, xt;                  // ghost rows (K = 9), extension points (K = 3), coupled-box slots (K = 10)
 };
 
 // one precision's vectors on one level
@@ -141,6 +156,12 @@ struct Tape {
   // convection-history adjoints (c^{n+1}, c^n, c^{n-1}, c^{n-2}; u and v), forcing adjoint, scratch
   double *xb = nullptr, *yb = nullptr, *xbn = nullptr, *lamp = nullptr, *ring = nullptr, *fb = nullptr, *tcb = nullptr;
   double *ub = nullptr;                 // device [2]: adjoint of the boundary-velocity offset
+  // device [2]: the part of dJ/dU that comes through the body path X(t) = X0 + U t (the rows' dependence on the
+  // body position), its per-point scratch (3 W^2 each) and the count of rows whose path could not be replayed
+  double *upath = nullptr, *pcx = nullptr, *pcy = nullptr;
+  int *d_mism = nullptr;
+  double h_upath[2] = {0, 0};
+  int h_mism = 0;
   int ring_head = 0;
 };
 
@@ -179,6 +200,10 @@ struct Ctx {
   Vec<float> v32[MAXLEV];
   Vec<double> adj[MAXLEV];          // transposed cycle: x = adjoint of x, b = adjoint of b, r = adjoint of r
   double *a_g = nullptr, *a_lam = nullptr;  // transposed solve: right-hand side and solution (finest)
+  AdjTabs atab[MAXLEV];             // transposed scatter tables per level
+  int *tt_cnt = nullptr, *tt_pos = nullptr, *tt_tgt = nullptr;  // table build scratch (points; entries)
+  int tt_ccap = 0, tt_tcap = 0;
+  double *a_S = nullptr;            // transposed box colour: the five box values per cell (finest size)
   Tape tape;
   double *phi = nullptr;            // fine half lattice (2N+1)^2
   double *gtmp = nullptr, *gtmp2 = nullptr;  // ghost Jacobi scratch, row-indexed (max gcap each)
@@ -273,6 +298,11 @@ gp_status coarse_factor(Ctx *ctx, BuildRes &B);
 gp_status sector_build(Ctx *ctx, int l);
 gp_status xb_factor(Ctx *ctx, int l, hipStream_t s);
 gp_status ensure_xb(Ctx *ctx);
+void adjoint_free_tabs(Ctx *ctx);  // the reverse mode's scatter tables and scratch
+// acc[0..1] += t * sum over the finest body ghost rows of lam_G d(b_G - M_G x)/dP (P the body position at time t,
+// discrete decisions of the geometry frozen); mism counts rows whose Alg. 1 path was not reproduced
+gp_status path_terms(Ctx *ctx, const gp_shape &sh, const gp_rigid &mo, double t, const double *x, const double *lam,
+                     double *cx, double *cy, double *acc, int *mism);
 
 // multigrid (mg.hip)
 gp_status mg_cycle64(Ctx *ctx, double *res_inf);

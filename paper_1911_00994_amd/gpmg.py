@@ -27,7 +27,7 @@ EXPORTS = [
     "gp_residual", "gp_set_state", "gp_cn_step", "gp_get_classes", "gp_get_ghost_rows", "gp_get_ext_rows",
     "gp_get_band_layout", "gp_get_coupled_boxes",
     "gp_relax", "gp_time_kernel", "gp_probe_start", "gp_probe_stop", "gp_apply_mt", "gp_adjoint_solve", "gp_apply_cycle", "gp_apply_cycle_t",
-    "gp_tape_forward", "gp_tape_backward",
+    "gp_tape_forward", "gp_tape_backward", "gp_tape_path_gradient",
 ]
 
 
@@ -122,6 +122,7 @@ def lib():
         "gp_tape_forward": (i, [vp, ctypes.POINTER(GpShape), ctypes.POINTER(GpRigid), d, d, i, vp, vp, i, vp, d, i, d, i,
                                 i, ctypes.POINTER(GpStats)]),
         "gp_tape_backward": (i, [vp, vp, vp, i, d, i, vp, vp, vp, vp, vp, ctypes.POINTER(GpStats)]),
+        "gp_tape_path_gradient": (i, [vp, vp, vp]),
     }
     for name, (res, args) in sigs.items():
         f = getattr(L, name)
@@ -437,3 +438,11 @@ class Solver:
                                     _ptr(dfv), _ptr(dU), _ptr(du0), _ptr(dv0), ctypes.byref(s))
         self._check(st, "gp_tape_backward")
         return dict(dfu=dfu, dfv=dfv, dU=dU, du0=du0, dv0=dv0, stats=s.as_dict())
+
+    def tape_path_gradient(self):
+        """(dJ/dU through the body path, count of rows whose Alg. 1 path was not reproduced) of the last
+        tape_backward; the total derivative along the motion's velocity is dU + this"""
+        g = np.zeros(2)
+        m = ctypes.c_int()
+        self._check(lib().gp_tape_path_gradient(self._h, _ptr(g), ctypes.byref(m)), "gp_tape_path_gradient")
+        return g, m.value

@@ -143,3 +143,77 @@ def test_gradient_matches_gpu_finite_differences():
     check(fd, float(gU[0]), "U offset x", 1e-5)
     # the run is left at its end state
     assert out["stats"]["cycles"] > 0
+
+
+def test_reverse_pass_is_deterministic():
+    """Two identical forward runs and reverse passes give bit-identical gradients (no atomics in the scatters)."""
+    N, nsteps, K = 64, 6, 2
+    say(f"[tape determinism] N={N} steps={nsteps}")
+    coeffs = wl.adjoint_coeffs(seed=1)
+    motion = wl.Motion(U=(0.1, 0.0))
+    outs = [adjoint_gradient(N, coeffs, motion, nsteps, K) for _ in range(2)]
+    assert outs[0][0] == outs[1][0]
+    assert np.array_equal(outs[0][1], outs[1][1])
+    assert np.array_equal(np.asarray(outs[0][2]), np.asarray(outs[1][2]))
+
+
+def _geometry_flips(N, motion_a, motion_b, times, eps_scale):
+    """discrete decisions of the geometry that differ between two motions at any of the times: classes, or a body
+    ghost's boundary point moving by more than eps_scale (a changed Alg. 1 branch moves it by a fixed fraction of h)"""
+    from paper_1911_00994_amd import gpmg
+    sides = [gpmg.Solver(N, Re=100.0) for _ in range(2)]
+    flips = 0
+    try:
+        for t in times:
+            rows = []
+            for s, mo in zip(sides, (motion_a, motion_b)):
+                s.set_levelset_analytic(CIRCLE.kind, CIRCLE.params, t, mo.as_array()[:5])
+                rows.append((s.classes(), s.ghost_rows()))
+            if not np.array_equal(rows[0][0], rows[1][0]):
+                flips += 1
+                continue
+            Ba, Bb = rows[0][1]["B"], rows[1][1]["B"]
+            m = ~np.isnan(Ba[:, 0])
+            flips += int((np.abs(Ba[m] - Bb[m]).max() > eps_scale))
+    finally:
+        for s in sides:
+            s.close()
+    return flips
+
+
+def test_path_gradient_matches_gpu_finite_differences():
+    """dJ/dU through the body path (the rows and boundary data of every step's geometry move with X(t) = X0 + U t,
+    discrete decisions frozen) plus the direct dependence of u_b on U, against central differences of the HIP
+    forward model in the motion's velocity; the difference quotient is taken with a step at which no discrete
+    decision of any step's geometry changes (checked)."""
+    from paper_1911_00994_amd import gpmg
+    N, nsteps, K = 64, 6, 2
+    h = 2.0 / N
+    coeffs = wl.adjoint_coeffs(seed=1)
+    # a velocity whose positions X(t) put no lattice point exactly on the circle (where the classification, and
+    # so the derivative, would be one-sided)
+    U0 = np.array([0.1137, 0.0471])
+    say(f"[path gradient] N={N} steps={nsteps} U={U0}")
+    J, s, u, v, cls = gpu_run(N, coeffs, wl.Motion(U=tuple(U0)), nsteps, K=K, keep=True)
+    seed_u = np.where(cls[0] == O.C_INT, 2 * h * h * u, 0.0)
+    seed_v = np.where(cls[1] == O.C_INT, 2 * h * h * v, 0.0)
+    out = s.tape_backward(seed_u, seed_v, tol=TOL, max_cycles=300)
+    gpath, unmatched = s.tape_path_gradient()
+    s.close()
+    assert unmatched == 0
+    total = np.asarray(out["dU"]) + gpath
+    say(f"  offset part {out['dU']}, path part {gpath}")
+    times = [(n + 1) * h for n in range(nsteps)]
+    for comp in range(2):
+        for eps in (1e-6, 3e-7, 1e-7, 3e-8):
+            e = np.zeros(2)
+            e[comp] = eps
+            mp, mm = wl.Motion(U=tuple(U0 + e)), wl.Motion(U=tuple(U0 - e))
+            if _geometry_flips(N, mp, mm, times, 1e3 * eps):
+                say(f"  component {comp}: eps {eps:.0e} changes a discrete decision, smaller step")
+                continue
+            fd = (gpu_run(N, coeffs, mp, nsteps, K=K) - gpu_run(N, coeffs, mm, nsteps, K=K)) / (2 * eps)
+            check(fd, float(total[comp]), f"dJ/dU_{comp} (path + direct)", 1e-5 if eps >= 1e-7 else 1e-4)
+            break
+        else:
+            pytest.fail("every step size changed a discrete decision")
