@@ -137,6 +137,68 @@ __global__ void __launch_bounds__(TPB) k_mt_xi(int W, const uint8_t *__restrict_
 // reference it (same-colour boxes share read-only neighbours, never unknowns, so an unknown of F gathers nothing).
 // The xi column collects sum of s_P (grid sum, added to xbar_xi by the last block).
 // ---------------------------------------------------------------------------------------------------------
+// the scatter of the transposed box colour as a gather.  A box at cell c with values sW, sE, sS, sN, sP (its W, E,
+// S, N faces and pressure) adds to the points c + o of the terms below (coefficient, and a condition on the box's
+// own unknowns where a face or the pressure is a fixed unknown of the box); point q gathers them from the boxes
+// c = q - o of the colour.
+//   u:  sW a at -1, -W, +W and at +1 (E fixed);  sE a at +2, +1-W, +1+W and at 0 (W fixed);
+//       sP -1/h at +1 (E fixed), +1/h at 0 (W fixed)
+//   v:  sS a at -W, -1, +1 and at +W (N fixed);  sN a at +2W, +W-1, +W+1 and at 0 (S fixed);
+//       sP -1/h at +W (N fixed), +1/h at 0 (S fixed)
+//   p:  sW +1/h at -1, -1/h at 0 (P fixed);  sE -1/h at +1, +1/h at 0 (P fixed);  sS +1/h at -W, -1/h at 0 (P fixed);
+//       sN -1/h at +W, +1/h at 0 (P fixed)
+__device__ __forceinline__ double box_gather(int N, int W, double h, double a, const uint8_t *__restrict__ cls,
+                                             const double *__restrict__ S, int colour, int t) {
+  const int WW = W * W;
+  const int g = t / WW, q = t - g * WW;
+  const double ih = 1.0 / h;
+  const double *sW = S, *sE = S + WW, *sS = S + 2 * WW, *sN = S + 3 * WW, *sP = S + 4 * WW;
+  // the box at cell (qi - di, qj - dj), if it is a cell of the grid and of this colour; its values at S[q - o],
+  // o = dj W + di
+  const int qi = q % W - 1, qj = q / W - 1;
+  auto box = [&](int di, int dj) {
+    const int i = qi - di, j = qj - dj;
+    return i >= 0 && i < N && j >= 0 && j < N && (i + 2 * j) % 5 == colour;
+  };
+  auto fixed = [&](int k) { return cls[k] != K_INT; };
+  double acc = 0;
+  if (g == 0) {
+    const bool fq = fixed(q);
+    if (box(-1, 0)) acc += a * sW[q + 1];
+    if (box(0, -1)) acc += a * sW[q + W];
+    if (box(0, 1)) acc += a * sW[q - W];
+    if (box(1, 0) && fq) acc += a * sW[q - 1];  // E face of box q - 1 is q
+    if (box(2, 0)) acc += a * sE[q - 2];
+    if (box(1, -1)) acc += a * sE[q - 1 + W];
+    if (box(1, 1)) acc += a * sE[q - 1 - W];
+    if (box(0, 0) && fq) acc += a * sE[q];  // W face of box q is q
+    if (box(1, 0) && fq) acc += -ih * sP[q - 1];
+    if (box(0, 0) && fq) acc += ih * sP[q];
+  } else if (g == 1) {
+    const bool fq = fixed(WW + q);
+    if (box(0, -1)) acc += a * sS[q + W];
+    if (box(-1, 0)) acc += a * sS[q + 1];
+    if (box(1, 0)) acc += a * sS[q - 1];
+    if (box(0, 1) && fq) acc += a * sS[q - W];  // N face of box q - W is q
+    if (box(0, 2)) acc += a * sN[q - 2 * W];
+    if (box(-1, 1)) acc += a * sN[q - W + 1];
+    if (box(1, 1)) acc += a * sN[q - W - 1];
+    if (box(0, 0) && fq) acc += a * sN[q];  // S face of box q is q
+    if (box(0, 1) && fq) acc += -ih * sP[q - W];
+    if (box(0, 0) && fq) acc += ih * sP[q];
+  } else {
+    const bool pf = fixed(2 * WW + q);
+    if (box(-1, 0)) acc += ih * sW[q + 1];
+    if (box(0, 0) && pf) acc += -ih * sW[q];
+    if (box(1, 0)) acc += -ih * sE[q - 1];
+    if (box(0, 0) && pf) acc += ih * sE[q];
+    if (box(0, -1)) acc += ih * sS[q + W];
+    if (box(0, 0) && pf) acc += -ih * sS[q];
+    if (box(0, 1)) acc += -ih * sN[q - W];
+    if (box(0, 0) && pf) acc += ih * sN[q];
+  }
+  return acc;
+}
 __device__ __forceinline__ double box_adj(int N, int W, double h, double a, double d, const uint8_t *__restrict__ cls,
                                           double *xb, double *bb, double *S, int i, int j) {
   const int WW = W * W, c = (j + 1) * W + (i + 1);
@@ -238,66 +300,11 @@ __global__ void __launch_bounds__(TPB) k_box_adj(int N, int W, double h, double 
   double tot;
   if (alast_total(sp, part, ticket, &tot) && threadIdx.x == 0) xb[3 * W * W] += tot;
 }
-
-// the scatter of the transposed box colour as a gather.  A box at cell c with values sW, sE, sS, sN, sP (its W, E,
-// S, N faces and pressure) adds to the points c + o of the terms below (coefficient, and a condition on the box's
-// own unknowns where a face or the pressure is a fixed unknown of the box); point q gathers them from the boxes
-// c = q - o of the colour.
-//   u:  sW a at -1, -W, +W and at +1 (E fixed);  sE a at +2, +1-W, +1+W and at 0 (W fixed);
-//       sP -1/h at +1 (E fixed), +1/h at 0 (W fixed)
-//   v:  sS a at -W, -1, +1 and at +W (N fixed);  sN a at +2W, +W-1, +W+1 and at 0 (S fixed);
-//       sP -1/h at +W (N fixed), +1/h at 0 (S fixed)
-//   p:  sW +1/h at -1, -1/h at 0 (P fixed);  sE -1/h at +1, +1/h at 0 (P fixed);  sS +1/h at -W, -1/h at 0 (P fixed);
-//       sN -1/h at +W, +1/h at 0 (P fixed)
 __global__ void __launch_bounds__(TPB) k_box_adj_g(int N, int W, double h, double a, const uint8_t *__restrict__ cls,
                                                    const double *__restrict__ S, int colour, double *xb) {
-  const int WW = W * W;
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= 3 * WW) return;
-  const int g = t / WW, q = t - g * WW;
-  const double ih = 1.0 / h;
-  const double *sW = S, *sE = S + WW, *sS = S + 2 * WW, *sN = S + 3 * WW, *sP = S + 4 * WW;
-  // the box at cell index c, if it is a cell of the grid and of this colour
-  auto box = [&](int c) {
-    if (c < 0 || c >= WW) return false;
-    const int i = c % W - 1, j = c / W - 1;
-    return i >= 0 && i < N && j >= 0 && j < N && (i + 2 * j) % 5 == colour;
-  };
-  auto fixed = [&](int k) { return cls[k] != K_INT; };
-  double acc = 0;
-  if (g == 0) {
-    if (box(q + 1)) acc += a * sW[q + 1];
-    if (box(q + W)) acc += a * sW[q + W];
-    if (box(q - W)) acc += a * sW[q - W];
-    if (box(q - 1) && fixed(q)) acc += a * sW[q - 1];  // E face of box q - 1 is q
-    if (box(q - 2)) acc += a * sE[q - 2];
-    if (box(q - 1 + W)) acc += a * sE[q - 1 + W];
-    if (box(q - 1 - W)) acc += a * sE[q - 1 - W];
-    if (box(q) && fixed(q)) acc += a * sE[q];  // W face of box q is q
-    if (box(q - 1) && fixed(q)) acc += -ih * sP[q - 1];
-    if (box(q) && fixed(q)) acc += ih * sP[q];
-  } else if (g == 1) {
-    if (box(q + W)) acc += a * sS[q + W];
-    if (box(q + 1)) acc += a * sS[q + 1];
-    if (box(q - 1)) acc += a * sS[q - 1];
-    if (box(q - W) && fixed(WW + q)) acc += a * sS[q - W];  // N face of box q - W is q
-    if (box(q - 2 * W)) acc += a * sN[q - 2 * W];
-    if (box(q - W + 1)) acc += a * sN[q - W + 1];
-    if (box(q - W - 1)) acc += a * sN[q - W - 1];
-    if (box(q) && fixed(WW + q)) acc += a * sN[q];  // S face of box q is q
-    if (box(q - W) && fixed(WW + q)) acc += -ih * sP[q - W];
-    if (box(q) && fixed(WW + q)) acc += ih * sP[q];
-  } else {
-    const bool pf = fixed(2 * WW + q);
-    if (box(q + 1)) acc += ih * sW[q + 1];
-    if (box(q) && pf) acc += -ih * sW[q];
-    if (box(q - 1)) acc += -ih * sE[q - 1];
-    if (box(q) && pf) acc += ih * sE[q];
-    if (box(q + W)) acc += ih * sS[q + W];
-    if (box(q) && pf) acc += -ih * sS[q];
-    if (box(q - W)) acc += -ih * sN[q - W];
-    if (box(q) && pf) acc += ih * sN[q];
-  }
+  if (t >= 3 * W * W) return;
+  const double acc = box_gather(N, W, h, a, cls, S, colour, t);
   if (acc != 0.0) xb[t] += acc;
 }
 
@@ -344,7 +351,7 @@ __global__ void k_xbt_t(int lo, int hi, const int *__restrict__ idx, const int *
 // the scatter of the transposed coupled boxes as a gather over the slot table: entry z = 0 of slot s is bbar on its
 // point (+t_s); entries z = 1.. are the columns of its row (xbar -= t_s times the row's coefficient): the internal
 // momentum row (d on itself, -a on the four neighbours, the pressure difference / h), the internal continuity row
-// (the four face differences / h and -1 for xi), or a ghost row (its 9 weights)
+// (the four face differences / h; its -1 for xi is k_xt_xi's), or a ghost row (its 9 weights)
 __device__ __forceinline__ double xt_coef(int k, int z, int W, double h, double a, double d,
                                           const uint8_t *__restrict__ cls, const int *__restrict__ g_rowof,
                                           const double *__restrict__ g_w) {
@@ -352,9 +359,23 @@ __device__ __forceinline__ double xt_coef(int k, int z, int W, double h, double 
   if (cls[k] != K_INT) return -g_w[9 * g_rowof[k] + z - 1];
   const double ih = 1.0 / h;
   if (k / WW < 2) return z == 1 ? -d : (z <= 5 ? a : (z == 6 ? -ih : ih));
-  return z == 5 ? 1.0 : ((z & 1) ? -ih : ih);
+  return (z & 1) ? -ih : ih;
 }
-__global__ void k_xt_apply(int lo, int hi, const int *__restrict__ tl, const int *__restrict__ off,
+// the xi column of the transposed coupled boxes: xbar_xi += sum of t_s over the internal continuity slots of
+// [lo, hi) (block partials in slot order, summed by the last block)
+__global__ void __launch_bounds__(TPB) k_xt_xi(int lo, int hi, int W, const uint8_t *__restrict__ cls,
+                                               const int *__restrict__ idx, const double *__restrict__ t, double *xb,
+                                               double *part, unsigned *ticket) {
+  const int WW = W * W;
+  double acc = 0;
+  for (int sl = lo + blockIdx.x * blockDim.x + threadIdx.x; sl < hi; sl += gridDim.x * blockDim.x) {
+    const int k = idx[sl];
+    if (k >= 2 * WW && cls[k] == K_INT) acc += t[sl];
+  }
+  double tot;
+  if (alast_total(acc, part, ticket, &tot) && threadIdx.x == 0) xb[3 * WW] += tot;
+}
+__global__ void k_xt_apply(int lo, const int *__restrict__ tl, const int *__restrict__ off,
                            const int *__restrict__ ent, const int *__restrict__ nt, int W, double h, double a, double d,
                            const uint8_t *__restrict__ cls, const int *__restrict__ idx, const int *__restrict__ g_rowof,
                            const double *__restrict__ g_w, const double *__restrict__ t, double *xb, double *bb) {
@@ -363,8 +384,7 @@ __global__ void k_xt_apply(int lo, int hi, const int *__restrict__ tl, const int
   double accb = 0, accx = 0;
   bool any = false;
   for (int q = off[s]; q < off[s + 1]; q++) {
-    const int e = ent[q], sl = e / 10, z = e - 10 * sl;
-    if (sl < lo || sl >= hi) continue;
+    const int e = ent[q], sl = lo + e / 10, z = e % 10;
     const double v = t[sl];
     if (v == 0.0) continue;
     any = true;
@@ -675,11 +695,12 @@ __global__ void k_tt_tgt_ext(const int *__restrict__ src, int n, int *tgt) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e < n) tgt[e] = src[3 * (e / 3)] < 0 ? -1 : src[e];
 }
-__global__ void k_tt_tgt_xb(int nxs, int W, const uint8_t *__restrict__ cls, const int *__restrict__ idx,
+// entries 10 (s - lo) + z of the slots s in [lo, lo + ns)
+__global__ void k_tt_tgt_xb(int lo, int ns, int W, const uint8_t *__restrict__ cls, const int *__restrict__ idx,
                             const int *__restrict__ g_rowof, const int *__restrict__ g_col, int *tgt) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= 10 * nxs) return;
-  const int sl = e / 10, z = e - 10 * sl, k = idx[sl], WW = W * W;
+  if (e >= 10 * ns) return;
+  const int sl = lo + e / 10, z = e % 10, k = idx[sl], WW = W * W;
   int t = -1;
   if (z == 0) {
     t = k;
@@ -691,8 +712,10 @@ __global__ void k_tt_tgt_xb(int nxs, int W, const uint8_t *__restrict__ cls, con
       const int tt[7] = {k, k - 1, k + 1, k - W, k + W, 2 * WW + q, 2 * WW + q - (g == 0 ? 1 : W)};
       if (z <= 7) t = tt[z - 1];
     } else {
-      const int tt[5] = {q + 1, q, WW + q + W, WW + q, 3 * WW};
-      if (z <= 5) t = tt[z - 1];
+      // the xi column (every internal continuity row) is summed by k_xt_xi: a table segment that long would be
+      // slow to order
+      const int tt[4] = {q + 1, q, WW + q + W, WW + q};
+      if (z <= 4) t = tt[z - 1];
     }
   }
   tgt[e] = t;
@@ -854,18 +877,22 @@ static gp_status ensure_tabs(Ctx *ctx) {
       k_tt_tgt_ext<<<nblk(3 * G.ne), TPB, 0, s>>>(G.e_src, 3 * G.ne, tgt);
     });
     if (st) return st;
-    const int nxs = (ctx->prm.ghost_boxes && G.nxb) ? G.nxs : 0;
-    st = tt_build(ctx, A.xt, 10 * nxs, T, nullptr, 10, [&](int *tgt) {
-      k_tt_tgt_xb<<<nblk(10 * nxs), TPB, 0, s>>>(nxs, G.W, G.cls, G.xb_idx, G.g_rowof, G.g_col, tgt);
-    });
-    if (st) return st;
+    const bool xb = ctx->prm.ghost_boxes && G.nxb;
+    for (int c = 0; c < 5; c++) {
+      const int lo = G.xb_soff[c], ns = xb ? G.xb_soff[c + 1] - lo : 0;
+      st = tt_build(ctx, A.xt[c], 10 * ns, T, nullptr, 10, [&](int *tgt) {
+        k_tt_tgt_xb<<<nblk(10 * ns), TPB, 0, s>>>(lo, ns, G.W, G.cls, G.xb_idx, G.g_rowof, G.g_col, tgt);
+      });
+      if (st) return st;
+    }
     A.gen = G.gen;
   }
   return GP_OK;
 }
 void adjoint_free_tabs(Ctx *ctx) {
   for (int l = 0; l < MAXLEV; l++)
-    for (TTab *t : {&ctx->atab[l].gt, &ctx->atab[l].et, &ctx->atab[l].xt}) {
+    for (TTab *t : {&ctx->atab[l].gt, &ctx->atab[l].et, &ctx->atab[l].xt[0], &ctx->atab[l].xt[1], &ctx->atab[l].xt[2],
+                     &ctx->atab[l].xt[3], &ctx->atab[l].xt[4]}) {
       ifree(t->tl);
       ifree(t->off);
       ifree(t->ent);
@@ -953,10 +980,12 @@ static void xb_relax_t(Ctx *ctx, int l) {
     if (hi == lo) continue;
     k_xbt_t<<<nblk(hi - lo), TPB, 0, s>>>(lo, hi, G.xb_idx, G.xb_box, G.xb_off, G.xb_ioff, G.xb_wr, G.xb_ok, G.xb_inv, A.x,
                                         G.xb_r);
-    const TTab &X = ctx->atab[l].xt;
+    const TTab &X = ctx->atab[l].xt[c];
     if (X.ne)
-      k_xt_apply<<<tt_blocks(X, 3 * G.WW + 1), TPB, 0, s>>>(lo, hi, X.tl, X.off, X.ent, X.d_nt, G.W, G.h, a, d, G.cls,
+      k_xt_apply<<<tt_blocks(X, 3 * G.WW + 1), TPB, 0, s>>>(lo, X.tl, X.off, X.ent, X.d_nt, G.W, G.h, a, d, G.cls,
                                                            G.xb_idx, G.g_rowof, G.g_w, G.xb_r, A.x, A.b);
+    k_xt_xi<<<std::min(ARED, nblk(hi - lo)), TPB, 0, s>>>(lo, hi, G.W, G.cls, G.xb_idx, G.xb_r, A.x, ctx->d_red,
+                                                        ctx->d_ticket);
   }
 }
 
@@ -1300,8 +1329,9 @@ static gp_status adjoint_step(Ctx *ctx, const CnSnap &pre, const CnSnap &post, d
   hipStream_t s = ctx->stream;
   const size_t WW = G.WW, n = G.n;
   gp_status st = GP_OK;
-  ctx->alpha = T.dt / (2.0 * ctx->Re);
-  ctx->c_ok = 0;
+  const double alpha = T.dt / (2.0 * ctx->Re);
+  if (alpha != ctx->alpha) ctx->c_ok = 0;  // the geometry build factored the coarsest system for the current alpha
+  ctx->alpha = alpha;
   if ((st = ready(ctx))) return st;
   const double *y = post.buf;  // x^{n+1} (extension values filled)
   double *R[4];  // adjoints of c^{n+1}, c^n, c^{n-1}, c^{n-2} (u grid, then v grid)
@@ -1313,7 +1343,8 @@ static gp_status adjoint_step(Ctx *ctx, const CnSnap &pre, const CnSnap &post, d
   // adjoint of the extension fill, then of the solve
   ext_fill_t(ctx, 0, T.xb);
   k_copy<<<nblk(n), TPB, 0, s>>>(ctx->a_g, T.xb, n);
-  k_fill0<<<nblk(n), TPB, 0, s>>>(ctx->a_lam, n);
+  // the previous step's adjoint as the initial guess (steps change smoothly; the first reversed step starts at 0)
+  k_mask_unknowns<<<nblk(3L * G.WW), TPB, 0, s>>>(3 * G.WW, G.cls, ctx->a_lam);
   gp_stats sub{};
   st = adjoint_solve_dev(ctx, tol, max_cycles, &sub);
   if (st != GP_OK && st != GP_ENOCONV) return st;
@@ -1432,6 +1463,7 @@ gp_status tape_backward(Ctx *ctx, const double *seed_u, const double *seed_v, in
   if (!T.d_mism) GP_HIP(hipMalloc((void **)&T.d_mism, sizeof(int)));
   k_izero<<<1, 1, 0, s>>>(T.d_mism, 1);
   T.ring_head = 0;
+  k_fill0<<<nblk((long)n), TPB, 0, s>>>(ctx->a_lam, (long)n);
   hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
   if (seed_u) GP_HIP(hipMemcpyAsync(T.xb, seed_u, WW * sizeof(double), kind, s));
   if (seed_v) GP_HIP(hipMemcpyAsync(T.xb + WW, seed_v, WW * sizeof(double), kind, s));
@@ -1442,14 +1474,18 @@ gp_status tape_backward(Ctx *ctx, const double *seed_u, const double *seed_v, in
   for (int sg = nseg - 1; sg >= 0; sg--) {
     const int s0 = sg * K, s1 = std::min(s0 + K, T.nsteps);
     if ((st = snap_restore(ctx, T.ckpt[sg]))) return st;
-    for (int m = s0; m < s1; m++) {
+    // the states inside the segment are replayed; the state after its last step is the next checkpoint (or the
+    // end of the run), which the forward run kept (the steps are deterministic, so a replay would reproduce it)
+    for (int m = s0; m < s1 - 1; m++) {
       if ((st = snap_save(ctx, T.seg[m - s0]))) return st;
       if ((st = tape_step(ctx, m, &sub))) return st;
     }
-    if ((st = snap_save(ctx, T.seg[s1 - s0]))) return st;
+    if ((st = snap_save(ctx, T.seg[s1 - 1 - s0]))) return st;
+    const CnSnap &end = sg + 1 < nseg ? T.ckpt[sg + 1] : T.last;
     for (int m = s1 - 1; m >= s0; m--) {
       if ((st = tape_geometry(ctx, m))) return st;
-      if ((st = adjoint_step(ctx, T.seg[m - s0], T.seg[m + 1 - s0], tol, max_cycles, &acc))) return st;
+      const CnSnap &post = m == s1 - 1 ? end : T.seg[m + 1 - s0];
+      if ((st = adjoint_step(ctx, T.seg[m - s0], post, tol, max_cycles, &acc))) return st;
     }
   }
   // c^0 = c(u^0) entered the first steps: its adjoint goes to u^0

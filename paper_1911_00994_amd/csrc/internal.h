@@ -123,7 +123,8 @@ struct TTab {
 };
 struct AdjTabs {
   long gen = -1;                    // Geo::gen of the tables below
-  TTab gt, et, xt;                  // ghost rows (K = 9), extension points (K = 3), coupled-box slots (K = 10)
+  TTab gt, et, xt[5];               // ghost rows (K = 9), extension points (K = 3), coupled-box slots of each
+                                    // colour (K = 10)
 };
 
 // one precision's vectors on one level

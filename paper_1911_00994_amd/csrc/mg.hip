@@ -723,12 +723,19 @@ __global__ void __launch_bounds__(BAND_T) k_xi_faces(int WW, double h, T *x, con
 // keeps the tables of its rows in registers for every sweep and its new values in registers between the read and
 // the write phase of a sweep; the face codes are loaded with the tables.
 constexpr int GX_F = 4;  // face codes per thread loaded ahead
-template <typename T>
+// R rows per thread (ng <= R * BAND_T)
+template <typename T, int R>
 __global__ void __launch_bounds__(BAND_T) k_ghost_xi(const int *__restrict__ pt, const int *__restrict__ col,
-                                                     const double *__restrict__ w, const double *__restrict__ dtau, int ng,
-                                                     T *x, const T *__restrict__ b, int sweeps, int WW, double h,
+                                                     const int *__restrict__ colr, const double *__restrict__ w,
+                                                     const double *__restrict__ dtau, int ng, T *x,
+                                                     const T *__restrict__ b, int sweeps, int WW, double h,
+                                                     const uint8_t *__restrict__ cls, const int *__restrict__ rowof,
                                                      const int *__restrict__ f_code, int nf,
                                                      const double *__restrict__ gp, int ngp, const int *__restrict__ mp) {
+  // with colr (every ghost column given as -(its row + 1)) the ghost values live in LDS by row during the sweeps:
+  // the other columns do not change in a ghost sweep, so every global load goes out before the first sweep and
+  // the sweeps and the face sum read registers and LDS only
+  __shared__ double gv[R * BAND_T];
   const int tid = threadIdx.x;
   const GpPre gpre = gp_start(gp, ngp);
   int fc[GX_F];
@@ -736,25 +743,87 @@ __global__ void __launch_bounds__(BAND_T) k_ghost_xi(const int *__restrict__ pt,
   for (int j = 0; j < GX_F; j++) fc[j] = tid + j * BAND_T < nf ? f_code[tid + j * BAND_T] : 0;
   // a thread without a second row computes a dummy one (point 0, weights 0) and does not store it, so that the
   // loads of both rows go out together
-  int kk[2], cc[2][9];
-  double ww[2][9], dt[2];
-  bool has[2];
+  int kk[R], cc[R][9];
+  double ww[R][9], dt[R];
+  bool has[R];
+  const int *cs = (R == 1 && colr) ? colr : col;
 #pragma unroll
-  for (int i = 0; i < 2; i++) {
+  for (int i = 0; i < R; i++) {
     const int r = tid + i * BAND_T;
     has[i] = r < ng;
     kk[i] = has[i] ? pt[r] : 0;
     dt[i] = has[i] ? dtau[r] : 0.0;
 #pragma unroll
     for (int z = 0; z < 9; z++) {
-      cc[i][z] = has[i] ? col[9 * r + z] : 0;
+      cc[i][z] = has[i] ? cs[9 * r + z] : 0;
       ww[i][z] = has[i] ? w[9 * r + z] : 0.0;
     }
   }
-  for (int it = 0; it < sweeps; it++) {
-    double nv[2];
+  if (R == 1 && colr) {
+    double xv[R][9], bb[R];
+    int fr[GX_F];
+    double fv[GX_F];
 #pragma unroll
-    for (int i = 0; i < 2; i++) {
+    for (int i = 0; i < R; i++) {
+#pragma unroll
+      for (int z = 0; z < 9; z++) xv[i][z] = cc[i][z] >= 0 ? (double)x[cc[i][z]] : 0.0;
+      bb[i] = (double)b[kk[i]];
+      if (has[i]) gv[tid + i * BAND_T] = (double)x[kk[i]];
+    }
+#pragma unroll
+    for (int j = 0; j < GX_F; j++) {
+      fr[j] = -1;
+      fv[j] = 0.0;
+      if (tid + j * BAND_T < nf) {
+        const int k = fc[j] >> 1;
+        const uint8_t c = cls[k];
+        if (c == K_GHOST || c == K_GHOSTX || c == K_WALLG)
+          fr[j] = rowof[k];
+        else
+          fv[j] = (double)x[k];
+      }
+    }
+    __syncthreads();
+    for (int it = 0; it < sweeps; it++) {
+      double nv[R];
+#pragma unroll
+      for (int i = 0; i < R; i++) {
+        double s = 0;
+#pragma unroll
+        for (int z = 0; z < 9; z++) s += ww[i][z] * (cc[i][z] >= 0 ? xv[i][z] : gv[-cc[i][z] - 1]);
+        nv[i] = (has[i] ? gv[tid + i * BAND_T] : 0.0) + dt[i] * (bb[i] - s);
+      }
+      __syncthreads();
+#pragma unroll
+      for (int i = 0; i < R; i++)
+        if (has[i]) gv[tid + i * BAND_T] = (double)(T)nv[i];
+      __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < R; i++)
+      if (has[i]) x[kk[i]] = (T)gv[tid + i * BAND_T];
+    double fs = 0;
+#pragma unroll
+    for (int j = 0; j < GX_F; j++)
+      if (tid + j * BAND_T < nf) {
+        const double v = fr[j] >= 0 ? gv[fr[j]] : fv[j];
+        fs += (fc[j] & 1) ? -v : v;
+      }
+    for (int q = tid + GX_F * BAND_T; q < nf; q += BAND_T) {
+      const int k = f_code[q] >> 1;
+      const uint8_t c = cls[k];
+      const double v = (c == K_GHOST || c == K_GHOSTX || c == K_WALLG) ? gv[rowof[k]] : (double)x[k];
+      fs += (f_code[q] & 1) ? -v : v;
+    }
+    fs = band_block_sum(fs);
+    const double gsum = gp_total(gpre, gp, ngp);
+    if (tid == 0) x[3 * WW] = (T)((fs / h - gsum) / *mp);
+    return;
+  }
+  for (int it = 0; it < sweeps; it++) {
+    double nv[R];
+#pragma unroll
+    for (int i = 0; i < R; i++) {
       double s = 0;
 #pragma unroll
       for (int z = 0; z < 9; z++) s += ww[i][z] * (double)x[cc[i][z]];
@@ -762,7 +831,7 @@ __global__ void __launch_bounds__(BAND_T) k_ghost_xi(const int *__restrict__ pt,
     }
     __syncthreads();
 #pragma unroll
-    for (int i = 0; i < 2; i++)
+    for (int i = 0; i < R; i++)
       if (has[i]) x[kk[i]] = (T)nv[i];
     __syncthreads();
   }
@@ -1972,7 +2041,7 @@ static void xb_relax(Ctx *ctx, int l) {
   hipStream_t s = ctx->stream;
   const double a = coef_a(ctx, l), d = 1.0 + 4.0 * a;
   const XbTab X = xb_tab(G);
-  if (G.xb_maxs < ctx->band_split_min) {
+  if (G.xb_maxs <= XW_T) {  // at most one slot per thread and colour: one workgroup, no launch per phase
     XbOff so;
     for (int c = 0; c < 6; c++) so.o[c] = G.xb_soff[c];
     k_xb_wg<T><<<1, XW_T, 0, s>>>(so, G.W, G.h, a, d, G.cls, V.x, V.b, X, G.xb_r);
@@ -2088,8 +2157,15 @@ static void relax(Ctx *ctx, int l) {
   }
   if (!band && G.ng <= 2 * BAND_T) {
     // the ghost sweeps and xi in one workgroup (a few rows per thread)
-    k_ghost_xi<T><<<1, BAND_T, 0, s>>>(G.g_pt, G.g_col, G.g_w, G.g_dtau, G.ng, V.x, V.b, ctx->prm.lambda_ghost, G.WW,
-                                      G.h, G.f_code, G.nf, ctx->gs_ptr[l], ctx->gs_n[l], G.d_mp);
+    // one row per thread: the sweeps run from registers and LDS (below 128 registers); two: from global memory
+    if (G.ng <= BAND_T)
+      k_ghost_xi<T, 1><<<1, BAND_T, 0, s>>>(G.g_pt, G.g_col, G.colr_ok ? G.g_colr : nullptr, G.g_w, G.g_dtau, G.ng,
+                                             V.x, V.b, ctx->prm.lambda_ghost, G.WW, G.h, G.cls, G.g_rowof, G.f_code,
+                                             G.nf, ctx->gs_ptr[l], ctx->gs_n[l], G.d_mp);
+    else
+      k_ghost_xi<T, 2><<<1, BAND_T, 0, s>>>(G.g_pt, G.g_col, nullptr, G.g_w, G.g_dtau, G.ng, V.x, V.b,
+                                             ctx->prm.lambda_ghost, G.WW, G.h, G.cls, G.g_rowof, G.f_code, G.nf,
+                                             ctx->gs_ptr[l], ctx->gs_n[l], G.d_mp);
     return;
   }
   if (!band && G.ng) {
