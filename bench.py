@@ -21,7 +21,7 @@ sys.path.insert(0, ROOT)
 PEAK_HBM_GBS = 8000.0
 # HBM bytes per launch of the finest-level five-colour box kernel from the two rocprofv3 counter runs (FETCH_SIZE
 # and WRITE_SIZE, each scaled by what it reads for a 64 MiB device copy); None until taken for the current kernel
-BOX_TRAFFIC_BYTES = 89.20e6
+BOX_TRAFFIC_BYTES = 89.43e6
 BOX_TRAFFIC_SOURCE = "profiles/k_box5_flower1024_hbm_traffic.md"
 # the launch probe times every 5th finest box sweep (5 is prime to the 4 finest sweeps of a V(2,2) cycle, so all
 # four positions are sampled in turn); each timed dispatch leaves the device idle for several microseconds
