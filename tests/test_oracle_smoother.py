@@ -177,7 +177,8 @@ def test_paper_cycle_convergence_factor():
     """Sect. 5.3: W cycle, two pre- and one post-relaxation, lexicographic box order; the paper's
     reference factor is 0.119 (a local Fourier analysis value).  Measured on the paper's petal body."""
     rhos = [_rho(N, wl.paper_flower(), gamma=2, nu2=1, lex_order=1, ghost_box_levels=99) for N in (128, 256)]
-    assert max(rhos) < 0.2 and abs(rhos[0] - rhos[1]) < 0.05, rhos
+    # measured 0.125 and 0.130: the paper's factor to within 0.02, and the same on both grids
+    assert all(abs(r - 0.119) < 0.02 for r in rhos) and abs(rhos[0] - rhos[1]) < 0.02, rhos
 
 
 # --------------------------------------------------------------------------------------------
