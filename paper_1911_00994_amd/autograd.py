@@ -7,6 +7,11 @@ the library's reverse mode (gp_tape_backward): the gradients with respect to fu,
 come from the transposed solves of every step, replayed from checkpoints.  All arithmetic runs in the library;
 this module only hands device buffers across.  One backward pass per forward (the tape holds the last run of the
 solver).
+
+`cn_run_body(solver, fu, fv, U, run)` is the same run with the body's velocity U (2) as the differentiable input in
+place of the offset: the motion is X(t) = X0 + U t, and the gradient with respect to U is the direct part (u_b
+depends on U as on the offset) plus the part through the body path (gp_tape_path_gradient: the boundary rows of every
+step move with the body, their discrete decisions held fixed).
 """
 from __future__ import annotations
 
@@ -57,6 +62,32 @@ class CNRun(torch.autograd.Function):
                                        device_out=(dfu.data_ptr(), dfv.data_ptr(), None, None))
         dU = torch.tensor(out["dU"], dtype=ctx.off_dtype, device=ctx.off_device)
         return dfu, dfv, dU, None, None
+
+
+class CNRunBody(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, fu, fv, U, solver, run):
+        motion = [float(v) for v in run["motion"]]
+        motion[2], motion[3] = [float(v) for v in U.detach().cpu().to(torch.float64)]
+        body_run = dict(run, motion=motion)
+        off = torch.zeros(2, dtype=torch.float64)
+        u, v = CNRun.forward(ctx, fu, fv, off, solver, body_run)
+        ctx.u_dtype, ctx.u_device = U.dtype, U.device
+        return u, v
+
+    @staticmethod
+    def backward(ctx, gu, gv):
+        dfu, dfv, d_off, _, _ = CNRun.backward(ctx, gu, gv)
+        path, unmatched = ctx.solver.tape_path_gradient()
+        if unmatched:
+            raise RuntimeError(f"cn_run_body: {unmatched} boundary rows did not reproduce their Alg. 1 path")
+        dU = d_off.to(torch.float64).cpu() + torch.tensor(path, dtype=torch.float64)
+        return dfu, dfv, dU.to(dtype=ctx.u_dtype, device=ctx.u_device), None, None
+
+
+def cn_run_body(solver: "gpmg.Solver", fu: torch.Tensor, fv: torch.Tensor, U: torch.Tensor, run: dict):
+    """(u, v) at the end of the run with the body moving at velocity U, differentiable with respect to fu, fv and U"""
+    return CNRunBody.apply(fu, fv, U, solver, run)
 
 
 def cn_run(solver: "gpmg.Solver", fu: torch.Tensor, fv: torch.Tensor, ub_offset: torch.Tensor, run: dict):

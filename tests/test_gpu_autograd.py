@@ -90,3 +90,50 @@ def test_autograd_matches_tape_and_finite_differences():
     fd = (J_of(fu0, fv0, [eps, 0]) - J_of(fu0, fv0, [-eps, 0])) / (2 * eps)
     say(f"  U offset x: fd {fd:.10e} autograd {float(off.grad[0]):.10e}")
     assert abs(fd - float(off.grad[0])) <= 1e-6 * abs(fd)
+
+
+def test_body_velocity_gradient_through_autograd():
+    """cn_run_body: the gradient with respect to the body's velocity U (direct part plus the body-path part) against
+    central differences of the forward run in U; a velocity whose positions put no lattice point exactly on the
+    circle, and a step at which no discrete decision of any step's geometry changes (checked)."""
+    import torch
+    from paper_1911_00994_amd.autograd import cn_run_body
+    from tests.test_gpu_tape import _geometry_flips
+    say(f"[autograd body velocity] N={N} steps={NSTEPS}")
+    s, run = setup()
+    h = 2.0 / N
+    fu0, fv0 = wl.streamfunction_forcing(N, wl.adjoint_coeffs(seed=1))
+    dev = torch.device("cuda:0")
+    U0 = np.array([0.1137, 0.0471])
+    reset(s, run)
+    cls = s.classes()
+    mu = torch.tensor(cls[0] == 1, dtype=torch.float64, device=dev)
+    mv = torch.tensor(cls[1] == 1, dtype=torch.float64, device=dev)
+    fu = torch.tensor(fu0, device=dev)
+    fv = torch.tensor(fv0, device=dev)
+    U = torch.tensor(U0, dtype=torch.float64, requires_grad=True)
+    u, v = cn_run_body(s, fu, fv, U, run)
+    objective(u, v, mu, mv, h).backward()
+    g = U.grad.numpy().copy()
+
+    def J_of(Ua):
+        reset(s, run)
+        with torch.no_grad():
+            uu, vv = cn_run_body(s, fu, fv, torch.tensor(Ua, dtype=torch.float64), run)
+        return float(objective(uu, vv, mu, mv, h))
+
+    times = [(n + 1) * h for n in range(NSTEPS)]
+    for comp in range(2):
+        for eps in (1e-6, 3e-7, 1e-7):
+            e = np.zeros(2)
+            e[comp] = eps
+            if _geometry_flips(N, wl.Motion(U=tuple(U0 + e)), wl.Motion(U=tuple(U0 - e)), times, 1e3 * eps):
+                continue
+            fd = (J_of(U0 + e) - J_of(U0 - e)) / (2 * eps)
+            err = abs(fd - g[comp]) / abs(fd)
+            say(f"  dJ/dU_{comp}: fd {fd:.10e} autograd {g[comp]:.10e} rel {err:.2e}")
+            assert err < 1e-5
+            break
+        else:
+            pytest.fail("every step size changed a discrete decision")
+    s.close()
