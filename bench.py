@@ -219,6 +219,8 @@ def parse():
     ap.add_argument("--no-cavity", action="store_true", help="skip the N = 2048 cavity time-to-tolerance comparison")
     ap.add_argument("--krylov", type=int, default=None,
                     help="GCR restart length of the solver (library default when not given; 0: the plain cycle)")
+    ap.add_argument("--cycle", default=None,
+                    help="nu1,nu2,gamma of the solver's cycle (library default V(2,2) when not given)")
     ap.add_argument("--profile-kernel", action="store_true",
                     help="set up the N=1024 system, run a plain 64 MiB device copy (counter calibration) and 10 "
                          "launches of the five-colour box sweep on the finest level, then exit (for rocprofv3 "
@@ -247,7 +249,10 @@ def main():
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream(dev)
     extra = {} if args.krylov is None else {"krylov": args.krylov}
+    if args.cycle:
+        extra.update(zip(("nu1", "nu2", "gamma"), (int(v) for v in args.cycle.split(","))))
     solver = gpmg.Solver(N, Re=Re, stream=stream.cuda_stream, graph_iterations=1 if args.graphs else 0, **extra)
+    cyc = f"{'W' if solver._p.gamma == 2 else 'V'}({solver._p.nu1},{solver._p.nu2})"
     fu, fv = wl.fourier_forcing(N, seed=0)
     fu_d = torch.from_numpy(fu).to(dev)
     fv_d = torch.from_numpy(fv).to(dev)
@@ -367,8 +372,8 @@ def main():
         "dtype": "f64" if prec == gpmg.GP_FP64 else "f32+f64",
         "data": "synthetic",
         "config": {"workload": wk.name, "N": N, "Re": Re, "dt": "h", "tol": args.tol,
-                   "solver": (f"GCR({solver._p.krylov}) around V(2,2) cycles" if solver._p.krylov > 0 else
-                              "V(2,2) cycles") + " (coupled ghost boxes on the finest level)",
+                   "solver": (f"GCR({solver._p.krylov}) around {cyc} cycles" if solver._p.krylov > 0 else
+                              f"{cyc} cycles") + " (coupled ghost boxes on the finest level)",
                    "precision": args.precision, "unknowns": n_unk, "cycles": cycles,
                    "cycles_per_step": cycles / args.steps, "wall_s": wall,
                    "cycle_level_hbm_fraction": cyc_gbs / PEAK_HBM_GBS},
