@@ -2409,19 +2409,38 @@ __global__ void k_zero2(double *a, double *b, long n) {
   const long q = blockIdx.x * (long)blockDim.x + threadIdx.x;
   if (q < n) a[q] = b[q] = 0.0;
 }
-// acc[0..1] += scale * (sum of cx, sum of cy) over the points, in a fixed order (one workgroup)
-__global__ void __launch_bounds__(1024) k_path_sum(const double *__restrict__ cx, const double *__restrict__ cy, long n,
-                                                   double scale, double *acc) {
-  __shared__ double sa[1024], sb[1024];
+// acc[0..1] += scale * (sum of cx, sum of cy) over the points, in a fixed order: PS_B block partials of a fixed
+// grid-stride split (k_path_part), then their sum in block order (k_path_fin)
+constexpr int PS_B = 256, PS_T = 256;
+__global__ void __launch_bounds__(PS_T) k_path_part(const double *__restrict__ cx, const double *__restrict__ cy, long n,
+                                                    double *part) {
+  __shared__ double sa[PS_T], sb[PS_T];
   double a = 0, b = 0;
-  for (long q = threadIdx.x; q < n; q += 1024) {
+  for (long q = blockIdx.x * (long)PS_T + threadIdx.x; q < n; q += (long)PS_B * PS_T) {
     a += cx[q];
     b += cy[q];
   }
   sa[threadIdx.x] = a;
   sb[threadIdx.x] = b;
   __syncthreads();
-  for (int o = 512; o > 0; o >>= 1) {
+  for (int o = PS_T / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) {
+      sa[threadIdx.x] += sa[threadIdx.x + o];
+      sb[threadIdx.x] += sb[threadIdx.x + o];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    part[blockIdx.x] = sa[0];
+    part[PS_B + blockIdx.x] = sb[0];
+  }
+}
+__global__ void __launch_bounds__(PS_B) k_path_fin(const double *__restrict__ part, double scale, double *acc) {
+  __shared__ double sa[PS_B], sb[PS_B];
+  sa[threadIdx.x] = part[threadIdx.x];
+  sb[threadIdx.x] = part[PS_B + threadIdx.x];
+  __syncthreads();
+  for (int o = PS_B / 2; o > 0; o >>= 1) {
     if ((int)threadIdx.x < o) {
       sa[threadIdx.x] += sa[threadIdx.x + o];
       sb[threadIdx.x] += sb[threadIdx.x + o];
@@ -2457,7 +2476,8 @@ gp_status path_terms(Ctx *ctx, const gp_shape &sh, const gp_rigid &mo, double t,
   k_path_rows<<<nblk(G.ng), TPB, 0, s>>>(L, S, mo.omega, G.cls, G.W, row_args(G), ctx->prm.march_max, (int)nbis_d, x,
                                           lam, cx, cy, mism);
   // X(t) = X0 + U t: the partials along the position times t are those along U
-  k_path_sum<<<1, 1024, 0, s>>>(cx, cy, n, t, acc);
+  k_path_part<<<PS_B, PS_T, 0, s>>>(cx, cy, n, ctx->d_red);
+  k_path_fin<<<1, PS_B, 0, s>>>(ctx->d_red, t, acc);
   GP_HIP(hipGetLastError());
   return GP_OK;
 }
