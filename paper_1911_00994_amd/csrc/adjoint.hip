@@ -147,137 +147,144 @@ __global__ void __launch_bounds__(TPB) k_mt_xi(int W, const uint8_t *__restrict_
 //       sP -1/h at +W (N fixed), +1/h at 0 (S fixed)
 //   p:  sW +1/h at -1, -1/h at 0 (P fixed);  sE -1/h at +1, +1/h at 0 (P fixed);  sS +1/h at -W, -1/h at 0 (P fixed);
 //       sN -1/h at +W, +1/h at 0 (P fixed)
-__device__ __forceinline__ double box_gather(int N, int W, double h, double a, const uint8_t *__restrict__ cls,
+template <bool CMP>
+__device__ __forceinline__ double box_gather(int N, int W, double ih, double a, const uint8_t *__restrict__ cls,
                                              const double *__restrict__ S, int colour, int t) {
-  const int WW = W * W;
+  const int WW = W * W, K = N / 5 + 1, sst = CMP ? K * N : WW;
   const int g = t / WW, q = t - g * WW;
-  const double ih = 1.0 / h;
-  const double *sW = S, *sE = S + WW, *sS = S + 2 * WW, *sN = S + 3 * WW, *sP = S + 4 * WW;
-  // the box at cell (qi - di, qj - dj), if it is a cell of the grid and of this colour; its values at S[q - o],
-  // o = dj W + di
+  const double *sW = S, *sE = S + sst, *sS = S + 2 * sst, *sN = S + 3 * sst, *sP = S + 4 * sst;
   const int qi = q % W - 1, qj = q / W - 1;
-  auto box = [&](int di, int dj) {
+  // the box at cell (qi - di, qj - dj) has the colour when di + 2 dj = m (mod 5)
+  const int m = ((qi + 2 * qj - colour) % 5 + 5) % 5;
+  // index in S of that box (cell q - o, o = dj W + di; or its slot j K + i / 5 in the per-colour layout), or -1
+  // when it is outside the grid or of another colour
+  auto at = [&](int di, int dj) -> int {
     const int i = qi - di, j = qj - dj;
-    return i >= 0 && i < N && j >= 0 && j < N && (i + 2 * j) % 5 == colour;
+    if (m != ((di + 2 * dj) % 5 + 5) % 5 || i < 0 || i >= N || j < 0 || j >= N) return -1;
+    return CMP ? j * K + (int)((unsigned)i / 5u) : q - dj * W - di;
   };
   auto fixed = [&](int k) { return cls[k] != K_INT; };
   double acc = 0;
+  int k;
   if (g == 0) {
     const bool fq = fixed(q);
-    if (box(-1, 0)) acc += a * sW[q + 1];
-    if (box(0, -1)) acc += a * sW[q + W];
-    if (box(0, 1)) acc += a * sW[q - W];
-    if (box(1, 0) && fq) acc += a * sW[q - 1];  // E face of box q - 1 is q
-    if (box(2, 0)) acc += a * sE[q - 2];
-    if (box(1, -1)) acc += a * sE[q - 1 + W];
-    if (box(1, 1)) acc += a * sE[q - 1 - W];
-    if (box(0, 0) && fq) acc += a * sE[q];  // W face of box q is q
-    if (box(1, 0) && fq) acc += -ih * sP[q - 1];
-    if (box(0, 0) && fq) acc += ih * sP[q];
+    if ((k = at(-1, 0)) >= 0) acc += a * sW[k];
+    if ((k = at(0, -1)) >= 0) acc += a * sW[k];
+    if ((k = at(0, 1)) >= 0) acc += a * sW[k];
+    if ((k = at(1, 0)) >= 0 && fq) acc += a * sW[k];  // E face of box q - 1 is q
+    if ((k = at(2, 0)) >= 0) acc += a * sE[k];
+    if ((k = at(1, -1)) >= 0) acc += a * sE[k];
+    if ((k = at(1, 1)) >= 0) acc += a * sE[k];
+    if ((k = at(0, 0)) >= 0 && fq) acc += a * sE[k];  // W face of box q is q
+    if ((k = at(1, 0)) >= 0 && fq) acc += -ih * sP[k];
+    if ((k = at(0, 0)) >= 0 && fq) acc += ih * sP[k];
   } else if (g == 1) {
     const bool fq = fixed(WW + q);
-    if (box(0, -1)) acc += a * sS[q + W];
-    if (box(-1, 0)) acc += a * sS[q + 1];
-    if (box(1, 0)) acc += a * sS[q - 1];
-    if (box(0, 1) && fq) acc += a * sS[q - W];  // N face of box q - W is q
-    if (box(0, 2)) acc += a * sN[q - 2 * W];
-    if (box(-1, 1)) acc += a * sN[q - W + 1];
-    if (box(1, 1)) acc += a * sN[q - W - 1];
-    if (box(0, 0) && fq) acc += a * sN[q];  // S face of box q is q
-    if (box(0, 1) && fq) acc += -ih * sP[q - W];
-    if (box(0, 0) && fq) acc += ih * sP[q];
+    if ((k = at(0, -1)) >= 0) acc += a * sS[k];
+    if ((k = at(-1, 0)) >= 0) acc += a * sS[k];
+    if ((k = at(1, 0)) >= 0) acc += a * sS[k];
+    if ((k = at(0, 1)) >= 0 && fq) acc += a * sS[k];  // N face of box q - W is q
+    if ((k = at(0, 2)) >= 0) acc += a * sN[k];
+    if ((k = at(-1, 1)) >= 0) acc += a * sN[k];
+    if ((k = at(1, 1)) >= 0) acc += a * sN[k];
+    if ((k = at(0, 0)) >= 0 && fq) acc += a * sN[k];  // S face of box q is q
+    if ((k = at(0, 1)) >= 0 && fq) acc += -ih * sP[k];
+    if ((k = at(0, 0)) >= 0 && fq) acc += ih * sP[k];
   } else {
     const bool pf = fixed(2 * WW + q);
-    if (box(-1, 0)) acc += ih * sW[q + 1];
-    if (box(0, 0) && pf) acc += -ih * sW[q];
-    if (box(1, 0)) acc += -ih * sE[q - 1];
-    if (box(0, 0) && pf) acc += ih * sE[q];
-    if (box(0, -1)) acc += ih * sS[q + W];
-    if (box(0, 0) && pf) acc += -ih * sS[q];
-    if (box(0, 1)) acc += -ih * sN[q - W];
-    if (box(0, 0) && pf) acc += ih * sN[q];
+    if ((k = at(-1, 0)) >= 0) acc += ih * sW[k];
+    if ((k = at(0, 0)) >= 0 && pf) acc += -ih * sW[k];
+    if ((k = at(1, 0)) >= 0) acc += -ih * sE[k];
+    if ((k = at(0, 0)) >= 0 && pf) acc += ih * sE[k];
+    if ((k = at(0, -1)) >= 0) acc += ih * sS[k];
+    if ((k = at(0, 0)) >= 0 && pf) acc += -ih * sS[k];
+    if ((k = at(0, 1)) >= 0) acc += -ih * sN[k];
+    if ((k = at(0, 0)) >= 0 && pf) acc += ih * sN[k];
   }
   return acc;
 }
-__device__ __forceinline__ double box_adj(int N, int W, double h, double a, double d, const uint8_t *__restrict__ cls,
-                                          double *xb, double *bb, double *S, int i, int j) {
+// the transposed solve of the box at cell (i, j); its five values go to S[f sst + si] for the faces f = W, E, S, N
+// and the pressure, and the return value is sP (for the xi column)
+__device__ __forceinline__ double box_adj(int W, const BoxK &BK, const uint8_t *__restrict__ cls, double *xb, double *bb,
+                                          double *S, int si, int sst, int i, int j) {
   const int WW = W * W, c = (j + 1) * W + (i + 1);
-  const bool fW = cls[c] == K_INT, fE = cls[c + 1] == K_INT, fS = cls[WW + c] == K_INT, fN = cls[WW + c + W] == K_INT,
-             fP = cls[2 * WW + c] == K_INT;
+  const int k0 = c, k1 = c + 1, k2 = WW + c, k3 = WW + c + W, k4 = 2 * WW + c;
+  // every load up front (all five indices are points of the level), so that they are in flight together
+  const uint8_t c0 = cls[k0], c1 = cls[k1], c2 = cls[k2], c3 = cls[k3], c4 = cls[k4];
+  const double x0 = xb[k0], x1 = xb[k1], x2 = xb[k2], x3 = xb[k3], x4 = xb[k4];
+  const double b0 = bb[k0], b1 = bb[k1], b2 = bb[k2], b3 = bb[k3], b4 = bb[k4];
+  const bool fW = c0 == K_INT, fE = c1 == K_INT, fS = c2 == K_INT, fN = c3 == K_INT, fP = c4 == K_INT;
   if (!(fW || fE || fS || fN || fP)) {
-    for (int f = 0; f < 5; f++) S[f * WW + c] = 0.0;
+    for (int f = 0; f < 5; f++) S[f * sst + si] = 0.0;
     return 0.0;
   }
-  const double ih = 1.0 / h, det = d * d - a * a;
   // right-hand side S y
-  const double rW = fW ? xb[c] : 0.0, rE = fE ? xb[c + 1] : 0.0, rS = fS ? xb[WW + c] : 0.0, rN = fN ? xb[WW + c + W] : 0.0,
-               rP = fP ? -xb[2 * WW + c] : 0.0;
+  const double rW = fW ? x0 : 0.0, rE = fE ? x1 : 0.0, rS = fS ? x2 : 0.0, rN = fN ? x3 : 0.0, rP = fP ? -x4 : 0.0;
   double aW = 0, bW = 0, aE = 0, bE = 0, aS = 0, bS = 0, aN = 0, bN = 0;
   if (fW && fE) {
-    aW = (d * rW + a * rE) / det;
-    bW = -ih / (d + a);
-    aE = (a * rW + d * rE) / det;
-    bE = ih / (d + a);
+    aW = BK.q1 * rW + BK.q2 * rE;
+    bW = -BK.bp;
+    aE = BK.q2 * rW + BK.q1 * rE;
+    bE = BK.bp;
   } else if (fW) {
-    aW = rW / d;
-    bW = -ih / d;
+    aW = rW * BK.id;
+    bW = -BK.ihd;
   } else if (fE) {
-    aE = rE / d;
-    bE = ih / d;
+    aE = rE * BK.id;
+    bE = BK.ihd;
   }
   if (fS && fN) {
-    aS = (d * rS + a * rN) / det;
-    bS = -ih / (d + a);
-    aN = (a * rS + d * rN) / det;
-    bN = ih / (d + a);
+    aS = BK.q1 * rS + BK.q2 * rN;
+    bS = -BK.bp;
+    aN = BK.q2 * rS + BK.q1 * rN;
+    bN = BK.bp;
   } else if (fS) {
-    aS = rS / d;
-    bS = -ih / d;
+    aS = rS * BK.id;
+    bS = -BK.ihd;
   } else if (fN) {
-    aN = rN / d;
-    bN = ih / d;
+    aN = rN * BK.id;
+    bN = BK.ihd;
   }
   double zP = 0;
   if (fP) {
     const double den = bE - bW + bN - bS;
     if (den == 0.0) {  // the forward sweep skips this box
-      for (int f = 0; f < 5; f++) S[f * WW + c] = 0.0;
+      for (int f = 0; f < 5; f++) S[f * sst + si] = 0.0;
       return 0.0;
     }
-    zP = (h * rP - (aE - aW + aN - aS)) / den;
+    zP = (BK.h * rP - (aE - aW + aN - aS)) / den;
   }
   const double sW = fW ? aW + bW * zP : 0.0, sE = fE ? aE + bE * zP : 0.0, sS = fS ? aS + bS * zP : 0.0,
                sN = fN ? aN + bN * zP : 0.0, sP = fP ? -zP : 0.0;
   if (fW) {
-    bb[c] += sW;
-    xb[c] = 0;
+    bb[k0] = b0 + sW;
+    xb[k0] = 0;
   }
   if (fE) {
-    bb[c + 1] += sE;
-    xb[c + 1] = 0;
+    bb[k1] = b1 + sE;
+    xb[k1] = 0;
   }
   if (fS) {
-    bb[WW + c] += sS;
-    xb[WW + c] = 0;
+    bb[k2] = b2 + sS;
+    xb[k2] = 0;
   }
   if (fN) {
-    bb[WW + c + W] += sN;
-    xb[WW + c + W] = 0;
+    bb[k3] = b3 + sN;
+    xb[k3] = 0;
   }
   if (fP) {
-    bb[2 * WW + c] += sP;
-    xb[2 * WW + c] = 0;
+    bb[k4] = b4 + sP;
+    xb[k4] = 0;
   }
-  S[c] = sW;
-  S[WW + c] = sE;
-  S[2 * WW + c] = sS;
-  S[3 * WW + c] = sN;
-  S[4 * WW + c] = sP;
-  (void)N;
+  S[si] = sW;
+  S[sst + si] = sE;
+  S[2 * sst + si] = sS;
+  S[3 * sst + si] = sN;
+  S[4 * sst + si] = sP;
   return sP;
 }
 // one colour over all cells (list == nullptr) or over the band cells list[lo, hi)
-__global__ void __launch_bounds__(TPB) k_box_adj(int N, int W, double h, double a, double d, const uint8_t *__restrict__ cls,
+__global__ void __launch_bounds__(TPB) k_box_adj(int N, int W, BoxK BK, const uint8_t *__restrict__ cls,
                                                  double *xb, double *bb, double *S, int colour, const int *__restrict__ list,
                                                  int lo, int hi, double *part, unsigned *ticket) {
   const int K = N / 5 + 1;
@@ -295,16 +302,16 @@ __global__ void __launch_bounds__(TPB) k_box_adj(int N, int W, double h, double 
       i = ((colour - 2 * j) % 5 + 5) % 5 + 5 * kk;
       if (i >= N) continue;
     }
-    sp += box_adj(N, W, h, a, d, cls, xb, bb, S, i, j);
+    sp += box_adj(W, BK, cls, xb, bb, S, (j + 1) * W + (i + 1), W * W, i, j);
   }
   double tot;
   if (alast_total(sp, part, ticket, &tot) && threadIdx.x == 0) xb[3 * W * W] += tot;
 }
-__global__ void __launch_bounds__(TPB) k_box_adj_g(int N, int W, double h, double a, const uint8_t *__restrict__ cls,
+__global__ void __launch_bounds__(TPB) k_box_adj_g(int N, int W, double ih, double a, const uint8_t *__restrict__ cls,
                                                    const double *__restrict__ S, int colour, double *xb) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= 3 * W * W) return;
-  const double acc = box_gather(N, W, h, a, cls, S, colour, t);
+  const double acc = box_gather<false>(N, W, ih, a, cls, S, colour, t);
   if (acc != 0.0) xb[t] += acc;
 }
 
@@ -423,6 +430,107 @@ __global__ void k_xi_adj(int N, int W, double h, const uint8_t *__restrict__ cls
     bb[t] -= c;
   }
   (void)N;
+}
+
+// One transposed relaxation of a small level in one workgroup: the xi update, the lambda ghost sweeps and the box
+// colours 4..0 of relax_t, with xbar, bbar, the classes, the ghost sweep's row values and the box values in LDS
+// (the box values of one colour in the per-colour layout, slot j K + i / 5) and a barrier after every grid-wide
+// step.  On a small level the separate launches (about 16 per relaxation) cost more than their work.
+constexpr int RT_T = 1024;
+struct RelaxT {
+  int N, W, lam, ng;
+  BoxK BK;
+  double inv_mp;
+  const uint8_t *cls;
+  const int *g_pt, *tl, *off, *ent, *nt;
+  const double *g_dtau, *g_w;
+  double *xb, *bb;
+};
+// LDS bytes of k_relax_t_wg on a level of size N
+inline size_t relax_t_lds(int N, int ng) {
+  const size_t W = N + 2, WW = W * W, K = N / 5 + 1;
+  return (6 * WW + 1 + 5 * K * N + ng) * sizeof(double) + ((3 * WW + 15) & ~(size_t)15);
+}
+__global__ void __launch_bounds__(RT_T) k_relax_t_wg(RelaxT P) {
+  extern __shared__ __align__(16) unsigned char rt_lds[];
+  __shared__ double red[RT_T / 64];
+  const int tid = threadIdx.x, N = P.N, W = P.W, WW = W * W, K = N / 5 + 1, KN = K * N;
+  double *xs = reinterpret_cast<double *>(rt_lds);
+  double *bb = xs + 3 * WW + 1;
+  double *Sc = bb + 3 * WW;
+  double *gt = Sc + 5 * KN;
+  uint8_t *cl = reinterpret_cast<uint8_t *>(gt + P.ng);
+  for (int t = tid; t <= 3 * WW; t += RT_T) xs[t] = P.xb[t];
+  for (int t = tid; t < 3 * WW; t += RT_T) {
+    bb[t] = P.bb[t];
+    cl[t] = P.cls[t];
+  }
+  __syncthreads();
+  // xi: take xibar, then its contributions to the divergence columns and the continuity right-hand sides
+  const double c = xs[3 * WW] * P.inv_mp, ih = P.BK.ih;
+  __syncthreads();
+  if (tid == 0) xs[3 * WW] = 0.0;
+  if (c != 0.0) {
+    const uint8_t *cp = cl + 2 * WW;
+    for (int t = tid; t < 3 * WW; t += RT_T) {
+      const int g = t / WW, q = t - g * WW, j = q / W - 1, i = q % W - 1;
+      if (g == 0) {
+        const double f = (i - 1 >= -1 && cp[q - 1] == K_INT ? 1.0 : 0.0) - (cp[q] == K_INT ? 1.0 : 0.0);
+        if (f != 0.0) xs[t] += f * c / P.BK.h;
+      } else if (g == 1) {
+        const double f = (j - 1 >= -1 && cp[q - W] == K_INT ? 1.0 : 0.0) - (cp[q] == K_INT ? 1.0 : 0.0);
+        if (f != 0.0) xs[t] += f * c / P.BK.h;
+      } else if (cp[q] == K_INT) {
+        bb[t] -= c;
+      }
+    }
+  }
+  __syncthreads();
+  // ghost sweeps: t = dtau xbar_G, bbar_G += t, then xbar -= B^T t gathered per column
+  if (P.ng) {
+    const int nt = *P.nt;
+    for (int it = 0; it < P.lam; it++) {
+      for (int r = tid; r < P.ng; r += RT_T) {
+        const double t = P.g_dtau[r] * xs[P.g_pt[r]];
+        gt[r] = t;
+        bb[P.g_pt[r]] += t;
+      }
+      __syncthreads();
+      for (int s = tid; s < nt; s += RT_T) {
+        double acc = 0;
+        for (int q = P.off[s]; q < P.off[s + 1]; q++) {
+          const int e = P.ent[q];
+          acc += -P.g_w[e] * gt[e / 9];
+        }
+        if (acc != 0.0) xs[P.tl[s]] += acc;
+      }
+      __syncthreads();
+    }
+  }
+  // box colours 4..0: the box solves of the colour, then the gather of their scatter
+  for (int colour = 4; colour >= 0; colour--) {
+    double sp = 0;
+    for (int t = tid; t < KN; t += RT_T) {
+      const int j = t / K, kk = t - j * K;
+      const int i = ((colour - 2 * j) % 5 + 5) % 5 + 5 * kk;
+      if (i < N) sp += box_adj(W, P.BK, cl, xs, bb, Sc, t, KN, i, j);
+    }
+    for (int o = 32; o > 0; o >>= 1) sp += __shfl_xor(sp, o);
+    if ((tid & 63) == 0) red[tid >> 6] = sp;
+    __syncthreads();
+    if (tid == 0) {
+      double tot = 0;
+      for (int w = 0; w < RT_T / 64; w++) tot += red[w];
+      xs[3 * WW] += tot;
+    }
+    for (int t = tid; t < 3 * WW; t += RT_T) {
+      const double acc = box_gather<true>(N, W, ih, P.BK.a, cl, Sc, colour, t);
+      if (acc != 0.0) xs[t] += acc;
+    }
+    __syncthreads();
+  }
+  for (int t = tid; t <= 3 * WW; t += RT_T) P.xb[t] = xs[t];
+  for (int t = tid; t < 3 * WW; t += RT_T) P.bb[t] = bb[t];
 }
 
 // transposed residual: bbar += rbar (the M^T part is k_mt_* with sgn = -1)
@@ -954,9 +1062,9 @@ static void box_colour_t(Ctx *ctx, int l, int colour, bool band) {
   int nb = std::min(4096, nblk(total));
   // a band colour writes the values of its listed boxes only: the others of the colour must read zero
   if (band) k_fill0<<<nblk(5L * G.WW), TPB, 0, ctx->stream>>>(ctx->a_S, 5L * G.WW);
-  k_box_adj<<<nb, TPB, 0, ctx->stream>>>(G.N, G.W, G.h, a, d, G.cls, A.x, A.b, ctx->a_S, colour, list, lo, hi, ctx->d_red,
+  k_box_adj<<<nb, TPB, 0, ctx->stream>>>(G.N, G.W, box_consts(G.h, a, d), G.cls, A.x, A.b, ctx->a_S, colour, list, lo, hi, ctx->d_red,
                                          ctx->d_ticket);
-  k_box_adj_g<<<nblk(3L * G.WW), TPB, 0, ctx->stream>>>(G.N, G.W, G.h, a, G.cls, ctx->a_S, colour, A.x);
+  k_box_adj_g<<<nblk(3L * G.WW), TPB, 0, ctx->stream>>>(G.N, G.W, 1.0 / G.h, a, G.cls, ctx->a_S, colour, A.x);
 }
 
 static void ghost_sweep_t(Ctx *ctx, int l) {
@@ -991,10 +1099,37 @@ static void xb_relax_t(Ctx *ctx, int l) {
 
 // reverse of: box colours 0..4, coupled boxes, lambda ghost sweeps, [band colours 0..4, lambda ghost sweeps] x
 // bnd_sweeps, xi
+// levels up to this size relax in one workgroup (k_relax_t_wg), when its LDS fits
+constexpr int RT_MAXN = 32;
+
 static void relax_t(Ctx *ctx, int l) {
   Geo &G = ctx->geo[l];
   Vec<double> &A = ctx->adj[l];
   hipStream_t s = ctx->stream;
+  const bool band = ctx->prm.bnd_sweeps > 0 && G.nband > 0, xbx = ctx->prm.ghost_boxes && G.nxb;
+  if (G.N <= RT_MAXN && !band && !xbx && relax_t_lds(G.N, G.ng) + 1024 <= ctx->max_lds) {
+    const TTab &GT = ctx->atab[l].gt;
+    RelaxT P;
+    P.N = G.N;
+    P.W = G.W;
+    P.lam = ctx->prm.lambda_ghost;
+    P.ng = G.ng;
+    const double a = coef_a_l(ctx, l);
+    P.BK = box_consts(G.h, a, 1.0 + 4.0 * a);
+    P.inv_mp = 1.0 / G.mp;
+    P.cls = G.cls;
+    P.g_pt = G.g_pt;
+    P.tl = GT.tl;
+    P.off = GT.off;
+    P.ent = GT.ent;
+    P.nt = GT.d_nt;
+    P.g_dtau = G.g_dtau;
+    P.g_w = G.g_w;
+    P.xb = A.x;
+    P.bb = A.b;
+    k_relax_t_wg<<<1, RT_T, relax_t_lds(G.N, G.ng), s>>>(P);
+    return;
+  }
   double *xib = ctx->d_scal + 8;
   k_take<<<1, 1, 0, s>>>(A.x + 3 * (size_t)G.WW, xib);
   k_xi_adj<<<nblk(3L * G.WW), TPB, 0, s>>>(G.N, G.W, G.h, G.cls, A.x, A.b, xib, 1.0 / G.mp);

@@ -290,6 +290,24 @@ struct Ctx {
 
 inline int nblk(long n) { return (int)((n + TPB - 1) / TPB); }
 
+// per-level constants of the box solve (the quotients by d, d + a and d^2 - a^2)
+struct BoxK {
+  double h, ih, a, q1, q2, bp, id, ihd;  // q1 = d / det, q2 = a / det, bp = (1/h) / (d + a), id = 1 / d, ihd = (1/h) / d
+};
+inline BoxK box_consts(double h, double a, double d) {
+  BoxK K;
+  const double det = d * d - a * a;
+  K.h = h;
+  K.ih = 1.0 / h;
+  K.a = a;
+  K.q1 = d / det;
+  K.q2 = a / det;
+  K.bp = K.ih / (d + a);
+  K.id = 1.0 / d;
+  K.ihd = K.ih / d;
+  return K;
+}
+
 // geometry (geom.hip)
 gp_status geometry_build(Ctx *ctx);
 gp_status levelset_analytic(Ctx *ctx, const gp_shape *shape, double t, const gp_rigid *mo);

@@ -25,23 +25,6 @@ __device__ __forceinline__ int pidx(int W, int i, int j) { return (j + 1) * W + 
 //   one free:   d uW = RW + a uE - p/h   (resp. d uE = RE + a uW + p/h)
 // and the continuity row fixes p.
 // ---------------------------------------------------------------------------------------------------------
-// per-level constants of the box solve (the quotients by d, d + a and d^2 - a^2)
-struct BoxK {
-  double h, ih, a, q1, q2, bp, id, ihd;  // q1 = d / det, q2 = a / det, bp = (1/h) / (d + a), id = 1 / d, ihd = (1/h) / d
-};
-inline BoxK box_consts(double h, double a, double d) {
-  BoxK K;
-  const double det = d * d - a * a;
-  K.h = h;
-  K.ih = 1.0 / h;
-  K.a = a;
-  K.q1 = d / det;
-  K.q2 = a / det;
-  K.bp = K.ih / (d + a);
-  K.id = 1.0 / d;
-  K.ihd = K.ih / d;
-  return K;
-}
 
 // new values of a box from its 21 neighbouring values and 5 right-hand sides; skip = the box is left unchanged
 struct BoxNew {
