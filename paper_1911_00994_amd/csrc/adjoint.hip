@@ -63,13 +63,36 @@ __device__ bool alast_total(double mine, double *part, unsigned *ticket, double 
   return true;
 }
 
+// grid sums over two kernels: each block of the producer writes its block sum to part[blockIdx.x]; one block of
+// the next kernel adds part[0, np) in a fixed order.  The kernel boundary orders the two, where the ticket of
+// alast_total costs a device-scope fence per block (an L2 write-back on a chip of several L2s) and a contended
+// atomic, which grows with the grid.
+__device__ void ablock_part(double v, double *part) {
+  const double bs = ablock_sum(v);
+  if (threadIdx.x == 0) part[blockIdx.x] = bs;
+}
+__device__ double apart_total(const double *__restrict__ part, int np) {
+  double v = 0;
+  for (int q = threadIdx.x; q < np; q += TPB) v += part[q];
+  return ablock_sum(v);
+}
+__global__ void __launch_bounds__(TPB) k_part_total(const double *__restrict__ part, int np, double *out, int add) {
+  const double t = apart_total(part, np);
+  if (threadIdx.x == 0) *out = add ? *out + t : t;
+}
+
 // ---------------------------------------------------------------------------------------------------------
 // y = base + sgn * M^T lam.  Point part: each unknown gathers the coefficients of the internal momentum and
 // continuity rows, the wall identity row and the mean row that reference it.
 // ---------------------------------------------------------------------------------------------------------
-__global__ void k_mt_pts(int N, int W, double h, double a, double d, const uint8_t *__restrict__ cls,
-                         const double *__restrict__ lam, const double *base, double sgn, double *y, double inv_mp) {
+__global__ void __launch_bounds__(TPB) k_mt_pts(int N, int W, double h, double a, double d, const uint8_t *__restrict__ cls,
+                                                const double *__restrict__ lam, const double *base, double sgn, double *y,
+                                                double inv_mp, const double *__restrict__ part, int np) {
   const int WW = W * W;
+  if (blockIdx.x == 0) {  // the xi entry: k_mt_xi's partials
+    const double tot = apart_total(part, np);
+    if (threadIdx.x == 0) y[3 * WW] = base[3 * WW] - sgn * tot;
+  }
   int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= 3 * WW) return;
   const int g = t / WW, q = t - g * WW, j = q / W - 1, i = q % W - 1;
@@ -120,13 +143,12 @@ __global__ void k_gt_mt(const int *__restrict__ tl, const int *__restrict__ off,
 }
 // xi column: -1 in every internal continuity row
 __global__ void __launch_bounds__(TPB) k_mt_xi(int W, const uint8_t *__restrict__ cls, const double *__restrict__ lam,
-                                               const double *base, double sgn, double *y, double *part, unsigned *ticket) {
+                                               double *part) {
   const int WW = W * W;
   double s = 0;
   for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < WW; t += gridDim.x * blockDim.x)
     if (cls[2 * WW + t] == K_INT) s += lam[2 * WW + t];
-  double tot;
-  if (alast_total(s, part, ticket, &tot) && threadIdx.x == 0) y[3 * WW] = base[3 * WW] - sgn * tot;
+  ablock_part(s, part);
 }
 
 // ---------------------------------------------------------------------------------------------------------
@@ -286,9 +308,9 @@ __device__ __forceinline__ double box_adj(int W, const BoxK &BK, const uint8_t *
 // one colour over all cells (list == nullptr) or over the band cells list[lo, hi)
 __global__ void __launch_bounds__(TPB) k_box_adj(int N, int W, BoxK BK, const uint8_t *__restrict__ cls,
                                                  double *xb, double *bb, double *S, int colour, const int *__restrict__ list,
-                                                 int lo, int hi, double *part, unsigned *ticket) {
-  const int K = N / 5 + 1;
-  const long total = list ? (long)(hi - lo) : (long)K * N;
+                                                 int lo, int hi, double *part) {
+  // all cells, one a thread (the boxes of the colour, one in five, read neighbouring cache lines together)
+  const long total = list ? (long)(hi - lo) : (long)N * N;
   double sp = 0;
   for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < total; t += (long)gridDim.x * blockDim.x) {
     int i, j;
@@ -297,18 +319,21 @@ __global__ void __launch_bounds__(TPB) k_box_adj(int N, int W, BoxK BK, const ui
       i = cell % N;
       j = cell / N;
     } else {
-      j = (int)(t / K);
-      int kk = (int)(t - (long)j * K);
-      i = ((colour - 2 * j) % 5 + 5) % 5 + 5 * kk;
-      if (i >= N) continue;
+      j = (int)(t / N);
+      i = (int)(t - (long)j * N);
+      if ((i + 2 * j) % 5 != colour) continue;
     }
     sp += box_adj(W, BK, cls, xb, bb, S, (j + 1) * W + (i + 1), W * W, i, j);
   }
-  double tot;
-  if (alast_total(sp, part, ticket, &tot) && threadIdx.x == 0) xb[3 * W * W] += tot;
+  ablock_part(sp, part);
 }
 __global__ void __launch_bounds__(TPB) k_box_adj_g(int N, int W, double ih, double a, const uint8_t *__restrict__ cls,
-                                                   const double *__restrict__ S, int colour, double *xb) {
+                                                   const double *__restrict__ S, int colour, double *xb,
+                                                   const double *__restrict__ part, int np) {
+  if (blockIdx.x == 0) {  // the xi column: k_box_adj's partials of sP
+    const double tot = apart_total(part, np);
+    if (threadIdx.x == 0) xb[3 * W * W] += tot;
+  }
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= 3 * W * W) return;
   const double acc = box_gather<false>(N, W, ih, a, cls, S, colour, t);
@@ -341,24 +366,44 @@ __global__ void k_gt_sweep(const int *__restrict__ tl, const int *__restrict__ o
 // transposed coupled boxes of one colour.  Forward: x_k <- x_k + sum_c Ainv[a_k][c] r_c over the written slots k of
 // each box, r = b - M x on the box's rows, all boxes of the colour from the same x.  Transposed: t_c = sum over the
 // written slots k of Ainv[a_k][c] xbar_k (all boxes first), then bbar on row c += t_c and xbar -= t_c (row c of M).
-__global__ void k_xbt_t(int lo, int hi, const int *__restrict__ idx, const int *__restrict__ box, const int *__restrict__ off,
-                        const int *__restrict__ ioff, const uint8_t *__restrict__ wr, const uint8_t *__restrict__ ok,
-                        const double *__restrict__ inv, const double *__restrict__ xb, double *t) {
-  const int s = lo + blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= hi) return;
-  const int bx = box[s], o = off[bx], m = off[bx + 1] - o, c = s - o;
-  double v = 0;
-  if (ok[bx]) {
-    const double *iv = inv + ioff[bx];
-    for (int q = 0; q < m; q++)
-      if (wr[o + q]) v += iv[(size_t)q * m + c] * xb[idx[o + q]];
+// t of the slots [lo, hi), XL lanes per slot (a fixed shuffle tree adds their parts), and the xi column: the sum of
+// t over the slots on internal continuity rows, added to xbar_xi by the last block
+constexpr int XL = 8;
+__global__ void __launch_bounds__(TPB) k_xbt_t(int lo, int hi, int W, const uint8_t *__restrict__ cls,
+                                               const int *__restrict__ idx, const int *__restrict__ box,
+                                               const int *__restrict__ off, const int *__restrict__ ioff,
+                                               const uint8_t *__restrict__ wr, const uint8_t *__restrict__ ok,
+                                               const double *__restrict__ inv, double *xb, double *t, double *part) {
+  const int WW = W * W;
+  const long n = (long)XL * (hi - lo);
+  double acc = 0;
+  for (long g0 = (long)blockIdx.x * blockDim.x; g0 < n; g0 += (long)gridDim.x * blockDim.x) {
+    const long g = g0 + threadIdx.x;
+    const int s = lo + (int)(g / XL), ln = (int)(g % XL);
+    double v = 0;
+    if (g < n) {
+      const int bx = box[s], o = off[bx], m = off[bx + 1] - o, c = s - o;
+      if (ok[bx]) {
+        const double *iv = inv + ioff[bx];
+        for (int q = ln; q < m; q += XL) {
+          const double w = iv[(size_t)q * m + c], xv = xb[idx[o + q]];  // idx is a point of the level for every slot
+          if (wr[o + q]) v += w * xv;
+        }
+      }
+    }
+    for (int d = XL / 2; d > 0; d >>= 1) v += __shfl_xor(v, d);
+    if (g < n && ln == 0) {
+      t[s] = v;
+      const int k = idx[s];
+      if (k >= 2 * WW && cls[k] == K_INT) acc += v;
+    }
   }
-  t[s] = v;
+  ablock_part(acc, part);
 }
 // the scatter of the transposed coupled boxes as a gather over the slot table: entry z = 0 of slot s is bbar on its
 // point (+t_s); entries z = 1.. are the columns of its row (xbar -= t_s times the row's coefficient): the internal
 // momentum row (d on itself, -a on the four neighbours, the pressure difference / h), the internal continuity row
-// (the four face differences / h; its -1 for xi is k_xt_xi's), or a ghost row (its 9 weights)
+// (the four face differences / h; its -1 for xi is summed in k_xbt_t), or a ghost row (its 9 weights)
 __device__ __forceinline__ double xt_coef(int k, int z, int W, double h, double a, double d,
                                           const uint8_t *__restrict__ cls, const int *__restrict__ g_rowof,
                                           const double *__restrict__ g_w) {
@@ -370,35 +415,40 @@ __device__ __forceinline__ double xt_coef(int k, int z, int W, double h, double 
 }
 // the xi column of the transposed coupled boxes: xbar_xi += sum of t_s over the internal continuity slots of
 // [lo, hi) (block partials in slot order, summed by the last block)
-__global__ void __launch_bounds__(TPB) k_xt_xi(int lo, int hi, int W, const uint8_t *__restrict__ cls,
-                                               const int *__restrict__ idx, const double *__restrict__ t, double *xb,
-                                               double *part, unsigned *ticket) {
-  const int WW = W * W;
-  double acc = 0;
-  for (int sl = lo + blockIdx.x * blockDim.x + threadIdx.x; sl < hi; sl += gridDim.x * blockDim.x) {
-    const int k = idx[sl];
-    if (k >= 2 * WW && cls[k] == K_INT) acc += t[sl];
+// the coefficient of every entry of a coupled-box table (the slot's row, column z), for k_xt_apply
+__global__ void k_xt_coef(int lo, const int *__restrict__ off, const int *__restrict__ ent, const int *__restrict__ nt,
+                          int W, double h, double a, double d, const uint8_t *__restrict__ cls,
+                          const int *__restrict__ idx, const int *__restrict__ g_rowof, const double *__restrict__ g_w,
+                          double *coef) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= *nt) return;
+  for (int q = off[s]; q < off[s + 1]; q++) {
+    const int e = ent[q], sl = lo + e / 10, z = e % 10;
+    coef[q] = z == 0 ? 1.0 : xt_coef(idx[sl], z, W, h, a, d, cls, g_rowof, g_w);
   }
-  double tot;
-  if (alast_total(acc, part, ticket, &tot) && threadIdx.x == 0) xb[3 * WW] += tot;
 }
-__global__ void k_xt_apply(int lo, const int *__restrict__ tl, const int *__restrict__ off,
-                           const int *__restrict__ ent, const int *__restrict__ nt, int W, double h, double a, double d,
-                           const uint8_t *__restrict__ cls, const int *__restrict__ idx, const int *__restrict__ g_rowof,
-                           const double *__restrict__ g_w, const double *__restrict__ t, double *xb, double *bb) {
+__global__ void __launch_bounds__(TPB) k_xt_apply(int lo, const int *__restrict__ tl, const int *__restrict__ off,
+                                                  const int *__restrict__ ent, const int *__restrict__ nt,
+                                                  const double *__restrict__ coef, const double *__restrict__ t,
+                                                  double *xb, double *bb, int W, const double *__restrict__ part,
+                                                  int np) {
+  if (blockIdx.x == 0) {  // the xi column: k_xbt_t's partials
+    const double tot = apart_total(part, np);
+    if (threadIdx.x == 0) xb[3 * W * W] += tot;
+  }
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= *nt) return;
   double accb = 0, accx = 0;
   bool any = false;
   for (int q = off[s]; q < off[s + 1]; q++) {
-    const int e = ent[q], sl = lo + e / 10, z = e % 10;
-    const double v = t[sl];
+    const int e = ent[q];
+    const double v = t[lo + e / 10], w = coef[q];
     if (v == 0.0) continue;
     any = true;
-    if (z == 0)
+    if (e % 10 == 0)
       accb += v;
     else
-      accx += xt_coef(idx[sl], z, W, h, a, d, cls, g_rowof, g_w) * v;
+      accx += w * v;
   }
   if (any) {
     bb[tl[s]] += accb;
@@ -720,15 +770,14 @@ __global__ void k_zero_at(const int *__restrict__ idx, int n, double *x) {
 // mean-row column of B': sigma = sum over those p of xbar_p goes to bbar_mean and, divided by mp, is taken
 // from xbar on the internal p
 __global__ void __launch_bounds__(TPB) k_mean_sum(int W, const uint8_t *__restrict__ cls, const double *__restrict__ xb,
-                                                  double *part, unsigned *ticket, double *out) {
+                                                  double *part) {
   const int WW = W * W;
   double s = 0;
   for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < WW; t += gridDim.x * blockDim.x) {
     uint8_t c = cls[2 * WW + t];
     if (c == K_INT || c == K_GHOST || c == K_GHOSTX) s += xb[2 * WW + t];
   }
-  double tot;
-  if (alast_total(s, part, ticket, &tot) && threadIdx.x == 0) *out = tot;
+  ablock_part(s, part);
 }
 __global__ void k_mean_apply(int W, const uint8_t *__restrict__ cls, double *xb, double *bb, const double *__restrict__ sig,
                              double inv_mp) {
@@ -820,7 +869,7 @@ __global__ void k_tt_tgt_xb(int lo, int ns, int W, const uint8_t *__restrict__ c
       const int tt[7] = {k, k - 1, k + 1, k - W, k + W, 2 * WW + q, 2 * WW + q - (g == 0 ? 1 : W)};
       if (z <= 7) t = tt[z - 1];
     } else {
-      // the xi column (every internal continuity row) is summed by k_xt_xi: a table segment that long would be
+      // the xi column (every internal continuity row) is summed in k_xbt_t: a table segment that long would be
       // slow to order
       const int tt[4] = {q + 1, q, WW + q + W, WW + q};
       if (z <= 4) t = tt[z - 1];
@@ -992,7 +1041,16 @@ static gp_status ensure_tabs(Ctx *ctx) {
         k_tt_tgt_xb<<<nblk(10 * ns), TPB, 0, s>>>(lo, ns, G.W, G.cls, G.xb_idx, G.g_rowof, G.g_col, tgt);
       });
       if (st) return st;
+      TTab &X = A.xt[c];
+      if (X.ne > X.cap_c) {
+        if (X.coef) (void)hipFree(X.coef);
+        X.coef = nullptr;
+        X.cap_c = 0;
+        GP_HIP(hipMalloc((void **)&X.coef, (size_t)X.ne * sizeof(double)));
+        X.cap_c = X.ne;
+      }
     }
+    A.xok = false;
     A.gen = G.gen;
   }
   return GP_OK;
@@ -1006,12 +1064,14 @@ void adjoint_free_tabs(Ctx *ctx) {
       ifree(t->ent);
       ifree(t->cur);
       ifree(t->d_nt);
+      if (t->coef) (void)hipFree(t->coef);
       *t = TTab();
     }
   ifree(ctx->tt_cnt);
   ifree(ctx->tt_pos);
   ifree(ctx->tt_tgt);
   ctx->tt_ccap = ctx->tt_tcap = 0;
+  for (int l = 0; l < MAXLEV; l++) ctx->atab[l].xok = false;
   if (ctx->a_S) (void)hipFree(ctx->a_S);
   ctx->a_S = nullptr;
 }
@@ -1036,8 +1096,9 @@ static void mt_apply(Ctx *ctx, int l, const double *lam, const double *base, dou
   hipStream_t s = ctx->stream;
   double a = coef_a_l(ctx, l), d = 1.0 + 4.0 * a;
   // every entry of y is written by one thread from the same entry of base, so y may alias base
-  k_mt_xi<<<std::min(ARED, nblk(G.WW)), TPB, 0, s>>>(G.W, G.cls, lam, base, sgn, y, ctx->d_red, ctx->d_ticket);
-  k_mt_pts<<<nblk(3L * G.WW), TPB, 0, s>>>(G.N, G.W, G.h, a, d, G.cls, lam, base, sgn, y, 1.0 / G.mp);
+  const int np = std::min(ARED, nblk(G.WW));
+  k_mt_xi<<<np, TPB, 0, s>>>(G.W, G.cls, lam, ctx->d_red);
+  k_mt_pts<<<nblk(3L * G.WW), TPB, 0, s>>>(G.N, G.W, G.h, a, d, G.cls, lam, base, sgn, y, 1.0 / G.mp, ctx->d_red, np);
   const TTab &GT = ctx->atab[l].gt;
   if (G.ng && GT.ne)
     k_gt_mt<<<tt_blocks(GT, 3 * G.WW + 1), TPB, 0, s>>>(GT.tl, GT.off, GT.ent, GT.d_nt, G.g_pt, G.g_w, lam, sgn, y);
@@ -1057,14 +1118,15 @@ static void box_colour_t(Ctx *ctx, int l, int colour, bool band) {
     list = G.band;
     total = hi - lo;
   } else {
-    total = (long)(G.N / 5 + 1) * G.N;
+    total = (long)G.N * G.N;
   }
   int nb = std::min(4096, nblk(total));
   // a band colour writes the values of its listed boxes only: the others of the colour must read zero
   if (band) k_fill0<<<nblk(5L * G.WW), TPB, 0, ctx->stream>>>(ctx->a_S, 5L * G.WW);
-  k_box_adj<<<nb, TPB, 0, ctx->stream>>>(G.N, G.W, box_consts(G.h, a, d), G.cls, A.x, A.b, ctx->a_S, colour, list, lo, hi, ctx->d_red,
-                                         ctx->d_ticket);
-  k_box_adj_g<<<nblk(3L * G.WW), TPB, 0, ctx->stream>>>(G.N, G.W, 1.0 / G.h, a, G.cls, ctx->a_S, colour, A.x);
+  k_box_adj<<<nb, TPB, 0, ctx->stream>>>(G.N, G.W, box_consts(G.h, a, d), G.cls, A.x, A.b, ctx->a_S, colour, list, lo, hi,
+                                         ctx->d_red);
+  k_box_adj_g<<<nblk(3L * G.WW), TPB, 0, ctx->stream>>>(G.N, G.W, 1.0 / G.h, a, G.cls, ctx->a_S, colour, A.x, ctx->d_red,
+                                                        nb);
 }
 
 static void ghost_sweep_t(Ctx *ctx, int l) {
@@ -1083,17 +1145,29 @@ static void xb_relax_t(Ctx *ctx, int l) {
   Vec<double> &A = ctx->adj[l];
   hipStream_t s = ctx->stream;
   const double a = coef_a_l(ctx, l), d = 1.0 + 4.0 * a;
+  AdjTabs &AT = ctx->atab[l];
+  if (!AT.xok || AT.xa != a) {
+    for (int c = 0; c < 5; c++) {
+      const TTab &X = AT.xt[c];
+      if (X.ne)
+        k_xt_coef<<<tt_blocks(X, 3 * G.WW + 1), TPB, 0, s>>>(G.xb_soff[c], X.off, X.ent, X.d_nt, G.W, G.h, a, d, G.cls,
+                                                            G.xb_idx, G.g_rowof, G.g_w, X.coef);
+    }
+    AT.xa = a;
+    AT.xok = true;
+  }
   for (int c = 4; c >= 0; c--) {
     const int lo = G.xb_soff[c], hi = G.xb_soff[c + 1];
     if (hi == lo) continue;
-    k_xbt_t<<<nblk(hi - lo), TPB, 0, s>>>(lo, hi, G.xb_idx, G.xb_box, G.xb_off, G.xb_ioff, G.xb_wr, G.xb_ok, G.xb_inv, A.x,
-                                        G.xb_r);
+    const int np = std::min(ARED, nblk((long)XL * (hi - lo)));
+    k_xbt_t<<<np, TPB, 0, s>>>(lo, hi, G.W, G.cls, G.xb_idx, G.xb_box, G.xb_off, G.xb_ioff, G.xb_wr, G.xb_ok, G.xb_inv,
+                               A.x, G.xb_r, ctx->d_red);
     const TTab &X = ctx->atab[l].xt[c];
     if (X.ne)
-      k_xt_apply<<<tt_blocks(X, 3 * G.WW + 1), TPB, 0, s>>>(lo, X.tl, X.off, X.ent, X.d_nt, G.W, G.h, a, d, G.cls,
-                                                           G.xb_idx, G.g_rowof, G.g_w, G.xb_r, A.x, A.b);
-    k_xt_xi<<<std::min(ARED, nblk(hi - lo)), TPB, 0, s>>>(lo, hi, G.W, G.cls, G.xb_idx, G.xb_r, A.x, ctx->d_red,
-                                                        ctx->d_ticket);
+      k_xt_apply<<<tt_blocks(X, 3 * G.WW + 1), TPB, 0, s>>>(lo, X.tl, X.off, X.ent, X.d_nt, X.coef, G.xb_r, A.x, A.b, G.W,
+                                                           ctx->d_red, np);
+    else
+      k_part_total<<<1, TPB, 0, s>>>(ctx->d_red, np, A.x + 3 * (size_t)G.WW, 1);
   }
 }
 
@@ -1174,7 +1248,9 @@ static void apply_cycle_t(Ctx *ctx) {
   Vec<double> &A = ctx->adj[0];
   hipStream_t s = ctx->stream;
   k_fill0<<<nblk(G.n), TPB, 0, s>>>(A.b, G.n);
-  k_mean_sum<<<std::min(ARED, nblk(G.WW)), TPB, 0, s>>>(G.W, G.cls, A.x, ctx->d_red, ctx->d_ticket, ctx->d_scal + 9);
+  const int np = std::min(ARED, nblk(G.WW));
+  k_mean_sum<<<np, TPB, 0, s>>>(G.W, G.cls, A.x, ctx->d_red);
+  k_part_total<<<1, TPB, 0, s>>>(ctx->d_red, np, ctx->d_scal + 9, 0);
   k_mean_apply<<<nblk(G.WW + 1), TPB, 0, s>>>(G.W, G.cls, A.x, A.b, ctx->d_scal + 9, 1.0 / G.mp);
   cycle_t(ctx, 0);
   k_walld_adj<<<nblk(3L * G.WW), TPB, 0, s>>>(3 * G.WW, G.cls, A.x, A.b);

@@ -118,13 +118,16 @@ struct Geo {
 // a fixed order (the scatter it replaces added them with atomics, in arrival order).  nt lives on the device.
 struct TTab {
   int *tl = nullptr, *off = nullptr, *ent = nullptr, *cur = nullptr, *d_nt = nullptr;
-  int cap_t = 0, cap_e = 0;
+  double *coef = nullptr;           // per entry: its matrix coefficient (coupled-box tables only)
+  int cap_t = 0, cap_e = 0, cap_c = 0;
   int ne = 0;                       // entries of the table (host)
 };
 struct AdjTabs {
   long gen = -1;                    // Geo::gen of the tables below
   TTab gt, et, xt[5];               // ghost rows (K = 9), extension points (K = 3), coupled-box slots of each
                                     // colour (K = 10)
+  double xa = 0;                    // the a of the coupled-box coefficients (valid when xok)
+  bool xok = false;
 };
 
 // one precision's vectors on one level
