@@ -999,6 +999,7 @@ __device__ double block_sum(double v) {
 // elements' loads in flight: the ticket (rd_last_total) costs one contended atomic and a fence per workgroup,
 // which with 512 workgroups of 256 threads took longer than reading the data.
 constexpr int RD_T = 1024, RD_B = 128, RD_U = 8;
+static_assert(RD_B <= TPB, "pmean_total reads one partial per thread");
 static inline int rd_blocks(long n) {
   return (int)std::max(1L, std::min((long)RD_B, (n + (long)RD_T * RD_U - 1) / ((long)RD_T * RD_U)));
 }
@@ -1053,10 +1054,12 @@ __global__ void __launch_bounds__(RD_T) k_gsum(int W, double h, const uint8_t *_
   if (rd_last_total(s, part, ticket, &tot) && threadIdx.x == 0) *out = tot;
 }
 
-// mean of the internal pressure (row eq:midpoint); result in *out
+// mean of the internal pressure (row eq:midpoint) as block partials part[0, gridDim.x): every block of the
+// consumer adds them (pmean_total), which costs less than electing a last block with a ticket (a device-scope fence
+// per block)
 template <typename T>
 __global__ void __launch_bounds__(RD_T) k_pmean(int W, const uint8_t *__restrict__ cls, const T *__restrict__ x,
-                                                double *part, unsigned *ticket, const int *mp, double *out) {
+                                                double *part) {
   const int WW = W * W, stride = gridDim.x * RD_T;
   double s = 0;
   for (int t0 = blockIdx.x * RD_T + threadIdx.x; t0 < WW; t0 += RD_U * stride) {
@@ -1073,16 +1076,34 @@ __global__ void __launch_bounds__(RD_T) k_pmean(int W, const uint8_t *__restrict
     for (int u = 0; u < RD_U; u++)
       if (c[u] == K_INT) s += v[u];
   }
-  double tot;
-  if (rd_last_total(s, part, ticket, &tot) && threadIdx.x == 0) *out = tot / *mp;
+  const double bs = band_block_sum(s);
+  if (threadIdx.x == 0) part[blockIdx.x] = bs;
+}
+// the mean from k_pmean's np <= TPB block partials, in a fixed order, in every block of a TPB-thread consumer (all
+// its threads call it); block 0 also stores it to *out
+__device__ double pmean_total(const double *__restrict__ part, int np, const int *__restrict__ mp, double *out) {
+  __shared__ double sm[TPB / 64];
+  double v = (int)threadIdx.x < np ? part[threadIdx.x] : 0.0;
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  if ((threadIdx.x & 63) == 0) sm[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double t = 0;
+  for (int q = 0; q < TPB / 64; q++) t += sm[q];
+  const double m = t / *mp;
+  if (blockIdx.x == 0 && threadIdx.x == 0) *out = m;
+  return m;
 }
 template <typename T>
-__global__ void k_pshift(int W, const uint8_t *__restrict__ cls, T *__restrict__ x, const double *mean) {
+__global__ void __launch_bounds__(TPB) k_pshift(int W, const uint8_t *__restrict__ cls, T *__restrict__ x,
+                                                const double *__restrict__ part, int np, const int *__restrict__ mp,
+                                                double *mean) {
   const int WW = W * W;
   int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int tc = min(t, WW - 1);
+  const uint8_t c = cls[2 * WW + tc];
+  const double v = (double)x[2 * WW + tc];  // loaded with the partials
+  const double m = pmean_total(part, np, mp, mean);
   if (t >= WW) return;
-  const uint8_t c = cls[2 * WW + t];
-  const double v = (double)x[2 * WW + t], m = *mean;  // loaded with the class
   if (c == K_INT || c == K_GHOST || c == K_GHOSTX) x[2 * WW + t] = (T)(v - m);
 }
 
@@ -2324,8 +2345,9 @@ template <typename T>
 static void mean_project(Ctx *ctx) {
   Geo &G = ctx->geo[0];
   Vec<T> &V = vec<T>(ctx, 0);
-  k_pmean<T><<<rd_blocks(G.WW), RD_T, 0, ctx->stream>>>(G.W, G.cls, V.x, ctx->d_red, ctx->d_ticket, G.d_mp, ctx->d_scal);
-  k_pshift<T><<<nblk(G.WW), TPB, 0, ctx->stream>>>(G.W, G.cls, V.x, ctx->d_scal);
+  const int np = rd_blocks(G.WW);
+  k_pmean<T><<<np, RD_T, 0, ctx->stream>>>(G.W, G.cls, V.x, ctx->d_red);
+  k_pshift<T><<<nblk(G.WW), TPB, 0, ctx->stream>>>(G.W, G.cls, V.x, ctx->d_red, np, G.d_mp, ctx->d_scal);
 }
 
 // The finest residual norm reaches the host through pinned memory: norm_launch clears the host slot to a value no
@@ -2793,12 +2815,14 @@ __global__ void __launch_bounds__(PC_T) k_pc_in(const uint8_t *__restrict__ cls,
 }
 // preconditioner output (FP64, in place): the pressure unknowns shifted by -mean + (mean-row entry of r), which is
 // the cycle's mean projection followed by the mean-row column of B' (a constant pressure changes no other row)
-__global__ void k_pc_shift(const uint8_t *__restrict__ cls, int WW, const double *__restrict__ mean,
-                           const double *__restrict__ r, double *z) {
+__global__ void __launch_bounds__(TPB) k_pc_shift(const uint8_t *__restrict__ cls, int WW, const double *__restrict__ part,
+                                                  int np, const int *__restrict__ mp, double *mean,
+                                                  const double *__restrict__ r, double *z) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const double m = pmean_total(part, np, mp, mean);
   if (t >= WW) return;
   const uint8_t c = cls[2 * WW + t];
-  if (c == K_INT || c == K_GHOST || c == K_GHOSTX) z[2 * WW + t] += r[3 * WW] - *mean;
+  if (c == K_INT || c == K_GHOST || c == K_GHOSTX) z[2 * WW + t] += r[3 * WW] - m;
 }
 
 gp_status gcr_alloc(Ctx *ctx) {
@@ -2926,8 +2950,9 @@ static gp_status gcr_mg_solve(Ctx *ctx, const GcrWs &ws, int precision, double t
       V.b = B0;
       V.y = Y0;
       // the mean projection and the mean-row column in one pass
-      k_pmean<double><<<rd_blocks(G.WW), RD_T, 0, s>>>(G.W, G.cls, z, ctx->d_red, ctx->d_ticket, G.d_mp, ctx->d_scal);
-      k_pc_shift<<<nblk(G.WW), TPB, 0, s>>>(G.cls, G.WW, ctx->d_scal, r, z);
+      const int np = rd_blocks(G.WW);
+      k_pmean<double><<<np, RD_T, 0, s>>>(G.W, G.cls, z, ctx->d_red);
+      k_pc_shift<<<nblk(G.WW), TPB, 0, s>>>(G.cls, G.WW, ctx->d_red, np, G.d_mp, ctx->d_scal, r, z);
     } else {
       Vec<float> &E = ctx->v32[0];
       k_cast_rhs<<<nblk(n), TPB, 0, s>>>(r, E.b, n);
