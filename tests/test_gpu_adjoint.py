@@ -97,3 +97,25 @@ def test_transposed_cycle_and_solve_are_deterministic(N, shape, motion):
     assert all(q[1] == 0 for q in sols)
     assert all(np.array_equal(sols[0][0], q[0]) for q in sols[1:])
     assert all(sols[0][2]["cycles"] == q[2]["cycles"] for q in sols[1:])
+
+
+def test_adjoint_after_alpha_change_matches_fresh_context():
+    """What the transposed cycle keeps per geometry and alpha (the coefficients of the coupled-box tables, the
+    coupled-box and coarsest inverses) follows a change of alpha: a context that solved at alpha1 and then at
+    alpha2 gives, bit for bit, the result of a context built at alpha2."""
+    N, shape, motion = 128, wl.paper_flower(), wl.Motion(omega=1.0)
+    a1 = 0.64 * (2.0 / N) ** 2
+    a2 = 2.5 * a1
+    say(f"[alpha change] N={N} alpha {a1:.3e} -> {a2:.3e}")
+    o, s = pair(N, shape, a1, motion=motion, t=0.2)
+    _, s2 = pair(N, shape, a2, motion=motion, t=0.2)
+    m = unknown_mask(o)
+    rng = np.random.default_rng(9)
+    g = rng.standard_normal(m.size) * m
+    _, st0, _ = s.adjoint_solve(g, tol=1e-12, max_cycles=200)
+    s.set_alpha(a2)
+    lam1, st1, info1 = s.adjoint_solve(g, tol=1e-12, max_cycles=200)
+    lam2, st2, info2 = s2.adjoint_solve(g, tol=1e-12, max_cycles=200)
+    assert st0 == st1 == st2 == 0
+    assert info1["cycles"] == info2["cycles"], (info1, info2)
+    assert np.array_equal(lam1, lam2), int((lam1 != lam2).sum())
