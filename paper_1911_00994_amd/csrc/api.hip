@@ -212,6 +212,8 @@ void gp_destroy(gp_ctx *ctx) {
     dfree(G.g_pt);
     dfree(G.g_col);
     dfree(G.g_colr);
+    dfree(G.g_colrT);
+    dfree(G.g_wT);
     dfree(G.g_w);
     dfree(G.g_dtau);
     dfree(G.g_B);
@@ -361,6 +363,8 @@ gp_status gp_setup_grid(gp_ctx **out, int N, double Re, const gp_params *prm, vo
     ALLOC(G.g_pt, (size_t)G.gcap);
     ALLOC(G.g_col, (size_t)9 * G.gcap);
     ALLOC(G.g_colr, (size_t)9 * G.gcap);
+    ALLOC(G.g_colrT, (size_t)9 * G.gcap);
+    ALLOC(G.g_wT, (size_t)9 * G.gcap);
     ALLOC(G.g_w, (size_t)9 * G.gcap);
     ALLOC(G.g_dtau, (size_t)G.gcap);
     ALLOC(G.g_B, (size_t)2 * G.gcap);

@@ -664,6 +664,14 @@ __global__ void k_row_of(const int *g_pt, int ng, int *row_of) {
   int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r < ng) row_of[g_pt[r]] = r;
 }
+// column-major copies of the ghost rows' columns (by row) and weights
+__global__ void k_rows_t(const int *g_colr, const double *g_w, int ng, int *colr_t, double *w_t) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= 9 * ng) return;
+  const int r = e / 9, z = e - 9 * r;
+  colr_t[(size_t)z * ng + r] = g_colr[e];
+  w_t[(size_t)z * ng + r] = g_w[e];
+}
 // the columns of the ghost rows with every ghost point replaced by -(its row + 1) (row_of from k_row_of; every
 // ghost, extrapolated-ghost and wall-ghost point has a row; a column whose row cannot be confirmed is reported)
 __global__ void k_colr(const uint8_t *cls, const int *g_pt, const int *g_col, int ng, const int *row_of, int *g_colr,
@@ -1843,6 +1851,7 @@ static gp_status build_level(Ctx *ctx, int l) {
     GP_HIP(hipMemsetAsync(B.flags + 12, 0, sizeof(int), s));
     k_row_of<<<nblk(G.ng), TPB, 0, s>>>(G.g_pt, G.ng, B.iscr);
     k_colr<<<nblk(9L * G.ng), TPB, 0, s>>>(G.cls, G.g_pt, G.g_col, G.ng, B.iscr, G.g_colr, B.flags + 12);
+    k_rows_t<<<nblk(9L * G.ng), TPB, 0, s>>>(G.g_colr, G.g_w, G.ng, G.g_colrT, G.g_wT);
   }
   // boundary faces of the internal pressure cells (and their band-region entries)
   {

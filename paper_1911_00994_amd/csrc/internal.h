@@ -40,6 +40,8 @@ struct Geo {
   int *g_pt = nullptr;              // global unknown index
   int *g_col = nullptr;             // 9 per row
   int *g_colr = nullptr;            // g_col with every ghost point given as -(its row + 1)
+  int *g_colrT = nullptr;           // g_colr and g_w column-major ([z ng + r]): a wavefront's loads of one column of
+  double *g_wT = nullptr;           // consecutive rows are contiguous
   double *g_w = nullptr;            // 9 per row
   double *g_dtau = nullptr;
   double *g_B = nullptr, *g_nB = nullptr, *g_th = nullptr;  // 2 per row

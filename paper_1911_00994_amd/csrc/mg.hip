@@ -709,7 +709,8 @@ constexpr int GX_F = 4;  // face codes per thread loaded ahead
 // R rows per thread (ng <= R * BAND_T)
 template <typename T, int R>
 __global__ void __launch_bounds__(BAND_T) k_ghost_xi(const int *__restrict__ pt, const int *__restrict__ col,
-                                                     const int *__restrict__ colr, const double *__restrict__ w,
+                                                     const int *__restrict__ colr, const int *__restrict__ colr_t,
+                                                     const double *__restrict__ w_t, const double *__restrict__ w,
                                                      const double *__restrict__ dtau, int ng, T *x,
                                                      const T *__restrict__ b, int sweeps, int WW, double h,
                                                      const uint8_t *__restrict__ cls, const int *__restrict__ rowof,
@@ -737,9 +738,9 @@ __global__ void __launch_bounds__(BAND_T) k_ghost_xi(const int *__restrict__ pt,
     kk[i] = has[i] ? pt[r] : 0;
     dt[i] = has[i] ? dtau[r] : 0.0;
 #pragma unroll
-    for (int z = 0; z < 9; z++) {
-      cc[i][z] = has[i] ? cs[9 * r + z] : 0;
-      ww[i][z] = has[i] ? w[9 * r + z] : 0.0;
+    for (int z = 0; z < 9; z++) {  // column-major tables (colr_t, w_t) when given: coalesced over the rows
+      cc[i][z] = has[i] ? (colr_t ? colr_t[(size_t)z * ng + r] : cs[9 * r + z]) : 0;
+      ww[i][z] = has[i] ? (w_t ? w_t[(size_t)z * ng + r] : w[9 * r + z]) : 0.0;
     }
   }
   if (R == 1 && colr) {
@@ -828,6 +829,79 @@ __global__ void __launch_bounds__(BAND_T) k_ghost_xi(const int *__restrict__ pt,
     }
   for (int q = tid + GX_F * BAND_T; q < nf; q += BAND_T) {
     const double v = (double)x[f_code[q] >> 1];
+    fs += (f_code[q] & 1) ? -v : v;
+  }
+  fs = band_block_sum(fs);
+  const double gsum = gp_total(gpre, gp, ngp);
+  if (tid == 0) x[3 * WW] = (T)((fs / h - gsum) / *mp);
+}
+// The ghost sweeps and xi with two rows a thread (BAND_T < ng <= 2 BAND_T) from the column-major row tables (ghost
+// columns by row): each row's fixed columns are summed once (they do not change in the sweeps) and its ghost
+// columns kept as (weight, LDS row), weight zero for the others, so that the sweeps read registers and LDS only
+template <typename T>
+__global__ void __launch_bounds__(BAND_T) k_ghost_xi2(const int *__restrict__ pt, const int *__restrict__ colr_t,
+                                                      const double *__restrict__ w_t, const double *__restrict__ dtau,
+                                                      int ng, T *x, const T *__restrict__ b, int sweeps, int WW, double h,
+                                                      const uint8_t *__restrict__ cls, const int *__restrict__ rowof,
+                                                      const int *__restrict__ f_code, int nf,
+                                                      const double *__restrict__ gp, int ngp, const int *__restrict__ mp) {
+  __shared__ double gv[2 * BAND_T];
+  const int tid = threadIdx.x;
+  const GpPre gpre = gp_start(gp, ngp);
+  double sf[2], bb[2], dt[2], wg[2][9];
+  int kk[2], ix[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};  // LDS rows of the ghost columns, row 0's in the low 16 bits
+  bool has[2];
+#pragma unroll
+  for (int i = 0; i < 2; i++) {
+    const int r = tid + i * BAND_T;
+    has[i] = r < ng;
+    kk[i] = has[i] ? pt[r] : 0;
+    dt[i] = has[i] ? dtau[r] : 0.0;
+    int cz[9];
+    double wz[9], xz[9];
+#pragma unroll
+    for (int z = 0; z < 9; z++) {
+      cz[z] = has[i] ? colr_t[(size_t)z * ng + r] : 0;
+      wz[z] = has[i] ? w_t[(size_t)z * ng + r] : 0.0;
+    }
+#pragma unroll
+    for (int z = 0; z < 9; z++) xz[z] = cz[z] >= 0 ? (double)x[cz[z]] : 0.0;
+    bb[i] = (double)b[kk[i]];
+    if (has[i]) gv[r] = (double)x[kk[i]];
+    sf[i] = 0.0;
+#pragma unroll
+    for (int z = 0; z < 9; z++) {
+      const bool gz = cz[z] < 0;
+      if (!gz) sf[i] += wz[z] * xz[z];
+      wg[i][z] = gz ? wz[z] : 0.0;
+      ix[z] |= (gz ? -cz[z] - 1 : 0) << (16 * i);
+    }
+  }
+  __syncthreads();
+  for (int it = 0; it < sweeps; it++) {
+    double nv[2];
+#pragma unroll
+    for (int i = 0; i < 2; i++) {
+      double s = sf[i];
+#pragma unroll
+      for (int z = 0; z < 9; z++) s += wg[i][z] * gv[(ix[z] >> (16 * i)) & 0xffff];
+      nv[i] = (has[i] ? gv[tid + i * BAND_T] : 0.0) + dt[i] * (bb[i] - s);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < 2; i++)
+      if (has[i]) gv[tid + i * BAND_T] = (double)(T)nv[i];
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 2; i++)
+    if (has[i]) x[kk[i]] = (T)gv[tid + i * BAND_T];
+  // xi: the boundary faces, ghost ones from LDS (the sweeps change only ghost points)
+  double fs = 0;
+  for (int q = tid; q < nf; q += BAND_T) {
+    const int k = f_code[q] >> 1;
+    const uint8_t c = cls[k];
+    const double v = (c == K_GHOST || c == K_GHOSTX || c == K_WALLG) ? gv[rowof[k]] : (double)x[k];
     fs += (f_code[q] & 1) ? -v : v;
   }
   fs = band_block_sum(fs);
@@ -2163,11 +2237,17 @@ static void relax(Ctx *ctx, int l) {
     // the ghost sweeps and xi in one workgroup (a few rows per thread)
     // one row per thread: the sweeps run from registers and LDS (below 128 registers); two: from global memory
     if (G.ng <= BAND_T)
-      k_ghost_xi<T, 1><<<1, BAND_T, 0, s>>>(G.g_pt, G.g_col, G.colr_ok ? G.g_colr : nullptr, G.g_w, G.g_dtau, G.ng,
+      k_ghost_xi<T, 1><<<1, BAND_T, 0, s>>>(G.g_pt, G.g_col, G.colr_ok ? G.g_colr : nullptr,
+                                             G.colr_ok ? G.g_colrT : nullptr, G.colr_ok ? G.g_wT : nullptr, G.g_w,
+                                             G.g_dtau, G.ng,
                                              V.x, V.b, ctx->prm.lambda_ghost, G.WW, G.h, G.cls, G.g_rowof, G.f_code,
                                              G.nf, ctx->gs_ptr[l], ctx->gs_n[l], G.d_mp);
+    else if (G.colr_ok)
+      k_ghost_xi2<T><<<1, BAND_T, 0, s>>>(G.g_pt, G.g_colrT, G.g_wT, G.g_dtau, G.ng, V.x, V.b, ctx->prm.lambda_ghost,
+                                          G.WW, G.h, G.cls, G.g_rowof, G.f_code, G.nf, ctx->gs_ptr[l], ctx->gs_n[l],
+                                          G.d_mp);
     else
-      k_ghost_xi<T, 2><<<1, BAND_T, 0, s>>>(G.g_pt, G.g_col, nullptr, G.g_w, G.g_dtau, G.ng, V.x, V.b,
+      k_ghost_xi<T, 2><<<1, BAND_T, 0, s>>>(G.g_pt, G.g_col, nullptr, nullptr, nullptr, G.g_w, G.g_dtau, G.ng, V.x, V.b,
                                              ctx->prm.lambda_ghost, G.WW, G.h, G.cls, G.g_rowof, G.f_code, G.nf,
                                              ctx->gs_ptr[l], ctx->gs_n[l], G.d_mp);
     return;
